@@ -1,0 +1,228 @@
+/*
+ * hipcone — C-ABI of an MI355X (gfx950) primal-dual interior-point solver for
+ *
+ *     minimize 1/2 x'Px + q'x   subject to   Ax + s = b,  s in K          (P)
+ *
+ * with K a product of zero, nonnegative, second-order, exponential, 3-d power
+ * and equal-size PSD cones (arXiv 2412.19027, Sec. 1 problem (P) and
+ * Sec. 2.1 "Supported cones").  Every per-iteration step of the method
+ * (Algorithm 1, Sec. 3.2) runs in this library's HIP kernels: residuals and
+ * termination, the cone scalings and their writes into the KKT system, the
+ * quasi-definite LDL' factorisation and triangular solves with iterative
+ * refinement, direction recovery, step lengths and the iterate update.
+ *
+ * Conventions
+ *   - Every function returns an int32 status: 0 = OK, < 0 = error (HC_ERR_*).
+ *     No C++ exception or abort crosses this boundary.  The text of the last
+ *     error of a handle is available from hc_last_error(handle) (or of the
+ *     last failed handle-less call from hc_last_error(NULL)).
+ *   - Host pointers unless a parameter says "device".  All input arrays are
+ *     copied; the caller may free them when the call returns.
+ *   - A solver handle is not thread-safe; distinct handles are independent.
+ *   - Solver outcomes (solved, infeasible, iteration limit, ...) are not
+ *     errors: they are reported in hc_info.status.
+ */
+#ifndef HIPCONE_H
+#define HIPCONE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define HC_OK              0
+#define HC_ERR_INVALID_ARG (-1)  /* NULL pointer or a size out of range            */
+#define HC_ERR_DIM         (-2)  /* cone rows do not add up to m, or n/m <= 0       */
+#define HC_ERR_CSR         (-3)  /* unsorted/duplicate/out-of-range CSR, or P has
+                                    an entry below its diagonal                    */
+#define HC_ERR_CONE        (-4)  /* unknown cone type, SOC dim < 2, EXP/POW dim !=
+                                    3, alpha outside (0,1), PSD sides unequal or
+                                    outside [1, 32]                               */
+#define HC_ERR_NONFINITE   (-5)  /* NaN or Inf in P, q, A or b                      */
+#define HC_ERR_OOM         (-6)  /* device memory (arena too small or allocation
+                                    failed); hc_last_error names the bytes needed */
+#define HC_ERR_DEVICE      (-7)  /* a HIP runtime call failed                       */
+#define HC_ERR_STATE       (-8)  /* call out of order (e.g. solve before bind)      */
+#define HC_ERR_UNSUPPORTED (-9)  /* problem shape this build does not handle        */
+
+/* ---- cone list (Sec. 2.1) ------------------------------------------------ */
+#define HC_CONE_ZERO   0   /* {0}^dim                                          */
+#define HC_CONE_NONNEG 1   /* R_+^dim                                          */
+#define HC_CONE_SOC    2   /* {(t, x) : |x|_2 <= t}, dim = 1 + len(x) >= 2     */
+#define HC_CONE_EXP    3   /* exponential cone, dim = 3                        */
+#define HC_CONE_POW    4   /* power cone with exponent alpha in (0,1), dim = 3 */
+#define HC_CONE_PSD    5   /* k x k PSD cone; dim = k, rows = k (k+1) / 2 in the
+                              svec encoding: upper triangle column by column,
+                              off-diagonal entries scaled by sqrt(2)            */
+
+typedef struct {
+  int32_t type;   /* HC_CONE_*                                  */
+  int32_t dim;    /* rows (PSD: the matrix side k)              */
+  double alpha;   /* POW exponent; ignored by the other types   */
+} hc_cone;
+
+/* ---- problem data (Sec. 1 (P)); CSR is 0-based, columns sorted, unique ------ */
+typedef struct {
+  int64_t n, m;
+  const int64_t* P_rowptr;  /* n+1; upper triangle of P (col >= row); may be NULL
+                               together with P_col/P_val when P = 0              */
+  const int32_t* P_col;
+  const double* P_val;
+  const double* q;          /* n */
+  const int64_t* A_rowptr;  /* m+1 */
+  const int32_t* A_col;
+  const double* A_val;
+  const double* b;          /* m */
+  const hc_cone* cones;     /* in row order; rows must add up to m */
+  int32_t ncones;
+} hc_problem;
+
+/* ---- settings (defaults from hc_settings_default) ------------------------ */
+#define HC_PRECISION_FP64  0   /* factor and solve in FP64 (the paper's default)  */
+#define HC_PRECISION_MIXED 1   /* factor and triangular solves in FP32, residuals,
+                                  refinement updates and everything else in FP64
+                                  (Sec. 3.5 mixed precision)                     */
+typedef struct {
+  double eps_feas;        /* 1e-8: optimality tests (eq. termination-check)        */
+  double eps_inf;         /* 1e-8: infeasibility tests (eq. infeasibility-check)   */
+  int32_t max_iter;       /* 200                                                   */
+  int32_t precision;      /* HC_PRECISION_FP64                                     */
+  double static_reg;      /* delta_s: 1e-8 (FP64) / sqrt(eps_32) (mixed); <= 0 picks
+                             the value for the precision                          */
+  double dyn_reg;         /* delta_d: eps^2 of the factor precision; < 0 picks it   */
+  double ir_abstol;       /* 1e-12 (refinement stop, Sec. 3.5)                      */
+  double ir_reltol;       /* 1e-12                                                  */
+  int32_t ir_max;         /* 10 corrections after the first solve                  */
+  double beta;            /* 1e-6: neighbourhood N(beta) (Sec. 2.2)                 */
+  double backtrack;       /* 0.8: exp/pow backtracking ratio                        */
+  double step_fraction;   /* 0.99 (Algorithm 1 update)                              */
+  int32_t equilibrate;    /* 1: modified Ruiz scaling of P, A, q, b at setup        */
+  int32_t equil_iters;    /* 10                                                     */
+  int32_t force_dual_scaling; /* 0: exp/pow use the primal-dual (BFGS) scaling      */
+  int32_t verbose;        /* 0                                                      */
+} hc_settings;
+
+/* ---- device hand-off ------------------------------------------------------ */
+typedef struct {
+  void* arena;          /* device memory the library sub-allocates from, or NULL
+                           to let the library allocate (and free) its own        */
+  size_t arena_bytes;
+  void* stream;         /* hipStream_t to run on; NULL = the null stream          */
+  int32_t device;       /* HIP device ordinal                                     */
+} hc_device;
+
+/* ---- results -------------------------------------------------------------- */
+#define HC_STATUS_UNSOLVED              0
+#define HC_STATUS_SOLVED                1
+#define HC_STATUS_PRIMAL_INFEASIBLE     2
+#define HC_STATUS_DUAL_INFEASIBLE       3
+#define HC_STATUS_MAX_ITER              4
+#define HC_STATUS_INSUFFICIENT_PROGRESS 5
+#define HC_STATUS_NUMERICAL_ERROR       6
+
+typedef struct {
+  int32_t status;          /* HC_STATUS_*                                          */
+  int32_t iterations;
+  double obj_primal;       /* g_p (eq. residuals-objectives), unscaled             */
+  double obj_dual;         /* g_d                                                  */
+  double res_primal;       /* |r_p|_inf                                            */
+  double res_dual;         /* |r_d|_inf                                            */
+  double gap;              /* |g_p - g_d|                                          */
+  double mu;
+  double setup_ms;         /* host analysis + upload + initial point               */
+  double solve_ms;         /* the iterations                                       */
+  double factor_ms;        /* summed over iterations (device events)               */
+  double solve_kkt_ms;
+  double cone_ms;
+  int64_t ir_solves;       /* triangular-solve passes including refinement         */
+  int64_t pivot_guard_hits;
+  int64_t dual_switches;   /* iterations redone with the dual exp/pow scaling      */
+  int64_t n_ordered;       /* size of the factored Schur complement                */
+  double factor_flops;     /* per factorisation                                    */
+} hc_info;
+
+typedef struct hc_solver hc_solver;
+
+/* Fill `out` with the defaults listed above.  HC_ERR_INVALID_ARG on NULL. */
+int32_t hc_settings_default(hc_settings* out);
+
+/* Validate and copy the problem, reorder rows by cone family, equilibrate and
+ * build the KKT structure on the host (setup phase of Algorithm 1).  No device
+ * memory is touched.  `settings` may be NULL (defaults).
+ * Errors: HC_ERR_INVALID_ARG, HC_ERR_DIM, HC_ERR_CSR, HC_ERR_CONE,
+ * HC_ERR_NONFINITE, HC_ERR_UNSUPPORTED.  On error *out is NULL. */
+int32_t hc_setup(hc_solver** out, const hc_problem* prob, const hc_settings* settings);
+
+/* Device bytes hc_bind needs for this handle (arena size). */
+int32_t hc_workspace_bytes(const hc_solver* s, size_t* bytes);
+
+/* Place the solver on a device: sub-allocate the arena (or allocate), upload the
+ * data and compute the initial point.  The arena and stream must outlive the
+ * handle.  Errors: HC_ERR_STATE (already bound), HC_ERR_OOM, HC_ERR_DEVICE. */
+int32_t hc_bind(hc_solver* s, const hc_device* dev);
+
+/* Run the iterations of Algorithm 1 to termination on the handle's stream;
+ * blocks until the status is known.  Errors: HC_ERR_STATE, HC_ERR_DEVICE. */
+int32_t hc_solve(hc_solver* s);
+
+int32_t hc_get_info(const hc_solver* s, hc_info* out);
+
+/* Solution in the user's row order, unscaled and divided by tau: x (n), s (m),
+ * z (m), caller-owned host buffers (any may be NULL).  For an infeasible
+ * status the unnormalised certificate is returned instead. */
+int32_t hc_get_solution(const hc_solver* s, double* x, double* sv, double* z);
+
+/* Raw internal iterate (scaled, rows in the library's family order):
+ * x (n), s (m), z (m), tau, kappa; and the internal->user row map (m int64). */
+int32_t hc_get_iterate(const hc_solver* s, double* x, double* sv, double* z, double* tau,
+                       double* kappa, int64_t* row_of_internal);
+
+void hc_destroy(hc_solver* s);                /* NULL is a no-op */
+const char* hc_last_error(const hc_solver* s);
+const char* hc_status_str(int32_t status);
+
+/* ---- kernel test entry points (device pointers, one cone family) ----------
+ * They run exactly the kernels hc_solve runs, on `count` cones of one family
+ * given cone by cone (AoS: cone i occupies rows [i*rows, (i+1)*rows)), and
+ * exist so a test can compare single steps with a reference.  `alpha` is the
+ * POW exponent per cone (NULL otherwise); `dim` is rows per cone (PSD: side).
+ * All buffers are device memory of count*rows doubles unless stated.
+ *
+ * hc_test_cone_scale: scaling at (s, z) with global mu (Appendix A): writes
+ *   H_out (count*rows*rows, row-major H of each cone), lam_out (count*rows:
+ *   nonneg/SOC/PSD lambda (PSD: k eigenvalues, rest 0), exp/pow: the shadow
+ *   point z~ = -grad f*(s)), branch_out (count int32: exp/pow 1 = dual
+ *   scaling taken, else 0).
+ * hc_test_cone_ds: combined-step d_s (eq. ds-correction-step) from the scaling
+ *   at (s, z) and the affine directions (dsa, dza), sigma*mu = sm.
+ * hc_test_cone_step: per cone the largest alpha <= amax with s + alpha ds and
+ *   z + alpha dz in the closed cones (nonneg/SOC/PSD: exact boundary step;
+ *   exp/pow: interior membership tested at alpha = amax * 0.8^j, j = 0..63,
+ *   reported as the first passing trial, or 0).
+ */
+int32_t hc_test_cone_scale(int32_t type, int64_t count, int32_t dim, const double* alpha,
+                           const double* s, const double* z, double mu, double* H_out,
+                           double* lam_out, int32_t* branch_out, void* stream);
+int32_t hc_test_cone_ds(int32_t type, int64_t count, int32_t dim, const double* alpha,
+                        const double* s, const double* z, const double* dsa, const double* dza,
+                        double mu, double sm, double* ds_out, void* stream);
+int32_t hc_test_cone_step(int32_t type, int64_t count, int32_t dim, const double* alpha,
+                          const double* s, const double* z, const double* ds, const double* dz,
+                          double amax, double* alpha_out, void* stream);
+
+/* Dense Cholesky of an SPD matrix (device, column-major, n x n, leading dim
+ * ld >= n, lower triangle referenced) followed by the solve of `nrhs`
+ * right-hand sides (device, n x nrhs column-major) in place, in the factor
+ * precision (HC_PRECISION_*): the kernels of the KKT solve's Schur
+ * complement.  The matrix is overwritten by the factor.  guard_hits may be
+ * NULL. */
+int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, double* A, int32_t nrhs,
+                                 double* B, int64_t* guard_hits, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HIPCONE_H */

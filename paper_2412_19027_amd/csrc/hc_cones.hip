@@ -1,0 +1,1460 @@
+// Cone layer of the IPM on gfx950 (Sec. 3.3 mixed parallel computing strategy,
+// Algorithm 2; scalings of Appendix A; corrections of eq. ds-correction-step).
+//
+// Mapping: zero and nonnegative rows are plain vector ops (one lane per row);
+// every other family runs one lane per cone with the cone's components stored
+// component-major (row base + j*count + i), so each component load of a wave is
+// one coalesced 512-byte access.  PSD cones (k <= 12 here) run one lane per
+// cone for the factorisations and one lane per (cone, svec row) for the
+// explicit (H + delta I)^-1 block.
+//
+// Scalings are kept in spectral form H = V diag(lam) V': near the optimum
+// cond(H) exceeds 1/eps, and applying H or (H + delta I)^-1 through the
+// eigenpairs keeps each spectral component to relative accuracy.
+//   nonneg: h = s/z.
+//   SOC:    NT point wbar, eta; eigenpairs (1, +-u)/sqrt2 with eta^2 (w0 +- r)^2
+//           (the small one as eta^2/(w0 + r)^2), eta^2 on the rest.
+//   exp/pow: Hess f = G G' with G built from rank-one PSD pieces; a one-sided
+//           Jacobi SVD of G gives Hess f^-1; the primal-dual (BFGS) scaling is
+//           the Gram matrix of [s/sqrt<s,z>, ds/sqrt<ds,dz>, u sqrt(mu/u'Hf^-1 u)],
+//           the dual scaling is mu G G'; both diagonalised by Jacobi.
+//   PSD:    R, R^-1 from Cholesky factors and a Jacobi SVD; M = R R' = Q diag(m) Q';
+//           H(X) = M X M has eigenvalues m_i m_j on svec(q_i q_j' + q_j q_i').
+#include "hc_cones.h"
+
+#include <cmath>
+
+namespace hc {
+
+constexpr int SOC_DMAX = 16;
+constexpr int PSD_KMAX = 12;
+
+__device__ inline double sq(double x) { return x * x; }
+
+// ===========================================================================
+// small dense helpers (per lane)
+// ===========================================================================
+
+// one-sided Jacobi on the 3 rows of G (3 x nc, row-major, nc <= 6):
+// on return rows are orthogonal, U (3x3, row-major) accumulates G = U G'.
+__device__ void jacobi_rows3(double* G, int nc, double* U) {
+  for (int i = 0; i < 9; ++i) U[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    bool rot = false;
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = (pq == 2) ? 1 : 0, q = (pq == 0) ? 1 : 2;
+      double a = 0, b = 0, g = 0;
+      for (int c = 0; c < nc; ++c) {
+        a += G[p * nc + c] * G[p * nc + c];
+        b += G[q * nc + c] * G[q * nc + c];
+        g += G[p * nc + c] * G[q * nc + c];
+      }
+      if (g == 0.0 || fabs(g) <= 1e-16 * sqrt(a * b)) continue;
+      rot = true;
+      const double zeta = (b - a) / (2.0 * g);
+      const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+      for (int c = 0; c < nc; ++c) {
+        const double gp = G[p * nc + c], gq = G[q * nc + c];
+        G[p * nc + c] = cs * gp - sn * gq;
+        G[q * nc + c] = sn * gp + cs * gq;
+      }
+      for (int r = 0; r < 3; ++r) {
+        const double up = U[r * 3 + p], uq = U[r * 3 + q];
+        U[r * 3 + p] = cs * up - sn * uq;
+        U[r * 3 + q] = sn * up + cs * uq;
+      }
+    }
+    if (!rot) break;
+  }
+}
+
+// ===========================================================================
+// exponential and power cones: barrier pieces on the dual cone
+// ===========================================================================
+
+// grad f(z)
+__device__ void exp_grad(const double* z, double* g) {
+  const double ell = log(z[2] / (-z[0]));
+  const double psi = z[1] - z[0] - z[0] * ell;
+  g[0] = ell / psi - 1.0 / z[0];
+  g[1] = -1.0 / psi;
+  g[2] = (z[0] / z[2]) / psi - 1.0 / z[2];
+}
+
+__device__ void pow_grad(const double* z, double a, double* g) {
+  const double Pi = pow(z[0] / a, a) * pow(z[1] / (1.0 - a), 1.0 - a);
+  const double gp0 = Pi * a / z[0], gp1 = Pi * (1.0 - a) / z[1];
+  const double dm = Pi - z[2], dp = Pi + z[2];
+  g[0] = -gp0 / dm - gp0 / dp - (1.0 - a) / z[0];
+  g[1] = -gp1 / dm - gp1 / dp - a / z[1];
+  g[2] = 1.0 / dm - 1.0 / dp;
+}
+
+// G (3 x nc, row-major) with G G' = Hess f(z); returns nc
+__device__ int exp_hess_factor(const double* z, double* G) {
+  const double z1 = z[0], z2 = z[1], z3 = z[2];
+  const double ell = log(z3 / (-z1));
+  const double psi = z2 - z1 - z1 * ell;
+  const double rp = sqrt(psi);
+  // columns: c/sqrt(psi), grad psi / psi, e1/|z1|, e3/z3
+  const double c0 = 1.0 / sqrt(-z1), c2 = sqrt(-z1) / z3;
+  G[0 * 4 + 0] = c0 / rp;    G[1 * 4 + 0] = 0.0;        G[2 * 4 + 0] = c2 / rp;
+  G[0 * 4 + 1] = -ell / psi; G[1 * 4 + 1] = 1.0 / psi;  G[2 * 4 + 1] = (-z1 / z3) / psi;
+  G[0 * 4 + 2] = 1.0 / (-z1); G[1 * 4 + 2] = 0.0;       G[2 * 4 + 2] = 0.0;
+  G[0 * 4 + 3] = 0.0;        G[1 * 4 + 3] = 0.0;        G[2 * 4 + 3] = 1.0 / z3;
+  return 4;
+}
+
+__device__ int pow_hess_factor(const double* z, double a, double* G) {
+  const double Pi = pow(z[0] / a, a) * pow(z[1] / (1.0 - a), 1.0 - a);
+  const double gp0 = Pi * a / z[0], gp1 = Pi * (1.0 - a) / z[1];
+  const double d0 = 1.0 / z[0], d1 = -1.0 / z[1];
+  int col = 0;
+  for (int sgn = -1; sgn <= 1; sgn += 2) {
+    const double den = Pi + sgn * z[2];
+    const double w = sqrt(Pi * a * (1.0 - a) / den);
+    G[0 * 6 + col] = w * d0; G[1 * 6 + col] = w * d1; G[2 * 6 + col] = 0.0;
+    ++col;
+    G[0 * 6 + col] = gp0 / den; G[1 * 6 + col] = gp1 / den; G[2 * 6 + col] = sgn / den;
+    ++col;
+  }
+  G[0 * 6 + 4] = sqrt(1.0 - a) / z[0]; G[1 * 6 + 4] = 0.0; G[2 * 6 + 4] = 0.0;
+  G[0 * 6 + 5] = 0.0; G[1 * 6 + 5] = sqrt(a) / z[1]; G[2 * 6 + 5] = 0.0;
+  return 6;
+}
+
+// Third derivative contraction T_i = f'''(z)[u, v, e_i] of a term -log g(z):
+//   -D3g[u,v]_i/g + (D2g[u,v] dg_i + (D2g u)_i dg[v] + (D2g v)_i dg[u])/g^2 - 2 dg[u] dg[v] dg_i / g^3
+__device__ void neglog_third(double g, const double* dg, const double* D2g /*3x3*/, const double* D3uv,
+                             const double* u, const double* v, double* T) {
+  double du = 0, dv = 0, Duv = 0, D2u[3], D2v[3];
+  for (int i = 0; i < 3; ++i) {
+    du += dg[i] * u[i];
+    dv += dg[i] * v[i];
+    D2u[i] = D2g[i * 3 + 0] * u[0] + D2g[i * 3 + 1] * u[1] + D2g[i * 3 + 2] * u[2];
+    D2v[i] = D2g[i * 3 + 0] * v[0] + D2g[i * 3 + 1] * v[1] + D2g[i * 3 + 2] * v[2];
+  }
+  for (int i = 0; i < 3; ++i) Duv += u[i] * D2v[i];
+  const double g2 = g * g;
+  for (int i = 0; i < 3; ++i)
+    T[i] += -D3uv[i] / g + (Duv * dg[i] + D2u[i] * dv + D2v[i] * du) / g2 - 2.0 * du * dv * dg[i] / (g2 * g);
+}
+
+__device__ void exp_third(const double* z, const double* u, const double* v, double* T) {
+  const double z1 = z[0], z2 = z[1], z3 = z[2];
+  const double ell = log(z3 / (-z1));
+  const double psi = z2 - z1 - z1 * ell;
+  const double dg[3] = {-ell, 1.0, -z1 / z3};
+  const double D2[9] = {1.0 / z1, 0.0, -1.0 / z3, 0.0, 0.0, 0.0, -1.0 / z3, 0.0, z1 / (z3 * z3)};
+  double D3[3];
+  D3[0] = -u[0] * v[0] / (z1 * z1) + u[2] * v[2] / (z3 * z3);
+  D3[1] = 0.0;
+  D3[2] = (u[0] * v[2] + u[2] * v[0]) / (z3 * z3) - 2.0 * z1 * u[2] * v[2] / (z3 * z3 * z3);
+  T[0] = T[1] = T[2] = 0.0;
+  neglog_third(psi, dg, D2, D3, u, v, T);
+  T[0] += -2.0 * u[0] * v[0] / (z1 * z1 * z1);
+  T[2] += -2.0 * u[2] * v[2] / (z3 * z3 * z3);
+}
+
+__device__ void pow_third(const double* z, double a, const double* u, const double* v, double* T) {
+  const double Pi = pow(z[0] / a, a) * pow(z[1] / (1.0 - a), 1.0 - a);
+  const double av[3] = {a / z[0], (1.0 - a) / z[1], 0.0};            // grad log Pi
+  const double Bd[3] = {-a / (z[0] * z[0]), -(1.0 - a) / (z[1] * z[1]), 0.0};  // Hess log Pi (diag)
+  const double au = av[0] * u[0] + av[1] * u[1], avv = av[0] * v[0] + av[1] * v[1];
+  const double uBv = Bd[0] * u[0] * v[0] + Bd[1] * u[1] * v[1];
+  double D2[9], D3[3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) D2[i * 3 + j] = Pi * (av[i] * av[j] + (i == j ? Bd[i] : 0.0));
+  const double dL[3] = {2.0 * a * u[0] * v[0] / (z[0] * z[0] * z[0]),
+                        2.0 * (1.0 - a) * u[1] * v[1] / (z[1] * z[1] * z[1]), 0.0};
+  for (int i = 0; i < 3; ++i)
+    D3[i] = Pi * (av[i] * au * avv + Bd[i] * u[i] * avv + Bd[i] * v[i] * au + av[i] * uBv + dL[i]);
+  T[0] = T[1] = T[2] = 0.0;
+  for (int sgn = -1; sgn <= 1; sgn += 2) {
+    const double g = Pi + sgn * z[2];
+    const double dg[3] = {Pi * av[0], Pi * av[1], (double)sgn};
+    neglog_third(g, dg, D2, D3, u, v, T);
+  }
+  T[0] += -2.0 * (1.0 - a) * u[0] * v[0] / (z[0] * z[0] * z[0]);
+  T[1] += -2.0 * a * u[1] * v[1] / (z[1] * z[1] * z[1]);
+}
+
+// membership of int K (primal) and int K* (dual)
+__device__ bool exp_primal_in(const double* s) {
+  if (!(s[1] > 0.0 && s[2] > 0.0)) return false;
+  return s[1] * log(s[2] / s[1]) - s[0] > 0.0;
+}
+__device__ bool exp_dual_in(const double* z) {
+  if (!(z[0] < 0.0 && z[2] > 0.0)) return false;
+  return z[1] - z[0] - z[0] * log(z[2] / (-z[0])) > 0.0;
+}
+__device__ bool pow_primal_in(const double* s, double a) {
+  if (!(s[0] > 0.0 && s[1] > 0.0)) return false;
+  return 2.0 * a * log(s[0]) + 2.0 * (1.0 - a) * log(s[1]) - log(s[2] * s[2]) > 0.0;
+}
+__device__ bool pow_dual_in(const double* z, double a) {
+  if (!(z[0] > 0.0 && z[1] > 0.0)) return false;
+  return 2.0 * a * log(z[0] / a) + 2.0 * (1.0 - a) * log(z[1] / (1.0 - a)) - log(z[2] * z[2]) > 0.0;
+}
+
+// z~ = -grad f*(s): the z with -grad f(z) = s (s in int K), through a scalar
+// equation solved by safeguarded Newton.
+__device__ bool exp_conj(const double* s, double* z) {
+  // y = 1/t > 0 solves log(1 + y) + y = r, r = log(s3/s2) - s1/s2; Newton from
+  // the lower bound y0 = r/2 increases monotonically to the root (the left side
+  // is concave increasing).
+  const double r = log(s[2] / s[1]) - s[0] / s[1];
+  if (!(r > 0.0)) return false;
+  double y = 0.5 * r;
+  for (int it = 0; it < 200; ++it) {
+    const double h = log1p(y) + y - r;
+    const double dy = -h / (1.0 / (1.0 + y) + 1.0);
+    y += dy;
+    if (fabs(dy) <= 1e-16 * y) break;
+  }
+  const double t = 1.0 / y;
+  const double u = -t / s[1];
+  const double lw = log1p(y) + log(s[1] / s[2]);   // log(w / (-u))
+  z[0] = u;
+  z[2] = (1.0 + t) / s[2];
+  z[1] = 1.0 / s[1] + u * (1.0 + lw);
+  return isfinite(z[0]) && isfinite(z[1]) && isfinite(z[2]);
+}
+
+__device__ bool pow_conj(const double* s, double a, double* z) {
+  if (s[2] == 0.0) {
+    z[0] = (1.0 + a) / s[0];
+    z[1] = (2.0 - a) / s[1];
+    z[2] = 0.0;
+    return true;
+  }
+  // y > 0 solves h(y) = 2a log(1+a+2ay) + 2(1-a) log(2-a+2(1-a)y) - log(1+y) - log y - log 4 + C = 0,
+  // h strictly decreasing; Newton in t = log y inside a bisection bracket.
+  const double C = 2.0 * log(fabs(s[2])) - 2.0 * a * log(a * s[0]) - 2.0 * (1.0 - a) * log((1.0 - a) * s[1]);
+  auto h = [&](double t, double* dh) {
+    const double y = exp(t);
+    const double p1 = 1.0 + a + 2.0 * a * y, p2 = 2.0 - a + 2.0 * (1.0 - a) * y;
+    const double val = 2.0 * a * log(p1) + 2.0 * (1.0 - a) * log(p2) - log1p(y) - t - 1.3862943611198906 + C;
+    *dh = y * (4.0 * a * a / p1 + 4.0 * (1.0 - a) * (1.0 - a) / p2 - 1.0 / (1.0 + y)) - 1.0;
+    return val;
+  };
+  double lo = -200.0, hi = 200.0;
+  double t = 2.0 * a * log(1.0 + a) + 2.0 * (1.0 - a) * log(2.0 - a) - 1.3862943611198906 + C;  // small-y asymptote
+  t = fmin(fmax(t, -150.0), 150.0);
+  for (int it = 0; it < 300; ++it) {
+    double dh;
+    const double v = h(t, &dh);
+    if (v > 0.0) lo = t; else hi = t;
+    double tn = t - v / dh;
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    const double step = fabs(tn - t);
+    t = tn;
+    if (step <= 1e-15 * fmax(1.0, fabs(t)) || hi - lo <= 1e-15 * fmax(1.0, fabs(t))) break;
+  }
+  const double y = exp(t);
+  z[0] = (1.0 + a + 2.0 * a * y) / s[0];
+  z[1] = (2.0 - a + 2.0 * (1.0 - a) * y) / s[1];
+  z[2] = -2.0 * y / s[2];
+  return isfinite(z[0]) && isfinite(z[1]) && isfinite(z[2]);
+}
+
+// ===========================================================================
+// SOC helpers (dim d <= SOC_DMAX, lane per cone)
+// ===========================================================================
+struct SocSpec {
+  double r, lp, lm, lo;   // |wbar_1|, eigenvalues eta^2 (w0 + r)^2, eta^2/(w0 + r)^2, eta^2
+};
+
+__device__ inline SocSpec soc_spec(const double* wb, int d, double eta) {
+  double r2 = 0;
+  for (int j = 1; j < d; ++j) r2 += wb[j] * wb[j];
+  SocSpec sp;
+  sp.r = sqrt(r2);
+  const double big = wb[0] + sp.r;
+  const double e2 = eta * eta;
+  sp.lp = e2 * big * big;
+  sp.lm = e2 / (big * big);
+  sp.lo = e2;
+  return sp;
+}
+
+// y = V f(lam) V' x with V = [(1,u)/sqrt2, (1,-u)/sqrt2, perp]; f given as three values
+__device__ inline void soc_spec_apply(const double* wb, int d, const SocSpec& sp, double fp, double fm, double fo,
+                                      const double* x, double* y) {
+  const double is2 = 0.70710678118654752440;
+  double u[SOC_DMAX];
+  if (sp.r > 0.0) {
+    for (int j = 1; j < d; ++j) u[j] = wb[j] / sp.r;
+  } else {
+    for (int j = 1; j < d; ++j) u[j] = (j == 1) ? 1.0 : 0.0;
+  }
+  double ux = 0;
+  for (int j = 1; j < d; ++j) ux += u[j] * x[j];
+  const double ap = (x[0] + ux) * is2, am = (x[0] - ux) * is2;
+  y[0] = (fp * ap + fm * am) * is2;
+  const double cu = (fp * ap - fm * am) * is2;
+  for (int j = 1; j < d; ++j) y[j] = cu * u[j] + fo * (x[j] - u[j] * ux);
+}
+
+// ===========================================================================
+// kernels: scaling
+// ===========================================================================
+__global__ void k_zero_scale(int64_t base, int64_t count, double* hdiag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) hdiag[base + i] = 0.0;
+}
+
+__global__ void k_nonneg_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+                               double* __restrict__ hdiag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.count) return;
+  const double h = s[g.base + i] / z[g.base + i];
+  g.state[i] = h;
+  hdiag[g.base + i] = h;
+}
+
+__global__ void k_soc_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+                            double* __restrict__ hdiag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.count) return;
+  const int d = g.dim;
+  const int64_t N = g.count;
+  double sv[SOC_DMAX], zv[SOC_DMAX];
+  for (int j = 0; j < d; ++j) {
+    sv[j] = s[g.base + j * N + i];
+    zv[j] = z[g.base + j * N + i];
+  }
+  double sJs = sv[0] * sv[0], zJz = zv[0] * zv[0];
+  for (int j = 1; j < d; ++j) {
+    sJs -= sv[j] * sv[j];
+    zJz -= zv[j] * zv[j];
+  }
+  const double ns = sqrt(sJs), nz = sqrt(zJz);
+  double sz = 0;
+  for (int j = 0; j < d; ++j) sz += (sv[j] / ns) * (zv[j] / nz);
+  const double gamma = sqrt((1.0 + sz) / 2.0);
+  double wb[SOC_DMAX];
+  for (int j = 0; j < d; ++j) wb[j] = (sv[j] / ns + (j == 0 ? 1.0 : -1.0) * (zv[j] / nz)) / (2.0 * gamma);
+  const double eta = sqrt(ns / nz);
+  // lambda = W z = eta Wbar z
+  double w1z1 = 0;
+  for (int j = 1; j < d; ++j) w1z1 += wb[j] * zv[j];
+  double lam[SOC_DMAX];
+  lam[0] = eta * (wb[0] * zv[0] + w1z1);
+  const double cf = zv[0] + w1z1 / (1.0 + wb[0]);
+  for (int j = 1; j < d; ++j) lam[j] = eta * (zv[j] + cf * wb[j]);
+  for (int j = 0; j < d; ++j) {
+    g.state[j * N + i] = wb[j];
+    g.state[(d + 1 + j) * N + i] = lam[j];
+  }
+  g.state[d * N + i] = eta;
+  const double e2 = eta * eta;
+  for (int j = 0; j < d; ++j) hdiag[g.base + j * N + i] = e2 * (2.0 * wb[j] * wb[j] - (j == 0 ? 1.0 : -1.0));
+}
+
+// exp/pow state fields (field-major): lam 0..2, V 3..11 (row-major), Uh 12..20,
+// sig_h 21..23, grad 24..26, branch 27
+constexpr int NS_LAM = 0, NS_V = 3, NS_UH = 12, NS_SH = 21, NS_GRAD = 24, NS_BR = 27;
+
+__global__ void k_nonsym_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z, double mu,
+                               int force_dual, double* __restrict__ hdiag, int* __restrict__ pd_count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.count) return;
+  const int64_t N = g.count;
+  const bool is_exp = (g.kind == HC_CONE_EXP);
+  const double a = is_exp ? 0.0 : g.alpha[i];
+  double sv[3], zv[3];
+  for (int j = 0; j < 3; ++j) {
+    sv[j] = s[g.base + j * N + i];
+    zv[j] = z[g.base + j * N + i];
+  }
+  double gr[3];
+  if (is_exp) exp_grad(zv, gr); else pow_grad(zv, a, gr);
+  const double st[3] = {-gr[0], -gr[1], -gr[2]};
+  double zt[3];
+  const bool ok = is_exp ? exp_conj(sv, zt) : pow_conj(sv, a, zt);
+  const double mu_i = (sv[0] * zv[0] + sv[1] * zv[1] + sv[2] * zv[2]) / 3.0;
+  const double mut_i = (st[0] * zt[0] + st[1] * zt[1] + st[2] * zt[2]) / 3.0;
+  bool dual = force_dual || !ok || !(mu_i * mut_i - 1.0 >= 1.4901161193847656e-08);
+  // factor of Hess f and its SVD (Hess f^-1 = Uh diag(1/sig^2) Uh')
+  double G[18], Uh[9];
+  const int nc = is_exp ? exp_hess_factor(zv, G) : pow_hess_factor(zv, a, G);
+  jacobi_rows3(G, nc, Uh);
+  double sig[3];
+  for (int r = 0; r < 3; ++r) {
+    double acc = 0;
+    for (int c = 0; c < nc; ++c) acc += G[r * nc + c] * G[r * nc + c];
+    sig[r] = sqrt(acc);
+  }
+  double lam[3], V[9];
+  if (!dual) {
+    const double szd = sv[0] * zv[0] + sv[1] * zv[1] + sv[2] * zv[2];
+    double dsv[3], dzv[3], uu[3];
+    for (int j = 0; j < 3; ++j) {
+      dsv[j] = sv[j] - mu_i * st[j];
+      dzv[j] = zv[j] - mu_i * zt[j];
+    }
+    uu[0] = zv[1] * zt[2] - zv[2] * zt[1];
+    uu[1] = zv[2] * zt[0] - zv[0] * zt[2];
+    uu[2] = zv[0] * zt[1] - zv[1] * zt[0];
+    double uHu = 0;
+    for (int r = 0; r < 3; ++r) {
+      const double pr = (Uh[0 * 3 + r] * uu[0] + Uh[1 * 3 + r] * uu[1] + Uh[2 * 3 + r] * uu[2]) / sig[r];
+      uHu += pr * pr;
+    }
+    const double dd = dsv[0] * dzv[0] + dsv[1] * dzv[1] + dsv[2] * dzv[2];
+    const double c1 = 1.0 / sqrt(szd), c2 = 1.0 / sqrt(dd), c3 = sqrt(mu / uHu);
+    double Gp[9];
+    for (int r = 0; r < 3; ++r) {
+      Gp[r * 3 + 0] = sv[r] * c1;
+      Gp[r * 3 + 1] = dsv[r] * c2;
+      Gp[r * 3 + 2] = uu[r] * c3;
+    }
+    bool fin = isfinite(c1) && isfinite(c2) && isfinite(c3) && dd > 0.0 && uHu > 0.0;
+    if (fin) {
+      jacobi_rows3(Gp, 3, V);
+      for (int r = 0; r < 3; ++r) lam[r] = Gp[r * 3 + 0] * Gp[r * 3 + 0] + Gp[r * 3 + 1] * Gp[r * 3 + 1] +
+                                           Gp[r * 3 + 2] * Gp[r * 3 + 2];
+    } else {
+      dual = true;
+    }
+  }
+  if (dual) {
+    for (int r = 0; r < 9; ++r) V[r] = Uh[r];
+    for (int r = 0; r < 3; ++r) lam[r] = mu * sig[r] * sig[r];
+  } else {
+    atomicAdd(pd_count, 1);
+  }
+  for (int j = 0; j < 3; ++j) g.state[(NS_LAM + j) * N + i] = lam[j];
+  for (int j = 0; j < 9; ++j) {
+    g.state[(NS_V + j) * N + i] = V[j];
+    g.state[(NS_UH + j) * N + i] = Uh[j];
+  }
+  for (int j = 0; j < 3; ++j) {
+    g.state[(NS_SH + j) * N + i] = sig[j];
+    g.state[(NS_GRAD + j) * N + i] = gr[j];
+  }
+  g.state[NS_BR * N + i] = dual ? 1.0 : 0.0;
+  for (int j = 0; j < 3; ++j) {
+    double hd = 0;
+    for (int r = 0; r < 3; ++r) hd += lam[r] * V[j * 3 + r] * V[j * 3 + r];
+    hdiag[g.base + j * N + i] = hd;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PSD (k <= PSD_KMAX), one lane per cone; matrices row-major in local arrays
+// ---------------------------------------------------------------------------
+__device__ inline void psd_smat(const double* v, int k, double* X) {
+  int p = 0;
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i <= j; ++i, ++p) {
+      const double f = (i == j) ? 1.0 : 0.70710678118654752440;
+      X[i * PSD_KMAX + j] = v[p] * f;
+      X[j * PSD_KMAX + i] = v[p] * f;
+    }
+}
+__device__ inline void psd_svec(const double* X, int k, double* v) {
+  int p = 0;
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i <= j; ++i, ++p) v[p] = X[i * PSD_KMAX + j] * ((i == j) ? 1.0 : 1.41421356237309504880);
+}
+// lower Cholesky in place (row-major), returns false if not positive definite
+__device__ bool psd_chol(double* A, int k) {
+  for (int j = 0; j < k; ++j) {
+    double d = A[j * PSD_KMAX + j];
+    for (int p = 0; p < j; ++p) d -= A[j * PSD_KMAX + p] * A[j * PSD_KMAX + p];
+    if (!(d > 0.0)) return false;
+    d = sqrt(d);
+    A[j * PSD_KMAX + j] = d;
+    for (int i = j + 1; i < k; ++i) {
+      double v = A[i * PSD_KMAX + j];
+      for (int p = 0; p < j; ++p) v -= A[i * PSD_KMAX + p] * A[j * PSD_KMAX + p];
+      A[i * PSD_KMAX + j] = v / d;
+    }
+    for (int i = 0; i < j; ++i) A[i * PSD_KMAX + j] = 0.0;
+  }
+  return true;
+}
+// one-sided Jacobi (Hestenes) on the columns of B (k x k): on return the
+// columns are orthogonal and W accumulates B_in W = B_out.
+__device__ void psd_jacobi_cols(double* B, int k, double* W) {
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) W[i * PSD_KMAX + j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    bool rot = false;
+    for (int p = 0; p < k - 1; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        double a = 0, b = 0, g = 0;
+        for (int r = 0; r < k; ++r) {
+          a += B[r * PSD_KMAX + p] * B[r * PSD_KMAX + p];
+          b += B[r * PSD_KMAX + q] * B[r * PSD_KMAX + q];
+          g += B[r * PSD_KMAX + p] * B[r * PSD_KMAX + q];
+        }
+        if (g == 0.0 || fabs(g) <= 1e-16 * sqrt(a * b)) continue;
+        rot = true;
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        for (int r = 0; r < k; ++r) {
+          const double bp = B[r * PSD_KMAX + p], bq = B[r * PSD_KMAX + q];
+          B[r * PSD_KMAX + p] = cs * bp - sn * bq;
+          B[r * PSD_KMAX + q] = sn * bp + cs * bq;
+          const double wp = W[r * PSD_KMAX + p], wq = W[r * PSD_KMAX + q];
+          W[r * PSD_KMAX + p] = cs * wp - sn * wq;
+          W[r * PSD_KMAX + q] = sn * wp + cs * wq;
+        }
+      }
+    if (!rot) break;
+  }
+}
+// cyclic Jacobi eigenvalues of a symmetric matrix (destroys A); returns lambda_min
+__device__ double psd_min_eig(double* A, int k) {
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0, tot = 0;
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        tot += sq(A[i * PSD_KMAX + j]);
+        if (i != j) off += sq(A[i * PSD_KMAX + j]);
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < k - 1; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = A[p * PSD_KMAX + q];
+        if (apq == 0.0) continue;
+        const double theta = (A[q * PSD_KMAX + q] - A[p * PSD_KMAX + p]) / (2.0 * apq);
+        const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(1.0 + theta * theta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int r = 0; r < k; ++r) {   // A <- A J (columns p, q)
+          const double arp = A[r * PSD_KMAX + p], arq = A[r * PSD_KMAX + q];
+          A[r * PSD_KMAX + p] = c * arp - s * arq;
+          A[r * PSD_KMAX + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {   // A <- J' A (rows p, q)
+          const double apr = A[p * PSD_KMAX + r], aqr = A[q * PSD_KMAX + r];
+          A[p * PSD_KMAX + r] = c * apr - s * aqr;
+          A[q * PSD_KMAX + r] = s * apr + c * aqr;
+        }
+      }
+  }
+  double m = A[0];
+  for (int i = 1; i < k; ++i) m = fmin(m, A[i * PSD_KMAX + i]);
+  return m;
+}
+
+// PSD state fields: R (k*k row-major) | Rinv | Q | lambda (k) | m (k)
+__global__ void k_psd_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+                            double* __restrict__ hdiag) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.count) return;
+  const int k = g.k, sd = g.dim;
+  const int64_t N = g.count;
+  const double* sc = s + g.base + c * sd;
+  const double* zc = z + g.base + c * sd;
+  double Ls[PSD_KMAX * PSD_KMAX], Lz[PSD_KMAX * PSD_KMAX], B[PSD_KMAX * PSD_KMAX], W[PSD_KMAX * PSD_KMAX];
+  psd_smat(sc, k, Ls);
+  psd_smat(zc, k, Lz);
+  psd_chol(Ls, k);
+  psd_chol(Lz, k);
+  // B = Lz' Ls
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += Lz[p * PSD_KMAX + i] * Ls[p * PSD_KMAX + j];
+      B[i * PSD_KMAX + j] = acc;
+    }
+  psd_jacobi_cols(B, k, W);   // B W = U diag(lam): V = W
+  double lam[PSD_KMAX];
+  for (int j = 0; j < k; ++j) {
+    double acc = 0;
+    for (int r = 0; r < k; ++r) acc += B[r * PSD_KMAX + j] * B[r * PSD_KMAX + j];
+    lam[j] = sqrt(acc);
+  }
+  // R = Ls V lam^-1/2 ; Rinv = lam^-1/2 U' Lz' with U = B diag(1/lam)
+  double R[PSD_KMAX * PSD_KMAX], Ri[PSD_KMAX * PSD_KMAX];
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += Ls[i * PSD_KMAX + p] * W[p * PSD_KMAX + j];
+      R[i * PSD_KMAX + j] = acc / sqrt(lam[j]);
+    }
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += (B[p * PSD_KMAX + i] / lam[i]) * Lz[j * PSD_KMAX + p];
+      Ri[i * PSD_KMAX + j] = acc / sqrt(lam[i]);
+    }
+  // M = R R' = Q diag(m) Q': one-sided Jacobi on the columns of R' gives Q
+  double Rt[PSD_KMAX * PSD_KMAX], Q[PSD_KMAX * PSD_KMAX];
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) Rt[i * PSD_KMAX + j] = R[j * PSD_KMAX + i];
+  psd_jacobi_cols(Rt, k, Q);
+  double m[PSD_KMAX];
+  for (int j = 0; j < k; ++j) {
+    double acc = 0;
+    for (int r = 0; r < k; ++r) acc += Rt[r * PSD_KMAX + j] * Rt[r * PSD_KMAX + j];
+    m[j] = acc;
+  }
+  const int64_t kk = (int64_t)k * k;
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      g.state[(i * k + j) * N + c] = R[i * PSD_KMAX + j];
+      g.state[(kk + i * k + j) * N + c] = Ri[i * PSD_KMAX + j];
+      g.state[(2 * kk + i * k + j) * N + c] = Q[i * PSD_KMAX + j];
+    }
+  for (int j = 0; j < k; ++j) {
+    g.state[(3 * kk + j) * N + c] = lam[j];
+    g.state[(3 * kk + k + j) * N + c] = m[j];
+  }
+  // diag of H in svec coordinates: H[(a,b),(a,b)] = (M_aa M_bb + M_ab^2) (off-diag) or M_aa^2
+  double Mm[PSD_KMAX * PSD_KMAX];
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += R[i * PSD_KMAX + p] * R[j * PSD_KMAX + p];
+      Mm[i * PSD_KMAX + j] = acc;
+    }
+  int p = 0;
+  for (int b = 0; b < k; ++b)
+    for (int a = 0; a <= b; ++a, ++p) {
+      const double v = (a == b) ? sq(Mm[a * PSD_KMAX + a])
+                                : (Mm[a * PSD_KMAX + a] * Mm[b * PSD_KMAX + b] + sq(Mm[a * PSD_KMAX + b]));
+      hdiag[g.base + c * sd + p] = v;
+    }
+}
+
+void cone_scale(const SegDev& g, const double* s, const double* z, double mu, int force_dual, double* hdiag,
+                int* pd_count, hipStream_t st) {
+  if (g.count == 0) return;
+  const int nb = cone_blocks(g);
+  switch (g.kind) {
+    case HC_CONE_ZERO:
+      hipLaunchKernelGGL(k_zero_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g.base, g.count, hdiag);
+      break;
+    case HC_CONE_NONNEG:
+      hipLaunchKernelGGL(k_nonneg_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, hdiag);
+      break;
+    case HC_CONE_SOC:
+      hipLaunchKernelGGL(k_soc_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, hdiag);
+      break;
+    case HC_CONE_EXP:
+    case HC_CONE_POW:
+      hipLaunchKernelGGL(k_nonsym_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, mu, force_dual, hdiag,
+                         pd_count);
+      break;
+    case HC_CONE_PSD:
+      hipLaunchKernelGGL(k_psd_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, hdiag);
+      break;
+  }
+  HC_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// spectral application of H or (H + delta I)^-1, and the explicit inverse block
+// ===========================================================================
+__device__ inline double fsel(int mode, double lam, double delta) { return mode == 0 ? lam : 1.0 / (lam + delta); }
+
+__device__ void psd_apply_one(const SegDev& g, int64_t c, int mode, double delta, const double* x, double* y) {
+  const int k = g.k;
+  const int64_t N = g.count, kk = (int64_t)k * k;
+  double Q[PSD_KMAX * PSD_KMAX], m[PSD_KMAX], X[PSD_KMAX * PSD_KMAX], T[PSD_KMAX * PSD_KMAX];
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) Q[i * PSD_KMAX + j] = g.state[(2 * kk + i * k + j) * N + c];
+  for (int j = 0; j < k; ++j) m[j] = g.state[(3 * kk + k + j) * N + c];
+  psd_smat(x, k, X);
+  // T = Q' X Q, scaled, then Y = Q T Q'
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += X[i * PSD_KMAX + p] * Q[p * PSD_KMAX + j];
+      T[i * PSD_KMAX + j] = acc;   // X Q
+    }
+  double U[PSD_KMAX * PSD_KMAX];
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += Q[p * PSD_KMAX + i] * T[p * PSD_KMAX + j];
+      U[i * PSD_KMAX + j] = acc * fsel(mode, m[i] * m[j], delta);
+    }
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += U[i * PSD_KMAX + p] * Q[j * PSD_KMAX + p];
+      T[i * PSD_KMAX + j] = acc;   // U Q'
+    }
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += Q[i * PSD_KMAX + p] * T[p * PSD_KMAX + j];
+      X[i * PSD_KMAX + j] = acc;
+    }
+  psd_svec(X, k, y);
+}
+
+__global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __restrict__ x,
+                             double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.count) return;
+  const int64_t N = g.count;
+  switch (g.kind) {
+    case HC_CONE_ZERO:
+      y[g.base + i] = (mode == 0) ? 0.0 : x[g.base + i] / delta;
+      break;
+    case HC_CONE_NONNEG:
+      y[g.base + i] = fsel(mode, g.state[i], delta) * (mode == 0 ? x[g.base + i] : 1.0) *
+                      (mode == 0 ? 1.0 : x[g.base + i]);
+      break;
+    case HC_CONE_SOC: {
+      const int d = g.dim;
+      double wb[SOC_DMAX], xv[SOC_DMAX], yv[SOC_DMAX];
+      for (int j = 0; j < d; ++j) {
+        wb[j] = g.state[j * N + i];
+        xv[j] = x[g.base + j * N + i];
+      }
+      const double eta = g.state[d * N + i];
+      const SocSpec sp = soc_spec(wb, d, eta);
+      soc_spec_apply(wb, d, sp, fsel(mode, sp.lp, delta), fsel(mode, sp.lm, delta), fsel(mode, sp.lo, delta), xv,
+                     yv);
+      for (int j = 0; j < d; ++j) y[g.base + j * N + i] = yv[j];
+      break;
+    }
+    case HC_CONE_EXP:
+    case HC_CONE_POW: {
+      double V[9], lam[3], xv[3];
+      for (int j = 0; j < 9; ++j) V[j] = g.state[(NS_V + j) * N + i];
+      for (int j = 0; j < 3; ++j) {
+        lam[j] = fsel(mode, g.state[(NS_LAM + j) * N + i], delta);
+        xv[j] = x[g.base + j * N + i];
+      }
+      double p[3];
+      for (int r = 0; r < 3; ++r) p[r] = lam[r] * (V[0 * 3 + r] * xv[0] + V[1 * 3 + r] * xv[1] + V[2 * 3 + r] * xv[2]);
+      for (int j = 0; j < 3; ++j) y[g.base + j * N + i] = V[j * 3 + 0] * p[0] + V[j * 3 + 1] * p[1] + V[j * 3 + 2] * p[2];
+      break;
+    }
+    case HC_CONE_PSD: {
+      double xv[PSD_KMAX * (PSD_KMAX + 1) / 2], yv[PSD_KMAX * (PSD_KMAX + 1) / 2];
+      for (int p = 0; p < g.dim; ++p) xv[p] = x[g.base + i * g.dim + p];
+      psd_apply_one(g, i, mode, delta, xv, yv);
+      for (int p = 0; p < g.dim; ++p) y[g.base + i * g.dim + p] = yv[p];
+      break;
+    }
+  }
+}
+
+void cone_apply(const SegDev& g, int mode, double delta, const double* x, double* y, hipStream_t st) {
+  if (g.count == 0) return;
+  hipLaunchKernelGGL(k_cone_apply, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, mode, delta, x, y);
+  HC_LAUNCH_CHECK();
+}
+
+__global__ void k_cone_recover(SegDev g, const double* __restrict__ dsr, const double* __restrict__ dz,
+                               double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.count) return;
+  const int64_t N = g.count;
+  switch (g.kind) {
+    case HC_CONE_ZERO:
+      out[g.base + i] = -dsr[g.base + i];
+      break;
+    case HC_CONE_NONNEG:
+      out[g.base + i] = -dsr[g.base + i] - g.state[i] * dz[g.base + i];
+      break;
+    case HC_CONE_SOC: {
+      const int d = g.dim;
+      double wb[SOC_DMAX], xv[SOC_DMAX], yv[SOC_DMAX];
+      for (int j = 0; j < d; ++j) {
+        wb[j] = g.state[j * N + i];
+        xv[j] = dz[g.base + j * N + i];
+      }
+      const SocSpec sp = soc_spec(wb, d, g.state[d * N + i]);
+      soc_spec_apply(wb, d, sp, sp.lp, sp.lm, sp.lo, xv, yv);
+      for (int j = 0; j < d; ++j) out[g.base + j * N + i] = -dsr[g.base + j * N + i] - yv[j];
+      break;
+    }
+    case HC_CONE_EXP:
+    case HC_CONE_POW: {
+      double V[9], lam[3], xv[3];
+      for (int j = 0; j < 9; ++j) V[j] = g.state[(NS_V + j) * N + i];
+      for (int j = 0; j < 3; ++j) {
+        lam[j] = g.state[(NS_LAM + j) * N + i];
+        xv[j] = dz[g.base + j * N + i];
+      }
+      double p[3];
+      for (int r = 0; r < 3; ++r) p[r] = lam[r] * (V[0 * 3 + r] * xv[0] + V[1 * 3 + r] * xv[1] + V[2 * 3 + r] * xv[2]);
+      for (int j = 0; j < 3; ++j)
+        out[g.base + j * N + i] =
+            -dsr[g.base + j * N + i] - (V[j * 3 + 0] * p[0] + V[j * 3 + 1] * p[1] + V[j * 3 + 2] * p[2]);
+      break;
+    }
+    case HC_CONE_PSD: {
+      double xv[PSD_KMAX * (PSD_KMAX + 1) / 2], yv[PSD_KMAX * (PSD_KMAX + 1) / 2];
+      for (int p = 0; p < g.dim; ++p) xv[p] = dz[g.base + i * g.dim + p];
+      psd_apply_one(g, i, 0, 0.0, xv, yv);
+      for (int p = 0; p < g.dim; ++p) out[g.base + i * g.dim + p] = -dsr[g.base + i * g.dim + p] - yv[p];
+      break;
+    }
+  }
+}
+
+void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, double* out, hipStream_t st) {
+  if (g.count == 0) return;
+  hipLaunchKernelGGL(k_cone_recover, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, dsrhs, dz, out);
+  HC_LAUNCH_CHECK();
+}
+
+// explicit lower-triangle entries of M = (H + delta I)^-1, packed index
+// p = a (a + 1) / 2 + b for a >= b, stored mblk[p * count + cone]
+__global__ void k_cone_mblock(SegDev g, double delta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = g.count;
+  if (g.kind == HC_CONE_PSD) {
+    // one lane per (cone, svec row a)
+    const int sd = g.dim, k = g.k;
+    if (i >= N * sd) return;
+    const int64_t c = i / sd;
+    const int arow = (int)(i % sd);
+    const int64_t kk = (int64_t)k * k;
+    double Q[PSD_KMAX * PSD_KMAX], m[PSD_KMAX];
+    for (int r = 0; r < k; ++r)
+      for (int j = 0; j < k; ++j) Q[r * PSD_KMAX + j] = g.state[(2 * kk + r * k + j) * N + c];
+    for (int j = 0; j < k; ++j) m[j] = g.state[(3 * kk + k + j) * N + c];
+    // (ia, ja) of svec row a
+    int ia = 0, ja = 0;
+    {
+      int p = 0;
+      for (int j = 0; j < k; ++j)
+        for (int r = 0; r <= j; ++r, ++p)
+          if (p == arow) { ia = r; ja = j; }
+    }
+    const double ca = (ia == ja) ? 1.0 : 1.41421356237309504880;
+    const double is2 = 0.70710678118654752440;
+    int p = 0;
+    for (int jb = 0; jb < k; ++jb)
+      for (int ib = 0; ib <= jb; ++ib, ++p) {
+        if (p > arow) continue;
+        const double cb = (ib == jb) ? 1.0 : 1.41421356237309504880;
+        double acc = 0;
+        for (int jj = 0; jj < k; ++jj)
+          for (int ii = 0; ii <= jj; ++ii) {
+            // svec(E_ii,jj) at (ia, ja) and (ib, jb)
+            double ea, eb;
+            if (ii == jj) {
+              ea = ca * Q[ia * PSD_KMAX + ii] * Q[ja * PSD_KMAX + ii];
+              eb = cb * Q[ib * PSD_KMAX + ii] * Q[jb * PSD_KMAX + ii];
+            } else {
+              ea = ca * is2 * (Q[ia * PSD_KMAX + ii] * Q[ja * PSD_KMAX + jj] + Q[ia * PSD_KMAX + jj] * Q[ja * PSD_KMAX + ii]);
+              eb = cb * is2 * (Q[ib * PSD_KMAX + ii] * Q[jb * PSD_KMAX + jj] + Q[ib * PSD_KMAX + jj] * Q[jb * PSD_KMAX + ii]);
+            }
+            acc += ea * eb / (m[ii] * m[jj] + delta);
+          }
+        const int64_t pk = (int64_t)arow * (arow + 1) / 2 + p;
+        g.mblk[pk * N + c] = acc;
+      }
+    return;
+  }
+  if (i >= N) return;
+  switch (g.kind) {
+    case HC_CONE_ZERO:
+      g.mblk[i] = 1.0 / delta;
+      break;
+    case HC_CONE_NONNEG:
+      g.mblk[i] = 1.0 / (g.state[i] + delta);
+      break;
+    case HC_CONE_SOC: {
+      const int d = g.dim;
+      double wb[SOC_DMAX], u[SOC_DMAX];
+      for (int j = 0; j < d; ++j) wb[j] = g.state[j * N + i];
+      const SocSpec sp = soc_spec(wb, d, g.state[d * N + i]);
+      for (int j = 1; j < d; ++j) u[j] = (sp.r > 0.0) ? wb[j] / sp.r : (j == 1 ? 1.0 : 0.0);
+      const double fp = 1.0 / (sp.lp + delta), fm = 1.0 / (sp.lm + delta), fo = 1.0 / (sp.lo + delta);
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b <= a; ++b) {
+          double v;
+          if (a == 0) v = 0.5 * (fp + fm);
+          else if (b == 0) v = 0.5 * (fp - fm) * u[a];
+          else v = 0.5 * (fp + fm) * u[a] * u[b] + fo * ((a == b ? 1.0 : 0.0) - u[a] * u[b]);
+          g.mblk[((int64_t)a * (a + 1) / 2 + b) * N + i] = v;
+        }
+      break;
+    }
+    case HC_CONE_EXP:
+    case HC_CONE_POW: {
+      double V[9], f[3];
+      for (int j = 0; j < 9; ++j) V[j] = g.state[(NS_V + j) * N + i];
+      for (int j = 0; j < 3; ++j) f[j] = 1.0 / (g.state[(NS_LAM + j) * N + i] + delta);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b <= a; ++b) {
+          double v = 0;
+          for (int r = 0; r < 3; ++r) v += V[a * 3 + r] * f[r] * V[b * 3 + r];
+          g.mblk[((int64_t)a * (a + 1) / 2 + b) * N + i] = v;
+        }
+      break;
+    }
+  }
+}
+
+void cone_mblock(const SegDev& g, double delta, hipStream_t st) {
+  if (g.count == 0) return;
+  int64_t units = (g.kind == HC_CONE_PSD) ? g.count * g.dim : g.count;
+  hipLaunchKernelGGL(k_cone_mblock, dim3((unsigned)std::max<int64_t>(1, ceil_div(units, CONE_BLOCK))),
+                     dim3(CONE_BLOCK), 0, st, g, delta);
+  HC_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// combined-step d_s (eq. ds-correction-step)
+// ===========================================================================
+__global__ void k_cone_ds(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+                          const double* __restrict__ dsa, const double* __restrict__ dza, double sm,
+                          double* __restrict__ ds) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.count) return;
+  const int64_t N = g.count;
+  switch (g.kind) {
+    case HC_CONE_ZERO:
+      ds[g.base + i] = 0.0;
+      break;
+    case HC_CONE_NONNEG: {
+      const int64_t r = g.base + i;
+      ds[r] = (s[r] * z[r] + dsa[r] * dza[r] - sm) / z[r];
+      break;
+    }
+    case HC_CONE_SOC: {
+      const int d = g.dim;
+      double wb[SOC_DMAX], lam[SOC_DMAX], a[SOC_DMAX], b[SOC_DMAX];
+      for (int j = 0; j < d; ++j) {
+        wb[j] = g.state[j * N + i];
+        lam[j] = g.state[(d + 1 + j) * N + i];
+        a[j] = dsa[g.base + j * N + i];
+        b[j] = dza[g.base + j * N + i];
+      }
+      const double eta = g.state[d * N + i];
+      // W^-T ds = W^-1 ds = eta^-1 J Wbar J ds ; W dz = eta Wbar dz
+      double Ja[SOC_DMAX], p[SOC_DMAX], q[SOC_DMAX];
+      for (int j = 0; j < d; ++j) Ja[j] = (j == 0) ? a[0] : -a[j];
+      double w1a = 0, w1b = 0;
+      for (int j = 1; j < d; ++j) {
+        w1a += wb[j] * Ja[j];
+        w1b += wb[j] * b[j];
+      }
+      p[0] = (wb[0] * Ja[0] + w1a) / eta;
+      const double cfa = Ja[0] + w1a / (1.0 + wb[0]);
+      for (int j = 1; j < d; ++j) p[j] = -(Ja[j] + cfa * wb[j]) / eta;   // J applied after Wbar
+      q[0] = eta * (wb[0] * b[0] + w1b);
+      const double cfb = b[0] + w1b / (1.0 + wb[0]);
+      for (int j = 1; j < d; ++j) q[j] = eta * (b[j] + cfb * wb[j]);
+      // v = lam o lam + p o q - sm e
+      double v[SOC_DMAX];
+      double ll = 0, pq = 0;
+      for (int j = 0; j < d; ++j) {
+        ll += lam[j] * lam[j];
+        pq += p[j] * q[j];
+      }
+      v[0] = ll + pq - sm;
+      for (int j = 1; j < d; ++j) v[j] = 2.0 * lam[0] * lam[j] + p[0] * q[j] + q[0] * p[j];
+      // x = lam \ v
+      double lJl = lam[0] * lam[0], l1v1 = 0;
+      for (int j = 1; j < d; ++j) {
+        lJl -= lam[j] * lam[j];
+        l1v1 += lam[j] * v[j];
+      }
+      double x[SOC_DMAX];
+      x[0] = (lam[0] * v[0] - l1v1) / lJl;
+      for (int j = 1; j < d; ++j) x[j] = (v[j] - x[0] * lam[j]) / lam[0];
+      // ds = W' x = eta Wbar x
+      double w1x = 0;
+      for (int j = 1; j < d; ++j) w1x += wb[j] * x[j];
+      ds[g.base + i] = eta * (wb[0] * x[0] + w1x);
+      const double cfx = x[0] + w1x / (1.0 + wb[0]);
+      for (int j = 1; j < d; ++j) ds[g.base + j * N + i] = eta * (x[j] + cfx * wb[j]);
+      break;
+    }
+    case HC_CONE_EXP:
+    case HC_CONE_POW: {
+      const bool is_exp = (g.kind == HC_CONE_EXP);
+      const double al = is_exp ? 0.0 : g.alpha[i];
+      double zv[3], sv[3], a[3], b[3], Uh[9], sig[3], gr[3];
+      for (int j = 0; j < 3; ++j) {
+        zv[j] = z[g.base + j * N + i];
+        sv[j] = s[g.base + j * N + i];
+        a[j] = dsa[g.base + j * N + i];
+        b[j] = dza[g.base + j * N + i];
+        sig[j] = g.state[(NS_SH + j) * N + i];
+        gr[j] = g.state[(NS_GRAD + j) * N + i];
+      }
+      for (int j = 0; j < 9; ++j) Uh[j] = g.state[(NS_UH + j) * N + i];
+      // u = Hess f^-1 ds_a
+      double pr[3], u[3];
+      for (int r = 0; r < 3; ++r) pr[r] = (Uh[0 * 3 + r] * a[0] + Uh[1 * 3 + r] * a[1] + Uh[2 * 3 + r] * a[2]) / (sig[r] * sig[r]);
+      for (int j = 0; j < 3; ++j) u[j] = Uh[j * 3 + 0] * pr[0] + Uh[j * 3 + 1] * pr[1] + Uh[j * 3 + 2] * pr[2];
+      double T[3];
+      if (is_exp) exp_third(zv, b, u, T); else pow_third(zv, al, b, u, T);
+      for (int j = 0; j < 3; ++j) ds[g.base + j * N + i] = sv[j] + sm * gr[j] - 0.5 * T[j];
+      break;
+    }
+    case HC_CONE_PSD: {
+      const int k = g.k, sd = g.dim;
+      const int64_t kk = (int64_t)k * k;
+      double R[PSD_KMAX * PSD_KMAX], Ri[PSD_KMAX * PSD_KMAX], lam[PSD_KMAX];
+      for (int r = 0; r < k; ++r)
+        for (int j = 0; j < k; ++j) {
+          R[r * PSD_KMAX + j] = g.state[(r * k + j) * N + i];
+          Ri[r * PSD_KMAX + j] = g.state[(kk + r * k + j) * N + i];
+        }
+      for (int j = 0; j < k; ++j) lam[j] = g.state[(3 * kk + j) * N + i];
+      double dS[PSD_KMAX * PSD_KMAX], dZ[PSD_KMAX * PSD_KMAX], T1[PSD_KMAX * PSD_KMAX], Aa[PSD_KMAX * PSD_KMAX],
+          Bb[PSD_KMAX * PSD_KMAX];
+      psd_smat(dsa + g.base + i * sd, k, dS);
+      psd_smat(dza + g.base + i * sd, k, dZ);
+      // Aa = Ri dS Ri'
+      for (int r = 0; r < k; ++r)
+        for (int j = 0; j < k; ++j) {
+          double acc = 0;
+          for (int p = 0; p < k; ++p) acc += Ri[r * PSD_KMAX + p] * dS[p * PSD_KMAX + j];
+          T1[r * PSD_KMAX + j] = acc;
+        }
+      for (int r = 0; r < k; ++r)
+        for (int j = 0; j < k; ++j) {
+          double acc = 0;
+          for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * Ri[j * PSD_KMAX + p];
+          Aa[r * PSD_KMAX + j] = acc;
+        }
+      // Bb = R' dZ R
+      for (int r = 0; r < k; ++r)
+        for (int j = 0; j < k; ++j) {
+          double acc = 0;
+          for (int p = 0; p < k; ++p) acc += R[p * PSD_KMAX + r] * dZ[p * PSD_KMAX + j];
+          T1[r * PSD_KMAX + j] = acc;
+        }
+      for (int r = 0; r < k; ++r)
+        for (int j = 0; j < k; ++j) {
+          double acc = 0;
+          for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * R[p * PSD_KMAX + j];
+          Bb[r * PSD_KMAX + j] = acc;
+        }
+      // V = (Aa Bb + Bb Aa)/2 + diag(lam^2) - sm I ;  X_ij = 2 V_ij / (lam_i + lam_j)
+      double X[PSD_KMAX * PSD_KMAX];
+      for (int r = 0; r < k; ++r)
+        for (int j = 0; j < k; ++j) {
+          double acc = 0;
+          for (int p = 0; p < k; ++p) acc += Aa[r * PSD_KMAX + p] * Bb[p * PSD_KMAX + j] + Bb[r * PSD_KMAX + p] * Aa[p * PSD_KMAX + j];
+          double v = 0.5 * acc;
+          if (r == j) v += lam[r] * lam[r] - sm;
+          X[r * PSD_KMAX + j] = 2.0 * v / (lam[r] + lam[j]);
+        }
+      // ds = svec(R X R')
+      for (int r = 0; r < k; ++r)
+        for (int j = 0; j < k; ++j) {
+          double acc = 0;
+          for (int p = 0; p < k; ++p) acc += R[r * PSD_KMAX + p] * X[p * PSD_KMAX + j];
+          T1[r * PSD_KMAX + j] = acc;
+        }
+      for (int r = 0; r < k; ++r)
+        for (int j = 0; j < k; ++j) {
+          double acc = 0;
+          for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * R[j * PSD_KMAX + p];
+          X[r * PSD_KMAX + j] = acc;
+        }
+      psd_svec(X, k, ds + g.base + i * sd);
+      break;
+    }
+  }
+}
+
+void cone_ds_combined(const SegDev& g, const double* s, const double* z, const double* dsa, const double* dza,
+                      double sm, double* ds, hipStream_t st) {
+  if (g.count == 0) return;
+  hipLaunchKernelGGL(k_cone_ds, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, s, z, dsa, dza, sm, ds);
+  HC_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// step lengths
+// ===========================================================================
+__device__ inline double soc_step_one(const double* x, const double* dx, int d) {
+  double a = dx[0] * dx[0], b = x[0] * dx[0], c = x[0] * x[0];
+  for (int j = 1; j < d; ++j) {
+    a -= dx[j] * dx[j];
+    b -= x[j] * dx[j];
+    c -= x[j] * x[j];
+  }
+  // smallest positive root of a t^2 + (2b) t + c = 0
+  const double B = 2.0 * b;
+  double best = INFINITY;
+  if (a == 0.0) {
+    if (B != 0.0) {
+      const double t = -c / B;
+      if (t > 0.0) best = t;
+    }
+    return best;
+  }
+  const double disc = B * B - 4.0 * a * c;
+  if (disc < 0.0) return best;
+  const double qq = -0.5 * (B + copysign(sqrt(disc), B));
+  if (qq != 0.0) {
+    const double r1 = qq / a, r2 = c / qq;
+    if (r1 > 0.0) best = fmin(best, r1);
+    if (r2 > 0.0) best = fmin(best, r2);
+  }
+  return best;
+}
+
+__device__ double psd_step_one(const double* x, const double* dx, int k) {
+  double L[PSD_KMAX * PSD_KMAX], D[PSD_KMAX * PSD_KMAX], T[PSD_KMAX * PSD_KMAX];
+  psd_smat(x, k, L);
+  psd_smat(dx, k, D);
+  if (!psd_chol(L, k)) return 0.0;
+  // T = L^-1 D, then Mm = T L^-T  (two triangular solves)
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i < k; ++i) {
+      double v = D[i * PSD_KMAX + j];
+      for (int p = 0; p < i; ++p) v -= L[i * PSD_KMAX + p] * T[p * PSD_KMAX + j];
+      T[i * PSD_KMAX + j] = v / L[i * PSD_KMAX + i];
+    }
+  // Mm = (L^-1 T')' : solve L Y = T' column by column, Mm = Y'
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i < k; ++i) {
+      double v = T[j * PSD_KMAX + i];
+      for (int p = 0; p < i; ++p) v -= L[i * PSD_KMAX + p] * D[p * PSD_KMAX + j];
+      D[i * PSD_KMAX + j] = v / L[i * PSD_KMAX + i];   // D now holds Y
+    }
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) T[i * PSD_KMAX + j] = 0.5 * (D[i * PSD_KMAX + j] + D[j * PSD_KMAX + i]);
+  const double lmin = psd_min_eig(T, k);
+  return (lmin < 0.0) ? -1.0 / lmin : INFINITY;
+}
+
+__global__ void k_step_sym(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+                           const double* __restrict__ ds, const double* __restrict__ dz, double* __restrict__ partial) {
+  __shared__ double red[CONE_BLOCK];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = g.count;
+  double a = INFINITY;
+  if (i < N) {
+    if (g.kind == HC_CONE_NONNEG) {
+      const int64_t r = g.base + i;
+      if (ds[r] < 0.0) a = fmin(a, -s[r] / ds[r]);
+      if (dz[r] < 0.0) a = fmin(a, -z[r] / dz[r]);
+    } else if (g.kind == HC_CONE_SOC) {
+      const int d = g.dim;
+      double xs[SOC_DMAX], xds[SOC_DMAX], xz[SOC_DMAX], xdz[SOC_DMAX];
+      for (int j = 0; j < d; ++j) {
+        xs[j] = s[g.base + j * N + i];
+        xds[j] = ds[g.base + j * N + i];
+        xz[j] = z[g.base + j * N + i];
+        xdz[j] = dz[g.base + j * N + i];
+      }
+      a = fmin(soc_step_one(xs, xds, d), soc_step_one(xz, xdz, d));
+    } else if (g.kind == HC_CONE_PSD) {
+      const int sd = g.dim;
+      a = fmin(psd_step_one(s + g.base + i * sd, ds + g.base + i * sd, g.k),
+               psd_step_one(z + g.base + i * sd, dz + g.base + i * sd, g.k));
+    }
+  }
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = CONE_BLOCK / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+int cone_step_sym(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz,
+                  double* partial, hipStream_t st) {
+  if (g.count == 0 || g.kind == HC_CONE_ZERO || g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) return 0;
+  const int nb = cone_blocks(g);
+  hipLaunchKernelGGL(k_step_sym, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, ds, dz, partial);
+  HC_LAUNCH_CHECK();
+  return nb;
+}
+
+struct Trials {
+  double a[8];
+};
+
+__global__ void k_trial_nonsym(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+                               const double* __restrict__ ds, const double* __restrict__ dz, Trials tr, int ntrial,
+                               int check_nbhd, double beta, double c0, double c1, double c2, double nu1,
+                               unsigned long long* __restrict__ partial) {
+  __shared__ unsigned long long red[CONE_BLOCK];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = g.count;
+  unsigned long long mask = (ntrial >= 64) ? ~0ull : ((1ull << ntrial) - 1ull);
+  if (i < N) {
+    const bool is_exp = (g.kind == HC_CONE_EXP);
+    const double al = is_exp ? 0.0 : g.alpha[i];
+    double sv[3], zv[3], dsv[3], dzv[3];
+    for (int j = 0; j < 3; ++j) {
+      sv[j] = s[g.base + j * N + i];
+      zv[j] = z[g.base + j * N + i];
+      dsv[j] = ds[g.base + j * N + i];
+      dzv[j] = dz[g.base + j * N + i];
+    }
+    mask = 0;
+    for (int t = 0; t < ntrial; ++t) {
+      const double a = tr.a[t];
+      double sa[3], za[3];
+      for (int j = 0; j < 3; ++j) {
+        sa[j] = sv[j] + a * dsv[j];
+        za[j] = zv[j] + a * dzv[j];
+      }
+      bool ok = is_exp ? (exp_primal_in(sa) && exp_dual_in(za)) : (pow_primal_in(sa, al) && pow_dual_in(za, al));
+      if (ok && check_nbhd) {
+        double gz[3], zt[3];
+        if (is_exp) exp_grad(za, gz); else pow_grad(za, al, gz);
+        const bool cok = is_exp ? exp_conj(sa, zt) : pow_conj(sa, al, zt);
+        const double inner = -(gz[0] * zt[0] + gz[1] * zt[1] + gz[2] * zt[2]);
+        const double mua = (c0 + a * (c1 + a * c2)) / nu1;
+        ok = cok && (3.0 / inner >= beta * mua);
+      }
+      if (ok) mask |= (1ull << t);
+    }
+  }
+  red[threadIdx.x] = mask;
+  __syncthreads();
+  for (int off = CONE_BLOCK / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] &= red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+int cone_trial_nonsym(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz,
+                      double a0, double ratio, int ntrial, int check_nbhd, double beta, double c0, double c1,
+                      double c2, double nu1, unsigned long long* partial, hipStream_t st) {
+  if (g.count == 0) return 0;
+  Trials tr;
+  double a = a0;
+  for (int t = 0; t < 8; ++t) {
+    tr.a[t] = a;
+    a *= ratio;
+  }
+  const int nb = cone_blocks(g);
+  hipLaunchKernelGGL(k_trial_nonsym, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, ds, dz, tr, std::min(ntrial, 8),
+                     check_nbhd, beta, c0, c1, c2, nu1, partial);
+  HC_LAUNCH_CHECK();
+  return nb;
+}
+
+// ===========================================================================
+// initial point helpers
+// ===========================================================================
+__global__ void k_cone_unit(SegDev g, double* __restrict__ v, double e0, double e1, double e2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = g.count;
+  if (i >= N) return;
+  switch (g.kind) {
+    case HC_CONE_ZERO: v[g.base + i] = 0.0; break;
+    case HC_CONE_NONNEG: v[g.base + i] = 1.0; break;
+    case HC_CONE_SOC:
+      for (int j = 0; j < g.dim; ++j) v[g.base + j * N + i] = (j == 0) ? 1.0 : 0.0;
+      break;
+    case HC_CONE_EXP:
+      v[g.base + i] = e0; v[g.base + N + i] = e1; v[g.base + 2 * N + i] = e2;
+      break;
+    case HC_CONE_POW: {
+      const double a = g.alpha[i];
+      v[g.base + i] = sqrt(1.0 + a); v[g.base + N + i] = sqrt(2.0 - a); v[g.base + 2 * N + i] = 0.0;
+      break;
+    }
+    case HC_CONE_PSD: {
+      int p = 0;
+      for (int j = 0; j < g.k; ++j)
+        for (int r = 0; r <= j; ++r, ++p) v[g.base + i * g.dim + p] = (r == j) ? 1.0 : 0.0;
+      break;
+    }
+  }
+}
+
+// the unit point of the exp cone: u = -grad f(u), by Newton on the host
+static void exp_unit_point(double* u) {
+  double z[3] = {-1.0513839, 0.5564096, 1.2589679};
+  for (int it = 0; it < 60; ++it) {
+    // F(z) = z + grad f(z); J = I + Hess f(z) (closed forms, host copy)
+    const double z1 = z[0], z2 = z[1], z3 = z[2];
+    const double ell = std::log(z3 / (-z1));
+    const double psi = z2 - z1 - z1 * ell;
+    const double g[3] = {ell / psi - 1.0 / z1, -1.0 / psi, (z1 / z3) / psi - 1.0 / z3};
+    const double dps[3] = {-ell, 1.0, -z1 / z3};
+    const double D2[9] = {1.0 / z1, 0.0, -1.0 / z3, 0.0, 0.0, 0.0, -1.0 / z3, 0.0, z1 / (z3 * z3)};
+    double J[9];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        J[a * 3 + b] = (a == b ? 1.0 : 0.0) - D2[a * 3 + b] / psi + dps[a] * dps[b] / (psi * psi) +
+                       (a == b && a == 0 ? 1.0 / (z1 * z1) : 0.0) + (a == b && a == 2 ? 1.0 / (z3 * z3) : 0.0);
+    double F[3] = {z[0] + g[0], z[1] + g[1], z[2] + g[2]};
+    // solve J d = F (Cramer)
+    const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                       J[2] * (J[3] * J[7] - J[4] * J[6]);
+    double d[3];
+    for (int c = 0; c < 3; ++c) {
+      double M[9];
+      for (int a = 0; a < 9; ++a) M[a] = J[a];
+      for (int a = 0; a < 3; ++a) M[a * 3 + c] = F[a];
+      d[c] = (M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
+              M[2] * (M[3] * M[7] - M[4] * M[6])) / det;
+    }
+    for (int c = 0; c < 3; ++c) z[c] -= d[c];
+  }
+  for (int c = 0; c < 3; ++c) u[c] = z[c];
+}
+
+void cone_unit(const SegDev& g, double* v, hipStream_t st) {
+  if (g.count == 0) return;
+  static double eu[3] = {0, 0, 0};
+  if (eu[0] == 0.0) exp_unit_point(eu);
+  hipLaunchKernelGGL(k_cone_unit, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, v, eu[0], eu[1], eu[2]);
+  HC_LAUNCH_CHECK();
+}
+
+__global__ void k_max_neg_eig(SegDev g, const double* __restrict__ v, double* __restrict__ partial) {
+  __shared__ double red[CONE_BLOCK];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = g.count;
+  double a = -INFINITY;
+  if (i < N) {
+    if (g.kind == HC_CONE_NONNEG) {
+      a = -v[g.base + i];
+    } else if (g.kind == HC_CONE_SOC) {
+      double nx = 0;
+      for (int j = 1; j < g.dim; ++j) nx += sq(v[g.base + j * N + i]);
+      a = sqrt(nx) - v[g.base + i];
+    } else if (g.kind == HC_CONE_PSD) {
+      double X[PSD_KMAX * PSD_KMAX];
+      psd_smat(v + g.base + i * g.dim, g.k, X);
+      a = -psd_min_eig(X, g.k);
+    }
+  }
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = CONE_BLOCK / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+int cone_max_neg_eig(const SegDev& g, const double* v, double* partial, hipStream_t st) {
+  if (g.count == 0 || !(g.kind == HC_CONE_NONNEG || g.kind == HC_CONE_SOC || g.kind == HC_CONE_PSD)) return 0;
+  const int nb = cone_blocks(g);
+  hipLaunchKernelGGL(k_max_neg_eig, dim3(nb), dim3(CONE_BLOCK), 0, st, g, v, partial);
+  HC_LAUNCH_CHECK();
+  return nb;
+}
+
+__global__ void k_add_e(SegDev g, double a, double* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = g.count;
+  if (i >= N) return;
+  if (g.kind == HC_CONE_NONNEG) v[g.base + i] += a;
+  else if (g.kind == HC_CONE_SOC) v[g.base + i] += a;
+  else if (g.kind == HC_CONE_PSD) {
+    int p = 0;
+    for (int j = 0; j < g.k; ++j)
+      for (int r = 0; r <= j; ++r, ++p)
+        if (r == j) v[g.base + i * g.dim + p] += a;
+  }
+}
+
+void cone_add_e(const SegDev& g, double a, double* v, hipStream_t st) {
+  if (g.count == 0) return;
+  hipLaunchKernelGGL(k_add_e, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, a, v);
+  HC_LAUNCH_CHECK();
+}
+
+}  // namespace hc
+
+namespace hc {
+
+// ===========================================================================
+// kernel test support: per-cone views of the state and per-cone steps
+// ===========================================================================
+__global__ void k_test_extract(SegDev g, const double* __restrict__ s, int what, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = g.count;
+  if (i >= N) return;
+  if (what == 2) {   // exp/pow branch
+    out[i] = (g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) ? g.state[NS_BR * N + i] : 0.0;
+    return;
+  }
+  switch (g.kind) {
+    case HC_CONE_ZERO: out[i] = 0.0; break;
+    case HC_CONE_NONNEG: out[i] = g.state[i]; break;
+    case HC_CONE_SOC:
+      for (int j = 0; j < g.dim; ++j) out[j * N + i] = g.state[(g.dim + 1 + j) * N + i];
+      break;
+    case HC_CONE_EXP:
+    case HC_CONE_POW: {
+      double sv[3], zt[3] = {NAN, NAN, NAN};
+      for (int j = 0; j < 3; ++j) sv[j] = s[g.base + j * N + i];
+      if (g.kind == HC_CONE_EXP) exp_conj(sv, zt); else pow_conj(sv, g.alpha[i], zt);
+      for (int j = 0; j < 3; ++j) out[j * N + i] = zt[j];
+      break;
+    }
+    case HC_CONE_PSD: {
+      const int64_t kk = (int64_t)g.k * g.k;
+      for (int j = 0; j < g.dim; ++j) out[i * g.dim + j] = (j < g.k) ? g.state[(3 * kk + j) * N + i] : 0.0;
+      break;
+    }
+  }
+}
+
+void cone_test_extract(const SegDev& g, const double* s, int what, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_test_extract, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, s, what, out);
+  HC_LAUNCH_CHECK();
+}
+
+__global__ void k_test_step(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+                            const double* __restrict__ ds, const double* __restrict__ dz, double amax,
+                            double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = g.count;
+  if (i >= N) return;
+  double a = amax;
+  if (g.kind == HC_CONE_NONNEG) {
+    const int64_t r = g.base + i;
+    if (ds[r] < 0.0) a = fmin(a, -s[r] / ds[r]);
+    if (dz[r] < 0.0) a = fmin(a, -z[r] / dz[r]);
+  } else if (g.kind == HC_CONE_SOC) {
+    double xs[SOC_DMAX], xds[SOC_DMAX], xz[SOC_DMAX], xdz[SOC_DMAX];
+    for (int j = 0; j < g.dim; ++j) {
+      xs[j] = s[g.base + j * N + i];
+      xds[j] = ds[g.base + j * N + i];
+      xz[j] = z[g.base + j * N + i];
+      xdz[j] = dz[g.base + j * N + i];
+    }
+    a = fmin(a, fmin(soc_step_one(xs, xds, g.dim), soc_step_one(xz, xdz, g.dim)));
+  } else if (g.kind == HC_CONE_PSD) {
+    a = fmin(a, fmin(psd_step_one(s + g.base + i * g.dim, ds + g.base + i * g.dim, g.k),
+                     psd_step_one(z + g.base + i * g.dim, dz + g.base + i * g.dim, g.k)));
+  } else if (g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) {
+    const double al = (g.kind == HC_CONE_POW) ? g.alpha[i] : 0.0;
+    double t = amax;
+    a = 0.0;
+    for (int j = 0; j < 64; ++j) {
+      double sa[3], za[3];
+      for (int c = 0; c < 3; ++c) {
+        sa[c] = s[g.base + c * N + i] + t * ds[g.base + c * N + i];
+        za[c] = z[g.base + c * N + i] + t * dz[g.base + c * N + i];
+      }
+      const bool ok = (g.kind == HC_CONE_EXP) ? (exp_primal_in(sa) && exp_dual_in(za))
+                                              : (pow_primal_in(sa, al) && pow_dual_in(za, al));
+      if (ok) {
+        a = t;
+        break;
+      }
+      t *= 0.8;
+    }
+  }
+  out[i] = a;
+}
+
+void cone_test_step(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz,
+                    double amax, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_test_step, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, s, z, ds, dz, amax, out);
+  HC_LAUNCH_CHECK();
+}
+
+}  // namespace hc

@@ -1,0 +1,24 @@
+// Dense Cholesky of the KKT Schur complement and triangular solves (gfx950).
+#pragma once
+#include "hc_common.h"
+
+namespace hc {
+// In-place lower Cholesky of the n x n column-major S (leading dim ld).
+// Linv receives the inverses of the 64 x 64 diagonal factor blocks
+// (linv_elems(n) entries).  Pivots <= tol are replaced by fix and counted.
+template <typename T>
+void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
+                    hipStream_t st);
+// X = L^-T L^-1 B for nrhs <= 4 right-hand sides (column-major, leading dim
+// n); B and Y are overwritten (Y receives the forward result).
+template <typename T>
+void dense_solve(const T* L, int64_t n, int64_t ld, const T* Linv, T* B, T* Y, T* X, int nrhs, hipStream_t st);
+// C[i, j] += alpha * sum_k A[i, k] B[j, k] (column-major operands); with
+// `lower`, tiles strictly above the diagonal of the global matrix (C[0,0] at
+// global (gr, gc)) are skipped.
+template <typename T>
+void gemm_nt(T* C, int64_t ldc, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t M, int64_t N, int64_t K,
+             T alpha, bool lower, int64_t gr, int64_t gc, hipStream_t st);
+int64_t linv_elems(int64_t n);
+double cholesky_flops(int64_t n);
+}  // namespace hc

@@ -1,0 +1,1317 @@
+// hipcone solver: setup on the host, every per-iteration step on the GPU.
+//
+// Algorithm 1 (Sec. 3.2) step by step; the host holds only scalars (tau,
+// kappa, step lengths, reduction results) and launches the kernels of the
+// cone layer (hc_cones.hip), the vector/sparse layer (hc_vec.hip) and the
+// dense factorisation of the KKT Schur complement (hc_dense.hip).
+//
+// Readings where the paper is silent or inconsistent (same as the design
+// notes):
+//   * Delta tau uses the first printed form of eq. step-direction;
+//   * affine d: d_kappa = kappa tau, d_s = s;
+//   * regularisation: +delta on the P block, -delta on the -H block;
+//     delta = delta_s + delta_d max_i |K_ii|;
+//   * refinement: first solve + at most ir_max corrections, stop on the
+//     tolerance or when a correction fails to halve the residual; FP32
+//     right-hand sides are scaled by 1/||r||_inf;
+//   * step rule: alpha_0 = min(1, tau/kappa ratio tests, symmetric-cone
+//     boundary steps), then x0.8 backtracking while an exp/pow cone leaves its
+//     interior or (combined step) violates N(beta); zero below 1e-10;
+//   * alpha_c < 0.1 with a primal-dual exp/pow scaling -> the iteration is
+//     redone with the dual scaling; alpha_c < 1e-4 -> insufficient progress;
+//   * equilibration: 10 modified Ruiz passes (factors clamped to
+//     [1e-4, 1e4], row factors averaged over each SOC/exp/pow/PSD cone), cost
+//     scale 1/max(1, mean column max of P, |Dq|_inf);
+//   * dual-infeasibility test multiplies by q'x.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+
+#include "hc_cones.h"
+#include "hc_dense.h"
+#include "hc_vec.h"
+
+using namespace hc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct HostCsr {
+  int64_t nrows = 0, ncols = 0;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v;
+};
+
+struct Buf {   // bump allocator over one device block; `dry` only counts bytes
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  bool dry = false;
+  template <typename T> T* take(size_t count) {
+    size_t bytes = ((std::max<size_t>(count, 1) * sizeof(T) + 255) / 256) * 256;
+    if (!dry && used + bytes > size) throw Error{HC_ERR_OOM, "device arena exhausted"};
+    T* p = dry ? nullptr : reinterpret_cast<T*>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
+}  // namespace
+
+struct hc_solver {
+  hc_settings st{};
+  int64_t n = 0, m = 0;
+  // ---- host setup products
+  std::vector<int64_t> perm;       // internal row -> user row
+  std::vector<Segment> segs;
+  std::vector<double> alpha_pow;   // POW exponents in segment order
+  HostCsr A, At, P;                // scaled, internal order (A without dense rows)
+  std::vector<double> Ad;          // dense rows, row-major nd x n
+  std::vector<int32_t> drows;      // their internal rows
+  std::vector<int64_t> dmidx;      // their M index
+  std::vector<double> q, b, D, E;  // scaled q, b; equilibration factors
+  double cscale = 1.0;
+  double bnorm_user = 0, qnorm_user = 0, maxPdiag = 0;
+  int64_t nu = 0;                  // cone degree
+  bool has_nonsym = false;
+  std::vector<int32_t> tra, trb;   // Schur assembly tasks
+  std::vector<int64_t> tm;
+  int64_t mtotal = 0, stotal = 0;  // M entries, state entries
+  int64_t ld = 0;
+  bool mixed = false;
+  // ---- device
+  bool bound = false;
+  bool own_mem = false;
+  void* mem = nullptr;
+  size_t mem_bytes = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Csr dA, dAt, dP;
+  double *dAd = nullptr, *dBd = nullptr;
+  int32_t* ddrows = nullptr;
+  int64_t* ddmidx = nullptr;
+  double *dq = nullptr, *db = nullptr, *dD = nullptr, *dE = nullptr, *dalpha = nullptr;
+  int32_t *dtra = nullptr, *dtrb = nullptr;
+  int64_t* dtm = nullptr;
+  double *dstate = nullptr, *dmval = nullptr, *dhdiag = nullptr;
+  double* dS = nullptr;
+  double* dLinv = nullptr;
+  float *dS32 = nullptr, *dLinv32 = nullptr;
+  unsigned long long* dhits = nullptr;
+  int* dpd = nullptr;
+  double* dscal = nullptr;          // device scalars (FP32 rhs scale)
+  double* dpart = nullptr;          // reduction partials
+  double* hpart = nullptr;          // pinned host copy
+  unsigned long long *dmask = nullptr, *hmask = nullptr;
+  // iterate and work vectors
+  double *x, *s, *z;
+  double tau = 1, kappa = 1;
+  double *Px, *Ax, *Atz, *rdv, *rpv;   // rdv = Px + A'z + q tau ; rpv = -Ax - s + b tau
+  double *x2, *z2, *x1, *z1, *dx, *dz, *dsv, *dsrhs, *dxa, *dza, *dsa;
+  double *r1, *r2, *irx, *irz, *irxn, *irzn, *irbx, *irbz, *irrx, *irrz, *kx, *kz, *t1, *t2, *u1, *w1;
+  double *sb, *sy, *sx;             // dense solve buffers (n)
+  float *sb32, *sy32, *sx32;
+  std::vector<SegDev> sdev;
+  // ---- results
+  hc_info info{};
+  int status = 0;
+  double delta = 0;
+  double xPx_cache = 0;             // x'Px of the current iterate (from residuals)
+  std::string last_error;
+};
+
+namespace {
+
+// ===========================================================================
+// setup
+// ===========================================================================
+void fail(int32_t code, const std::string& msg) { throw Error{code, msg}; }
+
+void validate(const hc_problem* p) {
+  if (!p) fail(HC_ERR_INVALID_ARG, "problem is NULL");
+  if (p->n <= 0 || p->m <= 0) fail(HC_ERR_DIM, "n and m must be positive");
+  if (p->n >= (int64_t)1 << 31 || p->m >= (int64_t)1 << 31) fail(HC_ERR_UNSUPPORTED, "n or m exceeds 2^31");
+  if (!p->q || !p->b || !p->A_rowptr || !p->cones || p->ncones <= 0) fail(HC_ERR_INVALID_ARG, "NULL array");
+  const int64_t nnzA = p->A_rowptr[p->m];
+  if (nnzA > 0 && (!p->A_col || !p->A_val)) fail(HC_ERR_INVALID_ARG, "A arrays NULL");
+  if (nnzA >= (int64_t)1 << 31) fail(HC_ERR_UNSUPPORTED, "nnz(A) exceeds 2^31");
+  if (p->A_rowptr[0] != 0) fail(HC_ERR_CSR, "A rowptr[0] != 0");
+  for (int64_t i = 0; i < p->m; ++i) {
+    if (p->A_rowptr[i + 1] < p->A_rowptr[i]) fail(HC_ERR_CSR, "A rowptr decreasing");
+    for (int64_t k = p->A_rowptr[i]; k < p->A_rowptr[i + 1]; ++k) {
+      if (p->A_col[k] < 0 || p->A_col[k] >= p->n) fail(HC_ERR_CSR, "A column out of range");
+      if (k > p->A_rowptr[i] && p->A_col[k] <= p->A_col[k - 1]) fail(HC_ERR_CSR, "A columns unsorted or duplicate");
+      if (!std::isfinite(p->A_val[k])) fail(HC_ERR_NONFINITE, "A has a non-finite value");
+    }
+  }
+  if (p->P_rowptr) {
+    if (p->P_rowptr[0] != 0) fail(HC_ERR_CSR, "P rowptr[0] != 0");
+    const int64_t nnzP = p->P_rowptr[p->n];
+    if (nnzP > 0 && (!p->P_col || !p->P_val)) fail(HC_ERR_INVALID_ARG, "P arrays NULL");
+    for (int64_t i = 0; i < p->n; ++i) {
+      if (p->P_rowptr[i + 1] < p->P_rowptr[i]) fail(HC_ERR_CSR, "P rowptr decreasing");
+      for (int64_t k = p->P_rowptr[i]; k < p->P_rowptr[i + 1]; ++k) {
+        if (p->P_col[k] < i || p->P_col[k] >= p->n) fail(HC_ERR_CSR, "P entry below the diagonal or out of range");
+        if (k > p->P_rowptr[i] && p->P_col[k] <= p->P_col[k - 1]) fail(HC_ERR_CSR, "P columns unsorted or duplicate");
+        if (!std::isfinite(p->P_val[k])) fail(HC_ERR_NONFINITE, "P has a non-finite value");
+      }
+    }
+  }
+  for (int64_t j = 0; j < p->n; ++j)
+    if (!std::isfinite(p->q[j])) fail(HC_ERR_NONFINITE, "q has a non-finite value");
+  for (int64_t i = 0; i < p->m; ++i)
+    if (!std::isfinite(p->b[i])) fail(HC_ERR_NONFINITE, "b has a non-finite value");
+  int64_t rows = 0;
+  int psd_k = -1;
+  for (int c = 0; c < p->ncones; ++c) {
+    const hc_cone& k = p->cones[c];
+    switch (k.type) {
+      case HC_CONE_ZERO:
+      case HC_CONE_NONNEG:
+        if (k.dim < 1) fail(HC_ERR_CONE, "zero/nonneg dim < 1");
+        rows += k.dim;
+        break;
+      case HC_CONE_SOC:
+        if (k.dim < 2) fail(HC_ERR_CONE, "SOC dim < 2");
+        if (k.dim > 16) fail(HC_ERR_UNSUPPORTED, "SOC dim > 16 is not handled by this build");
+        rows += k.dim;
+        break;
+      case HC_CONE_EXP:
+        if (k.dim != 3) fail(HC_ERR_CONE, "EXP dim != 3");
+        rows += 3;
+        break;
+      case HC_CONE_POW:
+        if (k.dim != 3) fail(HC_ERR_CONE, "POW dim != 3");
+        if (!(k.alpha > 0.0 && k.alpha < 1.0)) fail(HC_ERR_CONE, "POW alpha outside (0,1)");
+        rows += 3;
+        break;
+      case HC_CONE_PSD:
+        if (k.dim < 1 || k.dim > 32) fail(HC_ERR_CONE, "PSD side outside [1, 32]");
+        if (psd_k >= 0 && psd_k != k.dim) fail(HC_ERR_CONE, "PSD sides unequal");
+        if (k.dim > 12) fail(HC_ERR_UNSUPPORTED, "PSD side > 12 is not handled by this build");
+        psd_k = k.dim;
+        rows += (int64_t)k.dim * (k.dim + 1) / 2;
+        break;
+      default:
+        fail(HC_ERR_CONE, "unknown cone type");
+    }
+  }
+  if (rows != p->m) fail(HC_ERR_DIM, "cone rows do not add up to m");
+}
+
+void build_segments(hc_solver* S, const hc_problem* p) {
+  std::vector<int64_t> zero_rows, nn_rows, exp_st, pow_st, psd_st;
+  std::vector<double> pow_a;
+  std::map<int, std::vector<int64_t>> soc_st;
+  int psd_k = 0;
+  int64_t r = 0;
+  for (int c = 0; c < p->ncones; ++c) {
+    const hc_cone& k = p->cones[c];
+    switch (k.type) {
+      case HC_CONE_ZERO: for (int j = 0; j < k.dim; ++j) zero_rows.push_back(r + j); r += k.dim; break;
+      case HC_CONE_NONNEG: for (int j = 0; j < k.dim; ++j) nn_rows.push_back(r + j); r += k.dim; break;
+      case HC_CONE_SOC: soc_st[k.dim].push_back(r); r += k.dim; break;
+      case HC_CONE_EXP: exp_st.push_back(r); r += 3; break;
+      case HC_CONE_POW: pow_st.push_back(r); pow_a.push_back(k.alpha); r += 3; break;
+      case HC_CONE_PSD: psd_st.push_back(r); psd_k = k.dim; r += (int64_t)k.dim * (k.dim + 1) / 2; break;
+    }
+  }
+  S->perm.assign(S->m, -1);
+  int64_t base = 0, state = 0, moff = 0;
+  auto add = [&](int kind, int64_t count, int dim, int k) {
+    Segment g{kind, base, count, dim, k, state, moff};
+    S->segs.push_back(g);
+    const int64_t units = (kind == HC_CONE_ZERO || kind == HC_CONE_NONNEG) ? count : count;
+    state += state_doubles(kind, dim, k) * units;
+    moff += mblock_doubles(kind, dim) * units;
+    base += (kind == HC_CONE_ZERO || kind == HC_CONE_NONNEG) ? count : count * dim;
+  };
+  if (!zero_rows.empty()) {
+    for (size_t i = 0; i < zero_rows.size(); ++i) S->perm[base + i] = zero_rows[i];
+    add(HC_CONE_ZERO, zero_rows.size(), 1, 0);
+  }
+  if (!nn_rows.empty()) {
+    for (size_t i = 0; i < nn_rows.size(); ++i) S->perm[base + i] = nn_rows[i];
+    add(HC_CONE_NONNEG, nn_rows.size(), 1, 0);
+  }
+  for (auto& kv : soc_st) {
+    const int d = kv.first;
+    const int64_t N = kv.second.size();
+    for (int64_t i = 0; i < N; ++i)
+      for (int j = 0; j < d; ++j) S->perm[base + j * N + i] = kv.second[i] + j;
+    add(HC_CONE_SOC, N, d, 0);
+  }
+  if (!exp_st.empty()) {
+    const int64_t N = exp_st.size();
+    for (int64_t i = 0; i < N; ++i)
+      for (int j = 0; j < 3; ++j) S->perm[base + j * N + i] = exp_st[i] + j;
+    add(HC_CONE_EXP, N, 3, 0);
+  }
+  if (!pow_st.empty()) {
+    const int64_t N = pow_st.size();
+    for (int64_t i = 0; i < N; ++i)
+      for (int j = 0; j < 3; ++j) S->perm[base + j * N + i] = pow_st[i] + j;
+    S->alpha_pow = pow_a;
+    add(HC_CONE_POW, N, 3, 0);
+  }
+  if (!psd_st.empty()) {
+    const int64_t N = psd_st.size();
+    const int sd = psd_k * (psd_k + 1) / 2;
+    for (int64_t i = 0; i < N; ++i)
+      for (int j = 0; j < sd; ++j) S->perm[base + i * sd + j] = psd_st[i] + j;
+    add(HC_CONE_PSD, N, sd, psd_k);
+  }
+  S->stotal = state;
+  S->mtotal = moff;
+  S->nu = 0;
+  for (auto& g : S->segs) {
+    if (g.kind == HC_CONE_NONNEG) S->nu += g.count;
+    else if (g.kind == HC_CONE_SOC) S->nu += g.count;
+    else if (g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) S->nu += 3 * g.count;
+    else if (g.kind == HC_CONE_PSD) S->nu += (int64_t)g.k * g.count;
+    if (g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) S->has_nonsym = true;
+  }
+}
+
+// internal row -> (segment index, cone index, local component)
+struct RowLoc {
+  int seg;
+  int64_t cone;
+  int comp;
+};
+RowLoc locate(const hc_solver* S, int64_t r) {
+  for (int gi = 0; gi < (int)S->segs.size(); ++gi) {
+    const Segment& g = S->segs[gi];
+    const int64_t rows = (g.kind == HC_CONE_ZERO || g.kind == HC_CONE_NONNEG) ? g.count : g.count * g.dim;
+    if (r >= g.base && r < g.base + rows) {
+      const int64_t o = r - g.base;
+      if (g.kind == HC_CONE_ZERO || g.kind == HC_CONE_NONNEG) return {gi, o, 0};
+      if (g.kind == HC_CONE_PSD) return {gi, o / g.dim, (int)(o % g.dim)};
+      return {gi, o % g.count, (int)(o / g.count)};
+    }
+  }
+  return {-1, 0, 0};
+}
+
+void equilibrate(hc_solver* S, const HostCsr& A, const HostCsr& Pf, const std::vector<double>& q) {
+  const int64_t n = S->n, m = S->m;
+  S->D.assign(n, 1.0);
+  S->E.assign(m, 1.0);
+  S->cscale = 1.0;
+  if (!S->st.equilibrate) return;
+  const double lo = 1e-4, hi = 1e4;
+  auto clampv = [&](double v) { return std::min(std::max(v, lo), hi); };
+  std::vector<double> colP(n), colA(n), rowA(m), d(n), e(m);
+  for (int it = 0; it < S->st.equil_iters; ++it) {
+    std::fill(colP.begin(), colP.end(), 0.0);
+    std::fill(colA.begin(), colA.end(), 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int32_t k = Pf.rp[i]; k < Pf.rp[i + 1]; ++k) {
+        const int32_t j = Pf.ci[k];
+        colP[j] = std::max(colP[j], std::fabs(S->D[i] * Pf.v[k] * S->D[j]));
+      }
+    for (int64_t i = 0; i < m; ++i) {
+      double rmax = 0;
+      for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int32_t j = A.ci[k];
+        const double v = std::fabs(S->E[i] * A.v[k] * S->D[j]);
+        colA[j] = std::max(colA[j], v);
+        rmax = std::max(rmax, v);
+      }
+      rowA[i] = rmax;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+      const double cn = std::max(colP[j], colA[j]);
+      d[j] = cn > 0 ? 1.0 / std::sqrt(cn) : 1.0;
+    }
+    for (int64_t i = 0; i < m; ++i) e[i] = rowA[i] > 0 ? 1.0 / std::sqrt(rowA[i]) : 1.0;
+    // cone-uniform row factors for the non-separable cones
+    for (const Segment& g : S->segs) {
+      if (g.kind == HC_CONE_ZERO || g.kind == HC_CONE_NONNEG) continue;
+      for (int64_t c = 0; c < g.count; ++c) {
+        double sum = 0;
+        for (int j = 0; j < g.dim; ++j) {
+          const int64_t r = (g.kind == HC_CONE_PSD) ? g.base + c * g.dim + j : g.base + j * g.count + c;
+          sum += e[r];
+        }
+        const double mean = sum / g.dim;
+        for (int j = 0; j < g.dim; ++j) {
+          const int64_t r = (g.kind == HC_CONE_PSD) ? g.base + c * g.dim + j : g.base + j * g.count + c;
+          e[r] = mean;
+        }
+      }
+    }
+    for (int64_t j = 0; j < n; ++j) S->D[j] = clampv(S->D[j] * clampv(d[j]));
+    for (int64_t i = 0; i < m; ++i) S->E[i] = clampv(S->E[i] * clampv(e[i]));
+  }
+  std::fill(colP.begin(), colP.end(), 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t k = Pf.rp[i]; k < Pf.rp[i + 1]; ++k) {
+      const int32_t j = Pf.ci[k];
+      colP[j] = std::max(colP[j], std::fabs(S->D[i] * Pf.v[k] * S->D[j]));
+    }
+  double mean = 0;
+  for (int64_t j = 0; j < n; ++j) mean += colP[j];
+  mean /= (double)n;
+  double dq = 0;
+  for (int64_t j = 0; j < n; ++j) dq = std::max(dq, std::fabs(S->D[j] * q[j]));
+  S->cscale = clampv(1.0 / std::max(1.0, std::max(mean, dq)));
+}
+
+void setup_host(hc_solver* S, const hc_problem* p) {
+  const int64_t n = p->n, m = p->m;
+  S->n = n;
+  S->m = m;
+  S->mixed = (S->st.precision == HC_PRECISION_MIXED);
+  build_segments(S, p);
+  // full P (user order of variables is kept)
+  HostCsr Pf;
+  Pf.nrows = Pf.ncols = n;
+  {
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(n);
+    if (p->P_rowptr)
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = p->P_rowptr[i]; k < p->P_rowptr[i + 1]; ++k) {
+          const int32_t j = p->P_col[k];
+          const double v = p->P_val[k];
+          rows[i].push_back({j, v});
+          if (j != i) rows[j].push_back({(int32_t)i, v});
+        }
+    Pf.rp.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      std::sort(rows[i].begin(), rows[i].end());
+      Pf.rp[i + 1] = Pf.rp[i] + (int32_t)rows[i].size();
+      for (auto& e : rows[i]) {
+        Pf.ci.push_back(e.first);
+        Pf.v.push_back(e.second);
+      }
+    }
+  }
+  // A in internal row order
+  HostCsr Ai;
+  Ai.nrows = m;
+  Ai.ncols = n;
+  Ai.rp.assign(m + 1, 0);
+  for (int64_t r = 0; r < m; ++r) {
+    const int64_t u = S->perm[r];
+    Ai.rp[r + 1] = Ai.rp[r] + (int32_t)(p->A_rowptr[u + 1] - p->A_rowptr[u]);
+  }
+  Ai.ci.resize(Ai.rp[m]);
+  Ai.v.resize(Ai.rp[m]);
+  for (int64_t r = 0; r < m; ++r) {
+    const int64_t u = S->perm[r];
+    int32_t o = Ai.rp[r];
+    for (int64_t k = p->A_rowptr[u]; k < p->A_rowptr[u + 1]; ++k, ++o) {
+      Ai.ci[o] = p->A_col[k];
+      Ai.v[o] = p->A_val[k];
+    }
+  }
+  std::vector<double> qv(p->q, p->q + n), bi(m);
+  for (int64_t r = 0; r < m; ++r) bi[r] = p->b[S->perm[r]];
+  S->bnorm_user = 0;
+  for (int64_t i = 0; i < m; ++i) S->bnorm_user = std::max(S->bnorm_user, std::fabs(p->b[i]));
+  S->qnorm_user = 0;
+  for (int64_t j = 0; j < n; ++j) S->qnorm_user = std::max(S->qnorm_user, std::fabs(p->q[j]));
+  equilibrate(S, Ai, Pf, qv);
+  // scaled data
+  const double c = S->cscale;
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t k = Pf.rp[i]; k < Pf.rp[i + 1]; ++k) Pf.v[k] *= c * S->D[i] * S->D[Pf.ci[k]];
+  for (int64_t r = 0; r < m; ++r)
+    for (int32_t k = Ai.rp[r]; k < Ai.rp[r + 1]; ++k) Ai.v[k] *= S->E[r] * S->D[Ai.ci[k]];
+  S->q.resize(n);
+  for (int64_t j = 0; j < n; ++j) S->q[j] = c * S->D[j] * qv[j];
+  S->b.resize(m);
+  for (int64_t r = 0; r < m; ++r) S->b[r] = S->E[r] * bi[r];
+  S->maxPdiag = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t k = Pf.rp[i]; k < Pf.rp[i + 1]; ++k)
+      if (Pf.ci[k] == i) S->maxPdiag = std::max(S->maxPdiag, std::fabs(Pf.v[k]));
+  S->P = std::move(Pf);
+  // dense rows: zero/nonneg rows with more than 512 nonzeros go through a dense SYRK
+  std::vector<char> is_dense(m, 0);
+  for (const Segment& g : S->segs) {
+    if (g.kind != HC_CONE_ZERO && g.kind != HC_CONE_NONNEG) continue;
+    for (int64_t i = 0; i < g.count; ++i) {
+      const int64_t r = g.base + i;
+      if (Ai.rp[r + 1] - Ai.rp[r] > 512) {
+        is_dense[r] = 1;
+        S->drows.push_back((int32_t)r);
+        S->dmidx.push_back(g.moff + i);
+      }
+    }
+  }
+  const int nd = (int)S->drows.size();
+  S->Ad.assign((size_t)nd * n, 0.0);
+  for (int d = 0; d < nd; ++d) {
+    const int64_t r = S->drows[d];
+    for (int32_t k = Ai.rp[r]; k < Ai.rp[r + 1]; ++k) S->Ad[(size_t)d * n + Ai.ci[k]] = Ai.v[k];
+  }
+  HostCsr As;   // A without the dense rows
+  As.nrows = m;
+  As.ncols = n;
+  As.rp.assign(m + 1, 0);
+  for (int64_t r = 0; r < m; ++r) As.rp[r + 1] = As.rp[r] + (is_dense[r] ? 0 : (Ai.rp[r + 1] - Ai.rp[r]));
+  As.ci.reserve(As.rp[m]);
+  As.v.reserve(As.rp[m]);
+  for (int64_t r = 0; r < m; ++r)
+    if (!is_dense[r])
+      for (int32_t k = Ai.rp[r]; k < Ai.rp[r + 1]; ++k) {
+        As.ci.push_back(Ai.ci[k]);
+        As.v.push_back(Ai.v[k]);
+      }
+  // transpose of As
+  HostCsr At;
+  At.nrows = n;
+  At.ncols = m;
+  At.rp.assign(n + 1, 0);
+  for (int32_t k = 0; k < As.rp[m]; ++k) At.rp[As.ci[k] + 1]++;
+  for (int64_t j = 0; j < n; ++j) At.rp[j + 1] += At.rp[j];
+  At.ci.resize(As.rp[m]);
+  At.v.resize(As.rp[m]);
+  {
+    std::vector<int32_t> fillp(At.rp.begin(), At.rp.end() - 1);
+    for (int64_t r = 0; r < m; ++r)
+      for (int32_t k = As.rp[r]; k < As.rp[r + 1]; ++k) {
+        const int32_t j = As.ci[k];
+        At.ci[fillp[j]] = (int32_t)r;
+        At.v[fillp[j]] = As.v[k];
+        fillp[j]++;
+      }
+  }
+  // Schur assembly tasks: unordered row pairs within each cone
+  for (const Segment& g : S->segs) {
+    if (g.kind == HC_CONE_ZERO || g.kind == HC_CONE_NONNEG) {
+      for (int64_t i = 0; i < g.count; ++i) {
+        const int64_t r = g.base + i;
+        if (is_dense[r] || As.rp[r + 1] == As.rp[r]) continue;
+        S->tra.push_back((int32_t)r);
+        S->trb.push_back((int32_t)r);
+        S->tm.push_back(g.moff + i);
+      }
+      continue;
+    }
+    for (int64_t c2 = 0; c2 < g.count; ++c2)
+      for (int a = 0; a < g.dim; ++a)
+        for (int bb = 0; bb <= a; ++bb) {
+          const int64_t ra = (g.kind == HC_CONE_PSD) ? g.base + c2 * g.dim + a : g.base + a * g.count + c2;
+          const int64_t rb = (g.kind == HC_CONE_PSD) ? g.base + c2 * g.dim + bb : g.base + bb * g.count + c2;
+          if (As.rp[ra + 1] == As.rp[ra] || As.rp[rb + 1] == As.rp[rb]) continue;
+          S->tra.push_back((int32_t)ra);
+          S->trb.push_back((int32_t)rb);
+          S->tm.push_back(g.moff + ((int64_t)a * (a + 1) / 2 + bb) * g.count + c2);
+        }
+  }
+  S->A = std::move(As);
+  S->At = std::move(At);
+  S->ld = ((n + 63) / 64) * 64;
+  if (S->st.static_reg <= 0) S->st.static_reg = S->mixed ? 3.4526698300124393e-04 : 1e-8;
+  if (S->st.dyn_reg < 0) S->st.dyn_reg = S->mixed ? std::ldexp(1.0, -46) : std::ldexp(1.0, -104);
+}
+
+template <typename T> T* upload(Buf& buf, const std::vector<T>& h, hipStream_t st) {
+  T* d = buf.take<T>(std::max<size_t>(1, h.size()));
+  if (!buf.dry && !h.empty()) HC_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return d;
+}
+
+Csr upload_csr(Buf& buf, const HostCsr& h, hipStream_t st) {
+  Csr c;
+  c.nrows = (int32_t)h.nrows;
+  c.ncols = (int32_t)h.ncols;
+  c.nnz = h.ci.size();
+  c.rowptr = upload(buf, h.rp, st);
+  c.col = upload(buf, h.ci, st);
+  c.val = upload(buf, h.v, st);
+  c.lanes = choose_lanes(h.nrows ? (double)c.nnz / (double)h.nrows : 0.0);
+  return c;
+}
+
+// ===========================================================================
+// device-side building blocks of one iteration
+// ===========================================================================
+struct Red {
+  hc_solver* S;
+  RedOps ops{};
+  int64_t n;
+  explicit Red(hc_solver* s, int64_t len) : S(s), n(len) { ops.nops = 0; }
+  int dot(const double* x, const double* y) {
+    ops.op[ops.nops] = RedOp{RED_DOT, x, y, 0.0, nullptr};
+    return ops.nops++;
+  }
+  int maxabs(const double* x, const double* w = nullptr, bool divide = false, const double* y = nullptr,
+             double yc = 0.0) {
+    ops.op[ops.nops] = RedOp{divide ? RED_MAX_DIV : RED_MAX_MUL, x, y, yc, w};
+    return ops.nops++;
+  }
+  std::vector<double> run() {
+    std::vector<double> out(ops.nops, 0.0);
+    if (n == 0 || ops.nops == 0) return out;
+    const int nb = reduce_launch(n, ops, S->dpart, S->stream);
+    HC_HIP(hipMemcpyAsync(S->hpart, S->dpart, (size_t)nb * ops.nops * sizeof(double), hipMemcpyDeviceToHost,
+                          S->stream));
+    HC_HIP(hipStreamSynchronize(S->stream));
+    for (int o = 0; o < ops.nops; ++o) {
+      double acc = 0.0;
+      for (int bk = 0; bk < nb; ++bk) {
+        const double v = S->hpart[(size_t)bk * ops.nops + o];
+        if (ops.op[o].kind == RED_DOT) acc += v;
+        else acc = (std::isnan(v) || std::isnan(acc)) ? NAN : std::max(acc, v);
+      }
+      out[o] = acc;
+    }
+    return out;
+  }
+};
+
+void A_mul(hc_solver* S, const double* x, double* y, double alpha, double beta) {
+  spmv(S->dA, x, y, alpha, beta, S->stream);
+  dense_rows_gemv((int)S->drows.size(), S->n, S->dAd, S->ddrows, x, y, alpha, S->stream);
+}
+void At_mul(hc_solver* S, const double* z, double* y, double alpha, double beta) {
+  spmv(S->dAt, z, y, alpha, beta, S->stream);
+  dense_rows_gemv_t((int)S->drows.size(), S->n, S->dAd, S->ddrows, z, y, alpha, S->stream);
+}
+void P_mul(hc_solver* S, const double* x, double* y, double alpha, double beta) {
+  if (S->dP.nnz == 0) {
+    if (beta == 0.0) vfill(S->n, 0.0, y, S->stream);
+    else if (beta != 1.0) vaxpby(S->n, 0.0, x, beta, y, S->stream);
+    return;
+  }
+  spmv(S->dP, x, y, alpha, beta, S->stream);
+}
+void H_apply(hc_solver* S, int mode, const double* x, double* y) {
+  for (auto& g : S->sdev) cone_apply(g, mode, S->delta, x, y, S->stream);
+}
+
+// factor the regularised KKT system at the current scaling (state + hdiag filled)
+void factor(hc_solver* S) {
+  hipStream_t st = S->stream;
+  Red r(S, S->m);
+  r.maxabs(S->dhdiag);
+  const double hmax = r.run()[0];
+  S->delta = S->st.static_reg + S->st.dyn_reg * std::max(S->maxPdiag, hmax);
+  for (auto& g : S->sdev) cone_mblock(g, S->delta, st);
+  fill_lower_zero(S->n, S->ld, S->dS, st);
+  add_P_delta(S->dP, S->n, S->delta, S->ld, S->dS, st);
+  assemble_pairs((int64_t)S->tra.size(), S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->ld, S->dS, st);
+  const int nd = (int)S->drows.size();
+  if (nd) {
+    scale_dense_rows(nd, S->n, S->dAd, S->ddmidx, S->dmval, S->dBd, st);
+    gemm_nt<double>(S->dS, S->ld, S->dBd, S->n, S->dBd, S->n, S->n, S->n, nd, 1.0, true, 0, 0, st);
+  }
+  const double tol = 0.0;
+  if (S->mixed) {
+    lower_to_f32(S->n, S->ld, S->dS, S->dS32, st);
+    dense_cholesky<float>(S->dS32, S->n, S->ld, S->dLinv32, tol, S->delta, S->dhits, st);
+  } else {
+    dense_cholesky<double>(S->dS, S->n, S->ld, S->dLinv, tol, S->delta, S->dhits, st);
+  }
+}
+
+// x = S^-1 u (one right-hand side) in the factor precision
+void schur_solve(hc_solver* S, const double* u, double* x) {
+  hipStream_t st = S->stream;
+  const int64_t n = S->n;
+  if (S->mixed) {
+    Red r(S, n);
+    RedOps ops{};
+    ops.nops = 1;
+    ops.op[0] = RedOp{RED_MAX_MUL, u, nullptr, 0.0, nullptr};
+    const int nb = reduce_launch(n, ops, S->dpart, st);
+    combine_max(nb, S->dpart, S->dscal, st);
+    to_f32(n, u, S->dscal, S->sb32, st);
+    dense_solve<float>(S->dS32, n, S->ld, S->dLinv32, S->sb32, S->sy32, S->sx32, 1, st);
+    from_f32(n, S->sx32, S->dscal, x, st);
+  } else {
+    vcopy(n, u, S->sb, st);
+    dense_solve<double>(S->dS, n, S->ld, S->dLinv, S->sb, S->sy, x, 1, st);
+  }
+}
+
+// K_reg [x; z] = [r1; r2]:  z = M (A x - r2),  S x = r1 + A' M r2
+void solve_reg(hc_solver* S, const double* r1, const double* r2, double* x, double* z) {
+  hipStream_t st = S->stream;
+  H_apply(S, 1, r2, S->t1);                    // t1 = M r2
+  vcopy(S->n, r1, S->u1, st);
+  At_mul(S, S->t1, S->u1, 1.0, 1.0);           // u1 = r1 + A' t1
+  schur_solve(S, S->u1, x);
+  A_mul(S, x, S->w1, 1.0, 0.0);                // w1 = A x
+  vaxpby(S->m, -1.0, r2, 1.0, S->w1, st);      // w1 -= r2
+  H_apply(S, 1, S->w1, z);
+}
+
+// iterative refinement against the unregularised K; result in (xo, zo)
+int64_t kkt_solve(hc_solver* S, const double* r1, const double* r2, double* xo, double* zo) {
+  hipStream_t st = S->stream;
+  const int64_t n = S->n, m = S->m;
+  double nb;
+  {
+    Red a(S, n), b(S, m);
+    a.maxabs(r1);
+    b.maxabs(r2);
+    nb = std::max(a.run()[0], b.run()[0]);
+  }
+  double* x = S->irx;
+  double* z = S->irz;
+  double* xn = S->irxn;
+  double* zn = S->irzn;
+  vfill(n, 0.0, x, st);
+  vfill(m, 0.0, z, st);
+  vcopy(n, r1, S->irrx, st);
+  vcopy(m, r2, S->irrz, st);
+  double best = nb, rnorm = nb;
+  bool have_best = false;
+  int64_t solves = 0;
+  for (int it = 0; it <= S->st.ir_max; ++it) {
+    solve_reg(S, S->irrx, S->irrz, S->kx, S->kz);   // correction in kx, kz
+    vlin3(n, 1.0, x, 1.0, S->kx, 0.0, nullptr, xn, st);
+    vlin3(m, 1.0, z, 1.0, S->kz, 0.0, nullptr, zn, st);
+    ++solves;
+    // residual r - K [xn; zn] with the unregularised K
+    P_mul(S, xn, S->kx, 1.0, 0.0);
+    At_mul(S, zn, S->kx, 1.0, 1.0);
+    A_mul(S, xn, S->kz, 1.0, 0.0);
+    H_apply(S, 0, zn, S->t2);
+    vaxpby(m, -1.0, S->t2, 1.0, S->kz, st);         // kz = A xn - H zn
+    vlin3(n, 1.0, r1, -1.0, S->kx, 0.0, nullptr, S->kx, st);
+    vlin3(m, 1.0, r2, -1.0, S->kz, 0.0, nullptr, S->kz, st);
+    double rn;
+    {
+      Red a(S, n), b(S, m);
+      a.maxabs(S->kx);
+      b.maxabs(S->kz);
+      rn = std::max(a.run()[0], b.run()[0]);
+    }
+    if (rn < best || !have_best) {
+      if (rn < best) {
+        vcopy(n, xn, S->irbx, st);
+        vcopy(m, zn, S->irbz, st);
+        best = rn;
+        have_best = true;
+      }
+    }
+    if (rn <= S->st.ir_abstol + S->st.ir_reltol * nb) break;
+    if (it > 0 && rn > 0.5 * rnorm) break;
+    std::swap(x, xn);
+    std::swap(z, zn);
+    std::swap(S->irrx, S->kx);
+    std::swap(S->irrz, S->kz);
+    rnorm = rn;
+  }
+  if (have_best) {
+    vcopy(n, S->irbx, xo, st);
+    vcopy(m, S->irbz, zo, st);
+  } else {
+    vfill(n, 0.0, xo, st);
+    vfill(m, 0.0, zo, st);
+  }
+  S->irx = x;
+  S->irz = z;
+  S->irxn = xn;
+  S->irzn = zn;
+  S->info.ir_solves += solves;
+  return solves;
+}
+
+struct Resid {
+  double xPx, qx, bz, sz, rd_n, rp_n, x_n, s_n, z_n, atz_n, px_n, axs_n;
+};
+
+// Px, Ax, A'z, r_d and r_p vectors and all norms of the termination tests
+Resid residuals(hc_solver* S) {
+  hipStream_t st = S->stream;
+  const int64_t n = S->n, m = S->m;
+  P_mul(S, S->x, S->Px, 1.0, 0.0);
+  A_mul(S, S->x, S->Ax, 1.0, 0.0);
+  At_mul(S, S->z, S->Atz, 1.0, 0.0);
+  vlin3(n, 1.0, S->Px, 1.0, S->Atz, S->tau, S->dq, S->rdv, st);        // P x + A'z + q tau
+  vlin3(m, -1.0, S->Ax, -1.0, S->s, S->tau, S->db, S->rpv, st);        // -A x - s + b tau
+  Red rn(S, n), rm(S, m);
+  const int i_xPx = rn.dot(S->x, S->Px), i_qx = rn.dot(S->dq, S->x), i_rd = rn.maxabs(S->rdv, S->dD, true),
+            i_x = rn.maxabs(S->x, S->dD, false), i_atz = rn.maxabs(S->Atz, S->dD, true),
+            i_px = rn.maxabs(S->Px, S->dD, true);
+  const int i_bz = rm.dot(S->db, S->z), i_sz = rm.dot(S->s, S->z), i_rp = rm.maxabs(S->rpv, S->dE, true),
+            i_s = rm.maxabs(S->s, S->dE, true), i_z = rm.maxabs(S->z, S->dE, false),
+            i_axs = rm.maxabs(S->Ax, S->dE, true, S->s, 1.0);
+  const auto a = rn.run();
+  const auto b = rm.run();
+  Resid R;
+  R.xPx = a[i_xPx]; R.qx = a[i_qx]; R.rd_n = a[i_rd]; R.x_n = a[i_x]; R.atz_n = a[i_atz]; R.px_n = a[i_px];
+  R.bz = b[i_bz]; R.sz = b[i_sz]; R.rp_n = b[i_rp]; R.s_n = b[i_s]; R.z_n = b[i_z]; R.axs_n = b[i_axs];
+  return R;
+}
+
+int check(hc_solver* S, const Resid& R) {
+  const double t = S->tau, c = S->cscale, eps = S->st.eps_feas, ei = S->st.eps_inf;
+  const double rp = R.rp_n / t, rd = R.rd_n / (c * t);
+  const double gp = (0.5 * R.xPx / t + R.qx) / (c * t), gd = (-0.5 * R.xPx / t - R.bz) / (c * t);
+  const double xn = R.x_n / t, sn = R.s_n / t, zn = R.z_n / (c * t);
+  S->info.res_primal = rp;
+  S->info.res_dual = rd;
+  S->info.obj_primal = gp;
+  S->info.obj_dual = gd;
+  S->info.gap = std::fabs(gp - gd);
+  if (rp < eps * std::max(1.0, S->bnorm_user + xn + sn) && rd < eps * std::max(1.0, S->qnorm_user + xn + zn) &&
+      std::fabs(gp - gd) < eps * std::max(1.0, std::min(std::fabs(gp), std::fabs(gd))))
+    return HC_STATUS_SOLVED;
+  const double bz = R.bz / c, xu = R.x_n, zu = R.z_n / c, su = R.s_n;
+  if (bz < -ei && R.atz_n / c < -ei * std::max(1.0, xu + zu) * bz) return HC_STATUS_PRIMAL_INFEASIBLE;
+  const double qx = R.qx / c;
+  if (qx < -ei && R.px_n / c < -ei * std::max(1.0, xu) * qx && R.axs_n < -ei * std::max(1.0, xu + su) * qx)
+    return HC_STATUS_DUAL_INFEASIBLE;
+  if (!std::isfinite(rp) || !std::isfinite(rd) || !std::isfinite(gp)) return HC_STATUS_NUMERICAL_ERROR;
+  return 0;
+}
+
+void scale_all(hc_solver* S, double mu, bool force_dual, int* pd_count) {
+  HC_HIP(hipMemsetAsync(S->dpd, 0, sizeof(int), S->stream));
+  for (auto& g : S->sdev) cone_scale(g, S->s, S->z, mu, force_dual ? 1 : 0, S->dhdiag, S->dpd, S->stream);
+  int h = 0;
+  HC_HIP(hipMemcpyAsync(&h, S->dpd, sizeof(int), hipMemcpyDeviceToHost, S->stream));
+  HC_HIP(hipStreamSynchronize(S->stream));
+  *pd_count = h;
+}
+
+struct Dir {
+  double dtau, dkappa;
+};
+
+// solve for the RHS (d_x = r1, -(d_z - d_s) = r2, d_tau, d_kappa) and recover Delta
+Dir direction(hc_solver* S, const double* r1, const double* r2, double dtau_rhs, double dkap_rhs,
+              const double* ds_rhs, double* dxo, double* dzo, double* dso) {
+  hipStream_t st = S->stream;
+  const int64_t n = S->n, m = S->m;
+  kkt_solve(S, r1, r2, S->x1, S->z1);
+  // w = 2 P xi + q with xi = x / tau:  w'x1, w'x2 ; b'z1, b'z2
+  Red rn(S, n), rm(S, m);
+  const double ti = 1.0 / S->tau;
+  vlin3(n, 2.0 * ti, S->Px, 1.0, S->dq, 0.0, nullptr, S->t2, st);
+  const int a1 = rn.dot(S->t2, S->x1), a2 = rn.dot(S->t2, S->x2);
+  const int b1 = rm.dot(S->db, S->z1), b2 = rm.dot(S->db, S->z2);
+  const auto va = rn.run();
+  const auto vb = rm.run();
+  Dir d;
+  const double xPx = S->xPx_cache;
+  const double num = dtau_rhs - dkap_rhs / S->tau + va[a1] + vb[b1];
+  const double den = S->kappa / S->tau + xPx / (S->tau * S->tau) - va[a2] - vb[b2];
+  d.dtau = num / den;
+  vlin3(n, 1.0, S->x1, d.dtau, S->x2, 0.0, nullptr, dxo, st);
+  vlin3(m, 1.0, S->z1, d.dtau, S->z2, 0.0, nullptr, dzo, st);
+  for (auto& g : S->sdev) cone_recover_ds(g, ds_rhs, dzo, dso, st);
+  d.dkappa = -(dkap_rhs + S->kappa * d.dtau) / S->tau;
+  return d;
+}
+
+}  // namespace
+
+namespace {
+
+// ===========================================================================
+// step rule
+// ===========================================================================
+struct Step {
+  const double *ds, *dz;
+  double dtau, dkappa;
+};
+
+double step_length(hc_solver* S, const Step& d, bool combined) {
+  hipStream_t st = S->stream;
+  double a = 1.0;
+  if (d.dtau < 0) a = std::min(a, -S->tau / d.dtau);
+  if (d.dkappa < 0) a = std::min(a, -S->kappa / d.dkappa);
+  for (auto& g : S->sdev) {
+    const int nb = cone_step_sym(g, S->s, S->z, d.ds, d.dz, S->dpart, st);
+    if (!nb) continue;
+    HC_HIP(hipMemcpyAsync(S->hpart, S->dpart, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    HC_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < nb; ++i) a = std::min(a, S->hpart[i]);
+  }
+  if (!S->has_nonsym) return a;
+  // mu(alpha) = (c0 + c1 a + c2 a^2) / (nu + 1)
+  double c0 = 0, c1 = 0, c2 = 0;
+  if (combined) {
+    Red r(S, S->m);
+    const int i0 = r.dot(S->s, S->z), i1 = r.dot(S->s, d.dz), i2 = r.dot(d.ds, S->z), i3 = r.dot(d.ds, d.dz);
+    const auto v = r.run();
+    c0 = v[i0] + S->kappa * S->tau;
+    c1 = v[i1] + v[i2] + S->kappa * d.dtau + d.dkappa * S->tau;
+    c2 = v[i3] + d.dkappa * d.dtau;
+  }
+  const double ratio = S->st.backtrack;
+  while (true) {
+    if (a < 1e-10) return 0.0;
+    // the next 8 trials a, a r, a r^2, ... (products formed in sequence)
+    double trial[8];
+    double t = a;
+    int nt = 0;
+    for (; nt < 8; ++nt) {
+      if (t < 1e-10) break;
+      trial[nt] = t;
+      t *= ratio;
+    }
+    unsigned long long all = (nt >= 64) ? ~0ull : ((1ull << nt) - 1ull);
+    for (auto& g : S->sdev) {
+      if (g.kind != HC_CONE_EXP && g.kind != HC_CONE_POW) continue;
+      const int nb = cone_trial_nonsym(g, S->s, S->z, d.ds, d.dz, a, ratio, nt, combined ? 1 : 0, S->st.beta, c0, c1,
+                                       c2, (double)(S->nu + 1), S->dmask, st);
+      HC_HIP(hipMemcpyAsync(S->hmask, S->dmask, nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+      HC_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < nb; ++i) all &= S->hmask[i];
+    }
+    for (int j = 0; j < nt; ++j)
+      if (all & (1ull << j)) return trial[j];
+    if (nt < 8) return 0.0;
+    a = t;
+  }
+}
+
+// ===========================================================================
+// initial point
+// ===========================================================================
+__global__ void k_identity_state(SegDev g, double* hdiag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = g.count;
+  if (i >= N) return;
+  if (g.kind == HC_CONE_ZERO) {
+    hdiag[g.base + i] = 0.0;
+  } else if (g.kind == HC_CONE_NONNEG) {
+    g.state[i] = 1.0;
+    hdiag[g.base + i] = 1.0;
+  } else if (g.kind == HC_CONE_SOC) {
+    for (int j = 0; j < g.dim; ++j) {
+      g.state[j * N + i] = (j == 0) ? 1.0 : 0.0;
+      hdiag[g.base + j * N + i] = 1.0;
+    }
+    g.state[g.dim * N + i] = 1.0;
+  } else if (g.kind == HC_CONE_PSD) {
+    const int k = g.k;
+    const int64_t kk = (int64_t)k * k;
+    for (int r = 0; r < k; ++r)
+      for (int j = 0; j < k; ++j) {
+        const double v = (r == j) ? 1.0 : 0.0;
+        g.state[(r * k + j) * N + i] = v;
+        g.state[(kk + r * k + j) * N + i] = v;
+        g.state[(2 * kk + r * k + j) * N + i] = v;
+      }
+    for (int j = 0; j < k; ++j) {
+      g.state[(3 * kk + j) * N + i] = 1.0;
+      g.state[(3 * kk + k + j) * N + i] = 1.0;
+    }
+    for (int p = 0; p < g.dim; ++p) hdiag[g.base + i * g.dim + p] = 1.0;
+  }
+}
+
+void init_point(hc_solver* S) {
+  hipStream_t st = S->stream;
+  const int64_t n = S->n, m = S->m;
+  S->tau = S->kappa = 1.0;
+  if (S->has_nonsym) {
+    vfill(n, 0.0, S->x, st);
+    for (auto& g : S->sdev) {
+      cone_unit(g, S->s, st);
+      cone_unit(g, S->z, st);
+    }
+    return;
+  }
+  for (auto& g : S->sdev) {
+    hipLaunchKernelGGL(k_identity_state, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, S->dhdiag);
+    HC_LAUNCH_CHECK();
+  }
+  factor(S);
+  vlin3(n, -1.0, S->dq, 0.0, nullptr, 0.0, nullptr, S->r1, st);
+  kkt_solve(S, S->r1, S->db, S->x, S->z);
+  vaxpby(m, -1.0, S->z, 0.0, S->s, st);                      // s = -z
+  for (auto& g : S->sdev)
+    if (g.kind == HC_CONE_ZERO) vfill(g.count, 0.0, S->s + g.base, st);
+  for (int which = 0; which < 2; ++which) {
+    double* v = which == 0 ? S->s : S->z;
+    double amax = -INFINITY;
+    for (auto& g : S->sdev) {
+      const int nb = cone_max_neg_eig(g, v, S->dpart, st);
+      if (!nb) continue;
+      HC_HIP(hipMemcpyAsync(S->hpart, S->dpart, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+      HC_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < nb; ++i) amax = std::max(amax, S->hpart[i]);
+    }
+    if (amax >= 0)
+      for (auto& g : S->sdev) cone_add_e(g, 1.0 + amax, v, st);
+  }
+}
+
+// ===========================================================================
+// one iteration (loop body of Algorithm 1); returns a status (0 = continue)
+// ===========================================================================
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int iterate(hc_solver* S, const Resid& R) {
+  hipStream_t st = S->stream;
+  const int64_t n = S->n, m = S->m;
+  const double mu = (R.sz + S->kappa * S->tau) / (double)(S->nu + 1);
+  S->info.mu = mu;
+  // G(v): gx = -(P x + A'z + q tau) = -rdv ; gz = s + A x - b tau = -rpv
+  const double gt = S->kappa + R.qx + R.bz + R.xPx / S->tau;
+  bool force_dual = S->st.force_dual_scaling != 0;
+  double alpha_c = 0, sigma = 0;
+  Dir dc{};
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    double t0 = now_ms();
+    int pd = 0;
+    scale_all(S, mu, force_dual, &pd);
+    double t1 = now_ms();
+    factor(S);
+    HC_HIP(hipStreamSynchronize(st));
+    double t2 = now_ms();
+    S->info.cone_ms += t1 - t0;
+    S->info.factor_ms += t2 - t1;
+    // constant system K [x2; z2] = [-q; b]
+    vlin3(n, -1.0, S->dq, 0.0, nullptr, 0.0, nullptr, S->r1, st);
+    kkt_solve(S, S->r1, S->db, S->x2, S->z2);
+    // affine: r1 = gx, r2 = -(gz - s) = rpv + s
+    vlin3(n, -1.0, S->rdv, 0.0, nullptr, 0.0, nullptr, S->r1, st);
+    vlin3(m, 1.0, S->rpv, 1.0, S->s, 0.0, nullptr, S->r2, st);
+    const Dir da = direction(S, S->r1, S->r2, gt, S->kappa * S->tau, S->s, S->dxa, S->dza, S->dsa);
+    const double alpha_a = step_length(S, Step{S->dsa, S->dza, da.dtau, da.dkappa}, false);
+    sigma = (1.0 - alpha_a) * (1.0 - alpha_a) * (1.0 - alpha_a);
+    // combined
+    const double dk = S->kappa * S->tau + da.dkappa * da.dtau - sigma * mu;
+    for (auto& g : S->sdev) cone_ds_combined(g, S->s, S->z, S->dsa, S->dza, sigma * mu, S->dsrhs, st);
+    const double f = 1.0 - sigma;
+    vlin3(n, -f, S->rdv, 0.0, nullptr, 0.0, nullptr, S->r1, st);
+    // r2 = -(f gz - ds) = f rpv + ds
+    vlin3(m, f, S->rpv, 1.0, S->dsrhs, 0.0, nullptr, S->r2, st);
+    dc = direction(S, S->r1, S->r2, f * gt, dk, S->dsrhs, S->dx, S->dz, S->dsv);
+    alpha_c = step_length(S, Step{S->dsv, S->dz, dc.dtau, dc.dkappa}, true);
+    S->info.solve_kkt_ms += now_ms() - t2;
+    if (alpha_c < 0.1 && pd > 0 && !force_dual) {
+      force_dual = true;
+      S->info.dual_switches++;
+      continue;
+    }
+    break;
+  }
+  if (S->st.verbose)
+    std::printf("    sigma %.3e alpha_c %.4f delta %.2e\n", sigma, alpha_c, S->delta);
+  if (alpha_c < 1e-4) return HC_STATUS_INSUFFICIENT_PROGRESS;
+  const double a = S->st.step_fraction * alpha_c;
+  vaxpby(n, a, S->dx, 1.0, S->x, st);
+  vaxpby(m, a, S->dsv, 1.0, S->s, st);
+  vaxpby(m, a, S->dz, 1.0, S->z, st);
+  S->tau += a * dc.dtau;
+  S->kappa += a * dc.dkappa;
+  return 0;
+}
+
+void run_solve(hc_solver* S) {
+  S->info.iterations = 0;
+  S->status = 0;
+  for (int k = 0; k <= S->st.max_iter; ++k) {
+    const Resid R = residuals(S);
+    S->xPx_cache = R.xPx;
+    int status = check(S, R);
+    S->info.mu = (R.sz + S->kappa * S->tau) / (double)(S->nu + 1);
+    if (S->st.verbose)
+      std::printf("%3d gp=%+.8e gd=%+.8e rp=%.2e rd=%.2e mu=%.2e tau=%.3e\n", k, S->info.obj_primal,
+                  S->info.obj_dual, S->info.res_primal, S->info.res_dual, S->info.mu, S->tau);
+    if (status) {
+      S->status = status;
+      break;
+    }
+    if (k == S->st.max_iter) {
+      S->status = HC_STATUS_MAX_ITER;
+      break;
+    }
+    status = iterate(S, R);
+    S->info.iterations++;
+    if (status) {
+      S->status = status;
+      const Resid R2 = residuals(S);
+      check(S, R2);
+      break;
+    }
+  }
+  S->info.status = S->status;
+}
+
+// every device allocation of a solver, in order (dry run: byte count only)
+void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
+  const int64_t n = S->n, m = S->m;
+  S->dA = upload_csr(buf, S->A, st);
+  S->dAt = upload_csr(buf, S->At, st);
+  S->dP = upload_csr(buf, S->P, st);
+  S->dAd = upload(buf, S->Ad, st);
+  S->dBd = buf.take<double>(std::max<size_t>(1, S->Ad.size()));
+  S->ddrows = upload(buf, S->drows, st);
+  S->ddmidx = upload(buf, S->dmidx, st);
+  S->dq = upload(buf, S->q, st);
+  S->db = upload(buf, S->b, st);
+  S->dD = upload(buf, S->D, st);
+  S->dE = upload(buf, S->E, st);
+  S->dalpha = upload(buf, S->alpha_pow, st);
+  S->dtra = upload(buf, S->tra, st);
+  S->dtrb = upload(buf, S->trb, st);
+  S->dtm = upload(buf, S->tm, st);
+  S->dstate = buf.take<double>(S->stotal + 1);
+  S->dmval = buf.take<double>(S->mtotal + 1);
+  S->dhdiag = buf.take<double>(m);
+  S->dS = buf.take<double>((size_t)S->ld * n);
+  S->dLinv = buf.take<double>(linv_elems(n));
+  if (S->mixed) {
+    S->dS32 = buf.take<float>((size_t)S->ld * n);
+    S->dLinv32 = buf.take<float>(linv_elems(n));
+    S->sb32 = buf.take<float>(n);
+    S->sy32 = buf.take<float>(n);
+    S->sx32 = buf.take<float>(n);
+  }
+  S->dhits = buf.take<unsigned long long>(1);
+  S->dpd = buf.take<int>(2);
+  S->dscal = buf.take<double>(8);
+  S->dpart = buf.take<double>(4096);
+  S->dmask = buf.take<unsigned long long>(4096);
+  const int64_t L = std::max(n, m);
+  double** vecs[] = {&S->x, &S->s, &S->z, &S->Px, &S->Ax, &S->Atz, &S->rdv, &S->rpv, &S->x2, &S->z2, &S->x1,
+                     &S->z1, &S->dx, &S->dz, &S->dsv, &S->dsrhs, &S->dxa, &S->dza, &S->dsa, &S->r1, &S->r2,
+                     &S->irx, &S->irz, &S->irxn, &S->irzn, &S->irbx, &S->irbz, &S->irrx, &S->irrz, &S->kx};
+  for (double** v : vecs) *v = buf.take<double>(L);
+  S->kz = buf.take<double>(L);
+  S->t1 = buf.take<double>(L);
+  S->t2 = buf.take<double>(L);
+  S->u1 = buf.take<double>(L);
+  S->w1 = buf.take<double>(L);
+  S->sb = buf.take<double>(n);
+  S->sy = buf.take<double>(n);
+  S->sx = buf.take<double>(n);
+}
+
+size_t workspace_bytes(const hc_solver* S) {
+  if (S->bound) return S->mem_bytes;   // the dry run below would overwrite the device pointers
+  Buf b;
+  b.dry = true;
+  alloc_all(const_cast<hc_solver*>(S), b, nullptr);
+  return b.used + 4096;
+}
+
+void bind(hc_solver* S, const hc_device* dev) {
+  S->device = dev ? dev->device : 0;
+  HC_HIP(hipSetDevice(S->device));
+  S->stream = dev ? (hipStream_t)dev->stream : nullptr;
+  const size_t need = workspace_bytes(S);
+  Buf buf;
+  if (dev && dev->arena) {
+    if (dev->arena_bytes < need)
+      fail(HC_ERR_OOM, "arena too small: need " + std::to_string(need) + " bytes");
+    buf.base = (char*)dev->arena;
+    buf.size = dev->arena_bytes;
+  } else {
+    void* p = nullptr;
+    if (hipMalloc(&p, need) != hipSuccess) fail(HC_ERR_OOM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+    S->own_mem = true;
+    S->mem = p;
+    buf.base = (char*)p;
+    buf.size = need;
+  }
+  S->mem_bytes = need;
+  hipStream_t st = S->stream;
+  alloc_all(S, buf, st);
+  HC_HIP(hipHostMalloc((void**)&S->hpart, 4096 * sizeof(double), hipHostMallocDefault));
+  HC_HIP(hipHostMalloc((void**)&S->hmask, 4096 * sizeof(unsigned long long), hipHostMallocDefault));
+  HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), st));
+  // segment views
+  int pow_off = 0;
+  for (const Segment& g : S->segs) {
+    SegDev d;
+    d.kind = g.kind;
+    d.dim = g.dim;
+    d.k = g.k;
+    d.base = g.base;
+    d.count = g.count;
+    d.state = S->dstate + g.state;
+    d.mblk = S->dmval + g.moff;
+    d.alpha = (g.kind == HC_CONE_POW) ? S->dalpha + pow_off : nullptr;
+    if (g.kind == HC_CONE_POW) pow_off += (int)g.count;
+    S->sdev.push_back(d);
+  }
+  S->bound = true;
+  init_point(S);
+  HC_HIP(hipStreamSynchronize(st));
+}
+
+void record(hc_solver* S, const Error& e) { S->last_error = e.msg; }
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+int32_t hc_settings_default(hc_settings* o) {
+  if (!o) return HC_ERR_INVALID_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->eps_feas = 1e-8;
+  o->eps_inf = 1e-8;
+  o->max_iter = 200;
+  o->precision = HC_PRECISION_FP64;
+  o->static_reg = 0.0;
+  o->dyn_reg = -1.0;
+  o->ir_abstol = 1e-12;
+  o->ir_reltol = 1e-12;
+  o->ir_max = 10;
+  o->beta = 1e-6;
+  o->backtrack = 0.8;
+  o->step_fraction = 0.99;
+  o->equilibrate = 1;
+  o->equil_iters = 10;
+  o->force_dual_scaling = 0;
+  o->verbose = 0;
+  return HC_OK;
+}
+
+int32_t hc_setup(hc_solver** out, const hc_problem* prob, const hc_settings* settings) {
+  if (!out) return HC_ERR_INVALID_ARG;
+  *out = nullptr;
+  hc_solver* S = new (std::nothrow) hc_solver();
+  if (!S) return HC_ERR_OOM;
+  try {
+    if (settings) S->st = *settings;
+    else hc_settings_default(&S->st);
+    const double t0 = now_ms();
+    validate(prob);
+    setup_host(S, prob);
+    S->info.setup_ms = now_ms() - t0;
+    S->info.n_ordered = S->n;
+    S->info.factor_flops = cholesky_flops(S->n);
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    delete S;
+    return e.code;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    delete S;
+    return HC_ERR_INVALID_ARG;
+  }
+  *out = S;
+  return HC_OK;
+}
+
+int32_t hc_workspace_bytes(const hc_solver* S, size_t* bytes) {
+  if (!S || !bytes) return HC_ERR_INVALID_ARG;
+  *bytes = workspace_bytes(S);
+  return HC_OK;
+}
+
+int32_t hc_bind(hc_solver* S, const hc_device* dev) {
+  if (!S) return HC_ERR_INVALID_ARG;
+  if (S->bound) return HC_ERR_STATE;
+  try {
+    const double t0 = now_ms();
+    bind(S, dev);
+    S->info.setup_ms += now_ms() - t0;
+  } catch (const Error& e) {
+    record(S, e);
+    g_last_error = e.msg;
+    return e.code;
+  }
+  return HC_OK;
+}
+
+int32_t hc_solve(hc_solver* S) {
+  if (!S) return HC_ERR_INVALID_ARG;
+  if (!S->bound) return HC_ERR_STATE;
+  try {
+    HC_HIP(hipSetDevice(S->device));
+    const double t0 = now_ms();
+    run_solve(S);
+    HC_HIP(hipStreamSynchronize(S->stream));
+    S->info.solve_ms = now_ms() - t0;
+    unsigned long long h = 0;
+    HC_HIP(hipMemcpy(&h, S->dhits, sizeof(h), hipMemcpyDeviceToHost));
+    S->info.pivot_guard_hits = (int64_t)h;
+  } catch (const Error& e) {
+    record(S, e);
+    g_last_error = e.msg;
+    return e.code;
+  }
+  return HC_OK;
+}
+
+int32_t hc_get_info(const hc_solver* S, hc_info* out) {
+  if (!S || !out) return HC_ERR_INVALID_ARG;
+  *out = S->info;
+  return HC_OK;
+}
+
+int32_t hc_get_solution(const hc_solver* S, double* x, double* sv, double* z) {
+  if (!S) return HC_ERR_INVALID_ARG;
+  if (!S->bound) return HC_ERR_STATE;
+  try {
+    const int64_t n = S->n, m = S->m;
+    std::vector<double> hx(n), hs(m), hz(m);
+    HC_HIP(hipMemcpy(hx.data(), S->x, n * 8, hipMemcpyDeviceToHost));
+    HC_HIP(hipMemcpy(hs.data(), S->s, m * 8, hipMemcpyDeviceToHost));
+    HC_HIP(hipMemcpy(hz.data(), S->z, m * 8, hipMemcpyDeviceToHost));
+    const bool cert = S->status == HC_STATUS_PRIMAL_INFEASIBLE || S->status == HC_STATUS_DUAL_INFEASIBLE;
+    const double t = cert ? 1.0 : S->tau;
+    if (x)
+      for (int64_t j = 0; j < n; ++j) x[j] = S->D[j] * hx[j] / t;
+    for (int64_t r = 0; r < m; ++r) {
+      const int64_t u = S->perm[r];
+      if (sv) sv[u] = hs[r] / S->E[r] / t;
+      if (z) z[u] = S->E[r] * hz[r] / (S->cscale * t);
+    }
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
+  return HC_OK;
+}
+
+int32_t hc_get_iterate(const hc_solver* S, double* x, double* sv, double* z, double* tau, double* kappa,
+                       int64_t* row_of_internal) {
+  if (!S) return HC_ERR_INVALID_ARG;
+  if (!S->bound) return HC_ERR_STATE;
+  try {
+    if (x) HC_HIP(hipMemcpy(x, S->x, S->n * 8, hipMemcpyDeviceToHost));
+    if (sv) HC_HIP(hipMemcpy(sv, S->s, S->m * 8, hipMemcpyDeviceToHost));
+    if (z) HC_HIP(hipMemcpy(z, S->z, S->m * 8, hipMemcpyDeviceToHost));
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
+  if (tau) *tau = S->tau;
+  if (kappa) *kappa = S->kappa;
+  if (row_of_internal) std::memcpy(row_of_internal, S->perm.data(), S->m * sizeof(int64_t));
+  return HC_OK;
+}
+
+void hc_destroy(hc_solver* S) {
+  if (!S) return;
+  if (S->own_mem && S->mem) (void)hipFree(S->mem);
+  if (S->hpart) (void)hipHostFree(S->hpart);
+  if (S->hmask) (void)hipHostFree(S->hmask);
+  delete S;
+}
+
+const char* hc_last_error(const hc_solver* S) {
+  if (S && !S->last_error.empty()) return S->last_error.c_str();
+  return g_last_error.c_str();
+}
+
+const char* hc_status_str(int32_t status) {
+  switch (status) {
+    case HC_STATUS_UNSOLVED: return "unsolved";
+    case HC_STATUS_SOLVED: return "solved";
+    case HC_STATUS_PRIMAL_INFEASIBLE: return "primal_infeasible";
+    case HC_STATUS_DUAL_INFEASIBLE: return "dual_infeasible";
+    case HC_STATUS_MAX_ITER: return "max_iter";
+    case HC_STATUS_INSUFFICIENT_PROGRESS: return "insufficient_progress";
+    case HC_STATUS_NUMERICAL_ERROR: return "numerical_error";
+  }
+  return "unknown";
+}
+
+}  // extern "C"

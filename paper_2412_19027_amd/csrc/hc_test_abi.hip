@@ -1,0 +1,252 @@
+// Kernel-level test entry points of the C-ABI: each marshals one cone family
+// between the caller's cone-by-cone layout and the solver's internal layout
+// and then runs exactly the kernels the solver runs.
+#include <cstring>
+#include <vector>
+
+#include "hc_cones.h"
+#include "hc_dense.h"
+#include "hc_vec.h"
+
+using namespace hc;
+
+namespace {
+
+thread_local std::string g_test_error;
+
+struct TestSeg {
+  SegDev g{};
+  int rows = 0;           // rows per cone (caller's view)
+  int64_t count = 0;      // caller's cones
+  bool cm = false;        // component-major internally
+  std::vector<void*> owned;
+  ~TestSeg() {
+    for (void* p : owned) (void)hipFree(p);
+  }
+  double* alloc(int64_t n) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<int64_t>(1, n) * sizeof(double)) != hipSuccess)
+      throw Error{HC_ERR_OOM, "hipMalloc failed"};
+    owned.push_back(p);
+    return (double*)p;
+  }
+  // caller (AoS) -> internal
+  double* in(const double* a, hipStream_t st) {
+    double* d = alloc(count * rows);
+    if (cm) aos_to_cm(count, rows, a, d, false, st);
+    else HC_HIP(hipMemcpyAsync(d, a, count * rows * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return d;
+  }
+  void out(const double* d, double* a, hipStream_t st) {
+    if (cm) aos_to_cm(count, rows, d, a, true, st);
+    else HC_HIP(hipMemcpyAsync(a, d, count * rows * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+};
+
+void make(TestSeg& T, int32_t type, int64_t count, int32_t dim, const double* alpha) {
+  if (count <= 0) throw Error{HC_ERR_INVALID_ARG, "count must be positive"};
+  T.count = count;
+  T.g.kind = type;
+  switch (type) {
+    case HC_CONE_ZERO:
+    case HC_CONE_NONNEG:
+      T.rows = dim;
+      T.g.dim = 1;
+      T.g.count = count * dim;
+      T.cm = false;
+      break;
+    case HC_CONE_SOC:
+      if (dim < 2 || dim > 16) throw Error{HC_ERR_UNSUPPORTED, "SOC dim outside [2, 16]"};
+      T.rows = dim; T.g.dim = dim; T.g.count = count; T.cm = true;
+      break;
+    case HC_CONE_EXP:
+    case HC_CONE_POW:
+      if (dim != 3) throw Error{HC_ERR_CONE, "EXP/POW dim != 3"};
+      if (type == HC_CONE_POW && !alpha) throw Error{HC_ERR_INVALID_ARG, "alpha is NULL"};
+      T.rows = 3; T.g.dim = 3; T.g.count = count; T.cm = true;
+      break;
+    case HC_CONE_PSD:
+      if (dim < 1 || dim > 12) throw Error{HC_ERR_UNSUPPORTED, "PSD side outside [1, 12]"};
+      T.rows = dim * (dim + 1) / 2; T.g.dim = T.rows; T.g.k = dim; T.g.count = count; T.cm = false;
+      break;
+    default:
+      throw Error{HC_ERR_CONE, "unknown cone type"};
+  }
+  T.g.base = 0;
+  T.g.state = T.alloc(state_doubles(type, T.g.dim, T.g.k) * T.g.count);
+  T.g.mblk = T.alloc(mblock_doubles(type, T.g.dim) * T.g.count);
+  T.g.alpha = alpha;
+}
+
+template <typename F> int32_t guard(F&& f) {
+  try {
+    f();
+  } catch (const Error& e) {
+    g_test_error = e.msg;
+    return e.code;
+  }
+  return HC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t hc_test_cone_scale(int32_t type, int64_t count, int32_t dim, const double* alpha, const double* s,
+                           const double* z, double mu, double* H_out, double* lam_out, int32_t* branch_out,
+                           void* stream) {
+  return guard([&] {
+    hipStream_t st = (hipStream_t)stream;
+    TestSeg T;
+    make(T, type, count, dim, alpha);
+    const int64_t tot = count * T.rows;
+    double* si = T.in(s, st);
+    double* zi = T.in(z, st);
+    double* hd = T.alloc(tot);
+    int* pd = (int*)T.alloc(1);
+    HC_HIP(hipMemsetAsync(pd, 0, sizeof(double), st));
+    cone_scale(T.g, si, zi, mu, 0, hd, pd, st);
+    // H column by column: H e_j
+    double* e = T.alloc(tot);
+    double* y = T.alloc(tot);
+    std::vector<double> he(tot), hy(tot), hH((size_t)count * T.rows * T.rows);
+    for (int j = 0; j < T.rows; ++j) {
+      for (int64_t c = 0; c < count; ++c)
+        for (int i = 0; i < T.rows; ++i) he[c * T.rows + i] = (i == j) ? 1.0 : 0.0;
+      double* ea = T.alloc(tot);
+      HC_HIP(hipMemcpyAsync(ea, he.data(), tot * 8, hipMemcpyHostToDevice, st));
+      double* ei = T.in(ea, st);
+      cone_apply(T.g, 0, 0.0, ei, y, st);
+      double* ya = T.alloc(tot);
+      T.out(y, ya, st);
+      HC_HIP(hipMemcpyAsync(hy.data(), ya, tot * 8, hipMemcpyDeviceToHost, st));
+      HC_HIP(hipStreamSynchronize(st));
+      for (int64_t c = 0; c < count; ++c)
+        for (int i = 0; i < T.rows; ++i) hH[(c * T.rows + i) * T.rows + j] = hy[c * T.rows + i];
+    }
+    (void)e;
+    if (H_out) HC_HIP(hipMemcpyAsync(H_out, hH.data(), hH.size() * 8, hipMemcpyHostToDevice, st));
+    if (lam_out) {
+      double* li = T.alloc(tot);
+      HC_HIP(hipMemsetAsync(li, 0, tot * 8, st));
+      cone_test_extract(T.g, si, 0, li, st);
+      T.out(li, lam_out, st);
+    }
+    if (branch_out) {
+      double* bi = T.alloc(T.g.count);
+      cone_test_extract(T.g, si, 2, bi, st);
+      std::vector<double> hb(T.g.count);
+      HC_HIP(hipMemcpyAsync(hb.data(), bi, T.g.count * 8, hipMemcpyDeviceToHost, st));
+      HC_HIP(hipStreamSynchronize(st));
+      std::vector<int32_t> ib(count);
+      for (int64_t c = 0; c < count; ++c) ib[c] = (type == HC_CONE_EXP || type == HC_CONE_POW) ? (int32_t)hb[c] : 0;
+      HC_HIP(hipMemcpyAsync(branch_out, ib.data(), count * 4, hipMemcpyHostToDevice, st));
+    }
+    HC_HIP(hipStreamSynchronize(st));
+  });
+}
+
+int32_t hc_test_cone_ds(int32_t type, int64_t count, int32_t dim, const double* alpha, const double* s,
+                        const double* z, const double* dsa, const double* dza, double mu, double sm, double* ds_out,
+                        void* stream) {
+  return guard([&] {
+    hipStream_t st = (hipStream_t)stream;
+    TestSeg T;
+    make(T, type, count, dim, alpha);
+    const int64_t tot = count * T.rows;
+    double* si = T.in(s, st);
+    double* zi = T.in(z, st);
+    double* ai = T.in(dsa, st);
+    double* bi = T.in(dza, st);
+    double* hd = T.alloc(tot);
+    int* pd = (int*)T.alloc(1);
+    HC_HIP(hipMemsetAsync(pd, 0, sizeof(double), st));
+    cone_scale(T.g, si, zi, mu, 0, hd, pd, st);
+    double* o = T.alloc(tot);
+    cone_ds_combined(T.g, si, zi, ai, bi, sm, o, st);
+    T.out(o, ds_out, st);
+    HC_HIP(hipStreamSynchronize(st));
+  });
+}
+
+int32_t hc_test_cone_step(int32_t type, int64_t count, int32_t dim, const double* alpha, const double* s,
+                          const double* z, const double* ds, const double* dz, double amax, double* alpha_out,
+                          void* stream) {
+  return guard([&] {
+    hipStream_t st = (hipStream_t)stream;
+    TestSeg T;
+    make(T, type, count, dim, alpha);
+    double* si = T.in(s, st);
+    double* zi = T.in(z, st);
+    double* a = T.in(ds, st);
+    double* b = T.in(dz, st);
+    double* o = T.alloc(T.g.count);
+    cone_test_step(T.g, si, zi, a, b, amax, o, st);
+    if (type == HC_CONE_ZERO || type == HC_CONE_NONNEG) {
+      // per caller cone: minimum over its rows
+      std::vector<double> h(T.g.count), r(count);
+      HC_HIP(hipMemcpyAsync(h.data(), o, T.g.count * 8, hipMemcpyDeviceToHost, st));
+      HC_HIP(hipStreamSynchronize(st));
+      for (int64_t c = 0; c < count; ++c) {
+        double v = amax;
+        for (int i = 0; i < T.rows; ++i) v = std::min(v, h[c * T.rows + i]);
+        r[c] = v;
+      }
+      HC_HIP(hipMemcpyAsync(alpha_out, r.data(), count * 8, hipMemcpyHostToDevice, st));
+    } else {
+      HC_HIP(hipMemcpyAsync(alpha_out, o, count * 8, hipMemcpyDeviceToDevice, st));
+    }
+    HC_HIP(hipStreamSynchronize(st));
+  });
+}
+
+int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, double* A, int32_t nrhs, double* B,
+                                 int64_t* guard_hits, void* stream) {
+  return guard([&] {
+    if (n <= 0 || ld < n || nrhs < 1 || nrhs > 4 || !A || !B) throw Error{HC_ERR_INVALID_ARG, "bad dense test args"};
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<void*> owned;
+    auto al = [&](size_t bytes) {
+      void* p = nullptr;
+      if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) throw Error{HC_ERR_OOM, "hipMalloc failed"};
+      owned.push_back(p);
+      return p;
+    };
+    unsigned long long* hits = (unsigned long long*)al(8);
+    HC_HIP(hipMemsetAsync(hits, 0, 8, st));
+    try {
+      if (precision == HC_PRECISION_MIXED) {
+        float* A32 = (float*)al((size_t)ld * n * 4);
+        float* L32 = (float*)al(linv_elems(n) * 4);
+        float* b32 = (float*)al((size_t)n * nrhs * 4);
+        float* y32 = (float*)al((size_t)n * nrhs * 4);
+        float* x32 = (float*)al((size_t)n * nrhs * 4);
+        lower_to_f32(n, ld, A, A32, st);
+        dense_cholesky<float>(A32, n, ld, L32, 0.0, 1e-8, hits, st);
+        double* one = (double*)al(8);
+        const double h1 = 1.0;
+        HC_HIP(hipMemcpyAsync(one, &h1, 8, hipMemcpyHostToDevice, st));
+        to_f32((int64_t)n * nrhs, B, one, b32, st);
+        dense_solve<float>(A32, n, ld, L32, b32, y32, x32, nrhs, st);
+        from_f32((int64_t)n * nrhs, x32, one, B, st);
+      } else {
+        double* Li = (double*)al(linv_elems(n) * 8);
+        double* y = (double*)al((size_t)n * nrhs * 8);
+        double* x = (double*)al((size_t)n * nrhs * 8);
+        dense_cholesky<double>(A, n, ld, Li, 0.0, 1e-8, hits, st);
+        dense_solve<double>(A, n, ld, Li, B, y, x, nrhs, st);
+        HC_HIP(hipMemcpyAsync(B, x, (size_t)n * nrhs * 8, hipMemcpyDeviceToDevice, st));
+      }
+      unsigned long long h = 0;
+      HC_HIP(hipMemcpyAsync(&h, hits, 8, hipMemcpyDeviceToHost, st));
+      HC_HIP(hipStreamSynchronize(st));
+      if (guard_hits) *guard_hits = (int64_t)h;
+    } catch (...) {
+      for (void* p : owned) (void)hipFree(p);
+      throw;
+    }
+    for (void* p : owned) (void)hipFree(p);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,345 @@
+// Vector, sparse and reduction kernels of the IPM (gfx950): SpMV for A, A'
+// and P (residuals, eq. residuals-objectives; KKT products), fused axpys,
+// ordered block reductions, and the assembly of the KKT Schur complement.
+#include "hc_vec.h"
+
+#include <cmath>
+
+namespace hc {
+
+// max that propagates NaN (a NaN residual must never pass a test)
+__device__ inline double nmax(double a, double b) { return (a != a || b != b) ? NAN : (a > b ? a : b); }
+
+// ---------------------------------------------------------------------------
+// CSR SpMV: LPR lanes per row (1, 4, 16 or 64), chosen from the mean row length
+// ---------------------------------------------------------------------------
+template <int LPR>
+__global__ __launch_bounds__(256) void k_spmv(int32_t nrows, const int32_t* __restrict__ rp,
+                                              const int32_t* __restrict__ ci, const double* __restrict__ v,
+                                              const double* __restrict__ x, double* __restrict__ y, double alpha,
+                                              double beta) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = t / LPR;
+  const int sub = (int)(t % LPR);
+  double acc = 0.0;
+  if (row < nrows) {
+    const int32_t b = rp[row], e = rp[row + 1];
+    for (int32_t p = b + sub; p < e; p += LPR) acc += v[p] * x[ci[p]];
+  }
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (row < nrows && sub == 0) y[row] = alpha * acc + (beta == 0.0 ? 0.0 : beta * y[row]);
+}
+
+void spmv(const Csr& A, const double* x, double* y, double alpha, double beta, hipStream_t st) {
+  if (A.nrows == 0) return;
+  const int64_t threads = (int64_t)A.nrows * A.lanes;
+  const unsigned grid = (unsigned)ceil_div(threads, 256);
+  switch (A.lanes) {
+    case 1: hipLaunchKernelGGL(k_spmv<1>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta); break;
+    case 4: hipLaunchKernelGGL(k_spmv<4>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta); break;
+    case 16: hipLaunchKernelGGL(k_spmv<16>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta); break;
+    default: hipLaunchKernelGGL(k_spmv<64>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta); break;
+  }
+  HC_LAUNCH_CHECK();
+}
+
+int choose_lanes(double mean_nnz) {
+  if (mean_nnz <= 6.0) return 1;
+  if (mean_nnz <= 24.0) return 4;
+  if (mean_nnz <= 96.0) return 16;
+  return 64;
+}
+
+// dense rows (row-major nd x n): y[rows[r]] += alpha * Ad[r, :] x   (one workgroup per row)
+__global__ __launch_bounds__(256) void k_dense_rows(int64_t n, const double* __restrict__ Ad,
+                                                    const int32_t* __restrict__ rows, const double* __restrict__ x,
+                                                    double* __restrict__ y, double alpha) {
+  __shared__ double red[256];
+  const int r = blockIdx.x;
+  double acc = 0;
+  for (int64_t j = threadIdx.x; j < n; j += 256) acc += Ad[(int64_t)r * n + j] * x[j];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) y[rows[r]] += alpha * red[0];
+}
+
+void dense_rows_gemv(int nd, int64_t n, const double* Ad, const int32_t* rows, const double* x, double* y,
+                     double alpha, hipStream_t st) {
+  if (nd == 0) return;
+  hipLaunchKernelGGL(k_dense_rows, dim3(nd), dim3(256), 0, st, n, Ad, rows, x, y, alpha);
+  HC_LAUNCH_CHECK();
+}
+
+// y[j] += alpha * sum_r Ad[r, j] v[rows[r]]
+__global__ void k_dense_rows_t(int nd, int64_t n, const double* __restrict__ Ad, const int32_t* __restrict__ rows,
+                               const double* __restrict__ v, double* __restrict__ y, double alpha) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double acc = 0;
+  for (int r = 0; r < nd; ++r) acc += Ad[(int64_t)r * n + j] * v[rows[r]];
+  y[j] += alpha * acc;
+}
+
+void dense_rows_gemv_t(int nd, int64_t n, const double* Ad, const int32_t* rows, const double* v, double* y,
+                       double alpha, hipStream_t st) {
+  if (nd == 0) return;
+  hipLaunchKernelGGL(k_dense_rows_t, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, nd, n, Ad, rows, v, y,
+                     alpha);
+  HC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// elementwise
+// ---------------------------------------------------------------------------
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+void vaxpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, a, x, b, y);
+  HC_LAUNCH_CHECK();
+}
+// z = a x + b y + c w  (any of y, w may be null)
+__global__ void k_lin3(int64_t n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                       double c, const double* __restrict__ w, double* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = a * x[i];
+  if (y) v += b * y[i];
+  if (w) v += c * w[i];
+  z[i] = v;
+}
+void vlin3(int64_t n, double a, const double* x, double b, const double* y, double c, const double* w, double* z,
+           hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_lin3, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, a, x, b, y, c, w, z);
+  HC_LAUNCH_CHECK();
+}
+void vcopy(int64_t n, const double* x, double* y, hipStream_t st) {
+  if (n == 0 || x == y) return;
+  HC_HIP(hipMemcpyAsync(y, x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+}
+__global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+void vfill(int64_t n, double v, double* y, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, v, y);
+  HC_LAUNCH_CHECK();
+}
+// y[i] = x[i] * w[i]  or  x[i] / w[i]
+__global__ void k_scale_by(int64_t n, const double* __restrict__ x, const double* __restrict__ w, int divide,
+                           double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = divide ? x[i] / w[i] : x[i] * w[i];
+}
+void vscale_by(int64_t n, const double* x, const double* w, bool divide, double* y, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_scale_by, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, x, w, divide ? 1 : 0, y);
+  HC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// reductions: per-block partials, combined on the host in block order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce(int64_t n, RedOps ops, double* __restrict__ partial) {
+  __shared__ double red[256];
+  for (int o = 0; o < ops.nops; ++o) {
+    const RedOp op = ops.op[o];
+    const bool is_sum = (op.kind == RED_DOT);
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+      if (op.kind == RED_DOT) {
+        acc += op.x[i] * op.y[i];
+      } else {
+        double v = op.x[i];
+        if (op.y) v += op.yc * op.y[i];
+        if (op.w) v = (op.kind == RED_MAX_MUL) ? v * op.w[i] : v / op.w[i];
+        acc = nmax(acc, fabs(v));
+      }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off)
+        red[threadIdx.x] = is_sum ? red[threadIdx.x] + red[threadIdx.x + off] : nmax(red[threadIdx.x], red[threadIdx.x + off]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ops.nops + o] = red[0];
+    __syncthreads();
+  }
+}
+
+int reduce_launch(int64_t n, const RedOps& ops, double* partial, hipStream_t st) {
+  const int nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, ceil_div(n, 256)));
+  hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(256), 0, st, n, ops, partial);
+  HC_LAUNCH_CHECK();
+  return nb;
+}
+
+// device-side max of partials into out[0] (no host round trip); used to scale
+// FP32 right-hand sides
+__global__ void k_combine_max(int nb, const double* __restrict__ partial, double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0;
+  for (int i = threadIdx.x; i < nb; i += 256) acc = fmax(acc, partial[i]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (red[0] > 0.0) ? red[0] : 1.0;
+}
+void combine_max(int nb, const double* partial, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_combine_max, dim3(1), dim3(256), 0, st, nb, partial, out);
+  HC_LAUNCH_CHECK();
+}
+
+// FP64 <-> FP32 with a device-side scale
+__global__ void k_to_f32(int64_t n, const double* __restrict__ x, const double* __restrict__ scale,
+                         float* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)(x[i] / scale[0]);
+}
+__global__ void k_from_f32(int64_t n, const float* __restrict__ x, const double* __restrict__ scale,
+                           double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)x[i] * scale[0];
+}
+void to_f32(int64_t n, const double* x, const double* scale, float* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, x, scale, y);
+  HC_LAUNCH_CHECK();
+}
+void from_f32(int64_t n, const float* x, const double* scale, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_from_f32, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, x, scale, y);
+  HC_LAUNCH_CHECK();
+}
+// lower triangle (including diagonal) of a column-major n x n FP64 matrix -> FP32
+__global__ void k_lower_to_f32(int64_t n, int64_t ld, const double* __restrict__ S, float* __restrict__ S32) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = j + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    S32[i + j * ld] = (float)S[i + j * ld];
+}
+void lower_to_f32(int64_t n, int64_t ld, const double* S, float* S32, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_lower_to_f32, dim3((unsigned)std::min<int64_t>(64, ceil_div(n, 256)), (unsigned)n), dim3(256),
+                     0, st, n, ld, S, S32);
+  HC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Schur complement assembly  S = P + delta I + A' M A  (lower triangle)
+// ---------------------------------------------------------------------------
+__global__ void k_fill_lower_zero(int64_t n, int64_t ld, double* __restrict__ S) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = j + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    S[i + j * ld] = 0.0;
+}
+void fill_lower_zero(int64_t n, int64_t ld, double* S, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_lower_zero, dim3((unsigned)std::min<int64_t>(64, ceil_div(n, 256)), (unsigned)n),
+                     dim3(256), 0, st, n, ld, S);
+  HC_LAUNCH_CHECK();
+}
+
+// P (full CSR) lower part + delta on the diagonal
+__global__ void k_add_P(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                        const double* __restrict__ v, double delta, int64_t ld, double* __restrict__ S) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  S[i + (int64_t)i * ld] += delta;
+  if (!rp) return;
+  for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+    const int32_t j = ci[p];
+    if (j <= i) S[i + (int64_t)j * ld] += v[p];
+  }
+}
+void add_P_delta(const Csr& P, int64_t n, double delta, int64_t ld, double* S, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_P, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, (int32_t)n, P.rowptr, P.col, P.val,
+                     delta, ld, S);
+  HC_LAUNCH_CHECK();
+}
+
+// one task = an unordered pair of rows (ra >= rb, same cone) with the index of
+// M_c[ra, rb]; adds M * (a_ra a_rb' + a_rb a_ra') (or M a a' when ra == rb)
+// into the lower triangle with hardware FP64 atomics.
+__global__ __launch_bounds__(256) void k_assemble_pairs(int64_t ntask, const int32_t* __restrict__ tra,
+                                                        const int32_t* __restrict__ trb,
+                                                        const int64_t* __restrict__ tm,
+                                                        const double* __restrict__ mval, const int32_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ ci, const double* __restrict__ av,
+                                                        int64_t ld, double* __restrict__ S) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntask) return;
+  const int32_t ra = tra[t], rb = trb[t];
+  const double m = mval[tm[t]];
+  if (m == 0.0) return;
+  const int32_t ba = rp[ra], ea = rp[ra + 1], bb = rp[rb], eb = rp[rb + 1];
+  if (ra == rb) {
+    for (int32_t p = ba; p < ea; ++p) {
+      const int32_t j = ci[p];
+      const double mj = m * av[p];
+      for (int32_t q = ba; q <= p; ++q) atomicAdd(&S[j + (int64_t)ci[q] * ld], mj * av[q]);
+    }
+  } else {
+    for (int32_t p = ba; p < ea; ++p) {
+      const int32_t j = ci[p];
+      const double mj = m * av[p];
+      for (int32_t q = bb; q < eb; ++q) {
+        const int32_t k = ci[q];
+        double v = mj * av[q];
+        if (j == k) v *= 2.0;
+        const int32_t hi = j > k ? j : k, lo = j > k ? k : j;
+        atomicAdd(&S[hi + (int64_t)lo * ld], v);
+      }
+    }
+  }
+}
+void assemble_pairs(int64_t ntask, const int32_t* tra, const int32_t* trb, const int64_t* tm, const double* mval,
+                    const Csr& A, int64_t ld, double* S, hipStream_t st) {
+  if (ntask == 0) return;
+  hipLaunchKernelGGL(k_assemble_pairs, dim3((unsigned)ceil_div(ntask, 256)), dim3(256), 0, st, ntask, tra, trb, tm,
+                     mval, A.rowptr, A.col, A.val, ld, S);
+  HC_LAUNCH_CHECK();
+}
+
+// B (nd x n row-major, i.e. n x nd column-major with ld n) = sqrt(m_r) Ad[r, :]
+__global__ void k_scale_dense_rows(int nd, int64_t n, const double* __restrict__ Ad, const int64_t* __restrict__ midx,
+                                   const double* __restrict__ mval, double* __restrict__ B) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (j < n) B[(int64_t)r * n + j] = sqrt(mval[midx[r]]) * Ad[(int64_t)r * n + j];
+}
+void scale_dense_rows(int nd, int64_t n, const double* Ad, const int64_t* midx, const double* mval, double* B,
+                      hipStream_t st) {
+  if (nd == 0) return;
+  hipLaunchKernelGGL(k_scale_dense_rows, dim3((unsigned)ceil_div(n, 256), (unsigned)nd), dim3(256), 0, st, nd, n, Ad,
+                     midx, mval, B);
+  HC_LAUNCH_CHECK();
+}
+
+// transpose between cone-by-cone (AoS) and component-major layouts (test entry points)
+__global__ void k_aos_to_cm(int64_t count, int dim, const double* __restrict__ a, double* __restrict__ c, int inverse) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count * dim) return;
+  const int64_t i = t / dim;
+  const int j = (int)(t % dim);
+  if (!inverse) c[j * count + i] = a[t];
+  else c[t] = a[j * count + i];
+}
+void aos_to_cm(int64_t count, int dim, const double* a, double* c, bool inverse, hipStream_t st) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_aos_to_cm, dim3((unsigned)ceil_div(count * dim, 256)), dim3(256), 0, st, count, dim, a, c,
+                     inverse ? 1 : 0);
+  HC_LAUNCH_CHECK();
+}
+
+}  // namespace hc

@@ -1,0 +1,251 @@
+"""Python binding of the hipcone C-ABI (include/hipcone.h): argument marshalling only.
+
+Every step of the interior-point method runs in libhipcone.so's HIP kernels;
+PyTorch supplies the device arena and the stream.  The library must be built
+in-tree first (`python -m paper_2412_19027_amd.build`); importing the binding
+without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhipcone.so")
+
+ZERO, NONNEG, SOC, EXP, POW, PSD = 0, 1, 2, 3, 4, 5
+PRECISION_FP64, PRECISION_MIXED = 0, 1
+STATUS = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasible", 4: "max_iter",
+          5: "insufficient_progress", 6: "numerical_error"}
+
+EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "hc_solve", "hc_get_info",
+           "hc_get_solution", "hc_get_iterate", "hc_destroy", "hc_last_error", "hc_status_str",
+           "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_dense_chol_solve"]
+
+
+class hc_cone(C.Structure):
+    _fields_ = [("type", C.c_int32), ("dim", C.c_int32), ("alpha", C.c_double)]
+
+
+class hc_problem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64),
+                ("P_rowptr", C.POINTER(C.c_int64)), ("P_col", C.POINTER(C.c_int32)), ("P_val", C.POINTER(C.c_double)),
+                ("q", C.POINTER(C.c_double)),
+                ("A_rowptr", C.POINTER(C.c_int64)), ("A_col", C.POINTER(C.c_int32)), ("A_val", C.POINTER(C.c_double)),
+                ("b", C.POINTER(C.c_double)),
+                ("cones", C.POINTER(hc_cone)), ("ncones", C.c_int32)]
+
+
+class hc_settings(C.Structure):
+    _fields_ = [("eps_feas", C.c_double), ("eps_inf", C.c_double), ("max_iter", C.c_int32),
+                ("precision", C.c_int32), ("static_reg", C.c_double), ("dyn_reg", C.c_double),
+                ("ir_abstol", C.c_double), ("ir_reltol", C.c_double), ("ir_max", C.c_int32),
+                ("beta", C.c_double), ("backtrack", C.c_double), ("step_fraction", C.c_double),
+                ("equilibrate", C.c_int32), ("equil_iters", C.c_int32), ("force_dual_scaling", C.c_int32),
+                ("verbose", C.c_int32)]
+
+
+class hc_device(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("stream", C.c_void_p),
+                ("device", C.c_int32)]
+
+
+class hc_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("obj_primal", C.c_double),
+                ("obj_dual", C.c_double), ("res_primal", C.c_double), ("res_dual", C.c_double),
+                ("gap", C.c_double), ("mu", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
+                ("factor_ms", C.c_double), ("solve_kkt_ms", C.c_double), ("cone_ms", C.c_double),
+                ("ir_solves", C.c_int64), ("pivot_guard_hits", C.c_int64), ("dual_switches", C.c_int64),
+                ("n_ordered", C.c_int64), ("factor_flops", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhipcone.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2412_19027_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.hc_settings_default.argtypes = [C.POINTER(hc_settings)]
+        L.hc_setup.argtypes = [C.POINTER(vp), C.POINTER(hc_problem), C.POINTER(hc_settings)]
+        L.hc_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.hc_bind.argtypes = [vp, C.POINTER(hc_device)]
+        L.hc_solve.argtypes = [vp]
+        L.hc_get_info.argtypes = [vp, C.POINTER(hc_info)]
+        L.hc_get_solution.argtypes = [vp, vp, vp, vp]
+        L.hc_get_iterate.argtypes = [vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp]
+        L.hc_destroy.argtypes = [vp]
+        L.hc_destroy.restype = None
+        L.hc_last_error.argtypes = [vp]
+        L.hc_last_error.restype = C.c_char_p
+        L.hc_status_str.argtypes = [i32]
+        L.hc_status_str.restype = C.c_char_p
+        L.hc_test_cone_scale.argtypes = [i32, i64, i32, vp, vp, vp, dbl, vp, vp, vp, vp]
+        L.hc_test_cone_ds.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, dbl, dbl, vp, vp]
+        L.hc_test_cone_step.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, dbl, vp, vp]
+        L.hc_test_dense_chol_solve.argtypes = [i32, i64, i64, vp, i32, vp, C.POINTER(i64), vp]
+        for name in EXPORTS:
+            getattr(L, name)
+        _lib = L
+    return _lib
+
+
+class HipconeError(RuntimeError):
+    pass
+
+
+def _check(rc, handle=None):
+    if rc != 0:
+        msg = lib().hc_last_error(handle).decode(errors="replace")
+        raise HipconeError(f"hipcone error {rc}: {msg}")
+
+
+def default_settings(**overrides) -> hc_settings:
+    st = hc_settings()
+    _check(lib().hc_settings_default(C.byref(st)))
+    for k, v in overrides.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISION_MIXED if v == "mixed" else PRECISION_FP64
+        setattr(st, k, v)
+    return st
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class Solver:
+    """One problem on one GPU.  `prob` is a workloads.Problem (or any object
+    with n, m, P (upper CSR), q, A (CSR), b, cones)."""
+
+    def __init__(self, prob, device=0, stream=None, **settings):
+        import torch
+        self._torch = torch
+        L = lib()
+        P = prob.P.tocsr()
+        A = prob.A.tocsr()
+        self._keep = dict(
+            Prp=np.ascontiguousarray(P.indptr, dtype=np.int64), Pci=np.ascontiguousarray(P.indices, dtype=np.int32),
+            Pv=np.ascontiguousarray(P.data, dtype=np.float64), q=np.ascontiguousarray(prob.q, dtype=np.float64),
+            Arp=np.ascontiguousarray(A.indptr, dtype=np.int64), Aci=np.ascontiguousarray(A.indices, dtype=np.int32),
+            Av=np.ascontiguousarray(A.data, dtype=np.float64), b=np.ascontiguousarray(prob.b, dtype=np.float64))
+        cones = (hc_cone * len(prob.cones))(*[hc_cone(int(k), int(d), float(a)) for k, d, a in prob.cones])
+        self._keep["cones"] = cones
+        k = self._keep
+        pr = hc_problem(prob.n, prob.m, _ptr(k["Prp"], C.c_int64), _ptr(k["Pci"], C.c_int32), _ptr(k["Pv"], C.c_double),
+                        _ptr(k["q"], C.c_double), _ptr(k["Arp"], C.c_int64), _ptr(k["Aci"], C.c_int32),
+                        _ptr(k["Av"], C.c_double), _ptr(k["b"], C.c_double), cones, len(prob.cones))
+        self.settings = default_settings(**settings)
+        self.n, self.m = prob.n, prob.m
+        h = C.c_void_p()
+        _check(L.hc_setup(C.byref(h), C.byref(pr), C.byref(self.settings)))
+        self._h = h
+        nbytes = C.c_size_t()
+        _check(L.hc_workspace_bytes(h, C.byref(nbytes)), h)
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        dev = hc_device(self.arena.data_ptr(), int(nbytes.value), self.stream.cuda_stream, self.device.index or 0)
+        _check(L.hc_bind(h, C.byref(dev)), h)
+
+    def solve(self):
+        _check(lib().hc_solve(self._h), self._h)
+        return self.info()
+
+    def info(self) -> dict:
+        inf = hc_info()
+        _check(lib().hc_get_info(self._h, C.byref(inf)), self._h)
+        out = {f: getattr(inf, f) for f, _ in hc_info._fields_}
+        out["status_name"] = STATUS.get(inf.status, "unknown")
+        return out
+
+    def solution(self):
+        x = np.zeros(self.n)
+        s = np.zeros(self.m)
+        z = np.zeros(self.m)
+        _check(lib().hc_get_solution(self._h, x.ctypes.data, s.ctypes.data, z.ctypes.data), self._h)
+        return x, s, z
+
+    def iterate(self):
+        x = np.zeros(self.n)
+        s = np.zeros(self.m)
+        z = np.zeros(self.m)
+        perm = np.zeros(self.m, dtype=np.int64)
+        tau, kappa = C.c_double(), C.c_double()
+        _check(lib().hc_get_iterate(self._h, x.ctypes.data, s.ctypes.data, z.ctypes.data, C.byref(tau),
+                                    C.byref(kappa), perm.ctypes.data), self._h)
+        return x, s, z, tau.value, kappa.value, perm
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------
+# kernel test entry points (device tensors)
+# --------------------------------------------------------------------------
+def _dptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def test_cone_scale(kind, dim, s, z, mu, alpha=None):
+    """Scaling of `count` cones given cone by cone (torch cuda float64, shape (count, rows))."""
+    import torch
+    count, rows = s.shape
+    H = torch.zeros((count, rows, rows), dtype=torch.float64, device=s.device)
+    lam = torch.zeros((count, rows), dtype=torch.float64, device=s.device)
+    br = torch.zeros(count, dtype=torch.int32, device=s.device)
+    _check(lib().hc_test_cone_scale(kind, count, dim, _dptr(alpha), _dptr(s.contiguous()), _dptr(z.contiguous()),
+                                    float(mu), _dptr(H), _dptr(lam), _dptr(br), _stream()))
+    torch.cuda.synchronize()
+    return H, lam, br
+
+
+def test_cone_ds(kind, dim, s, z, dsa, dza, mu, sm, alpha=None):
+    import torch
+    out = torch.zeros_like(s)
+    _check(lib().hc_test_cone_ds(kind, s.shape[0], dim, _dptr(alpha), _dptr(s.contiguous()), _dptr(z.contiguous()),
+                                 _dptr(dsa.contiguous()), _dptr(dza.contiguous()), float(mu), float(sm), _dptr(out),
+                                 _stream()))
+    torch.cuda.synchronize()
+    return out
+
+
+def test_cone_step(kind, dim, s, z, ds, dz, amax, alpha=None):
+    import torch
+    out = torch.zeros(s.shape[0], dtype=torch.float64, device=s.device)
+    _check(lib().hc_test_cone_step(kind, s.shape[0], dim, _dptr(alpha), _dptr(s.contiguous()), _dptr(z.contiguous()),
+                                   _dptr(ds.contiguous()), _dptr(dz.contiguous()), float(amax), _dptr(out), _stream()))
+    torch.cuda.synchronize()
+    return out
+
+
+def test_dense_chol_solve(A, B, precision=PRECISION_FP64):
+    """A: (n, n) SPD (torch cuda float64, column-major taken as A.T storage); B: (n, nrhs). In place."""
+    import torch
+    n = A.shape[0]
+    At = A.t().contiguous()          # column-major storage of A
+    Bt = B.t().contiguous()          # column-major (n x nrhs)
+    hits = C.c_int64()
+    _check(lib().hc_test_dense_chol_solve(precision, n, n, _dptr(At), Bt.shape[0], _dptr(Bt), C.byref(hits),
+                                          _stream()))
+    torch.cuda.synchronize()
+    return Bt.t().contiguous(), At.t().contiguous(), hits.value

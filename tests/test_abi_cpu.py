@@ -1,0 +1,58 @@
+"""CPU-side checks of the C-ABI library: it loads and exports every entry
+point include/hipcone.h declares (no compute calls: there is no GPU here)."""
+import os
+import re
+
+import pytest
+
+from paper_2412_19027_amd import hipcone
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "hipcone.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int32_t|void|const char\*)\s+(hc_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_binding_exports():
+    assert set(declared_functions()) == set(hipcone.EXPORTS)
+
+
+@pytest.mark.skipif(not os.path.exists(hipcone.LIB_PATH), reason="libhipcone.so not built")
+def test_library_exports_every_declared_symbol():
+    L = hipcone.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(hipcone.LIB_PATH), reason="libhipcone.so not built")
+def test_settings_defaults_and_status_strings():
+    st = hipcone.default_settings()
+    assert st.eps_feas == 1e-8 and st.max_iter == 200 and st.ir_max == 10 and st.backtrack == 0.8
+    assert hipcone.lib().hc_status_str(1) == b"solved"
+
+
+@pytest.mark.skipif(not os.path.exists(hipcone.LIB_PATH), reason="libhipcone.so not built")
+def test_setup_validation_errors_on_host():
+    """hc_setup validates on the host without touching a device."""
+    import ctypes as C
+    import numpy as np
+    L = hipcone.lib()
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    ci = np.array([0, 0], dtype=np.int32)
+    v = np.array([1.0, np.nan])
+    q = np.zeros(1)
+    b = np.zeros(2)
+    cones = (hipcone.hc_cone * 1)(hipcone.hc_cone(1, 2, 0.0))
+    pr = hipcone.hc_problem(1, 2, None, None, None, q.ctypes.data_as(C.POINTER(C.c_double)),
+                            rp.ctypes.data_as(C.POINTER(C.c_int64)), ci.ctypes.data_as(C.POINTER(C.c_int32)),
+                            v.ctypes.data_as(C.POINTER(C.c_double)), b.ctypes.data_as(C.POINTER(C.c_double)), cones, 1)
+    h = C.c_void_p()
+    assert L.hc_setup(C.byref(h), C.byref(pr), None) == -5          # HC_ERR_NONFINITE
+    v[1] = 2.0
+    cones[0] = hipcone.hc_cone(1, 3, 0.0)
+    assert L.hc_setup(C.byref(h), C.byref(pr), None) == -2          # rows do not add up
+    cones[0] = hipcone.hc_cone(2, 2, 0.0)
+    assert L.hc_setup(C.byref(h), C.byref(pr), None) == 0
+    L.hc_destroy(h)

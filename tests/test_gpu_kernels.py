@@ -1,0 +1,185 @@
+"""GPU parity of single steps: the C-ABI's kernel entry points against the
+CPU oracle on the same seeded inputs (FP64: 1e-12 relative), and the dense
+Schur-complement factorisation against numpy."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import cones as C  # noqa: E402
+from paper_2412_19027_amd import hipcone as HC  # noqa: E402
+from tests.test_oracle_cones import exp_dual, exp_primal, pow_dual, pow_primal, soc_interior, spd  # noqa: E402
+
+DEV = "cuda"
+RNG = np.random.default_rng(2024)
+
+
+def T(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# ----------------------------------------------------------------- dense factor
+@pytest.mark.parametrize("n", [1, 37, 64, 200, 333, 700])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_dense_cholesky_fp64(n, nrhs):
+    G = RNG.standard_normal((n, n))
+    A = G @ G.T + n * np.eye(n)
+    B = RNG.standard_normal((n, nrhs))
+    X, L, hits = HC.test_dense_chol_solve(T(A), T(B), HC.PRECISION_FP64)
+    ref = np.linalg.solve(A, B)
+    assert hits == 0
+    assert relerr(N(X), ref) < 1e-11
+    Lh = np.tril(N(L))
+    assert relerr(Lh @ Lh.T, A) < 1e-13
+
+
+@pytest.mark.parametrize("n", [64, 300, 513])
+def test_dense_cholesky_fp32(n):
+    G = RNG.standard_normal((n, n))
+    A = G @ G.T + n * np.eye(n)
+    B = RNG.standard_normal((n, 2))
+    X, _, hits = HC.test_dense_chol_solve(T(A), T(B), HC.PRECISION_MIXED)
+    assert hits == 0
+    assert relerr(N(X), np.linalg.solve(A, B)) < 1e-4
+
+
+# ----------------------------------------------------------------- cone scaling
+def test_nonneg_scale():
+    s, z = RNG.uniform(0.01, 3, (40, 5)), RNG.uniform(0.01, 3, (40, 5))
+    H, lam, _ = HC.test_cone_scale(HC.NONNEG, 5, T(s), T(z), 1.0)
+    assert relerr(N(lam), s / z) < 1e-15
+    assert relerr(np.diagonal(N(H), axis1=1, axis2=2), s / z) < 1e-15
+
+
+@pytest.mark.parametrize("d", [2, 3, 5])
+def test_soc_scale(d):
+    s, z = soc_interior(300, d, RNG), soc_interior(300, d, RNG)
+    H, lam, _ = HC.test_cone_scale(HC.SOC, d, T(s), T(z), 1.0)
+    ref = C.soc_scale(s, z)
+    assert relerr(N(H), ref["H"]) < 1e-12
+    assert relerr(N(lam), ref["lam"]) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["exp", "pow"])
+def test_nonsym_scale(kind):
+    Nc = 400
+    if kind == "exp":
+        fam, s, z, alpha = C.NonsymFamily("exp"), exp_primal(Nc, RNG), exp_dual(Nc, RNG), None
+    else:
+        a = RNG.uniform(0.2, 0.8, Nc)
+        fam, s, z, alpha = C.NonsymFamily("pow", a), pow_primal(Nc, a, RNG), pow_dual(Nc, a, RNG), T(a)
+    mu = 0.37
+    H, zt, br = HC.test_cone_scale(HC.EXP if kind == "exp" else HC.POW, 3, T(s), T(z), mu, alpha)
+    ref = fam.scale(s, z, mu)
+    assert (N(br) == ref["branch"]).all()
+    assert relerr(N(zt), ref["zt"]) < 1e-12
+    assert relerr(N(H), ref["H"]) < 1e-12
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_psd_scale(k):
+    S, Z = spd(60, k, RNG), spd(60, k, RNG)
+    s, z = C.svec(S), C.svec(Z)
+    H, lam, _ = HC.test_cone_scale(HC.PSD, k, T(s), T(z), 1.0)
+    ref = C.psd_scale(s, z, k)
+    assert relerr(N(H), ref["H"]) < 1e-12
+    assert relerr(np.sort(N(lam)[:, :k], 1), np.sort(ref["lam"], 1)) < 1e-12
+
+
+# ----------------------------------------------------------------- combined-step d_s
+def _oracle_ds(kind, s, z, dsa, dza, mu, sm, k=None, alpha=None):
+    from oracle import ipm
+    if kind == "nonneg":
+        sc = C.nn_scale(s, z)
+        return (s * z + dsa * dza - sm) / z
+    if kind == "soc":
+        sc = C.soc_scale(s, z)
+        W, Winv, lam = sc["W"], sc["Winv"], sc["lam"]
+        eta = C.soc_circ(np.einsum("cji,cj->ci", Winv, dsa), np.einsum("cij,cj->ci", W, dza))
+        e = np.zeros_like(lam); e[:, 0] = 1
+        v = C.soc_circ(lam, lam) + eta - sm * e
+        return np.einsum("cji,cj->ci", W, C.soc_inv_circ(lam, v))
+    if kind == "psd":
+        sc = C.psd_scale(s, z, k)
+        R, Rinv, lam = sc["R"], sc["Rinv"], sc["lam"]
+        Aa = np.einsum("cij,cjk,clk->cil", Rinv, C.smat(dsa, k), Rinv)
+        Bb = np.einsum("cji,cjk,ckl->cil", R, C.smat(dza, k), R)
+        V = C.psd_circ(Aa, Bb) + np.einsum("ci,ij->cij", lam * lam, np.eye(k)) - sm * np.eye(k)[None]
+        X = 2.0 * V / (lam[:, :, None] + lam[:, None, :])
+        return C.svec(np.einsum("cij,cjk,clk->cil", R, X, R))
+    fam = C.NonsymFamily(kind, alpha)
+    sc = fam.scale(s, z, mu)
+    u = fam.hinv_apply(sc["hinv"], dsa)
+    return s + sm * sc["grad"] - 0.5 * fam.third(z, dza, u)
+
+
+@pytest.mark.parametrize("kind", ["nonneg", "soc", "exp", "pow", "psd"])
+def test_combined_ds(kind):
+    Nc = 200
+    mu, sm = 0.8, 0.05
+    alpha = None
+    if kind == "nonneg":
+        s, z, dim, code = RNG.uniform(0.1, 2, (Nc, 1)), RNG.uniform(0.1, 2, (Nc, 1)), 1, HC.NONNEG
+    elif kind == "soc":
+        s, z, dim, code = soc_interior(Nc, 4, RNG), soc_interior(Nc, 4, RNG), 4, HC.SOC
+    elif kind == "exp":
+        s, z, dim, code = exp_primal(Nc, RNG), exp_dual(Nc, RNG), 3, HC.EXP
+    elif kind == "pow":
+        alpha = RNG.uniform(0.2, 0.8, Nc)
+        s, z, dim, code = pow_primal(Nc, alpha, RNG), pow_dual(Nc, alpha, RNG), 3, HC.POW
+    else:
+        s, z, dim, code = C.svec(spd(Nc, 3, RNG)), C.svec(spd(Nc, 3, RNG)), 3, HC.PSD
+    dsa, dza = 0.3 * RNG.standard_normal(s.shape), 0.3 * RNG.standard_normal(s.shape)
+    out = HC.test_cone_ds(code, dim, T(s), T(z), T(dsa), T(dza), mu, sm, None if alpha is None else T(alpha))
+    ref = _oracle_ds(kind, s, z, dsa, dza, mu, sm, k=3, alpha=alpha)
+    assert relerr(N(out), ref) < 1e-12
+
+
+# ----------------------------------------------------------------- step lengths
+@pytest.mark.parametrize("kind", ["nonneg", "soc", "psd", "exp", "pow"])
+def test_step(kind):
+    Nc = 150
+    alpha = None
+    if kind == "nonneg":
+        s, z, dim, code = RNG.uniform(0.1, 2, (Nc, 1)), RNG.uniform(0.1, 2, (Nc, 1)), 1, HC.NONNEG
+    elif kind == "soc":
+        s, z, dim, code = soc_interior(Nc, 3, RNG), soc_interior(Nc, 3, RNG), 3, HC.SOC
+    elif kind == "psd":
+        s, z, dim, code = C.svec(spd(Nc, 3, RNG)), C.svec(spd(Nc, 3, RNG)), 3, HC.PSD
+    elif kind == "exp":
+        s, z, dim, code = exp_primal(Nc, RNG), exp_dual(Nc, RNG), 3, HC.EXP
+    else:
+        alpha = RNG.uniform(0.2, 0.8, Nc)
+        s, z, dim, code = pow_primal(Nc, alpha, RNG), pow_dual(Nc, alpha, RNG), 3, HC.POW
+    ds, dz = 2 * RNG.standard_normal(s.shape), 2 * RNG.standard_normal(s.shape)
+    out = N(HC.test_cone_step(code, dim, T(s), T(z), T(ds), T(dz), 1.0, None if alpha is None else T(alpha)))
+    if kind == "nonneg":
+        ref = np.minimum(1.0, np.minimum(C.nn_step(s, ds), C.nn_step(z, dz))[:, 0])
+    elif kind == "soc":
+        ref = np.minimum(1.0, np.minimum(C.soc_step(s, ds), C.soc_step(z, dz)))
+    elif kind == "psd":
+        ref = np.minimum(1.0, np.minimum(C.psd_step(s, ds, 3), C.psd_step(z, dz, 3)))
+    else:
+        fam = C.NonsymFamily(kind, alpha)
+        ref = np.zeros(Nc)
+        for i in range(Nc):
+            sub = C.NonsymFamily(kind, None if alpha is None else alpha[i:i + 1])
+            a = 1.0
+            for _ in range(64):
+                if sub.primal_interior(s[i:i + 1] + a * ds[i:i + 1])[0] and sub.dual_interior(z[i:i + 1] + a * dz[i:i + 1])[0]:
+                    ref[i] = a
+                    break
+                a *= 0.8
+        assert (out == ref).all()
+        return
+    assert relerr(out, ref) < 1e-12

@@ -1,0 +1,68 @@
+"""GPU whole-solver parity: hc_solve through the C-ABI against the FP64 CPU
+oracle on the same seeded problems (objective 1e-7 relative, residuals 1e-8),
+plus known optima."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import ipm  # noqa: E402
+from paper_2412_19027_amd import hipcone as HC  # noqa: E402
+from paper_2412_19027_amd import workloads as W  # noqa: E402
+from tests import problems_small as PS  # noqa: E402
+
+
+def gpu_solve(prob, **kw):
+    s = HC.Solver(prob, **kw)
+    info = s.solve()
+    x, sv, z = s.solution()
+    s.close()
+    return info, x, sv, z
+
+
+def certify(prob, x, sv, z, eps=1e-8):
+    P = prob.P + prob.P.T - sp.diags(prob.P.diagonal())
+    rp = -(prob.A @ x) - sv + prob.b
+    rd = P @ x + prob.A.T @ z + prob.q
+    gp = 0.5 * x @ (P @ x) + prob.q @ x
+    gd = -0.5 * x @ (P @ x) - prob.b @ z
+    inf = lambda v: np.abs(v).max() if v.size else 0.0
+    assert inf(rp) < eps * max(1, inf(prob.b) + inf(x) + inf(sv))
+    assert inf(rd) < eps * max(1, inf(prob.q) + inf(x) + inf(z))
+    assert abs(gp - gd) < eps * max(1, min(abs(gp), abs(gd)))
+    return gp
+
+
+@pytest.mark.parametrize("make", [PS.box_lp, PS.soc_ball, PS.exp_max, PS.softplus, PS.entropy, PS.pow_max,
+                                  PS.trace_min, PS.lqr])
+def test_known_optimum(make):
+    prob, fstar = make()
+    info, x, sv, z = gpu_solve(prob)
+    assert info["status_name"] == "solved", info
+    certify(prob, x, sv, z)
+    assert abs(info["obj_primal"] - fstar) <= 1e-6 * max(1.0, abs(fstar))
+
+
+CASES = [
+    ("tiny_lp_0", lambda: W.tiny_lp(0)),
+    ("tiny_lp_1", lambda: W.tiny_lp(1)),
+    ("socp_small", lambda: W.sparse_socp(0, nx=600, rank=5, n_zero=150, n_nonneg=400, n_soc=500)),
+    ("mpc_0", lambda: W.mpc_socp(0, 0)),
+    ("exp_small", lambda: W.logreg_exp(0, samples=400, features=30)),
+    ("psdpow_small", lambda: W.psd_pow(0, n=250, n_pow=120, n_psd=25, k=4)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_against_oracle(name, make, precision):
+    prob = make()
+    ref = ipm.solve(prob)
+    assert ref.status == ipm.SOLVED
+    info, x, sv, z = gpu_solve(prob, precision=precision)
+    assert info["status_name"] == "solved", (name, info)
+    gp = certify(prob, x, sv, z)
+    assert abs(gp - ref.objective) <= 1e-7 * max(1.0, abs(ref.objective)), (gp, ref.objective)
