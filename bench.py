@@ -1,0 +1,147 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X interior-point hot path on the sparse-SOCP workload.
+
+One step = one complete solve to the 1e-8 tests from the initial point
+(every row of the hot path: residuals, cone scalings, KKT factorisation,
+refinement solves, directions, step lengths, update), with the problem
+already resident in HBM.  `value` = IPM iterations per second over the timed
+solves; ms_per_step = milliseconds per solve.
+
+Prints one JSON line.  Flags: --steps K --warmup W (solves), --gpus N (only
+N = 1 exists: there is one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "time per IPM iteration & solve-to-1e-8 gap; batched solves/s + p50/p99 latency"
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def workload_desc(p):
+    return (f"sparse_socp: n={p.n} (x 20,000 + 20 factor vars), m={p.m} (zero 10,020 incl. 20 dense lift rows, "
+            f"nonneg 30,000, 40,000 SOC-3), A 6 nnz/row N(0,1), P = diag(U(0.01,1)) + rank-20 factor, seed 0")
+
+
+def run_gpu(prob, precision, steps, warmup):
+    import torch
+    from paper_2412_19027_amd import hipcone as HC
+    solver = HC.Solver(prob, precision=precision, profile=1)
+    for _ in range(warmup):
+        solver.solve()
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos.append(solver.solve())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    iters = sum(i["iterations"] for i in infos)
+    gemm_ms = sum(i["gemm_ms"] for i in infos)
+    gemm_flops = sum(i["gemm_flops"] for i in infos)
+    launches = sum(i["gemm_launches"] for i in infos)
+    last = infos[-1]
+    x, s, z = solver.solution()
+    solver.close()
+    peak = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
+    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+    return dict(
+        wall=wall, iters=iters, infos=infos, status=last["status_name"], objective=last["obj_primal"],
+        res_primal=last["res_primal"], res_dual=last["res_dual"], gap=last["gap"],
+        iterations_per_solve=iters / steps, ms_per_solve=1e3 * wall / steps, ms_per_iteration=1e3 * wall / iters,
+        factor_ms_per_iteration=sum(i["factor_ms"] for i in infos) / iters,
+        kkt_ms_per_iteration=sum(i["solve_kkt_ms"] for i in infos) / iters,
+        cone_ms_per_iteration=sum(i["cone_ms"] for i in infos) / iters,
+        ir_solves_per_iteration=sum(i["ir_solves"] for i in infos) / iters,
+        roofline=dict(bound="mfma", kernel=f"k_gemm_nt<{'double' if precision == 'fp64' else 'float'}>",
+                      achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                      traffic=None, launches=launches, avg_launch_us=1e3 * gemm_ms / max(1, launches),
+                      algorithmic_flops_per_launch=gemm_flops / max(1, launches)),
+    )
+
+
+def cpu_baseline(prob):
+    """The oracle as it stands, on one IPM iteration of the same problem
+    (its setup and initial point are not timed)."""
+    from oracle import ipm
+    s = ipm.Solver(prob)
+    t0 = time.perf_counter()
+    s.iterate()
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=1.0 / dt, unit="IPM iterations/s", cores=cores, kind="oracle",
+                sample="one IPM iteration of the same sparse-SOCP problem (oracle setup, equilibration and "
+                       "initial point excluded); numpy/scipy FP64 with a LAPACK Cholesky of the 20,020 Schur "
+                       f"complement; {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from paper_2412_19027_amd import workloads as W
+    sc = args.scale
+    prob = W.sparse_socp(0, nx=int(20000 * sc), n_zero=int(10000 * sc), n_nonneg=int(30000 * sc),
+                         n_soc=int(40000 * sc))
+    main_run = run_gpu(prob, args.precision, args.steps, args.warmup)
+    other = None
+    if not args.no_mixed:
+        alt = "mixed" if args.precision == "fp64" else "fp64"
+        r = run_gpu(prob, alt, args.steps, args.warmup)
+        other = {k: r[k] for k in ("status", "objective", "res_primal", "res_dual", "gap", "iterations_per_solve",
+                                   "ms_per_solve", "ms_per_iteration", "factor_ms_per_iteration",
+                                   "kkt_ms_per_iteration", "ir_solves_per_iteration")}
+        other["precision"] = alt
+        other["roofline"] = r["roofline"]
+        other["objective_rel_diff_vs_main"] = abs(r["objective"] - main_run["objective"]) / max(
+            1.0, abs(main_run["objective"]))
+    cpu = None if args.no_cpu_baseline else cpu_baseline(prob)
+    out = {
+        "metric": METRIC,
+        "value": main_run["iters"] / main_run["wall"],
+        "unit": "IPM iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32-factor/f64",
+        "data": "synthetic",
+        "config": {"workload": workload_desc(prob), "precision": args.precision, "eps": 1e-8,
+                   "step": "one full solve from the initial point"},
+        "status": main_run["status"],
+        "objective": main_run["objective"],
+        "res_primal": main_run["res_primal"],
+        "res_dual": main_run["res_dual"],
+        "iterations_per_solve": main_run["iterations_per_solve"],
+        "ms_per_iteration": main_run["ms_per_iteration"],
+        "factor_ms_per_iteration": main_run["factor_ms_per_iteration"],
+        "kkt_ms_per_iteration": main_run["kkt_ms_per_iteration"],
+        "cone_ms_per_iteration": main_run["cone_ms_per_iteration"],
+        "ir_solves_per_iteration": main_run["ir_solves_per_iteration"],
+        "roofline": main_run["roofline"],
+        "alt_precision": other,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -103,6 +103,8 @@ typedef struct {
   int32_t equil_iters;    /* 10                                                     */
   int32_t force_dual_scaling; /* 0: exp/pow use the primal-dual (BFGS) scaling      */
   int32_t verbose;        /* 0                                                      */
+  int32_t profile;        /* 1: time the factorisation's MFMA update kernels with HIP
+                             events (hc_info.gemm_*); 0 = off                      */
 } hc_settings;
 
 /* ---- device hand-off ------------------------------------------------------ */
@@ -142,6 +144,10 @@ typedef struct {
   int64_t dual_switches;   /* iterations redone with the dual exp/pow scaling      */
   int64_t n_ordered;       /* size of the factored Schur complement                */
   double factor_flops;     /* per factorisation                                    */
+  int64_t factorizations;
+  double gemm_ms;          /* with settings.profile: summed duration of the MFMA     */
+  double gemm_flops;       /* update kernels and their algorithmic flops (2K per    */
+  int64_t gemm_launches;   /* lower-triangle entry updated)                          */
 } hc_info;
 
 typedef struct hc_solver hc_solver;
@@ -159,13 +165,15 @@ int32_t hc_setup(hc_solver** out, const hc_problem* prob, const hc_settings* set
 /* Device bytes hc_bind needs for this handle (arena size). */
 int32_t hc_workspace_bytes(const hc_solver* s, size_t* bytes);
 
-/* Place the solver on a device: sub-allocate the arena (or allocate), upload the
- * data and compute the initial point.  The arena and stream must outlive the
+/* Place the solver on a device: sub-allocate the arena (or allocate) and upload
+ * the data.  The arena and stream must outlive the
  * handle.  Errors: HC_ERR_STATE (already bound), HC_ERR_OOM, HC_ERR_DEVICE. */
 int32_t hc_bind(hc_solver* s, const hc_device* dev);
 
-/* Run the iterations of Algorithm 1 to termination on the handle's stream;
- * blocks until the status is known.  Errors: HC_ERR_STATE, HC_ERR_DEVICE. */
+/* Compute the initial point and run the iterations of Algorithm 1 to
+ * termination on the handle's stream; blocks until the status is known.  Each
+ * call is a complete solve from the initial point (repeat calls give the same
+ * result).  Errors: HC_ERR_STATE, HC_ERR_DEVICE. */
 int32_t hc_solve(hc_solver* s);
 
 int32_t hc_get_info(const hc_solver* s, hc_info* out);

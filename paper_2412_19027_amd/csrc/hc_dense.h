@@ -3,12 +3,22 @@
 #include "hc_common.h"
 
 namespace hc {
+// Optional HIP-event timing of the MFMA update launches of a factorisation.
+struct Prof {
+  std::vector<hipEvent_t> ev;   // pairs (start, stop)
+  size_t used = 0;
+  double flops = 0;             // algorithmic flops of the recorded launches
+  int64_t launches = 0;
+  hipEvent_t next();
+  double collect_ms();          // synchronises, sums elapsed times, resets the pool
+  ~Prof();
+};
 // In-place lower Cholesky of the n x n column-major S (leading dim ld).
 // Linv receives the inverses of the 64 x 64 diagonal factor blocks
 // (linv_elems(n) entries).  Pivots <= tol are replaced by fix and counted.
 template <typename T>
 void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
-                    hipStream_t st);
+                    hipStream_t st, Prof* prof = nullptr);
 // X = L^-T L^-1 B for nrhs <= 4 right-hand sides (column-major, leading dim
 // n); B and Y are overwritten (Y receives the forward result).
 template <typename T>

@@ -233,16 +233,55 @@ void gemm_nt(T* C, int64_t ldc, const T* A, int64_t lda, const T* B, int64_t ldb
   HC_LAUNCH_CHECK();
 }
 
+hipEvent_t Prof::next() {
+  if (used == ev.size()) {
+    hipEvent_t e;
+    HC_HIP(hipEventCreate(&e));
+    ev.push_back(e);
+  }
+  return ev[used++];
+}
+
+double Prof::collect_ms() {
+  double ms = 0;
+  for (size_t i = 0; i + 1 < used; i += 2) {
+    HC_HIP(hipEventSynchronize(ev[i + 1]));
+    float t = 0;
+    HC_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+    ms += t;
+  }
+  used = 0;
+  return ms;
+}
+
+Prof::~Prof() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
+// lower-triangle entries (global row >= global col) of the C block
+static double lower_entries(int64_t rc, int64_t cc, int64_t M, int64_t N) {
+  double cnt = 0;
+  for (int64_t j = cc; j < cc + N; ++j) cnt += (double)std::max<int64_t>(0, rc + M - std::max(rc, j));
+  return cnt;
+}
+
 // C -= A B' with every operand inside the one column-major matrix S
 template <typename T>
 static void gemm_nt_sub(T* S, int64_t ld, int64_t rc, int64_t cc, int64_t ra, int64_t rb, int64_t ka, int64_t M,
-                        int64_t N, int64_t K, bool lower, hipStream_t st) {
+                        int64_t N, int64_t K, bool lower, hipStream_t st, Prof* prof) {
+  if (M <= 0 || N <= 0 || K <= 0) return;
+  if (prof) HC_HIP(hipEventRecord(prof->next(), st));
   gemm_nt<T>(S + rc + cc * ld, ld, S + ra + ka * ld, ld, S + rb + ka * ld, ld, M, N, K, T(-1), lower, rc, cc, st);
+  if (prof) {
+    HC_HIP(hipEventRecord(prof->next(), st));
+    prof->flops += 2.0 * (double)K * lower_entries(rc, cc, M, N);
+    prof->launches++;
+  }
 }
 
 template <typename T>
 void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
-                    hipStream_t st) {
+                    hipStream_t st, Prof* prof) {
   for (int64_t K0 = 0; K0 < n; K0 += NB) {
     const int64_t Kend = std::min<int64_t>(n, K0 + NB);
     for (int64_t c = K0; c < Kend; c += BS) {
@@ -258,10 +297,10 @@ void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix
       }
       // eager update of the rest of this panel: columns [r0, Kend), rows [r0, n)
       if (r0 < Kend)
-        gemm_nt_sub<T>(S, ld, r0, r0, r0, r0, c, n - r0, Kend - r0, cb, true, st);
+        gemm_nt_sub<T>(S, ld, r0, r0, r0, r0, c, n - r0, Kend - r0, cb, true, st, prof);
     }
     // delayed update of the trailing matrix with the whole panel
-    if (Kend < n) gemm_nt_sub<T>(S, ld, Kend, Kend, Kend, Kend, K0, n - Kend, n - Kend, Kend - K0, true, st);
+    if (Kend < n) gemm_nt_sub<T>(S, ld, Kend, Kend, Kend, Kend, K0, n - Kend, n - Kend, Kend - K0, true, st, prof);
   }
 }
 
@@ -406,9 +445,9 @@ void dense_solve(const T* L, int64_t n, int64_t ld, const T* Linv, T* B, T* Y, T
 }
 
 template void dense_cholesky<double>(double*, int64_t, int64_t, double*, double, double, unsigned long long*,
-                                     hipStream_t);
+                                     hipStream_t, Prof*);
 template void dense_cholesky<float>(float*, int64_t, int64_t, float*, double, double, unsigned long long*,
-                                    hipStream_t);
+                                    hipStream_t, Prof*);
 template void gemm_nt<double>(double*, int64_t, const double*, int64_t, const double*, int64_t, int64_t, int64_t,
                               int64_t, double, bool, int64_t, int64_t, hipStream_t);
 template void gemm_nt<float>(float*, int64_t, const float*, int64_t, const float*, int64_t, int64_t, int64_t,

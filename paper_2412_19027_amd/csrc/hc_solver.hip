@@ -119,6 +119,7 @@ struct hc_solver {
   int status = 0;
   double delta = 0;
   double xPx_cache = 0;             // x'Px of the current iterate (from residuals)
+  std::unique_ptr<Prof> prof;
   std::string last_error;
 };
 
@@ -603,11 +604,20 @@ void factor(hc_solver* S) {
     gemm_nt<double>(S->dS, S->ld, S->dBd, S->n, S->dBd, S->n, S->n, S->n, nd, 1.0, true, 0, 0, st);
   }
   const double tol = 0.0;
+  Prof* pf = S->st.profile ? S->prof.get() : nullptr;
   if (S->mixed) {
     lower_to_f32(S->n, S->ld, S->dS, S->dS32, st);
-    dense_cholesky<float>(S->dS32, S->n, S->ld, S->dLinv32, tol, S->delta, S->dhits, st);
+    dense_cholesky<float>(S->dS32, S->n, S->ld, S->dLinv32, tol, S->delta, S->dhits, st, pf);
   } else {
-    dense_cholesky<double>(S->dS, S->n, S->ld, S->dLinv, tol, S->delta, S->dhits, st);
+    dense_cholesky<double>(S->dS, S->n, S->ld, S->dLinv, tol, S->delta, S->dhits, st, pf);
+  }
+  S->info.factorizations++;
+  if (pf) {
+    S->info.gemm_ms += pf->collect_ms();
+    S->info.gemm_flops += pf->flops;
+    S->info.gemm_launches += pf->launches;
+    pf->flops = 0;
+    pf->launches = 0;
   }
 }
 
@@ -1007,7 +1017,13 @@ int iterate(hc_solver* S, const Resid& R) {
 }
 
 void run_solve(hc_solver* S) {
-  S->info.iterations = 0;
+  const hc_info keep = S->info;
+  S->info = hc_info{};
+  S->info.setup_ms = keep.setup_ms;
+  S->info.n_ordered = keep.n_ordered;
+  S->info.factor_flops = keep.factor_flops;
+  HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), S->stream));
+  init_point(S);
   S->status = 0;
   for (int k = 0; k <= S->st.max_iter; ++k) {
     const Resid R = residuals(S);
@@ -1135,8 +1151,8 @@ void bind(hc_solver* S, const hc_device* dev) {
     if (g.kind == HC_CONE_POW) pow_off += (int)g.count;
     S->sdev.push_back(d);
   }
+  S->prof.reset(new Prof());
   S->bound = true;
-  init_point(S);
   HC_HIP(hipStreamSynchronize(st));
 }
 
@@ -1168,6 +1184,7 @@ int32_t hc_settings_default(hc_settings* o) {
   o->equil_iters = 10;
   o->force_dual_scaling = 0;
   o->verbose = 0;
+  o->profile = 0;
   return HC_OK;
 }
 

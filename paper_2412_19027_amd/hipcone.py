@@ -44,7 +44,7 @@ class hc_settings(C.Structure):
                 ("ir_abstol", C.c_double), ("ir_reltol", C.c_double), ("ir_max", C.c_int32),
                 ("beta", C.c_double), ("backtrack", C.c_double), ("step_fraction", C.c_double),
                 ("equilibrate", C.c_int32), ("equil_iters", C.c_int32), ("force_dual_scaling", C.c_int32),
-                ("verbose", C.c_int32)]
+                ("verbose", C.c_int32), ("profile", C.c_int32)]
 
 
 class hc_device(C.Structure):
@@ -58,7 +58,8 @@ class hc_info(C.Structure):
                 ("gap", C.c_double), ("mu", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
                 ("factor_ms", C.c_double), ("solve_kkt_ms", C.c_double), ("cone_ms", C.c_double),
                 ("ir_solves", C.c_int64), ("pivot_guard_hits", C.c_int64), ("dual_switches", C.c_int64),
-                ("n_ordered", C.c_int64), ("factor_flops", C.c_double)]
+                ("n_ordered", C.c_int64), ("factor_flops", C.c_double), ("factorizations", C.c_int64),
+                ("gemm_ms", C.c_double), ("gemm_flops", C.c_double), ("gemm_launches", C.c_int64)]
 
 
 _lib = None
