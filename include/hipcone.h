@@ -148,6 +148,9 @@ typedef struct {
   double gemm_ms;          /* with settings.profile: summed duration of the MFMA     */
   double gemm_flops;       /* update kernels and their algorithmic flops (2K per    */
   int64_t gemm_launches;   /* lower-triangle entry updated)                          */
+  int64_t fp64_fallbacks;  /* mixed mode: iterations refactored in FP64 because the
+                              FP32-factor refinement left a residual above
+                              1e-6 (1 + |rhs|_inf) or not finite                 */
 } hc_info;
 
 typedef struct hc_solver hc_solver;

@@ -19,10 +19,16 @@ struct Prof {
 template <typename T>
 void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
                     hipStream_t st, Prof* prof = nullptr);
+// Inverses X (and X') of the 256 x 256 diagonal blocks of the factor, from
+// the 64 x 64 block inverses; inv256_elems(n) entries each.
+template <typename T>
+void dense_block_inverses(const T* L, int64_t n, int64_t ld, const T* Linv, T* X, T* XT, hipStream_t st);
+int64_t inv256_elems(int64_t n);
 // X = L^-T L^-1 B for nrhs <= 4 right-hand sides (column-major, leading dim
 // n); B and Y are overwritten (Y receives the forward result).
 template <typename T>
-void dense_solve(const T* L, int64_t n, int64_t ld, const T* Linv, T* B, T* Y, T* X, int nrhs, hipStream_t st);
+void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT256, T* B, T* Y, T* X, int nrhs,
+                 hipStream_t st);
 // C[i, j] += alpha * sum_k A[i, k] B[j, k] (column-major operands); with
 // `lower`, tiles strictly above the diagonal of the global matrix (C[0,0] at
 // global (gr, gc)) are skipped.

@@ -58,59 +58,73 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ A, int64_t ld, int64_t c, int64_t n,
                                                    T* __restrict__ Linv, double tol, double fix,
                                                    unsigned long long* __restrict__ hits) {
-  __shared__ T L[BS][BS + 1];   // L[row][col]
-  __shared__ T X[BS][BS + 1];   // inverse
-  const int tid = threadIdx.x;
+  // Right-looking Cholesky of one 64 x 64 diagonal block.  Thread (i, p) =
+  // (lane, wave) keeps r[q] = A[i][16p + q] and y[q] = (L^-1)[i][16p + q]: the
+  // inverse is produced by applying the same row operations to the identity.
+  // Each finished column of L and row of L^-1 is broadcast through LDS.
+  __shared__ T col[BS];
+  __shared__ T yrow[BS];
+  __shared__ T piv;
+  const int lane = threadIdx.x & 63;
+  const int p = threadIdx.x >> 6;
   const int bs = (int)std::min<int64_t>(BS, n - c);
-  for (int e = tid; e < BS * BS; e += 256) {
-    int i = e % BS, j = e / BS;
-    T v = 0;
-    if (i < bs && j < bs && i >= j) v = A[(c + i) + (c + j) * ld];
-    if (i >= bs || j >= bs) v = (i == j) ? T(1) : T(0);
-    L[i][j] = v;
+  T r[16], y[16];
+  // loads from clamped (always valid) addresses so that all 16 are in flight
+  // at once; a ragged last block is padded with the identity
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = 16 * p + q;
+    const T g = A[(c + std::min(lane, bs - 1)) + (c + std::min(k, bs - 1)) * ld];
+    r[q] = (lane < bs && k < bs) ? (k <= lane ? g : T(0)) : (lane == k ? T(1) : T(0));
+    y[q] = (lane == k) ? T(1) : T(0);
   }
-  __syncthreads();
-  for (int j = 0; j < bs; ++j) {
-    if (tid == 0) {
-      double d = (double)L[j][j];
-      if (!(d > tol)) {
-        d = fix;
-        atomicAdd(hits, 1ull);
+  int nhits = 0;
+#pragma unroll
+  for (int j = 0; j < BS; ++j) {
+    const int pj = j >> 4, qj = j & 15;
+    if (p == pj && lane == j) piv = r[qj];
+    __syncthreads();
+    double d = (double)piv;
+    if (j < bs && !(d > tol)) {
+      d = fix;
+      ++nhits;
+    }
+    const T ljj = (T)sqrt(d);
+    const T inv = T(1) / ljj;
+    if (p == pj) {
+      r[qj] = (lane == j) ? ljj : r[qj] * inv;
+      col[lane] = r[qj];
+    }
+    if (lane == j) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        y[q] *= inv;
+        yrow[16 * p + q] = y[q];
       }
-      L[j][j] = (T)sqrt(d);
     }
     __syncthreads();
-    const T ljj = L[j][j];
-    for (int i = j + 1 + tid; i < bs; i += 256) L[i][j] = L[i][j] / ljj;
-    __syncthreads();
-    // rank-1 update of the trailing triangle
-    const int m = bs - j - 1;
-    for (int e = tid; e < m * m; e += 256) {
-      int i = j + 1 + e % m, k = j + 1 + e / m;
-      if (i >= k) L[i][k] -= L[i][j] * L[k][j];
+    const T lij = (lane > j) ? col[lane] : T(0);
+    if (p > pj) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) r[q] -= lij * col[16 * p + q];
+    } else if (p == pj) {
+#pragma unroll
+      for (int q = qj + 1; q < 16; ++q) r[q] -= lij * col[16 * p + q];
     }
-    __syncthreads();
-  }
-  // inverse of the lower-triangular factor, one column per thread
-  if (tid < BS) {
-    const int j = tid;
-    for (int i = 0; i < BS; ++i) X[i][j] = 0;
-    if (j < bs) {
-      X[j][j] = T(1) / L[j][j];
-      for (int i = j + 1; i < bs; ++i) {
-        T acc = 0;
-        for (int k = j; k < i; ++k) acc += L[i][k] * X[k][j];
-        X[i][j] = -acc / L[i][i];
-      }
-    } else {
-      X[j][j] = 1;
+    if (p < pj) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) y[q] -= lij * yrow[16 * p + q];
+    } else if (p == pj) {
+#pragma unroll
+      for (int q = 0; q <= qj; ++q) y[q] -= lij * yrow[16 * p + q];
     }
   }
-  __syncthreads();
-  for (int e = tid; e < BS * BS; e += 256) {
-    int i = e % BS, j = e / BS;
-    if (i < bs && j < bs && i >= j) A[(c + i) + (c + j) * ld] = L[i][j];
-    Linv[i + j * BS] = X[i][j];
+  if (threadIdx.x == 0 && nhits) atomicAdd(hits, (unsigned long long)nhits);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = 16 * p + q;
+    if (lane < bs && k < bs && k <= lane) A[(c + lane) + (c + k) * ld] = r[q];
+    Linv[lane + k * BS] = (k <= lane) ? y[q] : T(0);
   }
 }
 
@@ -124,10 +138,14 @@ __global__ __launch_bounds__(256) void k_trsm(T* __restrict__ A, int64_t ld, int
   __shared__ T Ls[BS][BS + 1];   // Linv (j, k)
   const int tid = threadIdx.x;
   const int64_t rb = r0 + (int64_t)blockIdx.x * BS;
-  for (int e = tid; e < BS * BS; e += 256) {
-    int i = e % BS, k = e / BS;
-    int64_t r = rb + i;
-    Xs[i][k] = (r < r1) ? A[r + (c + k) * ld] : T(0);
+  // rows past r1 repeat the last row (never stored), so every load is
+  // unconditional and all of them are in flight together
+#pragma unroll
+  for (int t = 0; t < BS * BS / 256; ++t) {
+    const int e = tid + 256 * t;
+    const int i = e % BS, k = e / BS;
+    const int64_t r = std::min<int64_t>(rb + i, r1 - 1);
+    Xs[i][k] = A[r + (c + k) * ld];
     Ls[i][k] = Linv[i + k * BS];
   }
   __syncthreads();
@@ -162,12 +180,14 @@ __global__ __launch_bounds__(256) void k_trsm(T* __restrict__ A, int64_t ld, int
 // position is given by the global indices (gr, gc) of C[0, 0].
 // ---------------------------------------------------------------------------
 constexpr int TM = 128, TN = 128, TK = 16;
+static_assert(TK * TM % 512 == 0, "staging layout");
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_nt(T* __restrict__ C, int64_t ldc, const T* __restrict__ A, int64_t lda,
                                                  const T* __restrict__ B, int64_t ldb, int64_t M, int64_t N, int64_t K,
                                                  T alpha, int lower, int64_t gr, int64_t gc, int tiles_n) {
   typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int PER = TK * TM / 256;   // staged elements per thread and operand
   __shared__ T As[TK][TM + 4];
   __shared__ T Bs[TK][TN + 4];
   const int tile_m = blockIdx.x / tiles_n, tile_n = blockIdx.x % tiles_n;
@@ -181,15 +201,31 @@ __global__ __launch_bounds__(256) void k_gemm_nt(T* __restrict__ C, int64_t ldc,
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-  for (int64_t k0 = 0; k0 < K; k0 += TK) {
-    for (int e = tid; e < TK * TM; e += 256) {
-      const int i = e % TM, k = e / TM;
-      const int64_t gk = k0 + k;
-      const int64_t gi = i_base + i, gj = j_base + i;
-      As[k][i] = (gi < M && gk < K) ? A[gi + gk * lda] : T(0);
-      Bs[k][i] = (gj < N && gk < K) ? B[gj + gk * ldb] : T(0);
+  // thread tid stages rows i = tid % 128 (+0) for k = tid / 128 + 2 e, e < PER
+  const int si = tid % TM, sk = tid / TM;
+  const int64_t gi = i_base + si, gj = j_base + si;
+  T ra[PER], rb[PER];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int64_t gk = k0 + sk + 2 * e;
+      ra[e] = (gi < M && gk < K) ? A[gi + gk * lda] : T(0);
+      rb[e] = (gj < N && gk < K) ? B[gj + gk * ldb] : T(0);
     }
-    __syncthreads();
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      As[sk + 2 * e][si] = ra[e];
+      Bs[sk + 2 * e][si] = rb[e];
+    }
+  };
+  fetch(0);
+  stage();
+  __syncthreads();
+  for (int64_t k0 = 0; k0 < K; k0 += TK) {
+    const bool more = (k0 + TK < K);
+    if (more) fetch(k0 + TK);   // global loads in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       T a_op[4], b_op[4];
@@ -204,23 +240,40 @@ __global__ __launch_bounds__(256) void k_gemm_nt(T* __restrict__ C, int64_t ldc,
         for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::op(a_op[a], b_op[b], acc[a][b]);
     }
     __syncthreads();
+    if (more) {
+      stage();
+      __syncthreads();
+    }
   }
-  // lane holds D[row(lane, r)][lane % 16] of each 16 x 16 tile
+  // lane holds D[row(lane, r)][lane % 16] of each 16 x 16 tile.  The C loads
+  // of half a wave tile are issued together from clamped (always valid)
+  // addresses so that their latencies overlap; only the stores are predicated.
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int h = 0; h < 4; h += 2) {
+    T cv[2][4][4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t j = j_base + wn + b * 16 + (lane & 15);
-      if (j >= N) continue;
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t i = i_base + wm + a * 16 + Mfma<T>::row(lane, r);
-        if (i < M) {
-          T* p = &C[i + j * ldc];
-          *p = *p + alpha * acc[a][b][r];
+      for (int b = 0; b < 4; ++b) {
+        const int64_t j = std::min<int64_t>(j_base + wn + b * 16 + (lane & 15), N - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = std::min<int64_t>(i_base + wm + (h + a) * 16 + Mfma<T>::row(lane, r), M - 1);
+          cv[a][b][r] = C[i + j * ldc];
         }
       }
-    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t j = j_base + wn + b * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = i_base + wm + (h + a) * 16 + Mfma<T>::row(lane, r);
+          if (i < M && j < N) C[i + j * ldc] = cv[a][b][r] + alpha * acc[h + a][b][r];
+        }
+      }
+  }
 }
 
 template <typename T>
@@ -305,142 +358,233 @@ void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix
 }
 
 // ---------------------------------------------------------------------------
-// triangular solves with L (lower, column-major) and the Linv blocks,
-// nrhs right-hand sides stored column-major with leading dimension n.
-// forward:  Y = L^-1 B     (B is overwritten with partial updates)
-// backward: X = L^-T Y     (Y is overwritten with partial updates)
+// Inverses of the 256 x 256 diagonal blocks of L (one workgroup per block),
+// from the 64 x 64 block inverses:  X_ii = Linv_i,
+// X_ij = -Linv_i sum_{k=j}^{i-1} L_ik X_kj  (i > j).  X and X' are stored
+// column-major with leading dimension 256 (block b at b * 256 * 256).
 // ---------------------------------------------------------------------------
-constexpr int SB = 256;   // rows per launch
+constexpr int SB = 256;   // rows per triangular-solve step
 constexpr int MAXRHS = 4;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_fwd(const T* __restrict__ L, int64_t ld, const T* __restrict__ Linv,
-                                                  int64_t c, int64_t n, T* __restrict__ B, T* __restrict__ Y,
-                                                  int nrhs) {
-  __shared__ T yb[SB][MAXRHS];
+__global__ __launch_bounds__(256) void k_inv256(const T* __restrict__ L, int64_t ld, const T* __restrict__ Linv,
+                                                int64_t n, T* __restrict__ Xall, T* __restrict__ XTall) {
+  __shared__ T Tt[BS][BS + 1];
   const int tid = threadIdx.x;
-  const int64_t cb = std::min<int64_t>(SB, n - c);
-  // every workgroup solves the diagonal 256-block redundantly
-  for (int e = tid; e < SB * nrhs; e += 256) {
-    int i = e % SB, r = e / SB;
-    yb[i][r] = (i < cb) ? B[(c + i) + r * n] : T(0);
+  const int64_t c = (int64_t)blockIdx.x * SB;
+  const int cb = (int)std::min<int64_t>(SB, n - c);
+  const int nsub = (cb + BS - 1) / BS;
+  T* X = Xall + (int64_t)blockIdx.x * SB * SB;
+  T* XT = XTall + (int64_t)blockIdx.x * SB * SB;
+  for (int e = tid; e < SB * SB; e += 256) {
+    const int i = e % SB, j = e / SB;
+    T v = 0;
+    if (i / BS == j / BS) {
+      if (i / BS < nsub) v = Linv[((c + (i / BS) * BS) / BS) * BS * BS + (i % BS) + (j % BS) * BS];
+      else v = (i == j) ? T(1) : T(0);
+    }
+    X[i + j * SB] = v;
   }
   __syncthreads();
-  for (int s = 0; s < SB / BS && s * BS < cb; ++s) {
-    const T* Li = Linv + ((c + s * BS) / BS) * BS * BS;
-    // y_s = Linv_s * b_s  (64 x 64 matvec, thread per (row, rhs))
-    T v = 0;
-    int i = tid % BS, r = tid / BS;
-    if (r < nrhs) {
-      for (int k = 0; k <= i; ++k) v += Li[i + k * BS] * yb[s * BS + k][r];
-    }
-    __syncthreads();
-    if (r < nrhs) yb[s * BS + i][r] = v;
-    __syncthreads();
-    // b_t -= L[t, s] y_s for the later sub-blocks of this 256 block
-    for (int e = tid; e < (SB - (s + 1) * BS) * nrhs; e += 256) {
-      int ii = (s + 1) * BS + e % (SB - (s + 1) * BS), rr = e / (SB - (s + 1) * BS);
-      if (ii < cb) {
-        T acc = 0;
-        for (int k = 0; k < BS; ++k) acc += L[(c + ii) + (c + s * BS + k) * ld] * yb[s * BS + k][rr];
-        yb[ii][rr] -= acc;
-      }
-    }
-    __syncthreads();
-  }
-  if (blockIdx.x == 0)
-    for (int e = tid; e < cb * nrhs; e += 256) {
-      int i = e % cb, r = e / cb;
-      Y[(c + i) + r * n] = yb[i][r];
-    }
-  // rows below: B[row] -= L[row, c:c+cb] * y
-  const int64_t row = c + cb + (int64_t)blockIdx.x * 256 + tid;
-  if (row < n) {
-    T acc[MAXRHS] = {};
-    for (int k = 0; k < cb; ++k) {
-      T l = L[row + (c + k) * ld];
+  const int i0 = 4 * (tid % 16), j0 = 4 * (tid / 16);
+  for (int jb = 0; jb < nsub; ++jb)
+    for (int ib = jb + 1; ib < nsub; ++ib) {
+      T acc[4][4] = {};
+      for (int kb = jb; kb < ib; ++kb)
+        for (int p = 0; p < BS; ++p) {
+          T la[4], xb[4];
 #pragma unroll
-      for (int r = 0; r < MAXRHS; ++r)
-        if (r < nrhs) acc[r] += l * yb[k][r];
+          for (int a = 0; a < 4; ++a) {
+            const int row = ib * BS + i0 + a;   // local row inside the 256 block
+            la[a] = (row < cb && kb * BS + p < cb) ? L[(c + row) + (c + kb * BS + p) * ld] : T(0);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) xb[q] = X[(kb * BS + p) + (jb * BS + j0 + q) * SB];
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[a][q] += la[a] * xb[q];
+        }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Tt[i0 + a][j0 + q] = acc[a][q];
+      __syncthreads();
+      const T* Li = X + (ib * BS) + (ib * BS) * SB;   // Linv_ib sits on X's diagonal
+      T out[4][4] = {};
+      for (int p = 0; p < BS; ++p) {
+        T la[4], tb[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) la[a] = Li[(i0 + a) + p * SB];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tb[q] = Tt[p][j0 + q];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) out[a][q] -= la[a] * tb[q];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) X[(ib * BS + i0 + a) + (jb * BS + j0 + q) * SB] = out[a][q];
+      __syncthreads();
     }
-    for (int r = 0; r < nrhs; ++r) B[row + r * n] -= acc[r];
+  for (int e = tid; e < SB * SB; e += 256) {
+    const int i = e % SB, j = e / SB;
+    XT[i + j * SB] = X[j + i * SB];
   }
 }
 
+int64_t inv256_elems(int64_t n) { return ceil_div(n, SB) * SB * SB; }
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_bwd(const T* __restrict__ L, int64_t ld, const T* __restrict__ Linv,
-                                                  int64_t c, int64_t n, T* __restrict__ Yv, T* __restrict__ X,
-                                                  int nrhs) {
+void dense_block_inverses(const T* L, int64_t n, int64_t ld, const T* Linv, T* X, T* XT, hipStream_t st) {
+  hipLaunchKernelGGL(k_inv256<T>, dim3((unsigned)ceil_div(n, SB)), dim3(256), 0, st, L, ld, Linv, n, X, XT);
+  HC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// triangular solves, nrhs <= 4 right-hand sides stored column-major with
+// leading dimension n:  forward Y = L^-1 B (B overwritten), backward
+// X = L^-T Y (Y overwritten).  Per 256-row block: one workgroup applies the
+// block inverse (a 256 x 256 triangular matvec), then a bandwidth-bound kernel
+// updates the rows below (forward) or the columns to the left (backward).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(1024) void k_trsv_diag(const T* __restrict__ Xinv, int64_t c, int64_t n, int upper,
+                                                    const T* __restrict__ Bin, T* __restrict__ Yout, int nrhs) {
+  // Yout[c + i] = sum_k Xinv[i + k * 256] Bin[c + k]  (lower: k <= i; upper: k >= i);
+  // four threads per row, each over 64 values of k, loads unrolled by 16;
+  // `upper` only documents which triangle Xinv holds
+  __shared__ T bb[SB][MAXRHS];
+  __shared__ T part[4][SB][MAXRHS];
+  const int tid = threadIdx.x;
+  const int cb = (int)std::min<int64_t>(SB, n - c);
+  for (int e = tid; e < SB * MAXRHS; e += 1024) {
+    const int i = e % SB, r = e / SB;
+    bb[i][r] = (i < cb && r < nrhs) ? Bin[(c + i) + r * n] : T(0);
+  }
+  __syncthreads();
+  // the stored block inverse is zero outside its triangle and bb is zero past
+  // cb, so the products need no masks and the loads no conditions
+  const int i = tid % SB, pp = tid / SB;
+  T acc[MAXRHS] = {};
+#pragma unroll 16
+  for (int q = 0; q < 64; ++q) {
+    const int k = pp * 64 + q;
+    const T x = Xinv[i + (int64_t)k * SB];
+#pragma unroll
+    for (int r = 0; r < MAXRHS; ++r) acc[r] += x * bb[k][r];
+  }
+#pragma unroll
+  for (int r = 0; r < MAXRHS; ++r) part[pp][i][r] = acc[r];
+  __syncthreads();
+  if (pp == 0 && i < cb)
+    for (int r = 0; r < nrhs; ++r) Yout[(c + i) + r * n] = part[0][i][r] + part[1][i][r] + part[2][i][r] + part[3][i][r];
+}
+
+// rows below the block: B[row] -= L[row, c:c+cb] y_c.  A workgroup takes 64
+// rows; wave w sums columns [64 w, 64 w + 64) with one lane per row (each
+// column read is 512 contiguous bytes), and the four partial sums meet in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_fwd_update(const T* __restrict__ L, int64_t ld, int64_t c, int64_t n,
+                                                         T* __restrict__ B, const T* __restrict__ Y, int nrhs) {
+  __shared__ T yb[SB][MAXRHS];
+  __shared__ T part[4][64][MAXRHS];
+  const int tid = threadIdx.x;
+  const int cb = (int)std::min<int64_t>(SB, n - c);
+  for (int e = tid; e < SB * MAXRHS; e += 256) {
+    const int i = e % SB, r = e / SB;
+    yb[i][r] = (i < cb && r < nrhs) ? Y[(c + i) + r * n] : T(0);
+  }
+  __syncthreads();
+  const int lane = tid & 63, w = tid >> 6;
+  const int64_t row = c + cb + (int64_t)blockIdx.x * 64 + lane;
+  const int64_t rowc = std::min<int64_t>(row, n - 1);
+  T acc[MAXRHS] = {};
+#pragma unroll 16
+  for (int q = 0; q < 64; ++q) {
+    const int k = w * 64 + q;
+    const T l = L[rowc + (c + std::min(k, cb - 1)) * ld];   // yb is zero past cb
+#pragma unroll
+    for (int r = 0; r < MAXRHS; ++r) acc[r] += l * yb[k][r];
+  }
+#pragma unroll
+  for (int r = 0; r < MAXRHS; ++r) part[w][lane][r] = acc[r];
+  __syncthreads();
+  if (w == 0 && row < n)
+    for (int r = 0; r < nrhs; ++r) B[row + r * n] -= part[0][lane][r] + part[1][lane][r] + part[2][lane][r] + part[3][lane][r];
+}
+
+// columns left of the block: Y[j] -= sum_i L[c + i, j] x[i]; each wave takes
+// four columns (16 loads in flight per lane), lanes run over i
+constexpr int BWD_COLS = 4;
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv_bwd_update(const T* __restrict__ L, int64_t ld, int64_t c, int64_t n,
+                                                         T* __restrict__ Yv, const T* __restrict__ X, int nrhs) {
   __shared__ T xb[SB][MAXRHS];
   const int tid = threadIdx.x;
-  const int64_t cb = std::min<int64_t>(SB, n - c);
-  const int nsub = (int)ceil_div(cb, BS);
-  for (int e = tid; e < SB * nrhs; e += 256) {
-    int i = e % SB, r = e / SB;
-    xb[i][r] = (i < cb) ? Yv[(c + i) + r * n] : T(0);
+  const int cb = (int)std::min<int64_t>(SB, n - c);
+  for (int e = tid; e < SB * MAXRHS; e += 256) {
+    const int i = e % SB, r = e / SB;
+    xb[i][r] = (i < cb && r < nrhs) ? X[(c + i) + r * n] : T(0);
   }
   __syncthreads();
-  for (int s = nsub - 1; s >= 0; --s) {
-    const T* Li = Linv + ((c + s * BS) / BS) * BS * BS;
-    // x_s = Linv_s' * y_s
-    T v = 0;
-    int i = tid % BS, r = tid / BS;
-    if (r < nrhs)
-      for (int k = i; k < BS; ++k) v += Li[k + i * BS] * xb[s * BS + k][r];
-    __syncthreads();
-    if (r < nrhs) xb[s * BS + i][r] = v;
-    __syncthreads();
-    // y_t -= L[s rows, t cols]' x_s for earlier sub-blocks t < s
-    for (int e = tid; e < s * BS * nrhs; e += 256) {
-      int jj = e % (s * BS), rr = e / (s * BS);
-      T acc = 0;
-      for (int k = 0; k < BS; ++k)
-        if (s * BS + k < cb) acc += L[(c + s * BS + k) + (c + jj) * ld] * xb[s * BS + k][rr];
-      xb[jj][rr] -= acc;
-    }
-    __syncthreads();
-  }
-  if (blockIdx.x == 0)
-    for (int e = tid; e < cb * nrhs; e += 256) {
-      int i = e % cb, r = e / cb;
-      X[(c + i) + r * n] = xb[i][r];
-    }
-  // columns j < c: Y[j] -= sum_i L[c + i, j] x[i]; one wave per column
   const int lane = tid & 63;
-  const int64_t j = (int64_t)blockIdx.x * 4 + (tid >> 6);
-  if (j < c) {
-    T acc[MAXRHS] = {};
-    for (int i = lane; i < cb; i += 64) {
-      T l = L[(c + i) + j * ld];
+  const int64_t j0 = ((int64_t)blockIdx.x * 4 + (tid >> 6)) * BWD_COLS;
+  T acc[BWD_COLS][MAXRHS] = {};
 #pragma unroll
-      for (int r = 0; r < MAXRHS; ++r)
-        if (r < nrhs) acc[r] += l * xb[i][r];
+  for (int cc = 0; cc < BWD_COLS; ++cc) {
+    const int64_t j = std::min<int64_t>(j0 + cc, c - 1);
+#pragma unroll
+    for (int q = 0; q < SB / 64; ++q) {
+      const int i = lane + 64 * q;
+      const T l = L[(c + std::min(i, cb - 1)) + j * ld];   // xb is zero past cb
+#pragma unroll
+      for (int r = 0; r < MAXRHS; ++r) acc[cc][r] += l * xb[i][r];
     }
+  }
+#pragma unroll
+  for (int cc = 0; cc < BWD_COLS; ++cc)
 #pragma unroll
     for (int r = 0; r < MAXRHS; ++r) {
-      T v = acc[r];
+      T v = acc[cc][r];
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      acc[r] = v;
+      acc[cc][r] = v;
     }
-    if (lane == 0)
-      for (int r = 0; r < nrhs; ++r) Yv[j + r * n] -= acc[r];
-  }
+  if (lane == 0)
+#pragma unroll
+    for (int cc = 0; cc < BWD_COLS; ++cc)
+      if (j0 + cc < c)
+#pragma unroll
+        for (int r = 0; r < MAXRHS; ++r)
+          if (r < nrhs) Yv[(j0 + cc) + r * n] -= acc[cc][r];
 }
 
 template <typename T>
-void dense_solve(const T* L, int64_t n, int64_t ld, const T* Linv, T* B, T* Y, T* X, int nrhs, hipStream_t st) {
-  // B -> Y (forward), Y -> X (backward); B and Y are overwritten
+void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT256, T* B, T* Y, T* X, int nrhs,
+                 hipStream_t st) {
   for (int64_t c = 0; c < n; c += SB) {
-    const int64_t below = n - std::min<int64_t>(n, c + SB);
-    unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(below, 256));
-    hipLaunchKernelGGL(k_trsv_fwd<T>, dim3(grid), dim3(256), 0, st, L, ld, Linv, c, n, B, Y, nrhs);
+    const T* Xi = X256 + (c / SB) * SB * SB;
+    hipLaunchKernelGGL(k_trsv_diag<T>, dim3(1), dim3(1024), 0, st, Xi, c, n, 0, (const T*)B, Y, nrhs);
     HC_LAUNCH_CHECK();
+    const int64_t below = n - std::min<int64_t>(n, c + SB);
+    if (below > 0) {
+      hipLaunchKernelGGL(k_trsv_fwd_update<T>, dim3((unsigned)ceil_div(below, 64)), dim3(256), 0, st, L, ld, c, n, B,
+                         (const T*)Y, nrhs);
+      HC_LAUNCH_CHECK();
+    }
   }
   const int64_t last = ((n - 1) / SB) * SB;
   for (int64_t c = last; c >= 0; c -= SB) {
-    unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(c, 4));
-    hipLaunchKernelGGL(k_trsv_bwd<T>, dim3(grid), dim3(256), 0, st, L, ld, Linv, c, n, Y, X, nrhs);
+    const T* XTi = XT256 + (c / SB) * SB * SB;
+    hipLaunchKernelGGL(k_trsv_diag<T>, dim3(1), dim3(1024), 0, st, XTi, c, n, 1, (const T*)Y, X, nrhs);
     HC_LAUNCH_CHECK();
+    if (c > 0) {
+      hipLaunchKernelGGL(k_trsv_bwd_update<T>, dim3((unsigned)ceil_div(c, 4 * BWD_COLS)), dim3(256), 0, st, L, ld, c, n, Y,
+                         (const T*)X, nrhs);
+      HC_LAUNCH_CHECK();
+    }
   }
 }
 
@@ -452,10 +596,13 @@ template void gemm_nt<double>(double*, int64_t, const double*, int64_t, const do
                               int64_t, double, bool, int64_t, int64_t, hipStream_t);
 template void gemm_nt<float>(float*, int64_t, const float*, int64_t, const float*, int64_t, int64_t, int64_t,
                              int64_t, float, bool, int64_t, int64_t, hipStream_t);
-template void dense_solve<double>(const double*, int64_t, int64_t, const double*, double*, double*, double*, int,
-                                  hipStream_t);
-template void dense_solve<float>(const float*, int64_t, int64_t, const float*, float*, float*, float*, int,
-                                 hipStream_t);
+template void dense_solve<double>(const double*, int64_t, int64_t, const double*, const double*, double*, double*,
+                                  double*, int, hipStream_t);
+template void dense_solve<float>(const float*, int64_t, int64_t, const float*, const float*, float*, float*, float*,
+                                 int, hipStream_t);
+template void dense_block_inverses<double>(const double*, int64_t, int64_t, const double*, double*, double*,
+                                           hipStream_t);
+template void dense_block_inverses<float>(const float*, int64_t, int64_t, const float*, float*, float*, hipStream_t);
 
 int64_t linv_elems(int64_t n) { return ceil_div(n, BS) * BS * BS; }
 

@@ -99,6 +99,8 @@ struct hc_solver {
   double* dS = nullptr;
   double* dLinv = nullptr;
   float *dS32 = nullptr, *dLinv32 = nullptr;
+  double *dX256 = nullptr, *dXT256 = nullptr;
+  float *dX256f = nullptr, *dXT256f = nullptr;
   unsigned long long* dhits = nullptr;
   int* dpd = nullptr;
   double* dscal = nullptr;          // device scalars (FP32 rhs scale)
@@ -120,6 +122,7 @@ struct hc_solver {
   double delta = 0;
   double xPx_cache = 0;             // x'Px of the current iterate (from residuals)
   std::unique_ptr<Prof> prof;
+  bool use64 = false;               // mixed mode: this iteration fell back to the FP64 factor
   std::string last_error;
 };
 
@@ -604,12 +607,15 @@ void factor(hc_solver* S) {
     gemm_nt<double>(S->dS, S->ld, S->dBd, S->n, S->dBd, S->n, S->n, S->n, nd, 1.0, true, 0, 0, st);
   }
   const double tol = 0.0;
+  S->use64 = false;
   Prof* pf = S->st.profile ? S->prof.get() : nullptr;
   if (S->mixed) {
     lower_to_f32(S->n, S->ld, S->dS, S->dS32, st);
     dense_cholesky<float>(S->dS32, S->n, S->ld, S->dLinv32, tol, S->delta, S->dhits, st, pf);
+    dense_block_inverses<float>(S->dS32, S->n, S->ld, S->dLinv32, S->dX256f, S->dXT256f, st);
   } else {
     dense_cholesky<double>(S->dS, S->n, S->ld, S->dLinv, tol, S->delta, S->dhits, st, pf);
+    dense_block_inverses<double>(S->dS, S->n, S->ld, S->dLinv, S->dX256, S->dXT256, st);
   }
   S->info.factorizations++;
   if (pf) {
@@ -621,11 +627,20 @@ void factor(hc_solver* S) {
   }
 }
 
+// mixed mode: factor the (still FP64) Schur complement in FP64 for the rest of
+// this iteration
+void fallback_fp64(hc_solver* S) {
+  dense_cholesky<double>(S->dS, S->n, S->ld, S->dLinv, 0.0, S->delta, S->dhits, S->stream, nullptr);
+  dense_block_inverses<double>(S->dS, S->n, S->ld, S->dLinv, S->dX256, S->dXT256, S->stream);
+  S->use64 = true;
+  S->info.fp64_fallbacks++;
+}
+
 // x = S^-1 u (one right-hand side) in the factor precision
 void schur_solve(hc_solver* S, const double* u, double* x) {
   hipStream_t st = S->stream;
   const int64_t n = S->n;
-  if (S->mixed) {
+  if (S->mixed && !S->use64) {
     Red r(S, n);
     RedOps ops{};
     ops.nops = 1;
@@ -633,11 +648,11 @@ void schur_solve(hc_solver* S, const double* u, double* x) {
     const int nb = reduce_launch(n, ops, S->dpart, st);
     combine_max(nb, S->dpart, S->dscal, st);
     to_f32(n, u, S->dscal, S->sb32, st);
-    dense_solve<float>(S->dS32, n, S->ld, S->dLinv32, S->sb32, S->sy32, S->sx32, 1, st);
+    dense_solve<float>(S->dS32, n, S->ld, S->dX256f, S->dXT256f, S->sb32, S->sy32, S->sx32, 1, st);
     from_f32(n, S->sx32, S->dscal, x, st);
   } else {
     vcopy(n, u, S->sb, st);
-    dense_solve<double>(S->dS, n, S->ld, S->dLinv, S->sb, S->sy, x, 1, st);
+    dense_solve<double>(S->dS, n, S->ld, S->dX256, S->dXT256, S->sb, S->sy, x, 1, st);
   }
 }
 
@@ -654,7 +669,20 @@ void solve_reg(hc_solver* S, const double* r1, const double* r2, double* x, doub
 }
 
 // iterative refinement against the unregularised K; result in (xo, zo)
+int64_t kkt_solve_once(hc_solver* S, const double* r1, const double* r2, double* xo, double* zo, double* best_out,
+                       double* nb_out);
 int64_t kkt_solve(hc_solver* S, const double* r1, const double* r2, double* xo, double* zo) {
+  double best = 0, nb = 0;
+  int64_t k = kkt_solve_once(S, r1, r2, xo, zo, &best, &nb);
+  if (S->mixed && !S->use64 && !(best <= 1e-6 * (1.0 + nb))) {
+    fallback_fp64(S);
+    k += kkt_solve_once(S, r1, r2, xo, zo, &best, &nb);
+  }
+  return k;
+}
+
+int64_t kkt_solve_once(hc_solver* S, const double* r1, const double* r2, double* xo, double* zo, double* best_out,
+                       double* nb_out) {
   hipStream_t st = S->stream;
   const int64_t n = S->n, m = S->m;
   double nb;
@@ -723,6 +751,8 @@ int64_t kkt_solve(hc_solver* S, const double* r1, const double* r2, double* xo, 
   S->irxn = xn;
   S->irzn = zn;
   S->info.ir_solves += solves;
+  *best_out = have_best ? best : NAN;
+  *nb_out = nb;
   return solves;
 }
 
@@ -1076,9 +1106,13 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->dhdiag = buf.take<double>(m);
   S->dS = buf.take<double>((size_t)S->ld * n);
   S->dLinv = buf.take<double>(linv_elems(n));
+  S->dX256 = buf.take<double>(inv256_elems(n));
+  S->dXT256 = buf.take<double>(inv256_elems(n));
   if (S->mixed) {
     S->dS32 = buf.take<float>((size_t)S->ld * n);
     S->dLinv32 = buf.take<float>(linv_elems(n));
+    S->dX256f = buf.take<float>(inv256_elems(n));
+    S->dXT256f = buf.take<float>(inv256_elems(n));
     S->sb32 = buf.take<float>(n);
     S->sy32 = buf.take<float>(n);
     S->sx32 = buf.take<float>(n);

@@ -223,18 +223,24 @@ int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, doubl
         float* x32 = (float*)al((size_t)n * nrhs * 4);
         lower_to_f32(n, ld, A, A32, st);
         dense_cholesky<float>(A32, n, ld, L32, 0.0, 1e-8, hits, st);
+        float* X32 = (float*)al(inv256_elems(n) * 4);
+        float* XT32 = (float*)al(inv256_elems(n) * 4);
+        dense_block_inverses<float>(A32, n, ld, L32, X32, XT32, st);
         double* one = (double*)al(8);
         const double h1 = 1.0;
         HC_HIP(hipMemcpyAsync(one, &h1, 8, hipMemcpyHostToDevice, st));
         to_f32((int64_t)n * nrhs, B, one, b32, st);
-        dense_solve<float>(A32, n, ld, L32, b32, y32, x32, nrhs, st);
+        dense_solve<float>(A32, n, ld, X32, XT32, b32, y32, x32, nrhs, st);
         from_f32((int64_t)n * nrhs, x32, one, B, st);
       } else {
         double* Li = (double*)al(linv_elems(n) * 8);
         double* y = (double*)al((size_t)n * nrhs * 8);
         double* x = (double*)al((size_t)n * nrhs * 8);
         dense_cholesky<double>(A, n, ld, Li, 0.0, 1e-8, hits, st);
-        dense_solve<double>(A, n, ld, Li, B, y, x, nrhs, st);
+        double* X64 = (double*)al(inv256_elems(n) * 8);
+        double* XT64 = (double*)al(inv256_elems(n) * 8);
+        dense_block_inverses<double>(A, n, ld, Li, X64, XT64, st);
+        dense_solve<double>(A, n, ld, X64, XT64, B, y, x, nrhs, st);
         HC_HIP(hipMemcpyAsync(B, x, (size_t)n * nrhs * 8, hipMemcpyDeviceToDevice, st));
       }
       unsigned long long h = 0;

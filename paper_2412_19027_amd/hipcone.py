@@ -59,7 +59,8 @@ class hc_info(C.Structure):
                 ("factor_ms", C.c_double), ("solve_kkt_ms", C.c_double), ("cone_ms", C.c_double),
                 ("ir_solves", C.c_int64), ("pivot_guard_hits", C.c_int64), ("dual_switches", C.c_int64),
                 ("n_ordered", C.c_int64), ("factor_flops", C.c_double), ("factorizations", C.c_int64),
-                ("gemm_ms", C.c_double), ("gemm_flops", C.c_double), ("gemm_launches", C.c_int64)]
+                ("gemm_ms", C.c_double), ("gemm_flops", C.c_double), ("gemm_launches", C.c_int64),
+                ("fp64_fallbacks", C.c_int64)]
 
 
 _lib = None
