@@ -13,10 +13,14 @@ N = 1 exists: there is one GPU).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_nt_f64_sparse_socp_traffic.json")
 
 METRIC = "time per IPM iteration & solve-to-1e-8 gap; batched solves/s + p50/p99 latency"
 FP64_PEAK_TFLOPS = 78.6
@@ -26,6 +30,34 @@ FP32_PEAK_TFLOPS = 157.3
 def workload_desc(p):
     return (f"sparse_socp: n={p.n} (x 20,000 + 20 factor vars), m={p.m} (zero 10,020 incl. 20 dense lift rows, "
             f"nonneg 30,000, 40,000 SOC-3), A 6 nnz/row N(0,1), P = diag(U(0.01,1)) + rank-20 factor, seed 0")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the reference copy kernel), or
+    None when there is none or the kernel source changed since it was taken."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if rec.get("kernel") != kernel or hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def calibrate_copy(nbytes=1 << 30, reps=3):
+    """Runs the reference copy kernel (known traffic: nbytes read, nbytes
+    written per launch) so that a counter run can scale byte counters."""
+    import torch
+    from paper_2412_19027_amd import hipcone as HC
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        HC.test_copy(src, dst)
+    torch.cuda.synchronize()
+    assert bool((dst == 1).all())
+    print(f"reference copy: {reps} launches of {nbytes} bytes", file=sys.stderr)
 
 
 def run_gpu(prob, precision, steps, warmup):
@@ -50,6 +82,7 @@ def run_gpu(prob, precision, steps, warmup):
     solver.close()
     peak = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+    kernel = f"k_gemm_nt<{'double' if precision == 'fp64' else 'float'}>"
     return dict(
         wall=wall, iters=iters, infos=infos, status=last["status_name"], objective=last["obj_primal"],
         res_primal=last["res_primal"], res_dual=last["res_dual"], gap=last["gap"],
@@ -58,9 +91,10 @@ def run_gpu(prob, precision, steps, warmup):
         kkt_ms_per_iteration=sum(i["solve_kkt_ms"] for i in infos) / iters,
         cone_ms_per_iteration=sum(i["cone_ms"] for i in infos) / iters,
         ir_solves_per_iteration=sum(i["ir_solves"] for i in infos) / iters,
-        roofline=dict(bound="mfma", kernel=f"k_gemm_nt<{'double' if precision == 'fp64' else 'float'}>",
+        roofline=dict(bound="mfma", kernel=kernel,
                       achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
-                      traffic=None, launches=launches, avg_launch_us=1e3 * gemm_ms / max(1, launches),
+                      traffic=measured_traffic(kernel), traffic_unit="HBM bytes per launch",
+                      launches=launches, avg_launch_us=1e3 * gemm_ms / max(1, launches),
                       algorithmic_flops_per_launch=gemm_flops / max(1, launches)),
     )
 
@@ -89,11 +123,13 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run the reference copy kernel (for byte-counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, ROOT)
     from paper_2412_19027_amd import workloads as W
     sc = args.scale
     prob = W.sparse_socp(0, nx=int(20000 * sc), n_zero=int(10000 * sc), n_nonneg=int(30000 * sc),
@@ -110,6 +146,8 @@ def main():
         other["roofline"] = r["roofline"]
         other["objective_rel_diff_vs_main"] = abs(r["objective"] - main_run["objective"]) / max(
             1.0, abs(main_run["objective"]))
+    if args.calibrate_copy:
+        calibrate_copy()
     cpu = None if args.no_cpu_baseline else cpu_baseline(prob)
     out = {
         "metric": METRIC,

@@ -105,6 +105,10 @@ typedef struct {
   int32_t verbose;        /* 0                                                      */
   int32_t profile;        /* 1: time the factorisation's MFMA update kernels with HIP
                              events (hc_info.gemm_*); 0 = off                      */
+  int32_t leaf_blocks;    /* 1: columns of the Schur complement that fall into small
+                             connected components once the high-degree columns are
+                             set aside are factored as leaf blocks ahead of the
+                             dense tail (two-level LDL'); 0: one dense block      */
 } hc_settings;
 
 /* ---- device hand-off ------------------------------------------------------ */
@@ -142,7 +146,7 @@ typedef struct {
   int64_t ir_solves;       /* triangular-solve passes including refinement         */
   int64_t pivot_guard_hits;
   int64_t dual_switches;   /* iterations redone with the dual exp/pow scaling      */
-  int64_t n_ordered;       /* size of the factored Schur complement                */
+  int64_t n_ordered;       /* size of the dense tail of the Schur complement       */
   double factor_flops;     /* per factorisation                                    */
   int64_t factorizations;
   double gemm_ms;          /* with settings.profile: summed duration of the MFMA     */
@@ -151,6 +155,8 @@ typedef struct {
   int64_t fp64_fallbacks;  /* mixed mode: iterations refactored in FP64 because the
                               FP32-factor refinement left a residual above
                               1e-6 (1 + |rhs|_inf) or not finite                 */
+  int64_t n_leaves;        /* leaf blocks factored ahead of the tail               */
+  int64_t leaf_columns;    /* columns inside leaf blocks (n = leaf_columns + n_ordered) */
 } hc_info;
 
 typedef struct hc_solver hc_solver;
@@ -232,6 +238,13 @@ int32_t hc_test_cone_step(int32_t type, int64_t count, int32_t dim, const double
  * NULL. */
 int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, double* A, int32_t nrhs,
                                  double* B, int64_t* guard_hits, void* stream);
+
+/* Plain device-to-device copy of `bytes` bytes (src, dst: device, 16-byte
+ * aligned, bytes a multiple of 16; HC_ERR_INVALID_ARG otherwise), run to
+ * completion on `stream`.  It is the reference kernel of known traffic
+ * (bytes read, bytes written) against which hardware byte counters of the
+ * other kernels are scaled. */
+int32_t hc_test_copy(const void* src, void* dst, int64_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

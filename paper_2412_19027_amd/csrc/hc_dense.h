@@ -13,12 +13,25 @@ struct Prof {
   double collect_ms();          // synchronises, sums elapsed times, resets the pool
   ~Prof();
 };
+// A second stream (default priority) and a pool of events for the
+// look-ahead factorisation: the trailing update of a panel runs on `side`
+// while the next panel is factored on the caller's stream.
+struct Aux {
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  void init();          // creates the side stream (once)
+  hipEvent_t next();    // event from the pool (timing disabled)
+  ~Aux();
+};
 // In-place lower Cholesky of the n x n column-major S (leading dim ld).
 // Linv receives the inverses of the 64 x 64 diagonal factor blocks
 // (linv_elems(n) entries).  Pivots <= tol are replaced by fix and counted.
+// With `aux` the trailing updates overlap the next panel's factorisation;
+// all work is complete with respect to `st` on return.
 template <typename T>
 void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
-                    hipStream_t st, Prof* prof = nullptr);
+                    hipStream_t st, Prof* prof = nullptr, Aux* aux = nullptr);
 // Inverses X (and X') of the 256 x 256 diagonal blocks of the factor, from
 // the 64 x 64 block inverses; inv256_elems(n) entries each.
 template <typename T>

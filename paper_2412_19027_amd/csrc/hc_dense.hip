@@ -332,29 +332,87 @@ static void gemm_nt_sub(T* S, int64_t ld, int64_t rc, int64_t cc, int64_t ra, in
   }
 }
 
+void Aux::init() {
+  if (!side) HC_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+}
+
+hipEvent_t Aux::next() {
+  if (used == ev.size()) {
+    hipEvent_t e;
+    HC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ev.push_back(e);
+  }
+  return ev[used++];
+}
+
+Aux::~Aux() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  if (side) (void)hipStreamDestroy(side);
+}
+
+// factor the panel [K0, Kend): per 64-block the diagonal factor, the TRSM of
+// the rows below and the eager update of the rest of the panel
+template <typename T>
+static void factor_panel(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
+                         int64_t K0, int64_t Kend, hipStream_t st, Prof* prof) {
+  for (int64_t c = K0; c < Kend; c += BS) {
+    const int64_t cb = std::min<int64_t>(BS, n - c);
+    hipLaunchKernelGGL(k_chol_diag<T>, dim3(1), dim3(256), 0, st, S, ld, c, n, Linv + (c / BS) * BS * BS, tol,
+                       fix, hits);
+    HC_LAUNCH_CHECK();
+    const int64_t r0 = c + cb;
+    if (r0 < n) {
+      hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)ceil_div(n - r0, BS)), dim3(256), 0, st, S, ld, c, r0, n,
+                         (const T*)(Linv + (c / BS) * BS * BS));
+      HC_LAUNCH_CHECK();
+    }
+    if (r0 < Kend) gemm_nt_sub<T>(S, ld, r0, r0, r0, r0, c, n - r0, Kend - r0, cb, true, st, prof);
+  }
+}
+
 template <typename T>
 void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
-                    hipStream_t st, Prof* prof) {
+                    hipStream_t st, Prof* prof, Aux* aux) {
+  if (!aux) {
+    for (int64_t K0 = 0; K0 < n; K0 += NB) {
+      const int64_t Kend = std::min<int64_t>(n, K0 + NB);
+      factor_panel<T>(S, n, ld, Linv, tol, fix, hits, K0, Kend, st, prof);
+      // delayed update of the trailing matrix with the whole panel
+      if (Kend < n) gemm_nt_sub<T>(S, ld, Kend, Kend, Kend, Kend, K0, n - Kend, n - Kend, Kend - K0, true, st, prof);
+    }
+    return;
+  }
+  // Look-ahead.  After panel k is factored: U1 updates panel k+1 on `st`, U2
+  // updates every later column on `side`.  Panel k+1 is then factored on `st`
+  // while U2 runs.  U1 writes the columns that the previous U2 wrote, so it
+  // waits for that U2; U2 waits for panel k to be factored.
+  aux->init();
+  aux->used = 0;
+  hipEvent_t start = aux->next();
+  HC_HIP(hipEventRecord(start, st));
+  HC_HIP(hipStreamWaitEvent(aux->side, start, 0));
+  hipEvent_t u2_done = nullptr;
   for (int64_t K0 = 0; K0 < n; K0 += NB) {
     const int64_t Kend = std::min<int64_t>(n, K0 + NB);
-    for (int64_t c = K0; c < Kend; c += BS) {
-      const int64_t cb = std::min<int64_t>(BS, n - c);
-      hipLaunchKernelGGL(k_chol_diag<T>, dim3(1), dim3(256), 0, st, S, ld, c, n, Linv + (c / BS) * BS * BS, tol,
-                         fix, hits);
-      HC_LAUNCH_CHECK();
-      const int64_t r0 = c + cb;
-      if (r0 < n) {
-        hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)ceil_div(n - r0, BS)), dim3(256), 0, st, S, ld, c, r0, n,
-                           (const T*)(Linv + (c / BS) * BS * BS));
-        HC_LAUNCH_CHECK();
-      }
-      // eager update of the rest of this panel: columns [r0, Kend), rows [r0, n)
-      if (r0 < Kend)
-        gemm_nt_sub<T>(S, ld, r0, r0, r0, r0, c, n - r0, Kend - r0, cb, true, st, prof);
+    factor_panel<T>(S, n, ld, Linv, tol, fix, hits, K0, Kend, st, prof);
+    if (Kend >= n) break;
+    const int64_t K1 = std::min<int64_t>(n, Kend + NB);
+    if (K1 < n) {
+      hipEvent_t factored = aux->next();
+      HC_HIP(hipEventRecord(factored, st));
+      HC_HIP(hipStreamWaitEvent(aux->side, factored, 0));
+      // U2 on the side stream: rows and columns [K1, n)
+      gemm_nt_sub<T>(S, ld, K1, K1, K1, K1, K0, n - K1, n - K1, Kend - K0, true, aux->side, prof);
     }
-    // delayed update of the trailing matrix with the whole panel
-    if (Kend < n) gemm_nt_sub<T>(S, ld, Kend, Kend, Kend, Kend, K0, n - Kend, n - Kend, Kend - K0, true, st, prof);
+    if (u2_done) HC_HIP(hipStreamWaitEvent(st, u2_done, 0));
+    // U1 on the caller's stream: rows [Kend, n), columns [Kend, K1)
+    gemm_nt_sub<T>(S, ld, Kend, Kend, Kend, Kend, K0, n - Kend, K1 - Kend, Kend - K0, true, st, prof);
+    if (K1 < n) {
+      u2_done = aux->next();
+      HC_HIP(hipEventRecord(u2_done, aux->side));
+    }
   }
+  if (u2_done) HC_HIP(hipStreamWaitEvent(st, u2_done, 0));
 }
 
 // ---------------------------------------------------------------------------
@@ -450,50 +508,59 @@ void dense_block_inverses(const T* L, int64_t n, int64_t ld, const T* Linv, T* X
 // block inverse (a 256 x 256 triangular matvec), then a bandwidth-bound kernel
 // updates the rows below (forward) or the columns to the left (backward).
 // ---------------------------------------------------------------------------
+// Yout[c + i] = sum_k Xinv[i + k * 256] Bin[c + k] for the 256 x 256 block
+// inverse Xinv (lower for the forward pass, upper for the backward one).
+// 16 workgroups of 16 rows each; thread (row, g) sums k in [16 g, 16 g + 16)
+// and the 16 partial sums meet in LDS.  The stored inverse is zero outside
+// its triangle and bb is zero past cb, so loads and products need no masks.
+constexpr int DIAG_ROWS = 16;
 template <typename T>
-__global__ __launch_bounds__(1024) void k_trsv_diag(const T* __restrict__ Xinv, int64_t c, int64_t n, int upper,
-                                                    const T* __restrict__ Bin, T* __restrict__ Yout, int nrhs) {
-  // Yout[c + i] = sum_k Xinv[i + k * 256] Bin[c + k]  (lower: k <= i; upper: k >= i);
-  // four threads per row, each over 64 values of k, loads unrolled by 16;
-  // `upper` only documents which triangle Xinv holds
+__global__ __launch_bounds__(256) void k_trsv_diag(const T* __restrict__ Xinv, int64_t c, int64_t n,
+                                                   const T* __restrict__ Bin, T* __restrict__ Yout, int nrhs) {
   __shared__ T bb[SB][MAXRHS];
-  __shared__ T part[4][SB][MAXRHS];
+  __shared__ T part[16][DIAG_ROWS][MAXRHS];
   const int tid = threadIdx.x;
   const int cb = (int)std::min<int64_t>(SB, n - c);
-  for (int e = tid; e < SB * MAXRHS; e += 1024) {
+  for (int e = tid; e < SB * MAXRHS; e += 256) {
     const int i = e % SB, r = e / SB;
     bb[i][r] = (i < cb && r < nrhs) ? Bin[(c + i) + r * n] : T(0);
   }
   __syncthreads();
-  // the stored block inverse is zero outside its triangle and bb is zero past
-  // cb, so the products need no masks and the loads no conditions
-  const int i = tid % SB, pp = tid / SB;
+  const int il = tid % DIAG_ROWS, g = tid / DIAG_ROWS;
+  const int i = blockIdx.x * DIAG_ROWS + il;
   T acc[MAXRHS] = {};
-#pragma unroll 16
-  for (int q = 0; q < 64; ++q) {
-    const int k = pp * 64 + q;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = g * 16 + q;
     const T x = Xinv[i + (int64_t)k * SB];
 #pragma unroll
     for (int r = 0; r < MAXRHS; ++r) acc[r] += x * bb[k][r];
   }
 #pragma unroll
-  for (int r = 0; r < MAXRHS; ++r) part[pp][i][r] = acc[r];
+  for (int r = 0; r < MAXRHS; ++r) part[g][il][r] = acc[r];
   __syncthreads();
-  if (pp == 0 && i < cb)
-    for (int r = 0; r < nrhs; ++r) Yout[(c + i) + r * n] = part[0][i][r] + part[1][i][r] + part[2][i][r] + part[3][i][r];
+  if (tid < DIAG_ROWS * MAXRHS) {
+    const int row = tid % DIAG_ROWS, r = tid / DIAG_ROWS;
+    T v = 0;
+#pragma unroll
+    for (int gg = 0; gg < 16; ++gg) v += part[gg][row][r];
+    const int ig = blockIdx.x * DIAG_ROWS + row;
+    if (ig < cb && r < nrhs) Yout[(c + ig) + r * n] = v;
+  }
 }
 
 // rows below the block: B[row] -= L[row, c:c+cb] y_c.  A workgroup takes 64
-// rows; wave w sums columns [64 w, 64 w + 64) with one lane per row (each
-// column read is 512 contiguous bytes), and the four partial sums meet in LDS.
+// rows; wave w sums columns [16 w, 16 w + 16) with one lane per row (each
+// column read is 512 contiguous bytes, 16 loads in flight per lane), and the
+// 16 partial sums meet in LDS.
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsv_fwd_update(const T* __restrict__ L, int64_t ld, int64_t c, int64_t n,
-                                                         T* __restrict__ B, const T* __restrict__ Y, int nrhs) {
+__global__ __launch_bounds__(1024) void k_trsv_fwd_update(const T* __restrict__ L, int64_t ld, int64_t c, int64_t n,
+                                                          T* __restrict__ B, const T* __restrict__ Y, int nrhs) {
   __shared__ T yb[SB][MAXRHS];
-  __shared__ T part[4][64][MAXRHS];
+  __shared__ T part[16][64][MAXRHS];
   const int tid = threadIdx.x;
   const int cb = (int)std::min<int64_t>(SB, n - c);
-  for (int e = tid; e < SB * MAXRHS; e += 256) {
+  for (int e = tid; e < SB * MAXRHS; e += 1024) {
     const int i = e % SB, r = e / SB;
     yb[i][r] = (i < cb && r < nrhs) ? Y[(c + i) + r * n] : T(0);
   }
@@ -502,9 +569,9 @@ __global__ __launch_bounds__(256) void k_trsv_fwd_update(const T* __restrict__ L
   const int64_t row = c + cb + (int64_t)blockIdx.x * 64 + lane;
   const int64_t rowc = std::min<int64_t>(row, n - 1);
   T acc[MAXRHS] = {};
-#pragma unroll 16
-  for (int q = 0; q < 64; ++q) {
-    const int k = w * 64 + q;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = w * 16 + q;
     const T l = L[rowc + (c + std::min(k, cb - 1)) * ld];   // yb is zero past cb
 #pragma unroll
     for (int r = 0; r < MAXRHS; ++r) acc[r] += l * yb[k][r];
@@ -512,8 +579,14 @@ __global__ __launch_bounds__(256) void k_trsv_fwd_update(const T* __restrict__ L
 #pragma unroll
   for (int r = 0; r < MAXRHS; ++r) part[w][lane][r] = acc[r];
   __syncthreads();
-  if (w == 0 && row < n)
-    for (int r = 0; r < nrhs; ++r) B[row + r * n] -= part[0][lane][r] + part[1][lane][r] + part[2][lane][r] + part[3][lane][r];
+  if (tid < 64 * MAXRHS) {
+    const int ln = tid % 64, r = tid / 64;
+    const int64_t rw = c + cb + (int64_t)blockIdx.x * 64 + ln;
+    T v = 0;
+#pragma unroll
+    for (int ww = 0; ww < 16; ++ww) v += part[ww][ln][r];
+    if (rw < n && r < nrhs) B[rw + r * n] -= v;
+  }
 }
 
 // columns left of the block: Y[j] -= sum_i L[c + i, j] x[i]; each wave takes
@@ -566,11 +639,11 @@ void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT25
                  hipStream_t st) {
   for (int64_t c = 0; c < n; c += SB) {
     const T* Xi = X256 + (c / SB) * SB * SB;
-    hipLaunchKernelGGL(k_trsv_diag<T>, dim3(1), dim3(1024), 0, st, Xi, c, n, 0, (const T*)B, Y, nrhs);
+    hipLaunchKernelGGL(k_trsv_diag<T>, dim3(SB / DIAG_ROWS), dim3(256), 0, st, Xi, c, n, (const T*)B, Y, nrhs);
     HC_LAUNCH_CHECK();
     const int64_t below = n - std::min<int64_t>(n, c + SB);
     if (below > 0) {
-      hipLaunchKernelGGL(k_trsv_fwd_update<T>, dim3((unsigned)ceil_div(below, 64)), dim3(256), 0, st, L, ld, c, n, B,
+      hipLaunchKernelGGL(k_trsv_fwd_update<T>, dim3((unsigned)ceil_div(below, 64)), dim3(1024), 0, st, L, ld, c, n, B,
                          (const T*)Y, nrhs);
       HC_LAUNCH_CHECK();
     }
@@ -578,7 +651,7 @@ void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT25
   const int64_t last = ((n - 1) / SB) * SB;
   for (int64_t c = last; c >= 0; c -= SB) {
     const T* XTi = XT256 + (c / SB) * SB * SB;
-    hipLaunchKernelGGL(k_trsv_diag<T>, dim3(1), dim3(1024), 0, st, XTi, c, n, 1, (const T*)Y, X, nrhs);
+    hipLaunchKernelGGL(k_trsv_diag<T>, dim3(SB / DIAG_ROWS), dim3(256), 0, st, XTi, c, n, (const T*)Y, X, nrhs);
     HC_LAUNCH_CHECK();
     if (c > 0) {
       hipLaunchKernelGGL(k_trsv_bwd_update<T>, dim3((unsigned)ceil_div(c, 4 * BWD_COLS)), dim3(256), 0, st, L, ld, c, n, Y,
@@ -589,9 +662,9 @@ void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT25
 }
 
 template void dense_cholesky<double>(double*, int64_t, int64_t, double*, double, double, unsigned long long*,
-                                     hipStream_t, Prof*);
+                                     hipStream_t, Prof*, Aux*);
 template void dense_cholesky<float>(float*, int64_t, int64_t, float*, double, double, unsigned long long*,
-                                    hipStream_t, Prof*);
+                                    hipStream_t, Prof*, Aux*);
 template void gemm_nt<double>(double*, int64_t, const double*, int64_t, const double*, int64_t, int64_t, int64_t,
                               int64_t, double, bool, int64_t, int64_t, hipStream_t);
 template void gemm_nt<float>(float*, int64_t, const float*, int64_t, const float*, int64_t, int64_t, int64_t,

@@ -1,0 +1,256 @@
+// Leaf blocks of the two-level Schur factorisation (gfx950): assembly through
+// the column map, batched per-leaf Cholesky and coupling, leaf solves.
+#include "hc_leaf.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace hc {
+
+// address of S[j, k] (either order) inside the two-level storage
+__device__ inline double* dest(const ColMap& cm, int32_t j, int32_t k) {
+  const int32_t bj = cm.leaf[j], bk = cm.leaf[k];
+  const int32_t lj = cm.loc[j], lk = cm.loc[k];
+  if (bj < 0 && bk < 0) {
+    const int32_t hi = lj > lk ? lj : lk, lo = lj > lk ? lk : lj;
+    return cm.ST + hi + (int64_t)lo * cm.ldt;
+  }
+  if (bj >= 0 && bk >= 0) {
+    if (bj != bk) return cm.sink;   // cannot happen: leaves are connected components
+    const int32_t l = cm.lsize[bj];
+    const int32_t hi = lj > lk ? lj : lk, lo = lj > lk ? lk : lj;
+    return cm.lval + cm.lval_off[bj] + hi + (int64_t)lo * l;
+  }
+  const int32_t b = bj >= 0 ? bj : bk;
+  const int32_t l = bj >= 0 ? lj : lk;
+  const int32_t t = bj >= 0 ? lk : lj;
+  const int32_t* cl = cm.clist + cm.clist_off[b];
+  int lo = 0, hi = cm.ccnt[b] - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int32_t v = cl[mid];
+    if (v == t) return cm.cval + cm.cval_off[b] + mid + (int64_t)l * cm.ccnt[b];
+    if (v < t) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return cm.sink;   // cannot happen: the coupling list holds every neighbour
+}
+
+__global__ __launch_bounds__(256) void k_assemble_pairs_map(int64_t ntask, const int32_t* __restrict__ tra,
+                                                            const int32_t* __restrict__ trb,
+                                                            const int64_t* __restrict__ tm,
+                                                            const double* __restrict__ mval,
+                                                            const int32_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ ci,
+                                                            const double* __restrict__ av, ColMap cm) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntask) return;
+  const int32_t ra = tra[t], rb = trb[t];
+  const double m = mval[tm[t]];
+  if (m == 0.0) return;
+  const int32_t ba = rp[ra], ea = rp[ra + 1], bb = rp[rb], eb = rp[rb + 1];
+  if (ra == rb) {
+    for (int32_t p = ba; p < ea; ++p) {
+      const double mj = m * av[p];
+      for (int32_t q = ba; q <= p; ++q) atomicAdd(dest(cm, ci[p], ci[q]), mj * av[q]);
+    }
+  } else {
+    for (int32_t p = ba; p < ea; ++p) {
+      const int32_t j = ci[p];
+      const double mj = m * av[p];
+      for (int32_t q = bb; q < eb; ++q) {
+        const int32_t k = ci[q];
+        double v = mj * av[q];
+        if (j == k) v *= 2.0;
+        atomicAdd(dest(cm, j, k), v);
+      }
+    }
+  }
+}
+
+void assemble_pairs_map(int64_t ntask, const int32_t* tra, const int32_t* trb, const int64_t* tm, const double* mval,
+                        const Csr& A, const ColMap& cm, hipStream_t st) {
+  if (ntask == 0) return;
+  hipLaunchKernelGGL(k_assemble_pairs_map, dim3((unsigned)ceil_div(ntask, 256)), dim3(256), 0, st, ntask, tra, trb,
+                     tm, mval, A.rowptr, A.col, A.val, cm);
+  HC_LAUNCH_CHECK();
+}
+
+__global__ void k_add_P_map(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const double* __restrict__ v, double delta, ColMap cm) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  *dest(cm, i, i) += delta;   // each diagonal entry has exactly one writer here
+  if (!rp) return;
+  for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+    const int32_t j = ci[p];
+    if (j <= i) atomicAdd(dest(cm, i, j), v[p]);
+  }
+}
+
+void add_P_delta_map(const Csr& P, int64_t n, double delta, const ColMap& cm, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_add_P_map, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, (int32_t)n, P.rowptr, P.col,
+                     P.val, delta, cm);
+  HC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// one wave per leaf
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_leaf_factor(ColMap cm, double tol, double fix,
+                                                    unsigned long long* __restrict__ hits) {
+  __shared__ double Lb[LEAF_MAX][LEAF_MAX + 1];
+  __shared__ double W[LEAF_CPL_MAX][LEAF_MAX + 1];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int l = cm.lsize[b], cnt = cm.ccnt[b];
+  double* lv = cm.lval + cm.lval_off[b];
+  double* cv = cm.cval + cm.cval_off[b];
+  const int32_t* cl = cm.clist + cm.clist_off[b];
+  for (int e = lane; e < l * l; e += 64) {
+    const int i = e % l, j = e / l;
+    Lb[i][j] = (i >= j) ? lv[e] : 0.0;
+  }
+  for (int e = lane; e < cnt * l; e += 64) W[e % cnt][e / cnt] = cv[e];
+  __syncthreads();
+  int nh = 0;
+  for (int j = 0; j < l; ++j) {
+    double d = Lb[j][j];
+    if (!(d > tol)) {
+      d = fix;
+      ++nh;
+    }
+    const double ljj = sqrt(d);
+    __syncthreads();
+    if (lane == j) Lb[j][j] = ljj;
+    if (lane > j && lane < l) Lb[lane][j] /= ljj;
+    __syncthreads();
+    for (int k = j + 1; k < l; ++k)
+      if (lane >= k && lane < l) Lb[lane][k] -= Lb[lane][j] * Lb[k][j];
+    __syncthreads();
+  }
+  if (lane == 0 && nh) atomicAdd(hits, (unsigned long long)nh);
+  // row a of W solves L_b w = s_a:  w_j = (s_aj - sum_{k<j} L_jk w_k) / L_jj
+  if (lane < cnt)
+    for (int j = 0; j < l; ++j) {
+      double v = W[lane][j];
+      for (int k = 0; k < j; ++k) v -= Lb[j][k] * W[lane][k];
+      W[lane][j] = v / Lb[j][j];
+    }
+  __syncthreads();
+  for (int e = lane; e < l * l; e += 64) {
+    const int i = e % l, j = e / l;
+    lv[e] = (i >= j) ? Lb[i][j] : 0.0;
+  }
+  for (int e = lane; e < cnt * l; e += 64) cv[e] = W[e % cnt][e / cnt];
+  // S_TT[cl[a], cl[c]] -= sum_j W[a][j] W[c][j] for a >= c (cl ascending, so
+  // the target is in the lower triangle)
+  const int npair = cnt * (cnt + 1) / 2;
+  for (int p = lane; p < npair; p += 64) {
+    int a = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+    while (a * (a + 1) / 2 > p) --a;
+    while ((a + 1) * (a + 2) / 2 <= p) ++a;
+    const int c = p - a * (a + 1) / 2;
+    double v = 0.0;
+    for (int j = 0; j < l; ++j) v += W[a][j] * W[c][j];
+    atomicAdd(&cm.ST[cl[a] + (int64_t)cl[c] * cm.ldt], -v);
+  }
+}
+
+void leaf_factor(const ColMap& cm, double tol, double fix, unsigned long long* hits, hipStream_t st) {
+  if (cm.nleaf == 0) return;
+  hipLaunchKernelGGL(k_leaf_factor, dim3((unsigned)cm.nleaf), dim3(64), 0, st, cm, tol, fix, hits);
+  HC_LAUNCH_CHECK();
+}
+
+__device__ inline void load_leaf_L(const ColMap& cm, int b, int l, int lane, double (*Lb)[LEAF_MAX + 1]) {
+  const double* lv = cm.lval + cm.lval_off[b];
+  for (int e = lane; e < l * l; e += 64) Lb[e % l][e / l] = lv[e];
+}
+
+__global__ __launch_bounds__(64) void k_leaf_fwd(ColMap cm, const double* __restrict__ u, double* __restrict__ y,
+                                                 double* __restrict__ uT) {
+  __shared__ double Lb[LEAF_MAX][LEAF_MAX + 1];
+  __shared__ double yb[LEAF_MAX];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int l = cm.lsize[b], cnt = cm.ccnt[b];
+  const int32_t* cols = cm.lcols + cm.lcol_off[b];
+  load_leaf_L(cm, b, l, lane, Lb);
+  if (lane < l) yb[lane] = u[cols[lane]];
+  __syncthreads();
+  if (lane == 0)
+    for (int j = 0; j < l; ++j) {
+      double v = yb[j];
+      for (int k = 0; k < j; ++k) v -= Lb[j][k] * yb[k];
+      yb[j] = v / Lb[j][j];
+    }
+  __syncthreads();
+  if (lane < l) y[cols[lane]] = yb[lane];
+  if (lane < cnt) {
+    const double* cv = cm.cval + cm.cval_off[b];
+    double v = 0.0;
+    for (int j = 0; j < l; ++j) v += cv[lane + (int64_t)j * cnt] * yb[j];
+    atomicAdd(&uT[cm.clist[cm.clist_off[b] + lane]], -v);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_leaf_bwd(ColMap cm, const double* __restrict__ xT, double* __restrict__ x) {
+  __shared__ double Lb[LEAF_MAX][LEAF_MAX + 1];
+  __shared__ double vb[LEAF_MAX];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int l = cm.lsize[b], cnt = cm.ccnt[b];
+  const int32_t* cols = cm.lcols + cm.lcol_off[b];
+  const int32_t* cl = cm.clist + cm.clist_off[b];
+  const double* cv = cm.cval + cm.cval_off[b];
+  load_leaf_L(cm, b, l, lane, Lb);
+  if (lane < l) {
+    double v = x[cols[lane]];
+    for (int a = 0; a < cnt; ++a) v -= cv[a + (int64_t)lane * cnt] * xT[cl[a]];
+    vb[lane] = v;
+  }
+  __syncthreads();
+  if (lane == 0)
+    for (int j = l - 1; j >= 0; --j) {
+      double v = vb[j];
+      for (int k = j + 1; k < l; ++k) v -= Lb[k][j] * vb[k];
+      vb[j] = v / Lb[j][j];
+    }
+  __syncthreads();
+  if (lane < l) x[cols[lane]] = vb[lane];
+}
+
+void leaf_forward(const ColMap& cm, const double* u, double* y, double* uT, hipStream_t st) {
+  if (cm.nleaf == 0) return;
+  hipLaunchKernelGGL(k_leaf_fwd, dim3((unsigned)cm.nleaf), dim3(64), 0, st, cm, u, y, uT);
+  HC_LAUNCH_CHECK();
+}
+
+void leaf_backward(const ColMap& cm, const double* xT, double* x, hipStream_t st) {
+  if (cm.nleaf == 0) return;
+  hipLaunchKernelGGL(k_leaf_bwd, dim3((unsigned)cm.nleaf), dim3(64), 0, st, cm, xT, x);
+  HC_LAUNCH_CHECK();
+}
+
+__global__ void k_gather_tail(int64_t nt, const int32_t* __restrict__ tcols, const double* __restrict__ u,
+                              double* __restrict__ uT) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nt) uT[t] = u[tcols[t]];
+}
+__global__ void k_scatter_tail(int64_t nt, const int32_t* __restrict__ tcols, const double* __restrict__ xT,
+                               double* __restrict__ x) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nt) x[tcols[t]] = xT[t];
+}
+
+void gather_tail(const ColMap& cm, const double* u, double* uT, hipStream_t st) {
+  if (cm.nt == 0) return;
+  hipLaunchKernelGGL(k_gather_tail, dim3((unsigned)ceil_div(cm.nt, 256)), dim3(256), 0, st, cm.nt, cm.tcols, u, uT);
+  HC_LAUNCH_CHECK();
+}
+void scatter_tail(const ColMap& cm, const double* xT, double* x, hipStream_t st) {
+  if (cm.nt == 0) return;
+  hipLaunchKernelGGL(k_scatter_tail, dim3((unsigned)ceil_div(cm.nt, 256)), dim3(256), 0, st, cm.nt, cm.tcols, xT, x);
+  HC_LAUNCH_CHECK();
+}
+
+}  // namespace hc

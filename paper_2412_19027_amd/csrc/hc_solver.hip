@@ -31,6 +31,7 @@
 
 #include "hc_cones.h"
 #include "hc_dense.h"
+#include "hc_leaf.h"
 #include "hc_vec.h"
 
 using namespace hc;
@@ -78,6 +79,13 @@ struct hc_solver {
   bool has_nonsym = false;
   std::vector<int32_t> tra, trb;   // Schur assembly tasks
   std::vector<int64_t> tm;
+  // two-level split of the Schur complement (leaf blocks + dense tail)
+  int64_t nt = 0;                  // tail columns
+  bool leaves = false;             // any leaf block
+  std::vector<int32_t> col_leaf, col_loc, tail_cols, leaf_size, leaf_cols, leaf_ccnt, leaf_clist;
+  std::vector<int64_t> leaf_lval_off, leaf_lcol_off, leaf_clist_off, leaf_cval_off;
+  int64_t lval_total = 0, cval_total = 0;
+  double leaf_flops = 0;
   int64_t mtotal = 0, stotal = 0;  // M entries, state entries
   int64_t ld = 0;
   bool mixed = false;
@@ -96,8 +104,10 @@ struct hc_solver {
   int32_t *dtra = nullptr, *dtrb = nullptr;
   int64_t* dtm = nullptr;
   double *dstate = nullptr, *dmval = nullptr, *dhdiag = nullptr;
-  double* dS = nullptr;
+  double* dS = nullptr;             // dense tail (nt x nt, leading dim ld)
   double* dLinv = nullptr;
+  ColMap cm;                        // column map of the two-level split
+  double *uT = nullptr, *xT = nullptr;   // compact tail vectors
   float *dS32 = nullptr, *dLinv32 = nullptr;
   double *dX256 = nullptr, *dXT256 = nullptr;
   float *dX256f = nullptr, *dXT256f = nullptr;
@@ -122,6 +132,7 @@ struct hc_solver {
   double delta = 0;
   double xPx_cache = 0;             // x'Px of the current iterate (from residuals)
   std::unique_ptr<Prof> prof;
+  Aux aux;   // side stream + events of the look-ahead factorisation
   bool use64 = false;               // mixed mode: this iteration fell back to the FP64 factor
   std::string last_error;
 };
@@ -364,6 +375,179 @@ void equilibrate(hc_solver* S, const HostCsr& A, const HostCsr& Pf, const std::v
   S->cscale = clampv(1.0 / std::max(1.0, std::max(mean, dq)));
 }
 
+// ---------------------------------------------------------------------------
+// Two-level split of the Schur complement.  The graph of S is the union of one
+// clique per cone (the columns its rows touch; every nonneg/zero row is a cone
+// of its own) and the off-diagonal entries of P.  Columns touched by a dense
+// row or of estimated degree above LEAF_DEGREE go to the dense tail; the
+// connected components of the remaining columns become leaf blocks when they
+// have at most LEAF_MAX columns and touch at most LEAF_CPL_MAX tail columns,
+// otherwise they join the tail.  Removing a component from the leaves never
+// changes another leaf's coupling (distinct components are not adjacent).
+// ---------------------------------------------------------------------------
+constexpr int LEAF_DEGREE = 64;
+
+void build_leaves(hc_solver* S) {
+  const int64_t n = S->n;
+  const HostCsr& A = S->A;
+  const HostCsr& P = S->P;
+  std::vector<char> tail(n, 0);
+  const int nd = (int)S->drows.size();
+  for (int d = 0; d < nd; ++d)
+    for (int64_t j = 0; j < n; ++j)
+      if (S->Ad[(size_t)d * n + j] != 0.0) tail[j] = 1;
+  // cliques (CSR over columns)
+  std::vector<int64_t> cp{0};
+  std::vector<int32_t> cc;
+  std::vector<int32_t> buf;
+  auto close_clique = [&]() {
+    std::sort(buf.begin(), buf.end());
+    buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+    if (buf.size() > 0) {
+      cc.insert(cc.end(), buf.begin(), buf.end());
+      cp.push_back((int64_t)cc.size());
+    }
+    buf.clear();
+  };
+  auto add_row = [&](int64_t r) {
+    for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) buf.push_back(A.ci[k]);
+  };
+  for (const Segment& g : S->segs) {
+    if (g.kind == HC_CONE_ZERO || g.kind == HC_CONE_NONNEG) {
+      for (int64_t i = 0; i < g.count; ++i) {
+        add_row(g.base + i);
+        close_clique();
+      }
+      continue;
+    }
+    for (int64_t c = 0; c < g.count; ++c) {
+      for (int a = 0; a < g.dim; ++a)
+        add_row(g.kind == HC_CONE_PSD ? g.base + c * g.dim + a : g.base + (int64_t)a * g.count + c);
+      close_clique();
+    }
+  }
+  const int64_t ncl = (int64_t)cp.size() - 1;
+  std::vector<int64_t> deg(n, 0);
+  for (int64_t c = 0; c < ncl; ++c)
+    for (int64_t e = cp[c]; e < cp[c + 1]; ++e) deg[cc[e]] += cp[c + 1] - cp[c] - 1;
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t k = P.rp[i]; k < P.rp[i + 1]; ++k)
+      if (P.ci[k] != i) deg[i]++;
+  for (int64_t j = 0; j < n; ++j)
+    if (!S->st.leaf_blocks || deg[j] > LEAF_DEGREE) tail[j] = 1;
+  // connected components of the non-tail columns (union-find)
+  std::vector<int32_t> parent(n);
+  for (int64_t j = 0; j < n; ++j) parent[j] = (int32_t)j;
+  auto find = [&](int32_t x) {
+    while (parent[x] != x) {
+      parent[x] = parent[parent[x]];
+      x = parent[x];
+    }
+    return x;
+  };
+  auto unite = [&](int32_t a, int32_t b) {
+    a = find(a);
+    b = find(b);
+    if (a != b) parent[std::max(a, b)] = std::min(a, b);
+  };
+  for (int64_t c = 0; c < ncl; ++c) {
+    int32_t first = -1;
+    for (int64_t e = cp[c]; e < cp[c + 1]; ++e) {
+      const int32_t j = cc[e];
+      if (tail[j]) continue;
+      if (first < 0) first = j;
+      else unite(first, j);
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t k = P.rp[i]; k < P.rp[i + 1]; ++k)
+      if (!tail[i] && !tail[P.ci[k]]) unite((int32_t)i, P.ci[k]);
+  std::vector<std::vector<int32_t>> comp;   // members, indexed by root order
+  std::vector<int32_t> comp_of(n, -1);
+  for (int64_t j = 0; j < n; ++j) {
+    if (tail[j]) continue;
+    const int32_t r = find((int32_t)j);
+    if (comp_of[r] < 0) {
+      comp_of[r] = (int32_t)comp.size();
+      comp.emplace_back();
+    }
+    comp[comp_of[r]].push_back((int32_t)j);
+  }
+  for (auto& c : comp)
+    if ((int)c.size() > LEAF_MAX)
+      for (int32_t j : c) tail[j] = 1;
+  // incidence column -> cliques, then each leaf's coupled tail columns
+  std::vector<int64_t> ip(n + 1, 0);
+  for (int64_t e = 0; e < (int64_t)cc.size(); ++e) ip[cc[e] + 1]++;
+  for (int64_t j = 0; j < n; ++j) ip[j + 1] += ip[j];
+  std::vector<int32_t> inc(cc.size());
+  {
+    std::vector<int64_t> fillp(ip.begin(), ip.end() - 1);
+    for (int64_t c = 0; c < ncl; ++c)
+      for (int64_t e = cp[c]; e < cp[c + 1]; ++e) inc[fillp[cc[e]]++] = (int32_t)c;
+  }
+  std::vector<std::vector<int32_t>> cpl(comp.size());
+  for (size_t b = 0; b < comp.size(); ++b) {
+    if (tail[comp[b][0]]) continue;
+    std::vector<int32_t>& t = cpl[b];
+    for (int32_t j : comp[b]) {
+      for (int64_t e = ip[j]; e < ip[j + 1]; ++e) {
+        const int32_t c = inc[e];
+        for (int64_t f = cp[c]; f < cp[c + 1]; ++f)
+          if (tail[cc[f]]) t.push_back(cc[f]);
+      }
+      for (int32_t k = P.rp[j]; k < P.rp[j + 1]; ++k)
+        if (tail[P.ci[k]]) t.push_back(P.ci[k]);
+    }
+    std::sort(t.begin(), t.end());
+    t.erase(std::unique(t.begin(), t.end()), t.end());
+  }
+  for (size_t b = 0; b < comp.size(); ++b)
+    if (!tail[comp[b][0]] && (int)cpl[b].size() > LEAF_CPL_MAX)
+      for (int32_t j : comp[b]) tail[j] = 1;
+  // final numbering: tail ascending by column, leaves in order of first column
+  S->col_leaf.assign(n, -1);
+  S->col_loc.assign(n, 0);
+  S->tail_cols.clear();
+  for (int64_t j = 0; j < n; ++j)
+    if (tail[j]) {
+      S->col_loc[j] = (int32_t)S->tail_cols.size();
+      S->tail_cols.push_back((int32_t)j);
+    }
+  S->nt = (int64_t)S->tail_cols.size();
+  S->leaf_size.clear();
+  S->leaf_cols.clear();
+  S->leaf_ccnt.clear();
+  S->leaf_clist.clear();
+  S->leaf_lval_off.clear();
+  S->leaf_lcol_off.clear();
+  S->leaf_clist_off.clear();
+  S->leaf_cval_off.clear();
+  S->lval_total = S->cval_total = 0;
+  S->leaf_flops = 0;
+  for (size_t b = 0; b < comp.size(); ++b) {
+    if (tail[comp[b][0]]) continue;
+    const int32_t id = (int32_t)S->leaf_size.size();
+    const int l = (int)comp[b].size(), cnt = (int)cpl[b].size();
+    S->leaf_size.push_back(l);
+    S->leaf_lval_off.push_back(S->lval_total);
+    S->leaf_lcol_off.push_back((int64_t)S->leaf_cols.size());
+    S->leaf_clist_off.push_back((int64_t)S->leaf_clist.size());
+    S->leaf_cval_off.push_back(S->cval_total);
+    S->leaf_ccnt.push_back(cnt);
+    for (int i = 0; i < l; ++i) {
+      S->col_leaf[comp[b][i]] = id;
+      S->col_loc[comp[b][i]] = i;
+      S->leaf_cols.push_back(comp[b][i]);
+    }
+    for (int32_t k : cpl[b]) S->leaf_clist.push_back(S->col_loc[k]);
+    S->lval_total += (int64_t)l * l;
+    S->cval_total += (int64_t)cnt * l;
+    S->leaf_flops += (double)l * l * l / 3.0 + (double)cnt * l * l + (double)cnt * cnt * l;
+  }
+  S->leaves = !S->leaf_size.empty();
+}
+
 void setup_host(hc_solver* S, const hc_problem* p) {
   const int64_t n = p->n, m = p->m;
   S->n = n;
@@ -510,7 +694,14 @@ void setup_host(hc_solver* S, const hc_problem* p) {
   }
   S->A = std::move(As);
   S->At = std::move(At);
-  S->ld = ((n + 63) / 64) * 64;
+  build_leaves(S);
+  if (S->leaves && nd) {   // dense rows live on tail columns only: re-index them
+    std::vector<double> Adt((size_t)nd * S->nt);
+    for (int d = 0; d < nd; ++d)
+      for (int64_t t = 0; t < S->nt; ++t) Adt[(size_t)d * S->nt + t] = S->Ad[(size_t)d * n + S->tail_cols[t]];
+    S->Ad.swap(Adt);
+  }
+  S->ld = ((S->nt + 63) / 64) * 64;
   if (S->st.static_reg <= 0) S->st.static_reg = S->mixed ? 3.4526698300124393e-04 : 1e-8;
   if (S->st.dyn_reg < 0) S->st.dyn_reg = S->mixed ? std::ldexp(1.0, -46) : std::ldexp(1.0, -104);
 }
@@ -598,24 +789,34 @@ void factor(hc_solver* S) {
   const double hmax = r.run()[0];
   S->delta = S->st.static_reg + S->st.dyn_reg * std::max(S->maxPdiag, hmax);
   for (auto& g : S->sdev) cone_mblock(g, S->delta, st);
-  fill_lower_zero(S->n, S->ld, S->dS, st);
-  add_P_delta(S->dP, S->n, S->delta, S->ld, S->dS, st);
-  assemble_pairs((int64_t)S->tra.size(), S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->ld, S->dS, st);
+  const int64_t nt = S->nt;
+  fill_lower_zero(nt, S->ld, S->dS, st);
+  if (S->leaves) {
+    vfill(S->lval_total, 0.0, S->cm.lval, st);
+    vfill(S->cval_total, 0.0, S->cm.cval, st);
+    add_P_delta_map(S->dP, S->n, S->delta, S->cm, st);
+    assemble_pairs_map((int64_t)S->tra.size(), S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->cm, st);
+  } else {
+    add_P_delta(S->dP, S->n, S->delta, S->ld, S->dS, st);
+    assemble_pairs((int64_t)S->tra.size(), S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->ld, S->dS, st);
+  }
   const int nd = (int)S->drows.size();
   if (nd) {
-    scale_dense_rows(nd, S->n, S->dAd, S->ddmidx, S->dmval, S->dBd, st);
-    gemm_nt<double>(S->dS, S->ld, S->dBd, S->n, S->dBd, S->n, S->n, S->n, nd, 1.0, true, 0, 0, st);
+    scale_dense_rows(nd, nt, S->dAd, S->ddmidx, S->dmval, S->dBd, st);
+    gemm_nt<double>(S->dS, S->ld, S->dBd, nt, S->dBd, nt, nt, nt, nd, 1.0, true, 0, 0, st);
   }
   const double tol = 0.0;
+  // leaves are factored in FP64 in both modes; their updates land in the tail
+  leaf_factor(S->cm, tol, S->delta, S->dhits, st);
   S->use64 = false;
   Prof* pf = S->st.profile ? S->prof.get() : nullptr;
   if (S->mixed) {
-    lower_to_f32(S->n, S->ld, S->dS, S->dS32, st);
-    dense_cholesky<float>(S->dS32, S->n, S->ld, S->dLinv32, tol, S->delta, S->dhits, st, pf);
-    dense_block_inverses<float>(S->dS32, S->n, S->ld, S->dLinv32, S->dX256f, S->dXT256f, st);
+    lower_to_f32(nt, S->ld, S->dS, S->dS32, st);
+    dense_cholesky<float>(S->dS32, nt, S->ld, S->dLinv32, tol, S->delta, S->dhits, st, pf, &S->aux);
+    dense_block_inverses<float>(S->dS32, nt, S->ld, S->dLinv32, S->dX256f, S->dXT256f, st);
   } else {
-    dense_cholesky<double>(S->dS, S->n, S->ld, S->dLinv, tol, S->delta, S->dhits, st, pf);
-    dense_block_inverses<double>(S->dS, S->n, S->ld, S->dLinv, S->dX256, S->dXT256, st);
+    dense_cholesky<double>(S->dS, nt, S->ld, S->dLinv, tol, S->delta, S->dhits, st, pf, &S->aux);
+    dense_block_inverses<double>(S->dS, nt, S->ld, S->dLinv, S->dX256, S->dXT256, st);
   }
   S->info.factorizations++;
   if (pf) {
@@ -630,29 +831,41 @@ void factor(hc_solver* S) {
 // mixed mode: factor the (still FP64) Schur complement in FP64 for the rest of
 // this iteration
 void fallback_fp64(hc_solver* S) {
-  dense_cholesky<double>(S->dS, S->n, S->ld, S->dLinv, 0.0, S->delta, S->dhits, S->stream, nullptr);
-  dense_block_inverses<double>(S->dS, S->n, S->ld, S->dLinv, S->dX256, S->dXT256, S->stream);
+  dense_cholesky<double>(S->dS, S->nt, S->ld, S->dLinv, 0.0, S->delta, S->dhits, S->stream, nullptr, &S->aux);
+  dense_block_inverses<double>(S->dS, S->nt, S->ld, S->dLinv, S->dX256, S->dXT256, S->stream);
   S->use64 = true;
   S->info.fp64_fallbacks++;
 }
 
-// x = S^-1 u (one right-hand side) in the factor precision
+// x = S^-1 u (one right-hand side): leaves in FP64, the tail in the factor
+// precision
 void schur_solve(hc_solver* S, const double* u, double* x) {
   hipStream_t st = S->stream;
-  const int64_t n = S->n;
+  const int64_t nt = S->nt;
+  const double* ut = u;
+  double* xt = x;
+  if (S->leaves) {
+    gather_tail(S->cm, u, S->uT, st);
+    leaf_forward(S->cm, u, x, S->uT, st);   // y_b into x at the leaf columns
+    ut = S->uT;
+    xt = S->xT;
+  }
   if (S->mixed && !S->use64) {
-    Red r(S, n);
     RedOps ops{};
     ops.nops = 1;
-    ops.op[0] = RedOp{RED_MAX_MUL, u, nullptr, 0.0, nullptr};
-    const int nb = reduce_launch(n, ops, S->dpart, st);
+    ops.op[0] = RedOp{RED_MAX_MUL, ut, nullptr, 0.0, nullptr};
+    const int nb = reduce_launch(nt, ops, S->dpart, st);
     combine_max(nb, S->dpart, S->dscal, st);
-    to_f32(n, u, S->dscal, S->sb32, st);
-    dense_solve<float>(S->dS32, n, S->ld, S->dX256f, S->dXT256f, S->sb32, S->sy32, S->sx32, 1, st);
-    from_f32(n, S->sx32, S->dscal, x, st);
+    to_f32(nt, ut, S->dscal, S->sb32, st);
+    dense_solve<float>(S->dS32, nt, S->ld, S->dX256f, S->dXT256f, S->sb32, S->sy32, S->sx32, 1, st);
+    from_f32(nt, S->sx32, S->dscal, xt, st);
   } else {
-    vcopy(n, u, S->sb, st);
-    dense_solve<double>(S->dS, n, S->ld, S->dX256, S->dXT256, S->sb, S->sy, x, 1, st);
+    vcopy(nt, ut, S->sb, st);
+    dense_solve<double>(S->dS, nt, S->ld, S->dX256, S->dXT256, S->sb, S->sy, xt, 1, st);
+  }
+  if (S->leaves) {
+    leaf_backward(S->cm, S->xT, x, st);
+    scatter_tail(S->cm, S->xT, x, st);
   }
 }
 
@@ -996,7 +1209,7 @@ int iterate(hc_solver* S, const Resid& R) {
   // G(v): gx = -(P x + A'z + q tau) = -rdv ; gz = s + A x - b tau = -rpv
   const double gt = S->kappa + R.qx + R.bz + R.xPx / S->tau;
   bool force_dual = S->st.force_dual_scaling != 0;
-  double alpha_c = 0, sigma = 0;
+  double alpha_c = 0, sigma = 0, alpha_a = 0;
   Dir dc{};
   for (int attempt = 0; attempt < 2; ++attempt) {
     double t0 = now_ms();
@@ -1015,7 +1228,7 @@ int iterate(hc_solver* S, const Resid& R) {
     vlin3(n, -1.0, S->rdv, 0.0, nullptr, 0.0, nullptr, S->r1, st);
     vlin3(m, 1.0, S->rpv, 1.0, S->s, 0.0, nullptr, S->r2, st);
     const Dir da = direction(S, S->r1, S->r2, gt, S->kappa * S->tau, S->s, S->dxa, S->dza, S->dsa);
-    const double alpha_a = step_length(S, Step{S->dsa, S->dza, da.dtau, da.dkappa}, false);
+    alpha_a = step_length(S, Step{S->dsa, S->dza, da.dtau, da.dkappa}, false);
     sigma = (1.0 - alpha_a) * (1.0 - alpha_a) * (1.0 - alpha_a);
     // combined
     const double dk = S->kappa * S->tau + da.dkappa * da.dtau - sigma * mu;
@@ -1034,8 +1247,11 @@ int iterate(hc_solver* S, const Resid& R) {
     }
     break;
   }
-  if (S->st.verbose)
-    std::printf("    sigma %.3e alpha_c %.4f delta %.2e\n", sigma, alpha_c, S->delta);
+  if (S->st.verbose) {
+    std::printf("    sigma %.3e alpha_a %.4f alpha_c %.4f delta %.2e ir %lld fp64-fallbacks %lld\n", sigma, alpha_a,
+                alpha_c, S->delta, (long long)S->info.ir_solves, (long long)S->info.fp64_fallbacks);
+    std::fflush(stdout);
+  }
   if (alpha_c < 1e-4) return HC_STATUS_INSUFFICIENT_PROGRESS;
   const double a = S->st.step_fraction * alpha_c;
   vaxpby(n, a, S->dx, 1.0, S->x, st);
@@ -1051,6 +1267,8 @@ void run_solve(hc_solver* S) {
   S->info = hc_info{};
   S->info.setup_ms = keep.setup_ms;
   S->info.n_ordered = keep.n_ordered;
+  S->info.n_leaves = keep.n_leaves;
+  S->info.leaf_columns = keep.leaf_columns;
   S->info.factor_flops = keep.factor_flops;
   HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), S->stream));
   init_point(S);
@@ -1104,19 +1322,42 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->dstate = buf.take<double>(S->stotal + 1);
   S->dmval = buf.take<double>(S->mtotal + 1);
   S->dhdiag = buf.take<double>(m);
-  S->dS = buf.take<double>((size_t)S->ld * n);
-  S->dLinv = buf.take<double>(linv_elems(n));
-  S->dX256 = buf.take<double>(inv256_elems(n));
-  S->dXT256 = buf.take<double>(inv256_elems(n));
+  const int64_t nt = S->nt;
+  S->dS = buf.take<double>((size_t)S->ld * nt);
+  S->dLinv = buf.take<double>(linv_elems(nt));
+  S->dX256 = buf.take<double>(inv256_elems(nt));
+  S->dXT256 = buf.take<double>(inv256_elems(nt));
   if (S->mixed) {
-    S->dS32 = buf.take<float>((size_t)S->ld * n);
-    S->dLinv32 = buf.take<float>(linv_elems(n));
-    S->dX256f = buf.take<float>(inv256_elems(n));
-    S->dXT256f = buf.take<float>(inv256_elems(n));
-    S->sb32 = buf.take<float>(n);
-    S->sy32 = buf.take<float>(n);
-    S->sx32 = buf.take<float>(n);
+    S->dS32 = buf.take<float>((size_t)S->ld * nt);
+    S->dLinv32 = buf.take<float>(linv_elems(nt));
+    S->dX256f = buf.take<float>(inv256_elems(nt));
+    S->dXT256f = buf.take<float>(inv256_elems(nt));
+    S->sb32 = buf.take<float>(nt);
+    S->sy32 = buf.take<float>(nt);
+    S->sx32 = buf.take<float>(nt);
   }
+  // column map of the two-level split
+  ColMap& cm = S->cm;
+  cm.nleaf = (int64_t)S->leaf_size.size();
+  cm.nt = nt;
+  cm.ldt = S->ld;
+  cm.ST = S->dS;
+  cm.leaf = upload(buf, S->col_leaf, st);
+  cm.loc = upload(buf, S->col_loc, st);
+  cm.tcols = upload(buf, S->tail_cols, st);
+  cm.lsize = upload(buf, S->leaf_size, st);
+  cm.lval_off = upload(buf, S->leaf_lval_off, st);
+  cm.lcol_off = upload(buf, S->leaf_lcol_off, st);
+  cm.lcols = upload(buf, S->leaf_cols, st);
+  cm.ccnt = upload(buf, S->leaf_ccnt, st);
+  cm.clist_off = upload(buf, S->leaf_clist_off, st);
+  cm.clist = upload(buf, S->leaf_clist, st);
+  cm.cval_off = upload(buf, S->leaf_cval_off, st);
+  cm.lval = buf.take<double>(S->lval_total + 1);
+  cm.cval = buf.take<double>(S->cval_total + 1);
+  cm.sink = buf.take<double>(1);
+  S->uT = buf.take<double>(nt);
+  S->xT = buf.take<double>(nt);
   S->dhits = buf.take<unsigned long long>(1);
   S->dpd = buf.take<int>(2);
   S->dscal = buf.take<double>(8);
@@ -1132,9 +1373,9 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->t2 = buf.take<double>(L);
   S->u1 = buf.take<double>(L);
   S->w1 = buf.take<double>(L);
-  S->sb = buf.take<double>(n);
-  S->sy = buf.take<double>(n);
-  S->sx = buf.take<double>(n);
+  S->sb = buf.take<double>(nt);
+  S->sy = buf.take<double>(nt);
+  S->sx = buf.take<double>(nt);
 }
 
 size_t workspace_bytes(const hc_solver* S) {
@@ -1219,6 +1460,7 @@ int32_t hc_settings_default(hc_settings* o) {
   o->force_dual_scaling = 0;
   o->verbose = 0;
   o->profile = 0;
+  o->leaf_blocks = 1;
   return HC_OK;
 }
 
@@ -1234,8 +1476,10 @@ int32_t hc_setup(hc_solver** out, const hc_problem* prob, const hc_settings* set
     validate(prob);
     setup_host(S, prob);
     S->info.setup_ms = now_ms() - t0;
-    S->info.n_ordered = S->n;
-    S->info.factor_flops = cholesky_flops(S->n);
+    S->info.n_ordered = S->nt;
+    S->info.n_leaves = (int64_t)S->leaf_size.size();
+    S->info.leaf_columns = S->n - S->nt;
+    S->info.factor_flops = cholesky_flops(S->nt) + S->leaf_flops;
   } catch (const Error& e) {
     g_last_error = e.msg;
     delete S;

@@ -90,6 +90,13 @@ template <typename F> int32_t guard(F&& f) {
 
 }  // namespace
 
+// plain streaming copy, 16 bytes per lane per step (reference kernel for
+// the HBM byte counters)
+__global__ __launch_bounds__(256) void k_copy_reference(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                        int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+}
+
 extern "C" {
 
 int32_t hc_test_cone_scale(int32_t type, int64_t count, int32_t dim, const double* alpha, const double* s,
@@ -206,6 +213,7 @@ int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, doubl
     if (n <= 0 || ld < n || nrhs < 1 || nrhs > 4 || !A || !B) throw Error{HC_ERR_INVALID_ARG, "bad dense test args"};
     hipStream_t st = (hipStream_t)stream;
     std::vector<void*> owned;
+    Aux aux;
     auto al = [&](size_t bytes) {
       void* p = nullptr;
       if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) throw Error{HC_ERR_OOM, "hipMalloc failed"};
@@ -222,7 +230,7 @@ int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, doubl
         float* y32 = (float*)al((size_t)n * nrhs * 4);
         float* x32 = (float*)al((size_t)n * nrhs * 4);
         lower_to_f32(n, ld, A, A32, st);
-        dense_cholesky<float>(A32, n, ld, L32, 0.0, 1e-8, hits, st);
+        dense_cholesky<float>(A32, n, ld, L32, 0.0, 1e-8, hits, st, nullptr, &aux);
         float* X32 = (float*)al(inv256_elems(n) * 4);
         float* XT32 = (float*)al(inv256_elems(n) * 4);
         dense_block_inverses<float>(A32, n, ld, L32, X32, XT32, st);
@@ -236,7 +244,7 @@ int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, doubl
         double* Li = (double*)al(linv_elems(n) * 8);
         double* y = (double*)al((size_t)n * nrhs * 8);
         double* x = (double*)al((size_t)n * nrhs * 8);
-        dense_cholesky<double>(A, n, ld, Li, 0.0, 1e-8, hits, st);
+        dense_cholesky<double>(A, n, ld, Li, 0.0, 1e-8, hits, st, nullptr, &aux);
         double* X64 = (double*)al(inv256_elems(n) * 8);
         double* XT64 = (double*)al(inv256_elems(n) * 8);
         dense_block_inverses<double>(A, n, ld, Li, X64, XT64, st);
@@ -252,6 +260,20 @@ int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, doubl
       throw;
     }
     for (void* p : owned) (void)hipFree(p);
+  });
+}
+
+int32_t hc_test_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+  return guard([&] {
+    if (!src || !dst || bytes < 0 || bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16)
+      throw Error{HC_ERR_INVALID_ARG, "copy needs 16-byte aligned pointers and a multiple of 16 bytes"};
+    if (bytes == 0) return;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n16 = bytes / 16;
+    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n16, 256), 8192);
+    hipLaunchKernelGGL(k_copy_reference, dim3(grid), dim3(256), 0, st, (const uint4*)src, (uint4*)dst, n16);
+    HC_LAUNCH_CHECK();
+    HC_HIP(hipStreamSynchronize(st));
   });
 }
 

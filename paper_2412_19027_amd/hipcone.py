@@ -22,7 +22,8 @@ STATUS = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasibl
 
 EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "hc_solve", "hc_get_info",
            "hc_get_solution", "hc_get_iterate", "hc_destroy", "hc_last_error", "hc_status_str",
-           "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_dense_chol_solve"]
+           "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_dense_chol_solve",
+           "hc_test_copy"]
 
 
 class hc_cone(C.Structure):
@@ -44,7 +45,7 @@ class hc_settings(C.Structure):
                 ("ir_abstol", C.c_double), ("ir_reltol", C.c_double), ("ir_max", C.c_int32),
                 ("beta", C.c_double), ("backtrack", C.c_double), ("step_fraction", C.c_double),
                 ("equilibrate", C.c_int32), ("equil_iters", C.c_int32), ("force_dual_scaling", C.c_int32),
-                ("verbose", C.c_int32), ("profile", C.c_int32)]
+                ("verbose", C.c_int32), ("profile", C.c_int32), ("leaf_blocks", C.c_int32)]
 
 
 class hc_device(C.Structure):
@@ -60,7 +61,7 @@ class hc_info(C.Structure):
                 ("ir_solves", C.c_int64), ("pivot_guard_hits", C.c_int64), ("dual_switches", C.c_int64),
                 ("n_ordered", C.c_int64), ("factor_flops", C.c_double), ("factorizations", C.c_int64),
                 ("gemm_ms", C.c_double), ("gemm_flops", C.c_double), ("gemm_launches", C.c_int64),
-                ("fp64_fallbacks", C.c_int64)]
+                ("fp64_fallbacks", C.c_int64), ("n_leaves", C.c_int64), ("leaf_columns", C.c_int64)]
 
 
 _lib = None
@@ -92,6 +93,7 @@ def lib():
         L.hc_test_cone_ds.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, dbl, dbl, vp, vp]
         L.hc_test_cone_step.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, dbl, vp, vp]
         L.hc_test_dense_chol_solve.argtypes = [i32, i64, i64, vp, i32, vp, C.POINTER(i64), vp]
+        L.hc_test_copy.argtypes = [vp, vp, i64, vp]
         for name in EXPORTS:
             getattr(L, name)
         _lib = L
@@ -122,6 +124,45 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
 
 
+def _setup(prob, settings):
+    """hc_setup on the host: returns (handle, buffers kept alive for it)."""
+    L = lib()
+    P = prob.P.tocsr()
+    A = prob.A.tocsr()
+    keep = dict(
+        Prp=np.ascontiguousarray(P.indptr, dtype=np.int64), Pci=np.ascontiguousarray(P.indices, dtype=np.int32),
+        Pv=np.ascontiguousarray(P.data, dtype=np.float64), q=np.ascontiguousarray(prob.q, dtype=np.float64),
+        Arp=np.ascontiguousarray(A.indptr, dtype=np.int64), Aci=np.ascontiguousarray(A.indices, dtype=np.int32),
+        Av=np.ascontiguousarray(A.data, dtype=np.float64), b=np.ascontiguousarray(prob.b, dtype=np.float64))
+    cones = (hc_cone * len(prob.cones))(*[hc_cone(int(k), int(d), float(a)) for k, d, a in prob.cones])
+    keep["cones"] = cones
+    k = keep
+    pr = hc_problem(prob.n, prob.m, _ptr(k["Prp"], C.c_int64), _ptr(k["Pci"], C.c_int32), _ptr(k["Pv"], C.c_double),
+                    _ptr(k["q"], C.c_double), _ptr(k["Arp"], C.c_int64), _ptr(k["Aci"], C.c_int32),
+                    _ptr(k["Av"], C.c_double), _ptr(k["b"], C.c_double), cones, len(prob.cones))
+    h = C.c_void_p()
+    _check(L.hc_setup(C.byref(h), C.byref(pr), C.byref(settings)))
+    return h, keep
+
+
+def analyze(prob, **settings) -> dict:
+    """Host-only setup (no device): the hc_info fields known after the
+    analysis (n_ordered, n_leaves, leaf_columns, factor_flops) and the device
+    workspace in bytes."""
+    L = lib()
+    h, _ = _setup(prob, default_settings(**settings))
+    try:
+        nbytes = C.c_size_t()
+        _check(L.hc_workspace_bytes(h, C.byref(nbytes)), h)
+        inf = hc_info()
+        _check(L.hc_get_info(h, C.byref(inf)), h)
+        out = {f: getattr(inf, f) for f, _ in hc_info._fields_}
+        out["workspace_bytes"] = int(nbytes.value)
+        return out
+    finally:
+        L.hc_destroy(h)
+
+
 class Solver:
     """One problem on one GPU.  `prob` is a workloads.Problem (or any object
     with n, m, P (upper CSR), q, A (CSR), b, cones)."""
@@ -130,23 +171,9 @@ class Solver:
         import torch
         self._torch = torch
         L = lib()
-        P = prob.P.tocsr()
-        A = prob.A.tocsr()
-        self._keep = dict(
-            Prp=np.ascontiguousarray(P.indptr, dtype=np.int64), Pci=np.ascontiguousarray(P.indices, dtype=np.int32),
-            Pv=np.ascontiguousarray(P.data, dtype=np.float64), q=np.ascontiguousarray(prob.q, dtype=np.float64),
-            Arp=np.ascontiguousarray(A.indptr, dtype=np.int64), Aci=np.ascontiguousarray(A.indices, dtype=np.int32),
-            Av=np.ascontiguousarray(A.data, dtype=np.float64), b=np.ascontiguousarray(prob.b, dtype=np.float64))
-        cones = (hc_cone * len(prob.cones))(*[hc_cone(int(k), int(d), float(a)) for k, d, a in prob.cones])
-        self._keep["cones"] = cones
-        k = self._keep
-        pr = hc_problem(prob.n, prob.m, _ptr(k["Prp"], C.c_int64), _ptr(k["Pci"], C.c_int32), _ptr(k["Pv"], C.c_double),
-                        _ptr(k["q"], C.c_double), _ptr(k["Arp"], C.c_int64), _ptr(k["Aci"], C.c_int32),
-                        _ptr(k["Av"], C.c_double), _ptr(k["b"], C.c_double), cones, len(prob.cones))
         self.settings = default_settings(**settings)
         self.n, self.m = prob.n, prob.m
-        h = C.c_void_p()
-        _check(L.hc_setup(C.byref(h), C.byref(pr), C.byref(self.settings)))
+        h, self._keep = _setup(prob, self.settings)
         self._h = h
         nbytes = C.c_size_t()
         _check(L.hc_workspace_bytes(h, C.byref(nbytes)), h)
@@ -251,3 +278,10 @@ def test_dense_chol_solve(A, B, precision=PRECISION_FP64):
                                           _stream()))
     torch.cuda.synchronize()
     return Bt.t().contiguous(), At.t().contiguous(), hits.value
+
+
+def test_copy(src, dst):
+    """Reference copy kernel: dst[:] = src[:] (torch cuda tensors of equal byte size)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(lib().hc_test_copy(_dptr(src), _dptr(dst), nbytes, _stream()))

@@ -56,3 +56,22 @@ def test_setup_validation_errors_on_host():
     cones[0] = hipcone.hc_cone(2, 2, 0.0)
     assert L.hc_setup(C.byref(h), C.byref(pr), None) == 0
     L.hc_destroy(h)
+
+
+def test_two_level_split_on_host():
+    """The host analysis splits the logistic-regression Schur complement into
+    one leaf per sample and per |theta_j| <= r_j pair, with theta as the dense
+    tail; dense-coupled problems stay one dense block."""
+    from paper_2412_19027_amd import workloads as W
+    N, F = 400, 30
+    p = W.logreg_exp(0, samples=N, features=F)
+    a = hipcone.analyze(p)
+    assert a["n_ordered"] == F                     # theta
+    assert a["n_leaves"] == N + F                  # (t, w1, w2) per sample, r_j per feature
+    assert a["leaf_columns"] == p.n - F
+    off = hipcone.analyze(p, leaf_blocks=0)
+    assert off["n_ordered"] == p.n and off["n_leaves"] == 0
+    assert off["factor_flops"] > 100 * a["factor_flops"]
+    socp = W.sparse_socp(0, nx=600, rank=5, n_zero=150, n_nonneg=400, n_soc=500)
+    s = hipcone.analyze(socp)                      # the dense factor rows touch every column
+    assert s["n_ordered"] == socp.n and s["n_leaves"] == 0
