@@ -99,6 +99,45 @@ def run_gpu(prob, precision, steps, warmup):
     )
 
 
+def run_served(count, rate=2000.0, workers=4, slots=32, budget=16 << 30, seed=0):
+    """The served form on a stream of MPC requests: problems are generated
+    beforehand, submitted at Poisson arrival times by one thread, and every
+    ticket is waited for; throughput and latency come from the server."""
+    import threading
+    from paper_2412_19027_amd import hipcone as HC
+    from paper_2412_19027_amd import workloads as W
+    probs = [W.mpc_socp(seed, i) for i in range(count)]
+    arrivals = W.mpc_arrivals(seed, count, rate)
+    srv = HC.Server(hbm_budget_bytes=budget, max_slots=slots, workers=workers)
+    tickets = [None] * count
+    t0 = time.perf_counter()
+
+    def feed():
+        for i, (p, a) in enumerate(zip(probs, arrivals)):
+            dt = a - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets[i] = srv.submit(p, tag=i)
+
+    th = threading.Thread(target=feed)
+    th.start()
+    th.join()
+    res = [srv.wait(t) for t in tickets]
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    statuses = {}
+    for r in res:
+        statuses[r["status_name"]] = statuses.get(r["status_name"], 0) + 1
+    return dict(
+        workload=f"MPC SOCP stream: {count} requests, Poisson {rate:g}/s, T in [10,100], nx in [4,12], "
+                 f"nu in [2,6] (n in [64,1812]), seed {seed}",
+        requests=count, wall_s=wall, solves_per_s=st["solves_per_s"], p50_latency_ms=st["p50_latency_ms"],
+        p99_latency_ms=st["p99_latency_ms"], mean_latency_ms=st["mean_latency_ms"],
+        mean_iterations=st["iterations"] / max(1, st["completed"]), statuses=statuses,
+        hbm_peak_bytes=st["hbm_peak"], workers=workers, max_slots=slots, hbm_budget_bytes=budget)
+
+
 def cpu_baseline(prob):
     """The oracle as it stands, on one IPM iteration of the same problem
     (its setup and initial point are not timed)."""
@@ -123,6 +162,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--served", type=int, default=1000,
+                    help="requests in the served-form measurement (MPC stream at 2000/s); 0 = skip")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run the reference copy kernel (for byte-counter scaling)")
     args = ap.parse_args()
@@ -146,6 +187,7 @@ def main():
         other["roofline"] = r["roofline"]
         other["objective_rel_diff_vs_main"] = abs(r["objective"] - main_run["objective"]) / max(
             1.0, abs(main_run["objective"]))
+    served = run_served(args.served) if args.served > 0 else None
     if args.calibrate_copy:
         calibrate_copy()
     cpu = None if args.no_cpu_baseline else cpu_baseline(prob)
@@ -176,6 +218,7 @@ def main():
         "ir_solves_per_iteration": main_run["ir_solves_per_iteration"],
         "roofline": main_run["roofline"],
         "alt_precision": other,
+        "served": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

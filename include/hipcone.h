@@ -47,6 +47,9 @@ extern "C" {
 #define HC_ERR_DEVICE      (-7)  /* a HIP runtime call failed                       */
 #define HC_ERR_STATE       (-8)  /* call out of order (e.g. solve before bind)      */
 #define HC_ERR_UNSUPPORTED (-9)  /* problem shape this build does not handle        */
+#define HC_ERR_TOO_LARGE   (-10) /* server: one problem's workspace exceeds the
+                                    whole HBM budget                               */
+#define HC_PENDING         1     /* server: the ticket's solve has not finished    */
 
 /* ---- cone list (Sec. 2.1) ------------------------------------------------ */
 #define HC_CONE_ZERO   0   /* {0}^dim                                          */
@@ -128,6 +131,7 @@ typedef struct {
 #define HC_STATUS_MAX_ITER              4
 #define HC_STATUS_INSUFFICIENT_PROGRESS 5
 #define HC_STATUS_NUMERICAL_ERROR       6
+#define HC_STATUS_CANCELLED             7   /* server destroyed before the solve ended */
 
 typedef struct {
   int32_t status;          /* HC_STATUS_*                                          */
@@ -238,6 +242,73 @@ int32_t hc_test_cone_step(int32_t type, int64_t count, int32_t dim, const double
  * NULL. */
 int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, double* A, int32_t nrhs,
                                  double* B, int64_t* guard_hits, void* stream);
+
+/* ---- served form --------------------------------------------------------
+ * Continuous batching of many independent problems on one GPU (the paper's
+ * parametric re-solve setting, Sec. 4.3, served as a request stream).
+ * Requests are analysed on the submitting thread (as hc_setup: the problem is
+ * copied, the caller may free it on return), queued first in first out, and
+ * admitted into active slots while their device workspace fits the HBM
+ * budget; the server allocates one device pool of hbm_budget_bytes at
+ * creation and carves every workspace from it.  `workers` host threads each
+ * own a stream and a share of the slots; a tick advances each of a worker's
+ * problems by one interior-point iteration, so problems of uneven size
+ * interleave and a finished problem's slot and memory go to the next request.
+ * A server handle is internally locked: submit, poll, wait and stats may be
+ * called from any thread. */
+typedef struct {
+  size_t hbm_budget_bytes;  /* device pool for all active workspaces (64 GiB)      */
+  int32_t max_slots;        /* problems in flight at most (64)                     */
+  int32_t workers;          /* host threads / streams, 1..16 (4)                   */
+  hc_settings settings;     /* applied to every problem (hc_settings_default)     */
+  int32_t device;           /* HIP device ordinal (0)                              */
+} hc_server_config;
+
+typedef struct {
+  /* filled by hc_server_poll / hc_server_wait */
+  uint64_t tag;             /* as given to hc_server_submit                       */
+  int32_t status;           /* HC_STATUS_*                                         */
+  int32_t error;            /* HC_OK, or the error code that ended the solve     */
+  int32_t iterations;
+  double obj_primal, obj_dual, res_primal, res_dual;
+  double queue_ms;          /* submit -> admitted                                 */
+  double solve_ms;          /* admitted -> finished                               */
+  double latency_ms;        /* submit -> finished                                 */
+  int64_t n, m;
+  /* set by the caller before poll/wait: host buffers of n, m, m doubles that
+     receive x, s, z (user row order, unscaled, divided by tau), or NULL */
+  double* x;
+  double* s;
+  double* z;
+} hc_result;
+
+typedef struct {
+  int64_t submitted, completed, rejected, cancelled, active, pending, iterations;
+  double p50_latency_ms, p99_latency_ms, mean_latency_ms;
+  double solves_per_s;      /* completed / (last completion - first submission)   */
+  double busy_ms;           /* summed tick time of the workers                    */
+  size_t hbm_in_use, hbm_peak;
+} hc_server_report;
+
+typedef struct hc_server hc_server;
+
+/* Defaults listed above.  HC_ERR_INVALID_ARG on NULL. */
+int32_t hc_server_config_default(hc_server_config* out);
+/* Creates the pool and the workers.  HC_ERR_INVALID_ARG (bad config),
+ * HC_ERR_DEVICE, HC_ERR_OOM (pool allocation failed). */
+int32_t hc_server_create(hc_server** out, const hc_server_config* cfg);
+/* Validates and analyses `p` (errors as hc_setup; HC_ERR_TOO_LARGE when its
+ * workspace exceeds the budget) and queues it; *ticket identifies it. */
+int32_t hc_server_submit(hc_server* s, const hc_problem* p, uint64_t tag, uint64_t* ticket);
+/* HC_PENDING while the solve runs; HC_OK once `out` is filled (the ticket is
+ * then retired); HC_ERR_INVALID_ARG for an unknown or retired ticket. */
+int32_t hc_server_poll(hc_server* s, uint64_t ticket, hc_result* out);
+/* Blocks until the ticket's solve has finished, then as hc_server_poll. */
+int32_t hc_server_wait(hc_server* s, uint64_t ticket, hc_result* out);
+int32_t hc_server_stats(hc_server* s, hc_server_report* out);
+/* Stops the workers (problems still queued or active end as
+ * HC_STATUS_CANCELLED), frees the pool.  NULL is a no-op. */
+void hc_server_destroy(hc_server* s);
 
 /* Plain device-to-device copy of `bytes` bytes (src, dst: device, 16-byte
  * aligned, bytes a multiple of 16; HC_ERR_INVALID_ARG otherwise), run to

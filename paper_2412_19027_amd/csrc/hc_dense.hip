@@ -388,15 +388,16 @@ void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix
   // waits for that U2; U2 waits for panel k to be factored.
   aux->init();
   aux->used = 0;
+  const int64_t W = std::max<int64_t>(BS, aux->nb / BS * BS);   // panel width
   hipEvent_t start = aux->next();
   HC_HIP(hipEventRecord(start, st));
   HC_HIP(hipStreamWaitEvent(aux->side, start, 0));
   hipEvent_t u2_done = nullptr;
-  for (int64_t K0 = 0; K0 < n; K0 += NB) {
-    const int64_t Kend = std::min<int64_t>(n, K0 + NB);
+  for (int64_t K0 = 0; K0 < n; K0 += W) {
+    const int64_t Kend = std::min<int64_t>(n, K0 + W);
     factor_panel<T>(S, n, ld, Linv, tol, fix, hits, K0, Kend, st, prof);
     if (Kend >= n) break;
-    const int64_t K1 = std::min<int64_t>(n, Kend + NB);
+    const int64_t K1 = std::min<int64_t>(n, Kend + W);
     if (K1 < n) {
       hipEvent_t factored = aux->next();
       HC_HIP(hipEventRecord(factored, st));

@@ -1,0 +1,386 @@
+// Served form: continuous batching of many independent problems on one GPU.
+//
+// Requests are validated and analysed on the submitting thread (hc_setup),
+// queued first-in first-out, and admitted into active slots while their
+// device workspace fits the HBM budget; the workspace is carved from one
+// device pool allocated at creation, so admission and retirement never call
+// hipMalloc or hipFree.  Worker threads each own a stream (default priority)
+// and a share of the slots; every tick advances each of a worker's active
+// problems by one pass of the loop body of Algorithm 1, so short and long
+// solves interleave and a finished problem frees its slot and memory for the
+// next request at the following tick.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "hc_steps.h"
+#include "hipcone.h"
+
+namespace {
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Job {
+  uint64_t ticket = 0, tag = 0;
+  hc_solver* h = nullptr;
+  size_t bytes = 0, offset = 0;
+  int64_t n = 0, m = 0;
+  double t_submit = 0, t_start = 0, t_end = 0;
+  int32_t status = HC_STATUS_UNSOLVED;
+  int32_t error = HC_OK;
+  hc_info info{};
+  std::vector<double> x, s, z;
+  bool finished = false;
+};
+
+// first-fit allocator over [0, size) with coalescing, 256-byte granules
+struct Pool {
+  size_t size = 0;
+  std::map<size_t, size_t> free_;   // offset -> bytes
+  void init(size_t bytes) {
+    size = bytes;
+    free_.clear();
+    if (bytes) free_[0] = bytes;
+  }
+  static size_t round(size_t b) { return (std::max<size_t>(b, 1) + 255) / 256 * 256; }
+  bool take(size_t bytes, size_t* off) {
+    bytes = round(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t o = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[o] = rest;
+        return true;
+      }
+    return false;
+  }
+  void give(size_t off, size_t bytes) {
+    bytes = round(bytes);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+}  // namespace
+
+struct hc_server {
+  hc_server_config cfg{};
+  char* pool_base = nullptr;
+  Pool pool;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::deque<std::shared_ptr<Job>> pending;
+  std::unordered_map<uint64_t, std::shared_ptr<Job>> jobs;   // submitted, not yet collected
+  std::vector<std::thread> workers;
+  // statistics
+  size_t in_use = 0, peak = 0;
+  int64_t submitted = 0, completed = 0, rejected = 0, cancelled = 0, iterations = 0, active = 0;
+  std::vector<double> latencies;
+  double t_first = -1, t_last = 0, busy_ms = 0;
+
+  void worker(int w, int cap);
+  void finish(const std::shared_ptr<Job>& j, int32_t rc, hipStream_t st);
+};
+
+void hc_server::finish(const std::shared_ptr<Job>& j, int32_t rc, hipStream_t st) {
+  (void)st;
+  if (j->h) {
+    if (rc == HC_OK) rc = hc::solver_finish(j->h);
+    hc_get_info(j->h, &j->info);
+    if (rc == HC_OK) {
+      j->x.resize(j->n);
+      j->s.resize(j->m);
+      j->z.resize(j->m);
+      rc = hc_get_solution(j->h, j->x.data(), j->s.data(), j->z.data());
+    }
+    hc_destroy(j->h);
+    j->h = nullptr;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  j->error = rc;
+  j->status = rc == HC_OK ? j->info.status : HC_STATUS_NUMERICAL_ERROR;
+  j->t_end = now_ms();
+  j->finished = true;
+  pool.give(j->offset, j->bytes);
+  in_use -= Pool::round(j->bytes);
+  active--;
+  completed++;
+  iterations += j->info.iterations;
+  latencies.push_back(j->t_end - j->t_submit);
+  t_last = j->t_end;
+  cv_done.notify_all();
+  cv_work.notify_all();
+}
+
+void hc_server::worker(int w, int cap) {
+  (void)w;
+  (void)hipSetDevice(cfg.device);
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+  std::vector<std::shared_ptr<Job>> mine, fresh;
+  for (;;) {
+    fresh.clear();
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      auto admissible = [&]() {
+        if (pending.empty() || (int)mine.size() >= cap) return false;
+        size_t off = 0;
+        if (!pool.take(pending.front()->bytes, &off)) return false;
+        pool.give(off, pending.front()->bytes);
+        return true;
+      };
+      while (!stop && mine.empty() && !admissible()) cv_work.wait(lk);
+      if (stop) break;
+      while ((int)mine.size() < cap && !pending.empty()) {
+        auto j = pending.front();
+        size_t off = 0;
+        if (!pool.take(j->bytes, &off)) break;   // first in, first out: wait for memory
+        pending.pop_front();
+        j->offset = off;
+        in_use += Pool::round(j->bytes);
+        peak = std::max(peak, in_use);
+        active++;
+        mine.push_back(j);
+        fresh.push_back(j);
+      }
+    }
+    for (auto& j : fresh) {
+      hc_device dev{pool_base + j->offset, Pool::round(j->bytes), st, cfg.device};
+      j->t_start = now_ms();
+      int32_t rc = hc_bind(j->h, &dev);
+      if (rc == HC_OK) rc = hc::solver_begin(j->h);
+      if (rc != HC_OK) {
+        finish(j, rc, st);
+        mine.erase(std::find(mine.begin(), mine.end(), j));
+      }
+    }
+    // one tick: every active problem advances by one iteration
+    const double t0 = now_ms();
+    for (size_t i = 0; i < mine.size();) {
+      int done = 0;
+      const int32_t rc = hc::solver_step(mine[i]->h, &done);
+      if (rc != HC_OK || done) {
+        finish(mine[i], rc, st);
+        mine.erase(mine.begin() + (long)i);
+      } else {
+        ++i;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      busy_ms += now_ms() - t0;
+    }
+  }
+  // shutting down: cancel what this worker still holds
+  for (auto& j : mine) {
+    (void)hipStreamSynchronize(st);
+    hc_destroy(j->h);
+    j->h = nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    j->status = HC_STATUS_CANCELLED;
+    j->finished = true;
+    j->t_end = now_ms();
+    pool.give(j->offset, j->bytes);
+    in_use -= Pool::round(j->bytes);
+    active--;
+    cancelled++;
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipStreamDestroy(st);
+}
+
+namespace {
+
+void fill_result(const Job& j, hc_result* out) {
+  out->tag = j.tag;
+  out->status = j.status;
+  out->error = j.error;
+  out->iterations = j.info.iterations;
+  out->obj_primal = j.info.obj_primal;
+  out->obj_dual = j.info.obj_dual;
+  out->res_primal = j.info.res_primal;
+  out->res_dual = j.info.res_dual;
+  out->queue_ms = j.t_start > 0 ? j.t_start - j.t_submit : j.t_end - j.t_submit;
+  out->solve_ms = j.t_start > 0 ? j.t_end - j.t_start : 0.0;
+  out->latency_ms = j.t_end - j.t_submit;
+  out->n = j.n;
+  out->m = j.m;
+  if (out->x && !j.x.empty()) std::memcpy(out->x, j.x.data(), j.x.size() * sizeof(double));
+  if (out->s && !j.s.empty()) std::memcpy(out->s, j.s.data(), j.s.size() * sizeof(double));
+  if (out->z && !j.z.empty()) std::memcpy(out->z, j.z.data(), j.z.size() * sizeof(double));
+}
+
+double percentile(std::vector<double> v, double p) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  const double r = p * (double)(v.size() - 1);
+  const size_t i = (size_t)r;
+  const double f = r - (double)i;
+  return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t hc_server_config_default(hc_server_config* c) {
+  if (!c) return HC_ERR_INVALID_ARG;
+  std::memset(c, 0, sizeof(*c));
+  c->hbm_budget_bytes = (size_t)64 << 30;
+  c->max_slots = 64;
+  c->workers = 4;
+  c->device = 0;
+  return hc_settings_default(&c->settings);
+}
+
+int32_t hc_server_create(hc_server** out, const hc_server_config* cfg) {
+  if (!out || !cfg) return HC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (cfg->max_slots < 1 || cfg->workers < 1 || cfg->workers > 16 || cfg->hbm_budget_bytes < 4096)
+    return HC_ERR_INVALID_ARG;
+  std::unique_ptr<hc_server> s(new hc_server());
+  s->cfg = *cfg;
+  if (hipSetDevice(cfg->device) != hipSuccess) return HC_ERR_DEVICE;
+  void* p = nullptr;
+  if (hipMalloc(&p, cfg->hbm_budget_bytes) != hipSuccess) return HC_ERR_OOM;
+  s->pool_base = (char*)p;
+  s->pool.init(cfg->hbm_budget_bytes / 256 * 256);
+  const int nw = std::min(cfg->workers, cfg->max_slots);
+  for (int w = 0; w < nw; ++w) {
+    const int cap = cfg->max_slots / nw + (w < cfg->max_slots % nw ? 1 : 0);
+    s->workers.emplace_back(&hc_server::worker, s.get(), w, cap);
+  }
+  *out = s.release();
+  return HC_OK;
+}
+
+int32_t hc_server_submit(hc_server* s, const hc_problem* p, uint64_t tag, uint64_t* ticket) {
+  if (!s || !p || !ticket) return HC_ERR_INVALID_ARG;
+  const double t = now_ms();
+  hc_solver* h = nullptr;
+  int32_t rc = hc_setup(&h, p, &s->cfg.settings);
+  size_t bytes = 0;
+  if (rc == HC_OK) rc = hc_workspace_bytes(h, &bytes);
+  if (rc == HC_OK && Pool::round(bytes) > s->pool.size) rc = HC_ERR_TOO_LARGE;
+  if (rc != HC_OK) {
+    hc_destroy(h);
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->rejected++;
+    return rc;
+  }
+  auto j = std::make_shared<Job>();
+  j->tag = tag;
+  j->h = h;
+  j->bytes = bytes;
+  j->n = p->n;
+  j->m = p->m;
+  j->t_submit = t;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) {
+    hc_destroy(h);
+    return HC_ERR_STATE;
+  }
+  j->ticket = s->next_ticket++;
+  *ticket = j->ticket;
+  s->jobs[j->ticket] = j;
+  s->pending.push_back(j);
+  s->submitted++;
+  if (s->t_first < 0) s->t_first = t;
+  s->cv_work.notify_all();
+  return HC_OK;
+}
+
+int32_t hc_server_poll(hc_server* s, uint64_t ticket, hc_result* out) {
+  if (!s || !out) return HC_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return HC_ERR_INVALID_ARG;
+  if (!it->second->finished) return HC_PENDING;
+  fill_result(*it->second, out);
+  s->jobs.erase(it);
+  return HC_OK;
+}
+
+int32_t hc_server_wait(hc_server* s, uint64_t ticket, hc_result* out) {
+  if (!s || !out) return HC_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return HC_ERR_INVALID_ARG;
+  std::shared_ptr<Job> j = it->second;
+  s->cv_done.wait(lk, [&] { return j->finished || s->stop; });
+  if (!j->finished) return HC_ERR_STATE;
+  fill_result(*j, out);
+  s->jobs.erase(ticket);
+  return HC_OK;
+}
+
+int32_t hc_server_stats(hc_server* s, hc_server_report* out) {
+  if (!s || !out) return HC_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->rejected = s->rejected;
+  out->cancelled = s->cancelled;
+  out->active = s->active;
+  out->pending = (int64_t)s->pending.size();
+  out->iterations = s->iterations;
+  out->hbm_in_use = s->in_use;
+  out->hbm_peak = s->peak;
+  out->p50_latency_ms = percentile(s->latencies, 0.50);
+  out->p99_latency_ms = percentile(s->latencies, 0.99);
+  double sum = 0;
+  for (double v : s->latencies) sum += v;
+  out->mean_latency_ms = s->latencies.empty() ? 0.0 : sum / (double)s->latencies.size();
+  const double span = s->t_last - s->t_first;
+  out->solves_per_s = (s->completed > 0 && span > 0) ? 1e3 * (double)s->completed / span : 0.0;
+  out->busy_ms = s->busy_ms;
+  return HC_OK;
+}
+
+void hc_server_destroy(hc_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+  }
+  for (auto& t : s->workers) t.join();
+  for (auto& j : s->pending) {
+    hc_destroy(j->h);
+    j->h = nullptr;
+  }
+  (void)hipFree(s->pool_base);
+  delete s;
+}
+
+}  // extern "C"

@@ -134,6 +134,8 @@ struct hc_solver {
   std::unique_ptr<Prof> prof;
   Aux aux;   // side stream + events of the look-ahead factorisation
   bool use64 = false;               // mixed mode: this iteration fell back to the FP64 factor
+  int kiter = 0;                    // loop counter of the current solve
+  double t_begin = 0;               // host clock at the start of the solve
   std::string last_error;
 };
 
@@ -1262,7 +1264,7 @@ int iterate(hc_solver* S, const Resid& R) {
   return 0;
 }
 
-void run_solve(hc_solver* S) {
+void begin_solve(hc_solver* S) {
   const hc_info keep = S->info;
   S->info = hc_info{};
   S->info.setup_ms = keep.setup_ms;
@@ -1273,32 +1275,46 @@ void run_solve(hc_solver* S) {
   HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), S->stream));
   init_point(S);
   S->status = 0;
-  for (int k = 0; k <= S->st.max_iter; ++k) {
-    const Resid R = residuals(S);
-    S->xPx_cache = R.xPx;
-    int status = check(S, R);
-    S->info.mu = (R.sz + S->kappa * S->tau) / (double)(S->nu + 1);
-    if (S->st.verbose)
-      std::printf("%3d gp=%+.8e gd=%+.8e rp=%.2e rd=%.2e mu=%.2e tau=%.3e\n", k, S->info.obj_primal,
-                  S->info.obj_dual, S->info.res_primal, S->info.res_dual, S->info.mu, S->tau);
-    if (status) {
-      S->status = status;
-      break;
-    }
-    if (k == S->st.max_iter) {
-      S->status = HC_STATUS_MAX_ITER;
-      break;
-    }
+  S->kiter = 0;
+}
+
+// one pass of the loop body of Algorithm 1 (residuals, termination tests,
+// one iteration); true when the solve has ended
+bool step_solve(hc_solver* S) {
+  const int k = S->kiter;
+  const Resid R = residuals(S);
+  S->xPx_cache = R.xPx;
+  int status = check(S, R);
+  S->info.mu = (R.sz + S->kappa * S->tau) / (double)(S->nu + 1);
+  if (S->st.verbose)
+    std::printf("%3d gp=%+.8e gd=%+.8e rp=%.2e rd=%.2e mu=%.2e tau=%.3e\n", k, S->info.obj_primal, S->info.obj_dual,
+                S->info.res_primal, S->info.res_dual, S->info.mu, S->tau);
+  bool done = false;
+  if (status) {
+    S->status = status;
+    done = true;
+  } else if (k == S->st.max_iter) {
+    S->status = HC_STATUS_MAX_ITER;
+    done = true;
+  } else {
     status = iterate(S, R);
     S->info.iterations++;
     if (status) {
       S->status = status;
       const Resid R2 = residuals(S);
       check(S, R2);
-      break;
+      done = true;
     }
   }
+  S->kiter++;
   S->info.status = S->status;
+  return done;
+}
+
+void run_solve(hc_solver* S) {
+  begin_solve(S);
+  while (!step_solve(S)) {
+  }
 }
 
 // every device allocation of a solver, in order (dry run: byte count only)
@@ -1434,6 +1450,55 @@ void bind(hc_solver* S, const hc_device* dev) {
 void record(hc_solver* S, const Error& e) { S->last_error = e.msg; }
 
 }  // namespace
+
+// ===========================================================================
+// step-wise driving (continuous-batching server)
+// ===========================================================================
+namespace hc {
+
+int32_t solver_begin(hc_solver* S) {
+  if (!S || !S->bound) return HC_ERR_STATE;
+  try {
+    HC_HIP(hipSetDevice(S->device));
+    S->t_begin = now_ms();
+    begin_solve(S);
+  } catch (const Error& e) {
+    record(S, e);
+    return e.code;
+  }
+  return HC_OK;
+}
+
+int32_t solver_step(hc_solver* S, int* done) {
+  if (!S || !S->bound || !done) return HC_ERR_STATE;
+  try {
+    HC_HIP(hipSetDevice(S->device));
+    *done = step_solve(S) ? 1 : 0;
+  } catch (const Error& e) {
+    record(S, e);
+    *done = 1;
+    return e.code;
+  }
+  return HC_OK;
+}
+
+int32_t solver_finish(hc_solver* S) {
+  if (!S || !S->bound) return HC_ERR_STATE;
+  try {
+    HC_HIP(hipSetDevice(S->device));
+    HC_HIP(hipStreamSynchronize(S->stream));
+    S->info.solve_ms = now_ms() - S->t_begin;
+    unsigned long long h = 0;
+    HC_HIP(hipMemcpy(&h, S->dhits, sizeof(h), hipMemcpyDeviceToHost));
+    S->info.pivot_guard_hits = (int64_t)h;
+  } catch (const Error& e) {
+    record(S, e);
+    return e.code;
+  }
+  return HC_OK;
+}
+
+}  // namespace hc
 
 // ===========================================================================
 // C-ABI
@@ -1605,6 +1670,7 @@ const char* hc_status_str(int32_t status) {
     case HC_STATUS_MAX_ITER: return "max_iter";
     case HC_STATUS_INSUFFICIENT_PROGRESS: return "insufficient_progress";
     case HC_STATUS_NUMERICAL_ERROR: return "numerical_error";
+    case HC_STATUS_CANCELLED: return "cancelled";
   }
   return "unknown";
 }

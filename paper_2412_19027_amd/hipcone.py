@@ -18,12 +18,13 @@ LIB_PATH = os.path.join(_PKG, "libhipcone.so")
 ZERO, NONNEG, SOC, EXP, POW, PSD = 0, 1, 2, 3, 4, 5
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 STATUS = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasible", 4: "max_iter",
-          5: "insufficient_progress", 6: "numerical_error"}
+          5: "insufficient_progress", 6: "numerical_error", 7: "cancelled"}
 
 EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "hc_solve", "hc_get_info",
            "hc_get_solution", "hc_get_iterate", "hc_destroy", "hc_last_error", "hc_status_str",
            "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_dense_chol_solve",
-           "hc_test_copy"]
+           "hc_test_copy", "hc_server_config_default", "hc_server_create", "hc_server_submit", "hc_server_poll",
+           "hc_server_wait", "hc_server_stats", "hc_server_destroy"]
 
 
 class hc_cone(C.Structure):
@@ -64,6 +65,30 @@ class hc_info(C.Structure):
                 ("fp64_fallbacks", C.c_int64), ("n_leaves", C.c_int64), ("leaf_columns", C.c_int64)]
 
 
+class hc_server_config(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("workers", C.c_int32),
+                ("settings", hc_settings), ("device", C.c_int32)]
+
+
+class hc_result(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int32), ("error", C.c_int32), ("iterations", C.c_int32),
+                ("obj_primal", C.c_double), ("obj_dual", C.c_double), ("res_primal", C.c_double),
+                ("res_dual", C.c_double), ("queue_ms", C.c_double), ("solve_ms", C.c_double),
+                ("latency_ms", C.c_double), ("n", C.c_int64), ("m", C.c_int64),
+                ("x", C.POINTER(C.c_double)), ("s", C.POINTER(C.c_double)), ("z", C.POINTER(C.c_double))]
+
+
+class hc_server_report(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("cancelled", C.c_int64), ("active", C.c_int64), ("pending", C.c_int64), ("iterations", C.c_int64),
+                ("p50_latency_ms", C.c_double), ("p99_latency_ms", C.c_double), ("mean_latency_ms", C.c_double),
+                ("solves_per_s", C.c_double), ("busy_ms", C.c_double), ("hbm_in_use", C.c_size_t),
+                ("hbm_peak", C.c_size_t)]
+
+
+HC_PENDING = 1
+ERR_TOO_LARGE = -10
+
 _lib = None
 
 
@@ -94,6 +119,14 @@ def lib():
         L.hc_test_cone_step.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, dbl, vp, vp]
         L.hc_test_dense_chol_solve.argtypes = [i32, i64, i64, vp, i32, vp, C.POINTER(i64), vp]
         L.hc_test_copy.argtypes = [vp, vp, i64, vp]
+        L.hc_server_config_default.argtypes = [C.POINTER(hc_server_config)]
+        L.hc_server_create.argtypes = [C.POINTER(vp), C.POINTER(hc_server_config)]
+        L.hc_server_submit.argtypes = [vp, C.POINTER(hc_problem), C.c_uint64, C.POINTER(C.c_uint64)]
+        L.hc_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(hc_result)]
+        L.hc_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(hc_result)]
+        L.hc_server_stats.argtypes = [vp, C.POINTER(hc_server_report)]
+        L.hc_server_destroy.argtypes = [vp]
+        L.hc_server_destroy.restype = None
         for name in EXPORTS:
             getattr(L, name)
         _lib = L
@@ -107,7 +140,9 @@ class HipconeError(RuntimeError):
 def _check(rc, handle=None):
     if rc != 0:
         msg = lib().hc_last_error(handle).decode(errors="replace")
-        raise HipconeError(f"hipcone error {rc}: {msg}")
+        err = HipconeError(f"hipcone error {rc}: {msg}")
+        err.code = rc
+        raise err
 
 
 def default_settings(**overrides) -> hc_settings:
@@ -124,9 +159,8 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
 
 
-def _setup(prob, settings):
-    """hc_setup on the host: returns (handle, buffers kept alive for it)."""
-    L = lib()
+def _problem(prob):
+    """hc_problem view of a workloads.Problem: (struct, buffers kept alive for it)."""
     P = prob.P.tocsr()
     A = prob.A.tocsr()
     keep = dict(
@@ -140,8 +174,14 @@ def _setup(prob, settings):
     pr = hc_problem(prob.n, prob.m, _ptr(k["Prp"], C.c_int64), _ptr(k["Pci"], C.c_int32), _ptr(k["Pv"], C.c_double),
                     _ptr(k["q"], C.c_double), _ptr(k["Arp"], C.c_int64), _ptr(k["Aci"], C.c_int32),
                     _ptr(k["Av"], C.c_double), _ptr(k["b"], C.c_double), cones, len(prob.cones))
+    return pr, keep
+
+
+def _setup(prob, settings):
+    """hc_setup on the host: returns (handle, buffers kept alive for it)."""
+    pr, keep = _problem(prob)
     h = C.c_void_p()
-    _check(L.hc_setup(C.byref(h), C.byref(pr), C.byref(settings)))
+    _check(lib().hc_setup(C.byref(h), C.byref(pr), C.byref(settings)))
     return h, keep
 
 
@@ -285,3 +325,70 @@ def test_copy(src, dst):
     nbytes = src.numel() * src.element_size()
     assert dst.numel() * dst.element_size() == nbytes
     _check(lib().hc_test_copy(_dptr(src), _dptr(dst), nbytes, _stream()))
+
+
+class Server:
+    """Continuous-batching server (hc_server_*): many problems in flight on one
+    GPU, admitted by device-memory footprint."""
+
+    def __init__(self, hbm_budget_bytes=64 << 30, max_slots=64, workers=4, device=0, **settings):
+        L = lib()
+        cfg = hc_server_config()
+        _check(L.hc_server_config_default(C.byref(cfg)))
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.max_slots = int(max_slots)
+        cfg.workers = int(workers)
+        cfg.device = int(device)
+        cfg.settings = default_settings(**settings)
+        self._h = C.c_void_p()
+        _check(L.hc_server_create(C.byref(self._h), C.byref(cfg)))
+        self._shapes = {}
+
+    def submit(self, prob, tag=0):
+        """Queues `prob` (copied); returns its ticket."""
+        pr, _keep = _problem(prob)
+        t = C.c_uint64()
+        _check(lib().hc_server_submit(self._h, C.byref(pr), int(tag), C.byref(t)))
+        self._shapes[t.value] = (prob.n, prob.m)
+        return t.value
+
+    def _result(self, fn, ticket, solution):
+        n, m = self._shapes[ticket]
+        r = hc_result()
+        bufs = None
+        if solution:
+            bufs = (np.zeros(n), np.zeros(m), np.zeros(m))
+            r.x, r.s, r.z = (_ptr(b, C.c_double) for b in bufs)
+        rc = fn(self._h, C.c_uint64(ticket), C.byref(r))
+        if rc == HC_PENDING:
+            return None
+        _check(rc)
+        del self._shapes[ticket]
+        out = {f: getattr(r, f) for f, _ in hc_result._fields_ if f not in ("x", "s", "z")}
+        out["status_name"] = STATUS.get(r.status, "unknown")
+        if solution:
+            out["x"], out["s"], out["z"] = bufs
+        return out
+
+    def poll(self, ticket, solution=False):
+        """Result dict once finished (the ticket is then retired), else None."""
+        return self._result(lib().hc_server_poll, ticket, solution)
+
+    def wait(self, ticket, solution=False):
+        return self._result(lib().hc_server_wait, ticket, solution)
+
+    def stats(self) -> dict:
+        r = hc_server_report()
+        _check(lib().hc_server_stats(self._h, C.byref(r)))
+        return {f: getattr(r, f) for f, _ in hc_server_report._fields_}
+
+    def close(self):
+        if self._h:
+            lib().hc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -25,6 +25,7 @@ CASES = {
     "sparse_socp_full_s0": lambda: W.sparse_socp(0),
     "psd_pow_full_s0": lambda: W.psd_pow(0),
     "logreg_exp_2k_s0": lambda: W.logreg_exp(0, samples=2000, features=50),
+    "logreg_exp_20k_s0": lambda: W.logreg_exp(0, samples=20000, features=100),
 }
 
 

@@ -75,3 +75,21 @@ def test_two_level_split_on_host():
     socp = W.sparse_socp(0, nx=600, rank=5, n_zero=150, n_nonneg=400, n_soc=500)
     s = hipcone.analyze(socp)                      # the dense factor rows touch every column
     assert s["n_ordered"] == socp.n and s["n_leaves"] == 0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors have the sizes the C compiler gives the header's structs."""
+    import ctypes as C
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include "hipcone.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n",'
+                   'sizeof(hc_settings), sizeof(hc_info), sizeof(hc_problem), sizeof(hc_device),'
+                   'sizeof(hc_server_config), sizeof(hc_result), sizeof(hc_server_report));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = [C.sizeof(t) for t in (hipcone.hc_settings, hipcone.hc_info, hipcone.hc_problem, hipcone.hc_device,
+                                  hipcone.hc_server_config, hipcone.hc_result, hipcone.hc_server_report)]
+    assert got == want

@@ -1,0 +1,56 @@
+"""GPU solves at the full workload sizes, through the C-ABI.
+
+Expected objectives come from tests/golden/oracle_objectives.json, written by
+tests/golden/make_golden.py with the CPU oracle only.  Where no oracle value
+exists at that size (the logistic-regression problem with 100,000 samples),
+the solution is checked against the termination tests themselves, evaluated
+on the user's data (self-certifying)."""
+import json
+import os
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2412_19027_amd import workloads as W  # noqa: E402
+from tests.test_gpu_solver import certify, gpu_solve  # noqa: E402
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_objectives.json")))
+
+
+def close(a, b, tol=1e-7):
+    return abs(a - b) <= tol * max(1.0, abs(b))
+
+
+@pytest.mark.parametrize("key,make", [("sparse_socp_full_s0", lambda: W.sparse_socp(0)),
+                                      ("psd_pow_full_s0", lambda: W.psd_pow(0))])
+def test_full_size_against_oracle_objective(key, make):
+    prob = make()
+    info, x, sv, z = gpu_solve(prob)
+    print(key, {k: info[k] for k in ("status_name", "iterations", "obj_primal", "n_ordered", "n_leaves")}, flush=True)
+    assert info["status_name"] == "solved", info
+    gp = certify(prob, x, sv, z)
+    assert close(gp, GOLD[key]["objective"]), (gp, GOLD[key]["objective"])
+
+
+def test_logreg_full_two_level_certified():
+    prob = W.logreg_exp(0)
+    info, x, sv, z = gpu_solve(prob)
+    print({k: info[k] for k in ("status_name", "iterations", "obj_primal", "n_ordered", "n_leaves")}, flush=True)
+    assert info["n_leaves"] == 100000 + 500 and info["n_ordered"] == 500
+    assert info["status_name"] == "solved", info
+    certify(prob, x, sv, z)
+
+
+def test_leaf_blocks_match_one_dense_block():
+    key = "logreg_exp_2k_s0"
+    prob = W.logreg_exp(0, samples=2000, features=50)
+    a, xa, sa, za = gpu_solve(prob)
+    b, xb, sb, zb = gpu_solve(prob, leaf_blocks=0)
+    assert a["n_leaves"] > 0 and b["n_leaves"] == 0
+    for info, x, sv, z in ((a, xa, sa, za), (b, xb, sb, zb)):
+        assert info["status_name"] == "solved", info
+        gp = certify(prob, x, sv, z)
+        assert close(gp, GOLD[key]["objective"]), (gp, GOLD[key]["objective"])
