@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace hc {
 
@@ -276,10 +277,141 @@ __global__ __launch_bounds__(256) void k_gemm_nt(T* __restrict__ C, int64_t ldc,
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 update kernel for K % 16 == 0: 256 x 128 tiles of 8 waves (4 x 2 wave
+// tiles of 64 x 64, two waves per SIMD), operand panels streamed straight from
+// global memory into a 3-stage LDS ring with global_load_lds_dwordx4 (no
+// staging registers), so two chunks are always in flight while the MFMAs of
+// the third run.  The operand reads from LDS are issued as inline asm with
+// explicit waits: the compiler treats the LDS DMA as a store that may alias
+// every LDS read and would otherwise wait for all outstanding DMA (including
+// the prefetches) before each read.
+// ---------------------------------------------------------------------------
+constexpr int DM = 256, DN = 128, DK = 16, DST = 3;
+#define HC_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+
+__device__ inline uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+__global__ __launch_bounds__(512) void k_gemm_nt_dma(double* __restrict__ C, int64_t ldc, const double* __restrict__ A,
+                                                     int64_t lda, const double* __restrict__ B, int64_t ldb, int64_t M,
+                                                     int64_t N, int64_t K, double alpha, int lower, int64_t gr,
+                                                     int64_t gc, int tiles_n) {
+  __shared__ double As[DST][DK][DM];
+  __shared__ double Bs[DST][DK][DN];
+  const int tile_m = blockIdx.x / tiles_n, tile_n = blockIdx.x % tiles_n;
+  const int64_t i_base = (int64_t)tile_m * DM, j_base = (int64_t)tile_n * DN;
+  if (lower && gr + i_base + DM - 1 < gc + j_base) return;   // tile strictly above the diagonal
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 3) * 64, wn = (wave >> 2) * 64;
+  v4d acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+  // lane l loads rows (2l, 2l+1) of a 128-row half panel; rows past the end
+  // repeat the last even pair (their products land in rows / columns that are
+  // never stored).  M, N >= 2 and even row offsets keep every load in bounds
+  // and 16-byte aligned.
+  const int64_t alast = (M - 2) & ~int64_t(1), blast = (N - 2) & ~int64_t(1);
+  const double* pa0 = A + std::min<int64_t>(i_base + 2 * lane, alast);
+  const double* pa1 = A + std::min<int64_t>(i_base + 128 + 2 * lane, alast);
+  const double* pb = B + std::min<int64_t>(j_base + 2 * lane, blast);
+  const int nk = (int)(K / DK);
+  auto issue = [&](int kc, int stg) {   // wave w fills k-rows 2w and 2w + 1 of the chunk
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = wave * 2 + e;
+      const int64_t gk = (int64_t)kc * DK + k;
+      __builtin_amdgcn_global_load_lds((const void*)(pa0 + gk * lda), HC_LDS_PTR(&As[stg][k][0]), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(pa1 + gk * lda), HC_LDS_PTR(&As[stg][k][128]), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(pb + gk * ldb), HC_LDS_PTR(&Bs[stg][k][0]), 16, 0, 0);
+    }
+  };
+  const uint32_t a_off = lds_addr(&As[0][lane >> 4][wm + (lane & 15)]);
+  const uint32_t b_off = lds_addr(&Bs[0][lane >> 4][wn + (lane & 15)]);
+  constexpr uint32_t SA = DK * DM * 8, SB_ = DK * DN * 8;
+  issue(0, 0);
+  if (nk > 1) issue(1, 1);
+  for (int kc = 0; kc < nk; ++kc) {
+    // each wave has 6 loads per chunk in flight: vmcnt(6) leaves only the
+    // next chunk outstanding, i.e. chunk kc has landed
+    if (kc + 1 < nk) __builtin_amdgcn_s_waitcnt(0xF76);
+    else __builtin_amdgcn_s_waitcnt(0xF70);
+    __builtin_amdgcn_s_barrier();
+    if (kc + 2 < nk) issue(kc + 2, (kc + 2) % DST);   // that stage was last read before this barrier
+    const int stg = kc % DST;
+    const uint32_t sa = a_off + stg * SA, sb = b_off + stg * SB_;
+#pragma unroll
+    for (int kk = 0; kk < DK; kk += 4) {
+      double a0, a1, a2, a3, b0, b1, b2, b3;
+      const uint32_t ra = sa + kk * DM * 8, rb = sb + kk * DN * 8;
+      asm volatile("ds_read_b64 %0, %1 offset:0" : "=v"(a0) : "v"(ra));
+      asm volatile("ds_read_b64 %0, %1 offset:128" : "=v"(a1) : "v"(ra));
+      asm volatile("ds_read_b64 %0, %1 offset:256" : "=v"(a2) : "v"(ra));
+      asm volatile("ds_read_b64 %0, %1 offset:384" : "=v"(a3) : "v"(ra));
+      asm volatile("ds_read_b64 %0, %1 offset:0" : "=v"(b0) : "v"(rb));
+      asm volatile("ds_read_b64 %0, %1 offset:128" : "=v"(b1) : "v"(rb));
+      asm volatile("ds_read_b64 %0, %1 offset:256" : "=v"(b2) : "v"(rb));
+      asm volatile("ds_read_b64 %0, %1 offset:384" : "=v"(b3) : "v"(rb));
+      asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(b0), "+v"(b1), "+v"(b2),
+                   "+v"(b3));
+      const double ao[4] = {a0, a1, a2, a3}, bo[4] = {b0, b1, b2, b3};
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<double>::op(ao[a], bo[b], acc[a][b]);
+    }
+  }
+  // epilogue: C loads of half a wave tile issued together (clamped addresses),
+  // stores predicated
+#pragma unroll
+  for (int h = 0; h < 4; h += 2) {
+    double cv[2][4][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t j = std::min<int64_t>(j_base + wn + b * 16 + (lane & 15), N - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = std::min<int64_t>(i_base + wm + (h + a) * 16 + Mfma<double>::row(lane, r), M - 1);
+          cv[a][b][r] = C[i + j * ldc];
+        }
+      }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t j = j_base + wn + b * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = i_base + wm + (h + a) * 16 + Mfma<double>::row(lane, r);
+          if (i < M && j < N) C[i + j * ldc] = cv[a][b][r] + alpha * acc[h + a][b][r];
+        }
+      }
+  }
+}
+
+static bool dma_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t M, int64_t N, int64_t K) {
+  return K % DK == 0 && M >= 2 && N >= 2 && lda % 2 == 0 && ldb % 2 == 0 && ((uintptr_t)A % 16) == 0 &&
+         ((uintptr_t)B % 16) == 0;
+}
+
 template <typename T>
 void gemm_nt(T* C, int64_t ldc, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t M, int64_t N, int64_t K,
              T alpha, bool lower, int64_t gr, int64_t gc, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return;
+  if constexpr (std::is_same<T, double>::value) {
+    if (dma_ok(A, lda, B, ldb, M, N, K)) {
+      const int tm = (int)ceil_div(M, DM), tn = (int)ceil_div(N, DN);
+      hipLaunchKernelGGL(k_gemm_nt_dma, dim3(tm * tn), dim3(512), 0, st, C, ldc, A, lda, B, ldb, M, N, K, alpha,
+                         lower ? 1 : 0, gr, gc, tn);
+      HC_LAUNCH_CHECK();
+      return;
+    }
+  }
   const int tm = (int)ceil_div(M, TM), tn = (int)ceil_div(N, TN);
   hipLaunchKernelGGL(k_gemm_nt<T>, dim3(tm * tn), dim3(256), 0, st, C, ldc, A, lda, B, ldb, M, N, K, alpha,
                      lower ? 1 : 0, gr, gc, tn);
@@ -373,6 +505,7 @@ static void factor_panel(T* S, int64_t n, int64_t ld, T* Linv, double tol, doubl
 template <typename T>
 void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
                     hipStream_t st, Prof* prof, Aux* aux) {
+  if (n <= 0) return;
   if (!aux) {
     for (int64_t K0 = 0; K0 < n; K0 += NB) {
       const int64_t Kend = std::min<int64_t>(n, K0 + NB);
@@ -498,6 +631,7 @@ int64_t inv256_elems(int64_t n) { return ceil_div(n, SB) * SB * SB; }
 
 template <typename T>
 void dense_block_inverses(const T* L, int64_t n, int64_t ld, const T* Linv, T* X, T* XT, hipStream_t st) {
+  if (n <= 0) return;
   hipLaunchKernelGGL(k_inv256<T>, dim3((unsigned)ceil_div(n, SB)), dim3(256), 0, st, L, ld, Linv, n, X, XT);
   HC_LAUNCH_CHECK();
 }
@@ -638,6 +772,7 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_update(const T* __restrict__ L
 template <typename T>
 void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT256, T* B, T* Y, T* X, int nrhs,
                  hipStream_t st) {
+  if (n <= 0) return;
   for (int64_t c = 0; c < n; c += SB) {
     const T* Xi = X256 + (c / SB) * SB * SB;
     hipLaunchKernelGGL(k_trsv_diag<T>, dim3(SB / DIAG_ROWS), dim3(256), 0, st, Xi, c, n, (const T*)B, Y, nrhs);

@@ -135,6 +135,7 @@ struct hc_solver {
   Aux aux;   // side stream + events of the look-ahead factorisation
   bool use64 = false;               // mixed mode: this iteration fell back to the FP64 factor
   int kiter = 0;                    // loop counter of the current solve
+  double sdiag_max = 0;             // mixed mode: max |S_ii| of the last FP32 factorisation
   double t_begin = 0;               // host clock at the start of the solve
   std::string last_error;
 };
@@ -783,13 +784,30 @@ void H_apply(hc_solver* S, int mode, const double* x, double* y) {
   for (auto& g : S->sdev) cone_apply(g, mode, S->delta, x, y, S->stream);
 }
 
-// factor the regularised KKT system at the current scaling (state + hdiag filled)
-void factor(hc_solver* S) {
+__global__ void k_get_diag(int64_t n, int64_t ld, const double* __restrict__ A, double* __restrict__ d) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = A[i + i * ld];
+}
+
+// factor the regularised KKT system at the current scaling (state + hdiag
+// filled).  FP64: delta = delta_s + delta_d max|K_ii| (the oracle's reading).
+// Mixed mode factors only the Schur complement in FP32 (the cone pivots
+// -(H_c + delta I) are inverted exactly in FP64), so the proportional term
+// takes max|S_ii| of the last FP32-factored S; `fp64` redoes the whole
+// factorisation with the FP64 regularisation (the refinement fallback).
+void factor(hc_solver* S, bool fp64 = false) {
   hipStream_t st = S->stream;
-  Red r(S, S->m);
-  r.maxabs(S->dhdiag);
-  const double hmax = r.run()[0];
-  S->delta = S->st.static_reg + S->st.dyn_reg * std::max(S->maxPdiag, hmax);
+  const bool low = S->mixed && !fp64;
+  if (low) {
+    S->delta = S->st.static_reg + S->st.dyn_reg * std::max(S->maxPdiag, S->sdiag_max);
+  } else {
+    Red r(S, S->m);
+    r.maxabs(S->dhdiag);
+    const double hmax = r.run()[0];
+    const double ds = S->mixed ? 1e-8 : S->st.static_reg;
+    const double dd = S->mixed ? std::ldexp(1.0, -104) : S->st.dyn_reg;
+    S->delta = ds + dd * std::max(S->maxPdiag, hmax);
+  }
   for (auto& g : S->sdev) cone_mblock(g, S->delta, st);
   const int64_t nt = S->nt;
   fill_lower_zero(nt, S->ld, S->dS, st);
@@ -810,9 +828,18 @@ void factor(hc_solver* S) {
   const double tol = 0.0;
   // leaves are factored in FP64 in both modes; their updates land in the tail
   leaf_factor(S->cm, tol, S->delta, S->dhits, st);
-  S->use64 = false;
+  S->use64 = !low;
   Prof* pf = S->st.profile ? S->prof.get() : nullptr;
-  if (S->mixed) {
+  if (low && nt > 0) {   // max |S_ii| for the next FP32 factorisation's delta
+    hipLaunchKernelGGL(k_get_diag, dim3((unsigned)ceil_div(nt, 256)), dim3(256), 0, st, nt, S->ld, S->dS, S->sb);
+    HC_LAUNCH_CHECK();
+    Red r(S, nt);
+    r.maxabs(S->sb);
+    S->sdiag_max = r.run()[0];
+  }
+  if (nt == 0) {
+    // every column sits in a leaf block: nothing dense to factor
+  } else if (low) {
     lower_to_f32(nt, S->ld, S->dS, S->dS32, st);
     dense_cholesky<float>(S->dS32, nt, S->ld, S->dLinv32, tol, S->delta, S->dhits, st, pf, &S->aux);
     dense_block_inverses<float>(S->dS32, nt, S->ld, S->dLinv32, S->dX256f, S->dXT256f, st);
@@ -833,9 +860,7 @@ void factor(hc_solver* S) {
 // mixed mode: factor the (still FP64) Schur complement in FP64 for the rest of
 // this iteration
 void fallback_fp64(hc_solver* S) {
-  dense_cholesky<double>(S->dS, S->nt, S->ld, S->dLinv, 0.0, S->delta, S->dhits, S->stream, nullptr, &S->aux);
-  dense_block_inverses<double>(S->dS, S->nt, S->ld, S->dLinv, S->dX256, S->dXT256, S->stream);
-  S->use64 = true;
+  factor(S, true);
   S->info.fp64_fallbacks++;
 }
 
@@ -852,7 +877,9 @@ void schur_solve(hc_solver* S, const double* u, double* x) {
     ut = S->uT;
     xt = S->xT;
   }
-  if (S->mixed && !S->use64) {
+  if (nt == 0) {
+    // all columns in leaf blocks
+  } else if (S->mixed && !S->use64) {
     RedOps ops{};
     ops.nops = 1;
     ops.op[0] = RedOp{RED_MAX_MUL, ut, nullptr, 0.0, nullptr};
@@ -968,6 +995,11 @@ int64_t kkt_solve_once(hc_solver* S, const double* r1, const double* r2, double*
   S->info.ir_solves += solves;
   *best_out = have_best ? best : NAN;
   *nb_out = nb;
+  if (S->st.verbose >= 2) {
+    std::printf("      kkt solve: |rhs| %.3e best residual %.3e (%s) solves %lld\n", nb, have_best ? best : NAN,
+                S->mixed && !S->use64 ? "fp32 factor" : "fp64 factor", (long long)solves);
+    std::fflush(stdout);
+  }
   return solves;
 }
 
@@ -1273,6 +1305,7 @@ void begin_solve(hc_solver* S) {
   S->info.leaf_columns = keep.leaf_columns;
   S->info.factor_flops = keep.factor_flops;
   HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), S->stream));
+  S->sdiag_max = 0;
   init_point(S);
   S->status = 0;
   S->kiter = 0;

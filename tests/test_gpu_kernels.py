@@ -29,7 +29,7 @@ def relerr(a, b):
 
 
 # ----------------------------------------------------------------- dense factor
-@pytest.mark.parametrize("n", [1, 37, 64, 200, 333, 700])
+@pytest.mark.parametrize("n", [1, 37, 64, 200, 333, 700, 1100, 2049])
 @pytest.mark.parametrize("nrhs", [1, 3])
 def test_dense_cholesky_fp64(n, nrhs):
     G = RNG.standard_normal((n, n))
@@ -43,7 +43,7 @@ def test_dense_cholesky_fp64(n, nrhs):
     assert relerr(Lh @ Lh.T, A) < 1e-13
 
 
-@pytest.mark.parametrize("n", [64, 300, 513])
+@pytest.mark.parametrize("n", [64, 300, 513, 1600])
 def test_dense_cholesky_fp32(n):
     G = RNG.standard_normal((n, n))
     A = G @ G.T + n * np.eye(n)
