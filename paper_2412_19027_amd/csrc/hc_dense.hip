@@ -394,6 +394,114 @@ __global__ __launch_bounds__(512) void k_gemm_nt_dma(double* __restrict__ C, int
   }
 }
 
+// FP32 counterpart (mixed mode): 32-deep chunks, so one k-row of the A panel
+// (256 floats) is one dwordx4 DMA, and one dwordx4 DMA fills two adjacent
+// k-rows of the B panel (128 floats each: lanes 0-31 the first, 32-63 the
+// second); each wave fills 4 k-rows per chunk (6 loads in flight).
+constexpr int FK = 32;
+__global__ __launch_bounds__(512) void k_gemm_nt_dma32(float* __restrict__ C, int64_t ldc, const float* __restrict__ A,
+                                                       int64_t lda, const float* __restrict__ B, int64_t ldb,
+                                                       int64_t M, int64_t N, int64_t K, float alpha, int lower,
+                                                       int64_t gr, int64_t gc, int tiles_n) {
+  __shared__ float As[DST][FK][DM];
+  __shared__ float Bs[DST][FK][DN];
+  const int tile_m = blockIdx.x / tiles_n, tile_n = blockIdx.x % tiles_n;
+  const int64_t i_base = (int64_t)tile_m * DM, j_base = (int64_t)tile_n * DN;
+  if (lower && gr + i_base + DM - 1 < gc + j_base) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 3) * 64, wn = (wave >> 2) * 64;
+  v4f acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0, 0, 0, 0};
+  // lane l loads rows 4l..4l+3 of A, and rows 4 (l % 32) .. + 3 of B for
+  // k-row (l / 32) of a pair; clamped to the last aligned group of four
+  // (M, N >= 4, 16-byte aligned columns)
+  const int64_t alast = (M - 4) & ~int64_t(3), blast = (N - 4) & ~int64_t(3);
+  const float* pa = A + std::min<int64_t>(i_base + 4 * lane, alast);
+  const float* pb = B + std::min<int64_t>(j_base + 4 * (lane & 31), blast) + (int64_t)(lane >> 5) * ldb;
+  const int nk = (int)(K / FK);
+  auto issue = [&](int kc, int stg) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = wave * 4 + e;
+      const int64_t gk = (int64_t)kc * FK + k;
+      __builtin_amdgcn_global_load_lds((const void*)(pa + gk * lda), HC_LDS_PTR(&As[stg][k][0]), 16, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e += 2) {
+      const int k = wave * 4 + e;
+      const int64_t gk = (int64_t)kc * FK + k;
+      __builtin_amdgcn_global_load_lds((const void*)(pb + gk * ldb), HC_LDS_PTR(&Bs[stg][k][0]), 16, 0, 0);
+    }
+  };
+  const uint32_t a_off = lds_addr(&As[0][lane >> 4][wm + (lane & 15)]);
+  const uint32_t b_off = lds_addr(&Bs[0][lane >> 4][wn + (lane & 15)]);
+  constexpr uint32_t SA = FK * DM * 4, SB_ = FK * DN * 4;
+  issue(0, 0);
+  if (nk > 1) issue(1, 1);
+  for (int kc = 0; kc < nk; ++kc) {
+    if (kc + 1 < nk) __builtin_amdgcn_s_waitcnt(0xF76);   // vmcnt(6): chunk kc landed
+    else __builtin_amdgcn_s_waitcnt(0xF70);
+    __builtin_amdgcn_s_barrier();
+    if (kc + 2 < nk) issue(kc + 2, (kc + 2) % DST);
+    const int stg = kc % DST;
+    const uint32_t sa = a_off + stg * SA, sb = b_off + stg * SB_;
+#pragma unroll
+    for (int kk = 0; kk < FK; kk += 4) {
+      float a0, a1, a2, a3, b0, b1, b2, b3;
+      const uint32_t ra = sa + kk * DM * 4, rb = sb + kk * DN * 4;
+      asm volatile("ds_read_b32 %0, %1 offset:0" : "=v"(a0) : "v"(ra));
+      asm volatile("ds_read_b32 %0, %1 offset:64" : "=v"(a1) : "v"(ra));
+      asm volatile("ds_read_b32 %0, %1 offset:128" : "=v"(a2) : "v"(ra));
+      asm volatile("ds_read_b32 %0, %1 offset:192" : "=v"(a3) : "v"(ra));
+      asm volatile("ds_read_b32 %0, %1 offset:0" : "=v"(b0) : "v"(rb));
+      asm volatile("ds_read_b32 %0, %1 offset:64" : "=v"(b1) : "v"(rb));
+      asm volatile("ds_read_b32 %0, %1 offset:128" : "=v"(b2) : "v"(rb));
+      asm volatile("ds_read_b32 %0, %1 offset:192" : "=v"(b3) : "v"(rb));
+      asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(b0), "+v"(b1), "+v"(b2),
+                   "+v"(b3));
+      const float ao[4] = {a0, a1, a2, a3}, bo[4] = {b0, b1, b2, b3};
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<float>::op(ao[a], bo[b], acc[a][b]);
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 4; h += 2) {
+    float cv[2][4][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t j = std::min<int64_t>(j_base + wn + b * 16 + (lane & 15), N - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = std::min<int64_t>(i_base + wm + (h + a) * 16 + Mfma<float>::row(lane, r), M - 1);
+          cv[a][b][r] = C[i + j * ldc];
+        }
+      }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t j = j_base + wn + b * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = i_base + wm + (h + a) * 16 + Mfma<float>::row(lane, r);
+          if (i < M && j < N) C[i + j * ldc] = cv[a][b][r] + alpha * acc[h + a][b][r];
+        }
+      }
+  }
+}
+
+static bool dma32_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t M, int64_t N, int64_t K) {
+  return K % FK == 0 && M >= 4 && N >= 4 && lda % 4 == 0 && ldb % 4 == 0 && ((uintptr_t)A % 16) == 0 &&
+         ((uintptr_t)B % 16) == 0;
+}
+
 static bool dma_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t M, int64_t N, int64_t K) {
   return K % DK == 0 && M >= 2 && N >= 2 && lda % 2 == 0 && ldb % 2 == 0 && ((uintptr_t)A % 16) == 0 &&
          ((uintptr_t)B % 16) == 0;
@@ -407,6 +515,14 @@ void gemm_nt(T* C, int64_t ldc, const T* A, int64_t lda, const T* B, int64_t ldb
     if (dma_ok(A, lda, B, ldb, M, N, K)) {
       const int tm = (int)ceil_div(M, DM), tn = (int)ceil_div(N, DN);
       hipLaunchKernelGGL(k_gemm_nt_dma, dim3(tm * tn), dim3(512), 0, st, C, ldc, A, lda, B, ldb, M, N, K, alpha,
+                         lower ? 1 : 0, gr, gc, tn);
+      HC_LAUNCH_CHECK();
+      return;
+    }
+  } else {
+    if (dma32_ok(A, lda, B, ldb, M, N, K)) {
+      const int tm = (int)ceil_div(M, DM), tn = (int)ceil_div(N, DN);
+      hipLaunchKernelGGL(k_gemm_nt_dma32, dim3(tm * tn), dim3(512), 0, st, C, ldc, A, lda, B, ldb, M, N, K, alpha,
                          lower ? 1 : 0, gr, gc, tn);
       HC_LAUNCH_CHECK();
       return;

@@ -822,8 +822,10 @@ void factor(hc_solver* S, bool fp64 = false) {
   }
   const int nd = (int)S->drows.size();
   if (nd) {
+    // the operand carries zero columns up to a multiple of 16 (set at bind),
+    // which lets the update run on the MFMA DMA kernel
     scale_dense_rows(nd, nt, S->dAd, S->ddmidx, S->dmval, S->dBd, st);
-    gemm_nt<double>(S->dS, S->ld, S->dBd, nt, S->dBd, nt, nt, nt, nd, 1.0, true, 0, 0, st);
+    gemm_nt<double>(S->dS, S->ld, S->dBd, nt, S->dBd, nt, nt, nt, (nd + 15) / 16 * 16, 1.0, true, 0, 0, st);
   }
   const double tol = 0.0;
   // leaves are factored in FP64 in both modes; their updates land in the tail
@@ -1357,7 +1359,8 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->dAt = upload_csr(buf, S->At, st);
   S->dP = upload_csr(buf, S->P, st);
   S->dAd = upload(buf, S->Ad, st);
-  S->dBd = buf.take<double>(std::max<size_t>(1, S->Ad.size()));
+  const size_t nd_pad = (S->drows.size() + 15) / 16 * 16;
+  S->dBd = buf.take<double>(std::max<size_t>(1, nd_pad * (size_t)S->nt));
   S->ddrows = upload(buf, S->drows, st);
   S->ddmidx = upload(buf, S->dmidx, st);
   S->dq = upload(buf, S->q, st);
@@ -1460,6 +1463,8 @@ void bind(hc_solver* S, const hc_device* dev) {
   HC_HIP(hipHostMalloc((void**)&S->hpart, 4096 * sizeof(double), hipHostMallocDefault));
   HC_HIP(hipHostMalloc((void**)&S->hmask, 4096 * sizeof(unsigned long long), hipHostMallocDefault));
   HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), st));
+  if (!S->drows.empty())   // zero padding columns of the dense-row operand
+    HC_HIP(hipMemsetAsync(S->dBd, 0, (S->drows.size() + 15) / 16 * 16 * (size_t)S->nt * sizeof(double), st));
   // segment views
   int pow_off = 0;
   for (const Segment& g : S->segs) {
