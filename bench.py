@@ -82,7 +82,7 @@ def run_gpu(prob, precision, steps, warmup):
     solver.close()
     peak = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
-    kernel = "k_gemm_nt_dma" if precision == "fp64" else "k_gemm_nt<float>"
+    kernel = "k_gemm_nt_dma" if precision == "fp64" else "k_gemm_nt_dma32"
     return dict(
         wall=wall, iters=iters, infos=infos, status=last["status_name"], objective=last["obj_primal"],
         res_primal=last["res_primal"], res_dual=last["res_dual"], gap=last["gap"],

@@ -310,10 +310,10 @@ __global__ __launch_bounds__(512) void k_gemm_nt_dma(double* __restrict__ C, int
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
-  // lane l loads rows (2l, 2l+1) of a 128-row half panel; rows past the end
-  // repeat the last even pair (their products land in rows / columns that are
-  // never stored).  M, N >= 2 and even row offsets keep every load in bounds
-  // and 16-byte aligned.
+  // lane l loads rows (2l, 2l+1) of a 128-row half panel.  M and N are even
+  // here (the caller leaves odd last rows / columns to the edge kernel), so
+  // every pair below M is loaded whole; pairs past the end repeat the last
+  // pair, and their products land in rows / columns that are never stored.
   const int64_t alast = (M - 2) & ~int64_t(1), blast = (N - 2) & ~int64_t(1);
   const double* pa0 = A + std::min<int64_t>(i_base + 2 * lane, alast);
   const double* pa1 = A + std::min<int64_t>(i_base + 128 + 2 * lane, alast);
@@ -416,8 +416,9 @@ __global__ __launch_bounds__(512) void k_gemm_nt_dma32(float* __restrict__ C, in
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0, 0, 0, 0};
   // lane l loads rows 4l..4l+3 of A, and rows 4 (l % 32) .. + 3 of B for
-  // k-row (l / 32) of a pair; clamped to the last aligned group of four
-  // (M, N >= 4, 16-byte aligned columns)
+  // k-row (l / 32) of a pair.  M and N are multiples of four here (the caller
+  // leaves the rest to the edge kernel); groups past the end repeat the last
+  // group and only feed entries that are never stored.
   const int64_t alast = (M - 4) & ~int64_t(3), blast = (N - 4) & ~int64_t(3);
   const float* pa = A + std::min<int64_t>(i_base + 4 * lane, alast);
   const float* pb = B + std::min<int64_t>(j_base + 4 * (lane & 31), blast) + (int64_t)(lane >> 5) * ldb;
@@ -507,24 +508,66 @@ static bool dma_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int64
          ((uintptr_t)B % 16) == 0;
 }
 
+// Entries of C outside the leading M' x N' block (rows [M', M) and columns
+// [N', N)) that the DMA kernels leave to this one: their loads come in whole
+// 16-byte groups of rows, so the last M % g rows and N % g columns (g = 2 for
+// FP64, 4 for FP32) are updated here, one thread per entry.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_nt_edge(T* __restrict__ C, int64_t ldc, const T* __restrict__ A,
+                                                      int64_t lda, const T* __restrict__ B, int64_t ldb, int64_t M,
+                                                      int64_t N, int64_t K, T alpha, int lower, int64_t gr,
+                                                      int64_t gc, int64_t Mp, int64_t Np) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_rows = (M - Mp) * N;          // rows [Mp, M), every column
+  const int64_t n_cols = Mp * (N - Np);         // rows [0, Mp), columns [Np, N)
+  if (e >= n_rows + n_cols) return;
+  int64_t i, j;
+  if (e < n_rows) {
+    i = Mp + e / N;
+    j = e % N;
+  } else {
+    i = (e - n_rows) % Mp;
+    j = Np + (e - n_rows) / Mp;
+  }
+  if (lower && gr + i < gc + j) return;
+  T acc = 0;
+  for (int64_t k = 0; k < K; ++k) acc += A[i + k * lda] * B[j + k * ldb];
+  C[i + j * ldc] += alpha * acc;
+}
+
+template <typename T>
+static void gemm_edge(T* C, int64_t ldc, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t M, int64_t N,
+                      int64_t K, T alpha, bool lower, int64_t gr, int64_t gc, int64_t Mp, int64_t Np,
+                      hipStream_t st) {
+  const int64_t cnt = (M - Mp) * N + Mp * (N - Np);
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(k_gemm_nt_edge<T>, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, C, ldc, A, lda, B, ldb,
+                     M, N, K, alpha, lower ? 1 : 0, gr, gc, Mp, Np);
+  HC_LAUNCH_CHECK();
+}
+
 template <typename T>
 void gemm_nt(T* C, int64_t ldc, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t M, int64_t N, int64_t K,
              T alpha, bool lower, int64_t gr, int64_t gc, hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return;
   if constexpr (std::is_same<T, double>::value) {
-    if (dma_ok(A, lda, B, ldb, M, N, K)) {
-      const int tm = (int)ceil_div(M, DM), tn = (int)ceil_div(N, DN);
-      hipLaunchKernelGGL(k_gemm_nt_dma, dim3(tm * tn), dim3(512), 0, st, C, ldc, A, lda, B, ldb, M, N, K, alpha,
+    const int64_t Mp = M & ~int64_t(1), Np = N & ~int64_t(1);   // whole row pairs
+    if (dma_ok(A, lda, B, ldb, Mp, Np, K)) {
+      const int tm = (int)ceil_div(Mp, DM), tn = (int)ceil_div(Np, DN);
+      hipLaunchKernelGGL(k_gemm_nt_dma, dim3(tm * tn), dim3(512), 0, st, C, ldc, A, lda, B, ldb, Mp, Np, K, alpha,
                          lower ? 1 : 0, gr, gc, tn);
       HC_LAUNCH_CHECK();
+      gemm_edge<T>(C, ldc, A, lda, B, ldb, M, N, K, alpha, lower, gr, gc, Mp, Np, st);
       return;
     }
   } else {
-    if (dma32_ok(A, lda, B, ldb, M, N, K)) {
-      const int tm = (int)ceil_div(M, DM), tn = (int)ceil_div(N, DN);
-      hipLaunchKernelGGL(k_gemm_nt_dma32, dim3(tm * tn), dim3(512), 0, st, C, ldc, A, lda, B, ldb, M, N, K, alpha,
+    const int64_t Mp = M & ~int64_t(3), Np = N & ~int64_t(3);   // whole groups of four rows
+    if (dma32_ok(A, lda, B, ldb, Mp, Np, K)) {
+      const int tm = (int)ceil_div(Mp, DM), tn = (int)ceil_div(Np, DN);
+      hipLaunchKernelGGL(k_gemm_nt_dma32, dim3(tm * tn), dim3(512), 0, st, C, ldc, A, lda, B, ldb, Mp, Np, K, alpha,
                          lower ? 1 : 0, gr, gc, tn);
       HC_LAUNCH_CHECK();
+      gemm_edge<T>(C, ldc, A, lda, B, ldb, M, N, K, alpha, lower, gr, gc, Mp, Np, st);
       return;
     }
   }

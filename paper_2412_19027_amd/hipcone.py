@@ -307,17 +307,21 @@ def test_cone_step(kind, dim, s, z, ds, dz, amax, alpha=None):
     return out
 
 
-def test_dense_chol_solve(A, B, precision=PRECISION_FP64):
-    """A: (n, n) SPD (torch cuda float64, column-major taken as A.T storage); B: (n, nrhs). In place."""
+def test_dense_chol_solve(A, B, precision=PRECISION_FP64, ld=None):
+    """A: (n, n) SPD (torch cuda float64); B: (n, nrhs).  A is stored
+    column-major with leading dimension ld (default n) as the library keeps
+    its Schur complement.  Returns (X, L, pivot-guard hits)."""
     import torch
     n = A.shape[0]
-    At = A.t().contiguous()          # column-major storage of A
+    ld = n if ld is None else int(ld)
+    At = torch.zeros((n, ld), dtype=A.dtype, device=A.device)   # row j = column j of the matrix
+    At[:, :n] = A.t()
     Bt = B.t().contiguous()          # column-major (n x nrhs)
     hits = C.c_int64()
-    _check(lib().hc_test_dense_chol_solve(precision, n, n, _dptr(At), Bt.shape[0], _dptr(Bt), C.byref(hits),
+    _check(lib().hc_test_dense_chol_solve(precision, n, ld, _dptr(At), Bt.shape[0], _dptr(Bt), C.byref(hits),
                                           _stream()))
     torch.cuda.synchronize()
-    return Bt.t().contiguous(), At.t().contiguous(), hits.value
+    return Bt.t().contiguous(), At[:, :n].t().contiguous(), hits.value
 
 
 def test_copy(src, dst):

@@ -43,6 +43,25 @@ def test_dense_cholesky_fp64(n, nrhs):
     assert relerr(Lh @ Lh.T, A) < 1e-13
 
 
+@pytest.mark.parametrize("n", [333, 681, 1101, 1537])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dense_cholesky_odd_sizes_padded_ld(n, precision):
+    """The solver's layout: n odd (or not a multiple of 4), leading dimension
+    rounded up to 64, so the MFMA DMA updates run and leave edge rows/columns
+    to the edge kernel."""
+    ld = (n + 63) // 64 * 64
+    G = RNG.standard_normal((n, n))
+    A = G @ G.T + n * np.eye(n)
+    B = RNG.standard_normal((n, 2))
+    code = HC.PRECISION_FP64 if precision == "fp64" else HC.PRECISION_MIXED
+    X, L, hits = HC.test_dense_chol_solve(T(A), T(B), code, ld=ld)
+    assert hits == 0
+    assert relerr(N(X), np.linalg.solve(A, B)) < (1e-11 if precision == "fp64" else 1e-4)
+    if precision == "fp64":
+        Lh = np.tril(N(L))
+        assert relerr(Lh @ Lh.T, A) < 1e-13
+
+
 @pytest.mark.parametrize("n", [64, 300, 513, 1600])
 def test_dense_cholesky_fp32(n):
     G = RNG.standard_normal((n, n))
