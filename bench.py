@@ -99,6 +99,32 @@ def run_gpu(prob, precision, steps, warmup):
     )
 
 
+def run_other_workloads(steps=1):
+    """The other full-size configurations, one FP64 solve each after a warm-up
+    solve: status, iterations and time per iteration (problem resident)."""
+    import torch
+    from paper_2412_19027_amd import hipcone as HC
+    from paper_2412_19027_amd import workloads as W
+    out = {}
+    for name, make in (("logreg_exp", lambda: W.logreg_exp(0)), ("psd_pow", lambda: W.psd_pow(0))):
+        prob = make()
+        s = HC.Solver(prob)
+        s.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [s.solve() for _ in range(steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        it = sum(i["iterations"] for i in infos)
+        last = infos[-1]
+        s.close()
+        out[name] = dict(problem=prob.name, n=prob.n, m=prob.m, status=last["status_name"],
+                         iterations=last["iterations"], objective=last["obj_primal"],
+                         ms_per_iteration=1e3 * wall / max(1, it), ms_per_solve=1e3 * wall / steps,
+                         dense_tail=last["n_ordered"], leaf_blocks=last["n_leaves"])
+    return out
+
+
 def run_served(count, rate=2000.0, workers=4, slots=32, budget=16 << 30, seed=0):
     """The served form on a stream of MPC requests: problems are generated
     beforehand, submitted at Poisson arrival times by one thread, and every
@@ -164,6 +190,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--served", type=int, default=1000,
                     help="requests in the served-form measurement (MPC stream at 2000/s); 0 = skip")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the other full-size configurations")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run the reference copy kernel (for byte-counter scaling)")
     args = ap.parse_args()
@@ -188,6 +215,7 @@ def main():
         other["objective_rel_diff_vs_main"] = abs(r["objective"] - main_run["objective"]) / max(
             1.0, abs(main_run["objective"]))
     served = run_served(args.served) if args.served > 0 else None
+    others = None if args.no_workloads else run_other_workloads()
     if args.calibrate_copy:
         calibrate_copy()
     cpu = None if args.no_cpu_baseline else cpu_baseline(prob)
@@ -219,6 +247,7 @@ def main():
         "roofline": main_run["roofline"],
         "alt_precision": other,
         "served": served,
+        "workloads": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -201,6 +201,25 @@ int32_t hc_get_solution(const hc_solver* s, double* x, double* sv, double* z);
 int32_t hc_get_iterate(const hc_solver* s, double* x, double* sv, double* z, double* tau,
                        double* kappa, int64_t* row_of_internal);
 
+/* Replace the internal iterate (same order and scaling as hc_get_iterate;
+ * host arrays x (n), s (m), z (m); tau, kappa > 0).  The next hc_solve starts
+ * from its own initial point again; this exists for the KKT test below and
+ * for callers that restart a solve step by step. */
+int32_t hc_set_iterate(hc_solver* s, const double* x, const double* sv, const double* z,
+                       double tau, double kappa);
+
+/* Test entry: one KKT solve of an interior-point iteration at the current
+ * iterate (Sec. 3.4-3.5, Algorithm 1): the cone scalings at (s, z) with the
+ * given mu (force_dual != 0 forces the dual scaling of the exp/pow cones),
+ * the regularised factorisation, and
+ *   [P  A'; A  -H] [x; z] = [r1; r2]
+ * solved with iterative refinement against the unregularised matrix, exactly
+ * as inside hc_solve.  r1 (n), r2 (m), xo (n), zo (m): host arrays in the
+ * internal row order.  stats (NULL or 4 doubles): solves used, delta, number
+ * of exp/pow cones that took the dual scaling, FP64 refactorisations. */
+int32_t hc_test_kkt_solve(hc_solver* s, double mu, int32_t force_dual, const double* r1,
+                          const double* r2, double* xo, double* zo, double* stats);
+
 void hc_destroy(hc_solver* s);                /* NULL is a no-op */
 const char* hc_last_error(const hc_solver* s);
 const char* hc_status_str(int32_t status);
@@ -227,6 +246,13 @@ const char* hc_status_str(int32_t status);
 int32_t hc_test_cone_scale(int32_t type, int64_t count, int32_t dim, const double* alpha,
                            const double* s, const double* z, double mu, double* H_out,
                            double* lam_out, int32_t* branch_out, void* stream);
+/* hc_test_cone_mblock: the explicit blocks M_c = (H_c + delta I)^-1 that the
+ *   Schur complement is assembled from (eq. linsys_2x2 with the cone rows
+ *   eliminated first), at the scaling of (s, z); M_out (device, count x rows
+ *   x rows, dense symmetric).  delta > 0. */
+int32_t hc_test_cone_mblock(int32_t type, int64_t count, int32_t dim, const double* alpha,
+                            const double* s, const double* z, double mu, double delta, double* M_out,
+                            void* stream);
 int32_t hc_test_cone_ds(int32_t type, int64_t count, int32_t dim, const double* alpha,
                         const double* s, const double* z, const double* dsa, const double* dza,
                         double mu, double sm, double* ds_out, void* stream);

@@ -1686,6 +1686,56 @@ int32_t hc_get_iterate(const hc_solver* S, double* x, double* sv, double* z, dou
   return HC_OK;
 }
 
+int32_t hc_set_iterate(hc_solver* S, const double* x, const double* sv, const double* z, double tau, double kappa) {
+  if (!S || !x || !sv || !z) return HC_ERR_INVALID_ARG;
+  if (!S->bound) return HC_ERR_STATE;
+  if (!(tau > 0) || !(kappa > 0)) return HC_ERR_INVALID_ARG;
+  try {
+    HC_HIP(hipSetDevice(S->device));
+    HC_HIP(hipMemcpy(S->x, x, S->n * 8, hipMemcpyHostToDevice));
+    HC_HIP(hipMemcpy(S->s, sv, S->m * 8, hipMemcpyHostToDevice));
+    HC_HIP(hipMemcpy(S->z, z, S->m * 8, hipMemcpyHostToDevice));
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
+  S->tau = tau;
+  S->kappa = kappa;
+  return HC_OK;
+}
+
+int32_t hc_test_kkt_solve(hc_solver* S, double mu, int32_t force_dual, const double* r1, const double* r2,
+                          double* xo, double* zo, double* stats) {
+  if (!S || !r1 || !r2 || !xo || !zo) return HC_ERR_INVALID_ARG;
+  if (!S->bound) return HC_ERR_STATE;
+  if (!(mu > 0)) return HC_ERR_INVALID_ARG;
+  try {
+    HC_HIP(hipSetDevice(S->device));
+    hipStream_t st = S->stream;
+    const int64_t n = S->n, m = S->m;
+    int pd = 0;
+    scale_all(S, mu, force_dual != 0, &pd);
+    factor(S);
+    HC_HIP(hipMemcpyAsync(S->r1, r1, n * 8, hipMemcpyHostToDevice, st));
+    HC_HIP(hipMemcpyAsync(S->r2, r2, m * 8, hipMemcpyHostToDevice, st));
+    const int64_t before = S->info.ir_solves, fb = S->info.fp64_fallbacks;
+    kkt_solve(S, S->r1, S->r2, S->x1, S->z1);
+    HC_HIP(hipMemcpyAsync(xo, S->x1, n * 8, hipMemcpyDeviceToHost, st));
+    HC_HIP(hipMemcpyAsync(zo, S->z1, m * 8, hipMemcpyDeviceToHost, st));
+    HC_HIP(hipStreamSynchronize(st));
+    if (stats) {
+      stats[0] = (double)(S->info.ir_solves - before);
+      stats[1] = S->delta;
+      stats[2] = (double)pd;
+      stats[3] = (double)(S->info.fp64_fallbacks - fb);
+    }
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
+  return HC_OK;
+}
+
 void hc_destroy(hc_solver* S) {
   if (!S) return;
   if (S->own_mem && S->mem) (void)hipFree(S->mem);

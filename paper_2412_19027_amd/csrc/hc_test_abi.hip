@@ -153,6 +153,44 @@ int32_t hc_test_cone_scale(int32_t type, int64_t count, int32_t dim, const doubl
   });
 }
 
+int32_t hc_test_cone_mblock(int32_t type, int64_t count, int32_t dim, const double* alpha, const double* s,
+                            const double* z, double mu, double delta, double* M_out, void* stream) {
+  return guard([&] {
+    if (!M_out || !(delta > 0.0)) throw Error{HC_ERR_INVALID_ARG, "M_out is NULL or delta <= 0"};
+    hipStream_t st = (hipStream_t)stream;
+    TestSeg T;
+    make(T, type, count, dim, alpha);
+    const int64_t tot = count * T.rows;
+    double* si = T.in(s, st);
+    double* zi = T.in(z, st);
+    double* hd = T.alloc(tot);
+    int* pd = (int*)T.alloc(1);
+    HC_HIP(hipMemsetAsync(pd, 0, sizeof(double), st));
+    cone_scale(T.g, si, zi, mu, 0, hd, pd, st);
+    cone_mblock(T.g, delta, st);
+    const int64_t per = mblock_doubles(type, T.g.dim);
+    std::vector<double> hm(per * T.g.count), dense((size_t)count * T.rows * T.rows, 0.0);
+    HC_HIP(hipMemcpyAsync(hm.data(), T.g.mblk, hm.size() * 8, hipMemcpyDeviceToHost, st));
+    HC_HIP(hipStreamSynchronize(st));
+    const int64_t N = T.g.count;
+    for (int64_t c = 0; c < count; ++c) {
+      double* D = dense.data() + (size_t)c * T.rows * T.rows;
+      if (type == HC_CONE_ZERO || type == HC_CONE_NONNEG) {
+        for (int i = 0; i < T.rows; ++i) D[i * T.rows + i] = hm[c * T.rows + i];
+        continue;
+      }
+      for (int a = 0; a < T.rows; ++a)
+        for (int b = 0; b <= a; ++b) {
+          const double v = hm[((int64_t)a * (a + 1) / 2 + b) * N + c];
+          D[a * T.rows + b] = v;
+          D[b * T.rows + a] = v;
+        }
+    }
+    HC_HIP(hipMemcpyAsync(M_out, dense.data(), dense.size() * 8, hipMemcpyHostToDevice, st));
+    HC_HIP(hipStreamSynchronize(st));
+  });
+}
+
 int32_t hc_test_cone_ds(int32_t type, int64_t count, int32_t dim, const double* alpha, const double* s,
                         const double* z, const double* dsa, const double* dza, double mu, double sm, double* ds_out,
                         void* stream) {

@@ -21,9 +21,9 @@ STATUS = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasibl
           5: "insufficient_progress", 6: "numerical_error", 7: "cancelled"}
 
 EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "hc_solve", "hc_get_info",
-           "hc_get_solution", "hc_get_iterate", "hc_destroy", "hc_last_error", "hc_status_str",
+           "hc_get_solution", "hc_get_iterate", "hc_set_iterate", "hc_test_kkt_solve", "hc_destroy", "hc_last_error", "hc_status_str",
            "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_dense_chol_solve",
-           "hc_test_copy", "hc_server_config_default", "hc_server_create", "hc_server_submit", "hc_server_poll",
+           "hc_test_copy", "hc_test_cone_mblock", "hc_server_config_default", "hc_server_create", "hc_server_submit", "hc_server_poll",
            "hc_server_wait", "hc_server_stats", "hc_server_destroy"]
 
 
@@ -108,6 +108,8 @@ def lib():
         L.hc_get_info.argtypes = [vp, C.POINTER(hc_info)]
         L.hc_get_solution.argtypes = [vp, vp, vp, vp]
         L.hc_get_iterate.argtypes = [vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp]
+        L.hc_set_iterate.argtypes = [vp, vp, vp, vp, dbl, dbl]
+        L.hc_test_kkt_solve.argtypes = [vp, dbl, C.c_int32, vp, vp, vp, vp, vp]
         L.hc_destroy.argtypes = [vp]
         L.hc_destroy.restype = None
         L.hc_last_error.argtypes = [vp]
@@ -119,6 +121,7 @@ def lib():
         L.hc_test_cone_step.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, dbl, vp, vp]
         L.hc_test_dense_chol_solve.argtypes = [i32, i64, i64, vp, i32, vp, C.POINTER(i64), vp]
         L.hc_test_copy.argtypes = [vp, vp, i64, vp]
+        L.hc_test_cone_mblock.argtypes = [i32, i64, i32, vp, vp, vp, C.c_double, C.c_double, vp, vp]
         L.hc_server_config_default.argtypes = [C.POINTER(hc_server_config)]
         L.hc_server_create.argtypes = [C.POINTER(vp), C.POINTER(hc_server_config)]
         L.hc_server_submit.argtypes = [vp, C.POINTER(hc_problem), C.c_uint64, C.POINTER(C.c_uint64)]
@@ -251,6 +254,27 @@ class Solver:
                                     C.byref(kappa), perm.ctypes.data), self._h)
         return x, s, z, tau.value, kappa.value, perm
 
+    def set_iterate(self, x, s, z, tau, kappa):
+        """Replace the internal iterate (internal order and scaling, as `iterate()` returns it)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        assert x.shape == (self.n,) and s.shape == (self.m,) and z.shape == (self.m,)
+        _check(lib().hc_set_iterate(self._h, x.ctypes.data, s.ctypes.data, z.ctypes.data, float(tau), float(kappa)),
+               self._h)
+
+    def test_kkt_solve(self, mu, r1, r2, force_dual=False):
+        """One KKT solve at the current iterate (hc_test_kkt_solve); returns x, z, stats dict."""
+        r1 = np.ascontiguousarray(r1, dtype=np.float64)
+        r2 = np.ascontiguousarray(r2, dtype=np.float64)
+        assert r1.shape == (self.n,) and r2.shape == (self.m,)
+        x = np.zeros(self.n)
+        z = np.zeros(self.m)
+        st = np.zeros(4)
+        _check(lib().hc_test_kkt_solve(self._h, float(mu), int(bool(force_dual)), r1.ctypes.data, r2.ctypes.data,
+                                       x.ctypes.data, z.ctypes.data, st.ctypes.data), self._h)
+        return x, z, {"solves": int(st[0]), "delta": st[1], "dual_scaled": int(st[2]), "fp64_refactor": int(st[3])}
+
     def close(self):
         if getattr(self, "_h", None):
             lib().hc_destroy(self._h)
@@ -286,6 +310,17 @@ def test_cone_scale(kind, dim, s, z, mu, alpha=None):
                                     float(mu), _dptr(H), _dptr(lam), _dptr(br), _stream()))
     torch.cuda.synchronize()
     return H, lam, br
+
+
+def test_cone_mblock(kind, dim, s, z, mu, delta, alpha=None):
+    """Explicit M = (H + delta I)^-1 blocks used in the Schur assembly, (count, rows, rows)."""
+    import torch
+    count, rows = s.shape
+    M = torch.zeros((count, rows, rows), dtype=torch.float64, device=s.device)
+    _check(lib().hc_test_cone_mblock(kind, count, dim, _dptr(alpha), _dptr(s.contiguous()), _dptr(z.contiguous()),
+                                     float(mu), float(delta), _dptr(M), _stream()))
+    torch.cuda.synchronize()
+    return M
 
 
 def test_cone_ds(kind, dim, s, z, dsa, dza, mu, sm, alpha=None):

@@ -202,3 +202,39 @@ def test_step(kind):
         assert (out == ref).all()
         return
     assert relerr(out, ref) < 1e-12
+
+
+# ----------------------------------------------------------------- explicit M blocks
+@pytest.mark.parametrize("kind", ["nonneg", "soc", "exp", "pow", "psd3", "psd5"])
+@pytest.mark.parametrize("delta", [1e-8, 1e-3])
+def test_mblock_inverts_the_applied_scaling(kind, delta):
+    """The explicit blocks M_c that the Schur complement is assembled from are
+    (H_c + delta I)^-1 for the H_c that the refinement residual applies, and
+    match the oracle's scaling; both near the centre and close to the
+    boundary (mu small)."""
+    Nc = 120
+    alpha = None
+    if kind == "nonneg":
+        s, z, dim, code = RNG.uniform(0.1, 2, (Nc, 1)), RNG.uniform(0.1, 2, (Nc, 1)), 1, HC.NONNEG
+    elif kind == "soc":
+        s, z, dim, code = soc_interior(Nc, 4, RNG), soc_interior(Nc, 4, RNG), 4, HC.SOC
+    elif kind == "exp":
+        s, z, dim, code = exp_primal(Nc, RNG), exp_dual(Nc, RNG), 3, HC.EXP
+    elif kind == "pow":
+        alpha = RNG.uniform(0.2, 0.8, Nc)
+        s, z, dim, code = pow_primal(Nc, alpha, RNG), pow_dual(Nc, alpha, RNG), 3, HC.POW
+    else:
+        k = int(kind[3:])
+        s, z, dim, code = C.svec(spd(Nc, k, RNG)), C.svec(spd(Nc, k, RNG)), k, HC.PSD
+    mu = 0.7
+    a_t = None if alpha is None else T(alpha)
+    H, _, _ = HC.test_cone_scale(code, dim, T(s), T(z), mu, a_t)
+    M = HC.test_cone_mblock(code, dim, T(s), T(z), mu, delta, a_t)
+    H, M = N(H), N(M)
+    rows = H.shape[1]
+    eye = np.eye(rows)
+    prod = np.einsum("cij,cjk->cik", M, H + delta * eye[None])
+    err = np.abs(prod - eye[None]).max(axis=(1, 2))
+    cond = np.array([np.linalg.cond(h + delta * eye) for h in H])
+    assert np.all(err <= 1e-13 * np.maximum(cond, 1.0) + 1e-12), (err.max(), cond[np.argmax(err)])
+    assert np.allclose(M, np.transpose(M, (0, 2, 1)), rtol=0, atol=1e-12 * np.abs(M).max())
