@@ -216,9 +216,30 @@ int32_t hc_set_iterate(hc_solver* s, const double* x, const double* sv, const do
  * solved with iterative refinement against the unregularised matrix, exactly
  * as inside hc_solve.  r1 (n), r2 (m), xo (n), zo (m): host arrays in the
  * internal row order.  stats (NULL or 4 doubles): solves used, delta, number
- * of exp/pow cones that took the dual scaling, FP64 refactorisations. */
+ * of exp/pow cones on the primal-dual (rank-4) scaling, FP64
+ * refactorisations of the mixed mode. */
 int32_t hc_test_kkt_solve(hc_solver* s, double mu, int32_t force_dual, const double* r1,
                           const double* r2, double* xo, double* zo, double* stats);
+
+/* Test entry: the two operators of the refinement at the current iterate,
+ * after the same scaling and factorisation: one regularised solve
+ *   [P + delta I,  A'; A,  -(H + delta I)] [xr; zr] = [r1; r2]
+ * (z eliminated through M = (H + delta I)^-1, then S xr = r1 + A' M r2), and
+ * the unregularised product [kx; kz] = [P xr + A' zr; A xr - H zr].  Host
+ * arrays in the internal row order: r1, xr, kx (n); r2, zr, kz (m). */
+int32_t hc_test_kkt_ops(hc_solver* s, double mu, int32_t force_dual, const double* r1,
+                        const double* r2, double* xr, double* zr, double* kx, double* kz);
+
+/* Test entry: the Schur complement S = P + delta I + A' M A (Sec. 3.5, cone
+ * rows eliminated) assembled at the scaling of the current iterate, and its
+ * Cholesky factor.  Only for solvers whose columns all sit in the dense block
+ * (settings.leaf_blocks = 0, else HC_ERR_STATE).  S_out, L_out (NULL allowed):
+ * host n x n, column-major; the lower triangle (i >= j) is written, the rest
+ * is unspecified.  L_out is the factor the iteration would use (FP32 values in
+ * the mixed mode).  stats (NULL or 3 doubles): delta, exp/pow cones on the
+ * primal-dual scaling, factor precision in bits. */
+int32_t hc_test_schur(hc_solver* s, double mu, int32_t force_dual, double* S_out, double* L_out,
+                      double* stats);
 
 void hc_destroy(hc_solver* s);                /* NULL is a no-op */
 const char* hc_last_error(const hc_solver* s);

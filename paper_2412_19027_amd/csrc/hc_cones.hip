@@ -675,8 +675,21 @@ __device__ void psd_apply_one(const SegDev& g, int64_t c, int mode, double delta
     for (int j = 0; j < k; ++j) {
       double acc = 0;
       for (int p = 0; p < k; ++p) acc += Q[p * PSD_KMAX + i] * T[p * PSD_KMAX + j];
-      U[i * PSD_KMAX + j] = acc * fsel(mode, m[i] * m[j], delta);
+      U[i * PSD_KMAX + j] = acc;
     }
+  // Q'XQ is symmetric only up to rounding.  Its (i,j) and (j,i) entries are
+  // one coefficient of the eigenvector svec(q_i q_j' + q_j q_i'), so average
+  // them before scaling: with factors 1/(m_i m_j + delta) up to 1/delta the
+  // rounding asymmetry would otherwise turn, through the upper-triangle svec
+  // read below, into an error along the stiff eigenvectors, where H is large.
+  for (int i = 0; i < k; ++i) {
+    U[i * PSD_KMAX + i] *= fsel(mode, m[i] * m[i], delta);
+    for (int j = i + 1; j < k; ++j) {
+      const double v = 0.5 * (U[i * PSD_KMAX + j] + U[j * PSD_KMAX + i]) * fsel(mode, m[i] * m[j], delta);
+      U[i * PSD_KMAX + j] = v;
+      U[j * PSD_KMAX + i] = v;
+    }
+  }
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
@@ -1034,14 +1047,17 @@ __global__ void k_cone_ds(SegDev g, const double* __restrict__ s, const double* 
           Bb[r * PSD_KMAX + j] = acc;
         }
       // V = (Aa Bb + Bb Aa)/2 + diag(lam^2) - sm I ;  X_ij = 2 V_ij / (lam_i + lam_j)
+      // (V is formed on the upper triangle and mirrored, so X is exactly
+      // symmetric before the large 1/(lam_i + lam_j) factors)
       double X[PSD_KMAX * PSD_KMAX];
       for (int r = 0; r < k; ++r)
-        for (int j = 0; j < k; ++j) {
+        for (int j = r; j < k; ++j) {
           double acc = 0;
           for (int p = 0; p < k; ++p) acc += Aa[r * PSD_KMAX + p] * Bb[p * PSD_KMAX + j] + Bb[r * PSD_KMAX + p] * Aa[p * PSD_KMAX + j];
           double v = 0.5 * acc;
           if (r == j) v += lam[r] * lam[r] - sm;
           X[r * PSD_KMAX + j] = 2.0 * v / (lam[r] + lam[j]);
+          X[j * PSD_KMAX + r] = X[r * PSD_KMAX + j];
         }
       // ds = svec(R X R')
       for (int r = 0; r < k; ++r)

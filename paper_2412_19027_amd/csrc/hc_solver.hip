@@ -137,6 +137,7 @@ struct hc_solver {
   int kiter = 0;                    // loop counter of the current solve
   double sdiag_max = 0;             // mixed mode: max |S_ii| of the last FP32 factorisation
   double t_begin = 0;               // host clock at the start of the solve
+  double* snap_S = nullptr;         // test hook: host copy of the dense tail before its Cholesky
   std::string last_error;
 };
 
@@ -838,6 +839,10 @@ void factor(hc_solver* S, bool fp64 = false) {
     Red r(S, nt);
     r.maxabs(S->sb);
     S->sdiag_max = r.run()[0];
+  }
+  if (S->snap_S && nt > 0) {
+    HC_HIP(hipMemcpy2DAsync(S->snap_S, nt * 8, S->dS, S->ld * 8, nt * 8, nt, hipMemcpyDeviceToHost, st));
+    HC_HIP(hipStreamSynchronize(st));
   }
   if (nt == 0) {
     // every column sits in a leaf block: nothing dense to factor
@@ -1701,6 +1706,85 @@ int32_t hc_set_iterate(hc_solver* S, const double* x, const double* sv, const do
   }
   S->tau = tau;
   S->kappa = kappa;
+  return HC_OK;
+}
+
+int32_t hc_test_schur(hc_solver* S, double mu, int32_t force_dual, double* S_out, double* L_out, double* stats) {
+  if (!S || !S_out) return HC_ERR_INVALID_ARG;
+  if (!S->bound) return HC_ERR_STATE;
+  if (!(mu > 0)) return HC_ERR_INVALID_ARG;
+  if (S->leaves || S->nt != S->n) {
+    g_last_error = "hc_test_schur: leaf blocks in use (set leaf_blocks = 0)";
+    return HC_ERR_STATE;
+  }
+  try {
+    HC_HIP(hipSetDevice(S->device));
+    hipStream_t st = S->stream;
+    const int64_t n = S->n;
+    int pd = 0;
+    scale_all(S, mu, force_dual != 0, &pd);
+    S->snap_S = S_out;
+    try {
+      factor(S);
+    } catch (...) {
+      S->snap_S = nullptr;
+      throw;
+    }
+    S->snap_S = nullptr;
+    if (L_out && n > 0) {
+      if (S->use64) {
+        HC_HIP(hipMemcpy2DAsync(L_out, n * 8, S->dS, S->ld * 8, n * 8, n, hipMemcpyDeviceToHost, st));
+        HC_HIP(hipStreamSynchronize(st));
+      } else {
+        std::vector<float> tmp((size_t)n * n);
+        HC_HIP(hipMemcpy2DAsync(tmp.data(), n * 4, S->dS32, S->ld * 4, n * 4, n, hipMemcpyDeviceToHost, st));
+        HC_HIP(hipStreamSynchronize(st));
+        for (size_t i = 0; i < tmp.size(); ++i) L_out[i] = tmp[i];
+      }
+    }
+    HC_HIP(hipStreamSynchronize(st));
+    if (stats) {
+      stats[0] = S->delta;
+      stats[1] = (double)pd;
+      stats[2] = S->use64 ? 64.0 : 32.0;
+    }
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
+  return HC_OK;
+}
+
+int32_t hc_test_kkt_ops(hc_solver* S, double mu, int32_t force_dual, const double* r1, const double* r2, double* xr,
+                        double* zr, double* kx, double* kz) {
+  if (!S || !r1 || !r2 || !xr || !zr || !kx || !kz) return HC_ERR_INVALID_ARG;
+  if (!S->bound) return HC_ERR_STATE;
+  if (!(mu > 0)) return HC_ERR_INVALID_ARG;
+  try {
+    HC_HIP(hipSetDevice(S->device));
+    hipStream_t st = S->stream;
+    const int64_t n = S->n, m = S->m;
+    int pd = 0;
+    scale_all(S, mu, force_dual != 0, &pd);
+    factor(S);
+    HC_HIP(hipMemcpyAsync(S->r1, r1, n * 8, hipMemcpyHostToDevice, st));
+    HC_HIP(hipMemcpyAsync(S->r2, r2, m * 8, hipMemcpyHostToDevice, st));
+    solve_reg(S, S->r1, S->r2, S->x1, S->z1);
+    // K [x1; z1] with the unregularised K, as the refinement forms it
+    P_mul(S, S->x1, S->kx, 1.0, 0.0);
+    At_mul(S, S->z1, S->kx, 1.0, 1.0);
+    A_mul(S, S->x1, S->kz, 1.0, 0.0);
+    H_apply(S, 0, S->z1, S->t2);
+    vaxpby(m, -1.0, S->t2, 1.0, S->kz, st);
+    HC_HIP(hipMemcpyAsync(xr, S->x1, n * 8, hipMemcpyDeviceToHost, st));
+    HC_HIP(hipMemcpyAsync(zr, S->z1, m * 8, hipMemcpyDeviceToHost, st));
+    HC_HIP(hipMemcpyAsync(kx, S->kx, n * 8, hipMemcpyDeviceToHost, st));
+    HC_HIP(hipMemcpyAsync(kz, S->kz, m * 8, hipMemcpyDeviceToHost, st));
+    HC_HIP(hipStreamSynchronize(st));
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  }
   return HC_OK;
 }
 

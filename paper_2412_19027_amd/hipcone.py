@@ -21,7 +21,8 @@ STATUS = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasibl
           5: "insufficient_progress", 6: "numerical_error", 7: "cancelled"}
 
 EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "hc_solve", "hc_get_info",
-           "hc_get_solution", "hc_get_iterate", "hc_set_iterate", "hc_test_kkt_solve", "hc_destroy", "hc_last_error", "hc_status_str",
+           "hc_get_solution", "hc_get_iterate", "hc_set_iterate", "hc_test_kkt_solve", "hc_test_kkt_ops",
+           "hc_test_schur", "hc_destroy", "hc_last_error", "hc_status_str",
            "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_dense_chol_solve",
            "hc_test_copy", "hc_test_cone_mblock", "hc_server_config_default", "hc_server_create", "hc_server_submit", "hc_server_poll",
            "hc_server_wait", "hc_server_stats", "hc_server_destroy"]
@@ -110,6 +111,8 @@ def lib():
         L.hc_get_iterate.argtypes = [vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp]
         L.hc_set_iterate.argtypes = [vp, vp, vp, vp, dbl, dbl]
         L.hc_test_kkt_solve.argtypes = [vp, dbl, C.c_int32, vp, vp, vp, vp, vp]
+        L.hc_test_schur.argtypes = [vp, dbl, C.c_int32, vp, vp, vp]
+        L.hc_test_kkt_ops.argtypes = [vp, dbl, C.c_int32, vp, vp, vp, vp, vp, vp]
         L.hc_destroy.argtypes = [vp]
         L.hc_destroy.restype = None
         L.hc_last_error.argtypes = [vp]
@@ -273,7 +276,30 @@ class Solver:
         st = np.zeros(4)
         _check(lib().hc_test_kkt_solve(self._h, float(mu), int(bool(force_dual)), r1.ctypes.data, r2.ctypes.data,
                                        x.ctypes.data, z.ctypes.data, st.ctypes.data), self._h)
-        return x, z, {"solves": int(st[0]), "delta": st[1], "dual_scaled": int(st[2]), "fp64_refactor": int(st[3])}
+        return x, z, {"solves": int(st[0]), "delta": st[1], "pd_scaled": int(st[2]), "fp64_refactor": int(st[3])}
+
+    def test_kkt_ops(self, mu, r1, r2, force_dual=False):
+        """One regularised solve and the unregularised product K [xr; zr] (hc_test_kkt_ops)."""
+        r1 = np.ascontiguousarray(r1, dtype=np.float64)
+        r2 = np.ascontiguousarray(r2, dtype=np.float64)
+        assert r1.shape == (self.n,) and r2.shape == (self.m,)
+        xr, kx = np.zeros(self.n), np.zeros(self.n)
+        zr, kz = np.zeros(self.m), np.zeros(self.m)
+        _check(lib().hc_test_kkt_ops(self._h, float(mu), int(bool(force_dual)), r1.ctypes.data, r2.ctypes.data,
+                                     xr.ctypes.data, zr.ctypes.data, kx.ctypes.data, kz.ctypes.data), self._h)
+        return xr, zr, kx, kz
+
+    def test_schur(self, mu, force_dual=False, factor=True):
+        """Schur complement at the current iterate and its Cholesky factor
+        (hc_test_schur; lower triangles, requires leaf_blocks=0)."""
+        S = np.zeros((self.n, self.n), order="F")
+        L = np.zeros((self.n, self.n), order="F") if factor else None
+        st = np.zeros(3)
+        _check(lib().hc_test_schur(self._h, float(mu), int(bool(force_dual)), S.ctypes.data,
+                                   L.ctypes.data if factor else None, st.ctypes.data), self._h)
+        S = np.tril(S)
+        S = S + np.tril(S, -1).T
+        return S, (np.tril(L) if factor else None), {"delta": st[0], "pd_scaled": int(st[1]), "bits": int(st[2])}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -55,19 +55,9 @@ CASES = [
     ("psdpow_small", lambda: W.psd_pow(0, n=250, n_pow=120, n_psd=25, k=4)),
 ]
 
-# Known open discrepancy: in FP64 the GPU run of psdpow_small follows the
-# oracle through iteration 15, then at mu ~ 6e-10 takes an affine step of
-# 0.953 where the oracle (from the same iterate) backtracks to 0.797 on the
-# power cones, and the primal residual jumps.  Kept visible as xfail until
-# the cause (step test or KKT solve accuracy at that iterate) is fixed.
-XFAIL = {("psdpow_small", "fp64")}
-
-
 @pytest.mark.parametrize("name,make", CASES)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_against_oracle(name, make, precision, request):
-    if (name, precision) in XFAIL:
-        request.applymarker(pytest.mark.xfail(reason="end-game divergence on power/PSD cones", strict=False))
+def test_against_oracle(name, make, precision):
     prob = make()
     ref = ipm.solve(prob)
     assert ref.status == ipm.SOLVED
