@@ -10,8 +10,8 @@
 //
 // Layout: S is column-major with leading dimension ld, lower triangle used.
 // Algorithm: blocked right-looking Cholesky with 64-wide diagonal blocks.
-//   diag:   the 64x64 block is factored in LDS by one workgroup, which also
-//           writes the inverse of the factor block (Linv, 64x64 per block)
+//   diag:   the 64x64 block is factored in registers by one workgroup, which
+//           also writes the inverse of the factor block (Linv, 64x64 per block)
 //   trsm:   L21 = A21 * Linv' in place, one workgroup per 64 rows
 //   update: trailing C -= L21 L21' on MFMA (v_mfma_f64_16x16x4f64 or
 //           v_mfma_f32_16x16x4f32), 128x128 tiles, lower tiles only.  The
@@ -53,21 +53,33 @@ constexpr int BS = 64;    // diagonal block
 constexpr int NB = 256;   // delayed-update panel width (multiple of BS)
 
 // ---------------------------------------------------------------------------
-// diagonal block: Cholesky in LDS + inverse of the factor
+// diagonal block: Cholesky + inverse of the factor, one wave
 // ---------------------------------------------------------------------------
+// value of v in lane `src` (compile-time), for every lane
+__device__ inline double lane_bcast(double v, int src) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, src);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ inline float lane_bcast(float v, int src) {
+  return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), src));
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ A, int64_t ld, int64_t c, int64_t n,
                                                    T* __restrict__ Linv, double tol, double fix,
                                                    unsigned long long* __restrict__ hits) {
   // Right-looking Cholesky of one 64 x 64 diagonal block.  Thread (i, p) =
-  // (lane, wave) keeps r[q] = A[i][16p + q] and y[q] = (L^-1)[i][16p + q]: the
+  // (lane, wave) keeps r[q] = A[i][16p + q] and y[q] = (L^-1)[i][16p + q]; the
   // inverse is produced by applying the same row operations to the identity.
-  // Each finished column of L and row of L^-1 is broadcast through LDS.
-  __shared__ T col[BS];
-  __shared__ T yrow[BS];
-  __shared__ T piv;
+  // One barrier per column: the owning wave publishes the raw column j in a
+  // double-buffered LDS slot, every thread derives the pivot, its own
+  // multiplier and those of its columns from it, and row j of L^-1 (which a
+  // wave needs only for its own columns) is taken from lane j by readlane.
+  __shared__ T colb[2][BS];
   const int lane = threadIdx.x & 63;
-  const int p = threadIdx.x >> 6;
+  const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index (uniform)
   const int bs = (int)std::min<int64_t>(BS, n - c);
   T r[16], y[16];
   // loads from clamped (always valid) addresses so that all 16 are in flight
@@ -80,44 +92,41 @@ __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ A, int64_t ld
     y[q] = (lane == k) ? T(1) : T(0);
   }
   int nhits = 0;
+  // column j = 16 pj + qj: the loop over the owning wave pj is a runtime loop,
+  // the 16 columns of a wave are unrolled so r[qj] and y[q] index registers
+#pragma unroll 1
+  for (int pj = 0; pj < 4; ++pj)
 #pragma unroll
-  for (int j = 0; j < BS; ++j) {
-    const int pj = j >> 4, qj = j & 15;
-    if (p == pj && lane == j) piv = r[qj];
+  for (int qj = 0; qj < 16; ++qj) {
+    const int j = 16 * pj + qj, bj = qj & 1;
+    if (p == pj) colb[bj][lane] = r[qj];
     __syncthreads();
-    double d = (double)piv;
+    double d = (double)colb[bj][j];
     if (j < bs && !(d > tol)) {
       d = fix;
       ++nhits;
     }
-    const T ljj = (T)sqrt(d);
-    const T inv = T(1) / ljj;
-    if (p == pj) {
-      r[qj] = (lane == j) ? ljj : r[qj] * inv;
-      col[lane] = r[qj];
+    // 1/sqrt(d) from the hardware estimate and two Newton steps
+    double e = __builtin_amdgcn_rsq(d);
+    e = e * (1.5 - 0.5 * d * e * e);
+    e = e * (1.5 - 0.5 * d * e * e);
+    const T inv = (T)e, ljj = (T)(d * e);
+    const T li = (lane > j) ? colb[bj][lane] * inv : T(0);
+    if (p == pj) r[qj] = (lane == j) ? ljj : (lane > j ? li : r[qj]);
+    if (p >= pj) {
+      T lk[16];   // all 16 reads issued before the first use
+#pragma unroll
+      for (int q = 0; q < 16; ++q) lk[q] = colb[bj][16 * p + q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (16 * p + q > j) r[q] -= li * (lk[q] * inv);
     }
-    if (lane == j) {
+    if (p <= pj) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        y[q] *= inv;
-        yrow[16 * p + q] = y[q];
+        const T yj = lane_bcast(y[q], j) * inv;   // (L^-1)[j][16p + q]
+        y[q] = (lane == j) ? yj : y[q] - li * yj;
       }
-    }
-    __syncthreads();
-    const T lij = (lane > j) ? col[lane] : T(0);
-    if (p > pj) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) r[q] -= lij * col[16 * p + q];
-    } else if (p == pj) {
-#pragma unroll
-      for (int q = qj + 1; q < 16; ++q) r[q] -= lij * col[16 * p + q];
-    }
-    if (p < pj) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q) y[q] -= lij * yrow[16 * p + q];
-    } else if (p == pj) {
-#pragma unroll
-      for (int q = 0; q <= qj; ++q) y[q] -= lij * yrow[16 * p + q];
     }
   }
   if (threadIdx.x == 0 && nhits) atomicAdd(hits, (unsigned long long)nhits);
