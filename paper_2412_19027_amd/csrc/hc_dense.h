@@ -17,7 +17,7 @@ struct Prof {
 // look-ahead factorisation: the trailing update of a panel runs on `side`
 // while the next panel is factored on the caller's stream.
 struct Aux {
-  int64_t nb = 512;     // panel width (multiple of 64) of the delayed updates
+  int64_t nb = 768;     // panel width (multiple of 64) of the delayed updates
   hipStream_t side = nullptr;
   std::vector<hipEvent_t> ev;
   size_t used = 0;

@@ -28,6 +28,7 @@
 namespace hc {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Mfma;
@@ -307,8 +308,11 @@ __global__ __launch_bounds__(512) void k_gemm_nt_dma(double* __restrict__ C, int
                                                      int64_t lda, const double* __restrict__ B, int64_t ldb, int64_t M,
                                                      int64_t N, int64_t K, double alpha, int lower, int64_t gr,
                                                      int64_t gc, int tiles_n) {
-  __shared__ double As[DST][DK][DM];
-  __shared__ double Bs[DST][DK][DN];
+  // one LDS block: the operand ring during the k loop, then the C staging
+  // area of the epilogue
+  __shared__ __align__(16) double smem[DST * DK * DM + DST * DK * DN];
+  double(*As)[DK][DM] = reinterpret_cast<double(*)[DK][DM]>(smem);
+  double(*Bs)[DK][DN] = reinterpret_cast<double(*)[DK][DN]>(smem + DST * DK * DM);
   const int tile_m = blockIdx.x / tiles_n, tile_n = blockIdx.x % tiles_n;
   const int64_t i_base = (int64_t)tile_m * DM, j_base = (int64_t)tile_n * DN;
   if (lower && gr + i_base + DM - 1 < gc + j_base) return;   // tile strictly above the diagonal
@@ -373,33 +377,49 @@ __global__ __launch_bounds__(512) void k_gemm_nt_dma(double* __restrict__ C, int
         for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<double>::op(ao[a], bo[b], acc[a][b]);
     }
   }
-  // epilogue: C loads of half a wave tile issued together (clamped addresses),
-  // stores predicated
+  // epilogue through LDS, one half of the tile's columns at a time: the four
+  // waves owning those columns write their accumulators column-major (stride
+  // CS doubles: two-way bank conflicts on the write, none on the read), then
+  // all eight waves stream whole columns, lane l handling rows 4l .. 4l + 3
+  // with 16-byte loads and stores of C (full cache lines per wave instead of
+  // 32-byte pieces of 16 lines).  M and N are even here, so rows come in
+  // pairs and each 16-byte piece is either wholly inside or wholly outside.
+  constexpr int CS = DM + 2;
+  static_assert(DN / 2 * CS <= DST * DK * (DM + DN), "C staging fits the operand ring");
+  __syncthreads();   // every wave is done with the operand ring
+  double* Cs = smem;
+  const int64_t i0 = i_base + 4 * lane;
+  const bool lo_ok = i0 < M, hi_ok = i0 + 2 < M;
 #pragma unroll
-  for (int h = 0; h < 4; h += 2) {
-    double cv[2][4][4];
+  for (int h = 0; h < 2; ++h) {
+    if (wn == 64 * h) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int64_t j = std::min<int64_t>(j_base + wn + b * 16 + (lane & 15), N - 1);
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t i = std::min<int64_t>(i_base + wm + (h + a) * 16 + Mfma<double>::row(lane, r), M - 1);
-          cv[a][b][r] = C[i + j * ldc];
-        }
-      }
+          for (int r = 0; r < 4; ++r)
+            Cs[(16 * b + (lane & 15)) * CS + wm + 16 * a + Mfma<double>::row(lane, r)] = acc[a][b][r];
+    }
+    __syncthreads();
+    v2d cg[8][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int cc = 0; cc < 8; ++cc) {
+      const int64_t j = std::min<int64_t>(j_base + 64 * h + 8 * wave + cc, N - 1);
+      cg[cc][0] = *reinterpret_cast<const v2d*>(C + std::min<int64_t>(i0, M - 2) + j * ldc);
+      cg[cc][1] = *reinterpret_cast<const v2d*>(C + std::min<int64_t>(i0 + 2, M - 2) + j * ldc);
+    }
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int64_t j = j_base + wn + b * 16 + (lane & 15);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t i = i_base + wm + (h + a) * 16 + Mfma<double>::row(lane, r);
-          if (i < M && j < N) C[i + j * ldc] = cv[a][b][r] + alpha * acc[h + a][b][r];
-        }
-      }
+    for (int cc = 0; cc < 8; ++cc) {
+      const int col = 8 * wave + cc;
+      const int64_t j = j_base + 64 * h + col;
+      const v2d* cs = reinterpret_cast<const v2d*>(Cs + col * CS + 4 * lane);
+      const v2d u0 = cs[0], u1 = cs[1];
+      v2d* dst = reinterpret_cast<v2d*>(C + i0 + j * ldc);
+      if (j < N && lo_ok) dst[0] = cg[cc][0] + alpha * u0;
+      if (j < N && hi_ok) dst[1] = cg[cc][1] + alpha * u1;
+    }
+    __syncthreads();
   }
 }
 
@@ -412,8 +432,9 @@ __global__ __launch_bounds__(512) void k_gemm_nt_dma32(float* __restrict__ C, in
                                                        int64_t lda, const float* __restrict__ B, int64_t ldb,
                                                        int64_t M, int64_t N, int64_t K, float alpha, int lower,
                                                        int64_t gr, int64_t gc, int tiles_n) {
-  __shared__ float As[DST][FK][DM];
-  __shared__ float Bs[DST][FK][DN];
+  __shared__ __align__(16) float smem[DST * FK * DM + DST * FK * DN];
+  float(*As)[FK][DM] = reinterpret_cast<float(*)[FK][DM]>(smem);
+  float(*Bs)[FK][DN] = reinterpret_cast<float(*)[FK][DN]>(smem + DST * FK * DM);
   const int tile_m = blockIdx.x / tiles_n, tile_n = blockIdx.x % tiles_n;
   const int64_t i_base = (int64_t)tile_m * DM, j_base = (int64_t)tile_n * DN;
   if (lower && gr + i_base + DM - 1 < gc + j_base) return;
@@ -479,31 +500,41 @@ __global__ __launch_bounds__(512) void k_gemm_nt_dma32(float* __restrict__ C, in
         for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<float>::op(ao[a], bo[b], acc[a][b]);
     }
   }
+  // epilogue through LDS as in the FP64 kernel; M is a multiple of four
+  // here, so each lane's 16-byte piece of a column is wholly inside or
+  // wholly outside
+  constexpr int CS = DM + 4;
+  static_assert(DN / 2 * CS <= DST * FK * (DM + DN), "C staging fits the operand ring");
+  __syncthreads();
+  float* Cs = smem;
+  const int64_t i0 = i_base + 4 * lane;
+  const bool ok = i0 < M;
 #pragma unroll
-  for (int h = 0; h < 4; h += 2) {
-    float cv[2][4][4];
+  for (int h = 0; h < 2; ++h) {
+    if (wn == 64 * h) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int64_t j = std::min<int64_t>(j_base + wn + b * 16 + (lane & 15), N - 1);
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t i = std::min<int64_t>(i_base + wm + (h + a) * 16 + Mfma<float>::row(lane, r), M - 1);
-          cv[a][b][r] = C[i + j * ldc];
-        }
-      }
+          for (int r = 0; r < 4; ++r)
+            Cs[(16 * b + (lane & 15)) * CS + wm + 16 * a + Mfma<float>::row(lane, r)] = acc[a][b][r];
+    }
+    __syncthreads();
+    v4f cg[8];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int cc = 0; cc < 8; ++cc) {
+      const int64_t j = std::min<int64_t>(j_base + 64 * h + 8 * wave + cc, N - 1);
+      cg[cc] = *reinterpret_cast<const v4f*>(C + std::min<int64_t>(i0, M - 4) + j * ldc);
+    }
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int64_t j = j_base + wn + b * 16 + (lane & 15);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t i = i_base + wm + (h + a) * 16 + Mfma<float>::row(lane, r);
-          if (i < M && j < N) C[i + j * ldc] = cv[a][b][r] + alpha * acc[h + a][b][r];
-        }
-      }
+    for (int cc = 0; cc < 8; ++cc) {
+      const int col = 8 * wave + cc;
+      const int64_t j = j_base + 64 * h + col;
+      const v4f u = *reinterpret_cast<const v4f*>(Cs + col * CS + 4 * lane);
+      if (j < N && ok) *reinterpret_cast<v4f*>(C + i0 + j * ldc) = cg[cc] + alpha * u;
+    }
+    __syncthreads();
   }
 }
 
@@ -561,7 +592,7 @@ void gemm_nt(T* C, int64_t ldc, const T* A, int64_t lda, const T* B, int64_t ldb
   if (M <= 0 || N <= 0 || K <= 0) return;
   if constexpr (std::is_same<T, double>::value) {
     const int64_t Mp = M & ~int64_t(1), Np = N & ~int64_t(1);   // whole row pairs
-    if (dma_ok(A, lda, B, ldb, Mp, Np, K)) {
+    if (dma_ok(A, lda, B, ldb, Mp, Np, K) && Mp >= 4 && ((uintptr_t)C % 16) == 0 && ldc % 2 == 0) {
       const int tm = (int)ceil_div(Mp, DM), tn = (int)ceil_div(Np, DN);
       hipLaunchKernelGGL(k_gemm_nt_dma, dim3(tm * tn), dim3(512), 0, st, C, ldc, A, lda, B, ldb, Mp, Np, K, alpha,
                          lower ? 1 : 0, gr, gc, tn);
@@ -571,7 +602,7 @@ void gemm_nt(T* C, int64_t ldc, const T* A, int64_t lda, const T* B, int64_t ldb
     }
   } else {
     const int64_t Mp = M & ~int64_t(3), Np = N & ~int64_t(3);   // whole groups of four rows
-    if (dma32_ok(A, lda, B, ldb, Mp, Np, K)) {
+    if (dma32_ok(A, lda, B, ldb, Mp, Np, K) && ((uintptr_t)C % 16) == 0 && ldc % 4 == 0) {
       const int tm = (int)ceil_div(Mp, DM), tn = (int)ceil_div(Np, DN);
       hipLaunchKernelGGL(k_gemm_nt_dma32, dim3(tm * tn), dim3(512), 0, st, C, ldc, A, lda, B, ldb, Mp, Np, K, alpha,
                          lower ? 1 : 0, gr, gc, tn);
