@@ -56,86 +56,148 @@ constexpr int NB = 256;   // delayed-update panel width (multiple of BS)
 // ---------------------------------------------------------------------------
 // diagonal block: Cholesky + inverse of the factor, one wave
 // ---------------------------------------------------------------------------
-// value of v in lane `src` (compile-time), for every lane
-__device__ inline double lane_bcast(double v, int src) {
+// value of v in a runtime-uniform lane
+__device__ inline double lane_bcast_u(double v, int src) {
   const unsigned long long u = (unsigned long long)__double_as_longlong(v);
   const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, src);
   const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), src);
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-__device__ inline float lane_bcast(float v, int src) {
+__device__ inline float lane_bcast_u(float v, int src) {
   return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), src));
 }
+__device__ inline double lane_shfl(double v, int src) { return __shfl(v, src, 64); }
+__device__ inline float lane_shfl(float v, int src) { return __shfl(v, src, 64); }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ A, int64_t ld, int64_t c, int64_t n,
                                                    T* __restrict__ Linv, double tol, double fix,
                                                    unsigned long long* __restrict__ hits) {
-  // Right-looking Cholesky of one 64 x 64 diagonal block.  Thread (i, p) =
-  // (lane, wave) keeps r[q] = A[i][16p + q] and y[q] = (L^-1)[i][16p + q]; the
-  // inverse is produced by applying the same row operations to the identity.
-  // One barrier per column: the owning wave publishes the raw column j in a
-  // double-buffered LDS slot, every thread derives the pivot, its own
-  // multiplier and those of its columns from it, and row j of L^-1 (which a
-  // wave needs only for its own columns) is taken from lane j by readlane.
-  __shared__ T colb[2][BS];
+  // Cholesky of one 64 x 64 diagonal block and the inverse of its factor, by
+  // 16-column blocks.  Thread (i, p) = (lane, wave) keeps r[q] = A[i][16p + q].
+  // Column block pj is factored by wave pj alone: the pivot comes from lane
+  // j by readlane and so do the multipliers of the later columns, so the 16
+  // steps need no barrier.  The finished block goes to LDS and the waves to
+  // its right apply it (a rank-16 update), one barrier per block.  L^-1 is
+  // then built by 16 x 16 blocks: each wave inverts its diagonal block by
+  // forward substitution (rows exchanged with shuffles), and the blocks
+  // below the diagonal follow by distance from it,
+  // Y_ij = -Y_ii sum_{k=j}^{i-1} L_ik Y_kj.
+  __shared__ T Ls[BS][BS + 1];          // L, then read by the inverse
+  __shared__ T Ys[BS][BS + 1];          // L^-1
+  __shared__ T Ts[4][16][17];           // per-wave scratch of the inverse
   const int lane = threadIdx.x & 63;
-  const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index (uniform)
+  const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int bs = (int)std::min<int64_t>(BS, n - c);
-  T r[16], y[16];
-  // loads from clamped (always valid) addresses so that all 16 are in flight
-  // at once; a ragged last block is padded with the identity
+  T r[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int k = 16 * p + q;
     const T g = A[(c + std::min(lane, bs - 1)) + (c + std::min(k, bs - 1)) * ld];
     r[q] = (lane < bs && k < bs) ? (k <= lane ? g : T(0)) : (lane == k ? T(1) : T(0));
-    y[q] = (lane == k) ? T(1) : T(0);
   }
   int nhits = 0;
-  // column j = 16 pj + qj: the loop over the owning wave pj is a runtime loop,
-  // the 16 columns of a wave are unrolled so r[qj] and y[q] index registers
+  // ---- L: column block pj is factored by its owning wave alone (pivots by
+  // readlane, no barrier), published, and applied by the waves to its right
 #pragma unroll 1
-  for (int pj = 0; pj < 4; ++pj)
+  for (int pj = 0; pj < 4; ++pj) {
+    if (p == pj) {
 #pragma unroll
-  for (int qj = 0; qj < 16; ++qj) {
-    const int j = 16 * pj + qj, bj = qj & 1;
-    if (p == pj) colb[bj][lane] = r[qj];
+      for (int qj = 0; qj < 16; ++qj) {
+        const int j = 16 * pj + qj;
+        double d = (double)lane_bcast_u(r[qj], j);
+        if (j < bs && !(d > tol)) {
+          d = fix;
+          ++nhits;
+        }
+        double e = __builtin_amdgcn_rsq(d);
+        e = e * (1.5 - 0.5 * d * e * e);
+        e = e * (1.5 - 0.5 * d * e * e);
+        const T inv = (T)e, ljj = (T)(d * e);
+        const T li = (lane > j) ? r[qj] * inv : T(0);
+        r[qj] = (lane == j) ? ljj : li;   // zero above the diagonal
+#pragma unroll
+        for (int q = qj + 1; q < 16; ++q) r[q] -= li * lane_bcast_u(li, 16 * pj + q);
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) Ls[lane][16 * pj + q] = (16 * pj + q <= lane) ? r[q] : T(0);
+    }
     __syncthreads();
-    double d = (double)colb[bj][j];
-    if (j < bs && !(d > tol)) {
-      d = fix;
-      ++nhits;
-    }
-    // 1/sqrt(d) from the hardware estimate and two Newton steps
-    double e = __builtin_amdgcn_rsq(d);
-    e = e * (1.5 - 0.5 * d * e * e);
-    e = e * (1.5 - 0.5 * d * e * e);
-    const T inv = (T)e, ljj = (T)(d * e);
-    const T li = (lane > j) ? colb[bj][lane] * inv : T(0);
-    if (p == pj) r[qj] = (lane == j) ? ljj : (lane > j ? li : r[qj]);
-    if (p >= pj) {
-      T lk[16];   // all 16 reads issued before the first use
+    if (p > pj) {
+      T a[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) lk[q] = colb[bj][16 * p + q];
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (16 * p + q > j) r[q] -= li * (lk[q] * inv);
-    }
-    if (p <= pj) {
+      for (int t = 0; t < 16; ++t) a[t] = Ls[lane][16 * pj + t];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const T yj = lane_bcast(y[q], j) * inv;   // (L^-1)[j][16p + q]
-        y[q] = (lane == j) ? yj : y[q] - li * yj;
+        T s = 0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) s += a[t] * Ls[16 * p + q][16 * pj + t];
+        r[q] -= s;
       }
     }
   }
-  if (threadIdx.x == 0 && nhits) atomicAdd(hits, (unsigned long long)nhits);
+  if (lane == 0 && nhits) atomicAdd(hits, (unsigned long long)nhits);
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int k = 16 * p + q;
     if (lane < bs && k < bs && k <= lane) A[(c + lane) + (c + k) * ld] = r[q];
-    Linv[lane + k * BS] = (k <= lane) ? y[q] : T(0);
+  }
+  // ---- L^-1 by 16 x 16 blocks.  Lane (s, g) = (lane % 16, lane / 16) holds
+  // row s, columns 4g .. 4g + 3 of a block.
+  const int s = lane & 15, g = lane >> 4;
+  {
+    // diagonal block p: forward substitution over its rows
+    const int o = 16 * p;
+    T y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) y[u] = (s == 4 * g + u) ? T(1) : T(0);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const T dinv = T(1) / Ls[o + t][o + t];
+      const T lst = Ls[o + s][o + t];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const T yt = lane_shfl(y[u], t + 16 * g) * dinv;   // row t, final
+        y[u] = (s == t) ? yt : ((s > t) ? y[u] - lst * yt : y[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) Ys[o + s][o + 4 * g + u] = y[u];
+  }
+  __syncthreads();
+  // off-diagonal blocks by distance from the diagonal:
+  //   Y_ij = -Y_ii sum_{k=j}^{i-1} L_ik Y_kj
+#pragma unroll 1
+  for (int dist = 1; dist < 4; ++dist) {
+    if (p + dist < 4) {
+      const int i = p + dist, j = p;
+      T t4[4] = {};
+      for (int k = j; k < i; ++k)
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const T l = Ls[16 * i + s][16 * k + m];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) t4[u] += l * Ys[16 * k + m][16 * j + 4 * g + u];
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Ts[p][s][4 * g + u] = t4[u];
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // this wave's scratch writes landed
+      T o4[4] = {};
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const T yim = Ys[16 * i + s][16 * i + m];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) o4[u] -= yim * Ts[p][m][4 * g + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Ys[16 * i + s][16 * j + 4 * g + u] = o4[u];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = 16 * p + q;
+    Linv[lane + k * BS] = (k <= lane) ? Ys[lane][k] : T(0);
   }
 }
 
