@@ -910,32 +910,32 @@ void dense_block_inverses(const T* L, int64_t n, int64_t ld, const T* Linv, T* X
 // and the 16 partial sums meet in LDS.  The stored inverse is zero outside
 // its triangle and bb is zero past cb, so loads and products need no masks.
 constexpr int DIAG_ROWS = 16;
-template <typename T>
+template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_trsv_diag(const T* __restrict__ Xinv, int64_t c, int64_t n,
                                                    const T* __restrict__ Bin, T* __restrict__ Yout, int nrhs) {
-  __shared__ T bb[SB][MAXRHS];
-  __shared__ T part[16][DIAG_ROWS][MAXRHS];
+  __shared__ T bb[SB][NR];
+  __shared__ T part[16][DIAG_ROWS][NR];
   const int tid = threadIdx.x;
   const int cb = (int)std::min<int64_t>(SB, n - c);
-  for (int e = tid; e < SB * MAXRHS; e += 256) {
+  for (int e = tid; e < SB * NR; e += 256) {
     const int i = e % SB, r = e / SB;
     bb[i][r] = (i < cb && r < nrhs) ? Bin[(c + i) + r * n] : T(0);
   }
   __syncthreads();
   const int il = tid % DIAG_ROWS, g = tid / DIAG_ROWS;
   const int i = blockIdx.x * DIAG_ROWS + il;
-  T acc[MAXRHS] = {};
+  T acc[NR] = {};
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int k = g * 16 + q;
     const T x = Xinv[i + (int64_t)k * SB];
 #pragma unroll
-    for (int r = 0; r < MAXRHS; ++r) acc[r] += x * bb[k][r];
+    for (int r = 0; r < NR; ++r) acc[r] += x * bb[k][r];
   }
 #pragma unroll
-  for (int r = 0; r < MAXRHS; ++r) part[g][il][r] = acc[r];
+  for (int r = 0; r < NR; ++r) part[g][il][r] = acc[r];
   __syncthreads();
-  if (tid < DIAG_ROWS * MAXRHS) {
+  if (tid < DIAG_ROWS * NR) {
     const int row = tid % DIAG_ROWS, r = tid / DIAG_ROWS;
     T v = 0;
 #pragma unroll
@@ -949,14 +949,14 @@ __global__ __launch_bounds__(256) void k_trsv_diag(const T* __restrict__ Xinv, i
 // rows; wave w sums columns [16 w, 16 w + 16) with one lane per row (each
 // column read is 512 contiguous bytes, 16 loads in flight per lane), and the
 // 16 partial sums meet in LDS.
-template <typename T>
+template <typename T, int NR>
 __global__ __launch_bounds__(1024) void k_trsv_fwd_update(const T* __restrict__ L, int64_t ld, int64_t c, int64_t n,
                                                           T* __restrict__ B, const T* __restrict__ Y, int nrhs) {
-  __shared__ T yb[SB][MAXRHS];
-  __shared__ T part[16][64][MAXRHS];
+  __shared__ T yb[SB][NR];
+  __shared__ T part[16][64][NR];
   const int tid = threadIdx.x;
   const int cb = (int)std::min<int64_t>(SB, n - c);
-  for (int e = tid; e < SB * MAXRHS; e += 1024) {
+  for (int e = tid; e < SB * NR; e += 1024) {
     const int i = e % SB, r = e / SB;
     yb[i][r] = (i < cb && r < nrhs) ? Y[(c + i) + r * n] : T(0);
   }
@@ -964,18 +964,18 @@ __global__ __launch_bounds__(1024) void k_trsv_fwd_update(const T* __restrict__ 
   const int lane = tid & 63, w = tid >> 6;
   const int64_t row = c + cb + (int64_t)blockIdx.x * 64 + lane;
   const int64_t rowc = std::min<int64_t>(row, n - 1);
-  T acc[MAXRHS] = {};
+  T acc[NR] = {};
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int k = w * 16 + q;
     const T l = L[rowc + (c + std::min(k, cb - 1)) * ld];   // yb is zero past cb
 #pragma unroll
-    for (int r = 0; r < MAXRHS; ++r) acc[r] += l * yb[k][r];
+    for (int r = 0; r < NR; ++r) acc[r] += l * yb[k][r];
   }
 #pragma unroll
-  for (int r = 0; r < MAXRHS; ++r) part[w][lane][r] = acc[r];
+  for (int r = 0; r < NR; ++r) part[w][lane][r] = acc[r];
   __syncthreads();
-  if (tid < 64 * MAXRHS) {
+  if (tid < 64 * NR) {
     const int ln = tid % 64, r = tid / 64;
     const int64_t rw = c + cb + (int64_t)blockIdx.x * 64 + ln;
     T v = 0;
@@ -988,20 +988,20 @@ __global__ __launch_bounds__(1024) void k_trsv_fwd_update(const T* __restrict__ 
 // columns left of the block: Y[j] -= sum_i L[c + i, j] x[i]; each wave takes
 // four columns (16 loads in flight per lane), lanes run over i
 constexpr int BWD_COLS = 4;
-template <typename T>
+template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_trsv_bwd_update(const T* __restrict__ L, int64_t ld, int64_t c, int64_t n,
                                                          T* __restrict__ Yv, const T* __restrict__ X, int nrhs) {
-  __shared__ T xb[SB][MAXRHS];
+  __shared__ T xb[SB][NR];
   const int tid = threadIdx.x;
   const int cb = (int)std::min<int64_t>(SB, n - c);
-  for (int e = tid; e < SB * MAXRHS; e += 256) {
+  for (int e = tid; e < SB * NR; e += 256) {
     const int i = e % SB, r = e / SB;
     xb[i][r] = (i < cb && r < nrhs) ? X[(c + i) + r * n] : T(0);
   }
   __syncthreads();
   const int lane = tid & 63;
   const int64_t j0 = ((int64_t)blockIdx.x * 4 + (tid >> 6)) * BWD_COLS;
-  T acc[BWD_COLS][MAXRHS] = {};
+  T acc[BWD_COLS][NR] = {};
 #pragma unroll
   for (int cc = 0; cc < BWD_COLS; ++cc) {
     const int64_t j = std::min<int64_t>(j0 + cc, c - 1);
@@ -1010,13 +1010,13 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_update(const T* __restrict__ L
       const int i = lane + 64 * q;
       const T l = L[(c + std::min(i, cb - 1)) + j * ld];   // xb is zero past cb
 #pragma unroll
-      for (int r = 0; r < MAXRHS; ++r) acc[cc][r] += l * xb[i][r];
+      for (int r = 0; r < NR; ++r) acc[cc][r] += l * xb[i][r];
     }
   }
 #pragma unroll
   for (int cc = 0; cc < BWD_COLS; ++cc)
 #pragma unroll
-    for (int r = 0; r < MAXRHS; ++r) {
+    for (int r = 0; r < NR; ++r) {
       T v = acc[cc][r];
       for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
       acc[cc][r] = v;
@@ -1026,36 +1026,45 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_update(const T* __restrict__ L
     for (int cc = 0; cc < BWD_COLS; ++cc)
       if (j0 + cc < c)
 #pragma unroll
-        for (int r = 0; r < MAXRHS; ++r)
+        for (int r = 0; r < NR; ++r)
           if (r < nrhs) Yv[(j0 + cc) + r * n] -= acc[cc][r];
 }
 
-template <typename T>
-void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT256, T* B, T* Y, T* X, int nrhs,
-                 hipStream_t st) {
-  if (n <= 0) return;
+template <typename T, int NR>
+static void dense_solve_nr(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT256, T* B, T* Y, T* X,
+                           int nrhs, hipStream_t st) {
   for (int64_t c = 0; c < n; c += SB) {
     const T* Xi = X256 + (c / SB) * SB * SB;
-    hipLaunchKernelGGL(k_trsv_diag<T>, dim3(SB / DIAG_ROWS), dim3(256), 0, st, Xi, c, n, (const T*)B, Y, nrhs);
+    hipLaunchKernelGGL((k_trsv_diag<T, NR>), dim3(SB / DIAG_ROWS), dim3(256), 0, st, Xi, c, n, (const T*)B, Y, nrhs);
     HC_LAUNCH_CHECK();
     const int64_t below = n - std::min<int64_t>(n, c + SB);
     if (below > 0) {
-      hipLaunchKernelGGL(k_trsv_fwd_update<T>, dim3((unsigned)ceil_div(below, 64)), dim3(1024), 0, st, L, ld, c, n, B,
-                         (const T*)Y, nrhs);
+      hipLaunchKernelGGL((k_trsv_fwd_update<T, NR>), dim3((unsigned)ceil_div(below, 64)), dim3(1024), 0, st, L, ld, c,
+                         n, B, (const T*)Y, nrhs);
       HC_LAUNCH_CHECK();
     }
   }
   const int64_t last = ((n - 1) / SB) * SB;
   for (int64_t c = last; c >= 0; c -= SB) {
     const T* XTi = XT256 + (c / SB) * SB * SB;
-    hipLaunchKernelGGL(k_trsv_diag<T>, dim3(SB / DIAG_ROWS), dim3(256), 0, st, XTi, c, n, (const T*)Y, X, nrhs);
+    hipLaunchKernelGGL((k_trsv_diag<T, NR>), dim3(SB / DIAG_ROWS), dim3(256), 0, st, XTi, c, n, (const T*)Y, X, nrhs);
     HC_LAUNCH_CHECK();
     if (c > 0) {
-      hipLaunchKernelGGL(k_trsv_bwd_update<T>, dim3((unsigned)ceil_div(c, 4 * BWD_COLS)), dim3(256), 0, st, L, ld, c, n, Y,
-                         (const T*)X, nrhs);
+      hipLaunchKernelGGL((k_trsv_bwd_update<T, NR>), dim3((unsigned)ceil_div(c, 4 * BWD_COLS)), dim3(256), 0, st, L, ld,
+                         c, n, Y, (const T*)X, nrhs);
       HC_LAUNCH_CHECK();
     }
   }
+}
+
+// kernels specialised for one right-hand side (the iteration's case) and for
+// up to MAXRHS
+template <typename T>
+void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT256, T* B, T* Y, T* X, int nrhs,
+                 hipStream_t st) {
+  if (n <= 0) return;
+  if (nrhs == 1) dense_solve_nr<T, 1>(L, n, ld, X256, XT256, B, Y, X, nrhs, st);
+  else dense_solve_nr<T, MAXRHS>(L, n, ld, X256, XT256, B, Y, X, nrhs, st);
 }
 
 template void dense_cholesky<double>(double*, int64_t, int64_t, double*, double, double, unsigned long long*,
