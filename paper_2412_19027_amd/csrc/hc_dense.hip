@@ -204,46 +204,40 @@ __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ A, int64_t ld
 // ---------------------------------------------------------------------------
 // TRSM: rows [r0, r1) of the 64 columns starting at c: A21 <- A21 * Linv'
 // ---------------------------------------------------------------------------
+// On MFMA with operands straight from global memory (Linv is 32 KB and stays
+// in cache): each wave takes 16 rows and all 64 columns (four 16 x 16 output
+// tiles, 16 k-steps of four).  No LDS and few registers, so a workgroup fits
+// beside a running trailing-update workgroup on the same CU instead of
+// waiting for one to finish: this kernel sits on the factorisation's critical
+// path while the trailing update runs.
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsm(T* __restrict__ A, int64_t ld, int64_t c, int64_t r0, int64_t r1,
-                                              const T* __restrict__ Linv) {
-  __shared__ T Xs[BS][BS + 1];   // A rows (local row, k)
-  __shared__ T Ls[BS][BS + 1];   // Linv (j, k)
-  const int tid = threadIdx.x;
-  const int64_t rb = r0 + (int64_t)blockIdx.x * BS;
-  // rows past r1 repeat the last row (never stored), so every load is
-  // unconditional and all of them are in flight together
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_trsm(
+    T* __restrict__ A, int64_t ld, int64_t c, int64_t r0, int64_t r1, const T* __restrict__ Linv) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t rb = r0 + (int64_t)blockIdx.x * BS + wave * 16;   // first row of this wave
+  // operand lanes: A[i = lane % 16][k = lane / 16], B[k = lane / 16][j = lane % 16]
+  const int64_t ra = std::min<int64_t>(rb + (lane & 15), r1 - 1);   // rows past r1 repeat the last one
+  const T* pa = A + ra + (c + (lane >> 4)) * ld;
+  const T* pb = Linv + (lane & 15) + (lane >> 4) * BS;
+  acc_t acc[4];
 #pragma unroll
-  for (int t = 0; t < BS * BS / 256; ++t) {
-    const int e = tid + 256 * t;
-    const int i = e % BS, k = e / BS;
-    const int64_t r = std::min<int64_t>(rb + i, r1 - 1);
-    Xs[i][k] = A[r + (c + k) * ld];
-    Ls[i][k] = Linv[i + k * BS];
+  for (int t = 0; t < 4; ++t) acc[t] = acc_t{0, 0, 0, 0};
+#pragma unroll 2
+  for (int kk = 0; kk < BS; kk += 4) {
+    const T a = pa[(int64_t)kk * ld];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::op(a, pb[16 * t + kk * BS], acc[t]);
   }
-  __syncthreads();
-  // each thread computes a 4 x 4 sub-block: rows 4*(tid%16)+a, cols 4*(tid/16)+b
-  const int i0 = 4 * (tid % 16), j0 = 4 * (tid / 16);
-  T acc[4][4] = {};
-  for (int k = 0; k < BS; ++k) {
-    T xa[4], lb[4];
+  // X[i][j] = sum_k A[i][k] Linv[j][k]; stores after this wave's loads of the
+  // same rows (program order), other waves own other rows
 #pragma unroll
-    for (int a = 0; a < 4; ++a) xa[a] = Xs[i0 + a][k];
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) lb[b] = Ls[j0 + b][k];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += xa[a] * lb[b];
-  }
-  // X[i][j] = sum_k A[i][k] Linv[j][k]; only k <= j contributes (Linv lower)
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    int64_t r = rb + i0 + a;
-    if (r < r1)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) A[r + (c + j0 + b) * ld] = acc[a][b];
-  }
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = rb + Mfma<T>::row(lane, r);
+      if (row < r1) A[row + (c + 16 * t + (lane & 15)) * ld] = acc[t][r];
+    }
 }
 
 // ---------------------------------------------------------------------------
