@@ -511,18 +511,20 @@ __device__ void psd_jacobi_cols(double* B, int k, double* W) {
 }
 // cyclic Jacobi eigenvalues of a symmetric matrix (destroys A); returns lambda_min
 __device__ double psd_min_eig(double* A, int k) {
+  // an off-diagonal entry below 1e-18 |A|_F moves no eigenvalue by more than
+  // rounding does, so it is not rotated away; the sweeps end when a sweep
+  // rotates nothing (quadratic convergence: a handful of sweeps), or at 60
+  double tot = 0;
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) tot += sq(A[i * PSD_KMAX + j]);
+  const double small = 1e-18 * sqrt(tot);
   for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0, tot = 0;
-    for (int i = 0; i < k; ++i)
-      for (int j = 0; j < k; ++j) {
-        tot += sq(A[i * PSD_KMAX + j]);
-        if (i != j) off += sq(A[i * PSD_KMAX + j]);
-      }
-    if (off <= 1e-32 * tot) break;
+    bool rot = false;
     for (int p = 0; p < k - 1; ++p)
       for (int q = p + 1; q < k; ++q) {
         const double apq = A[p * PSD_KMAX + q];
-        if (apq == 0.0) continue;
+        if (!(fabs(apq) > small)) continue;
+        rot = true;
         const double theta = (A[q * PSD_KMAX + q] - A[p * PSD_KMAX + p]) / (2.0 * apq);
         const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(1.0 + theta * theta));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
@@ -537,22 +539,44 @@ __device__ double psd_min_eig(double* A, int k) {
           A[q * PSD_KMAX + r] = s * apr + c * aqr;
         }
       }
+    if (!rot) break;
   }
   double m = A[0];
   for (int i = 1; i < k; ++i) m = fmin(m, A[i * PSD_KMAX + i]);
   return m;
 }
 
+// ---------------------------------------------------------------------------
+// PSD kernels: one lane per cone, with the lane's k x k matrices in an LDS
+// slice of its own (private arrays of this size would sit in scratch memory,
+// and the per-entry loops below would pay a memory round trip on every
+// access).  Blocks of PSD_TB lanes keep the slices within LDS; slice strides
+// are odd so the lanes of a block fall on distinct banks.
+// ---------------------------------------------------------------------------
+constexpr int PSD_MAT = PSD_KMAX * PSD_KMAX;
+constexpr int PSD_SVEC = PSD_KMAX * (PSD_KMAX + 1) / 2;
+constexpr int PSD_TB = 8;
+constexpr int odd_stride(int n) { return n | 1; }
+constexpr int WS_SCALE = odd_stride(9 * PSD_MAT + 2 * PSD_KMAX);
+constexpr int WS_APPLY = odd_stride(4 * PSD_MAT + PSD_KMAX + PSD_SVEC);
+constexpr int WS_DS = odd_stride(8 * PSD_MAT + PSD_KMAX);
+constexpr int WS_STEP = odd_stride(3 * PSD_MAT);
+inline int psd_blocks(int64_t count) { return (int)std::max<int64_t>(1, ceil_div(count, PSD_TB)); }
+
 // PSD state fields: R (k*k row-major) | Rinv | Q | lambda (k) | m (k)
-__global__ void k_psd_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
-                            double* __restrict__ hdiag) {
+__global__ __launch_bounds__(PSD_TB) void k_psd_scale(SegDev g, const double* __restrict__ s,
+                                                      const double* __restrict__ z, double* __restrict__ hdiag) {
+  __shared__ double wsall[PSD_TB * WS_SCALE];
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.count) return;
   const int k = g.k, sd = g.dim;
   const int64_t N = g.count;
   const double* sc = s + g.base + c * sd;
   const double* zc = z + g.base + c * sd;
-  double Ls[PSD_KMAX * PSD_KMAX], Lz[PSD_KMAX * PSD_KMAX], B[PSD_KMAX * PSD_KMAX], W[PSD_KMAX * PSD_KMAX];
+  double* ws = wsall + threadIdx.x * WS_SCALE;
+  double *Ls = ws, *Lz = ws + PSD_MAT, *B = ws + 2 * PSD_MAT, *W = ws + 3 * PSD_MAT, *R = ws + 4 * PSD_MAT,
+         *Ri = ws + 5 * PSD_MAT, *Rt = ws + 6 * PSD_MAT, *Q = ws + 7 * PSD_MAT, *Mm = ws + 8 * PSD_MAT,
+         *lam = ws + 9 * PSD_MAT, *m = lam + PSD_KMAX;
   psd_smat(sc, k, Ls);
   psd_smat(zc, k, Lz);
   psd_chol(Ls, k);
@@ -565,14 +589,12 @@ __global__ void k_psd_scale(SegDev g, const double* __restrict__ s, const double
       B[i * PSD_KMAX + j] = acc;
     }
   psd_jacobi_cols(B, k, W);   // B W = U diag(lam): V = W
-  double lam[PSD_KMAX];
   for (int j = 0; j < k; ++j) {
     double acc = 0;
     for (int r = 0; r < k; ++r) acc += B[r * PSD_KMAX + j] * B[r * PSD_KMAX + j];
     lam[j] = sqrt(acc);
   }
   // R = Ls V lam^-1/2 ; Rinv = lam^-1/2 U' Lz' with U = B diag(1/lam)
-  double R[PSD_KMAX * PSD_KMAX], Ri[PSD_KMAX * PSD_KMAX];
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
@@ -586,11 +608,9 @@ __global__ void k_psd_scale(SegDev g, const double* __restrict__ s, const double
       Ri[i * PSD_KMAX + j] = acc / sqrt(lam[i]);
     }
   // M = R R' = Q diag(m) Q': one-sided Jacobi on the columns of R' gives Q
-  double Rt[PSD_KMAX * PSD_KMAX], Q[PSD_KMAX * PSD_KMAX];
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) Rt[i * PSD_KMAX + j] = R[j * PSD_KMAX + i];
   psd_jacobi_cols(Rt, k, Q);
-  double m[PSD_KMAX];
   for (int j = 0; j < k; ++j) {
     double acc = 0;
     for (int r = 0; r < k; ++r) acc += Rt[r * PSD_KMAX + j] * Rt[r * PSD_KMAX + j];
@@ -608,7 +628,6 @@ __global__ void k_psd_scale(SegDev g, const double* __restrict__ s, const double
     g.state[(3 * kk + k + j) * N + c] = m[j];
   }
   // diag of H in svec coordinates: H[(a,b),(a,b)] = (M_aa M_bb + M_ab^2) (off-diag) or M_aa^2
-  double Mm[PSD_KMAX * PSD_KMAX];
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
@@ -644,7 +663,7 @@ void cone_scale(const SegDev& g, const double* s, const double* z, double mu, in
                          pd_count);
       break;
     case HC_CONE_PSD:
-      hipLaunchKernelGGL(k_psd_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, hdiag);
+      hipLaunchKernelGGL(k_psd_scale, dim3(psd_blocks(g.count)), dim3(PSD_TB), 0, st, g, s, z, hdiag);
       break;
   }
   HC_LAUNCH_CHECK();
@@ -655,10 +674,12 @@ void cone_scale(const SegDev& g, const double* s, const double* z, double mu, in
 // ===========================================================================
 __device__ inline double fsel(int mode, double lam, double delta) { return mode == 0 ? lam : 1.0 / (lam + delta); }
 
-__device__ void psd_apply_one(const SegDev& g, int64_t c, int mode, double delta, const double* x, double* y) {
+// y = H x (mode 0) or (H + delta I)^-1 x (mode 1) for PSD cone c; ws: WS_APPLY doubles
+__device__ void psd_apply_one(const SegDev& g, int64_t c, int mode, double delta, const double* x, double* y,
+                              double* ws) {
   const int k = g.k;
   const int64_t N = g.count, kk = (int64_t)k * k;
-  double Q[PSD_KMAX * PSD_KMAX], m[PSD_KMAX], X[PSD_KMAX * PSD_KMAX], T[PSD_KMAX * PSD_KMAX];
+  double *Q = ws, *X = ws + PSD_MAT, *T = ws + 2 * PSD_MAT, *U = ws + 3 * PSD_MAT, *m = ws + 4 * PSD_MAT;
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) Q[i * PSD_KMAX + j] = g.state[(2 * kk + i * k + j) * N + c];
   for (int j = 0; j < k; ++j) m[j] = g.state[(3 * kk + k + j) * N + c];
@@ -670,7 +691,6 @@ __device__ void psd_apply_one(const SegDev& g, int64_t c, int mode, double delta
       for (int p = 0; p < k; ++p) acc += X[i * PSD_KMAX + p] * Q[p * PSD_KMAX + j];
       T[i * PSD_KMAX + j] = acc;   // X Q
     }
-  double U[PSD_KMAX * PSD_KMAX];
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
@@ -745,19 +765,25 @@ __global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __r
       for (int j = 0; j < 3; ++j) y[g.base + j * N + i] = V[j * 3 + 0] * p[0] + V[j * 3 + 1] * p[1] + V[j * 3 + 2] * p[2];
       break;
     }
-    case HC_CONE_PSD: {
-      double xv[PSD_KMAX * (PSD_KMAX + 1) / 2], yv[PSD_KMAX * (PSD_KMAX + 1) / 2];
-      for (int p = 0; p < g.dim; ++p) xv[p] = x[g.base + i * g.dim + p];
-      psd_apply_one(g, i, mode, delta, xv, yv);
-      for (int p = 0; p < g.dim; ++p) y[g.base + i * g.dim + p] = yv[p];
-      break;
-    }
+    case HC_CONE_PSD:
+      break;   // k_psd_apply
   }
+}
+
+__global__ __launch_bounds__(PSD_TB) void k_psd_apply(SegDev g, int mode, double delta, const double* __restrict__ x,
+                                                      double* __restrict__ y) {
+  __shared__ double wsall[PSD_TB * WS_APPLY];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.count) return;
+  psd_apply_one(g, i, mode, delta, x + g.base + i * g.dim, y + g.base + i * g.dim, wsall + threadIdx.x * WS_APPLY);
 }
 
 void cone_apply(const SegDev& g, int mode, double delta, const double* x, double* y, hipStream_t st) {
   if (g.count == 0) return;
-  hipLaunchKernelGGL(k_cone_apply, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, mode, delta, x, y);
+  if (g.kind == HC_CONE_PSD)
+    hipLaunchKernelGGL(k_psd_apply, dim3(psd_blocks(g.count)), dim3(PSD_TB), 0, st, g, mode, delta, x, y);
+  else
+    hipLaunchKernelGGL(k_cone_apply, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, mode, delta, x, y);
   HC_LAUNCH_CHECK();
 }
 
@@ -800,38 +826,46 @@ __global__ void k_cone_recover(SegDev g, const double* __restrict__ dsr, const d
             -dsr[g.base + j * N + i] - (V[j * 3 + 0] * p[0] + V[j * 3 + 1] * p[1] + V[j * 3 + 2] * p[2]);
       break;
     }
-    case HC_CONE_PSD: {
-      double xv[PSD_KMAX * (PSD_KMAX + 1) / 2], yv[PSD_KMAX * (PSD_KMAX + 1) / 2];
-      for (int p = 0; p < g.dim; ++p) xv[p] = dz[g.base + i * g.dim + p];
-      psd_apply_one(g, i, 0, 0.0, xv, yv);
-      for (int p = 0; p < g.dim; ++p) out[g.base + i * g.dim + p] = -dsr[g.base + i * g.dim + p] - yv[p];
-      break;
-    }
+    case HC_CONE_PSD:
+      break;   // k_psd_recover
   }
+}
+
+__global__ __launch_bounds__(PSD_TB) void k_psd_recover(SegDev g, const double* __restrict__ dsr,
+                                                        const double* __restrict__ dz, double* __restrict__ out) {
+  __shared__ double wsall[PSD_TB * WS_APPLY];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.count) return;
+  double* ws = wsall + threadIdx.x * WS_APPLY;
+  double* yv = ws + 4 * PSD_MAT + PSD_KMAX;
+  psd_apply_one(g, i, 0, 0.0, dz + g.base + i * g.dim, yv, ws);
+  for (int p = 0; p < g.dim; ++p) out[g.base + i * g.dim + p] = -dsr[g.base + i * g.dim + p] - yv[p];
 }
 
 void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, double* out, hipStream_t st) {
   if (g.count == 0) return;
-  hipLaunchKernelGGL(k_cone_recover, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, dsrhs, dz, out);
+  if (g.kind == HC_CONE_PSD)
+    hipLaunchKernelGGL(k_psd_recover, dim3(psd_blocks(g.count)), dim3(PSD_TB), 0, st, g, dsrhs, dz, out);
+  else
+    hipLaunchKernelGGL(k_cone_recover, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, dsrhs, dz, out);
   HC_LAUNCH_CHECK();
 }
 
 // explicit lower-triangle entries of M = (H + delta I)^-1, packed index
 // p = a (a + 1) / 2 + b for a >= b, stored mblk[p * count + cone]
-__global__ void k_cone_mblock(SegDev g, double delta) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t N = g.count;
-  if (g.kind == HC_CONE_PSD) {
-    // one lane per (cone, svec row a)
-    const int sd = g.dim, k = g.k;
-    if (i >= N * sd) return;
-    const int64_t c = i / sd;
-    const int arow = (int)(i % sd);
-    const int64_t kk = (int64_t)k * k;
-    double Q[PSD_KMAX * PSD_KMAX], m[PSD_KMAX];
-    for (int r = 0; r < k; ++r)
-      for (int j = 0; j < k; ++j) Q[r * PSD_KMAX + j] = g.state[(2 * kk + r * k + j) * N + c];
-    for (int j = 0; j < k; ++j) m[j] = g.state[(3 * kk + k + j) * N + c];
+// PSD: one workgroup per cone, one lane per svec row a; Q and m of the cone
+// staged in LDS
+__global__ __launch_bounds__(128) void k_psd_mblock(SegDev g, double delta) {
+  __shared__ double Q[PSD_MAT], m[PSD_KMAX];
+  const int64_t N = g.count, c = blockIdx.x;
+  const int sd = g.dim, k = g.k;
+  const int64_t kk = (int64_t)k * k;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) Q[(e / k) * PSD_KMAX + e % k] = g.state[(2 * kk + e) * N + c];
+  for (int e = threadIdx.x; e < k; e += blockDim.x) m[e] = g.state[(3 * kk + k + e) * N + c];
+  __syncthreads();
+  const int arow = threadIdx.x;
+  if (arow >= sd) return;
+  {
     // (ia, ja) of svec row a
     int ia = 0, ja = 0;
     {
@@ -864,8 +898,12 @@ __global__ void k_cone_mblock(SegDev g, double delta) {
         const int64_t pk = (int64_t)arow * (arow + 1) / 2 + p;
         g.mblk[pk * N + c] = acc;
       }
-    return;
   }
+}
+
+__global__ void k_cone_mblock(SegDev g, double delta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = g.count;
   if (i >= N) return;
   switch (g.kind) {
     case HC_CONE_ZERO:
@@ -909,9 +947,12 @@ __global__ void k_cone_mblock(SegDev g, double delta) {
 
 void cone_mblock(const SegDev& g, double delta, hipStream_t st) {
   if (g.count == 0) return;
-  int64_t units = (g.kind == HC_CONE_PSD) ? g.count * g.dim : g.count;
-  hipLaunchKernelGGL(k_cone_mblock, dim3((unsigned)std::max<int64_t>(1, ceil_div(units, CONE_BLOCK))),
-                     dim3(CONE_BLOCK), 0, st, g, delta);
+  if (g.kind == HC_CONE_PSD)
+    hipLaunchKernelGGL(k_psd_mblock, dim3((unsigned)g.count), dim3((unsigned)(ceil_div(g.dim, 64) * 64)), 0, st, g,
+                       delta);
+  else
+    hipLaunchKernelGGL(k_cone_mblock, dim3((unsigned)std::max<int64_t>(1, ceil_div(g.count, CONE_BLOCK))),
+                       dim3(CONE_BLOCK), 0, st, g, delta);
   HC_LAUNCH_CHECK();
 }
 
@@ -1006,82 +1047,91 @@ __global__ void k_cone_ds(SegDev g, const double* __restrict__ s, const double* 
       for (int j = 0; j < 3; ++j) ds[g.base + j * N + i] = sv[j] + sm * gr[j] - 0.5 * T[j];
       break;
     }
-    case HC_CONE_PSD: {
-      const int k = g.k, sd = g.dim;
-      const int64_t kk = (int64_t)k * k;
-      double R[PSD_KMAX * PSD_KMAX], Ri[PSD_KMAX * PSD_KMAX], lam[PSD_KMAX];
-      for (int r = 0; r < k; ++r)
-        for (int j = 0; j < k; ++j) {
-          R[r * PSD_KMAX + j] = g.state[(r * k + j) * N + i];
-          Ri[r * PSD_KMAX + j] = g.state[(kk + r * k + j) * N + i];
-        }
-      for (int j = 0; j < k; ++j) lam[j] = g.state[(3 * kk + j) * N + i];
-      double dS[PSD_KMAX * PSD_KMAX], dZ[PSD_KMAX * PSD_KMAX], T1[PSD_KMAX * PSD_KMAX], Aa[PSD_KMAX * PSD_KMAX],
-          Bb[PSD_KMAX * PSD_KMAX];
-      psd_smat(dsa + g.base + i * sd, k, dS);
-      psd_smat(dza + g.base + i * sd, k, dZ);
-      // Aa = Ri dS Ri'
-      for (int r = 0; r < k; ++r)
-        for (int j = 0; j < k; ++j) {
-          double acc = 0;
-          for (int p = 0; p < k; ++p) acc += Ri[r * PSD_KMAX + p] * dS[p * PSD_KMAX + j];
-          T1[r * PSD_KMAX + j] = acc;
-        }
-      for (int r = 0; r < k; ++r)
-        for (int j = 0; j < k; ++j) {
-          double acc = 0;
-          for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * Ri[j * PSD_KMAX + p];
-          Aa[r * PSD_KMAX + j] = acc;
-        }
-      // Bb = R' dZ R
-      for (int r = 0; r < k; ++r)
-        for (int j = 0; j < k; ++j) {
-          double acc = 0;
-          for (int p = 0; p < k; ++p) acc += R[p * PSD_KMAX + r] * dZ[p * PSD_KMAX + j];
-          T1[r * PSD_KMAX + j] = acc;
-        }
-      for (int r = 0; r < k; ++r)
-        for (int j = 0; j < k; ++j) {
-          double acc = 0;
-          for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * R[p * PSD_KMAX + j];
-          Bb[r * PSD_KMAX + j] = acc;
-        }
-      // V = (Aa Bb + Bb Aa)/2 + diag(lam^2) - sm I ;  X_ij = 2 V_ij / (lam_i + lam_j)
-      // (V is formed on the upper triangle and mirrored, so X is exactly
-      // symmetric before the large 1/(lam_i + lam_j) factors)
-      double X[PSD_KMAX * PSD_KMAX];
-      for (int r = 0; r < k; ++r)
-        for (int j = r; j < k; ++j) {
-          double acc = 0;
-          for (int p = 0; p < k; ++p) acc += Aa[r * PSD_KMAX + p] * Bb[p * PSD_KMAX + j] + Bb[r * PSD_KMAX + p] * Aa[p * PSD_KMAX + j];
-          double v = 0.5 * acc;
-          if (r == j) v += lam[r] * lam[r] - sm;
-          X[r * PSD_KMAX + j] = 2.0 * v / (lam[r] + lam[j]);
-          X[j * PSD_KMAX + r] = X[r * PSD_KMAX + j];
-        }
-      // ds = svec(R X R')
-      for (int r = 0; r < k; ++r)
-        for (int j = 0; j < k; ++j) {
-          double acc = 0;
-          for (int p = 0; p < k; ++p) acc += R[r * PSD_KMAX + p] * X[p * PSD_KMAX + j];
-          T1[r * PSD_KMAX + j] = acc;
-        }
-      for (int r = 0; r < k; ++r)
-        for (int j = 0; j < k; ++j) {
-          double acc = 0;
-          for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * R[j * PSD_KMAX + p];
-          X[r * PSD_KMAX + j] = acc;
-        }
-      psd_svec(X, k, ds + g.base + i * sd);
-      break;
-    }
+    case HC_CONE_PSD:
+      break;   // k_psd_ds
   }
+}
+
+__global__ __launch_bounds__(PSD_TB) void k_psd_ds(SegDev g, const double* __restrict__ dsa,
+                                                   const double* __restrict__ dza, double sm, double* __restrict__ ds) {
+  __shared__ double wsall[PSD_TB * WS_DS];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.count) return;
+  const int64_t N = g.count;
+  const int k = g.k, sd = g.dim;
+  const int64_t kk = (int64_t)k * k;
+  double* ws = wsall + threadIdx.x * WS_DS;
+  double *R = ws, *Ri = ws + PSD_MAT, *dS = ws + 2 * PSD_MAT, *dZ = ws + 3 * PSD_MAT, *T1 = ws + 4 * PSD_MAT,
+         *Aa = ws + 5 * PSD_MAT, *Bb = ws + 6 * PSD_MAT, *X = ws + 7 * PSD_MAT, *lam = ws + 8 * PSD_MAT;
+  for (int r = 0; r < k; ++r)
+    for (int j = 0; j < k; ++j) {
+      R[r * PSD_KMAX + j] = g.state[(r * k + j) * N + i];
+      Ri[r * PSD_KMAX + j] = g.state[(kk + r * k + j) * N + i];
+    }
+  for (int j = 0; j < k; ++j) lam[j] = g.state[(3 * kk + j) * N + i];
+  psd_smat(dsa + g.base + i * sd, k, dS);
+  psd_smat(dza + g.base + i * sd, k, dZ);
+  // Aa = Ri dS Ri'
+  for (int r = 0; r < k; ++r)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += Ri[r * PSD_KMAX + p] * dS[p * PSD_KMAX + j];
+      T1[r * PSD_KMAX + j] = acc;
+    }
+  for (int r = 0; r < k; ++r)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * Ri[j * PSD_KMAX + p];
+      Aa[r * PSD_KMAX + j] = acc;
+    }
+  // Bb = R' dZ R
+  for (int r = 0; r < k; ++r)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += R[p * PSD_KMAX + r] * dZ[p * PSD_KMAX + j];
+      T1[r * PSD_KMAX + j] = acc;
+    }
+  for (int r = 0; r < k; ++r)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * R[p * PSD_KMAX + j];
+      Bb[r * PSD_KMAX + j] = acc;
+    }
+  // V = (Aa Bb + Bb Aa)/2 + diag(lam^2) - sm I ;  X_ij = 2 V_ij / (lam_i + lam_j)
+  // (V is formed on the upper triangle and mirrored, so X is exactly
+  // symmetric before the large 1/(lam_i + lam_j) factors)
+  for (int r = 0; r < k; ++r)
+    for (int j = r; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += Aa[r * PSD_KMAX + p] * Bb[p * PSD_KMAX + j] + Bb[r * PSD_KMAX + p] * Aa[p * PSD_KMAX + j];
+      double v = 0.5 * acc;
+      if (r == j) v += lam[r] * lam[r] - sm;
+      X[r * PSD_KMAX + j] = 2.0 * v / (lam[r] + lam[j]);
+      X[j * PSD_KMAX + r] = X[r * PSD_KMAX + j];
+    }
+  // ds = svec(R X R')
+  for (int r = 0; r < k; ++r)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += R[r * PSD_KMAX + p] * X[p * PSD_KMAX + j];
+      T1[r * PSD_KMAX + j] = acc;
+    }
+  for (int r = 0; r < k; ++r)
+    for (int j = 0; j < k; ++j) {
+      double acc = 0;
+      for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * R[j * PSD_KMAX + p];
+      X[r * PSD_KMAX + j] = acc;
+    }
+  psd_svec(X, k, ds + g.base + i * sd);
 }
 
 void cone_ds_combined(const SegDev& g, const double* s, const double* z, const double* dsa, const double* dza,
                       double sm, double* ds, hipStream_t st) {
   if (g.count == 0) return;
-  hipLaunchKernelGGL(k_cone_ds, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, s, z, dsa, dza, sm, ds);
+  if (g.kind == HC_CONE_PSD)
+    hipLaunchKernelGGL(k_psd_ds, dim3(psd_blocks(g.count)), dim3(PSD_TB), 0, st, g, dsa, dza, sm, ds);
+  else
+    hipLaunchKernelGGL(k_cone_ds, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, s, z, dsa, dza, sm, ds);
   HC_LAUNCH_CHECK();
 }
 
@@ -1116,8 +1166,9 @@ __device__ inline double soc_step_one(const double* x, const double* dx, int d) 
   return best;
 }
 
-__device__ double psd_step_one(const double* x, const double* dx, int k) {
-  double L[PSD_KMAX * PSD_KMAX], D[PSD_KMAX * PSD_KMAX], T[PSD_KMAX * PSD_KMAX];
+// largest alpha with x + alpha dx PSD (INFINITY if unbounded); ws: 3 PSD_MAT doubles
+__device__ double psd_step_one(const double* x, const double* dx, int k, double* ws) {
+  double *L = ws, *D = ws + PSD_MAT, *T = ws + 2 * PSD_MAT;
   psd_smat(x, k, L);
   psd_smat(dx, k, D);
   if (!psd_chol(L, k)) return 0.0;
@@ -1162,10 +1213,6 @@ __global__ void k_step_sym(SegDev g, const double* __restrict__ s, const double*
         xdz[j] = dz[g.base + j * N + i];
       }
       a = fmin(soc_step_one(xs, xds, d), soc_step_one(xz, xdz, d));
-    } else if (g.kind == HC_CONE_PSD) {
-      const int sd = g.dim;
-      a = fmin(psd_step_one(s + g.base + i * sd, ds + g.base + i * sd, g.k),
-               psd_step_one(z + g.base + i * sd, dz + g.base + i * sd, g.k));
     }
   }
   red[threadIdx.x] = a;
@@ -1177,9 +1224,32 @@ __global__ void k_step_sym(SegDev g, const double* __restrict__ s, const double*
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// PSD: grid-stride over the cones with at most PSD_STEP_GRID blocks, one
+// partial minimum per block
+constexpr int PSD_STEP_GRID = 2048;
+__global__ __launch_bounds__(PSD_TB) void k_step_psd(SegDev g, const double* __restrict__ s,
+                                                     const double* __restrict__ z, const double* __restrict__ ds,
+                                                     const double* __restrict__ dz, double* __restrict__ partial) {
+  __shared__ double wsall[PSD_TB * WS_STEP];
+  double* ws = wsall + threadIdx.x * WS_STEP;
+  const int sd = g.dim;
+  double a = INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * PSD_TB + threadIdx.x; i < g.count; i += (int64_t)gridDim.x * PSD_TB)
+    a = fmin(a, fmin(psd_step_one(s + g.base + i * sd, ds + g.base + i * sd, g.k, ws),
+                     psd_step_one(z + g.base + i * sd, dz + g.base + i * sd, g.k, ws)));
+  for (int off = PSD_TB / 2; off > 0; off >>= 1) a = fmin(a, __shfl_xor(a, off, PSD_TB));
+  if (threadIdx.x == 0) partial[blockIdx.x] = a;
+}
+
 int cone_step_sym(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz,
                   double* partial, hipStream_t st) {
   if (g.count == 0 || g.kind == HC_CONE_ZERO || g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) return 0;
+  if (g.kind == HC_CONE_PSD) {
+    const int nbp = std::min(psd_blocks(g.count), PSD_STEP_GRID);
+    hipLaunchKernelGGL(k_step_psd, dim3(nbp), dim3(PSD_TB), 0, st, g, s, z, ds, dz, partial);
+    HC_LAUNCH_CHECK();
+    return nbp;
+  }
   const int nb = cone_blocks(g);
   hipLaunchKernelGGL(k_step_sym, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, ds, dz, partial);
   HC_LAUNCH_CHECK();
@@ -1443,8 +1513,9 @@ __global__ void k_test_step(SegDev g, const double* __restrict__ s, const double
     }
     a = fmin(a, fmin(soc_step_one(xs, xds, g.dim), soc_step_one(xz, xdz, g.dim)));
   } else if (g.kind == HC_CONE_PSD) {
-    a = fmin(a, fmin(psd_step_one(s + g.base + i * g.dim, ds + g.base + i * g.dim, g.k),
-                     psd_step_one(z + g.base + i * g.dim, dz + g.base + i * g.dim, g.k)));
+    double ws[3 * PSD_MAT];   // test entry only: scratch is fine here
+    a = fmin(a, fmin(psd_step_one(s + g.base + i * g.dim, ds + g.base + i * g.dim, g.k, ws),
+                     psd_step_one(z + g.base + i * g.dim, dz + g.base + i * g.dim, g.k, ws)));
   } else if (g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) {
     const double al = (g.kind == HC_CONE_POW) ? g.alpha[i] : 0.0;
     double t = amax;
