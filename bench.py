@@ -99,15 +99,21 @@ def run_gpu(prob, precision, steps, warmup):
     )
 
 
-def run_other_workloads(steps=1):
+OTHER_WORKLOADS = ("logreg_exp", "psd_pow")
+
+
+def run_other_workloads(steps=1, only=None):
     """The other full-size configurations, one FP64 solve each after a warm-up
     solve: status, iterations and time per iteration (problem resident)."""
     import torch
     from paper_2412_19027_amd import hipcone as HC
     from paper_2412_19027_amd import workloads as W
+    makers = {"logreg_exp": lambda: W.logreg_exp(0), "psd_pow": lambda: W.psd_pow(0)}
     out = {}
-    for name, make in (("logreg_exp", lambda: W.logreg_exp(0)), ("psd_pow", lambda: W.psd_pow(0))):
-        prob = make()
+    for name in OTHER_WORKLOADS:
+        if only and name != only:
+            continue
+        prob = makers[name]()
         s = HC.Solver(prob)
         s.solve()
         torch.cuda.synchronize()
@@ -164,6 +170,31 @@ def run_served(count, rate=2000.0, workers=4, slots=32, budget=16 << 30, seed=0)
         hbm_peak_bytes=st["hbm_peak"], workers=workers, max_slots=slots, hbm_budget_bytes=budget)
 
 
+def run_sequential(count, seed=0):
+    """The same MPC requests solved one after another by a plain FP64 solver
+    (set-up, solve, results, release per request): the baseline the served
+    form is compared with."""
+    import torch
+    from paper_2412_19027_amd import hipcone as HC
+    from paper_2412_19027_amd import workloads as W
+    probs = [W.mpc_socp(seed, i) for i in range(count)]
+    s = HC.Solver(probs[0])   # warm-up (first-call costs)
+    s.solve()
+    s.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solved = 0
+    for p in probs:
+        s = HC.Solver(p)
+        info = s.solve()
+        s.solution()
+        s.close()
+        solved += info["status_name"] == "solved"
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return dict(requests=count, solves_per_s=count / wall, mean_latency_ms=1e3 * wall / count, solved=solved)
+
+
 def cpu_baseline(prob):
     """The oracle as it stands, on one IPM iteration of the same problem
     (its setup and initial point are not timed)."""
@@ -193,12 +224,20 @@ def main():
     ap.add_argument("--no-workloads", action="store_true", help="skip the other full-size configurations")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run the reference copy kernel (for byte-counter scaling)")
+    ap.add_argument("--sequential", type=int, default=200,
+                    help="requests of the same stream solved one by one (plain FP64 baseline of the served form); "
+                         "0 = skip")
+    ap.add_argument("--workload-only", choices=OTHER_WORKLOADS,
+                    help="run only this other configuration (one warm-up and one timed solve) and print its line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     sys.path.insert(0, ROOT)
     from paper_2412_19027_amd import workloads as W
+    if args.workload_only:
+        print(json.dumps(run_other_workloads(only=args.workload_only)))
+        return
     sc = args.scale
     prob = W.sparse_socp(0, nx=int(20000 * sc), n_zero=int(10000 * sc), n_nonneg=int(30000 * sc),
                          n_soc=int(40000 * sc))
@@ -215,6 +254,8 @@ def main():
         other["objective_rel_diff_vs_main"] = abs(r["objective"] - main_run["objective"]) / max(
             1.0, abs(main_run["objective"]))
     served = run_served(args.served) if args.served > 0 else None
+    if served is not None and args.sequential > 0:
+        served["plain_fp64_sequential"] = run_sequential(args.sequential)
     others = None if args.no_workloads else run_other_workloads()
     if args.calibrate_copy:
         calibrate_copy()
