@@ -195,6 +195,46 @@ def run_sequential(count, seed=0):
     return dict(requests=count, solves_per_s=count / wall, mean_latency_ms=1e3 * wall / count, solved=solved)
 
 
+def run_parametric(count=50, T=100, nx=12, nu=6):
+    """Parametric re-solves (hc_update_data) against fresh set-ups, on MPC
+    problems of one structure (the largest request shape of the stream):
+    re-solves per second both ways and the host time of a data update
+    against that of a set-up."""
+    import torch
+    from paper_2412_19027_amd import hipcone as HC
+    from paper_2412_19027_amd import workloads as W
+    probs = [W.mpc_socp(seed, 0, T=T, nx=nx, nu=nu) for seed in range(count + 1)]
+    s = HC.Solver(probs[0])
+    s.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    upd_ms, solved_u = 0.0, 0
+    for p in probs[1:]:
+        t1 = time.perf_counter()
+        s.update_data(P_val=p.P.tocsr().data, q=p.q, A_val=p.A.tocsr().data, b=p.b)
+        upd_ms += 1e3 * (time.perf_counter() - t1)
+        solved_u += s.solve()["status_name"] == "solved"
+        s.solution()
+    torch.cuda.synchronize()
+    wall_u = time.perf_counter() - t0
+    s.close()
+    t0 = time.perf_counter()
+    setup_ms, solved_f = 0.0, 0
+    for p in probs[1:]:
+        f = HC.Solver(p)
+        info = f.solve()
+        f.solution()
+        setup_ms += info["setup_ms"]
+        solved_f += info["status_name"] == "solved"
+        f.close()
+    torch.cuda.synchronize()
+    wall_f = time.perf_counter() - t0
+    return dict(workload=f"MPC SOCP T={T}, nx={nx}, nu={nu} (n={probs[0].n}, m={probs[0].m}), {count} data sets",
+                update_solves_per_s=count / wall_u, fresh_solves_per_s=count / wall_f,
+                update_host_ms=upd_ms / count, setup_host_ms=setup_ms / count, solved_update=solved_u,
+                solved_fresh=solved_f)
+
+
 def cpu_baseline(prob):
     """The oracle as it stands, on one IPM iteration of the same problem
     (its setup and initial point are not timed)."""
@@ -256,6 +296,7 @@ def main():
     served = run_served(args.served) if args.served > 0 else None
     if served is not None and args.sequential > 0:
         served["plain_fp64_sequential"] = run_sequential(args.sequential)
+    parametric = run_parametric() if args.served > 0 else None
     others = None if args.no_workloads else run_other_workloads()
     if args.calibrate_copy:
         calibrate_copy()
@@ -288,6 +329,7 @@ def main():
         "roofline": main_run["roofline"],
         "alt_precision": other,
         "served": served,
+        "parametric": parametric,
         "workloads": others,
         "cpu_baseline": cpu,
     }

@@ -241,6 +241,18 @@ int32_t hc_test_kkt_ops(hc_solver* s, double mu, int32_t force_dual, const doubl
 int32_t hc_test_schur(hc_solver* s, double mu, int32_t force_dual, double* S_out, double* L_out,
                       double* stats);
 
+/* Parametric re-solve (Sec. 5, re-solving with new data of one structure):
+ * replace the values of P (upper triangle, in the set-up's CSR order; nnz
+ * of P), q (n), A (set-up's CSR order; nnz of A) and b (m); NULL keeps an
+ * array as it is.  The sparsity pattern and cones stay those of hc_setup:
+ * the row order, the assembly plan, the leaf blocks and the tail ordering
+ * are reused, only equilibration and the scaled data are recomputed and
+ * copied into the bound device buffers.  The next hc_solve starts from the
+ * method's initial point (no warm start).  Host arrays, copied.  Errors:
+ * HC_ERR_NONFINITE (nothing changed), HC_ERR_CSR if P's pattern changed. */
+int32_t hc_update_data(hc_solver* s, const double* P_val, const double* q, const double* A_val,
+                       const double* b);
+
 void hc_destroy(hc_solver* s);                /* NULL is a no-op */
 const char* hc_last_error(const hc_solver* s);
 const char* hc_status_str(int32_t status);

@@ -138,6 +138,11 @@ struct hc_solver {
   double sdiag_max = 0;             // mixed mode: max |S_ii| of the last FP32 factorisation
   double t_begin = 0;               // host clock at the start of the solve
   double* snap_S = nullptr;         // test hook: host copy of the dense tail before its Cholesky
+  // the user's data as last given (structure fixed at setup), for hc_update_data
+  std::vector<int64_t> uPrp, uArp;
+  std::vector<int32_t> uPci, uAci;
+  std::vector<double> uPv, uq, uAv, ub;
+  std::vector<hc_cone> ucones;
   std::string last_error;
 };
 
@@ -708,6 +713,137 @@ void setup_host(hc_solver* S, const hc_problem* p) {
   S->ld = ((S->nt + 63) / 64) * 64;
   if (S->st.static_reg <= 0) S->st.static_reg = S->mixed ? 3.4526698300124393e-04 : 1e-8;
   if (S->st.dyn_reg < 0) S->st.dyn_reg = S->mixed ? std::ldexp(1.0, -46) : std::ldexp(1.0, -104);
+}
+
+// keep a copy of the user's problem (hc_update_data rebuilds from it)
+void keep_user_data(hc_solver* S, const hc_problem* p) {
+  const int64_t n = p->n, m = p->m;
+  if (p->P_rowptr) {
+    S->uPrp.assign(p->P_rowptr, p->P_rowptr + n + 1);
+    S->uPci.assign(p->P_col, p->P_col + p->P_rowptr[n]);
+    S->uPv.assign(p->P_val, p->P_val + p->P_rowptr[n]);
+  }
+  S->uArp.assign(p->A_rowptr, p->A_rowptr + m + 1);
+  S->uAci.assign(p->A_col, p->A_col + p->A_rowptr[m]);
+  S->uAv.assign(p->A_val, p->A_val + p->A_rowptr[m]);
+  S->uq.assign(p->q, p->q + n);
+  S->ub.assign(p->b, p->b + m);
+  S->ucones.assign(p->cones, p->cones + p->ncones);
+}
+
+hc_problem user_problem(hc_solver* S) {
+  hc_problem p{};
+  p.n = S->n;
+  p.m = S->m;
+  if (!S->uPrp.empty()) {
+    p.P_rowptr = S->uPrp.data();
+    p.P_col = S->uPci.data();
+    p.P_val = S->uPv.data();
+  }
+  p.q = S->uq.data();
+  p.A_rowptr = S->uArp.data();
+  p.A_col = S->uAci.data();
+  p.A_val = S->uAv.data();
+  p.b = S->ub.data();
+  p.cones = S->ucones.data();
+  p.ncones = (int32_t)S->ucones.size();
+  return p;
+}
+
+// Parametric update (same sparsity, new values): redo every value-dependent
+// step of the set-up -- full P, A in the internal row order, equilibration,
+// scaling, the dense rows, A without them and its transpose -- on the
+// structures kept from the set-up (row order, dense-row choice, assembly
+// tasks, leaf blocks and tail ordering are reused as they are).
+void refresh_values(hc_solver* S) {
+  const hc_problem up = user_problem(S);
+  const hc_problem* p = &up;
+  const int64_t n = S->n, m = S->m;
+  HostCsr Pf;
+  Pf.nrows = Pf.ncols = n;
+  {
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(n);
+    if (p->P_rowptr)
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = p->P_rowptr[i]; k < p->P_rowptr[i + 1]; ++k) {
+          const int32_t j = p->P_col[k];
+          rows[i].push_back({j, p->P_val[k]});
+          if (j != i) rows[j].push_back({(int32_t)i, p->P_val[k]});
+        }
+    Pf.rp.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      std::sort(rows[i].begin(), rows[i].end());
+      Pf.rp[i + 1] = Pf.rp[i] + (int32_t)rows[i].size();
+      for (auto& e : rows[i]) {
+        Pf.ci.push_back(e.first);
+        Pf.v.push_back(e.second);
+      }
+    }
+  }
+  if (Pf.ci != S->P.ci || Pf.rp != S->P.rp) fail(HC_ERR_CSR, "hc_update_data: P structure differs from set-up");
+  HostCsr Ai;
+  Ai.nrows = m;
+  Ai.ncols = n;
+  Ai.rp.assign(m + 1, 0);
+  for (int64_t r = 0; r < m; ++r) {
+    const int64_t u = S->perm[r];
+    Ai.rp[r + 1] = Ai.rp[r] + (int32_t)(p->A_rowptr[u + 1] - p->A_rowptr[u]);
+  }
+  Ai.ci.resize(Ai.rp[m]);
+  Ai.v.resize(Ai.rp[m]);
+  for (int64_t r = 0; r < m; ++r) {
+    const int64_t u = S->perm[r];
+    int32_t o = Ai.rp[r];
+    for (int64_t k = p->A_rowptr[u]; k < p->A_rowptr[u + 1]; ++k, ++o) {
+      Ai.ci[o] = p->A_col[k];
+      Ai.v[o] = p->A_val[k];
+    }
+  }
+  std::vector<double> qv(p->q, p->q + n), bi(m);
+  for (int64_t r = 0; r < m; ++r) bi[r] = p->b[S->perm[r]];
+  S->bnorm_user = 0;
+  for (int64_t i = 0; i < m; ++i) S->bnorm_user = std::max(S->bnorm_user, std::fabs(p->b[i]));
+  S->qnorm_user = 0;
+  for (int64_t j = 0; j < n; ++j) S->qnorm_user = std::max(S->qnorm_user, std::fabs(p->q[j]));
+  equilibrate(S, Ai, Pf, qv);
+  const double c = S->cscale;
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t k = Pf.rp[i]; k < Pf.rp[i + 1]; ++k) Pf.v[k] *= c * S->D[i] * S->D[Pf.ci[k]];
+  for (int64_t r = 0; r < m; ++r)
+    for (int32_t k = Ai.rp[r]; k < Ai.rp[r + 1]; ++k) Ai.v[k] *= S->E[r] * S->D[Ai.ci[k]];
+  for (int64_t j = 0; j < n; ++j) S->q[j] = c * S->D[j] * qv[j];
+  for (int64_t r = 0; r < m; ++r) S->b[r] = S->E[r] * bi[r];
+  S->maxPdiag = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t k = Pf.rp[i]; k < Pf.rp[i + 1]; ++k)
+      if (Pf.ci[k] == i) S->maxPdiag = std::max(S->maxPdiag, std::fabs(Pf.v[k]));
+  S->P.v = Pf.v;
+  // dense rows (full n columns first, then re-indexed to the tail as at set-up)
+  const int nd = (int)S->drows.size();
+  std::vector<char> is_dense(m, 0);
+  for (int d = 0; d < nd; ++d) is_dense[S->drows[d]] = 1;
+  std::vector<double> Ad((size_t)nd * n, 0.0);
+  for (int d = 0; d < nd; ++d) {
+    const int64_t r = S->drows[d];
+    for (int32_t k = Ai.rp[r]; k < Ai.rp[r + 1]; ++k) Ad[(size_t)d * n + Ai.ci[k]] = Ai.v[k];
+  }
+  if (S->leaves && nd) {
+    std::vector<double> Adt((size_t)nd * S->nt);
+    for (int d = 0; d < nd; ++d)
+      for (int64_t t = 0; t < S->nt; ++t) Adt[(size_t)d * S->nt + t] = Ad[(size_t)d * n + S->tail_cols[t]];
+    Ad.swap(Adt);
+  }
+  S->Ad.swap(Ad);
+  // A without the dense rows, and its transpose, in the set-up's positions
+  {
+    int64_t o = 0;
+    for (int64_t r = 0; r < m; ++r)
+      if (!is_dense[r])
+        for (int32_t k = Ai.rp[r]; k < Ai.rp[r + 1]; ++k) S->A.v[o++] = Ai.v[k];
+    std::vector<int32_t> fillp(S->At.rp.begin(), S->At.rp.end() - 1);
+    for (int64_t r = 0; r < m; ++r)
+      for (int32_t k = S->A.rp[r]; k < S->A.rp[r + 1]; ++k) S->At.v[fillp[S->A.ci[k]]++] = S->A.v[k];
+  }
 }
 
 template <typename T> T* upload(Buf& buf, const std::vector<T>& h, hipStream_t st) {
@@ -1583,6 +1719,7 @@ int32_t hc_setup(hc_solver** out, const hc_problem* prob, const hc_settings* set
     const double t0 = now_ms();
     validate(prob);
     setup_host(S, prob);
+    keep_user_data(S, prob);
     S->info.setup_ms = now_ms() - t0;
     S->info.n_ordered = S->nt;
     S->info.n_leaves = (int64_t)S->leaf_size.size();
@@ -1706,6 +1843,49 @@ int32_t hc_set_iterate(hc_solver* S, const double* x, const double* sv, const do
   }
   S->tau = tau;
   S->kappa = kappa;
+  return HC_OK;
+}
+
+int32_t hc_update_data(hc_solver* S, const double* P_val, const double* q, const double* A_val, const double* b) {
+  if (!S) return HC_ERR_INVALID_ARG;
+  try {
+    auto finite = [](const double* v, size_t cnt) {
+      for (size_t i = 0; i < cnt; ++i)
+        if (!std::isfinite(v[i])) return false;
+      return true;
+    };
+    const size_t pn = S->uPv.size(), an = S->uAv.size();
+    if ((P_val && !finite(P_val, pn)) || (q && !finite(q, S->n)) || (A_val && !finite(A_val, an)) ||
+        (b && !finite(b, S->m)))
+      fail(HC_ERR_NONFINITE, "hc_update_data: non-finite value");
+    if (P_val) std::copy(P_val, P_val + pn, S->uPv.begin());
+    if (q) std::copy(q, q + S->n, S->uq.begin());
+    if (A_val) std::copy(A_val, A_val + an, S->uAv.begin());
+    if (b) std::copy(b, b + S->m, S->ub.begin());
+    refresh_values(S);
+    if (S->bound) {
+      HC_HIP(hipSetDevice(S->device));
+      hipStream_t st = S->stream;
+      auto put = [&](double* d, const std::vector<double>& h) {
+        if (!h.empty()) HC_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      };
+      put(S->dA.val, S->A.v);
+      put(S->dAt.val, S->At.v);
+      put(S->dP.val, S->P.v);
+      put(S->dAd, S->Ad);
+      put(S->dq, S->q);
+      put(S->db, S->b);
+      put(S->dD, S->D);
+      put(S->dE, S->E);
+      HC_HIP(hipStreamSynchronize(st));
+    }
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HC_ERR_INVALID_ARG;
+  }
   return HC_OK;
 }
 

@@ -21,7 +21,7 @@ STATUS = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasibl
           5: "insufficient_progress", 6: "numerical_error", 7: "cancelled"}
 
 EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "hc_solve", "hc_get_info",
-           "hc_get_solution", "hc_get_iterate", "hc_set_iterate", "hc_test_kkt_solve", "hc_test_kkt_ops",
+           "hc_get_solution", "hc_get_iterate", "hc_set_iterate", "hc_update_data", "hc_test_kkt_solve", "hc_test_kkt_ops",
            "hc_test_schur", "hc_destroy", "hc_last_error", "hc_status_str",
            "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_dense_chol_solve",
            "hc_test_copy", "hc_test_cone_mblock", "hc_server_config_default", "hc_server_create", "hc_server_submit", "hc_server_poll",
@@ -110,6 +110,7 @@ def lib():
         L.hc_get_solution.argtypes = [vp, vp, vp, vp]
         L.hc_get_iterate.argtypes = [vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp]
         L.hc_set_iterate.argtypes = [vp, vp, vp, vp, dbl, dbl]
+        L.hc_update_data.argtypes = [vp, vp, vp, vp, vp]
         L.hc_test_kkt_solve.argtypes = [vp, dbl, C.c_int32, vp, vp, vp, vp, vp]
         L.hc_test_schur.argtypes = [vp, dbl, C.c_int32, vp, vp, vp]
         L.hc_test_kkt_ops.argtypes = [vp, dbl, C.c_int32, vp, vp, vp, vp, vp, vp]
@@ -221,6 +222,7 @@ class Solver:
         self.n, self.m = prob.n, prob.m
         h, self._keep = _setup(prob, self.settings)
         self._h = h
+        self._nnzP, self._nnzA = len(self._keep["Pv"]), len(self._keep["Av"])
         nbytes = C.c_size_t()
         _check(L.hc_workspace_bytes(h, C.byref(nbytes)), h)
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
@@ -256,6 +258,20 @@ class Solver:
         _check(lib().hc_get_iterate(self._h, x.ctypes.data, s.ctypes.data, z.ctypes.data, C.byref(tau),
                                     C.byref(kappa), perm.ctypes.data), self._h)
         return x, s, z, tau.value, kappa.value, perm
+
+    def update_data(self, P_val=None, q=None, A_val=None, b=None):
+        """New values for a problem of the same structure (hc_update_data); None keeps an array."""
+        keep = []
+
+        def ptr(v, size):
+            if v is None:
+                return None
+            a = np.ascontiguousarray(v, dtype=np.float64)
+            assert a.shape == (size,), (a.shape, size)
+            keep.append(a)
+            return a.ctypes.data
+        _check(lib().hc_update_data(self._h, ptr(P_val, self._nnzP), ptr(q, self.n), ptr(A_val, self._nnzA),
+                                    ptr(b, self.m)), self._h)
 
     def set_iterate(self, x, s, z, tau, kappa):
         """Replace the internal iterate (internal order and scaling, as `iterate()` returns it)."""

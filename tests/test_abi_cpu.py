@@ -93,3 +93,34 @@ def test_struct_layouts_match_the_header(tmp_path):
     want = [C.sizeof(t) for t in (hipcone.hc_settings, hipcone.hc_info, hipcone.hc_problem, hipcone.hc_device,
                                   hipcone.hc_server_config, hipcone.hc_result, hipcone.hc_server_report)]
     assert got == want
+
+
+def test_update_data_on_host():
+    """hc_update_data recomputes the scaled data on the host (no device
+    bound): new values of the same structure are accepted, non-finite values
+    are rejected with HC_ERR_NONFINITE, and an unchanged update leaves the
+    analysis the same."""
+    import ctypes as C
+    import numpy as np
+    from paper_2412_19027_amd import workloads as W
+    L = hipcone.lib()
+    a, b = W.mpc_socp(0, 0, T=12, nx=5, nu=3), W.mpc_socp(1, 0, T=12, nx=5, nu=3)
+    h, keep = hipcone._setup(a, hipcone.default_settings())
+    try:
+        before = hipcone.hc_info()
+        assert L.hc_get_info(h, C.byref(before)) == 0
+        Pb, Ab = b.P.tocsr(), b.A.tocsr()
+        Pv = np.ascontiguousarray(Pb.data, dtype=np.float64)
+        Av = np.ascontiguousarray(Ab.data, dtype=np.float64)
+        q = np.ascontiguousarray(b.q, dtype=np.float64)
+        bb = np.ascontiguousarray(b.b, dtype=np.float64)
+        assert L.hc_update_data(h, Pv.ctypes.data, q.ctypes.data, Av.ctypes.data, bb.ctypes.data) == 0
+        bad = bb.copy()
+        bad[3] = np.inf
+        assert L.hc_update_data(h, None, None, None, bad.ctypes.data) == -5   # HC_ERR_NONFINITE
+        assert L.hc_update_data(h, None, None, None, None) == 0
+        after = hipcone.hc_info()
+        assert L.hc_get_info(h, C.byref(after)) == 0
+        assert (after.n_ordered, after.n_leaves) == (before.n_ordered, before.n_leaves)
+    finally:
+        L.hc_destroy(h)
