@@ -99,7 +99,7 @@ def run_gpu(prob, precision, steps, warmup):
     )
 
 
-OTHER_WORKLOADS = ("logreg_exp", "psd_pow")
+OTHER_WORKLOADS = ("logreg_exp", "psd_pow", "entropy_max", "portfolio_qp")
 
 
 def run_other_workloads(steps=1, only=None):
@@ -108,7 +108,8 @@ def run_other_workloads(steps=1, only=None):
     import torch
     from paper_2412_19027_amd import hipcone as HC
     from paper_2412_19027_amd import workloads as W
-    makers = {"logreg_exp": lambda: W.logreg_exp(0), "psd_pow": lambda: W.psd_pow(0)}
+    makers = {"logreg_exp": lambda: W.logreg_exp(0), "psd_pow": lambda: W.psd_pow(0),
+              "entropy_max": lambda: W.entropy_max(0, n=10000), "portfolio_qp": lambda: W.portfolio_qp(0, n=25000)}
     out = {}
     for name in OTHER_WORKLOADS:
         if only and name != only:

@@ -80,12 +80,13 @@ struct Csr {          // device CSR, int32 indices
 
 // y = alpha * A x + beta * y
 void spmv(const Csr& A, const double* x, double* y, double alpha, double beta, hipStream_t st);
-// y[rows_i] += alpha * (Ad x)_i for the dense rows Ad (nd x n row-major)
-void dense_rows_gemv(int nd, int64_t n, const double* Ad, const int32_t* rows, const double* x,
+// y[rows_i] += alpha * (Ad x)_i for the dense rows Ad (nd x n row-major;
+// column j is variable cols[j], or j when cols is null)
+void dense_rows_gemv(int nd, int64_t n, const double* Ad, const int32_t* rows, const int32_t* cols, const double* x,
                      double* y, double alpha, hipStream_t st);
-// y += alpha * Ad' v[rows]
-void dense_rows_gemv_t(int nd, int64_t n, const double* Ad, const int32_t* rows, const double* v,
-                       double* y, double alpha, hipStream_t st);
+// y[cols[j]] += alpha * sum_r Ad[r, j] v[rows[r]]  (cols null: y[j])
+void dense_rows_gemv_t(int nd, int64_t n, const double* Ad, const int32_t* rows, const int32_t* cols,
+                       const double* v, double* y, double alpha, hipStream_t st);
 
 // generic fused vector kernels
 void vaxpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);   // y = a x + b y

@@ -903,11 +903,14 @@ struct Red {
 
 void A_mul(hc_solver* S, const double* x, double* y, double alpha, double beta) {
   spmv(S->dA, x, y, alpha, beta, S->stream);
-  dense_rows_gemv((int)S->drows.size(), S->n, S->dAd, S->ddrows, x, y, alpha, S->stream);
+  // with leaf blocks the dense rows are stored on the tail columns only
+  dense_rows_gemv((int)S->drows.size(), S->leaves ? S->nt : S->n, S->dAd, S->ddrows,
+                  S->leaves ? S->cm.tcols : nullptr, x, y, alpha, S->stream);
 }
 void At_mul(hc_solver* S, const double* z, double* y, double alpha, double beta) {
   spmv(S->dAt, z, y, alpha, beta, S->stream);
-  dense_rows_gemv_t((int)S->drows.size(), S->n, S->dAd, S->ddrows, z, y, alpha, S->stream);
+  dense_rows_gemv_t((int)S->drows.size(), S->leaves ? S->nt : S->n, S->dAd, S->ddrows,
+                    S->leaves ? S->cm.tcols : nullptr, z, y, alpha, S->stream);
 }
 void P_mul(hc_solver* S, const double* x, double* y, double alpha, double beta) {
   if (S->dP.nnz == 0) {

@@ -51,14 +51,16 @@ int choose_lanes(double mean_nnz) {
   return 64;
 }
 
-// dense rows (row-major nd x n): y[rows[r]] += alpha * Ad[r, :] x   (one workgroup per row)
+// dense rows (row-major nd x n; column t is variable cols[t], or t when cols
+// is null): y[rows[r]] += alpha * Ad[r, :] x   (one workgroup per row)
 __global__ __launch_bounds__(256) void k_dense_rows(int64_t n, const double* __restrict__ Ad,
-                                                    const int32_t* __restrict__ rows, const double* __restrict__ x,
+                                                    const int32_t* __restrict__ rows,
+                                                    const int32_t* __restrict__ cols, const double* __restrict__ x,
                                                     double* __restrict__ y, double alpha) {
   __shared__ double red[256];
   const int r = blockIdx.x;
   double acc = 0;
-  for (int64_t j = threadIdx.x; j < n; j += 256) acc += Ad[(int64_t)r * n + j] * x[j];
+  for (int64_t j = threadIdx.x; j < n; j += 256) acc += Ad[(int64_t)r * n + j] * x[cols ? cols[j] : j];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
@@ -68,27 +70,29 @@ __global__ __launch_bounds__(256) void k_dense_rows(int64_t n, const double* __r
   if (threadIdx.x == 0) y[rows[r]] += alpha * red[0];
 }
 
-void dense_rows_gemv(int nd, int64_t n, const double* Ad, const int32_t* rows, const double* x, double* y,
-                     double alpha, hipStream_t st) {
+void dense_rows_gemv(int nd, int64_t n, const double* Ad, const int32_t* rows, const int32_t* cols, const double* x,
+                     double* y, double alpha, hipStream_t st) {
   if (nd == 0) return;
-  hipLaunchKernelGGL(k_dense_rows, dim3(nd), dim3(256), 0, st, n, Ad, rows, x, y, alpha);
+  hipLaunchKernelGGL(k_dense_rows, dim3(nd), dim3(256), 0, st, n, Ad, rows, cols, x, y, alpha);
   HC_LAUNCH_CHECK();
 }
 
-// y[j] += alpha * sum_r Ad[r, j] v[rows[r]]
+// y[cols[j]] += alpha * sum_r Ad[r, j] v[rows[r]]  (cols null: y[j]; cols is
+// one-to-one, so no two threads write one entry)
 __global__ void k_dense_rows_t(int nd, int64_t n, const double* __restrict__ Ad, const int32_t* __restrict__ rows,
-                               const double* __restrict__ v, double* __restrict__ y, double alpha) {
+                               const int32_t* __restrict__ cols, const double* __restrict__ v,
+                               double* __restrict__ y, double alpha) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   double acc = 0;
   for (int r = 0; r < nd; ++r) acc += Ad[(int64_t)r * n + j] * v[rows[r]];
-  y[j] += alpha * acc;
+  y[cols ? cols[j] : j] += alpha * acc;
 }
 
-void dense_rows_gemv_t(int nd, int64_t n, const double* Ad, const int32_t* rows, const double* v, double* y,
-                       double alpha, hipStream_t st) {
+void dense_rows_gemv_t(int nd, int64_t n, const double* Ad, const int32_t* rows, const int32_t* cols,
+                       const double* v, double* y, double alpha, hipStream_t st) {
   if (nd == 0) return;
-  hipLaunchKernelGGL(k_dense_rows_t, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, nd, n, Ad, rows, v, y,
+  hipLaunchKernelGGL(k_dense_rows_t, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, nd, n, Ad, rows, cols, v, y,
                      alpha);
   HC_LAUNCH_CHECK();
 }

@@ -20,6 +20,10 @@ Workload families (sizes of the full configurations in parentheses):
   logreg_exp    l1-regularised logistic regression via exp cones (n=301,000)
   psd_pow       equal-size PSD cones plus 3-d power cones (n=5,000)
   mpc_socp      one request of the served MPC stream (n <= 1,812)
+  entropy_max   the paper's entropy maximisation with m = n/2 dense
+                inequalities (n = 2,000 .. 10,000)
+  portfolio_qp  the paper's factor-model portfolio QP, rank p = n/10
+                (n = 5,000 .. 25,000)
 """
 from __future__ import annotations
 
@@ -387,6 +391,59 @@ def mpc_arrivals(seed: int, count: int, rate: float = 2000.0) -> np.ndarray:
 # named full-size configurations
 # --------------------------------------------------------------------------
 
+# --------------------------------------------------------------------------
+# the paper's exponential-cone and QP benchmark problems (Sec. 5)
+# --------------------------------------------------------------------------
+
+def entropy_max(seed: int = 0, n: int = 10000) -> Problem:
+    """maximize -sum x_i log x_i s.t. 1'x = 1, A x <= b, with m = round(n/2)
+    dense rows A_ij ~ N(0, n) (variance n) and b = A v / 1'v, v_i ~ U(0, 1)
+    (so v / 1'v is feasible).  Variables [x (n), t (n)], minimize -sum t with
+    (t_i, x_i, 1) in K_exp, i.e. x_i exp(t_i / x_i) <= 1."""
+    rng = np.random.default_rng(seed)
+    m_in = int(round(0.5 * n))
+    Ad = rng.standard_normal((m_in, n)) * math.sqrt(n)
+    v = rng.uniform(0.0, 1.0, n)
+    bin_ = Ad @ v / v.sum()
+    nv = 2 * n
+    q = np.concatenate([np.zeros(n), -np.ones(n)])
+    idx = np.arange(n)
+    # row 0: 1'x = 1 (zero cone); rows 1..m_in: A x + s = b (nonneg); then exp cones
+    top = sp.hstack([sp.csr_matrix(np.vstack([np.ones((1, n)), Ad])), sp.csr_matrix((1 + m_in, n))]).tocsr()
+    r0 = np.repeat(3 * idx, 1)
+    ex = sp.csr_matrix((-np.ones(2 * n), (np.concatenate([r0, r0 + 1]), np.concatenate([n + idx, idx]))),
+                       shape=(3 * n, nv))
+    A = sp.vstack([top, ex]).tocsr()
+    bexp = np.zeros(3 * n)
+    bexp[3 * idx + 2] = 1.0
+    b = np.concatenate([[1.0], bin_, bexp])
+    cones = [(ZERO, 1, 0.0), (NONNEG, m_in, 0.0)] + [(EXP, 3, 0.0)] * n
+    return Problem(nv, A.shape[0], sp.csr_matrix((nv, nv)), q, A, b, cones, name=f"entropy_max(seed={seed},n={n})")
+
+
+def portfolio_qp(seed: int = 0, n: int = 25000, density: float = 0.1, gamma: float = 1.0) -> Problem:
+    """maximize mu'x - gamma x'(F F' + D)x s.t. 1'x = 1, x >= 0, rank
+    p = round(n/10), lifted as y = F'x: minimize gamma (x'Dx + y'y) - mu'x
+    with the p rows y - F'x = 0 and 1'x = 1 in the zero cone and x >= 0.
+    Distributions (the paper gives none): F_ij ~ N(0, 1) present with
+    probability `density`, D_ii ~ U(0, sqrt(p)), mu_i ~ N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    p = max(1, int(round(0.1 * n)))
+    F = sp.random(n, p, density=density, random_state=rng, data_rvs=rng.standard_normal, format="csc")
+    D = rng.uniform(0.0, math.sqrt(p), n)
+    mu = rng.standard_normal(n)
+    nv = n + p
+    P = sp.diags(np.concatenate([2.0 * gamma * D, 2.0 * gamma * np.ones(p)])).tocsr()
+    q = np.concatenate([-mu, np.zeros(p)])
+    lift = sp.hstack([-F.T, sp.identity(p)]).tocsr()                 # y - F'x = 0
+    budget = sp.csr_matrix(np.concatenate([np.ones(n), np.zeros(p)])[None, :])
+    nonneg = sp.hstack([-sp.identity(n), sp.csr_matrix((n, p))]).tocsr()   # s = x >= 0
+    A = sp.vstack([lift, budget, nonneg]).tocsr()
+    b = np.concatenate([np.zeros(p), [1.0], np.zeros(n)])
+    cones = [(ZERO, p + 1, 0.0), (NONNEG, n, 0.0)]
+    return Problem(nv, A.shape[0], sp.triu(P).tocsr(), q, A, b, cones, name=f"portfolio_qp(seed={seed},n={n},p={p})")
+
+
 def config(name: str, seed: int = 0) -> Problem:
     if name == "tiny_lp":
         return tiny_lp(seed)
@@ -396,4 +453,8 @@ def config(name: str, seed: int = 0) -> Problem:
         return logreg_exp(seed)
     if name == "psd_pow":
         return psd_pow(seed)
+    if name == "entropy_max":
+        return entropy_max(seed)
+    if name == "portfolio_qp":
+        return portfolio_qp(seed)
     raise KeyError(name)

@@ -53,6 +53,11 @@ CASES = [
     ("mpc_0", lambda: W.mpc_socp(0, 0)),
     ("exp_small", lambda: W.logreg_exp(0, samples=400, features=30)),
     ("psdpow_small", lambda: W.psd_pow(0, n=250, n_pow=120, n_psd=25, k=4)),
+    ("entropy_small", lambda: W.entropy_max(0, n=200)),
+    # rows of more than 512 entries go through the dense-row path, here together
+    # with leaf blocks (the t variables)
+    ("entropy_dense_rows", lambda: W.entropy_max(0, n=600)),
+    ("portfolio_small", lambda: W.portfolio_qp(0, n=300)),
 ]
 
 @pytest.mark.parametrize("name,make", CASES)
