@@ -4,8 +4,9 @@
  *     minimize 1/2 x'Px + q'x   subject to   Ax + s = b,  s in K          (P)
  *
  * with K a product of zero, nonnegative, second-order, exponential, 3-d power
- * and equal-size PSD cones (arXiv 2412.19027, Sec. 1 problem (P) and
- * Sec. 2.1 "Supported cones").  Every per-iteration step of the method
+ * and PSD cones (arXiv 2412.19027, Sec. 1 problem (P) and Sec. 2.1
+ * "Supported cones"; PSD cones may have different sides, which the paper
+ * leaves to future work, Sec. 6).  Every per-iteration step of the method
  * (Algorithm 1, Sec. 3.2) runs in this library's HIP kernels: residuals and
  * termination, the cone scalings and their writes into the KKT system, the
  * quasi-definite LDL' factorisation and triangular solves with iterative
@@ -39,8 +40,8 @@ extern "C" {
 #define HC_ERR_CSR         (-3)  /* unsorted/duplicate/out-of-range CSR, or P has
                                     an entry below its diagonal                    */
 #define HC_ERR_CONE        (-4)  /* unknown cone type, SOC dim < 2, EXP/POW dim !=
-                                    3, alpha outside (0,1), PSD sides unequal or
-                                    outside [1, 32]                               */
+                                    3, alpha outside (0,1), PSD side outside
+                                    [1, 32] (sides above 12: HC_ERR_UNSUPPORTED) */
 #define HC_ERR_NONFINITE   (-5)  /* NaN or Inf in P, q, A or b                      */
 #define HC_ERR_OOM         (-6)  /* device memory (arena too small or allocation
                                     failed); hc_last_error names the bytes needed */

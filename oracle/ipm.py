@@ -106,10 +106,10 @@ class Group:
 
 def build_groups(cones):
     """Cone list (kind, dim, alpha) in row order -> families of equal-size cones."""
-    rows = {ZERO: [], NONNEG: [], EXP: [], POW: [], PSD: []}
+    rows = {ZERO: [], NONNEG: [], EXP: [], POW: []}
     soc = {}
+    psd = {}
     alphas = []
-    psd_k = None
     r = 0
     for kind, dim, a in cones:
         if kind in (ZERO, NONNEG):
@@ -124,11 +124,8 @@ def build_groups(cones):
                 alphas.append(a)
             r += 3
         elif kind == PSD:
-            if psd_k is not None and psd_k != dim:
-                raise ValueError("all PSD cones must have the same side")
-            psd_k = dim
             sd = dim * (dim + 1) // 2
-            rows[PSD].append(list(range(r, r + sd)))
+            psd.setdefault(dim, []).append(list(range(r, r + sd)))
             r += sd
         else:
             raise ValueError(f"unknown cone kind {kind}")
@@ -142,8 +139,8 @@ def build_groups(cones):
         groups.append(Group(EXP, np.array(rows[EXP], dtype=np.int64)))
     if rows[POW]:
         groups.append(Group(POW, np.array(rows[POW], dtype=np.int64), alpha=np.array(alphas)))
-    if rows[PSD]:
-        groups.append(Group(PSD, np.array(rows[PSD], dtype=np.int64), k=psd_k))
+    for k in sorted(psd):   # PSD cones of several sides: one family per side
+        groups.append(Group(PSD, np.array(psd[k], dtype=np.int64), k=k))
     return groups, r
 
 

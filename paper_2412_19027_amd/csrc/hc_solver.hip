@@ -188,7 +188,6 @@ void validate(const hc_problem* p) {
   for (int64_t i = 0; i < p->m; ++i)
     if (!std::isfinite(p->b[i])) fail(HC_ERR_NONFINITE, "b has a non-finite value");
   int64_t rows = 0;
-  int psd_k = -1;
   for (int c = 0; c < p->ncones; ++c) {
     const hc_cone& k = p->cones[c];
     switch (k.type) {
@@ -213,9 +212,7 @@ void validate(const hc_problem* p) {
         break;
       case HC_CONE_PSD:
         if (k.dim < 1 || k.dim > 32) fail(HC_ERR_CONE, "PSD side outside [1, 32]");
-        if (psd_k >= 0 && psd_k != k.dim) fail(HC_ERR_CONE, "PSD sides unequal");
         if (k.dim > 12) fail(HC_ERR_UNSUPPORTED, "PSD side > 12 is not handled by this build");
-        psd_k = k.dim;
         rows += (int64_t)k.dim * (k.dim + 1) / 2;
         break;
       default:
@@ -226,10 +223,9 @@ void validate(const hc_problem* p) {
 }
 
 void build_segments(hc_solver* S, const hc_problem* p) {
-  std::vector<int64_t> zero_rows, nn_rows, exp_st, pow_st, psd_st;
+  std::vector<int64_t> zero_rows, nn_rows, exp_st, pow_st;
   std::vector<double> pow_a;
-  std::map<int, std::vector<int64_t>> soc_st;
-  int psd_k = 0;
+  std::map<int, std::vector<int64_t>> soc_st, psd_st;   // by SOC dim / PSD side
   int64_t r = 0;
   for (int c = 0; c < p->ncones; ++c) {
     const hc_cone& k = p->cones[c];
@@ -239,7 +235,7 @@ void build_segments(hc_solver* S, const hc_problem* p) {
       case HC_CONE_SOC: soc_st[k.dim].push_back(r); r += k.dim; break;
       case HC_CONE_EXP: exp_st.push_back(r); r += 3; break;
       case HC_CONE_POW: pow_st.push_back(r); pow_a.push_back(k.alpha); r += 3; break;
-      case HC_CONE_PSD: psd_st.push_back(r); psd_k = k.dim; r += (int64_t)k.dim * (k.dim + 1) / 2; break;
+      case HC_CONE_PSD: psd_st[k.dim].push_back(r); r += (int64_t)k.dim * (k.dim + 1) / 2; break;
     }
   }
   S->perm.assign(S->m, -1);
@@ -280,12 +276,15 @@ void build_segments(hc_solver* S, const hc_problem* p) {
     S->alpha_pow = pow_a;
     add(HC_CONE_POW, N, 3, 0);
   }
-  if (!psd_st.empty()) {
-    const int64_t N = psd_st.size();
-    const int sd = psd_k * (psd_k + 1) / 2;
+  // PSD cones of several sides: one segment per side (ascending), each with
+  // its own k, state and M-block layout
+  for (auto& kv : psd_st) {
+    const int pk = kv.first;
+    const int64_t N = kv.second.size();
+    const int sd = pk * (pk + 1) / 2;
     for (int64_t i = 0; i < N; ++i)
-      for (int j = 0; j < sd; ++j) S->perm[base + i * sd + j] = psd_st[i] + j;
-    add(HC_CONE_PSD, N, sd, psd_k);
+      for (int j = 0; j < sd; ++j) S->perm[base + i * sd + j] = kv.second[i] + j;
+    add(HC_CONE_PSD, N, sd, pk);
   }
   S->stotal = state;
   S->mtotal = moff;

@@ -327,6 +327,25 @@ def psd_pow(seed: int = 0, n: int = 5000, n_pow: int = 20000, n_psd: int = 2000,
                    name=f"psd_pow(seed={seed},n={n},pow={n_pow},psd={n_psd}x{k})")
 
 
+def psd_mixed(seed: int = 0, n: int = 300, sides=(3, 5, 8), per_side: int = 20, nnz_row: int = 8) -> Problem:
+    """P = 0; PSD cones of several sides (per_side cones of each side, the
+    sides interleaved in row order) with planted interior points as in
+    psd_pow; A has nnz_row distinct uniform columns per row, N(0,1)."""
+    rng = np.random.default_rng(seed)
+    order = [k for _ in range(per_side) for k in sides]
+    m = sum(k * (k + 1) // 2 for k in order)
+    cols, vals = _random_rows_fast(rng, m, n, nnz_row)
+    A = sp.csr_matrix((vals.ravel(), cols.ravel(), np.arange(m + 1) * nnz_row), shape=(m, n))
+    x0 = rng.standard_normal(n)
+    s0 = np.concatenate([svec_encode(_spd_sample(rng, 1, k)).ravel() for k in order])
+    z0 = np.concatenate([svec_encode(_spd_sample(rng, 1, k)).ravel() for k in order])
+    b = A @ x0 + s0
+    q = -(A.T @ z0)
+    cones = [(PSD, k, 0.0) for k in order]
+    return Problem(n, m, sp.csr_matrix((n, n)), q, A, b, cones,
+                   name=f"psd_mixed(seed={seed},n={n},sides={tuple(sides)}x{per_side})")
+
+
 # --------------------------------------------------------------------------
 # served MPC stream
 # --------------------------------------------------------------------------

@@ -58,6 +58,7 @@ CASES = [
     # with leaf blocks (the t variables)
     ("entropy_dense_rows", lambda: W.entropy_max(0, n=600)),
     ("portfolio_small", lambda: W.portfolio_qp(0, n=300)),
+    ("psd_mixed_sides", lambda: W.psd_mixed(0)),
 ]
 
 @pytest.mark.parametrize("name,make", CASES)

@@ -69,3 +69,28 @@ def test_portfolio_qp_oracle_bounds(seed):
     xs = x[:n]
     assert abs(xs.sum() - 1.0) < 1e-7 and xs.min() > -1e-8
     assert abs(f(xs) - r.objective) <= 1e-6 * max(1.0, abs(r.objective))
+
+
+def test_psd_cones_of_several_sides_oracle():
+    """PSD cones of sides 3, 5 and 8 interleaved in row order: the oracle
+    groups them by side and solves; the solution satisfies the termination
+    inequalities on the user's data and s, z are PSD cone by cone."""
+    p = W.psd_mixed(0, n=120, sides=(2, 4, 6), per_side=6)
+    r = ipm.solve(p)
+    assert r.status == ipm.SOLVED
+    x, s, z = r.solution()
+    row = 0
+    for kind, k, _ in p.cones:
+        sd = k * (k + 1) // 2
+        for v in (s, z):
+            X = np.zeros((k, k))
+            # svec: upper triangle column by column, off-diagonals scaled by sqrt 2
+            vals = v[row:row + sd]
+            idx = 0
+            for j in range(k):
+                for i in range(j + 1):
+                    X[i, j] = X[j, i] = vals[idx] / (1.0 if i == j else np.sqrt(2.0))
+                    idx += 1
+            assert np.linalg.eigvalsh(X).min() > -1e-7
+        row += sd
+    assert abs(s @ z) <= 1e-6 * max(1.0, abs(r.objective))
