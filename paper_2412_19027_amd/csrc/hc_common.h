@@ -49,12 +49,20 @@ struct Segment {
   int64_t moff;    // offset of its (H + delta I)^-1 lower-triangle entries
 };
 
+// Second-order cones of dimension up to SOC_DMAX run one lane per cone; larger
+// ones one workgroup per cone (the intra-cone reductions of Sec. 3.4) and enter
+// the Schur complement through a diagonal plus rank-2 form of their block
+// (M_c = f_o I + (f_+ - f_o) v_+ v_+' + (f_- - f_o) v_- v_-').
+constexpr int SOC_DMAX = 16;
+__host__ __device__ inline bool soc_large(int kind, int dim) { return kind == HC_CONE_SOC && dim > SOC_DMAX; }
+
 // per-cone scaling state, doubles per cone
 inline int64_t state_doubles(int kind, int dim, int k) {
   switch (kind) {
     case HC_CONE_ZERO: return 0;
     case HC_CONE_NONNEG: return 1;                 // h = s / z
-    case HC_CONE_SOC: return dim + 1 + dim;        // wbar (dim), eta, lambda (dim)
+    case HC_CONE_SOC:                              // wbar (dim), eta, lambda (dim) [, |wbar_1|]
+      return dim + 1 + dim + (dim > SOC_DMAX ? 1 : 0);
     case HC_CONE_EXP:
     case HC_CONE_POW: return 3 + 9 + 9 + 3 + 3 + 1;  // lam, V, Uhinv, sig_hinv, grad, branch
     case HC_CONE_PSD: return 3 * (int64_t)k * k + 2 * k;    // R, Rinv, Q, lambda, m
@@ -63,6 +71,7 @@ inline int64_t state_doubles(int kind, int dim, int k) {
 }
 inline int64_t mblock_doubles(int kind, int dim) {
   if (kind == HC_CONE_ZERO || kind == HC_CONE_NONNEG) return 1;
+  if (soc_large(kind, dim)) return 3;   // f_o, f_+ - f_o, f_- - f_o
   return (int64_t)dim * (dim + 1) / 2;
 }
 

@@ -48,9 +48,52 @@ void cone_unit(const SegDev& g, double* v, hipStream_t st);   // v[rows] = unit 
 int cone_max_neg_eig(const SegDev& g, const double* v, double* partial, hipStream_t st);
 void cone_add_e(const SegDev& g, double a, double* v, hipStream_t st);   // v += a e (symmetric cones)
 
+// largest alpha > 0 with (x + alpha dx)'J(x + alpha dx) >= 0 given
+// a = dx'J dx, b = x'J dx, c = x'J x: the smallest positive root of
+// a t^2 + 2b t + c (INFINITY when there is none)
+__device__ inline double soc_boundary_step(double a, double b, double c) {
+  const double B = 2.0 * b;
+  double best = INFINITY;
+  if (a == 0.0) {
+    if (B != 0.0) {
+      const double t = -c / B;
+      if (t > 0.0) best = t;
+    }
+    return best;
+  }
+  const double disc = B * B - 4.0 * a * c;
+  if (disc < 0.0) return best;
+  const double qq = -0.5 * (B + copysign(sqrt(disc), B));
+  if (qq != 0.0) {
+    const double r1 = qq / a, r2 = c / qq;
+    if (r1 > 0.0) best = fmin(best, r1);
+    if (r2 > 0.0) best = fmin(best, r2);
+  }
+  return best;
+}
+
+// second-order cones above SOC_DMAX: one workgroup per cone (hc_soc.hip), a
+// grid of at most LS_GRID workgroups striding over the cones
+constexpr int LS_GRID = 2048;
+inline int lsoc_grid(int64_t count) { return (int)std::min<int64_t>(std::max<int64_t>(count, 1), LS_GRID); }
+void lsoc_scale(const SegDev& g, const double* s, const double* z, double* hdiag, hipStream_t st);
+// y = H x (mode 0) or (H + delta I)^-1 x (mode 1); with dsr: y = -dsr - H x
+void lsoc_apply(const SegDev& g, int mode, double delta, const double* x, const double* dsr, double* y,
+                hipStream_t st);
+void lsoc_ds(const SegDev& g, const double* dsa, const double* dza, double sm, double* ds, hipStream_t st);
+// per workgroup minimum step (or per cone, capped at amax); returns the grid
+int lsoc_step(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz, double amax,
+              bool per_cone, double* out, hipStream_t st);
+int lsoc_max_neg_eig(const SegDev& g, const double* v, double* partial, hipStream_t st);
+// p_- = A_c' v_- at Ad[ent_dst[e]] and p_+ = A_c' v_+ at Ad[ent_dst[e] + plus_off]
+// for each (cone, column) entry e of the segment
+void lsoc_lowrank(const SegDev& g, int64_t nent, const int32_t* ent_cone, const int32_t* ent_col,
+                  const int64_t* ent_dst, const Csr& At, int64_t plus_off, double* Ad, hipStream_t st);
+
 constexpr int CONE_BLOCK = 256;
 inline int cone_blocks(const SegDev& g) {
   if (g.kind == HC_CONE_PSD) return (int)std::max<int64_t>(1, ceil_div(g.count, CONE_BLOCK));
+  if (soc_large(g.kind, g.dim)) return lsoc_grid(g.count);
   int64_t units = (g.kind == HC_CONE_ZERO || g.kind == HC_CONE_NONNEG) ? g.count : g.count;
   return (int)std::max<int64_t>(1, ceil_div(units, CONE_BLOCK));
 }

@@ -26,7 +26,6 @@
 
 namespace hc {
 
-constexpr int SOC_DMAX = 16;
 constexpr int PSD_KMAX = 12;
 
 __device__ inline double sq(double x) { return x * x; }
@@ -655,6 +654,10 @@ void cone_scale(const SegDev& g, const double* s, const double* z, double mu, in
       hipLaunchKernelGGL(k_nonneg_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, hdiag);
       break;
     case HC_CONE_SOC:
+      if (soc_large(g.kind, g.dim)) {
+        lsoc_scale(g, s, z, hdiag, st);
+        return;
+      }
       hipLaunchKernelGGL(k_soc_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, hdiag);
       break;
     case HC_CONE_EXP:
@@ -780,7 +783,9 @@ __global__ __launch_bounds__(PSD_TB) void k_psd_apply(SegDev g, int mode, double
 
 void cone_apply(const SegDev& g, int mode, double delta, const double* x, double* y, hipStream_t st) {
   if (g.count == 0) return;
-  if (g.kind == HC_CONE_PSD)
+  if (soc_large(g.kind, g.dim))
+    lsoc_apply(g, mode, delta, x, nullptr, y, st);
+  else if (g.kind == HC_CONE_PSD)
     hipLaunchKernelGGL(k_psd_apply, dim3(psd_blocks(g.count)), dim3(PSD_TB), 0, st, g, mode, delta, x, y);
   else
     hipLaunchKernelGGL(k_cone_apply, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, mode, delta, x, y);
@@ -844,7 +849,9 @@ __global__ __launch_bounds__(PSD_TB) void k_psd_recover(SegDev g, const double* 
 
 void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, double* out, hipStream_t st) {
   if (g.count == 0) return;
-  if (g.kind == HC_CONE_PSD)
+  if (soc_large(g.kind, g.dim))
+    lsoc_apply(g, 0, 0.0, dz, dsrhs, out, st);
+  else if (g.kind == HC_CONE_PSD)
     hipLaunchKernelGGL(k_psd_recover, dim3(psd_blocks(g.count)), dim3(PSD_TB), 0, st, g, dsrhs, dz, out);
   else
     hipLaunchKernelGGL(k_cone_recover, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, dsrhs, dz, out);
@@ -914,6 +921,16 @@ __global__ void k_cone_mblock(SegDev g, double delta) {
       break;
     case HC_CONE_SOC: {
       const int d = g.dim;
+      if (d > SOC_DMAX) {   // diagonal plus rank-2 coefficients (hc_soc.hip)
+        const double w0 = g.state[i], eta = g.state[(int64_t)d * N + i], r = g.state[(2 * (int64_t)d + 1) * N + i];
+        const double big = w0 + r, e2 = eta * eta;
+        const double fp = 1.0 / (e2 * big * big + delta), fm = 1.0 / (e2 / (big * big) + delta);
+        const double fo = 1.0 / (e2 + delta);
+        g.mblk[i] = fo;
+        g.mblk[N + i] = fp - fo;
+        g.mblk[2 * N + i] = fm - fo;
+        break;
+      }
       double wb[SOC_DMAX], u[SOC_DMAX];
       for (int j = 0; j < d; ++j) wb[j] = g.state[j * N + i];
       const SocSpec sp = soc_spec(wb, d, g.state[d * N + i]);
@@ -1128,7 +1145,9 @@ __global__ __launch_bounds__(PSD_TB) void k_psd_ds(SegDev g, const double* __res
 void cone_ds_combined(const SegDev& g, const double* s, const double* z, const double* dsa, const double* dza,
                       double sm, double* ds, hipStream_t st) {
   if (g.count == 0) return;
-  if (g.kind == HC_CONE_PSD)
+  if (soc_large(g.kind, g.dim))
+    lsoc_ds(g, dsa, dza, sm, ds, st);
+  else if (g.kind == HC_CONE_PSD)
     hipLaunchKernelGGL(k_psd_ds, dim3(psd_blocks(g.count)), dim3(PSD_TB), 0, st, g, dsa, dza, sm, ds);
   else
     hipLaunchKernelGGL(k_cone_ds, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, s, z, dsa, dza, sm, ds);
@@ -1145,25 +1164,7 @@ __device__ inline double soc_step_one(const double* x, const double* dx, int d) 
     b -= x[j] * dx[j];
     c -= x[j] * x[j];
   }
-  // smallest positive root of a t^2 + (2b) t + c = 0
-  const double B = 2.0 * b;
-  double best = INFINITY;
-  if (a == 0.0) {
-    if (B != 0.0) {
-      const double t = -c / B;
-      if (t > 0.0) best = t;
-    }
-    return best;
-  }
-  const double disc = B * B - 4.0 * a * c;
-  if (disc < 0.0) return best;
-  const double qq = -0.5 * (B + copysign(sqrt(disc), B));
-  if (qq != 0.0) {
-    const double r1 = qq / a, r2 = c / qq;
-    if (r1 > 0.0) best = fmin(best, r1);
-    if (r2 > 0.0) best = fmin(best, r2);
-  }
-  return best;
+  return soc_boundary_step(a, b, c);
 }
 
 // largest alpha with x + alpha dx PSD (INFINITY if unbounded); ws: 3 PSD_MAT doubles
@@ -1244,6 +1245,7 @@ __global__ __launch_bounds__(PSD_TB) void k_step_psd(SegDev g, const double* __r
 int cone_step_sym(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz,
                   double* partial, hipStream_t st) {
   if (g.count == 0 || g.kind == HC_CONE_ZERO || g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) return 0;
+  if (soc_large(g.kind, g.dim)) return lsoc_step(g, s, z, ds, dz, INFINITY, false, partial, st);
   if (g.kind == HC_CONE_PSD) {
     const int nbp = std::min(psd_blocks(g.count), PSD_STEP_GRID);
     hipLaunchKernelGGL(k_step_psd, dim3(nbp), dim3(PSD_TB), 0, st, g, s, z, ds, dz, partial);
@@ -1424,6 +1426,7 @@ __global__ void k_max_neg_eig(SegDev g, const double* __restrict__ v, double* __
 
 int cone_max_neg_eig(const SegDev& g, const double* v, double* partial, hipStream_t st) {
   if (g.count == 0 || !(g.kind == HC_CONE_NONNEG || g.kind == HC_CONE_SOC || g.kind == HC_CONE_PSD)) return 0;
+  if (soc_large(g.kind, g.dim)) return lsoc_max_neg_eig(g, v, partial, st);
   const int nb = cone_blocks(g);
   hipLaunchKernelGGL(k_max_neg_eig, dim3(nb), dim3(CONE_BLOCK), 0, st, g, v, partial);
   HC_LAUNCH_CHECK();
@@ -1540,6 +1543,10 @@ __global__ void k_test_step(SegDev g, const double* __restrict__ s, const double
 
 void cone_test_step(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz,
                     double amax, double* out, hipStream_t st) {
+  if (soc_large(g.kind, g.dim)) {
+    lsoc_step(g, s, z, ds, dz, amax, true, out, st);
+    return;
+  }
   hipLaunchKernelGGL(k_test_step, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, s, z, ds, dz, amax, out);
   HC_LAUNCH_CHECK();
 }

@@ -72,6 +72,20 @@ struct hc_solver {
   std::vector<double> Ad;          // dense rows, row-major nd x n
   std::vector<int32_t> drows;      // their internal rows
   std::vector<int64_t> dmidx;      // their M index
+  // second-order cones above SOC_DMAX enter S as f_o A_c'A_c (diagonal tasks)
+  // plus two dense rows each, p_- = A_c'v_- (weight f_- - f_o >= 0) and
+  // p_+ = A_c'v_+ (weight f_+ - f_o <= 0).  Dense-row operand rows:
+  // [0, nd) real dense rows, [nd, nd + nls) p_-, zero padding to K1 (a multiple
+  // of 16, product with +1), [K1, K1 + nls) p_+, padding to K1 + K2 (with -1).
+  int64_t nls = 0, K1 = 0, K2 = 0;
+  std::vector<int64_t> dmidx_all;  // M index per operand row (-1: padding)
+  std::vector<int32_t> ls_cone, ls_col;   // (cone, column) entries of the p rows
+  std::vector<int64_t> ls_dst;            // offset of p_- for the entry in the operand
+  struct LsRange {
+    int seg;
+    int64_t first, count;
+  };
+  std::vector<LsRange> ls_ranges;  // entries of each large-SOC segment
   std::vector<double> q, b, D, E;  // scaled q, b; equilibration factors
   double cscale = 1.0;
   double bnorm_user = 0, qnorm_user = 0, maxPdiag = 0;
@@ -100,6 +114,8 @@ struct hc_solver {
   double *dAd = nullptr, *dBd = nullptr;
   int32_t* ddrows = nullptr;
   int64_t* ddmidx = nullptr;
+  int32_t *dls_cone = nullptr, *dls_col = nullptr;
+  int64_t* dls_dst = nullptr;
   double *dq = nullptr, *db = nullptr, *dD = nullptr, *dE = nullptr, *dalpha = nullptr;
   int32_t *dtra = nullptr, *dtrb = nullptr;
   int64_t* dtm = nullptr;
@@ -198,7 +214,7 @@ void validate(const hc_problem* p) {
         break;
       case HC_CONE_SOC:
         if (k.dim < 2) fail(HC_ERR_CONE, "SOC dim < 2");
-        if (k.dim > 16) fail(HC_ERR_UNSUPPORTED, "SOC dim > 16 is not handled by this build");
+        if (k.dim > (1 << 24)) fail(HC_ERR_UNSUPPORTED, "SOC dim > 2^24 is not handled by this build");
         rows += k.dim;
         break;
       case HC_CONE_EXP:
@@ -395,6 +411,8 @@ void equilibrate(hc_solver* S, const HostCsr& A, const HostCsr& Pf, const std::v
 // ---------------------------------------------------------------------------
 constexpr int LEAF_DEGREE = 64;
 
+void build_lowrank(hc_solver* S, int nd);
+
 void build_leaves(hc_solver* S) {
   const int64_t n = S->n;
   const HostCsr& A = S->A;
@@ -404,6 +422,11 @@ void build_leaves(hc_solver* S) {
   for (int d = 0; d < nd; ++d)
     for (int64_t j = 0; j < n; ++j)
       if (S->Ad[(size_t)d * n + j] != 0.0) tail[j] = 1;
+  // the rank-2 rows of large second-order cones are dense rows on the tail
+  for (const Segment& g : S->segs)
+    if (soc_large(g.kind, g.dim))
+      for (int64_t r = g.base; r < g.base + (int64_t)g.dim * g.count; ++r)
+        for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) tail[A.ci[k]] = 1;
   // cliques (CSR over columns)
   std::vector<int64_t> cp{0};
   std::vector<int32_t> cc;
@@ -689,6 +712,17 @@ void setup_host(hc_solver* S, const hc_problem* p) {
       }
       continue;
     }
+    if (soc_large(g.kind, g.dim)) {   // f_o A_c'A_c: one diagonal task per row, weight f_o of its cone
+      for (int a = 0; a < g.dim; ++a)
+        for (int64_t c2 = 0; c2 < g.count; ++c2) {
+          const int64_t ra = g.base + a * g.count + c2;
+          if (As.rp[ra + 1] == As.rp[ra]) continue;
+          S->tra.push_back((int32_t)ra);
+          S->trb.push_back((int32_t)ra);
+          S->tm.push_back(g.moff + c2);
+        }
+      continue;
+    }
     for (int64_t c2 = 0; c2 < g.count; ++c2)
       for (int a = 0; a < g.dim; ++a)
         for (int bb = 0; bb <= a; ++bb) {
@@ -709,9 +743,56 @@ void setup_host(hc_solver* S, const hc_problem* p) {
       for (int64_t t = 0; t < S->nt; ++t) Adt[(size_t)d * S->nt + t] = S->Ad[(size_t)d * n + S->tail_cols[t]];
     S->Ad.swap(Adt);
   }
+  build_lowrank(S, nd);
   S->ld = ((S->nt + 63) / 64) * 64;
   if (S->st.static_reg <= 0) S->st.static_reg = S->mixed ? 3.4526698300124393e-04 : 1e-8;
   if (S->st.dyn_reg < 0) S->st.dyn_reg = S->mixed ? std::ldexp(1.0, -46) : std::ldexp(1.0, -104);
+}
+
+// (cone, column) entries of the rank-2 rows of the large second-order cones
+// and the M index of every row of the dense-row operand
+void build_lowrank(hc_solver* S, int nd) {
+  const int64_t nt = S->nt;
+  S->nls = 0;
+  S->ls_cone.clear();
+  S->ls_col.clear();
+  S->ls_dst.clear();
+  S->ls_ranges.clear();
+  std::vector<int32_t> cols;
+  for (size_t si = 0; si < S->segs.size(); ++si) {
+    const Segment& g = S->segs[si];
+    if (!soc_large(g.kind, g.dim)) continue;
+    const int64_t first = (int64_t)S->ls_cone.size();
+    for (int64_t c = 0; c < g.count; ++c) {
+      cols.clear();
+      for (int a = 0; a < g.dim; ++a) {
+        const int64_t r = g.base + a * g.count + c;
+        for (int32_t k = S->A.rp[r]; k < S->A.rp[r + 1]; ++k) cols.push_back(S->A.ci[k]);
+      }
+      std::sort(cols.begin(), cols.end());
+      cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+      for (int32_t j : cols) {
+        if (S->col_leaf[j] >= 0) fail(HC_ERR_UNSUPPORTED, "large SOC column outside the dense tail");
+        S->ls_cone.push_back((int32_t)c);
+        S->ls_col.push_back(j);
+        S->ls_dst.push_back((nd + S->nls + c) * nt + S->col_loc[j]);
+      }
+    }
+    S->ls_ranges.push_back({(int)si, first, (int64_t)S->ls_cone.size() - first});
+    S->nls += g.count;
+  }
+  S->K1 = (nd + S->nls + 15) / 16 * 16;
+  S->K2 = (S->nls + 15) / 16 * 16;
+  S->dmidx_all.assign(S->K1 + S->K2, -1);
+  for (int d = 0; d < nd; ++d) S->dmidx_all[d] = S->dmidx[d];
+  int64_t lc = 0;
+  for (const auto& rg : S->ls_ranges) {
+    const Segment& g = S->segs[rg.seg];
+    for (int64_t c = 0; c < g.count; ++c, ++lc) {
+      S->dmidx_all[nd + lc] = g.moff + 2 * g.count + c;   // f_- - f_o
+      S->dmidx_all[S->K1 + lc] = g.moff + g.count + c;    // f_+ - f_o
+    }
+  }
 }
 
 // keep a copy of the user's problem (hc_update_data rebuilds from it)
@@ -960,11 +1041,18 @@ void factor(hc_solver* S, bool fp64 = false) {
     assemble_pairs((int64_t)S->tra.size(), S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->ld, S->dS, st);
   }
   const int nd = (int)S->drows.size();
-  if (nd) {
-    // the operand carries zero columns up to a multiple of 16 (set at bind),
-    // which lets the update run on the MFMA DMA kernel
-    scale_dense_rows(nd, nt, S->dAd, S->ddmidx, S->dmval, S->dBd, st);
-    gemm_nt<double>(S->dS, S->ld, S->dBd, nt, S->dBd, nt, nt, nt, (nd + 15) / 16 * 16, 1.0, true, 0, 0, st);
+  if (S->K1 > 0) {
+    for (const auto& rg : S->ls_ranges)
+      lsoc_lowrank(S->sdev[rg.seg], rg.count, S->dls_cone + rg.first, S->dls_col + rg.first, S->dls_dst + rg.first,
+                   S->dAt, (S->K1 - nd) * nt, S->dAd, st);
+    // the operand carries zero rows up to multiples of 16 (set at bind), which
+    // lets the update run on the MFMA DMA kernel; rows of negative weight
+    // (the p_+ rows) form the second block, subtracted
+    scale_dense_rows((int)(S->K1 + S->K2), nt, S->dAd, S->ddmidx, S->dmval, S->dBd, st);
+    gemm_nt<double>(S->dS, S->ld, S->dBd, nt, S->dBd, nt, nt, nt, S->K1, 1.0, true, 0, 0, st);
+    if (S->K2 > 0)
+      gemm_nt<double>(S->dS, S->ld, S->dBd + S->K1 * nt, nt, S->dBd + S->K1 * nt, nt, nt, nt, S->K2, -1.0, true, 0,
+                      0, st);
   }
   const double tol = 0.0;
   // leaves are factored in FP64 in both modes; their updates land in the tail
@@ -1318,6 +1406,7 @@ __global__ void k_identity_state(SegDev g, double* hdiag) {
       hdiag[g.base + j * N + i] = 1.0;
     }
     g.state[g.dim * N + i] = 1.0;
+    if (g.dim > SOC_DMAX) g.state[(2 * (int64_t)g.dim + 1) * N + i] = 0.0;   // |wbar_1|
   } else if (g.kind == HC_CONE_PSD) {
     const int k = g.k;
     const int64_t kk = (int64_t)k * k;
@@ -1501,11 +1590,18 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->dA = upload_csr(buf, S->A, st);
   S->dAt = upload_csr(buf, S->At, st);
   S->dP = upload_csr(buf, S->P, st);
-  S->dAd = upload(buf, S->Ad, st);
-  const size_t nd_pad = (S->drows.size() + 15) / 16 * 16;
-  S->dBd = buf.take<double>(std::max<size_t>(1, nd_pad * (size_t)S->nt));
+  {   // real dense rows, then the rows the large second-order cones fill
+    const size_t rows = std::max<size_t>(S->drows.size(), (size_t)(S->K1 + S->K2));
+    S->dAd = buf.take<double>(std::max<size_t>(1, rows * (size_t)S->nt));
+    if (!buf.dry && !S->Ad.empty())
+      HC_HIP(hipMemcpyAsync(S->dAd, S->Ad.data(), S->Ad.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  S->dBd = buf.take<double>(std::max<size_t>(1, (size_t)(S->K1 + S->K2) * (size_t)S->nt));
   S->ddrows = upload(buf, S->drows, st);
-  S->ddmidx = upload(buf, S->dmidx, st);
+  S->ddmidx = upload(buf, S->dmidx_all, st);
+  S->dls_cone = upload(buf, S->ls_cone, st);
+  S->dls_col = upload(buf, S->ls_col, st);
+  S->dls_dst = upload(buf, S->ls_dst, st);
   S->dq = upload(buf, S->q, st);
   S->db = upload(buf, S->b, st);
   S->dD = upload(buf, S->D, st);
@@ -1606,8 +1702,13 @@ void bind(hc_solver* S, const hc_device* dev) {
   HC_HIP(hipHostMalloc((void**)&S->hpart, 4096 * sizeof(double), hipHostMallocDefault));
   HC_HIP(hipHostMalloc((void**)&S->hmask, 4096 * sizeof(unsigned long long), hipHostMallocDefault));
   HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), st));
-  if (!S->drows.empty())   // zero padding columns of the dense-row operand
-    HC_HIP(hipMemsetAsync(S->dBd, 0, (S->drows.size() + 15) / 16 * 16 * (size_t)S->nt * sizeof(double), st));
+  if (S->K1 + S->K2 > 0) {   // zero padding rows of the dense-row operand, zero rank-2 rows
+    HC_HIP(hipMemsetAsync(S->dBd, 0, (size_t)(S->K1 + S->K2) * S->nt * sizeof(double), st));
+    const size_t real = S->drows.size() * (size_t)S->nt;
+    const size_t rows = std::max<size_t>(S->drows.size(), (size_t)(S->K1 + S->K2));
+    if (rows * S->nt > real)
+      HC_HIP(hipMemsetAsync(S->dAd + real, 0, (rows * S->nt - real) * sizeof(double), st));
+  }
   // segment views
   int pow_off = 0;
   for (const Segment& g : S->segs) {

@@ -56,7 +56,7 @@ void make(TestSeg& T, int32_t type, int64_t count, int32_t dim, const double* al
       T.cm = false;
       break;
     case HC_CONE_SOC:
-      if (dim < 2 || dim > 16) throw Error{HC_ERR_UNSUPPORTED, "SOC dim outside [2, 16]"};
+      if (dim < 2 || dim > (1 << 24)) throw Error{HC_ERR_UNSUPPORTED, "SOC dim outside [2, 2^24]"};
       T.rows = dim; T.g.dim = dim; T.g.count = count; T.cm = true;
       break;
     case HC_CONE_EXP:
@@ -173,8 +173,31 @@ int32_t hc_test_cone_mblock(int32_t type, int64_t count, int32_t dim, const doub
     HC_HIP(hipMemcpyAsync(hm.data(), T.g.mblk, hm.size() * 8, hipMemcpyDeviceToHost, st));
     HC_HIP(hipStreamSynchronize(st));
     const int64_t N = T.g.count;
+    std::vector<double> hs;
+    if (soc_large(type, T.g.dim)) {   // the stored form: f_o I + (f_+ - f_o) v_+v_+' + (f_- - f_o) v_-v_-'
+      hs.resize(state_doubles(type, T.g.dim, 0) * N);
+      HC_HIP(hipMemcpyAsync(hs.data(), T.g.state, hs.size() * 8, hipMemcpyDeviceToHost, st));
+      HC_HIP(hipStreamSynchronize(st));
+    }
     for (int64_t c = 0; c < count; ++c) {
       double* D = dense.data() + (size_t)c * T.rows * T.rows;
+      if (!hs.empty()) {
+        const int d = T.rows;
+        const double r = hs[(2 * (int64_t)d + 1) * N + c];
+        std::vector<double> vp(d), vm(d);
+        const double is2 = 0.70710678118654752440;
+        vp[0] = vm[0] = is2;
+        for (int j = 1; j < d; ++j) {
+          const double u = r > 0.0 ? hs[(int64_t)j * N + c] / r : (j == 1 ? 1.0 : 0.0);
+          vp[j] = is2 * u;
+          vm[j] = -is2 * u;
+        }
+        const double fo = hm[c], cp = hm[N + c], cmn = hm[2 * N + c];
+        for (int a = 0; a < d; ++a)
+          for (int b = 0; b < d; ++b)
+            D[a * d + b] = (a == b ? fo : 0.0) + cp * vp[a] * vp[b] + cmn * vm[a] * vm[b];
+        continue;
+      }
       if (type == HC_CONE_ZERO || type == HC_CONE_NONNEG) {
         for (int i = 0; i < T.rows; ++i) D[i * T.rows + i] = hm[c * T.rows + i];
         continue;

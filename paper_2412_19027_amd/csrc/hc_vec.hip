@@ -315,12 +315,14 @@ void assemble_pairs(int64_t ntask, const int32_t* tra, const int32_t* trb, const
   HC_LAUNCH_CHECK();
 }
 
-// B (nd x n row-major, i.e. n x nd column-major with ld n) = sqrt(m_r) Ad[r, :]
+// B (nd x n row-major, i.e. n x nd column-major with ld n) = sqrt|m_r| Ad[r, :];
+// rows with midx < 0 are padding and stay zero
 __global__ void k_scale_dense_rows(int nd, int64_t n, const double* __restrict__ Ad, const int64_t* __restrict__ midx,
                                    const double* __restrict__ mval, double* __restrict__ B) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (j < n) B[(int64_t)r * n + j] = sqrt(mval[midx[r]]) * Ad[(int64_t)r * n + j];
+  const int64_t mi = midx[r];
+  if (j < n) B[(int64_t)r * n + j] = mi < 0 ? 0.0 : sqrt(fabs(mval[mi])) * Ad[(int64_t)r * n + j];
 }
 void scale_dense_rows(int nd, int64_t n, const double* Ad, const int64_t* midx, const double* mval, double* B,
                       hipStream_t st) {

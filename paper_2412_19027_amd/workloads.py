@@ -463,6 +463,106 @@ def portfolio_qp(seed: int = 0, n: int = 25000, density: float = 0.1, gamma: flo
     return Problem(nv, A.shape[0], sp.triu(P).tocsr(), q, A, b, cones, name=f"portfolio_qp(seed={seed},n={n},p={p})")
 
 
+def multistage_portfolio(seed: int = 0, n: int = 5000, k: int = 50, T: int = 5, density: float = 0.1,
+                         gamma: float = 1.0, cost: float = 0.01, inflow: float = 0.1) -> Problem:
+    """Multistage portfolio SOCP (eq. multistage_socp): over T periods,
+    minimize sum_t -mu_t'x_t + cost 1'z_t + gamma r_t subject to
+    z_t >= +-(x_t - x_{t-1}), 1'x_1 = inflow + 1'x_0, 1'x_t = 1'x_{t-1},
+    y_t = F_t x_t, (r_t, U y_t, D_sqrt o x_t) in the SOC of dimension n + k + 1,
+    x_t in [0, 0.1]^n, y_t in [0, 0.1]^k, r_t >= 0 (z_t free).
+    Variables stage by stage: [x_t (n), y_t (k), z_t (n), r_t].
+    Distributions (the paper gives none): x_0 = 1/n, mu_t ~ N(0, 1),
+    F_t (k x n) with N(0, 1) entries present with probability `density`,
+    U the upper Cholesky factor of G G'/k + I (G ~ N(0, 1), k x k),
+    D_sqrt = sqrt(D) with D_ii ~ U(0, sqrt(k))."""
+    rng = np.random.default_rng(seed)
+    V = 2 * n + k + 1
+    nv = T * V
+    G = rng.standard_normal((k, k))
+    U = np.linalg.cholesky(G @ G.T / k + np.eye(k)).T
+    Dsq = np.sqrt(rng.uniform(0.0, math.sqrt(k), n))
+    x0 = np.full(n, 1.0 / n)
+    xo = lambda t: t * V
+    yo = lambda t: t * V + n
+    zo = lambda t: t * V + n + k
+    ro = lambda t: t * V + 2 * n + k
+    q = np.zeros(nv)
+    zr, zc, zv, zb = [], [], [], []       # zero rows
+    nr, nc_, nvv, nb = [], [], [], []     # nonneg rows
+    sr, sc, svv = [], [], []              # SOC rows
+    row = [0, 0]
+
+    def add(cols, vals, tgt, r):
+        tgt[0].extend([r] * len(cols))
+        tgt[1].extend(cols)
+        tgt[2].extend(vals)
+
+    ar = np.arange(n)
+    for t in range(T):
+        q[xo(t):xo(t) + n] = -rng.standard_normal(n)
+        q[zo(t):zo(t) + n] = cost
+        q[ro(t)] = gamma
+        F = sp.random(k, n, density=density, random_state=rng, data_rvs=rng.standard_normal, format="csr")
+        # budget
+        cols = list(xo(t) + ar)
+        vals = [1.0] * n
+        if t > 0:
+            cols += list(xo(t - 1) + ar)
+            vals += [-1.0] * n
+        add(cols, vals, (zr, zc, zv), row[0])
+        zb.append(inflow + x0.sum() if t == 0 else 0.0)
+        row[0] += 1
+        # y_t - F_t x_t = 0
+        for i in range(k):
+            lo, hi = F.indptr[i], F.indptr[i + 1]
+            add([yo(t) + i] + list(xo(t) + F.indices[lo:hi]), [1.0] + list(-F.data[lo:hi]),
+                (zr, zc, zv), row[0])
+            zb.append(0.0)
+            row[0] += 1
+        # transactions: +-(x_t - x_{t-1}) - z_t <= 0 (x_0 moves to the right-hand side)
+        for sgn in (1.0, -1.0):
+            for i in range(n):
+                cols, vals = [xo(t) + i, zo(t) + i], [sgn, -1.0]
+                if t > 0:
+                    cols.append(xo(t - 1) + i)
+                    vals.append(-sgn)
+                add(cols, vals, (nr, nc_, nvv), row[1])
+                nb.append(sgn * x0[i] if t == 0 else 0.0)
+                row[1] += 1
+        # bounds: -x <= 0, x <= 0.1, -y <= 0, y <= 0.1, -r <= 0
+        for off, cnt in ((xo(t), n), (yo(t), k)):
+            for sgn, bound in ((-1.0, 0.0), (1.0, 0.1)):
+                for i in range(cnt):
+                    add([off + i], [sgn], (nr, nc_, nvv), row[1])
+                    nb.append(bound)
+                    row[1] += 1
+        add([ro(t)], [-1.0], (nr, nc_, nvv), row[1])
+        nb.append(0.0)
+        row[1] += 1
+    # SOC blocks: s = -A v = (r_t, U y_t, D_sqrt o x_t)
+    d = n + k + 1
+    for t in range(T):
+        base = t * d
+        add([ro(t)], [-1.0], (sr, sc, svv), base)
+        for i in range(k):
+            cols = [yo(t) + j for j in range(i, k)]
+            add(cols, list(-U[i, i:]), (sr, sc, svv), base + 1 + i)
+        sr.extend(base + 1 + k + ar)
+        sc.extend(xo(t) + ar)
+        svv.extend(-Dsq)
+    mz, mn, ms = row[0], row[1], T * d
+    Az = sp.csr_matrix((zv, (zr, zc)), shape=(mz, nv))
+    An = sp.csr_matrix((nvv, (nr, nc_)), shape=(mn, nv))
+    As = sp.csr_matrix((svv, (sr, sc)), shape=(ms, nv))
+    A = sp.vstack([Az, An, As]).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    b = np.concatenate([zb, nb, np.zeros(ms)])
+    cones = [(ZERO, mz, 0.0), (NONNEG, mn, 0.0)] + [(SOC, d, 0.0)] * T
+    return Problem(nv, A.shape[0], sp.csr_matrix((nv, nv)), q, A, b, cones,
+                   name=f"multistage_portfolio(seed={seed},n={n},k={k},T={T})")
+
+
 def config(name: str, seed: int = 0) -> Problem:
     if name == "tiny_lp":
         return tiny_lp(seed)
@@ -476,4 +576,6 @@ def config(name: str, seed: int = 0) -> Problem:
         return entropy_max(seed)
     if name == "portfolio_qp":
         return portfolio_qp(seed)
+    if name == "multistage_portfolio":
+        return multistage_portfolio(seed)
     raise KeyError(name)

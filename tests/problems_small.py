@@ -29,6 +29,36 @@ def soc_ball(seed=0, n=4, r=1.7):
     return Problem(n, n + 1, sp.csr_matrix((n, n)), c, A, b, [(SOC, n + 1, 0.0)], "soc_ball"), -r * np.linalg.norm(c)
 
 
+def soc_balls(seed=0, dims=(20, 150, 700), radii=(0.5, 1.0, 2.0)):
+    """min sum_i c_i'x_i, |x_i|_2 <= r_i over separate balls  ->  -sum_i r_i |c_i|."""
+    rng = np.random.default_rng(seed)
+    n = sum(dims)
+    c = rng.standard_normal(n)
+    blocks, b, fstar, off = [], [], 0.0, 0
+    for d, r in zip(dims, radii):
+        blk = sp.lil_matrix((d + 1, n))
+        for i in range(d):
+            blk[1 + i, off + i] = -1.0
+        blocks.append(blk.tocsr())
+        b += [r] + [0.0] * d
+        fstar -= r * np.linalg.norm(c[off:off + d])
+        off += d
+    A = sp.vstack(blocks).tocsr()
+    cones = [(SOC, d + 1, 0.0) for d in dims]
+    return Problem(n, A.shape[0], sp.csr_matrix((n, n)), c, A, np.array(b), cones, "soc_balls"), fstar
+
+
+def soc_ball_budget(seed=0, n=600, r=1.3):
+    """min c'x, |x|_2 <= r, 1'x = 0  ->  -r |c - mean(c) 1|  (the minimiser is
+    -r times the unit projection of c onto the hyperplane 1'x = 0)."""
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal(n)
+    A = sp.vstack([sp.csr_matrix(np.ones((1, n))), sp.csr_matrix((1, n)), -sp.identity(n)]).tocsr()
+    b = np.concatenate([[0.0, r], np.zeros(n)])
+    cones = [(ZERO, 1, 0.0), (SOC, n + 1, 0.0)]
+    return Problem(n, n + 2, sp.csr_matrix((n, n)), c, A, b, cones, "soc_ball_budget"), -r * np.linalg.norm(c - c.mean())
+
+
 def exp_max():
     """max x s.t. (x, 1, e) in K_exp  ->  x = 1 (objective -1)."""
     A = sp.csr_matrix(np.array([[-1.0], [0.0], [0.0]]))

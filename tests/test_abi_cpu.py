@@ -124,3 +124,23 @@ def test_update_data_on_host():
         assert (after.n_ordered, after.n_leaves) == (before.n_ordered, before.n_leaves)
     finally:
         L.hc_destroy(h)
+
+
+def test_large_soc_setup_on_host():
+    """Second-order cones above 16 rows: the host analysis accepts them, keeps
+    every column they touch in the dense tail (their rank-2 rows are dense
+    there) and leaves the z variables of the multistage problem as leaves."""
+    import ctypes as C
+    from paper_2412_19027_amd import workloads as W
+    L = hipcone.lib()
+    n, k, T = 40, 4, 3
+    prob = W.multistage_portfolio(0, n=n, k=k, T=T)
+    h, keep = hipcone._setup(prob, hipcone.default_settings())
+    try:
+        inf = hipcone.hc_info()
+        assert L.hc_get_info(h, C.byref(inf)) == 0
+        assert inf.n_ordered == T * (n + k + 1) and inf.n_leaves == T * n
+        nb = C.c_size_t()
+        assert L.hc_workspace_bytes(h, C.byref(nb)) == 0 and nb.value > 0
+    finally:
+        L.hc_destroy(h)

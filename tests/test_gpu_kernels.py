@@ -80,9 +80,10 @@ def test_nonneg_scale():
     assert relerr(np.diagonal(N(H), axis1=1, axis2=2), s / z) < 1e-15
 
 
-@pytest.mark.parametrize("d", [2, 3, 5])
+@pytest.mark.parametrize("d", [2, 3, 5, 17, 64, 700])
 def test_soc_scale(d):
-    s, z = soc_interior(300, d, RNG), soc_interior(300, d, RNG)
+    Nc = 300 if d <= 64 else 5
+    s, z = soc_interior(Nc, d, RNG), soc_interior(Nc, d, RNG)
     H, lam, _ = HC.test_cone_scale(HC.SOC, d, T(s), T(z), 1.0)
     ref = C.soc_scale(s, z)
     assert relerr(N(H), ref["H"]) < 1e-12
@@ -142,7 +143,7 @@ def _oracle_ds(kind, s, z, dsa, dza, mu, sm, k=None, alpha=None):
     return s + sm * sc["grad"] - 0.5 * fam.third(z, dza, u)
 
 
-@pytest.mark.parametrize("kind", ["nonneg", "soc", "exp", "pow", "psd"])
+@pytest.mark.parametrize("kind", ["nonneg", "soc", "soc_large", "exp", "pow", "psd"])
 def test_combined_ds(kind):
     Nc = 200
     mu, sm = 0.8, 0.05
@@ -151,6 +152,9 @@ def test_combined_ds(kind):
         s, z, dim, code = RNG.uniform(0.1, 2, (Nc, 1)), RNG.uniform(0.1, 2, (Nc, 1)), 1, HC.NONNEG
     elif kind == "soc":
         s, z, dim, code = soc_interior(Nc, 4, RNG), soc_interior(Nc, 4, RNG), 4, HC.SOC
+    elif kind == "soc_large":
+        s, z, dim, code = soc_interior(30, 300, RNG), soc_interior(30, 300, RNG), 300, HC.SOC
+        kind = "soc"
     elif kind == "exp":
         s, z, dim, code = exp_primal(Nc, RNG), exp_dual(Nc, RNG), 3, HC.EXP
     elif kind == "pow":
@@ -165,7 +169,7 @@ def test_combined_ds(kind):
 
 
 # ----------------------------------------------------------------- step lengths
-@pytest.mark.parametrize("kind", ["nonneg", "soc", "psd", "exp", "pow"])
+@pytest.mark.parametrize("kind", ["nonneg", "soc", "soc_large", "psd", "exp", "pow"])
 def test_step(kind):
     Nc = 150
     alpha = None
@@ -173,6 +177,10 @@ def test_step(kind):
         s, z, dim, code = RNG.uniform(0.1, 2, (Nc, 1)), RNG.uniform(0.1, 2, (Nc, 1)), 1, HC.NONNEG
     elif kind == "soc":
         s, z, dim, code = soc_interior(Nc, 3, RNG), soc_interior(Nc, 3, RNG), 3, HC.SOC
+    elif kind == "soc_large":   # more cones than the grid of one launch (2048)
+        Nc = 2100
+        s, z, dim, code = soc_interior(Nc, 257, RNG), soc_interior(Nc, 257, RNG), 257, HC.SOC
+        kind = "soc"
     elif kind == "psd":
         s, z, dim, code = C.svec(spd(Nc, 3, RNG)), C.svec(spd(Nc, 3, RNG)), 3, HC.PSD
     elif kind == "exp":
@@ -205,7 +213,7 @@ def test_step(kind):
 
 
 # ----------------------------------------------------------------- explicit M blocks
-@pytest.mark.parametrize("kind", ["nonneg", "soc", "exp", "pow", "psd3", "psd5"])
+@pytest.mark.parametrize("kind", ["nonneg", "soc", "soc_large", "exp", "pow", "psd3", "psd5"])
 @pytest.mark.parametrize("delta", [1e-8, 1e-3])
 def test_mblock_inverts_the_applied_scaling(kind, delta):
     """The explicit blocks M_c that the Schur complement is assembled from are
@@ -218,6 +226,8 @@ def test_mblock_inverts_the_applied_scaling(kind, delta):
         s, z, dim, code = RNG.uniform(0.1, 2, (Nc, 1)), RNG.uniform(0.1, 2, (Nc, 1)), 1, HC.NONNEG
     elif kind == "soc":
         s, z, dim, code = soc_interior(Nc, 4, RNG), soc_interior(Nc, 4, RNG), 4, HC.SOC
+    elif kind == "soc_large":   # the diagonal plus rank-2 form of M_c
+        s, z, dim, code = soc_interior(12, 90, RNG), soc_interior(12, 90, RNG), 90, HC.SOC
     elif kind == "exp":
         s, z, dim, code = exp_primal(Nc, RNG), exp_dual(Nc, RNG), 3, HC.EXP
     elif kind == "pow":

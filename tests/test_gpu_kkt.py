@@ -38,6 +38,8 @@ CASES = [
     ("mpc_0", lambda: W.mpc_socp(0, 0)),
     ("exp_small", lambda: W.logreg_exp(0, samples=400, features=30)),
     ("psdpow_small", lambda: W.psd_pow(0, n=250, n_pow=120, n_psd=25, k=4)),
+    ("multistage_small", lambda: W.multistage_portfolio(0, n=40, k=4, T=3)),
+    ("multistage_dense_rows", lambda: W.multistage_portfolio(1, n=600, k=6, T=2)),
 ]
 
 

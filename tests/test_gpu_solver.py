@@ -37,7 +37,7 @@ def certify(prob, x, sv, z, eps=1e-8):
 
 
 @pytest.mark.parametrize("make", [PS.box_lp, PS.soc_ball, PS.exp_max, PS.softplus, PS.entropy, PS.pow_max,
-                                  PS.trace_min, PS.lqr])
+                                  PS.trace_min, PS.lqr, PS.soc_balls, PS.soc_ball_budget])
 def test_known_optimum(make):
     prob, fstar = make()
     info, x, sv, z = gpu_solve(prob)
@@ -59,6 +59,15 @@ CASES = [
     ("entropy_dense_rows", lambda: W.entropy_max(0, n=600)),
     ("portfolio_small", lambda: W.portfolio_qp(0, n=300)),
     ("psd_mixed_sides", lambda: W.psd_mixed(0)),
+    # second-order cones above 16 rows (one workgroup per cone, diagonal plus
+    # rank-2 Schur form): several dims, with leaf blocks (the z variables),
+    # and with dense budget rows on the same columns
+    ("multistage_small", lambda: W.multistage_portfolio(0, n=40, k=4, T=3)),
+    ("multistage_dense_rows", lambda: W.multistage_portfolio(1, n=600, k=6, T=2)),
+    # SOC dimension 16, the largest on the lane-per-cone path (a withdrawal
+    # instead of an inflow: with 12 assets capped at 0.1 a budget of 1.1
+    # leaves y_t = F_t x_t >= 0 infeasible)
+    ("multistage_dim16", lambda: W.multistage_portfolio(2, n=12, k=3, T=2, inflow=-0.5)),
 ]
 
 @pytest.mark.parametrize("name,make", CASES)

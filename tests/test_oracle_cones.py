@@ -84,7 +84,7 @@ def _bisect(member, hi=1e6, halvings=200):
 
 
 # ------------------------------------------------------------------ SOC
-@pytest.mark.parametrize("d", [2, 3, 5])
+@pytest.mark.parametrize("d", [2, 3, 5, 64, 400])
 def test_soc_nt_identities(d):
     s, z = soc_interior(100, d), soc_interior(100, d)
     sc = C.soc_scale(s, z)
@@ -99,7 +99,7 @@ def test_soc_nt_identities(d):
     assert np.allclose(C.jdot(wb, wb), 1.0, rtol=1e-12)
 
 
-@pytest.mark.parametrize("d", [2, 3, 5])
+@pytest.mark.parametrize("d", [2, 3, 5, 64, 200])
 def test_soc_spectral_equals_explicit(d):
     s, z = soc_interior(60, d), soc_interior(60, d)
     sc = C.soc_scale(s, z)
@@ -117,9 +117,10 @@ def test_soc_jordan_inverse():
     assert np.abs(C.soc_circ(lam, x) - v).max() < 1e-12
 
 
-def test_soc_step_bisection():
-    x = soc_interior(60, 3)
-    dx = 2 * RNG.standard_normal((60, 3))
+@pytest.mark.parametrize("d", [3, 300])
+def test_soc_step_bisection(d):
+    x = soc_interior(60, d)
+    dx = 2 * RNG.standard_normal((60, d))
     a = C.soc_step(x, dx)
     for i in range(60):
         member = lambda t: (x[i, 0] + t * dx[i, 0]) >= np.linalg.norm(x[i, 1:] + t * dx[i, 1:])

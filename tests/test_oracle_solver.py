@@ -33,7 +33,7 @@ def certify(s, prob, eps=1e-8):
 
 
 @pytest.mark.parametrize("make", [PS.box_lp, PS.soc_ball, PS.exp_max, PS.softplus, PS.entropy,
-                                  PS.pow_max, PS.trace_min, PS.lqr])
+                                  PS.pow_max, PS.trace_min, PS.lqr, PS.soc_balls, PS.soc_ball_budget])
 def test_known_optimum(make):
     prob, fstar = make()
     s = solved(prob)
