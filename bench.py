@@ -99,7 +99,7 @@ def run_gpu(prob, precision, steps, warmup):
     )
 
 
-OTHER_WORKLOADS = ("logreg_exp", "psd_pow", "entropy_max", "portfolio_qp")
+OTHER_WORKLOADS = ("logreg_exp", "psd_pow", "entropy_max", "portfolio_qp", "multistage_portfolio")
 
 
 def run_other_workloads(steps=1, only=None):
@@ -109,7 +109,8 @@ def run_other_workloads(steps=1, only=None):
     from paper_2412_19027_amd import hipcone as HC
     from paper_2412_19027_amd import workloads as W
     makers = {"logreg_exp": lambda: W.logreg_exp(0), "psd_pow": lambda: W.psd_pow(0),
-              "entropy_max": lambda: W.entropy_max(0, n=10000), "portfolio_qp": lambda: W.portfolio_qp(0, n=25000)}
+              "entropy_max": lambda: W.entropy_max(0, n=10000), "portfolio_qp": lambda: W.portfolio_qp(0, n=25000),
+              "multistage_portfolio": lambda: W.multistage_portfolio(0, n=5000, k=50, T=5)}
     out = {}
     for name in OTHER_WORKLOADS:
         if only and name != only:
@@ -128,6 +129,8 @@ def run_other_workloads(steps=1, only=None):
         out[name] = dict(problem=prob.name, n=prob.n, m=prob.m, status=last["status_name"],
                          iterations=last["iterations"], objective=last["obj_primal"],
                          ms_per_iteration=1e3 * wall / max(1, it), ms_per_solve=1e3 * wall / steps,
+                         factor_ms_per_iteration=last["factor_ms"] / max(1, last["iterations"]),
+                         setup_ms=last["setup_ms"],
                          dense_tail=last["n_ordered"], leaf_blocks=last["n_leaves"])
     return out
 

@@ -302,6 +302,14 @@ int32_t hc_test_cone_step(int32_t type, int64_t count, int32_t dim, const double
  * NULL. */
 int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, double* A, int32_t nrhs,
                                  double* B, int64_t* guard_hits, void* stream);
+/* The same with the envelope that the solver derives for its dense tail:
+ * `last` (host, n entries, NULL = dense) with last[j] - 1 the largest row
+ * holding a nonzero of columns 0..j (j < last[j] <= n, non-decreasing; else
+ * HC_ERR_INVALID_ARG).  The factorisation touches only rows inside it, which
+ * is exact when A is zero below it (Cholesky fill stays in the envelope). */
+int32_t hc_test_dense_chol_solve_env(int32_t precision, int64_t n, int64_t ld, double* A,
+                                     const int64_t* last, int32_t nrhs, double* B, int64_t* guard_hits,
+                                     void* stream);
 
 /* ---- served form --------------------------------------------------------
  * Continuous batching of many independent problems on one GPU (the paper's

@@ -30,9 +30,16 @@ struct Aux {
 // (linv_elems(n) entries).  Pivots <= tol are replaced by fix and counted.
 // With `aux` the trailing updates overlap the next panel's factorisation;
 // all work is complete with respect to `st` on return.
+// `last` (host, n entries, or null for a dense matrix) is the envelope of
+// the lower triangle: last[j] - 1 is the largest row i with a nonzero S[i, k]
+// for some k <= j (non-decreasing in j).  Cholesky fill stays inside it, so
+// the TRSM and trailing updates of a panel stop at the rows its columns
+// reach; entries below the envelope are never touched and stay zero.
 template <typename T>
 void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
-                    hipStream_t st, Prof* prof = nullptr, Aux* aux = nullptr);
+                    hipStream_t st, Prof* prof = nullptr, Aux* aux = nullptr, const int64_t* last = nullptr);
+// flops of the envelope-limited factorisation (n^3 / 3 when last is null)
+double envelope_cholesky_flops(int64_t n, const int64_t* last);
 // Inverses X (and X') of the 256 x 256 diagonal blocks of the factor, from
 // the 64 x 64 block inverses; inv256_elems(n) entries each.
 template <typename T>

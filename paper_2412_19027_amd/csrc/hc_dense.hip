@@ -737,43 +737,55 @@ Aux::~Aux() {
   if (side) (void)hipStreamDestroy(side);
 }
 
+// rows [0, rows_below(j)) hold every nonzero of columns <= j: the envelope
+// rounded up to whole 64-blocks (dense without an envelope)
+static int64_t rows_below(const int64_t* last, int64_t n, int64_t j) {
+  if (!last) return n;
+  return std::min<int64_t>(n, ceil_div(std::max<int64_t>(last[j], j + 1), BS) * BS);
+}
+
 // factor the panel [K0, Kend): per 64-block the diagonal factor, the TRSM of
-// the rows below and the eager update of the rest of the panel
+// the rows below (down to the envelope) and the eager update of the rest of
+// the panel
 template <typename T>
 static void factor_panel(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
-                         int64_t K0, int64_t Kend, hipStream_t st, Prof* prof) {
+                         int64_t K0, int64_t Kend, const int64_t* last, hipStream_t st, Prof* prof) {
   for (int64_t c = K0; c < Kend; c += BS) {
     const int64_t cb = std::min<int64_t>(BS, n - c);
     hipLaunchKernelGGL(k_chol_diag<T>, dim3(1), dim3(256), 0, st, S, ld, c, n, Linv + (c / BS) * BS * BS, tol,
                        fix, hits);
     HC_LAUNCH_CHECK();
-    const int64_t r0 = c + cb;
-    if (r0 < n) {
-      hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)ceil_div(n - r0, BS)), dim3(256), 0, st, S, ld, c, r0, n,
+    const int64_t r0 = c + cb, R = rows_below(last, n, c + cb - 1);
+    if (r0 < R) {
+      hipLaunchKernelGGL(k_trsm<T>, dim3((unsigned)ceil_div(R - r0, BS)), dim3(256), 0, st, S, ld, c, r0, R,
                          (const T*)(Linv + (c / BS) * BS * BS));
       HC_LAUNCH_CHECK();
     }
-    if (r0 < Kend) gemm_nt_sub<T>(S, ld, r0, r0, r0, r0, c, n - r0, Kend - r0, cb, true, st, prof);
+    if (r0 < Kend && r0 < R)
+      gemm_nt_sub<T>(S, ld, r0, r0, r0, r0, c, R - r0, std::min(Kend, R) - r0, cb, true, st, prof);
   }
 }
 
 template <typename T>
 void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
-                    hipStream_t st, Prof* prof, Aux* aux) {
+                    hipStream_t st, Prof* prof, Aux* aux, const int64_t* last) {
   if (n <= 0) return;
   if (!aux) {
     for (int64_t K0 = 0; K0 < n; K0 += NB) {
       const int64_t Kend = std::min<int64_t>(n, K0 + NB);
-      factor_panel<T>(S, n, ld, Linv, tol, fix, hits, K0, Kend, st, prof);
+      factor_panel<T>(S, n, ld, Linv, tol, fix, hits, K0, Kend, last, st, prof);
       // delayed update of the trailing matrix with the whole panel
-      if (Kend < n) gemm_nt_sub<T>(S, ld, Kend, Kend, Kend, Kend, K0, n - Kend, n - Kend, Kend - K0, true, st, prof);
+      const int64_t R = rows_below(last, n, Kend - 1);
+      if (Kend < R) gemm_nt_sub<T>(S, ld, Kend, Kend, Kend, Kend, K0, R - Kend, R - Kend, Kend - K0, true, st, prof);
     }
     return;
   }
   // Look-ahead.  After panel k is factored: U1 updates panel k+1 on `st`, U2
   // updates every later column on `side`.  Panel k+1 is then factored on `st`
   // while U2 runs.  U1 writes the columns that the previous U2 wrote, so it
-  // waits for that U2; U2 waits for panel k to be factored.
+  // waits for that U2; U2 waits for panel k to be factored.  Both stop at the
+  // rows the panel's columns reach (the envelope); a panel whose columns reach
+  // no row past the next panel launches no U2.
   aux->init();
   aux->used = 0;
   const int64_t W = std::max<int64_t>(BS, aux->nb / BS * BS);   // panel width
@@ -783,20 +795,24 @@ void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix
   hipEvent_t u2_done = nullptr;
   for (int64_t K0 = 0; K0 < n; K0 += W) {
     const int64_t Kend = std::min<int64_t>(n, K0 + W);
-    factor_panel<T>(S, n, ld, Linv, tol, fix, hits, K0, Kend, st, prof);
+    factor_panel<T>(S, n, ld, Linv, tol, fix, hits, K0, Kend, last, st, prof);
     if (Kend >= n) break;
     const int64_t K1 = std::min<int64_t>(n, Kend + W);
-    if (K1 < n) {
+    const int64_t R = rows_below(last, n, Kend - 1);
+    const bool u2 = K1 < R;
+    if (u2) {
       hipEvent_t factored = aux->next();
       HC_HIP(hipEventRecord(factored, st));
       HC_HIP(hipStreamWaitEvent(aux->side, factored, 0));
-      // U2 on the side stream: rows and columns [K1, n)
-      gemm_nt_sub<T>(S, ld, K1, K1, K1, K1, K0, n - K1, n - K1, Kend - K0, true, aux->side, prof);
+      // U2 on the side stream: rows and columns [K1, R)
+      gemm_nt_sub<T>(S, ld, K1, K1, K1, K1, K0, R - K1, R - K1, Kend - K0, true, aux->side, prof);
     }
     if (u2_done) HC_HIP(hipStreamWaitEvent(st, u2_done, 0));
-    // U1 on the caller's stream: rows [Kend, n), columns [Kend, K1)
-    gemm_nt_sub<T>(S, ld, Kend, Kend, Kend, Kend, K0, n - Kend, K1 - Kend, Kend - K0, true, st, prof);
-    if (K1 < n) {
+    // U1 on the caller's stream: rows [Kend, R), columns [Kend, min(K1, R))
+    if (Kend < R)
+      gemm_nt_sub<T>(S, ld, Kend, Kend, Kend, Kend, K0, R - Kend, std::min(K1, R) - Kend, Kend - K0, true, st, prof);
+    u2_done = nullptr;
+    if (u2) {
       u2_done = aux->next();
       HC_HIP(hipEventRecord(u2_done, aux->side));
     }
@@ -1062,9 +1078,9 @@ void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT25
 }
 
 template void dense_cholesky<double>(double*, int64_t, int64_t, double*, double, double, unsigned long long*,
-                                     hipStream_t, Prof*, Aux*);
+                                     hipStream_t, Prof*, Aux*, const int64_t*);
 template void dense_cholesky<float>(float*, int64_t, int64_t, float*, double, double, unsigned long long*,
-                                    hipStream_t, Prof*, Aux*);
+                                    hipStream_t, Prof*, Aux*, const int64_t*);
 template void gemm_nt<double>(double*, int64_t, const double*, int64_t, const double*, int64_t, int64_t, int64_t,
                               int64_t, double, bool, int64_t, int64_t, hipStream_t);
 template void gemm_nt<float>(float*, int64_t, const float*, int64_t, const float*, int64_t, int64_t, int64_t,
@@ -1081,5 +1097,15 @@ int64_t linv_elems(int64_t n) { return ceil_div(n, BS) * BS * BS; }
 
 // factor flops of a dense n x n Cholesky
 double cholesky_flops(int64_t n) { return (double)n * n * n / 3.0; }
+
+double envelope_cholesky_flops(int64_t n, const int64_t* last) {
+  if (!last) return cholesky_flops(n);
+  double f = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    const double h = (double)(std::max<int64_t>(last[j], j + 1) - j - 1);   // rows below the pivot
+    f += h * h + h;
+  }
+  return f;
+}
 
 }  // namespace hc

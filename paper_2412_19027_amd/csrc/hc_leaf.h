@@ -42,9 +42,9 @@ struct ColMap {
 };
 
 // Schur assembly over row pairs of one cone (as assemble_pairs), routed
-// through the column map.
+// through the column map; wide: one wave per task.
 void assemble_pairs_map(int64_t ntask, const int32_t* tra, const int32_t* trb, const int64_t* tm, const double* mval,
-                        const Csr& A, const ColMap& cm, hipStream_t st);
+                        const Csr& A, const ColMap& cm, bool wide, hipStream_t st);
 // P (full CSR, lower part used) and delta on the diagonal, through the map.
 void add_P_delta_map(const Csr& P, int64_t n, double delta, const ColMap& cm, hipStream_t st);
 // Per leaf: Cholesky of S_bb (pivots <= tol replaced by fix and counted),

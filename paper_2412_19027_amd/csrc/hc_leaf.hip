@@ -36,6 +36,9 @@ __device__ inline double* dest(const ColMap& cm, int32_t j, int32_t k) {
   return cm.sink;   // cannot happen: the coupling list holds every neighbour
 }
 
+// pair tasks through the column map (lane per task, or wave per long task:
+// see k_assemble_pairs)
+template <bool WIDE>
 __global__ __launch_bounds__(256) void k_assemble_pairs_map(int64_t ntask, const int32_t* __restrict__ tra,
                                                             const int32_t* __restrict__ trb,
                                                             const int64_t* __restrict__ tm,
@@ -43,19 +46,21 @@ __global__ __launch_bounds__(256) void k_assemble_pairs_map(int64_t ntask, const
                                                             const int32_t* __restrict__ rp,
                                                             const int32_t* __restrict__ ci,
                                                             const double* __restrict__ av, ColMap cm) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = WIDE ? gid / 64 : gid;
+  const int lane = WIDE ? (int)(threadIdx.x & 63) : 0, nl = WIDE ? 64 : 1;
   if (t >= ntask) return;
   const int32_t ra = tra[t], rb = trb[t];
   const double m = mval[tm[t]];
   if (m == 0.0) return;
   const int32_t ba = rp[ra], ea = rp[ra + 1], bb = rp[rb], eb = rp[rb + 1];
   if (ra == rb) {
-    for (int32_t p = ba; p < ea; ++p) {
+    for (int32_t p = ba + lane; p < ea; p += nl) {
       const double mj = m * av[p];
       for (int32_t q = ba; q <= p; ++q) atomicAdd(dest(cm, ci[p], ci[q]), mj * av[q]);
     }
   } else {
-    for (int32_t p = ba; p < ea; ++p) {
+    for (int32_t p = ba + lane; p < ea; p += nl) {
       const int32_t j = ci[p];
       const double mj = m * av[p];
       for (int32_t q = bb; q < eb; ++q) {
@@ -69,10 +74,14 @@ __global__ __launch_bounds__(256) void k_assemble_pairs_map(int64_t ntask, const
 }
 
 void assemble_pairs_map(int64_t ntask, const int32_t* tra, const int32_t* trb, const int64_t* tm, const double* mval,
-                        const Csr& A, const ColMap& cm, hipStream_t st) {
+                        const Csr& A, const ColMap& cm, bool wide, hipStream_t st) {
   if (ntask == 0) return;
-  hipLaunchKernelGGL(k_assemble_pairs_map, dim3((unsigned)ceil_div(ntask, 256)), dim3(256), 0, st, ntask, tra, trb,
-                     tm, mval, A.rowptr, A.col, A.val, cm);
+  if (wide)
+    hipLaunchKernelGGL(k_assemble_pairs_map<true>, dim3((unsigned)ceil_div(ntask * 64, 256)), dim3(256), 0, st,
+                       ntask, tra, trb, tm, mval, A.rowptr, A.col, A.val, cm);
+  else
+    hipLaunchKernelGGL(k_assemble_pairs_map<false>, dim3((unsigned)ceil_div(ntask, 256)), dim3(256), 0, st, ntask,
+                       tra, trb, tm, mval, A.rowptr, A.col, A.val, cm);
   HC_LAUNCH_CHECK();
 }
 

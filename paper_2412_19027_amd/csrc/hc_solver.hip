@@ -91,10 +91,12 @@ struct hc_solver {
   double bnorm_user = 0, qnorm_user = 0, maxPdiag = 0;
   int64_t nu = 0;                  // cone degree
   bool has_nonsym = false;
-  std::vector<int32_t> tra, trb;   // Schur assembly tasks
-  std::vector<int64_t> tm;
+  std::vector<int32_t> tra, trb;   // Schur assembly tasks: short ones first, then
+  std::vector<int64_t> tm;         // those of more than PAIR_WIDE products (one wave each)
+  int64_t ntask_short = 0;
   // two-level split of the Schur complement (leaf blocks + dense tail)
   int64_t nt = 0;                  // tail columns
+  std::vector<int64_t> tail_last;  // envelope of the tail (see dense_cholesky), padded to ld
   bool leaves = false;             // any leaf block
   std::vector<int32_t> col_leaf, col_loc, tail_cols, leaf_size, leaf_cols, leaf_ccnt, leaf_clist;
   std::vector<int64_t> leaf_lval_off, leaf_lcol_off, leaf_clist_off, leaf_cval_off;
@@ -410,6 +412,7 @@ void equilibrate(hc_solver* S, const HostCsr& A, const HostCsr& Pf, const std::v
 // changes another leaf's coupling (distinct components are not adjacent).
 // ---------------------------------------------------------------------------
 constexpr int LEAF_DEGREE = 64;
+constexpr int64_t PAIR_WIDE = 1024;   // products per pair task above which one wave takes the task
 
 void build_lowrank(hc_solver* S, int nd);
 
@@ -577,6 +580,44 @@ void build_leaves(hc_solver* S) {
     S->leaf_flops += (double)l * l * l / 3.0 + (double)cnt * l * l + (double)cnt * cnt * l;
   }
   S->leaves = !S->leaf_size.empty();
+  // Envelope of the tail in its order: the first tail column each tail row is
+  // coupled to, through a cone's clique (dense rows and large SOC rank-2 rows
+  // included), an entry of P, or a leaf block's update W_b W_b' (a clique on
+  // the leaf's coupled columns).  Then tail_last[j] = 1 + the last row whose
+  // first coupled column is <= j.
+  const int64_t nt = S->nt;
+  std::vector<int64_t> first(nt);
+  for (int64_t t = 0; t < nt; ++t) first[t] = t;
+  std::vector<int64_t> mem;
+  auto clique = [&](const std::vector<int64_t>& ts) {
+    if (ts.empty()) return;
+    const int64_t mn = *std::min_element(ts.begin(), ts.end());
+    for (int64_t t : ts) first[t] = std::min(first[t], mn);
+  };
+  for (int64_t c = 0; c < ncl; ++c) {
+    mem.clear();
+    for (int64_t e = cp[c]; e < cp[c + 1]; ++e)
+      if (tail[cc[e]]) mem.push_back(S->col_loc[cc[e]]);
+    clique(mem);
+  }
+  for (int d = 0; d < nd; ++d) {
+    mem.clear();
+    for (int64_t j = 0; j < n; ++j)
+      if (S->Ad[(size_t)d * n + j] != 0.0) mem.push_back(S->col_loc[j]);
+    clique(mem);
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t k = P.rp[i]; k < P.rp[i + 1]; ++k)
+      if (tail[i] && tail[P.ci[k]]) clique({(int64_t)S->col_loc[i], (int64_t)S->col_loc[P.ci[k]]});
+  for (size_t b = 0; b < S->leaf_size.size(); ++b) {
+    mem.assign(S->leaf_clist.begin() + S->leaf_clist_off[b],
+               S->leaf_clist.begin() + S->leaf_clist_off[b] + S->leaf_ccnt[b]);
+    clique(mem);
+  }
+  S->tail_last.assign(nt, 0);
+  for (int64_t t = 0; t < nt; ++t) S->tail_last[first[t]] = std::max(S->tail_last[first[t]], t + 1);
+  for (int64_t t = 0; t < nt; ++t)
+    S->tail_last[t] = std::max({S->tail_last[t], t + 1, t > 0 ? S->tail_last[t - 1] : 0});
 }
 
 void setup_host(hc_solver* S, const hc_problem* p) {
@@ -734,6 +775,27 @@ void setup_host(hc_solver* S, const hc_problem* p) {
           S->tm.push_back(g.moff + ((int64_t)a * (a + 1) / 2 + bb) * g.count + c2);
         }
   }
+  {   // long tasks last, for the one-wave-per-task kernel
+    const int64_t nt = (int64_t)S->tra.size();
+    std::vector<int64_t> ord(nt);
+    for (int64_t t = 0; t < nt; ++t) ord[t] = t;
+    auto cost = [&](int64_t t) {
+      const int64_t a = As.rp[S->tra[t] + 1] - As.rp[S->tra[t]], b = As.rp[S->trb[t] + 1] - As.rp[S->trb[t]];
+      return a * b;
+    };
+    auto mid = std::stable_partition(ord.begin(), ord.end(), [&](int64_t t) { return cost(t) <= PAIR_WIDE; });
+    S->ntask_short = mid - ord.begin();
+    std::vector<int32_t> a2(nt), b2(nt);
+    std::vector<int64_t> m2(nt);
+    for (int64_t t = 0; t < nt; ++t) {
+      a2[t] = S->tra[ord[t]];
+      b2[t] = S->trb[ord[t]];
+      m2[t] = S->tm[ord[t]];
+    }
+    S->tra.swap(a2);
+    S->trb.swap(b2);
+    S->tm.swap(m2);
+  }
   S->A = std::move(As);
   S->At = std::move(At);
   build_leaves(S);
@@ -745,6 +807,7 @@ void setup_host(hc_solver* S, const hc_problem* p) {
   }
   build_lowrank(S, nd);
   S->ld = ((S->nt + 63) / 64) * 64;
+  for (int64_t t = S->nt; t < S->ld; ++t) S->tail_last.push_back(t + 1);   // identity padding
   if (S->st.static_reg <= 0) S->st.static_reg = S->mixed ? 3.4526698300124393e-04 : 1e-8;
   if (S->st.dyn_reg < 0) S->st.dyn_reg = S->mixed ? std::ldexp(1.0, -46) : std::ldexp(1.0, -104);
 }
@@ -1004,6 +1067,11 @@ void H_apply(hc_solver* S, int mode, const double* x, double* y) {
   for (auto& g : S->sdev) cone_apply(g, mode, S->delta, x, y, S->stream);
 }
 
+// unit diagonal on the padding rows [nt, ntp) of the dense tail
+__global__ void k_pad_identity(int64_t nt, int64_t ntp, int64_t ld, double* __restrict__ S) {
+  for (int64_t i = nt + threadIdx.x; i < ntp; i += blockDim.x) S[i + i * ld] = 1.0;
+}
+
 __global__ void k_get_diag(int64_t n, int64_t ld, const double* __restrict__ A, double* __restrict__ d) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = A[i + i * ld];
@@ -1029,16 +1097,28 @@ void factor(hc_solver* S, bool fp64 = false) {
     S->delta = ds + dd * std::max(S->maxPdiag, hmax);
   }
   for (auto& g : S->sdev) cone_mblock(g, S->delta, st);
-  const int64_t nt = S->nt;
-  fill_lower_zero(nt, S->ld, S->dS, st);
+  // The tail is factored padded to ld (a multiple of 64) with an identity
+  // block on the padding: [[S, 0], [0, I]] = [[L, 0], [0, I]] [[L, 0], [0, I]]',
+  // so every panel, TRSM and trailing update is a whole number of 64-blocks
+  // (no edge tiles), and the solves use the leading nt x nt part.
+  const int64_t nt = S->nt, ntp = S->ld;
+  fill_lower_zero(ntp, S->ld, S->dS, st);
+  if (ntp > nt) {
+    hipLaunchKernelGGL(k_pad_identity, dim3(1), dim3(64), 0, st, nt, ntp, S->ld, S->dS);
+    HC_LAUNCH_CHECK();
+  }
   if (S->leaves) {
     vfill(S->lval_total, 0.0, S->cm.lval, st);
     vfill(S->cval_total, 0.0, S->cm.cval, st);
     add_P_delta_map(S->dP, S->n, S->delta, S->cm, st);
-    assemble_pairs_map((int64_t)S->tra.size(), S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->cm, st);
+    const int64_t ns = S->ntask_short, nl = (int64_t)S->tra.size() - ns;
+    assemble_pairs_map(ns, S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->cm, false, st);
+    assemble_pairs_map(nl, S->dtra + ns, S->dtrb + ns, S->dtm + ns, S->dmval, S->dA, S->cm, true, st);
   } else {
     add_P_delta(S->dP, S->n, S->delta, S->ld, S->dS, st);
-    assemble_pairs((int64_t)S->tra.size(), S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->ld, S->dS, st);
+    const int64_t ns = S->ntask_short, nl = (int64_t)S->tra.size() - ns;
+    assemble_pairs(ns, S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->ld, S->dS, false, st);
+    assemble_pairs(nl, S->dtra + ns, S->dtrb + ns, S->dtm + ns, S->dmval, S->dA, S->ld, S->dS, true, st);
   }
   const int nd = (int)S->drows.size();
   if (S->K1 > 0) {
@@ -1073,12 +1153,14 @@ void factor(hc_solver* S, bool fp64 = false) {
   if (nt == 0) {
     // every column sits in a leaf block: nothing dense to factor
   } else if (low) {
-    lower_to_f32(nt, S->ld, S->dS, S->dS32, st);
-    dense_cholesky<float>(S->dS32, nt, S->ld, S->dLinv32, tol, S->delta, S->dhits, st, pf, &S->aux);
-    dense_block_inverses<float>(S->dS32, nt, S->ld, S->dLinv32, S->dX256f, S->dXT256f, st);
+    lower_to_f32(ntp, S->ld, S->dS, S->dS32, st);
+    dense_cholesky<float>(S->dS32, ntp, S->ld, S->dLinv32, tol, S->delta, S->dhits, st, pf, &S->aux,
+                          S->tail_last.data());
+    dense_block_inverses<float>(S->dS32, ntp, S->ld, S->dLinv32, S->dX256f, S->dXT256f, st);
   } else {
-    dense_cholesky<double>(S->dS, nt, S->ld, S->dLinv, tol, S->delta, S->dhits, st, pf, &S->aux);
-    dense_block_inverses<double>(S->dS, nt, S->ld, S->dLinv, S->dX256, S->dXT256, st);
+    dense_cholesky<double>(S->dS, ntp, S->ld, S->dLinv, tol, S->delta, S->dhits, st, pf, &S->aux,
+                           S->tail_last.data());
+    dense_block_inverses<double>(S->dS, ntp, S->ld, S->dLinv, S->dX256, S->dXT256, st);
   }
   S->info.factorizations++;
   if (pf) {
@@ -1613,16 +1695,16 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->dstate = buf.take<double>(S->stotal + 1);
   S->dmval = buf.take<double>(S->mtotal + 1);
   S->dhdiag = buf.take<double>(m);
-  const int64_t nt = S->nt;
-  S->dS = buf.take<double>((size_t)S->ld * nt);
-  S->dLinv = buf.take<double>(linv_elems(nt));
-  S->dX256 = buf.take<double>(inv256_elems(nt));
-  S->dXT256 = buf.take<double>(inv256_elems(nt));
+  const int64_t nt = S->nt, ntp = S->ld;   // the tail is factored padded to ld
+  S->dS = buf.take<double>((size_t)S->ld * ntp);
+  S->dLinv = buf.take<double>(linv_elems(ntp));
+  S->dX256 = buf.take<double>(inv256_elems(ntp));
+  S->dXT256 = buf.take<double>(inv256_elems(ntp));
   if (S->mixed) {
-    S->dS32 = buf.take<float>((size_t)S->ld * nt);
-    S->dLinv32 = buf.take<float>(linv_elems(nt));
-    S->dX256f = buf.take<float>(inv256_elems(nt));
-    S->dXT256f = buf.take<float>(inv256_elems(nt));
+    S->dS32 = buf.take<float>((size_t)S->ld * ntp);
+    S->dLinv32 = buf.take<float>(linv_elems(ntp));
+    S->dX256f = buf.take<float>(inv256_elems(ntp));
+    S->dXT256f = buf.take<float>(inv256_elems(ntp));
     S->sb32 = buf.take<float>(nt);
     S->sy32 = buf.take<float>(nt);
     S->sx32 = buf.take<float>(nt);
@@ -1827,7 +1909,7 @@ int32_t hc_setup(hc_solver** out, const hc_problem* prob, const hc_settings* set
     S->info.n_ordered = S->nt;
     S->info.n_leaves = (int64_t)S->leaf_size.size();
     S->info.leaf_columns = S->n - S->nt;
-    S->info.factor_flops = cholesky_flops(S->nt) + S->leaf_flops;
+    S->info.factor_flops = envelope_cholesky_flops(S->nt, S->tail_last.data()) + S->leaf_flops;
   } catch (const Error& e) {
     g_last_error = e.msg;
     delete S;

@@ -270,8 +270,17 @@ int32_t hc_test_cone_step(int32_t type, int64_t count, int32_t dim, const double
 
 int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, double* A, int32_t nrhs, double* B,
                                  int64_t* guard_hits, void* stream) {
+  return hc_test_dense_chol_solve_env(precision, n, ld, A, nullptr, nrhs, B, guard_hits, stream);
+}
+
+int32_t hc_test_dense_chol_solve_env(int32_t precision, int64_t n, int64_t ld, double* A, const int64_t* last,
+                                     int32_t nrhs, double* B, int64_t* guard_hits, void* stream) {
   return guard([&] {
     if (n <= 0 || ld < n || nrhs < 1 || nrhs > 4 || !A || !B) throw Error{HC_ERR_INVALID_ARG, "bad dense test args"};
+    if (last)
+      for (int64_t j = 0; j < n; ++j)
+        if (last[j] <= j || last[j] > n || (j > 0 && last[j] < last[j - 1]))
+          throw Error{HC_ERR_INVALID_ARG, "envelope must satisfy j < last[j] <= n and be non-decreasing"};
     hipStream_t st = (hipStream_t)stream;
     std::vector<void*> owned;
     Aux aux;
@@ -291,7 +300,7 @@ int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, doubl
         float* y32 = (float*)al((size_t)n * nrhs * 4);
         float* x32 = (float*)al((size_t)n * nrhs * 4);
         lower_to_f32(n, ld, A, A32, st);
-        dense_cholesky<float>(A32, n, ld, L32, 0.0, 1e-8, hits, st, nullptr, &aux);
+        dense_cholesky<float>(A32, n, ld, L32, 0.0, 1e-8, hits, st, nullptr, &aux, last);
         float* X32 = (float*)al(inv256_elems(n) * 4);
         float* XT32 = (float*)al(inv256_elems(n) * 4);
         dense_block_inverses<float>(A32, n, ld, L32, X32, XT32, st);
@@ -305,7 +314,7 @@ int32_t hc_test_dense_chol_solve(int32_t precision, int64_t n, int64_t ld, doubl
         double* Li = (double*)al(linv_elems(n) * 8);
         double* y = (double*)al((size_t)n * nrhs * 8);
         double* x = (double*)al((size_t)n * nrhs * 8);
-        dense_cholesky<double>(A, n, ld, Li, 0.0, 1e-8, hits, st, nullptr, &aux);
+        dense_cholesky<double>(A, n, ld, Li, 0.0, 1e-8, hits, st, nullptr, &aux, last);
         double* X64 = (double*)al(inv256_elems(n) * 8);
         double* XT64 = (double*)al(inv256_elems(n) * 8);
         dense_block_inverses<double>(A, n, ld, Li, X64, XT64, st);

@@ -31,8 +31,9 @@ void from_f32(int64_t n, const float* x, const double* scale, double* y, hipStre
 void lower_to_f32(int64_t n, int64_t ld, const double* S, float* S32, hipStream_t st);
 void fill_lower_zero(int64_t n, int64_t ld, double* S, hipStream_t st);
 void add_P_delta(const Csr& P, int64_t n, double delta, int64_t ld, double* S, hipStream_t st);
+// wide: one wave per task (long rows) instead of one lane
 void assemble_pairs(int64_t ntask, const int32_t* tra, const int32_t* trb, const int64_t* tm, const double* mval,
-                    const Csr& A, int64_t ld, double* S, hipStream_t st);
+                    const Csr& A, int64_t ld, double* S, bool wide, hipStream_t st);
 void scale_dense_rows(int nd, int64_t n, const double* Ad, const int64_t* midx, const double* mval, double* B,
                       hipStream_t st);
 void aos_to_cm(int64_t count, int dim, const double* a, double* c, bool inverse, hipStream_t st);

@@ -275,26 +275,33 @@ void add_P_delta(const Csr& P, int64_t n, double delta, int64_t ld, double* S, h
 // one task = an unordered pair of rows (ra >= rb, same cone) with the index of
 // M_c[ra, rb]; adds M * (a_ra a_rb' + a_rb a_ra') (or M a a' when ra == rb)
 // into the lower triangle with hardware FP64 atomics.
+// One task adds m (a_ra a_rb' + a_rb a_ra') (m a_ra a_ra' when ra = rb) to the
+// lower triangle of S.  Short tasks run one lane each; long ones (rows with
+// hundreds of entries) one wave each, the lanes striding over the entries of
+// row ra, so no single lane issues the whole row's quadratic update.
+template <bool WIDE>
 __global__ __launch_bounds__(256) void k_assemble_pairs(int64_t ntask, const int32_t* __restrict__ tra,
                                                         const int32_t* __restrict__ trb,
                                                         const int64_t* __restrict__ tm,
                                                         const double* __restrict__ mval, const int32_t* __restrict__ rp,
                                                         const int32_t* __restrict__ ci, const double* __restrict__ av,
                                                         int64_t ld, double* __restrict__ S) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = WIDE ? gid / 64 : gid;
+  const int lane = WIDE ? (int)(threadIdx.x & 63) : 0, nl = WIDE ? 64 : 1;
   if (t >= ntask) return;
   const int32_t ra = tra[t], rb = trb[t];
   const double m = mval[tm[t]];
   if (m == 0.0) return;
   const int32_t ba = rp[ra], ea = rp[ra + 1], bb = rp[rb], eb = rp[rb + 1];
   if (ra == rb) {
-    for (int32_t p = ba; p < ea; ++p) {
+    for (int32_t p = ba + lane; p < ea; p += nl) {
       const int32_t j = ci[p];
       const double mj = m * av[p];
       for (int32_t q = ba; q <= p; ++q) atomicAdd(&S[j + (int64_t)ci[q] * ld], mj * av[q]);
     }
   } else {
-    for (int32_t p = ba; p < ea; ++p) {
+    for (int32_t p = ba + lane; p < ea; p += nl) {
       const int32_t j = ci[p];
       const double mj = m * av[p];
       for (int32_t q = bb; q < eb; ++q) {
@@ -308,10 +315,14 @@ __global__ __launch_bounds__(256) void k_assemble_pairs(int64_t ntask, const int
   }
 }
 void assemble_pairs(int64_t ntask, const int32_t* tra, const int32_t* trb, const int64_t* tm, const double* mval,
-                    const Csr& A, int64_t ld, double* S, hipStream_t st) {
+                    const Csr& A, int64_t ld, double* S, bool wide, hipStream_t st) {
   if (ntask == 0) return;
-  hipLaunchKernelGGL(k_assemble_pairs, dim3((unsigned)ceil_div(ntask, 256)), dim3(256), 0, st, ntask, tra, trb, tm,
-                     mval, A.rowptr, A.col, A.val, ld, S);
+  if (wide)
+    hipLaunchKernelGGL(k_assemble_pairs<true>, dim3((unsigned)ceil_div(ntask * 64, 256)), dim3(256), 0, st, ntask,
+                       tra, trb, tm, mval, A.rowptr, A.col, A.val, ld, S);
+  else
+    hipLaunchKernelGGL(k_assemble_pairs<false>, dim3((unsigned)ceil_div(ntask, 256)), dim3(256), 0, st, ntask, tra,
+                       trb, tm, mval, A.rowptr, A.col, A.val, ld, S);
   HC_LAUNCH_CHECK();
 }
 

@@ -24,6 +24,7 @@ EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "
            "hc_get_solution", "hc_get_iterate", "hc_set_iterate", "hc_update_data", "hc_test_kkt_solve", "hc_test_kkt_ops",
            "hc_test_schur", "hc_destroy", "hc_last_error", "hc_status_str",
            "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_dense_chol_solve",
+           "hc_test_dense_chol_solve_env",
            "hc_test_copy", "hc_test_cone_mblock", "hc_server_config_default", "hc_server_create", "hc_server_submit", "hc_server_poll",
            "hc_server_wait", "hc_server_stats", "hc_server_destroy"]
 
@@ -124,6 +125,7 @@ def lib():
         L.hc_test_cone_ds.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, dbl, dbl, vp, vp]
         L.hc_test_cone_step.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, dbl, vp, vp]
         L.hc_test_dense_chol_solve.argtypes = [i32, i64, i64, vp, i32, vp, C.POINTER(i64), vp]
+        L.hc_test_dense_chol_solve_env.argtypes = [i32, i64, i64, vp, vp, i32, vp, C.POINTER(i64), vp]
         L.hc_test_copy.argtypes = [vp, vp, i64, vp]
         L.hc_test_cone_mblock.argtypes = [i32, i64, i32, vp, vp, vp, C.c_double, C.c_double, vp, vp]
         L.hc_server_config_default.argtypes = [C.POINTER(hc_server_config)]
@@ -384,10 +386,12 @@ def test_cone_step(kind, dim, s, z, ds, dz, amax, alpha=None):
     return out
 
 
-def test_dense_chol_solve(A, B, precision=PRECISION_FP64, ld=None):
+def test_dense_chol_solve(A, B, precision=PRECISION_FP64, ld=None, last=None):
     """A: (n, n) SPD (torch cuda float64); B: (n, nrhs).  A is stored
     column-major with leading dimension ld (default n) as the library keeps
-    its Schur complement.  Returns (X, L, pivot-guard hits)."""
+    its Schur complement.  `last` (int sequence, optional): the envelope of A
+    (hc_test_dense_chol_solve_env).  Returns (X, L, pivot-guard hits)."""
+    import numpy as np
     import torch
     n = A.shape[0]
     ld = n if ld is None else int(ld)
@@ -395,8 +399,13 @@ def test_dense_chol_solve(A, B, precision=PRECISION_FP64, ld=None):
     At[:, :n] = A.t()
     Bt = B.t().contiguous()          # column-major (n x nrhs)
     hits = C.c_int64()
-    _check(lib().hc_test_dense_chol_solve(precision, n, ld, _dptr(At), Bt.shape[0], _dptr(Bt), C.byref(hits),
-                                          _stream()))
+    if last is None:
+        _check(lib().hc_test_dense_chol_solve(precision, n, ld, _dptr(At), Bt.shape[0], _dptr(Bt), C.byref(hits),
+                                              _stream()))
+    else:
+        env = np.ascontiguousarray(last, dtype=np.int64)
+        _check(lib().hc_test_dense_chol_solve_env(precision, n, ld, _dptr(At), env.ctypes.data, Bt.shape[0],
+                                                  _dptr(Bt), C.byref(hits), _stream()))
     torch.cuda.synchronize()
     return Bt.t().contiguous(), At[:, :n].t().contiguous(), hits.value
 

@@ -62,6 +62,53 @@ def test_dense_cholesky_odd_sizes_padded_ld(n, precision):
         assert relerr(Lh @ Lh.T, A) < 1e-13
 
 
+def _envelope_spd(first, rng):
+    """SPD matrix whose row i has its first nonzero at column first[i]
+    (non-decreasing): L0 L0' with L0 lower triangular of that profile."""
+    n = len(first)
+    L0 = np.tril(rng.standard_normal((n, n)))
+    cols = np.arange(n)[None, :]
+    L0[cols < np.asarray(first)[:, None]] = 0.0
+    L0[np.arange(n), np.arange(n)] = np.sqrt(n) + np.abs(L0[np.arange(n), np.arange(n)])
+    return L0 @ L0.T
+
+
+def _envelope_last(first):
+    n = len(first)
+    last = np.arange(1, n + 1)
+    for i, f in enumerate(first):
+        last[f] = max(last[f], i + 1)
+    return np.maximum.accumulate(last)
+
+
+@pytest.mark.parametrize("shape", ["stages", "random"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dense_cholesky_envelope(shape, precision):
+    """Envelope-limited factorisation (the solver's dense tail): rows of a
+    stage couple back to the start of the previous stage (stages wider than a
+    768-column panel, so some panels update later columns and some do not),
+    or a random non-decreasing profile; n not a multiple of 64."""
+    n = 3300
+    if shape == "stages":
+        w = 900
+        first = np.array([max(0, w * (i // w - 1)) for i in range(n)])
+    else:
+        first = np.maximum.accumulate(np.maximum(0, np.arange(n) - RNG.integers(1, 700, n)))
+    A = _envelope_spd(first, RNG)
+    last = _envelope_last(first)
+    B = RNG.standard_normal((n, 2))
+    ld = (n + 63) // 64 * 64
+    code = HC.PRECISION_FP64 if precision == "fp64" else HC.PRECISION_MIXED
+    X, L, hits = HC.test_dense_chol_solve(T(A), T(B), code, ld=ld, last=last)
+    assert hits == 0
+    assert relerr(N(X), np.linalg.solve(A, B)) < (1e-11 if precision == "fp64" else 1e-4)
+    if precision == "fp64":
+        Lh = np.tril(N(L))
+        assert relerr(Lh @ Lh.T, A) < 1e-13
+        outside = np.arange(n)[None, :] < first[:, None]
+        assert np.all(Lh[outside] == 0.0)
+
+
 @pytest.mark.parametrize("n", [64, 300, 513, 1600])
 def test_dense_cholesky_fp32(n):
     G = RNG.standard_normal((n, n))

@@ -68,6 +68,9 @@ CASES = [
     # instead of an inflow: with 12 assets capped at 0.1 a budget of 1.1
     # leaves y_t = F_t x_t >= 0 infeasible)
     ("multistage_dim16", lambda: W.multistage_portfolio(2, n=12, k=3, T=2, inflow=-0.5)),
+    # a tail of 2,040 columns in ten stages (three panels) whose envelope ends
+    # one stage below each column: envelope-limited TRSM and updates
+    ("multistage_panels", lambda: W.multistage_portfolio(3, n=200, k=3, T=10)),
 ]
 
 @pytest.mark.parametrize("name,make", CASES)

@@ -57,12 +57,14 @@ def test_leaf_blocks_match_one_dense_block():
         assert close(gp, GOLD[key]["objective"]), (gp, GOLD[key]["objective"])
 
 
-@pytest.mark.parametrize("make", [lambda: W.entropy_max(0, n=10000), lambda: W.portfolio_qp(0, n=25000)],
-                         ids=["entropy_max_10000", "portfolio_qp_25000"])
+@pytest.mark.parametrize("make", [lambda: W.entropy_max(0, n=10000), lambda: W.portfolio_qp(0, n=25000),
+                                  lambda: W.multistage_portfolio(0, n=5000, k=50, T=5)],
+                         ids=["entropy_max_10000", "portfolio_qp_25000", "multistage_portfolio_T5"])
 def test_paper_workloads_full_size_certified(make):
-    """The paper's largest entropy-maximisation and portfolio instances (no
-    oracle value at these sizes): solved, and the termination inequalities
-    hold on the user's data."""
+    """The paper's largest entropy-maximisation and portfolio instances and
+    the multistage portfolio at 5,000 assets, 50 factors and horizon 5 (SOC
+    dimension 5,051; no oracle value at these sizes): solved, and the
+    termination inequalities hold on the user's data."""
     prob = make()
     info, x, sv, z = gpu_solve(prob)
     print(prob.name, {k: info[k] for k in ("status_name", "iterations", "obj_primal", "n_ordered", "n_leaves")},
