@@ -41,7 +41,7 @@ extern "C" {
                                     an entry below its diagonal                    */
 #define HC_ERR_CONE        (-4)  /* unknown cone type, SOC dim < 2, EXP/POW dim !=
                                     3, alpha outside (0,1), PSD side outside
-                                    [1, 32] (sides above 12: HC_ERR_UNSUPPORTED) */
+                                    [1, 32]                                        */
 #define HC_ERR_NONFINITE   (-5)  /* NaN or Inf in P, q, A or b                      */
 #define HC_ERR_OOM         (-6)  /* device memory (arena too small or allocation
                                     failed); hc_last_error names the bytes needed */

@@ -26,7 +26,6 @@
 
 namespace hc {
 
-constexpr int PSD_KMAX = 12;
 
 __device__ inline double sq(double x) { return x * x; }
 
@@ -443,53 +442,57 @@ __global__ void k_nonsym_scale(SegDev g, const double* __restrict__ s, const dou
 }
 
 // ---------------------------------------------------------------------------
-// PSD (k <= PSD_KMAX), one lane per cone; matrices row-major in local arrays
+// PSD (k <= KM), one lane per cone; matrices row-major in local arrays
 // ---------------------------------------------------------------------------
+template <int KM>
 __device__ inline void psd_smat(const double* v, int k, double* X) {
   int p = 0;
   for (int j = 0; j < k; ++j)
     for (int i = 0; i <= j; ++i, ++p) {
       const double f = (i == j) ? 1.0 : 0.70710678118654752440;
-      X[i * PSD_KMAX + j] = v[p] * f;
-      X[j * PSD_KMAX + i] = v[p] * f;
+      X[i * KM + j] = v[p] * f;
+      X[j * KM + i] = v[p] * f;
     }
 }
+template <int KM>
 __device__ inline void psd_svec(const double* X, int k, double* v) {
   int p = 0;
   for (int j = 0; j < k; ++j)
-    for (int i = 0; i <= j; ++i, ++p) v[p] = X[i * PSD_KMAX + j] * ((i == j) ? 1.0 : 1.41421356237309504880);
+    for (int i = 0; i <= j; ++i, ++p) v[p] = X[i * KM + j] * ((i == j) ? 1.0 : 1.41421356237309504880);
 }
 // lower Cholesky in place (row-major), returns false if not positive definite
+template <int KM>
 __device__ bool psd_chol(double* A, int k) {
   for (int j = 0; j < k; ++j) {
-    double d = A[j * PSD_KMAX + j];
-    for (int p = 0; p < j; ++p) d -= A[j * PSD_KMAX + p] * A[j * PSD_KMAX + p];
+    double d = A[j * KM + j];
+    for (int p = 0; p < j; ++p) d -= A[j * KM + p] * A[j * KM + p];
     if (!(d > 0.0)) return false;
     d = sqrt(d);
-    A[j * PSD_KMAX + j] = d;
+    A[j * KM + j] = d;
     for (int i = j + 1; i < k; ++i) {
-      double v = A[i * PSD_KMAX + j];
-      for (int p = 0; p < j; ++p) v -= A[i * PSD_KMAX + p] * A[j * PSD_KMAX + p];
-      A[i * PSD_KMAX + j] = v / d;
+      double v = A[i * KM + j];
+      for (int p = 0; p < j; ++p) v -= A[i * KM + p] * A[j * KM + p];
+      A[i * KM + j] = v / d;
     }
-    for (int i = 0; i < j; ++i) A[i * PSD_KMAX + j] = 0.0;
+    for (int i = 0; i < j; ++i) A[i * KM + j] = 0.0;
   }
   return true;
 }
 // one-sided Jacobi (Hestenes) on the columns of B (k x k): on return the
 // columns are orthogonal and W accumulates B_in W = B_out.
+template <int KM>
 __device__ void psd_jacobi_cols(double* B, int k, double* W) {
   for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) W[i * PSD_KMAX + j] = (i == j) ? 1.0 : 0.0;
+    for (int j = 0; j < k; ++j) W[i * KM + j] = (i == j) ? 1.0 : 0.0;
   for (int sweep = 0; sweep < 60; ++sweep) {
     bool rot = false;
     for (int p = 0; p < k - 1; ++p)
       for (int q = p + 1; q < k; ++q) {
         double a = 0, b = 0, g = 0;
         for (int r = 0; r < k; ++r) {
-          a += B[r * PSD_KMAX + p] * B[r * PSD_KMAX + p];
-          b += B[r * PSD_KMAX + q] * B[r * PSD_KMAX + q];
-          g += B[r * PSD_KMAX + p] * B[r * PSD_KMAX + q];
+          a += B[r * KM + p] * B[r * KM + p];
+          b += B[r * KM + q] * B[r * KM + q];
+          g += B[r * KM + p] * B[r * KM + q];
         }
         if (g == 0.0 || fabs(g) <= 1e-16 * sqrt(a * b)) continue;
         rot = true;
@@ -497,51 +500,52 @@ __device__ void psd_jacobi_cols(double* B, int k, double* W) {
         const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
         for (int r = 0; r < k; ++r) {
-          const double bp = B[r * PSD_KMAX + p], bq = B[r * PSD_KMAX + q];
-          B[r * PSD_KMAX + p] = cs * bp - sn * bq;
-          B[r * PSD_KMAX + q] = sn * bp + cs * bq;
-          const double wp = W[r * PSD_KMAX + p], wq = W[r * PSD_KMAX + q];
-          W[r * PSD_KMAX + p] = cs * wp - sn * wq;
-          W[r * PSD_KMAX + q] = sn * wp + cs * wq;
+          const double bp = B[r * KM + p], bq = B[r * KM + q];
+          B[r * KM + p] = cs * bp - sn * bq;
+          B[r * KM + q] = sn * bp + cs * bq;
+          const double wp = W[r * KM + p], wq = W[r * KM + q];
+          W[r * KM + p] = cs * wp - sn * wq;
+          W[r * KM + q] = sn * wp + cs * wq;
         }
       }
     if (!rot) break;
   }
 }
 // cyclic Jacobi eigenvalues of a symmetric matrix (destroys A); returns lambda_min
+template <int KM>
 __device__ double psd_min_eig(double* A, int k) {
   // an off-diagonal entry below 1e-18 |A|_F moves no eigenvalue by more than
   // rounding does, so it is not rotated away; the sweeps end when a sweep
   // rotates nothing (quadratic convergence: a handful of sweeps), or at 60
   double tot = 0;
   for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) tot += sq(A[i * PSD_KMAX + j]);
+    for (int j = 0; j < k; ++j) tot += sq(A[i * KM + j]);
   const double small = 1e-18 * sqrt(tot);
   for (int sweep = 0; sweep < 60; ++sweep) {
     bool rot = false;
     for (int p = 0; p < k - 1; ++p)
       for (int q = p + 1; q < k; ++q) {
-        const double apq = A[p * PSD_KMAX + q];
+        const double apq = A[p * KM + q];
         if (!(fabs(apq) > small)) continue;
         rot = true;
-        const double theta = (A[q * PSD_KMAX + q] - A[p * PSD_KMAX + p]) / (2.0 * apq);
+        const double theta = (A[q * KM + q] - A[p * KM + p]) / (2.0 * apq);
         const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(1.0 + theta * theta));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
         for (int r = 0; r < k; ++r) {   // A <- A J (columns p, q)
-          const double arp = A[r * PSD_KMAX + p], arq = A[r * PSD_KMAX + q];
-          A[r * PSD_KMAX + p] = c * arp - s * arq;
-          A[r * PSD_KMAX + q] = s * arp + c * arq;
+          const double arp = A[r * KM + p], arq = A[r * KM + q];
+          A[r * KM + p] = c * arp - s * arq;
+          A[r * KM + q] = s * arp + c * arq;
         }
         for (int r = 0; r < k; ++r) {   // A <- J' A (rows p, q)
-          const double apr = A[p * PSD_KMAX + r], aqr = A[q * PSD_KMAX + r];
-          A[p * PSD_KMAX + r] = c * apr - s * aqr;
-          A[q * PSD_KMAX + r] = s * apr + c * aqr;
+          const double apr = A[p * KM + r], aqr = A[q * KM + r];
+          A[p * KM + r] = c * apr - s * aqr;
+          A[q * KM + r] = s * apr + c * aqr;
         }
       }
     if (!rot) break;
   }
   double m = A[0];
-  for (int i = 1; i < k; ++i) m = fmin(m, A[i * PSD_KMAX + i]);
+  for (int i = 1; i < k; ++i) m = fmin(m, A[i * KM + i]);
   return m;
 }
 
@@ -549,78 +553,88 @@ __device__ double psd_min_eig(double* A, int k) {
 // PSD kernels: one lane per cone, with the lane's k x k matrices in an LDS
 // slice of its own (private arrays of this size would sit in scratch memory,
 // and the per-entry loops below would pay a memory round trip on every
-// access).  Blocks of PSD_TB lanes keep the slices within LDS; slice strides
+// access).  Blocks of a few lanes keep the slices within LDS; slice strides
 // are odd so the lanes of a block fall on distinct banks.
 // ---------------------------------------------------------------------------
-constexpr int PSD_MAT = PSD_KMAX * PSD_KMAX;
-constexpr int PSD_SVEC = PSD_KMAX * (PSD_KMAX + 1) / 2;
-constexpr int PSD_TB = 8;
 constexpr int odd_stride(int n) { return n | 1; }
-constexpr int WS_SCALE = odd_stride(9 * PSD_MAT + 2 * PSD_KMAX);
-constexpr int WS_APPLY = odd_stride(4 * PSD_MAT + PSD_KMAX + PSD_SVEC);
-constexpr int WS_DS = odd_stride(8 * PSD_MAT + PSD_KMAX);
-constexpr int WS_STEP = odd_stride(3 * PSD_MAT);
-inline int psd_blocks(int64_t count) { return (int)std::max<int64_t>(1, ceil_div(count, PSD_TB)); }
+// Two instantiations: KM = 12 (sides up to 12, eight cones per workgroup)
+// and KM = 32 (sides 13..32, the paper's limit; a 32 x 32 FP64 matrix is 8 KB,
+// so two to four cones per workgroup keep the slices within ~150 KB of LDS).
+template <int KM> struct Psd {
+  static constexpr int MAT = KM * KM;
+  static constexpr int SVEC = KM * (KM + 1) / 2;
+  static constexpr int WS_SCALE = odd_stride(9 * MAT + 2 * KM);
+  static constexpr int WS_APPLY = odd_stride(4 * MAT + KM + SVEC);
+  static constexpr int WS_DS = odd_stride(8 * MAT + KM);
+  static constexpr int WS_STEP = odd_stride(3 * MAT);
+  static constexpr int TB_SCALE = KM <= 12 ? 8 : 2;   // lanes (cones) per workgroup
+  static constexpr int TB_APPLY = KM <= 12 ? 8 : 4;
+  static constexpr int TB_DS = KM <= 12 ? 8 : 2;
+  static constexpr int TB_STEP = KM <= 12 ? 8 : 4;
+  static int blocks(int64_t count, int tb) { return (int)std::max<int64_t>(1, ceil_div(count, tb)); }
+};
+constexpr int PSD_KSMALL = 12, PSD_KLARGE = 32;
 
 // PSD state fields: R (k*k row-major) | Rinv | Q | lambda (k) | m (k)
-__global__ __launch_bounds__(PSD_TB) void k_psd_scale(SegDev g, const double* __restrict__ s,
+template <int KM>
+__global__ __launch_bounds__(Psd<KM>::TB_SCALE) void k_psd_scale(SegDev g, const double* __restrict__ s,
                                                       const double* __restrict__ z, double* __restrict__ hdiag) {
-  __shared__ double wsall[PSD_TB * WS_SCALE];
+  __shared__ double wsall[Psd<KM>::TB_SCALE * Psd<KM>::WS_SCALE];
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.count) return;
   const int k = g.k, sd = g.dim;
   const int64_t N = g.count;
   const double* sc = s + g.base + c * sd;
   const double* zc = z + g.base + c * sd;
-  double* ws = wsall + threadIdx.x * WS_SCALE;
-  double *Ls = ws, *Lz = ws + PSD_MAT, *B = ws + 2 * PSD_MAT, *W = ws + 3 * PSD_MAT, *R = ws + 4 * PSD_MAT,
-         *Ri = ws + 5 * PSD_MAT, *Rt = ws + 6 * PSD_MAT, *Q = ws + 7 * PSD_MAT, *Mm = ws + 8 * PSD_MAT,
-         *lam = ws + 9 * PSD_MAT, *m = lam + PSD_KMAX;
-  psd_smat(sc, k, Ls);
-  psd_smat(zc, k, Lz);
-  psd_chol(Ls, k);
-  psd_chol(Lz, k);
+  double* ws = wsall + threadIdx.x * Psd<KM>::WS_SCALE;
+  double *Ls = ws, *Lz = ws + Psd<KM>::MAT, *B = ws + 2 * Psd<KM>::MAT, *W = ws + 3 * Psd<KM>::MAT, *R = ws + 4 * Psd<KM>::MAT,
+         *Ri = ws + 5 * Psd<KM>::MAT, *Rt = ws + 6 * Psd<KM>::MAT, *Q = ws + 7 * Psd<KM>::MAT, *Mm = ws + 8 * Psd<KM>::MAT,
+         *lam = ws + 9 * Psd<KM>::MAT, *m = lam + KM;
+  psd_smat<KM>(sc, k, Ls);
+  psd_smat<KM>(zc, k, Lz);
+  psd_chol<KM>(Ls, k);
+  psd_chol<KM>(Lz, k);
   // B = Lz' Ls
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Lz[p * PSD_KMAX + i] * Ls[p * PSD_KMAX + j];
-      B[i * PSD_KMAX + j] = acc;
+      for (int p = 0; p < k; ++p) acc += Lz[p * KM + i] * Ls[p * KM + j];
+      B[i * KM + j] = acc;
     }
-  psd_jacobi_cols(B, k, W);   // B W = U diag(lam): V = W
+  psd_jacobi_cols<KM>(B, k, W);   // B W = U diag(lam): V = W
   for (int j = 0; j < k; ++j) {
     double acc = 0;
-    for (int r = 0; r < k; ++r) acc += B[r * PSD_KMAX + j] * B[r * PSD_KMAX + j];
+    for (int r = 0; r < k; ++r) acc += B[r * KM + j] * B[r * KM + j];
     lam[j] = sqrt(acc);
   }
   // R = Ls V lam^-1/2 ; Rinv = lam^-1/2 U' Lz' with U = B diag(1/lam)
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Ls[i * PSD_KMAX + p] * W[p * PSD_KMAX + j];
-      R[i * PSD_KMAX + j] = acc / sqrt(lam[j]);
+      for (int p = 0; p < k; ++p) acc += Ls[i * KM + p] * W[p * KM + j];
+      R[i * KM + j] = acc / sqrt(lam[j]);
     }
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += (B[p * PSD_KMAX + i] / lam[i]) * Lz[j * PSD_KMAX + p];
-      Ri[i * PSD_KMAX + j] = acc / sqrt(lam[i]);
+      for (int p = 0; p < k; ++p) acc += (B[p * KM + i] / lam[i]) * Lz[j * KM + p];
+      Ri[i * KM + j] = acc / sqrt(lam[i]);
     }
   // M = R R' = Q diag(m) Q': one-sided Jacobi on the columns of R' gives Q
   for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) Rt[i * PSD_KMAX + j] = R[j * PSD_KMAX + i];
-  psd_jacobi_cols(Rt, k, Q);
+    for (int j = 0; j < k; ++j) Rt[i * KM + j] = R[j * KM + i];
+  psd_jacobi_cols<KM>(Rt, k, Q);
   for (int j = 0; j < k; ++j) {
     double acc = 0;
-    for (int r = 0; r < k; ++r) acc += Rt[r * PSD_KMAX + j] * Rt[r * PSD_KMAX + j];
+    for (int r = 0; r < k; ++r) acc += Rt[r * KM + j] * Rt[r * KM + j];
     m[j] = acc;
   }
   const int64_t kk = (int64_t)k * k;
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
-      g.state[(i * k + j) * N + c] = R[i * PSD_KMAX + j];
-      g.state[(kk + i * k + j) * N + c] = Ri[i * PSD_KMAX + j];
-      g.state[(2 * kk + i * k + j) * N + c] = Q[i * PSD_KMAX + j];
+      g.state[(i * k + j) * N + c] = R[i * KM + j];
+      g.state[(kk + i * k + j) * N + c] = Ri[i * KM + j];
+      g.state[(2 * kk + i * k + j) * N + c] = Q[i * KM + j];
     }
   for (int j = 0; j < k; ++j) {
     g.state[(3 * kk + j) * N + c] = lam[j];
@@ -630,14 +644,14 @@ __global__ __launch_bounds__(PSD_TB) void k_psd_scale(SegDev g, const double* __
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += R[i * PSD_KMAX + p] * R[j * PSD_KMAX + p];
-      Mm[i * PSD_KMAX + j] = acc;
+      for (int p = 0; p < k; ++p) acc += R[i * KM + p] * R[j * KM + p];
+      Mm[i * KM + j] = acc;
     }
   int p = 0;
   for (int b = 0; b < k; ++b)
     for (int a = 0; a <= b; ++a, ++p) {
-      const double v = (a == b) ? sq(Mm[a * PSD_KMAX + a])
-                                : (Mm[a * PSD_KMAX + a] * Mm[b * PSD_KMAX + b] + sq(Mm[a * PSD_KMAX + b]));
+      const double v = (a == b) ? sq(Mm[a * KM + a])
+                                : (Mm[a * KM + a] * Mm[b * KM + b] + sq(Mm[a * KM + b]));
       hdiag[g.base + c * sd + p] = v;
     }
 }
@@ -666,7 +680,12 @@ void cone_scale(const SegDev& g, const double* s, const double* z, double mu, in
                          pd_count);
       break;
     case HC_CONE_PSD:
-      hipLaunchKernelGGL(k_psd_scale, dim3(psd_blocks(g.count)), dim3(PSD_TB), 0, st, g, s, z, hdiag);
+      if (g.k <= PSD_KSMALL)
+        hipLaunchKernelGGL(k_psd_scale<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_SCALE)),
+                           dim3(Psd<PSD_KSMALL>::TB_SCALE), 0, st, g, s, z, hdiag);
+      else
+        hipLaunchKernelGGL(k_psd_scale<PSD_KLARGE>, dim3(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_SCALE)),
+                           dim3(Psd<PSD_KLARGE>::TB_SCALE), 0, st, g, s, z, hdiag);
       break;
   }
   HC_LAUNCH_CHECK();
@@ -677,28 +696,29 @@ void cone_scale(const SegDev& g, const double* s, const double* z, double mu, in
 // ===========================================================================
 __device__ inline double fsel(int mode, double lam, double delta) { return mode == 0 ? lam : 1.0 / (lam + delta); }
 
-// y = H x (mode 0) or (H + delta I)^-1 x (mode 1) for PSD cone c; ws: WS_APPLY doubles
+// y = H x (mode 0) or (H + delta I)^-1 x (mode 1) for PSD cone c; ws: Psd<KM>::WS_APPLY doubles
+template <int KM>
 __device__ void psd_apply_one(const SegDev& g, int64_t c, int mode, double delta, const double* x, double* y,
                               double* ws) {
   const int k = g.k;
   const int64_t N = g.count, kk = (int64_t)k * k;
-  double *Q = ws, *X = ws + PSD_MAT, *T = ws + 2 * PSD_MAT, *U = ws + 3 * PSD_MAT, *m = ws + 4 * PSD_MAT;
+  double *Q = ws, *X = ws + Psd<KM>::MAT, *T = ws + 2 * Psd<KM>::MAT, *U = ws + 3 * Psd<KM>::MAT, *m = ws + 4 * Psd<KM>::MAT;
   for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) Q[i * PSD_KMAX + j] = g.state[(2 * kk + i * k + j) * N + c];
+    for (int j = 0; j < k; ++j) Q[i * KM + j] = g.state[(2 * kk + i * k + j) * N + c];
   for (int j = 0; j < k; ++j) m[j] = g.state[(3 * kk + k + j) * N + c];
-  psd_smat(x, k, X);
+  psd_smat<KM>(x, k, X);
   // T = Q' X Q, scaled, then Y = Q T Q'
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += X[i * PSD_KMAX + p] * Q[p * PSD_KMAX + j];
-      T[i * PSD_KMAX + j] = acc;   // X Q
+      for (int p = 0; p < k; ++p) acc += X[i * KM + p] * Q[p * KM + j];
+      T[i * KM + j] = acc;   // X Q
     }
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Q[p * PSD_KMAX + i] * T[p * PSD_KMAX + j];
-      U[i * PSD_KMAX + j] = acc;
+      for (int p = 0; p < k; ++p) acc += Q[p * KM + i] * T[p * KM + j];
+      U[i * KM + j] = acc;
     }
   // Q'XQ is symmetric only up to rounding.  Its (i,j) and (j,i) entries are
   // one coefficient of the eigenvector svec(q_i q_j' + q_j q_i'), so average
@@ -706,26 +726,26 @@ __device__ void psd_apply_one(const SegDev& g, int64_t c, int mode, double delta
   // rounding asymmetry would otherwise turn, through the upper-triangle svec
   // read below, into an error along the stiff eigenvectors, where H is large.
   for (int i = 0; i < k; ++i) {
-    U[i * PSD_KMAX + i] *= fsel(mode, m[i] * m[i], delta);
+    U[i * KM + i] *= fsel(mode, m[i] * m[i], delta);
     for (int j = i + 1; j < k; ++j) {
-      const double v = 0.5 * (U[i * PSD_KMAX + j] + U[j * PSD_KMAX + i]) * fsel(mode, m[i] * m[j], delta);
-      U[i * PSD_KMAX + j] = v;
-      U[j * PSD_KMAX + i] = v;
+      const double v = 0.5 * (U[i * KM + j] + U[j * KM + i]) * fsel(mode, m[i] * m[j], delta);
+      U[i * KM + j] = v;
+      U[j * KM + i] = v;
     }
   }
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += U[i * PSD_KMAX + p] * Q[j * PSD_KMAX + p];
-      T[i * PSD_KMAX + j] = acc;   // U Q'
+      for (int p = 0; p < k; ++p) acc += U[i * KM + p] * Q[j * KM + p];
+      T[i * KM + j] = acc;   // U Q'
     }
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Q[i * PSD_KMAX + p] * T[p * PSD_KMAX + j];
-      X[i * PSD_KMAX + j] = acc;
+      for (int p = 0; p < k; ++p) acc += Q[i * KM + p] * T[p * KM + j];
+      X[i * KM + j] = acc;
     }
-  psd_svec(X, k, y);
+  psd_svec<KM>(X, k, y);
 }
 
 __global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __restrict__ x,
@@ -773,12 +793,13 @@ __global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __r
   }
 }
 
-__global__ __launch_bounds__(PSD_TB) void k_psd_apply(SegDev g, int mode, double delta, const double* __restrict__ x,
+template <int KM>
+__global__ __launch_bounds__(Psd<KM>::TB_APPLY) void k_psd_apply(SegDev g, int mode, double delta, const double* __restrict__ x,
                                                       double* __restrict__ y) {
-  __shared__ double wsall[PSD_TB * WS_APPLY];
+  __shared__ double wsall[Psd<KM>::TB_APPLY * Psd<KM>::WS_APPLY];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.count) return;
-  psd_apply_one(g, i, mode, delta, x + g.base + i * g.dim, y + g.base + i * g.dim, wsall + threadIdx.x * WS_APPLY);
+  psd_apply_one<KM>(g, i, mode, delta, x + g.base + i * g.dim, y + g.base + i * g.dim, wsall + threadIdx.x * Psd<KM>::WS_APPLY);
 }
 
 void cone_apply(const SegDev& g, int mode, double delta, const double* x, double* y, hipStream_t st) {
@@ -786,7 +807,12 @@ void cone_apply(const SegDev& g, int mode, double delta, const double* x, double
   if (soc_large(g.kind, g.dim))
     lsoc_apply(g, mode, delta, x, nullptr, y, st);
   else if (g.kind == HC_CONE_PSD)
-    hipLaunchKernelGGL(k_psd_apply, dim3(psd_blocks(g.count)), dim3(PSD_TB), 0, st, g, mode, delta, x, y);
+    if (g.k <= PSD_KSMALL)
+      hipLaunchKernelGGL(k_psd_apply<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_APPLY)),
+                         dim3(Psd<PSD_KSMALL>::TB_APPLY), 0, st, g, mode, delta, x, y);
+    else
+      hipLaunchKernelGGL(k_psd_apply<PSD_KLARGE>, dim3(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_APPLY)),
+                         dim3(Psd<PSD_KLARGE>::TB_APPLY), 0, st, g, mode, delta, x, y);
   else
     hipLaunchKernelGGL(k_cone_apply, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, mode, delta, x, y);
   HC_LAUNCH_CHECK();
@@ -836,14 +862,15 @@ __global__ void k_cone_recover(SegDev g, const double* __restrict__ dsr, const d
   }
 }
 
-__global__ __launch_bounds__(PSD_TB) void k_psd_recover(SegDev g, const double* __restrict__ dsr,
+template <int KM>
+__global__ __launch_bounds__(Psd<KM>::TB_APPLY) void k_psd_recover(SegDev g, const double* __restrict__ dsr,
                                                         const double* __restrict__ dz, double* __restrict__ out) {
-  __shared__ double wsall[PSD_TB * WS_APPLY];
+  __shared__ double wsall[Psd<KM>::TB_APPLY * Psd<KM>::WS_APPLY];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.count) return;
-  double* ws = wsall + threadIdx.x * WS_APPLY;
-  double* yv = ws + 4 * PSD_MAT + PSD_KMAX;
-  psd_apply_one(g, i, 0, 0.0, dz + g.base + i * g.dim, yv, ws);
+  double* ws = wsall + threadIdx.x * Psd<KM>::WS_APPLY;
+  double* yv = ws + 4 * Psd<KM>::MAT + KM;
+  psd_apply_one<KM>(g, i, 0, 0.0, dz + g.base + i * g.dim, yv, ws);
   for (int p = 0; p < g.dim; ++p) out[g.base + i * g.dim + p] = -dsr[g.base + i * g.dim + p] - yv[p];
 }
 
@@ -852,7 +879,12 @@ void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, dou
   if (soc_large(g.kind, g.dim))
     lsoc_apply(g, 0, 0.0, dz, dsrhs, out, st);
   else if (g.kind == HC_CONE_PSD)
-    hipLaunchKernelGGL(k_psd_recover, dim3(psd_blocks(g.count)), dim3(PSD_TB), 0, st, g, dsrhs, dz, out);
+    if (g.k <= PSD_KSMALL)
+      hipLaunchKernelGGL(k_psd_recover<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_APPLY)),
+                         dim3(Psd<PSD_KSMALL>::TB_APPLY), 0, st, g, dsrhs, dz, out);
+    else
+      hipLaunchKernelGGL(k_psd_recover<PSD_KLARGE>, dim3(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_APPLY)),
+                         dim3(Psd<PSD_KLARGE>::TB_APPLY), 0, st, g, dsrhs, dz, out);
   else
     hipLaunchKernelGGL(k_cone_recover, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, dsrhs, dz, out);
   HC_LAUNCH_CHECK();
@@ -862,12 +894,13 @@ void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, dou
 // p = a (a + 1) / 2 + b for a >= b, stored mblk[p * count + cone]
 // PSD: one workgroup per cone, one lane per svec row a; Q and m of the cone
 // staged in LDS
-__global__ __launch_bounds__(128) void k_psd_mblock(SegDev g, double delta) {
-  __shared__ double Q[PSD_MAT], m[PSD_KMAX];
+template <int KM>
+__global__ __launch_bounds__(KM <= 12 ? 128 : 576) void k_psd_mblock(SegDev g, double delta) {
+  __shared__ double Q[Psd<KM>::MAT], m[KM];
   const int64_t N = g.count, c = blockIdx.x;
   const int sd = g.dim, k = g.k;
   const int64_t kk = (int64_t)k * k;
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) Q[(e / k) * PSD_KMAX + e % k] = g.state[(2 * kk + e) * N + c];
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) Q[(e / k) * KM + e % k] = g.state[(2 * kk + e) * N + c];
   for (int e = threadIdx.x; e < k; e += blockDim.x) m[e] = g.state[(3 * kk + k + e) * N + c];
   __syncthreads();
   const int arow = threadIdx.x;
@@ -894,11 +927,11 @@ __global__ __launch_bounds__(128) void k_psd_mblock(SegDev g, double delta) {
             // svec(E_ii,jj) at (ia, ja) and (ib, jb)
             double ea, eb;
             if (ii == jj) {
-              ea = ca * Q[ia * PSD_KMAX + ii] * Q[ja * PSD_KMAX + ii];
-              eb = cb * Q[ib * PSD_KMAX + ii] * Q[jb * PSD_KMAX + ii];
+              ea = ca * Q[ia * KM + ii] * Q[ja * KM + ii];
+              eb = cb * Q[ib * KM + ii] * Q[jb * KM + ii];
             } else {
-              ea = ca * is2 * (Q[ia * PSD_KMAX + ii] * Q[ja * PSD_KMAX + jj] + Q[ia * PSD_KMAX + jj] * Q[ja * PSD_KMAX + ii]);
-              eb = cb * is2 * (Q[ib * PSD_KMAX + ii] * Q[jb * PSD_KMAX + jj] + Q[ib * PSD_KMAX + jj] * Q[jb * PSD_KMAX + ii]);
+              ea = ca * is2 * (Q[ia * KM + ii] * Q[ja * KM + jj] + Q[ia * KM + jj] * Q[ja * KM + ii]);
+              eb = cb * is2 * (Q[ib * KM + ii] * Q[jb * KM + jj] + Q[ib * KM + jj] * Q[jb * KM + ii]);
             }
             acc += ea * eb / (m[ii] * m[jj] + delta);
           }
@@ -964,9 +997,11 @@ __global__ void k_cone_mblock(SegDev g, double delta) {
 
 void cone_mblock(const SegDev& g, double delta, hipStream_t st) {
   if (g.count == 0) return;
-  if (g.kind == HC_CONE_PSD)
-    hipLaunchKernelGGL(k_psd_mblock, dim3((unsigned)g.count), dim3((unsigned)(ceil_div(g.dim, 64) * 64)), 0, st, g,
-                       delta);
+  const dim3 psd_threads((unsigned)(ceil_div(g.dim, 64) * 64));
+  if (g.kind == HC_CONE_PSD && g.k <= PSD_KSMALL)
+    hipLaunchKernelGGL(k_psd_mblock<PSD_KSMALL>, dim3((unsigned)g.count), psd_threads, 0, st, g, delta);
+  else if (g.kind == HC_CONE_PSD)
+    hipLaunchKernelGGL(k_psd_mblock<PSD_KLARGE>, dim3((unsigned)g.count), psd_threads, 0, st, g, delta);
   else
     hipLaunchKernelGGL(k_cone_mblock, dim3((unsigned)std::max<int64_t>(1, ceil_div(g.count, CONE_BLOCK))),
                        dim3(CONE_BLOCK), 0, st, g, delta);
@@ -1069,50 +1104,51 @@ __global__ void k_cone_ds(SegDev g, const double* __restrict__ s, const double* 
   }
 }
 
-__global__ __launch_bounds__(PSD_TB) void k_psd_ds(SegDev g, const double* __restrict__ dsa,
+template <int KM>
+__global__ __launch_bounds__(Psd<KM>::TB_DS) void k_psd_ds(SegDev g, const double* __restrict__ dsa,
                                                    const double* __restrict__ dza, double sm, double* __restrict__ ds) {
-  __shared__ double wsall[PSD_TB * WS_DS];
+  __shared__ double wsall[Psd<KM>::TB_DS * Psd<KM>::WS_DS];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.count) return;
   const int64_t N = g.count;
   const int k = g.k, sd = g.dim;
   const int64_t kk = (int64_t)k * k;
-  double* ws = wsall + threadIdx.x * WS_DS;
-  double *R = ws, *Ri = ws + PSD_MAT, *dS = ws + 2 * PSD_MAT, *dZ = ws + 3 * PSD_MAT, *T1 = ws + 4 * PSD_MAT,
-         *Aa = ws + 5 * PSD_MAT, *Bb = ws + 6 * PSD_MAT, *X = ws + 7 * PSD_MAT, *lam = ws + 8 * PSD_MAT;
+  double* ws = wsall + threadIdx.x * Psd<KM>::WS_DS;
+  double *R = ws, *Ri = ws + Psd<KM>::MAT, *dS = ws + 2 * Psd<KM>::MAT, *dZ = ws + 3 * Psd<KM>::MAT, *T1 = ws + 4 * Psd<KM>::MAT,
+         *Aa = ws + 5 * Psd<KM>::MAT, *Bb = ws + 6 * Psd<KM>::MAT, *X = ws + 7 * Psd<KM>::MAT, *lam = ws + 8 * Psd<KM>::MAT;
   for (int r = 0; r < k; ++r)
     for (int j = 0; j < k; ++j) {
-      R[r * PSD_KMAX + j] = g.state[(r * k + j) * N + i];
-      Ri[r * PSD_KMAX + j] = g.state[(kk + r * k + j) * N + i];
+      R[r * KM + j] = g.state[(r * k + j) * N + i];
+      Ri[r * KM + j] = g.state[(kk + r * k + j) * N + i];
     }
   for (int j = 0; j < k; ++j) lam[j] = g.state[(3 * kk + j) * N + i];
-  psd_smat(dsa + g.base + i * sd, k, dS);
-  psd_smat(dza + g.base + i * sd, k, dZ);
+  psd_smat<KM>(dsa + g.base + i * sd, k, dS);
+  psd_smat<KM>(dza + g.base + i * sd, k, dZ);
   // Aa = Ri dS Ri'
   for (int r = 0; r < k; ++r)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Ri[r * PSD_KMAX + p] * dS[p * PSD_KMAX + j];
-      T1[r * PSD_KMAX + j] = acc;
+      for (int p = 0; p < k; ++p) acc += Ri[r * KM + p] * dS[p * KM + j];
+      T1[r * KM + j] = acc;
     }
   for (int r = 0; r < k; ++r)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * Ri[j * PSD_KMAX + p];
-      Aa[r * PSD_KMAX + j] = acc;
+      for (int p = 0; p < k; ++p) acc += T1[r * KM + p] * Ri[j * KM + p];
+      Aa[r * KM + j] = acc;
     }
   // Bb = R' dZ R
   for (int r = 0; r < k; ++r)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += R[p * PSD_KMAX + r] * dZ[p * PSD_KMAX + j];
-      T1[r * PSD_KMAX + j] = acc;
+      for (int p = 0; p < k; ++p) acc += R[p * KM + r] * dZ[p * KM + j];
+      T1[r * KM + j] = acc;
     }
   for (int r = 0; r < k; ++r)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * R[p * PSD_KMAX + j];
-      Bb[r * PSD_KMAX + j] = acc;
+      for (int p = 0; p < k; ++p) acc += T1[r * KM + p] * R[p * KM + j];
+      Bb[r * KM + j] = acc;
     }
   // V = (Aa Bb + Bb Aa)/2 + diag(lam^2) - sm I ;  X_ij = 2 V_ij / (lam_i + lam_j)
   // (V is formed on the upper triangle and mirrored, so X is exactly
@@ -1120,26 +1156,26 @@ __global__ __launch_bounds__(PSD_TB) void k_psd_ds(SegDev g, const double* __res
   for (int r = 0; r < k; ++r)
     for (int j = r; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Aa[r * PSD_KMAX + p] * Bb[p * PSD_KMAX + j] + Bb[r * PSD_KMAX + p] * Aa[p * PSD_KMAX + j];
+      for (int p = 0; p < k; ++p) acc += Aa[r * KM + p] * Bb[p * KM + j] + Bb[r * KM + p] * Aa[p * KM + j];
       double v = 0.5 * acc;
       if (r == j) v += lam[r] * lam[r] - sm;
-      X[r * PSD_KMAX + j] = 2.0 * v / (lam[r] + lam[j]);
-      X[j * PSD_KMAX + r] = X[r * PSD_KMAX + j];
+      X[r * KM + j] = 2.0 * v / (lam[r] + lam[j]);
+      X[j * KM + r] = X[r * KM + j];
     }
   // ds = svec(R X R')
   for (int r = 0; r < k; ++r)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += R[r * PSD_KMAX + p] * X[p * PSD_KMAX + j];
-      T1[r * PSD_KMAX + j] = acc;
+      for (int p = 0; p < k; ++p) acc += R[r * KM + p] * X[p * KM + j];
+      T1[r * KM + j] = acc;
     }
   for (int r = 0; r < k; ++r)
     for (int j = 0; j < k; ++j) {
       double acc = 0;
-      for (int p = 0; p < k; ++p) acc += T1[r * PSD_KMAX + p] * R[j * PSD_KMAX + p];
-      X[r * PSD_KMAX + j] = acc;
+      for (int p = 0; p < k; ++p) acc += T1[r * KM + p] * R[j * KM + p];
+      X[r * KM + j] = acc;
     }
-  psd_svec(X, k, ds + g.base + i * sd);
+  psd_svec<KM>(X, k, ds + g.base + i * sd);
 }
 
 void cone_ds_combined(const SegDev& g, const double* s, const double* z, const double* dsa, const double* dza,
@@ -1148,7 +1184,12 @@ void cone_ds_combined(const SegDev& g, const double* s, const double* z, const d
   if (soc_large(g.kind, g.dim))
     lsoc_ds(g, dsa, dza, sm, ds, st);
   else if (g.kind == HC_CONE_PSD)
-    hipLaunchKernelGGL(k_psd_ds, dim3(psd_blocks(g.count)), dim3(PSD_TB), 0, st, g, dsa, dza, sm, ds);
+    if (g.k <= PSD_KSMALL)
+      hipLaunchKernelGGL(k_psd_ds<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_DS)),
+                         dim3(Psd<PSD_KSMALL>::TB_DS), 0, st, g, dsa, dza, sm, ds);
+    else
+      hipLaunchKernelGGL(k_psd_ds<PSD_KLARGE>, dim3(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_DS)),
+                         dim3(Psd<PSD_KLARGE>::TB_DS), 0, st, g, dsa, dza, sm, ds);
   else
     hipLaunchKernelGGL(k_cone_ds, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, s, z, dsa, dza, sm, ds);
   HC_LAUNCH_CHECK();
@@ -1167,29 +1208,30 @@ __device__ inline double soc_step_one(const double* x, const double* dx, int d) 
   return soc_boundary_step(a, b, c);
 }
 
-// largest alpha with x + alpha dx PSD (INFINITY if unbounded); ws: 3 PSD_MAT doubles
+// largest alpha with x + alpha dx PSD (INFINITY if unbounded); ws: 3 Psd<KM>::MAT doubles
+template <int KM>
 __device__ double psd_step_one(const double* x, const double* dx, int k, double* ws) {
-  double *L = ws, *D = ws + PSD_MAT, *T = ws + 2 * PSD_MAT;
-  psd_smat(x, k, L);
-  psd_smat(dx, k, D);
-  if (!psd_chol(L, k)) return 0.0;
+  double *L = ws, *D = ws + Psd<KM>::MAT, *T = ws + 2 * Psd<KM>::MAT;
+  psd_smat<KM>(x, k, L);
+  psd_smat<KM>(dx, k, D);
+  if (!psd_chol<KM>(L, k)) return 0.0;
   // T = L^-1 D, then Mm = T L^-T  (two triangular solves)
   for (int j = 0; j < k; ++j)
     for (int i = 0; i < k; ++i) {
-      double v = D[i * PSD_KMAX + j];
-      for (int p = 0; p < i; ++p) v -= L[i * PSD_KMAX + p] * T[p * PSD_KMAX + j];
-      T[i * PSD_KMAX + j] = v / L[i * PSD_KMAX + i];
+      double v = D[i * KM + j];
+      for (int p = 0; p < i; ++p) v -= L[i * KM + p] * T[p * KM + j];
+      T[i * KM + j] = v / L[i * KM + i];
     }
   // Mm = (L^-1 T')' : solve L Y = T' column by column, Mm = Y'
   for (int j = 0; j < k; ++j)
     for (int i = 0; i < k; ++i) {
-      double v = T[j * PSD_KMAX + i];
-      for (int p = 0; p < i; ++p) v -= L[i * PSD_KMAX + p] * D[p * PSD_KMAX + j];
-      D[i * PSD_KMAX + j] = v / L[i * PSD_KMAX + i];   // D now holds Y
+      double v = T[j * KM + i];
+      for (int p = 0; p < i; ++p) v -= L[i * KM + p] * D[p * KM + j];
+      D[i * KM + j] = v / L[i * KM + i];   // D now holds Y
     }
   for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) T[i * PSD_KMAX + j] = 0.5 * (D[i * PSD_KMAX + j] + D[j * PSD_KMAX + i]);
-  const double lmin = psd_min_eig(T, k);
+    for (int j = 0; j < k; ++j) T[i * KM + j] = 0.5 * (D[i * KM + j] + D[j * KM + i]);
+  const double lmin = psd_min_eig<KM>(T, k);
   return (lmin < 0.0) ? -1.0 / lmin : INFINITY;
 }
 
@@ -1228,17 +1270,19 @@ __global__ void k_step_sym(SegDev g, const double* __restrict__ s, const double*
 // PSD: grid-stride over the cones with at most PSD_STEP_GRID blocks, one
 // partial minimum per block
 constexpr int PSD_STEP_GRID = 2048;
-__global__ __launch_bounds__(PSD_TB) void k_step_psd(SegDev g, const double* __restrict__ s,
+template <int KM>
+__global__ __launch_bounds__(Psd<KM>::TB_STEP) void k_step_psd(SegDev g, const double* __restrict__ s,
                                                      const double* __restrict__ z, const double* __restrict__ ds,
                                                      const double* __restrict__ dz, double* __restrict__ partial) {
-  __shared__ double wsall[PSD_TB * WS_STEP];
-  double* ws = wsall + threadIdx.x * WS_STEP;
+  __shared__ double wsall[Psd<KM>::TB_STEP * Psd<KM>::WS_STEP];
+  double* ws = wsall + threadIdx.x * Psd<KM>::WS_STEP;
   const int sd = g.dim;
   double a = INFINITY;
-  for (int64_t i = (int64_t)blockIdx.x * PSD_TB + threadIdx.x; i < g.count; i += (int64_t)gridDim.x * PSD_TB)
-    a = fmin(a, fmin(psd_step_one(s + g.base + i * sd, ds + g.base + i * sd, g.k, ws),
-                     psd_step_one(z + g.base + i * sd, dz + g.base + i * sd, g.k, ws)));
-  for (int off = PSD_TB / 2; off > 0; off >>= 1) a = fmin(a, __shfl_xor(a, off, PSD_TB));
+  for (int64_t i = (int64_t)blockIdx.x * Psd<KM>::TB_STEP + threadIdx.x; i < g.count;
+       i += (int64_t)gridDim.x * Psd<KM>::TB_STEP)
+    a = fmin(a, fmin(psd_step_one<KM>(s + g.base + i * sd, ds + g.base + i * sd, g.k, ws),
+                     psd_step_one<KM>(z + g.base + i * sd, dz + g.base + i * sd, g.k, ws)));
+  for (int off = Psd<KM>::TB_STEP / 2; off > 0; off >>= 1) a = fmin(a, __shfl_xor(a, off, Psd<KM>::TB_STEP));
   if (threadIdx.x == 0) partial[blockIdx.x] = a;
 }
 
@@ -1247,8 +1291,16 @@ int cone_step_sym(const SegDev& g, const double* s, const double* z, const doubl
   if (g.count == 0 || g.kind == HC_CONE_ZERO || g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) return 0;
   if (soc_large(g.kind, g.dim)) return lsoc_step(g, s, z, ds, dz, INFINITY, false, partial, st);
   if (g.kind == HC_CONE_PSD) {
-    const int nbp = std::min(psd_blocks(g.count), PSD_STEP_GRID);
-    hipLaunchKernelGGL(k_step_psd, dim3(nbp), dim3(PSD_TB), 0, st, g, s, z, ds, dz, partial);
+    int nbp;
+    if (g.k <= PSD_KSMALL) {
+      nbp = std::min(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_STEP), PSD_STEP_GRID);
+      hipLaunchKernelGGL(k_step_psd<PSD_KSMALL>, dim3(nbp), dim3(Psd<PSD_KSMALL>::TB_STEP), 0, st, g, s, z, ds, dz,
+                         partial);
+    } else {
+      nbp = std::min(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_STEP), PSD_STEP_GRID);
+      hipLaunchKernelGGL(k_step_psd<PSD_KLARGE>, dim3(nbp), dim3(Psd<PSD_KLARGE>::TB_STEP), 0, st, g, s, z, ds, dz,
+                         partial);
+    }
     HC_LAUNCH_CHECK();
     return nbp;
   }
@@ -1409,10 +1461,6 @@ __global__ void k_max_neg_eig(SegDev g, const double* __restrict__ v, double* __
       double nx = 0;
       for (int j = 1; j < g.dim; ++j) nx += sq(v[g.base + j * N + i]);
       a = sqrt(nx) - v[g.base + i];
-    } else if (g.kind == HC_CONE_PSD) {
-      double X[PSD_KMAX * PSD_KMAX];
-      psd_smat(v + g.base + i * g.dim, g.k, X);
-      a = -psd_min_eig(X, g.k);
     }
   }
   red[threadIdx.x] = a;
@@ -1424,9 +1472,40 @@ __global__ void k_max_neg_eig(SegDev g, const double* __restrict__ v, double* __
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// PSD: one lane per cone (k x k matrix in an LDS slice), grid-stride over
+// the cones, one partial maximum per workgroup
+template <int KM>
+__global__ __launch_bounds__(Psd<KM>::TB_STEP) void k_psd_max_neg_eig(SegDev g, const double* __restrict__ v,
+                                                                      double* __restrict__ partial) {
+  __shared__ double wsall[Psd<KM>::TB_STEP * Psd<KM>::WS_STEP];
+  double* X = wsall + threadIdx.x * Psd<KM>::WS_STEP;
+  double a = -INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * Psd<KM>::TB_STEP + threadIdx.x; i < g.count;
+       i += (int64_t)gridDim.x * Psd<KM>::TB_STEP) {
+    psd_smat<KM>(v + g.base + i * g.dim, g.k, X);
+    a = fmax(a, -psd_min_eig<KM>(X, g.k));
+  }
+  for (int off = Psd<KM>::TB_STEP / 2; off > 0; off >>= 1) a = fmax(a, __shfl_xor(a, off, Psd<KM>::TB_STEP));
+  if (threadIdx.x == 0) partial[blockIdx.x] = a;
+}
+
 int cone_max_neg_eig(const SegDev& g, const double* v, double* partial, hipStream_t st) {
   if (g.count == 0 || !(g.kind == HC_CONE_NONNEG || g.kind == HC_CONE_SOC || g.kind == HC_CONE_PSD)) return 0;
   if (soc_large(g.kind, g.dim)) return lsoc_max_neg_eig(g, v, partial, st);
+  if (g.kind == HC_CONE_PSD) {
+    int nbp;
+    if (g.k <= PSD_KSMALL) {
+      nbp = std::min(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_STEP), PSD_STEP_GRID);
+      hipLaunchKernelGGL(k_psd_max_neg_eig<PSD_KSMALL>, dim3(nbp), dim3(Psd<PSD_KSMALL>::TB_STEP), 0, st, g, v,
+                         partial);
+    } else {
+      nbp = std::min(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_STEP), PSD_STEP_GRID);
+      hipLaunchKernelGGL(k_psd_max_neg_eig<PSD_KLARGE>, dim3(nbp), dim3(Psd<PSD_KLARGE>::TB_STEP), 0, st, g, v,
+                         partial);
+    }
+    HC_LAUNCH_CHECK();
+    return nbp;
+  }
   const int nb = cone_blocks(g);
   hipLaunchKernelGGL(k_max_neg_eig, dim3(nb), dim3(CONE_BLOCK), 0, st, g, v, partial);
   HC_LAUNCH_CHECK();
@@ -1515,10 +1594,6 @@ __global__ void k_test_step(SegDev g, const double* __restrict__ s, const double
       xdz[j] = dz[g.base + j * N + i];
     }
     a = fmin(a, fmin(soc_step_one(xs, xds, g.dim), soc_step_one(xz, xdz, g.dim)));
-  } else if (g.kind == HC_CONE_PSD) {
-    double ws[3 * PSD_MAT];   // test entry only: scratch is fine here
-    a = fmin(a, fmin(psd_step_one(s + g.base + i * g.dim, ds + g.base + i * g.dim, g.k, ws),
-                     psd_step_one(z + g.base + i * g.dim, dz + g.base + i * g.dim, g.k, ws)));
   } else if (g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) {
     const double al = (g.kind == HC_CONE_POW) ? g.alpha[i] : 0.0;
     double t = amax;
@@ -1541,10 +1616,34 @@ __global__ void k_test_step(SegDev g, const double* __restrict__ s, const double
   out[i] = a;
 }
 
+template <int KM>
+__global__ __launch_bounds__(Psd<KM>::TB_STEP) void k_psd_test_step(SegDev g, const double* __restrict__ s,
+                                                                    const double* __restrict__ z,
+                                                                    const double* __restrict__ ds,
+                                                                    const double* __restrict__ dz, double amax,
+                                                                    double* __restrict__ out) {
+  __shared__ double wsall[Psd<KM>::TB_STEP * Psd<KM>::WS_STEP];
+  double* ws = wsall + threadIdx.x * Psd<KM>::WS_STEP;
+  const int64_t i = (int64_t)blockIdx.x * Psd<KM>::TB_STEP + threadIdx.x;
+  if (i >= g.count) return;
+  out[i] = fmin(amax, fmin(psd_step_one<KM>(s + g.base + i * g.dim, ds + g.base + i * g.dim, g.k, ws),
+                           psd_step_one<KM>(z + g.base + i * g.dim, dz + g.base + i * g.dim, g.k, ws)));
+}
+
 void cone_test_step(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz,
                     double amax, double* out, hipStream_t st) {
   if (soc_large(g.kind, g.dim)) {
     lsoc_step(g, s, z, ds, dz, amax, true, out, st);
+    return;
+  }
+  if (g.kind == HC_CONE_PSD) {
+    if (g.k <= PSD_KSMALL)
+      hipLaunchKernelGGL(k_psd_test_step<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_STEP)),
+                         dim3(Psd<PSD_KSMALL>::TB_STEP), 0, st, g, s, z, ds, dz, amax, out);
+    else
+      hipLaunchKernelGGL(k_psd_test_step<PSD_KLARGE>, dim3(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_STEP)),
+                         dim3(Psd<PSD_KLARGE>::TB_STEP), 0, st, g, s, z, ds, dz, amax, out);
+    HC_LAUNCH_CHECK();
     return;
   }
   hipLaunchKernelGGL(k_test_step, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, s, z, ds, dz, amax, out);

@@ -230,7 +230,6 @@ void validate(const hc_problem* p) {
         break;
       case HC_CONE_PSD:
         if (k.dim < 1 || k.dim > 32) fail(HC_ERR_CONE, "PSD side outside [1, 32]");
-        if (k.dim > 12) fail(HC_ERR_UNSUPPORTED, "PSD side > 12 is not handled by this build");
         rows += (int64_t)k.dim * (k.dim + 1) / 2;
         break;
       default:

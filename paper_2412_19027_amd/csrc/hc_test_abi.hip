@@ -66,7 +66,7 @@ void make(TestSeg& T, int32_t type, int64_t count, int32_t dim, const double* al
       T.rows = 3; T.g.dim = 3; T.g.count = count; T.cm = true;
       break;
     case HC_CONE_PSD:
-      if (dim < 1 || dim > 12) throw Error{HC_ERR_UNSUPPORTED, "PSD side outside [1, 12]"};
+      if (dim < 1 || dim > 32) throw Error{HC_ERR_CONE, "PSD side outside [1, 32]"};
       T.rows = dim * (dim + 1) / 2; T.g.dim = T.rows; T.g.k = dim; T.g.count = count; T.cm = false;
       break;
     default:

@@ -37,7 +37,8 @@ def certify(prob, x, sv, z, eps=1e-8):
 
 
 @pytest.mark.parametrize("make", [PS.box_lp, PS.soc_ball, PS.exp_max, PS.softplus, PS.entropy, PS.pow_max,
-                                  PS.trace_min, PS.lqr, PS.soc_balls, PS.soc_ball_budget])
+                                  PS.trace_min, PS.lqr, PS.soc_balls, PS.soc_ball_budget,
+                                  lambda: PS.trace_min(0, k=24), lambda: PS.trace_min(1, k=32)])
 def test_known_optimum(make):
     prob, fstar = make()
     info, x, sv, z = gpu_solve(prob)
@@ -59,6 +60,8 @@ CASES = [
     ("entropy_dense_rows", lambda: W.entropy_max(0, n=600)),
     ("portfolio_small", lambda: W.portfolio_qp(0, n=300)),
     ("psd_mixed_sides", lambda: W.psd_mixed(0)),
+    # sides above 12 (two cones per workgroup, up to the paper's 32) beside a small one
+    ("psd_sides_to_32", lambda: W.psd_mixed(0, n=300, sides=(3, 14, 32), per_side=6)),
     # second-order cones above 16 rows (one workgroup per cone, diagonal plus
     # rank-2 Schur form): several dims, with leaf blocks (the z variables),
     # and with dense budget rows on the same columns

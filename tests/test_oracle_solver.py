@@ -33,7 +33,8 @@ def certify(s, prob, eps=1e-8):
 
 
 @pytest.mark.parametrize("make", [PS.box_lp, PS.soc_ball, PS.exp_max, PS.softplus, PS.entropy,
-                                  PS.pow_max, PS.trace_min, PS.lqr, PS.soc_balls, PS.soc_ball_budget])
+                                  PS.pow_max, PS.trace_min, PS.lqr, PS.soc_balls, PS.soc_ball_budget,
+                                  lambda: PS.trace_min(1, k=32)])
 def test_known_optimum(make):
     prob, fstar = make()
     s = solved(prob)
