@@ -99,7 +99,7 @@ def run_gpu(prob, precision, steps, warmup):
     )
 
 
-OTHER_WORKLOADS = ("logreg_exp", "psd_pow", "entropy_max", "portfolio_qp", "multistage_portfolio")
+OTHER_WORKLOADS = ("logreg_exp", "psd_pow", "entropy_max", "portfolio_qp", "multistage_portfolio", "psd_sides_to_32")
 
 
 def run_other_workloads(steps=1, only=None):
@@ -110,7 +110,8 @@ def run_other_workloads(steps=1, only=None):
     from paper_2412_19027_amd import workloads as W
     makers = {"logreg_exp": lambda: W.logreg_exp(0), "psd_pow": lambda: W.psd_pow(0),
               "entropy_max": lambda: W.entropy_max(0, n=10000), "portfolio_qp": lambda: W.portfolio_qp(0, n=25000),
-              "multistage_portfolio": lambda: W.multistage_portfolio(0, n=5000, k=50, T=5)}
+              "multistage_portfolio": lambda: W.multistage_portfolio(0, n=5000, k=50, T=5),
+              "psd_sides_to_32": lambda: W.psd_mixed(0, n=2000, sides=(8, 20, 32), per_side=30)}
     out = {}
     for name in OTHER_WORKLOADS:
         if only and name != only:

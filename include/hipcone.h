@@ -6,7 +6,7 @@
  * with K a product of zero, nonnegative, second-order, exponential, 3-d power
  * and PSD cones (arXiv 2412.19027, Sec. 1 problem (P) and Sec. 2.1
  * "Supported cones"; PSD cones may have different sides, which the paper
- * leaves to future work, Sec. 6).  Every per-iteration step of the method
+ * leaves to future work, Sec. 5).  Every per-iteration step of the method
  * (Algorithm 1, Sec. 3.2) runs in this library's HIP kernels: residuals and
  * termination, the cone scalings and their writes into the KKT system, the
  * quasi-definite LDL' factorisation and triangular solves with iterative
@@ -88,7 +88,7 @@ typedef struct {
 #define HC_PRECISION_FP64  0   /* factor and solve in FP64 (the paper's default)  */
 #define HC_PRECISION_MIXED 1   /* factor and triangular solves in FP32, residuals,
                                   refinement updates and everything else in FP64
-                                  (Sec. 3.5 mixed precision)                     */
+                                  (Sec. 3.7 mixed precision)                     */
 typedef struct {
   double eps_feas;        /* 1e-8: optimality tests (eq. termination-check)        */
   double eps_inf;         /* 1e-8: infeasibility tests (eq. infeasibility-check)   */
@@ -97,7 +97,7 @@ typedef struct {
   double static_reg;      /* delta_s: 1e-8 (FP64) / sqrt(eps_32) (mixed); <= 0 picks
                              the value for the precision                          */
   double dyn_reg;         /* delta_d: eps^2 of the factor precision; < 0 picks it   */
-  double ir_abstol;       /* 1e-12 (refinement stop, Sec. 3.5)                      */
+  double ir_abstol;       /* 1e-12 (refinement stop, Sec. 3.7)                      */
   double ir_reltol;       /* 1e-12                                                  */
   int32_t ir_max;         /* 10 corrections after the first solve                  */
   double beta;            /* 1e-6: neighbourhood N(beta) (Sec. 2.2)                 */
@@ -210,7 +210,7 @@ int32_t hc_set_iterate(hc_solver* s, const double* x, const double* sv, const do
                        double tau, double kappa);
 
 /* Test entry: one KKT solve of an interior-point iteration at the current
- * iterate (Sec. 3.4-3.5, Algorithm 1): the cone scalings at (s, z) with the
+ * iterate (Sec. 3.3 and 3.7, Algorithm 1): the cone scalings at (s, z) with the
  * given mu (force_dual != 0 forces the dual scaling of the exp/pow cones),
  * the regularised factorisation, and
  *   [P  A'; A  -H] [x; z] = [r1; r2]
@@ -231,7 +231,7 @@ int32_t hc_test_kkt_solve(hc_solver* s, double mu, int32_t force_dual, const dou
 int32_t hc_test_kkt_ops(hc_solver* s, double mu, int32_t force_dual, const double* r1,
                         const double* r2, double* xr, double* zr, double* kx, double* kz);
 
-/* Test entry: the Schur complement S = P + delta I + A' M A (Sec. 3.5, cone
+/* Test entry: the Schur complement S = P + delta I + A' M A (Sec. 3.7, cone
  * rows eliminated) assembled at the scaling of the current iterate, and its
  * Cholesky factor.  Only for solvers whose columns all sit in the dense block
  * (settings.leaf_blocks = 0, else HC_ERR_STATE).  S_out, L_out (NULL allowed):
@@ -242,7 +242,7 @@ int32_t hc_test_kkt_ops(hc_solver* s, double mu, int32_t force_dual, const doubl
 int32_t hc_test_schur(hc_solver* s, double mu, int32_t force_dual, double* S_out, double* L_out,
                       double* stats);
 
-/* Parametric re-solve (Sec. 5, re-solving with new data of one structure):
+/* Parametric re-solve (Sec. 4.6, re-solving with new data of one structure):
  * replace the values of P (upper triangle, in the set-up's CSR order; nnz
  * of P), q (n), A (set-up's CSR order; nnz of A) and b (m); NULL keeps an
  * array as it is.  The sparsity pattern and cones stay those of hc_setup:
@@ -313,7 +313,7 @@ int32_t hc_test_dense_chol_solve_env(int32_t precision, int64_t n, int64_t ld, d
 
 /* ---- served form --------------------------------------------------------
  * Continuous batching of many independent problems on one GPU (the paper's
- * parametric re-solve setting, Sec. 4.3, served as a request stream).
+ * parametric re-solve setting, Sec. 4.6, served as a request stream).
  * Requests are analysed on the submitting thread (as hc_setup: the problem is
  * copied, the caller may free it on return), queued first in first out, and
  * admitted into active slots while their device workspace fits the HBM

@@ -6,7 +6,7 @@ path may import this package.
 
 The reduced system (eq. linsys_2x2) is K [dx; dz] = rhs with
 K = [[P, A'], [A, -H]], H block diagonal over the cones.  A regularisation
-delta = delta_s + delta_d max_i |K_ii| makes K quasi-definite (Sec. 3.5
+delta = delta_s + delta_d max_i |K_ii| makes K quasi-definite (Sec. 3.7
 "Solving linear systems"): +delta on the P block and -delta on the -H block
 (reading: adding +delta to the -H block as printed breaks quasi-definiteness).
 
@@ -21,7 +21,7 @@ eigenvector, which H_c then amplifies into an O(1) residual.  Explicit
 M_c entries are only used to assemble S, where that component is
 negligible.
 
-Iterative refinement (Sec. 3.5, the three-step loop): residual with the
+Iterative refinement (Sec. 3.7, the three-step loop): residual with the
 *unregularised* K, correction with the regularised factor, stop when
 ||r||_inf <= t_abs + t_rel ||rhs||_inf, after T_max corrections, or when a
 correction fails to halve the residual (the best iterate is kept).

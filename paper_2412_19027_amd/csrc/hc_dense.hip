@@ -2,10 +2,10 @@
 //
 // After the cone rows are eliminated (their pivots are the -(H_c + delta I)
 // blocks), the quasi-definite LDL' of the regularised KKT matrix
-// (eq. linsys_2x2, Sec. 3.5) continues on the positive definite Schur
+// (eq. linsys_2x2, Sec. 3.7) continues on the positive definite Schur
 // complement S = P + delta I + A' M A.  This file factors S = L L' (the
 // positive pivots of the LDL', D = diag(L)^2 absorbed into L) and solves with
-// L, in FP64 or -- for the mixed-precision mode of Sec. 3.5 -- FP32 with FP32
+// L, in FP64 or -- for the mixed-precision mode of Sec. 3.7 -- FP32 with FP32
 // accumulation.
 //
 // Layout: S is column-major with leading dimension ld, lower triangle used.

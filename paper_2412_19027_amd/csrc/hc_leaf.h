@@ -7,7 +7,7 @@
 //   S = [ S_LL  S_TL' ]      S_LL block diagonal (one dense block per leaf),
 //       [ S_TL  S_TT  ]      S_TL: each leaf couples to a few tail columns,
 //
-// so the LDL' of Sec. 3.5 becomes: per leaf L_b L_b' = S_bb and
+// so the LDL' of Sec. 3.7 becomes: per leaf L_b L_b' = S_bb and
 // W_b = S_Tb L_b^-T (batched, one wave per leaf), then the tail
 // S_TT - sum_b W_b W_b' is factored densely on MFMA.  The leaves are the
 // "many tiny supernodes" of a supernodal factorisation and the tail its dense

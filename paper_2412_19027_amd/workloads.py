@@ -411,7 +411,7 @@ def mpc_arrivals(seed: int, count: int, rate: float = 2000.0) -> np.ndarray:
 # --------------------------------------------------------------------------
 
 # --------------------------------------------------------------------------
-# the paper's exponential-cone and QP benchmark problems (Sec. 5)
+# the paper's exponential-cone and QP benchmark problems (Sec. 4.4, 4.2)
 # --------------------------------------------------------------------------
 
 def entropy_max(seed: int = 0, n: int = 10000) -> Problem:

@@ -3,10 +3,10 @@
 The oracle runs the homogeneous-embedding iteration (Algorithm 1) on the CPU;
 at each of its iterates the same (x, s, z, tau, kappa) is loaded into the GPU
 solver (hc_set_iterate) and the GPU forms, at the scaling of that iterate
-(Sec. 3.4, Appendix A), the three things one iteration needs:
+(Sec. 3.3, Appendix A), the three things one iteration needs:
 
 * the Schur complement S = P + delta I + A'MA and its Cholesky factor
-  (Sec. 3.5; hc_test_schur), against the oracle's S;
+  (Sec. 3.7; hc_test_schur), against the oracle's S;
 * one regularised solve and the unregularised product K [x; z]
   (hc_test_kkt_ops): the residual left by one regularised solve must be as
   small as the oracle's, which catches operators H and M = (H + delta I)^-1

@@ -1,4 +1,4 @@
-"""The paper's entropy-maximisation and portfolio-QP problems (Sec. 5) as
+"""The paper's entropy-maximisation and portfolio-QP problems (Sec. 4.4, 4.2) as
 generated here, and the oracle's solutions of small instances pinned by
 bounds that hold for any correct optimum."""
 import numpy as np
