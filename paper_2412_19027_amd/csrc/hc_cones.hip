@@ -656,6 +656,10 @@ __global__ __launch_bounds__(Psd<KM>::TB_SCALE) void k_psd_scale(SegDev g, const
     }
 }
 
+// sides 13..32: one wave per cone (defined with the other wave kernels below)
+__global__ __launch_bounds__(64) void k_psd_scale_wave(SegDev g, const double* __restrict__ s,
+                                                       const double* __restrict__ z, double* __restrict__ hdiag);
+
 void cone_scale(const SegDev& g, const double* s, const double* z, double mu, int force_dual, double* hdiag,
                 int* pd_count, hipStream_t st) {
   if (g.count == 0) return;
@@ -684,8 +688,8 @@ void cone_scale(const SegDev& g, const double* s, const double* z, double mu, in
         hipLaunchKernelGGL(k_psd_scale<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_SCALE)),
                            dim3(Psd<PSD_KSMALL>::TB_SCALE), 0, st, g, s, z, hdiag);
       else
-        hipLaunchKernelGGL(k_psd_scale<PSD_KLARGE>, dim3(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_SCALE)),
-                           dim3(Psd<PSD_KLARGE>::TB_SCALE), 0, st, g, s, z, hdiag);
+        hipLaunchKernelGGL(k_psd_scale_wave, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0, st, g, s,
+                           z, hdiag);
       break;
   }
   HC_LAUNCH_CHECK();
@@ -1360,6 +1364,324 @@ __global__ __launch_bounds__(Psd<KM>::TB_STEP) void k_step_psd(SegDev g, const d
   if (threadIdx.x == 0) partial[blockIdx.x] = a;
 }
 
+// ---------------------------------------------------------------------------
+// Sides 13..32: one wave per cone for the Jacobi-based PSD kernels.  The k
+// indices (padded to an even count kk with one that never rotates) are paired
+// round-robin (circle method: index kk - 1 fixed, the others turning), so the
+// kk/2 pairs of a round are disjoint and their rotations are applied at once;
+// a sweep is kk - 1 rounds.  Matrices sit in LDS, row stride PW_LD.
+// ---------------------------------------------------------------------------
+constexpr int PW_LD = PSD_KLARGE + 1;
+constexpr int PW_MAT = PSD_KLARGE * PW_LD;
+
+__device__ inline void rr_pair(int kk, int r, int i, int& p, int& q) {
+  if (i == 0) {
+    p = kk - 1;
+    q = r;
+  } else {
+    p = (r + i) % (kk - 1);
+    q = (r - i + (kk - 1)) % (kk - 1);
+  }
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+}
+
+// (i, j) of entry e of the packed triangle i >= j (row by row)
+__device__ inline void tri_index(int e, int& i, int& j) {
+  i = (int)((sqrt(8.0 * e + 1.0) - 1.0) / 2.0);
+  while (i * (i + 1) / 2 > e) --i;
+  while ((i + 1) * (i + 2) / 2 <= e) ++i;
+  j = e - i * (i + 1) / 2;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline double wave_min(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// X = smat(v) (k x k, symmetric)
+__device__ inline void wave_smat(const double* v, int k, double* X, int lane) {
+  const int sd = k * (k + 1) / 2;
+  for (int p = lane; p < sd; p += 64) {
+    int j, i;
+    tri_index(p, j, i);   // svec: column j, rows i <= j
+    const double x = v[p] * (i == j ? 1.0 : 0.70710678118654752440);
+    X[i * PW_LD + j] = x;
+    X[j * PW_LD + i] = x;
+  }
+}
+
+// lower Cholesky in place (upper part zeroed); false (on every lane) when a
+// pivot is not positive
+__device__ bool wave_chol(double* A, int k, int lane) {
+  for (int j = 0; j < k; ++j) {
+    __syncthreads();
+    const double d = A[j * PW_LD + j];
+    if (!(d > 0.0)) return false;
+    const double r = sqrt(d);
+    __syncthreads();
+    if (lane == 0) A[j * PW_LD + j] = r;
+    for (int i = j + 1 + lane; i < k; i += 64) A[i * PW_LD + j] /= r;
+    __syncthreads();
+    const int t = k - j - 1;
+    for (int e = lane; e < t * (t + 1) / 2; e += 64) {
+      int i, l;
+      tri_index(e, i, l);
+      i += j + 1;
+      l += j + 1;
+      A[i * PW_LD + l] -= A[i * PW_LD + j] * A[l * PW_LD + j];
+    }
+  }
+  __syncthreads();
+  for (int e = lane; e < k * k; e += 64)
+    if (e / k < e % k) A[(e / k) * PW_LD + e % k] = 0.0;
+  __syncthreads();
+  return true;
+}
+
+// smallest eigenvalue of the symmetric A (destroyed): parallel cyclic Jacobi
+// with the per-lane kernel's stopping rule (no rotation of entries at most
+// 1e-18 |A|_F; end on a sweep without rotations, or after 60)
+__device__ double wave_min_eig(double* A, int k, int lane, double* rc, double* rs, int* rp, int* rq, int* flag) {
+  double tot = 0;
+  for (int e = lane; e < k * k; e += 64) tot += sq(A[(e / k) * PW_LD + e % k]);
+  const double small = 1e-18 * sqrt(wave_sum(tot));
+  const int kk = (k + 1) & ~1, np = kk / 2;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    __syncthreads();
+    if (lane == 0) *flag = 0;
+    for (int r = 0; r < kk - 1; ++r) {
+      __syncthreads();
+      if (lane < np) {
+        int p, q;
+        rr_pair(kk, r, lane, p, q);
+        double c = 1.0, sn = 0.0;
+        if (q < k) {
+          const double apq = A[p * PW_LD + q];
+          if (fabs(apq) > small) {
+            const double theta = (A[q * PW_LD + q] - A[p * PW_LD + p]) / (2.0 * apq);
+            const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(1.0 + theta * theta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = c * t;
+            *flag = 1;
+          }
+        }
+        rp[lane] = p;
+        rq[lane] = q;
+        rc[lane] = c;
+        rs[lane] = sn;
+      }
+      __syncthreads();
+      for (int e = lane; e < k * np; e += 64) {   // A <- A J: columns p, q of every pair
+        const int row = e / np, pi = e % np, p = rp[pi], q = rq[pi];
+        if (q >= k || rs[pi] == 0.0) continue;
+        const double arp = A[row * PW_LD + p], arq = A[row * PW_LD + q];
+        A[row * PW_LD + p] = rc[pi] * arp - rs[pi] * arq;
+        A[row * PW_LD + q] = rs[pi] * arp + rc[pi] * arq;
+      }
+      __syncthreads();
+      for (int e = lane; e < k * np; e += 64) {   // A <- J' A: rows p, q
+        const int col = e / np, pi = e % np, p = rp[pi], q = rq[pi];
+        if (q >= k || rs[pi] == 0.0) continue;
+        const double apc = A[p * PW_LD + col], aqc = A[q * PW_LD + col];
+        A[p * PW_LD + col] = rc[pi] * apc - rs[pi] * aqc;
+        A[q * PW_LD + col] = rs[pi] * apc + rc[pi] * aqc;
+      }
+    }
+    __syncthreads();
+    if (!*flag) break;
+  }
+  double m = INFINITY;
+  for (int i = lane; i < k; i += 64) m = fmin(m, A[i * PW_LD + i]);
+  return wave_min(m);
+}
+
+// one-sided Jacobi (Hestenes) on the columns of B (k x k): on return the
+// columns are orthogonal and W accumulates B_in W = B_out.  Four lanes per
+// pair, each summing and rotating rows sub, sub + 4, ...; the rule of the
+// per-lane kernel skips a pair when |b_p'b_q| <= 1e-16 |b_p||b_q|.
+__device__ void wave_jacobi_cols(double* B, int k, double* W, int lane, int* flag) {
+  for (int e = lane; e < k * k; e += 64) W[(e / k) * PW_LD + e % k] = (e / k == e % k) ? 1.0 : 0.0;
+  const int kk = (k + 1) & ~1, np = kk / 2, grp = lane >> 2, sub = lane & 3;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    __syncthreads();
+    if (lane == 0) *flag = 0;
+    for (int r = 0; r < kk - 1; ++r) {
+      __syncthreads();
+      if (grp >= np) continue;
+      int p, q;
+      rr_pair(kk, r, grp, p, q);
+      if (q >= k) continue;
+      double a = 0, b = 0, gg = 0;
+      for (int row = sub; row < k; row += 4) {
+        const double bp = B[row * PW_LD + p], bq = B[row * PW_LD + q];
+        a += bp * bp;
+        b += bq * bq;
+        gg += bp * bq;
+      }
+      for (int off = 1; off < 4; off <<= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        gg += __shfl_xor(gg, off, 64);
+      }
+      if (gg == 0.0 || fabs(gg) <= 1e-16 * sqrt(a * b)) continue;
+      const double zeta = (b - a) / (2.0 * gg);
+      const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+      for (int row = sub; row < k; row += 4) {
+        const double bp = B[row * PW_LD + p], bq = B[row * PW_LD + q];
+        B[row * PW_LD + p] = cs * bp - sn * bq;
+        B[row * PW_LD + q] = sn * bp + cs * bq;
+        const double wp = W[row * PW_LD + p], wq = W[row * PW_LD + q];
+        W[row * PW_LD + p] = cs * wp - sn * wq;
+        W[row * PW_LD + q] = sn * wp + cs * wq;
+      }
+      if (sub == 0) *flag = 1;
+    }
+    __syncthreads();
+    if (!*flag) break;
+  }
+  __syncthreads();
+}
+
+// C = op(X) op(Y) over the wave (entry per lane); tx / ty transpose X / Y
+__device__ inline void wave_mm(const double* X, bool tx, const double* Y, bool ty, int k, double* C, int lane) {
+  for (int e = lane; e < k * k; e += 64) {
+    const int i = e / k, j = e % k;
+    double acc = 0;
+    for (int p = 0; p < k; ++p)
+      acc += (tx ? X[p * PW_LD + i] : X[i * PW_LD + p]) * (ty ? Y[j * PW_LD + p] : Y[p * PW_LD + j]);
+    C[i * PW_LD + j] = acc;
+  }
+  __syncthreads();
+}
+
+// PSD scaling of sides 13..32, one wave per cone (the steps of k_psd_scale)
+__global__ __launch_bounds__(64) void k_psd_scale_wave(SegDev g, const double* __restrict__ s,
+                                                       const double* __restrict__ z, double* __restrict__ hdiag) {
+  __shared__ double Ls[PW_MAT], Lz[PW_MAT], B[PW_MAT], W[PW_MAT], R[PW_MAT], Ri[PW_MAT], lam[PSD_KLARGE],
+      m[PSD_KLARGE];
+  __shared__ int flag;
+  const int lane = threadIdx.x, k = g.k, sd = g.dim;
+  const int64_t N = g.count, kk = (int64_t)k * k;
+  for (int64_t c = blockIdx.x; c < N; c += gridDim.x) {
+    __syncthreads();
+    wave_smat(s + g.base + c * sd, k, Ls, lane);
+    wave_smat(z + g.base + c * sd, k, Lz, lane);
+    wave_chol(Ls, k, lane);
+    wave_chol(Lz, k, lane);
+    wave_mm(Lz, true, Ls, false, k, B, lane);   // B = Lz' Ls
+    wave_jacobi_cols(B, k, W, lane, &flag);     // B W = U diag(lam), V = W
+    if (lane < k) {
+      double acc = 0;
+      for (int r = 0; r < k; ++r) acc += B[r * PW_LD + lane] * B[r * PW_LD + lane];
+      lam[lane] = sqrt(acc);
+    }
+    __syncthreads();
+    // R = Ls V lam^-1/2 ; Rinv = lam^-1/2 U' Lz' with U = B diag(1/lam)
+    for (int e = lane; e < k * k; e += 64) {
+      const int i = e / k, j = e % k;
+      double acc = 0, acc2 = 0;
+      for (int p = 0; p < k; ++p) {
+        acc += Ls[i * PW_LD + p] * W[p * PW_LD + j];
+        acc2 += (B[p * PW_LD + i] / lam[i]) * Lz[j * PW_LD + p];
+      }
+      R[i * PW_LD + j] = acc / sqrt(lam[j]);
+      Ri[i * PW_LD + j] = acc2 / sqrt(lam[i]);
+    }
+    __syncthreads();
+    // M = R R' = Q diag(m) Q': one-sided Jacobi on the columns of R' (in Ls) gives Q (in W)
+    for (int e = lane; e < k * k; e += 64) Ls[(e / k) * PW_LD + e % k] = R[(e % k) * PW_LD + e / k];
+    __syncthreads();
+    wave_jacobi_cols(Ls, k, W, lane, &flag);
+    if (lane < k) {
+      double acc = 0;
+      for (int r = 0; r < k; ++r) acc += Ls[r * PW_LD + lane] * Ls[r * PW_LD + lane];
+      m[lane] = acc;
+    }
+    for (int e = lane; e < k * k; e += 64) {
+      const int i = e / k, j = e % k;
+      g.state[(int64_t)e * N + c] = R[i * PW_LD + j];
+      g.state[(kk + e) * N + c] = Ri[i * PW_LD + j];
+      g.state[(2 * kk + e) * N + c] = W[i * PW_LD + j];
+    }
+    __syncthreads();
+    if (lane < k) {
+      g.state[(3 * kk + lane) * N + c] = lam[lane];
+      g.state[(3 * kk + k + lane) * N + c] = m[lane];
+    }
+    wave_mm(R, false, R, true, k, B, lane);     // Mm = R R'
+    for (int p = lane; p < sd; p += 64) {       // diag of H in svec coordinates
+      int b, a;
+      tri_index(p, b, a);
+      const double v = (a == b) ? sq(B[a * PW_LD + a])
+                                : (B[a * PW_LD + a] * B[b * PW_LD + b] + sq(B[a * PW_LD + b]));
+      hdiag[g.base + c * sd + p] = v;
+    }
+  }
+}
+
+// largest alpha with x + alpha dx PSD (INFINITY if unbounded), as psd_step_one
+__device__ double wave_step_one(const double* x, const double* dx, int k, int lane, double* L, double* D, double* T,
+                                double* rc, double* rs, int* rp, int* rq, int* flag) {
+  __syncthreads();
+  wave_smat(x, k, L, lane);
+  wave_smat(dx, k, D, lane);
+  if (!wave_chol(L, k, lane)) return 0.0;
+  // Y = L^-1 D (lane j owns column j), then Z = L^-1 Y', T = (Z + Z')/2
+  if (lane < k)
+    for (int i = 0; i < k; ++i) {
+      double v = D[i * PW_LD + lane];
+      for (int p = 0; p < i; ++p) v -= L[i * PW_LD + p] * D[p * PW_LD + lane];
+      D[i * PW_LD + lane] = v / L[i * PW_LD + i];
+    }
+  __syncthreads();
+  if (lane < k)
+    for (int i = 0; i < k; ++i) {
+      double v = D[lane * PW_LD + i];
+      for (int p = 0; p < i; ++p) v -= L[i * PW_LD + p] * T[p * PW_LD + lane];
+      T[i * PW_LD + lane] = v / L[i * PW_LD + i];
+    }
+  __syncthreads();
+  for (int e = lane; e < k * k; e += 64) {
+    const int i = e / k, j = e % k;
+    L[i * PW_LD + j] = 0.5 * (T[i * PW_LD + j] + T[j * PW_LD + i]);
+  }
+  const double lmin = wave_min_eig(L, k, lane, rc, rs, rp, rq, flag);
+  return (lmin < 0.0) ? -1.0 / lmin : INFINITY;
+}
+
+// one wave per cone: per-workgroup minimum over its cones, or per cone
+// (capped at amax) when per_cone
+__global__ __launch_bounds__(64) void k_step_psd_wave(SegDev g, const double* __restrict__ s,
+                                                      const double* __restrict__ z, const double* __restrict__ ds,
+                                                      const double* __restrict__ dz, double amax, int per_cone,
+                                                      double* __restrict__ out) {
+  __shared__ double L[PW_MAT], D[PW_MAT], T[PW_MAT], rc[PSD_KLARGE / 2], rs[PSD_KLARGE / 2];
+  __shared__ int rp[PSD_KLARGE / 2], rq[PSD_KLARGE / 2], flag;
+  const int lane = threadIdx.x, sd = g.dim;
+  double best = INFINITY;
+  for (int64_t c = blockIdx.x; c < g.count; c += gridDim.x) {
+    const int64_t o = g.base + c * sd;
+    const double a1 = wave_step_one(s + o, ds + o, g.k, lane, L, D, T, rc, rs, rp, rq, &flag);
+    const double a2 = wave_step_one(z + o, dz + o, g.k, lane, L, D, T, rc, rs, rp, rq, &flag);
+    const double a = fmin(a1, a2);
+    if (per_cone) {
+      if (lane == 0) out[c] = fmin(amax, a);
+    } else {
+      best = fmin(best, a);
+    }
+  }
+  if (!per_cone && lane == 0) out[blockIdx.x] = best;
+}
+
 int cone_step_sym(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz,
                   double* partial, hipStream_t st) {
   if (g.count == 0 || g.kind == HC_CONE_ZERO || g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) return 0;
@@ -1371,9 +1693,8 @@ int cone_step_sym(const SegDev& g, const double* s, const double* z, const doubl
       hipLaunchKernelGGL(k_step_psd<PSD_KSMALL>, dim3(nbp), dim3(Psd<PSD_KSMALL>::TB_STEP), 0, st, g, s, z, ds, dz,
                          partial);
     } else {
-      nbp = std::min(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_STEP), PSD_STEP_GRID);
-      hipLaunchKernelGGL(k_step_psd<PSD_KLARGE>, dim3(nbp), dim3(Psd<PSD_KLARGE>::TB_STEP), 0, st, g, s, z, ds, dz,
-                         partial);
+      nbp = (int)std::min<int64_t>(g.count, PSD_STEP_GRID);
+      hipLaunchKernelGGL(k_step_psd_wave, dim3(nbp), dim3(64), 0, st, g, s, z, ds, dz, INFINITY, 0, partial);
     }
     HC_LAUNCH_CHECK();
     return nbp;
@@ -1715,8 +2036,8 @@ void cone_test_step(const SegDev& g, const double* s, const double* z, const dou
       hipLaunchKernelGGL(k_psd_test_step<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_STEP)),
                          dim3(Psd<PSD_KSMALL>::TB_STEP), 0, st, g, s, z, ds, dz, amax, out);
     else
-      hipLaunchKernelGGL(k_psd_test_step<PSD_KLARGE>, dim3(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_STEP)),
-                         dim3(Psd<PSD_KLARGE>::TB_STEP), 0, st, g, s, z, ds, dz, amax, out);
+      hipLaunchKernelGGL(k_step_psd_wave, dim3((unsigned)std::min<int64_t>(g.count, PSD_STEP_GRID)), dim3(64), 0, st,
+                         g, s, z, ds, dz, amax, 1, out);
     HC_LAUNCH_CHECK();
     return;
   }
