@@ -144,3 +144,24 @@ def test_large_soc_setup_on_host():
         assert L.hc_workspace_bytes(h, C.byref(nb)) == 0 and nb.value > 0
     finally:
         L.hc_destroy(h)
+
+
+def test_cone_size_limits_on_host():
+    """PSD sides 1..32 are accepted (33 is HC_ERR_CONE, as in the paper's
+    limit); second-order cones of any dimension up to 2^24 are accepted."""
+    import scipy.sparse as sp
+    from paper_2412_19027_amd.workloads import PSD, SOC, Problem
+    from tests import problems_small as PS
+    for k in (12, 13, 32):
+        prob, _ = PS.trace_min(0, k=k)
+        info = hipcone.analyze(prob)
+        assert info["n_ordered"] == k * (k + 1) // 2
+    k = 33
+    sd = k * (k + 1) // 2
+    bad = Problem(sd, sd, sp.csr_matrix((sd, sd)), [0.0] * sd, -sp.identity(sd, format="csr"), [0.0] * sd,
+                  [(PSD, k, 0.0)], "psd33")
+    with pytest.raises(hipcone.HipconeError) as e:
+        hipcone.analyze(bad)
+    assert e.value.code == -4   # HC_ERR_CONE
+    prob, _ = PS.soc_ball(0, n=5000)
+    assert hipcone.analyze(prob)["n_ordered"] == 5000
