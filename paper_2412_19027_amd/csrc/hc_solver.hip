@@ -132,6 +132,7 @@ struct hc_solver {
   unsigned long long* dhits = nullptr;
   int* dpd = nullptr;
   double* dscal = nullptr;          // device scalars (FP32 rhs scale)
+  int64_t npart = 4096;             // capacity of the partial buffers (partials of every segment fit at once)
   double* dpart = nullptr;          // reduction partials
   double* hpart = nullptr;          // pinned host copy
   unsigned long long *dmask = nullptr, *hmask = nullptr;
@@ -1043,6 +1044,25 @@ struct Red {
   }
 };
 
+// max(|x|_inf, |y|_inf) for vectors of lengths n and m, one host round trip
+double maxabs2(hc_solver* S, const double* x, int64_t n, const double* y, int64_t m) {
+  RedOps ox{}, oy{};
+  ox.nops = oy.nops = 1;
+  ox.op[0] = RedOp{RED_MAX_MUL, x, nullptr, 0.0, nullptr};
+  oy.op[0] = RedOp{RED_MAX_MUL, y, nullptr, 0.0, nullptr};
+  const int na = n > 0 ? reduce_launch(n, ox, S->dpart, S->stream) : 0;
+  const int nb = m > 0 ? reduce_launch(m, oy, S->dpart + na, S->stream) : 0;
+  if (na + nb == 0) return 0.0;
+  HC_HIP(hipMemcpyAsync(S->hpart, S->dpart, (size_t)(na + nb) * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+  HC_HIP(hipStreamSynchronize(S->stream));
+  double acc = 0.0;
+  for (int i = 0; i < na + nb; ++i) {
+    const double v = S->hpart[i];
+    acc = (std::isnan(v) || std::isnan(acc)) ? NAN : std::max(acc, v);
+  }
+  return acc;
+}
+
 void A_mul(hc_solver* S, const double* x, double* y, double alpha, double beta) {
   spmv(S->dA, x, y, alpha, beta, S->stream);
   // with leaf blocks the dense rows are stored on the tail columns only
@@ -1242,12 +1262,7 @@ int64_t kkt_solve_once(hc_solver* S, const double* r1, const double* r2, double*
   hipStream_t st = S->stream;
   const int64_t n = S->n, m = S->m;
   double nb;
-  {
-    Red a(S, n), b(S, m);
-    a.maxabs(r1);
-    b.maxabs(r2);
-    nb = std::max(a.run()[0], b.run()[0]);
-  }
+  nb = maxabs2(S, r1, n, r2, m);
   double* x = S->irx;
   double* z = S->irz;
   double* xn = S->irxn;
@@ -1272,13 +1287,7 @@ int64_t kkt_solve_once(hc_solver* S, const double* r1, const double* r2, double*
     vaxpby(m, -1.0, S->t2, 1.0, S->kz, st);         // kz = A xn - H zn
     vlin3(n, 1.0, r1, -1.0, S->kx, 0.0, nullptr, S->kx, st);
     vlin3(m, 1.0, r2, -1.0, S->kz, 0.0, nullptr, S->kz, st);
-    double rn;
-    {
-      Red a(S, n), b(S, m);
-      a.maxabs(S->kx);
-      b.maxabs(S->kz);
-      rn = std::max(a.run()[0], b.run()[0]);
-    }
+    const double rn = maxabs2(S, S->kx, n, S->kz, m);
     if (rn < best || !have_best) {
       if (rn < best) {
         vcopy(n, xn, S->irbx, st);
@@ -1423,12 +1432,14 @@ double step_length(hc_solver* S, const Step& d, bool combined) {
   double a = 1.0;
   if (d.dtau < 0) a = std::min(a, -S->tau / d.dtau);
   if (d.dkappa < 0) a = std::min(a, -S->kappa / d.dkappa);
-  for (auto& g : S->sdev) {
-    const int nb = cone_step_sym(g, S->s, S->z, d.ds, d.dz, S->dpart, st);
-    if (!nb) continue;
-    HC_HIP(hipMemcpyAsync(S->hpart, S->dpart, nb * sizeof(double), hipMemcpyDeviceToHost, st));
-    HC_HIP(hipStreamSynchronize(st));
-    for (int i = 0; i < nb; ++i) a = std::min(a, S->hpart[i]);
+  {   // every symmetric segment's partial minima, then one host round trip
+    int64_t off = 0;
+    for (auto& g : S->sdev) off += cone_step_sym(g, S->s, S->z, d.ds, d.dz, S->dpart + off, st);
+    if (off) {
+      HC_HIP(hipMemcpyAsync(S->hpart, S->dpart, off * sizeof(double), hipMemcpyDeviceToHost, st));
+      HC_HIP(hipStreamSynchronize(st));
+      for (int64_t i = 0; i < off; ++i) a = std::min(a, S->hpart[i]);
+    }
   }
   if (!S->has_nonsym) return a;
   // mu(alpha) = (c0 + c1 a + c2 a^2) / (nu + 1)
@@ -1733,8 +1744,17 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->dhits = buf.take<unsigned long long>(1);
   S->dpd = buf.take<int>(2);
   S->dscal = buf.take<double>(8);
-  S->dpart = buf.take<double>(4096);
-  S->dmask = buf.take<unsigned long long>(4096);
+  S->npart = 4096;
+  for (const Segment& sg : S->segs) {
+    SegDev d{};
+    d.kind = sg.kind;
+    d.dim = sg.dim;
+    d.k = sg.k;
+    d.count = sg.count;
+    S->npart += cone_blocks(d) + 2048;   // a step or max kernel writes at most this many
+  }
+  S->dpart = buf.take<double>(S->npart);
+  S->dmask = buf.take<unsigned long long>(S->npart);
   const int64_t L = std::max(n, m);
   double** vecs[] = {&S->x, &S->s, &S->z, &S->Px, &S->Ax, &S->Atz, &S->rdv, &S->rpv, &S->x2, &S->z2, &S->x1,
                      &S->z1, &S->dx, &S->dz, &S->dsv, &S->dsrhs, &S->dxa, &S->dza, &S->dsa, &S->r1, &S->r2,
@@ -1780,8 +1800,8 @@ void bind(hc_solver* S, const hc_device* dev) {
   S->mem_bytes = need;
   hipStream_t st = S->stream;
   alloc_all(S, buf, st);
-  HC_HIP(hipHostMalloc((void**)&S->hpart, 4096 * sizeof(double), hipHostMallocDefault));
-  HC_HIP(hipHostMalloc((void**)&S->hmask, 4096 * sizeof(unsigned long long), hipHostMallocDefault));
+  HC_HIP(hipHostMalloc((void**)&S->hpart, S->npart * sizeof(double), hipHostMallocDefault));
+  HC_HIP(hipHostMalloc((void**)&S->hmask, S->npart * sizeof(unsigned long long), hipHostMallocDefault));
   HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), st));
   if (S->K1 + S->K2 > 0) {   // zero padding rows of the dense-row operand, zero rank-2 rows
     HC_HIP(hipMemsetAsync(S->dBd, 0, (size_t)(S->K1 + S->K2) * S->nt * sizeof(double), st));
