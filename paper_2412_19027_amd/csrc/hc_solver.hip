@@ -132,7 +132,7 @@ struct hc_solver {
   unsigned long long* dhits = nullptr;
   int* dpd = nullptr;
   double* dscal = nullptr;          // device scalars (FP32 rhs scale)
-  int64_t npart = 4096;             // capacity of the partial buffers (partials of every segment fit at once)
+  int64_t npart = 0;                // capacity of the partial buffers (two reductions, or every segment's step partials)
   double* dpart = nullptr;          // reduction partials
   double* hpart = nullptr;          // pinned host copy
   unsigned long long *dmask = nullptr, *hmask = nullptr;
@@ -1024,17 +1024,21 @@ struct Red {
     ops.op[ops.nops] = RedOp{divide ? RED_MAX_DIV : RED_MAX_MUL, x, y, yc, w};
     return ops.nops++;
   }
-  std::vector<double> run() {
+  // launch into dpart + off; returns the partials it will write
+  int64_t launch(int64_t off) {
+    if (n == 0 || ops.nops == 0) return 0;
+    nblk = reduce_launch(n, ops, S->dpart + off, S->stream);
+    base = off;
+    return (int64_t)nblk * ops.nops;
+  }
+  // combine this reduction's partials (already copied to hpart)
+  std::vector<double> collect() const {
     std::vector<double> out(ops.nops, 0.0);
     if (n == 0 || ops.nops == 0) return out;
-    const int nb = reduce_launch(n, ops, S->dpart, S->stream);
-    HC_HIP(hipMemcpyAsync(S->hpart, S->dpart, (size_t)nb * ops.nops * sizeof(double), hipMemcpyDeviceToHost,
-                          S->stream));
-    HC_HIP(hipStreamSynchronize(S->stream));
     for (int o = 0; o < ops.nops; ++o) {
       double acc = 0.0;
-      for (int bk = 0; bk < nb; ++bk) {
-        const double v = S->hpart[(size_t)bk * ops.nops + o];
+      for (int bk = 0; bk < nblk; ++bk) {
+        const double v = S->hpart[base + (size_t)bk * ops.nops + o];
         if (ops.op[o].kind == RED_DOT) acc += v;
         else acc = (std::isnan(v) || std::isnan(acc)) ? NAN : std::max(acc, v);
       }
@@ -1042,7 +1046,29 @@ struct Red {
     }
     return out;
   }
+  std::vector<double> run() {
+    const int64_t cnt = launch(0);
+    if (cnt) {
+      HC_HIP(hipMemcpyAsync(S->hpart, S->dpart, cnt * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+      HC_HIP(hipStreamSynchronize(S->stream));
+    }
+    return collect();
+  }
+  int nblk = 0;
+  int64_t base = 0;
 };
+
+// two reductions (over lengths n and m) with one host round trip
+void run_pair(Red& a, Red& b, std::vector<double>& va, std::vector<double>& vb) {
+  const int64_t ca = a.launch(0);
+  const int64_t cb = b.launch(ca);
+  if (ca + cb) {
+    HC_HIP(hipMemcpyAsync(a.S->hpart, a.S->dpart, (ca + cb) * sizeof(double), hipMemcpyDeviceToHost, a.S->stream));
+    HC_HIP(hipStreamSynchronize(a.S->stream));
+  }
+  va = a.collect();
+  vb = b.collect();
+}
 
 // max(|x|_inf, |y|_inf) for vectors of lengths n and m, one host round trip
 double maxabs2(hc_solver* S, const double* x, int64_t n, const double* y, int64_t m) {
@@ -1346,8 +1372,8 @@ Resid residuals(hc_solver* S) {
   const int i_bz = rm.dot(S->db, S->z), i_sz = rm.dot(S->s, S->z), i_rp = rm.maxabs(S->rpv, S->dE, true),
             i_s = rm.maxabs(S->s, S->dE, true), i_z = rm.maxabs(S->z, S->dE, false),
             i_axs = rm.maxabs(S->Ax, S->dE, true, S->s, 1.0);
-  const auto a = rn.run();
-  const auto b = rm.run();
+  std::vector<double> a, b;
+  run_pair(rn, rm, a, b);
   Resid R;
   R.xPx = a[i_xPx]; R.qx = a[i_qx]; R.rd_n = a[i_rd]; R.x_n = a[i_x]; R.atz_n = a[i_atz]; R.px_n = a[i_px];
   R.bz = b[i_bz]; R.sz = b[i_sz]; R.rp_n = b[i_rp]; R.s_n = b[i_s]; R.z_n = b[i_z]; R.axs_n = b[i_axs];
@@ -1401,8 +1427,8 @@ Dir direction(hc_solver* S, const double* r1, const double* r2, double dtau_rhs,
   vlin3(n, 2.0 * ti, S->Px, 1.0, S->dq, 0.0, nullptr, S->t2, st);
   const int a1 = rn.dot(S->t2, S->x1), a2 = rn.dot(S->t2, S->x2);
   const int b1 = rm.dot(S->db, S->z1), b2 = rm.dot(S->db, S->z2);
-  const auto va = rn.run();
-  const auto vb = rm.run();
+  std::vector<double> va, vb;
+  run_pair(rn, rm, va, vb);
   Dir d;
   const double xPx = S->xPx_cache;
   const double num = dtau_rhs - dkap_rhs / S->tau + va[a1] + vb[b1];
@@ -1744,7 +1770,7 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->dhits = buf.take<unsigned long long>(1);
   S->dpd = buf.take<int>(2);
   S->dscal = buf.take<double>(8);
-  S->npart = 4096;
+  S->npart = 2 * 512 * MAX_RED_OPS;   // two reductions read back together
   for (const Segment& sg : S->segs) {
     SegDev d{};
     d.kind = sg.kind;
