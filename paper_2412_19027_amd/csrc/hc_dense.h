@@ -46,10 +46,11 @@ template <typename T>
 void dense_block_inverses(const T* L, int64_t n, int64_t ld, const T* Linv, T* X, T* XT, hipStream_t st);
 int64_t inv256_elems(int64_t n);
 // X = L^-T L^-1 B for nrhs <= 4 right-hand sides (column-major, leading dim
-// n); B and Y are overwritten (Y receives the forward result).
+// n); B and Y are overwritten (Y receives the forward result).  With the
+// factorisation's envelope `last` the updates skip the zero blocks.
 template <typename T>
 void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT256, T* B, T* Y, T* X, int nrhs,
-                 hipStream_t st);
+                 hipStream_t st, const int64_t* last = nullptr);
 // C[i, j] += alpha * sum_k A[i, k] B[j, k] (column-major operands); with
 // `lower`, tiles strictly above the diagonal of the global matrix (C[0,0] at
 // global (gr, gc)) are skipped.

@@ -1000,7 +1000,8 @@ __global__ __launch_bounds__(1024) void k_trsv_fwd_update(const T* __restrict__ 
 constexpr int BWD_COLS = 4;
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_trsv_bwd_update(const T* __restrict__ L, int64_t ld, int64_t c, int64_t n,
-                                                         T* __restrict__ Yv, const T* __restrict__ X, int nrhs) {
+                                                         int64_t j_begin, T* __restrict__ Yv, const T* __restrict__ X,
+                                                         int nrhs) {
   __shared__ T xb[SB][NR];
   const int tid = threadIdx.x;
   const int cb = (int)std::min<int64_t>(SB, n - c);
@@ -1010,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_update(const T* __restrict__ L
   }
   __syncthreads();
   const int lane = tid & 63;
-  const int64_t j0 = ((int64_t)blockIdx.x * 4 + (tid >> 6)) * BWD_COLS;
+  const int64_t j0 = j_begin + ((int64_t)blockIdx.x * 4 + (tid >> 6)) * BWD_COLS;
   T acc[BWD_COLS][NR] = {};
 #pragma unroll
   for (int cc = 0; cc < BWD_COLS; ++cc) {
@@ -1040,28 +1041,35 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_update(const T* __restrict__ L
           if (r < nrhs) Yv[(j0 + cc) + r * n] -= acc[cc][r];
 }
 
+// With an envelope (`last`, see dense_cholesky) the forward updates stop at
+// the rows a block's columns reach and the backward updates start at the
+// first column its rows reach: entries outside are zero.
 template <typename T, int NR>
 static void dense_solve_nr(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT256, T* B, T* Y, T* X,
-                           int nrhs, hipStream_t st) {
+                           int nrhs, const int64_t* last, hipStream_t st) {
   for (int64_t c = 0; c < n; c += SB) {
     const T* Xi = X256 + (c / SB) * SB * SB;
     hipLaunchKernelGGL((k_trsv_diag<T, NR>), dim3(SB / DIAG_ROWS), dim3(256), 0, st, Xi, c, n, (const T*)B, Y, nrhs);
     HC_LAUNCH_CHECK();
-    const int64_t below = n - std::min<int64_t>(n, c + SB);
+    const int64_t cend = std::min<int64_t>(n, c + SB);
+    const int64_t below = rows_below(last, n, cend - 1) - cend;
     if (below > 0) {
       hipLaunchKernelGGL((k_trsv_fwd_update<T, NR>), dim3((unsigned)ceil_div(below, 64)), dim3(1024), 0, st, L, ld, c,
                          n, B, (const T*)Y, nrhs);
       HC_LAUNCH_CHECK();
     }
   }
-  const int64_t last = ((n - 1) / SB) * SB;
-  for (int64_t c = last; c >= 0; c -= SB) {
+  const int64_t lastb = ((n - 1) / SB) * SB;
+  for (int64_t c = lastb; c >= 0; c -= SB) {
     const T* XTi = XT256 + (c / SB) * SB * SB;
     hipLaunchKernelGGL((k_trsv_diag<T, NR>), dim3(SB / DIAG_ROWS), dim3(256), 0, st, XTi, c, n, (const T*)Y, X, nrhs);
     HC_LAUNCH_CHECK();
-    if (c > 0) {
-      hipLaunchKernelGGL((k_trsv_bwd_update<T, NR>), dim3((unsigned)ceil_div(c, 4 * BWD_COLS)), dim3(256), 0, st, L, ld,
-                         c, n, Y, (const T*)X, nrhs);
+    // first column with a nonzero in rows >= c (last is non-decreasing)
+    int64_t jb = 0;
+    if (last) jb = (std::upper_bound(last, last + c, c) - last) / (4 * BWD_COLS) * (4 * BWD_COLS);
+    if (c > jb) {
+      hipLaunchKernelGGL((k_trsv_bwd_update<T, NR>), dim3((unsigned)ceil_div(c - jb, 4 * BWD_COLS)), dim3(256), 0, st,
+                         L, ld, c, n, jb, Y, (const T*)X, nrhs);
       HC_LAUNCH_CHECK();
     }
   }
@@ -1071,10 +1079,10 @@ static void dense_solve_nr(const T* L, int64_t n, int64_t ld, const T* X256, con
 // up to MAXRHS
 template <typename T>
 void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT256, T* B, T* Y, T* X, int nrhs,
-                 hipStream_t st) {
+                 hipStream_t st, const int64_t* last) {
   if (n <= 0) return;
-  if (nrhs == 1) dense_solve_nr<T, 1>(L, n, ld, X256, XT256, B, Y, X, nrhs, st);
-  else dense_solve_nr<T, MAXRHS>(L, n, ld, X256, XT256, B, Y, X, nrhs, st);
+  if (nrhs == 1) dense_solve_nr<T, 1>(L, n, ld, X256, XT256, B, Y, X, nrhs, last, st);
+  else dense_solve_nr<T, MAXRHS>(L, n, ld, X256, XT256, B, Y, X, nrhs, last, st);
 }
 
 template void dense_cholesky<double>(double*, int64_t, int64_t, double*, double, double, unsigned long long*,
@@ -1086,9 +1094,9 @@ template void gemm_nt<double>(double*, int64_t, const double*, int64_t, const do
 template void gemm_nt<float>(float*, int64_t, const float*, int64_t, const float*, int64_t, int64_t, int64_t,
                              int64_t, float, bool, int64_t, int64_t, hipStream_t);
 template void dense_solve<double>(const double*, int64_t, int64_t, const double*, const double*, double*, double*,
-                                  double*, int, hipStream_t);
+                                  double*, int, hipStream_t, const int64_t*);
 template void dense_solve<float>(const float*, int64_t, int64_t, const float*, const float*, float*, float*, float*,
-                                 int, hipStream_t);
+                                 int, hipStream_t, const int64_t*);
 template void dense_block_inverses<double>(const double*, int64_t, int64_t, const double*, double*, double*,
                                            hipStream_t);
 template void dense_block_inverses<float>(const float*, int64_t, int64_t, const float*, float*, float*, hipStream_t);

@@ -155,7 +155,8 @@ __global__ __launch_bounds__(LS_TB) void k_lsoc_ds(SegDev g, const double* __res
     const LsView v{g, c};
     const double w0 = v.wb(0), eta = v.eta(), l0 = v.lam(0);
     const double a0 = dsa[v.row(0)], b0 = dza[v.row(0)];
-    // W^-1 J-reflected dsa and W dza need wbar_1'(J dsa)_1 and wbar_1' dza_1
+    // W^-T dsa (= W^-1 dsa, W symmetric) needs wbar_1'(J dsa)_1 = -wbar_1'dsa_1,
+    // W dza needs wbar_1'dza_1
     double t[2] = {0.0, 0.0};
     for (int j = 1 + threadIdx.x; j < d; j += LS_TB) {
       const double wj = v.wb(j);

@@ -1246,11 +1246,12 @@ void schur_solve(hc_solver* S, const double* u, double* x) {
     const int nb = reduce_launch(nt, ops, S->dpart, st);
     combine_max(nb, S->dpart, S->dscal, st);
     to_f32(nt, ut, S->dscal, S->sb32, st);
-    dense_solve<float>(S->dS32, nt, S->ld, S->dX256f, S->dXT256f, S->sb32, S->sy32, S->sx32, 1, st);
+    dense_solve<float>(S->dS32, nt, S->ld, S->dX256f, S->dXT256f, S->sb32, S->sy32, S->sx32, 1, st,
+                       S->tail_last.data());
     from_f32(nt, S->sx32, S->dscal, xt, st);
   } else {
     vcopy(nt, ut, S->sb, st);
-    dense_solve<double>(S->dS, nt, S->ld, S->dX256, S->dXT256, S->sb, S->sy, xt, 1, st);
+    dense_solve<double>(S->dS, nt, S->ld, S->dX256, S->dXT256, S->sb, S->sy, xt, 1, st, S->tail_last.data());
   }
   if (S->leaves) {
     leaf_backward(S->cm, S->xT, x, st);

@@ -308,7 +308,7 @@ int32_t hc_test_dense_chol_solve_env(int32_t precision, int64_t n, int64_t ld, d
         const double h1 = 1.0;
         HC_HIP(hipMemcpyAsync(one, &h1, 8, hipMemcpyHostToDevice, st));
         to_f32((int64_t)n * nrhs, B, one, b32, st);
-        dense_solve<float>(A32, n, ld, X32, XT32, b32, y32, x32, nrhs, st);
+        dense_solve<float>(A32, n, ld, X32, XT32, b32, y32, x32, nrhs, st, last);
         from_f32((int64_t)n * nrhs, x32, one, B, st);
       } else {
         double* Li = (double*)al(linv_elems(n) * 8);
@@ -318,7 +318,7 @@ int32_t hc_test_dense_chol_solve_env(int32_t precision, int64_t n, int64_t ld, d
         double* X64 = (double*)al(inv256_elems(n) * 8);
         double* XT64 = (double*)al(inv256_elems(n) * 8);
         dense_block_inverses<double>(A, n, ld, Li, X64, XT64, st);
-        dense_solve<double>(A, n, ld, X64, XT64, B, y, x, nrhs, st);
+        dense_solve<double>(A, n, ld, X64, XT64, B, y, x, nrhs, st, last);
         HC_HIP(hipMemcpyAsync(B, x, (size_t)n * nrhs * 8, hipMemcpyDeviceToDevice, st));
       }
       unsigned long long h = 0;

@@ -25,6 +25,10 @@ def same_structure(a, b):
 PAIRS = [
     ("tiny_lp", lambda s: W.tiny_lp(s)),
     ("mpc", lambda s: W.mpc_socp(s, 7, T=40, nx=8, nu=3)),
+    # SOCs of dimension 45 (rank-2 Schur rows) with new risk aversion,
+    # transaction cost and inflow: new q and b on the same structure
+    ("multistage", lambda s: W.multistage_portfolio(0, n=40, k=4, T=3, gamma=1.0 + s, cost=0.01 * (1 + s),
+                                                    inflow=0.1 - 0.05 * s)),
 ]
 
 
