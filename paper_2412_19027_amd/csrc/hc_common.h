@@ -85,6 +85,11 @@ struct Csr {          // device CSR, int32 indices
   int32_t* col = nullptr;
   double* val = nullptr;
   int32_t lanes = 1;  // lanes per row used by spmv
+  // rows longer than long_nnz entries (a few long rows among short ones) are
+  // left to a second kernel with one wave per row
+  int32_t long_nnz = 0x7fffffff;
+  int32_t nlong = 0;
+  int32_t* longrows = nullptr;
 };
 
 // y = alpha * A x + beta * y

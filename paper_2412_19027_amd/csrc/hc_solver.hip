@@ -1004,6 +1004,13 @@ Csr upload_csr(Buf& buf, const HostCsr& h, hipStream_t st) {
   c.col = upload(buf, h.ci, st);
   c.val = upload(buf, h.v, st);
   c.lanes = choose_lanes(h.nrows ? (double)c.nnz / (double)h.nrows : 0.0);
+  // rows of more than 32 x lanes entries go to one wave each
+  c.long_nnz = 32 * c.lanes;
+  std::vector<int32_t> lr;
+  for (int64_t r = 0; r < h.nrows; ++r)
+    if (h.rp[r + 1] - h.rp[r] > c.long_nnz) lr.push_back((int32_t)r);
+  c.nlong = (int32_t)lr.size();
+  c.longrows = upload(buf, lr, st);
   return c;
 }
 

@@ -17,31 +17,55 @@ template <int LPR>
 __global__ __launch_bounds__(256) void k_spmv(int32_t nrows, const int32_t* __restrict__ rp,
                                               const int32_t* __restrict__ ci, const double* __restrict__ v,
                                               const double* __restrict__ x, double* __restrict__ y, double alpha,
-                                              double beta) {
+                                              double beta, int32_t long_nnz) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t row = t / LPR;
   const int sub = (int)(t % LPR);
   double acc = 0.0;
+  bool mine = false;   // rows above long_nnz entries belong to k_spmv_long
   if (row < nrows) {
     const int32_t b = rp[row], e = rp[row + 1];
-    for (int32_t p = b + sub; p < e; p += LPR) acc += v[p] * x[ci[p]];
+    mine = (e - b) <= long_nnz;
+    if (mine)
+      for (int32_t p = b + sub; p < e; p += LPR) acc += v[p] * x[ci[p]];
   }
 #pragma unroll
   for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (row < nrows && sub == 0) y[row] = alpha * acc + (beta == 0.0 ? 0.0 : beta * y[row]);
+  if (mine && sub == 0) y[row] = alpha * acc + (beta == 0.0 ? 0.0 : beta * y[row]);
+}
+
+// the long rows, one wave each
+__global__ __launch_bounds__(256) void k_spmv_long(int32_t nlong, const int32_t* __restrict__ rows,
+                                                   const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                   const double* __restrict__ v, const double* __restrict__ x,
+                                                   double* __restrict__ y, double alpha, double beta) {
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const int lane = threadIdx.x & 63;
+  if (w >= nlong) return;
+  const int32_t row = rows[w], b = rp[row], e = rp[row + 1];
+  double acc = 0.0;
+  for (int32_t p = b + lane; p < e; p += 64) acc += v[p] * x[ci[p]];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) y[row] = alpha * acc + (beta == 0.0 ? 0.0 : beta * y[row]);
 }
 
 void spmv(const Csr& A, const double* x, double* y, double alpha, double beta, hipStream_t st) {
   if (A.nrows == 0) return;
   const int64_t threads = (int64_t)A.nrows * A.lanes;
   const unsigned grid = (unsigned)ceil_div(threads, 256);
+  const int32_t ln = A.long_nnz;
   switch (A.lanes) {
-    case 1: hipLaunchKernelGGL(k_spmv<1>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta); break;
-    case 4: hipLaunchKernelGGL(k_spmv<4>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta); break;
-    case 16: hipLaunchKernelGGL(k_spmv<16>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta); break;
-    default: hipLaunchKernelGGL(k_spmv<64>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta); break;
+    case 1: hipLaunchKernelGGL(k_spmv<1>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta, ln); break;
+    case 4: hipLaunchKernelGGL(k_spmv<4>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta, ln); break;
+    case 16: hipLaunchKernelGGL(k_spmv<16>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta, ln); break;
+    default: hipLaunchKernelGGL(k_spmv<64>, dim3(grid), dim3(256), 0, st, A.nrows, A.rowptr, A.col, A.val, x, y, alpha, beta, ln); break;
   }
   HC_LAUNCH_CHECK();
+  if (A.nlong > 0) {
+    hipLaunchKernelGGL(k_spmv_long, dim3((unsigned)ceil_div((int64_t)A.nlong * 64, 256)), dim3(256), 0, st, A.nlong,
+                       A.longrows, A.rowptr, A.col, A.val, x, y, alpha, beta);
+    HC_LAUNCH_CHECK();
+  }
 }
 
 int choose_lanes(double mean_nnz) {
