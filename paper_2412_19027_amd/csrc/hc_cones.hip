@@ -4,9 +4,12 @@
 // Mapping: zero and nonnegative rows are plain vector ops (one lane per row);
 // every other family runs one lane per cone with the cone's components stored
 // component-major (row base + j*count + i), so each component load of a wave is
-// one coalesced 512-byte access.  PSD cones (k <= 12 here) run one lane per
-// cone for the factorisations and one lane per (cone, svec row) for the
-// explicit (H + delta I)^-1 block.
+// one coalesced 512-byte access.  Second-order cones above 16 rows run one
+// workgroup per cone (hc_soc.hip).  PSD cones of side k <= 12 run one lane per
+// cone for the factorisations; sides 13..32 one wave per cone for the
+// scaling, step and spectral apply (parallel Jacobi) and one lane per cone for
+// the d_s correction; the explicit (H + delta I)^-1 block takes one lane per
+// (cone, svec row).
 //
 // Scalings are kept in spectral form H = V diag(lam) V': near the optimum
 // cond(H) exceeds 1/eps, and applying H or (H + delta I)^-1 through the
@@ -560,6 +563,8 @@ constexpr int odd_stride(int n) { return n | 1; }
 // Two instantiations: KM = 12 (sides up to 12, eight cones per workgroup)
 // and KM = 32 (sides 13..32, the paper's limit; a 32 x 32 FP64 matrix is 8 KB,
 // so two to four cones per workgroup keep the slices within ~150 KB of LDS).
+// At KM = 32 only the d_s, M-block and initial-shift kernels use this per-lane
+// form; scaling, step and apply run the one-wave-per-cone kernels below.
 template <int KM> struct Psd {
   static constexpr int MAT = KM * KM;
   static constexpr int SVEC = KM * (KM + 1) / 2;
