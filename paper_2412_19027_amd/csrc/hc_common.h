@@ -98,9 +98,11 @@ void spmv(const Csr& A, const double* x, double* y, double alpha, double beta, h
 // column j is variable cols[j], or j when cols is null)
 void dense_rows_gemv(int nd, int64_t n, const double* Ad, const int32_t* rows, const int32_t* cols, const double* x,
                      double* y, double alpha, hipStream_t st);
-// y[cols[j]] += alpha * sum_r Ad[r, j] v[rows[r]]  (cols null: y[j])
+// y[cols[j]] += alpha * sum_r Ad[r, j] v[rows[r]]  (cols null: y[j]); part is
+// scratch of dense_rows_t_parts(nd) * n doubles (per-chunk partial sums)
 void dense_rows_gemv_t(int nd, int64_t n, const double* Ad, const int32_t* rows, const int32_t* cols,
-                       const double* v, double* y, double alpha, hipStream_t st);
+                       const double* v, double* y, double alpha, double* part, hipStream_t st);
+int64_t dense_rows_t_parts(int nd);
 
 // generic fused vector kernels
 void vaxpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);   // y = a x + b y

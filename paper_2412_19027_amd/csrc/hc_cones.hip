@@ -5,11 +5,10 @@
 // every other family runs one lane per cone with the cone's components stored
 // component-major (row base + j*count + i), so each component load of a wave is
 // one coalesced 512-byte access.  Second-order cones above 16 rows run one
-// workgroup per cone (hc_soc.hip).  PSD cones of side k <= 12 run one lane per
-// cone for the factorisations; sides 13..32 one wave per cone for the
-// scaling, step and spectral apply (parallel Jacobi) and one lane per cone for
-// the d_s correction; the explicit (H + delta I)^-1 block takes one lane per
-// (cone, svec row).
+// workgroup per cone (hc_soc.hip).  PSD cones (sides up to 32) run one wave
+// per cone for the scaling, step and spectral apply (parallel Jacobi), one
+// lane per cone for the d_s correction, and one lane per (cone, svec row) for
+// the explicit (H + delta I)^-1 block.
 //
 // Scalings are kept in spectral form H = V diag(lam) V': near the optimum
 // cond(H) exceeds 1/eps, and applying H or (H + delta I)^-1 through the
@@ -463,57 +462,6 @@ __device__ inline void psd_svec(const double* X, int k, double* v) {
   for (int j = 0; j < k; ++j)
     for (int i = 0; i <= j; ++i, ++p) v[p] = X[i * KM + j] * ((i == j) ? 1.0 : 1.41421356237309504880);
 }
-// lower Cholesky in place (row-major), returns false if not positive definite
-template <int KM>
-__device__ bool psd_chol(double* A, int k) {
-  for (int j = 0; j < k; ++j) {
-    double d = A[j * KM + j];
-    for (int p = 0; p < j; ++p) d -= A[j * KM + p] * A[j * KM + p];
-    if (!(d > 0.0)) return false;
-    d = sqrt(d);
-    A[j * KM + j] = d;
-    for (int i = j + 1; i < k; ++i) {
-      double v = A[i * KM + j];
-      for (int p = 0; p < j; ++p) v -= A[i * KM + p] * A[j * KM + p];
-      A[i * KM + j] = v / d;
-    }
-    for (int i = 0; i < j; ++i) A[i * KM + j] = 0.0;
-  }
-  return true;
-}
-// one-sided Jacobi (Hestenes) on the columns of B (k x k): on return the
-// columns are orthogonal and W accumulates B_in W = B_out.
-template <int KM>
-__device__ void psd_jacobi_cols(double* B, int k, double* W) {
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) W[i * KM + j] = (i == j) ? 1.0 : 0.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    bool rot = false;
-    for (int p = 0; p < k - 1; ++p)
-      for (int q = p + 1; q < k; ++q) {
-        double a = 0, b = 0, g = 0;
-        for (int r = 0; r < k; ++r) {
-          a += B[r * KM + p] * B[r * KM + p];
-          b += B[r * KM + q] * B[r * KM + q];
-          g += B[r * KM + p] * B[r * KM + q];
-        }
-        if (g == 0.0 || fabs(g) <= 1e-16 * sqrt(a * b)) continue;
-        rot = true;
-        const double zeta = (b - a) / (2.0 * g);
-        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        for (int r = 0; r < k; ++r) {
-          const double bp = B[r * KM + p], bq = B[r * KM + q];
-          B[r * KM + p] = cs * bp - sn * bq;
-          B[r * KM + q] = sn * bp + cs * bq;
-          const double wp = W[r * KM + p], wq = W[r * KM + q];
-          W[r * KM + p] = cs * wp - sn * wq;
-          W[r * KM + q] = sn * wp + cs * wq;
-        }
-      }
-    if (!rot) break;
-  }
-}
 // cyclic Jacobi eigenvalues of a symmetric matrix (destroys A); returns lambda_min
 template <int KM>
 __device__ double psd_min_eig(double* A, int k) {
@@ -560,108 +508,25 @@ __device__ double psd_min_eig(double* A, int k) {
 // are odd so the lanes of a block fall on distinct banks.
 // ---------------------------------------------------------------------------
 constexpr int odd_stride(int n) { return n | 1; }
-// Two instantiations: KM = 12 (sides up to 12, eight cones per workgroup)
-// and KM = 32 (sides 13..32, the paper's limit; a 32 x 32 FP64 matrix is 8 KB,
-// so two to four cones per workgroup keep the slices within ~150 KB of LDS).
-// At KM = 32 only the d_s, M-block and initial-shift kernels use this per-lane
-// form; scaling, step and apply run the one-wave-per-cone kernels below.
+// The per-lane PSD kernels (d_s correction, initial-point shift) come in two
+// instantiations: KM = 12 (sides up to 12, eight cones per workgroup) and
+// KM = 32 (sides 13..32, the paper's limit; a 32 x 32 FP64 matrix is 8 KB, so
+// two to four cones per workgroup keep the slices within ~150 KB of LDS).
+// Scaling, step and spectral apply run one wave per cone for every side
+// (the wave kernels below); the M block one lane per (cone, svec row).
 template <int KM> struct Psd {
   static constexpr int MAT = KM * KM;
   static constexpr int SVEC = KM * (KM + 1) / 2;
-  static constexpr int WS_SCALE = odd_stride(9 * MAT + 2 * KM);
-  static constexpr int WS_APPLY = odd_stride(4 * MAT + KM + SVEC);
   static constexpr int WS_DS = odd_stride(8 * MAT + KM);
   static constexpr int WS_STEP = odd_stride(3 * MAT);
-  static constexpr int TB_SCALE = KM <= 12 ? 8 : 2;   // lanes (cones) per workgroup
-  static constexpr int TB_APPLY = KM <= 12 ? 8 : 4;
-  static constexpr int TB_DS = KM <= 12 ? 8 : 2;
+  static constexpr int TB_DS = KM <= 12 ? 8 : 2;     // lanes (cones) per workgroup
   static constexpr int TB_STEP = KM <= 12 ? 8 : 4;
   static int blocks(int64_t count, int tb) { return (int)std::max<int64_t>(1, ceil_div(count, tb)); }
 };
 constexpr int PSD_KSMALL = 12, PSD_KLARGE = 32;
 
-// PSD state fields: R (k*k row-major) | Rinv | Q | lambda (k) | m (k)
-template <int KM>
-__global__ __launch_bounds__(Psd<KM>::TB_SCALE) void k_psd_scale(SegDev g, const double* __restrict__ s,
-                                                      const double* __restrict__ z, double* __restrict__ hdiag) {
-  __shared__ double wsall[Psd<KM>::TB_SCALE * Psd<KM>::WS_SCALE];
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.count) return;
-  const int k = g.k, sd = g.dim;
-  const int64_t N = g.count;
-  const double* sc = s + g.base + c * sd;
-  const double* zc = z + g.base + c * sd;
-  double* ws = wsall + threadIdx.x * Psd<KM>::WS_SCALE;
-  double *Ls = ws, *Lz = ws + Psd<KM>::MAT, *B = ws + 2 * Psd<KM>::MAT, *W = ws + 3 * Psd<KM>::MAT, *R = ws + 4 * Psd<KM>::MAT,
-         *Ri = ws + 5 * Psd<KM>::MAT, *Rt = ws + 6 * Psd<KM>::MAT, *Q = ws + 7 * Psd<KM>::MAT, *Mm = ws + 8 * Psd<KM>::MAT,
-         *lam = ws + 9 * Psd<KM>::MAT, *m = lam + KM;
-  psd_smat<KM>(sc, k, Ls);
-  psd_smat<KM>(zc, k, Lz);
-  psd_chol<KM>(Ls, k);
-  psd_chol<KM>(Lz, k);
-  // B = Lz' Ls
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Lz[p * KM + i] * Ls[p * KM + j];
-      B[i * KM + j] = acc;
-    }
-  psd_jacobi_cols<KM>(B, k, W);   // B W = U diag(lam): V = W
-  for (int j = 0; j < k; ++j) {
-    double acc = 0;
-    for (int r = 0; r < k; ++r) acc += B[r * KM + j] * B[r * KM + j];
-    lam[j] = sqrt(acc);
-  }
-  // R = Ls V lam^-1/2 ; Rinv = lam^-1/2 U' Lz' with U = B diag(1/lam)
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Ls[i * KM + p] * W[p * KM + j];
-      R[i * KM + j] = acc / sqrt(lam[j]);
-    }
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += (B[p * KM + i] / lam[i]) * Lz[j * KM + p];
-      Ri[i * KM + j] = acc / sqrt(lam[i]);
-    }
-  // M = R R' = Q diag(m) Q': one-sided Jacobi on the columns of R' gives Q
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) Rt[i * KM + j] = R[j * KM + i];
-  psd_jacobi_cols<KM>(Rt, k, Q);
-  for (int j = 0; j < k; ++j) {
-    double acc = 0;
-    for (int r = 0; r < k; ++r) acc += Rt[r * KM + j] * Rt[r * KM + j];
-    m[j] = acc;
-  }
-  const int64_t kk = (int64_t)k * k;
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) {
-      g.state[(i * k + j) * N + c] = R[i * KM + j];
-      g.state[(kk + i * k + j) * N + c] = Ri[i * KM + j];
-      g.state[(2 * kk + i * k + j) * N + c] = Q[i * KM + j];
-    }
-  for (int j = 0; j < k; ++j) {
-    g.state[(3 * kk + j) * N + c] = lam[j];
-    g.state[(3 * kk + k + j) * N + c] = m[j];
-  }
-  // diag of H in svec coordinates: H[(a,b),(a,b)] = (M_aa M_bb + M_ab^2) (off-diag) or M_aa^2
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += R[i * KM + p] * R[j * KM + p];
-      Mm[i * KM + j] = acc;
-    }
-  int p = 0;
-  for (int b = 0; b < k; ++b)
-    for (int a = 0; a <= b; ++a, ++p) {
-      const double v = (a == b) ? sq(Mm[a * KM + a])
-                                : (Mm[a * KM + a] * Mm[b * KM + b] + sq(Mm[a * KM + b]));
-      hdiag[g.base + c * sd + p] = v;
-    }
-}
 
-// sides 13..32: one wave per cone (defined with the other wave kernels below)
+// PSD scaling, one wave per cone (defined with the other wave kernels below)
 __global__ __launch_bounds__(64) void k_psd_scale_wave(SegDev g, const double* __restrict__ s,
                                                        const double* __restrict__ z, double* __restrict__ hdiag);
 
@@ -689,12 +554,8 @@ void cone_scale(const SegDev& g, const double* s, const double* z, double mu, in
                          pd_count);
       break;
     case HC_CONE_PSD:
-      if (g.k <= PSD_KSMALL)
-        hipLaunchKernelGGL(k_psd_scale<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_SCALE)),
-                           dim3(Psd<PSD_KSMALL>::TB_SCALE), 0, st, g, s, z, hdiag);
-      else
-        hipLaunchKernelGGL(k_psd_scale_wave, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0, st, g, s,
-                           z, hdiag);
+      hipLaunchKernelGGL(k_psd_scale_wave, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0, st, g, s, z,
+                         hdiag);
       break;
   }
   HC_LAUNCH_CHECK();
@@ -704,58 +565,6 @@ void cone_scale(const SegDev& g, const double* s, const double* z, double mu, in
 // spectral application of H or (H + delta I)^-1, and the explicit inverse block
 // ===========================================================================
 __device__ inline double fsel(int mode, double lam, double delta) { return mode == 0 ? lam : 1.0 / (lam + delta); }
-
-// y = H x (mode 0) or (H + delta I)^-1 x (mode 1) for PSD cone c; ws: Psd<KM>::WS_APPLY doubles
-template <int KM>
-__device__ void psd_apply_one(const SegDev& g, int64_t c, int mode, double delta, const double* x, double* y,
-                              double* ws) {
-  const int k = g.k;
-  const int64_t N = g.count, kk = (int64_t)k * k;
-  double *Q = ws, *X = ws + Psd<KM>::MAT, *T = ws + 2 * Psd<KM>::MAT, *U = ws + 3 * Psd<KM>::MAT, *m = ws + 4 * Psd<KM>::MAT;
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) Q[i * KM + j] = g.state[(2 * kk + i * k + j) * N + c];
-  for (int j = 0; j < k; ++j) m[j] = g.state[(3 * kk + k + j) * N + c];
-  psd_smat<KM>(x, k, X);
-  // T = Q' X Q, scaled, then Y = Q T Q'
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += X[i * KM + p] * Q[p * KM + j];
-      T[i * KM + j] = acc;   // X Q
-    }
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Q[p * KM + i] * T[p * KM + j];
-      U[i * KM + j] = acc;
-    }
-  // Q'XQ is symmetric only up to rounding.  Its (i,j) and (j,i) entries are
-  // one coefficient of the eigenvector svec(q_i q_j' + q_j q_i'), so average
-  // them before scaling: with factors 1/(m_i m_j + delta) up to 1/delta the
-  // rounding asymmetry would otherwise turn, through the upper-triangle svec
-  // read below, into an error along the stiff eigenvectors, where H is large.
-  for (int i = 0; i < k; ++i) {
-    U[i * KM + i] *= fsel(mode, m[i] * m[i], delta);
-    for (int j = i + 1; j < k; ++j) {
-      const double v = 0.5 * (U[i * KM + j] + U[j * KM + i]) * fsel(mode, m[i] * m[j], delta);
-      U[i * KM + j] = v;
-      U[j * KM + i] = v;
-    }
-  }
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += U[i * KM + p] * Q[j * KM + p];
-      T[i * KM + j] = acc;   // U Q'
-    }
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Q[i * KM + p] * T[p * KM + j];
-      X[i * KM + j] = acc;
-    }
-  psd_svec<KM>(X, k, y);
-}
 
 __global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __restrict__ x,
                              double* __restrict__ y) {
@@ -798,17 +607,8 @@ __global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __r
       break;
     }
     case HC_CONE_PSD:
-      break;   // k_psd_apply
+      break;   // k_psd_apply_wave
   }
-}
-
-template <int KM>
-__global__ __launch_bounds__(Psd<KM>::TB_APPLY) void k_psd_apply(SegDev g, int mode, double delta, const double* __restrict__ x,
-                                                      double* __restrict__ y) {
-  __shared__ double wsall[Psd<KM>::TB_APPLY * Psd<KM>::WS_APPLY];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.count) return;
-  psd_apply_one<KM>(g, i, mode, delta, x + g.base + i * g.dim, y + g.base + i * g.dim, wsall + threadIdx.x * Psd<KM>::WS_APPLY);
 }
 
 // Sides 13..32: one wave per cone for the spectral application (the per-lane
@@ -891,8 +691,8 @@ void cone_apply(const SegDev& g, int mode, double delta, const double* x, double
     lsoc_apply(g, mode, delta, x, nullptr, y, st);
   else if (g.kind == HC_CONE_PSD)
     if (g.k <= PSD_KSMALL)
-      hipLaunchKernelGGL(k_psd_apply<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_APPLY)),
-                         dim3(Psd<PSD_KSMALL>::TB_APPLY), 0, st, g, mode, delta, x, y);
+      hipLaunchKernelGGL(k_psd_apply_wave<PSD_KSMALL>, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0,
+                         st, g, mode, delta, x, (const double*)nullptr, y);
     else
       hipLaunchKernelGGL(k_psd_apply_wave<PSD_KLARGE>, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0,
                          st, g, mode, delta, x, (const double*)nullptr, y);
@@ -941,20 +741,8 @@ __global__ void k_cone_recover(SegDev g, const double* __restrict__ dsr, const d
       break;
     }
     case HC_CONE_PSD:
-      break;   // k_psd_recover
+      break;   // k_psd_apply_wave (with dsr)
   }
-}
-
-template <int KM>
-__global__ __launch_bounds__(Psd<KM>::TB_APPLY) void k_psd_recover(SegDev g, const double* __restrict__ dsr,
-                                                        const double* __restrict__ dz, double* __restrict__ out) {
-  __shared__ double wsall[Psd<KM>::TB_APPLY * Psd<KM>::WS_APPLY];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.count) return;
-  double* ws = wsall + threadIdx.x * Psd<KM>::WS_APPLY;
-  double* yv = ws + 4 * Psd<KM>::MAT + KM;
-  psd_apply_one<KM>(g, i, 0, 0.0, dz + g.base + i * g.dim, yv, ws);
-  for (int p = 0; p < g.dim; ++p) out[g.base + i * g.dim + p] = -dsr[g.base + i * g.dim + p] - yv[p];
 }
 
 void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, double* out, hipStream_t st) {
@@ -963,8 +751,8 @@ void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, dou
     lsoc_apply(g, 0, 0.0, dz, dsrhs, out, st);
   else if (g.kind == HC_CONE_PSD)
     if (g.k <= PSD_KSMALL)
-      hipLaunchKernelGGL(k_psd_recover<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_APPLY)),
-                         dim3(Psd<PSD_KSMALL>::TB_APPLY), 0, st, g, dsrhs, dz, out);
+      hipLaunchKernelGGL(k_psd_apply_wave<PSD_KSMALL>, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0,
+                         st, g, 0, 0.0, dz, dsrhs, out);
     else
       hipLaunchKernelGGL(k_psd_apply_wave<PSD_KLARGE>, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0,
                          st, g, 0, 0.0, dz, dsrhs, out);
@@ -1291,33 +1079,6 @@ __device__ inline double soc_step_one(const double* x, const double* dx, int d) 
   return soc_boundary_step(a, b, c);
 }
 
-// largest alpha with x + alpha dx PSD (INFINITY if unbounded); ws: 3 Psd<KM>::MAT doubles
-template <int KM>
-__device__ double psd_step_one(const double* x, const double* dx, int k, double* ws) {
-  double *L = ws, *D = ws + Psd<KM>::MAT, *T = ws + 2 * Psd<KM>::MAT;
-  psd_smat<KM>(x, k, L);
-  psd_smat<KM>(dx, k, D);
-  if (!psd_chol<KM>(L, k)) return 0.0;
-  // T = L^-1 D, then Mm = T L^-T  (two triangular solves)
-  for (int j = 0; j < k; ++j)
-    for (int i = 0; i < k; ++i) {
-      double v = D[i * KM + j];
-      for (int p = 0; p < i; ++p) v -= L[i * KM + p] * T[p * KM + j];
-      T[i * KM + j] = v / L[i * KM + i];
-    }
-  // Mm = (L^-1 T')' : solve L Y = T' column by column, Mm = Y'
-  for (int j = 0; j < k; ++j)
-    for (int i = 0; i < k; ++i) {
-      double v = T[j * KM + i];
-      for (int p = 0; p < i; ++p) v -= L[i * KM + p] * D[p * KM + j];
-      D[i * KM + j] = v / L[i * KM + i];   // D now holds Y
-    }
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) T[i * KM + j] = 0.5 * (D[i * KM + j] + D[j * KM + i]);
-  const double lmin = psd_min_eig<KM>(T, k);
-  return (lmin < 0.0) ? -1.0 / lmin : INFINITY;
-}
-
 __global__ void k_step_sym(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
                            const double* __restrict__ ds, const double* __restrict__ dz, double* __restrict__ partial) {
   __shared__ double red[CONE_BLOCK];
@@ -1353,24 +1114,9 @@ __global__ void k_step_sym(SegDev g, const double* __restrict__ s, const double*
 // PSD: grid-stride over the cones with at most PSD_STEP_GRID blocks, one
 // partial minimum per block
 constexpr int PSD_STEP_GRID = 2048;
-template <int KM>
-__global__ __launch_bounds__(Psd<KM>::TB_STEP) void k_step_psd(SegDev g, const double* __restrict__ s,
-                                                     const double* __restrict__ z, const double* __restrict__ ds,
-                                                     const double* __restrict__ dz, double* __restrict__ partial) {
-  __shared__ double wsall[Psd<KM>::TB_STEP * Psd<KM>::WS_STEP];
-  double* ws = wsall + threadIdx.x * Psd<KM>::WS_STEP;
-  const int sd = g.dim;
-  double a = INFINITY;
-  for (int64_t i = (int64_t)blockIdx.x * Psd<KM>::TB_STEP + threadIdx.x; i < g.count;
-       i += (int64_t)gridDim.x * Psd<KM>::TB_STEP)
-    a = fmin(a, fmin(psd_step_one<KM>(s + g.base + i * sd, ds + g.base + i * sd, g.k, ws),
-                     psd_step_one<KM>(z + g.base + i * sd, dz + g.base + i * sd, g.k, ws)));
-  for (int off = Psd<KM>::TB_STEP / 2; off > 0; off >>= 1) a = fmin(a, __shfl_xor(a, off, Psd<KM>::TB_STEP));
-  if (threadIdx.x == 0) partial[blockIdx.x] = a;
-}
 
 // ---------------------------------------------------------------------------
-// Sides 13..32: one wave per cone for the Jacobi-based PSD kernels.  The k
+// One wave per cone for the Jacobi-based PSD kernels (every side).  The k
 // indices (padded to an even count kk with one that never rotates) are paired
 // round-robin (circle method: index kk - 1 fixed, the others turning), so the
 // kk/2 pairs of a round are disjoint and their rotations are applied at once;
@@ -1452,7 +1198,7 @@ __device__ bool wave_chol(double* A, int k, int lane) {
 }
 
 // smallest eigenvalue of the symmetric A (destroyed): parallel cyclic Jacobi
-// with the per-lane kernel's stopping rule (no rotation of entries at most
+// with psd_min_eig's stopping rule (no rotation of entries at most
 // 1e-18 |A|_F; end on a sweep without rotations, or after 60)
 __device__ double wave_min_eig(double* A, int k, int lane, double* rc, double* rs, int* rp, int* rq, int* flag) {
   double tot = 0;
@@ -1510,8 +1256,8 @@ __device__ double wave_min_eig(double* A, int k, int lane, double* rc, double* r
 
 // one-sided Jacobi (Hestenes) on the columns of B (k x k): on return the
 // columns are orthogonal and W accumulates B_in W = B_out.  Four lanes per
-// pair, each summing and rotating rows sub, sub + 4, ...; the rule of the
-// per-lane kernel skips a pair when |b_p'b_q| <= 1e-16 |b_p||b_q|.
+// pair, each summing and rotating rows sub, sub + 4, ...; a pair is skipped
+// when |b_p'b_q| <= 1e-16 |b_p||b_q| (as the exp/pow Jacobi does).
 __device__ void wave_jacobi_cols(double* B, int k, double* W, int lane, int* flag) {
   for (int e = lane; e < k * k; e += 64) W[(e / k) * PW_LD + e % k] = (e / k == e % k) ? 1.0 : 0.0;
   const int kk = (k + 1) & ~1, np = kk / 2, grp = lane >> 2, sub = lane & 3;
@@ -1568,7 +1314,10 @@ __device__ inline void wave_mm(const double* X, bool tx, const double* Y, bool t
   __syncthreads();
 }
 
-// PSD scaling of sides 13..32, one wave per cone (the steps of k_psd_scale)
+// PSD scaling, one wave per cone: Cholesky factors L_s, L_z; the SVD of
+// L_z' L_s = U diag(lam) V' gives R = L_s V lam^-1/2 and R^-1 = lam^-1/2 U' L_z';
+// a second one-sided Jacobi on R' gives M = R R' = Q diag(m) Q'.  State
+// fields: R (k*k row-major) | R^-1 | Q | lambda (k) | m (k)
 __global__ __launch_bounds__(64) void k_psd_scale_wave(SegDev g, const double* __restrict__ s,
                                                        const double* __restrict__ z, double* __restrict__ hdiag) {
   __shared__ double Ls[PW_MAT], Lz[PW_MAT], B[PW_MAT], W[PW_MAT], R[PW_MAT], Ri[PW_MAT], lam[PSD_KLARGE],
@@ -1633,7 +1382,8 @@ __global__ __launch_bounds__(64) void k_psd_scale_wave(SegDev g, const double* _
   }
 }
 
-// largest alpha with x + alpha dx PSD (INFINITY if unbounded), as psd_step_one
+// largest alpha with x + alpha dx PSD (INFINITY if unbounded): Cholesky
+// L L' = x, then the smallest eigenvalue of L^-1 dx L^-T
 __device__ double wave_step_one(const double* x, const double* dx, int k, int lane, double* L, double* D, double* T,
                                 double* rc, double* rs, int* rp, int* rq, int* flag) {
   __syncthreads();
@@ -1693,14 +1443,8 @@ int cone_step_sym(const SegDev& g, const double* s, const double* z, const doubl
   if (soc_large(g.kind, g.dim)) return lsoc_step(g, s, z, ds, dz, INFINITY, false, partial, st);
   if (g.kind == HC_CONE_PSD) {
     int nbp;
-    if (g.k <= PSD_KSMALL) {
-      nbp = std::min(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_STEP), PSD_STEP_GRID);
-      hipLaunchKernelGGL(k_step_psd<PSD_KSMALL>, dim3(nbp), dim3(Psd<PSD_KSMALL>::TB_STEP), 0, st, g, s, z, ds, dz,
-                         partial);
-    } else {
-      nbp = (int)std::min<int64_t>(g.count, PSD_STEP_GRID);
-      hipLaunchKernelGGL(k_step_psd_wave, dim3(nbp), dim3(64), 0, st, g, s, z, ds, dz, INFINITY, 0, partial);
-    }
+    nbp = (int)std::min<int64_t>(g.count, PSD_STEP_GRID);
+    hipLaunchKernelGGL(k_step_psd_wave, dim3(nbp), dim3(64), 0, st, g, s, z, ds, dz, INFINITY, 0, partial);
     HC_LAUNCH_CHECK();
     return nbp;
   }
@@ -2016,20 +1760,6 @@ __global__ void k_test_step(SegDev g, const double* __restrict__ s, const double
   out[i] = a;
 }
 
-template <int KM>
-__global__ __launch_bounds__(Psd<KM>::TB_STEP) void k_psd_test_step(SegDev g, const double* __restrict__ s,
-                                                                    const double* __restrict__ z,
-                                                                    const double* __restrict__ ds,
-                                                                    const double* __restrict__ dz, double amax,
-                                                                    double* __restrict__ out) {
-  __shared__ double wsall[Psd<KM>::TB_STEP * Psd<KM>::WS_STEP];
-  double* ws = wsall + threadIdx.x * Psd<KM>::WS_STEP;
-  const int64_t i = (int64_t)blockIdx.x * Psd<KM>::TB_STEP + threadIdx.x;
-  if (i >= g.count) return;
-  out[i] = fmin(amax, fmin(psd_step_one<KM>(s + g.base + i * g.dim, ds + g.base + i * g.dim, g.k, ws),
-                           psd_step_one<KM>(z + g.base + i * g.dim, dz + g.base + i * g.dim, g.k, ws)));
-}
-
 void cone_test_step(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz,
                     double amax, double* out, hipStream_t st) {
   if (soc_large(g.kind, g.dim)) {
@@ -2037,12 +1767,8 @@ void cone_test_step(const SegDev& g, const double* s, const double* z, const dou
     return;
   }
   if (g.kind == HC_CONE_PSD) {
-    if (g.k <= PSD_KSMALL)
-      hipLaunchKernelGGL(k_psd_test_step<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_STEP)),
-                         dim3(Psd<PSD_KSMALL>::TB_STEP), 0, st, g, s, z, ds, dz, amax, out);
-    else
-      hipLaunchKernelGGL(k_step_psd_wave, dim3((unsigned)std::min<int64_t>(g.count, PSD_STEP_GRID)), dim3(64), 0, st,
-                         g, s, z, ds, dz, amax, 1, out);
+    hipLaunchKernelGGL(k_step_psd_wave, dim3((unsigned)std::min<int64_t>(g.count, PSD_STEP_GRID)), dim3(64), 0, st, g,
+                       s, z, ds, dz, amax, 1, out);
     HC_LAUNCH_CHECK();
     return;
   }

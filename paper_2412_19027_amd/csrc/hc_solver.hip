@@ -116,6 +116,7 @@ struct hc_solver {
   double *dAd = nullptr, *dBd = nullptr;
   int32_t* ddrows = nullptr;
   int64_t* ddmidx = nullptr;
+  double* dDrT = nullptr;           // per-chunk partial sums of A'z over the dense rows
   int32_t *dls_cone = nullptr, *dls_col = nullptr;
   int64_t* dls_dst = nullptr;
   double *dq = nullptr, *db = nullptr, *dD = nullptr, *dE = nullptr, *dalpha = nullptr;
@@ -1105,7 +1106,7 @@ void A_mul(hc_solver* S, const double* x, double* y, double alpha, double beta) 
 void At_mul(hc_solver* S, const double* z, double* y, double alpha, double beta) {
   spmv(S->dAt, z, y, alpha, beta, S->stream);
   dense_rows_gemv_t((int)S->drows.size(), S->leaves ? S->nt : S->n, S->dAd, S->ddrows,
-                    S->leaves ? S->cm.tcols : nullptr, z, y, alpha, S->stream);
+                    S->leaves ? S->cm.tcols : nullptr, z, y, alpha, S->dDrT, S->stream);
 }
 void P_mul(hc_solver* S, const double* x, double* y, double alpha, double beta) {
   if (S->dP.nnz == 0) {
@@ -1723,6 +1724,8 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
       HC_HIP(hipMemcpyAsync(S->dAd, S->Ad.data(), S->Ad.size() * sizeof(double), hipMemcpyHostToDevice, st));
   }
   S->dBd = buf.take<double>(std::max<size_t>(1, (size_t)(S->K1 + S->K2) * (size_t)S->nt));
+  S->dDrT = buf.take<double>(std::max<size_t>(
+      1, (size_t)dense_rows_t_parts((int)S->drows.size()) * (size_t)(S->leaves ? S->nt : S->n)));
   S->ddrows = upload(buf, S->drows, st);
   S->ddmidx = upload(buf, S->dmidx_all, st);
   S->dls_cone = upload(buf, S->ls_cone, st);

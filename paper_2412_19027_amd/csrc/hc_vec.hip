@@ -102,21 +102,42 @@ void dense_rows_gemv(int nd, int64_t n, const double* Ad, const int32_t* rows, c
 }
 
 // y[cols[j]] += alpha * sum_r Ad[r, j] v[rows[r]]  (cols null: y[j]; cols is
-// one-to-one, so no two threads write one entry)
-__global__ void k_dense_rows_t(int nd, int64_t n, const double* __restrict__ Ad, const int32_t* __restrict__ rows,
-                               const int32_t* __restrict__ cols, const double* __restrict__ v,
-                               double* __restrict__ y, double alpha) {
+// one-to-one).  The rows are split into chunks of DRT_ROWS: workgroup (x, c)
+// sums chunk c for 256 columns (coalesced row reads) into part[c][j], and a
+// second kernel adds the chunks in order, so the result does not depend on
+// scheduling.  part holds dense_rows_t_parts(nd) * n doubles.
+constexpr int DRT_ROWS = 64;
+int64_t dense_rows_t_parts(int nd) { return ceil_div(nd, DRT_ROWS); }
+
+__global__ __launch_bounds__(256) void k_dense_rows_t(int nd, int64_t n, const double* __restrict__ Ad,
+                                                      const int32_t* __restrict__ rows, const double* __restrict__ v,
+                                                      double* __restrict__ part) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r0 = blockIdx.y * DRT_ROWS, r1 = min(nd, r0 + DRT_ROWS);
+  if (j >= n) return;
+  double acc = 0;
+  for (int r = r0; r < r1; ++r) acc += Ad[(int64_t)r * n + j] * v[rows[r]];
+  part[(int64_t)blockIdx.y * n + j] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_dense_rows_t_sum(int64_t n, int nparts, const double* __restrict__ part,
+                                                          const int32_t* __restrict__ cols, double* __restrict__ y,
+                                                          double alpha) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   double acc = 0;
-  for (int r = 0; r < nd; ++r) acc += Ad[(int64_t)r * n + j] * v[rows[r]];
+  for (int c = 0; c < nparts; ++c) acc += part[(int64_t)c * n + j];
   y[cols ? cols[j] : j] += alpha * acc;
 }
 
 void dense_rows_gemv_t(int nd, int64_t n, const double* Ad, const int32_t* rows, const int32_t* cols,
-                       const double* v, double* y, double alpha, hipStream_t st) {
+                       const double* v, double* y, double alpha, double* part, hipStream_t st) {
   if (nd == 0) return;
-  hipLaunchKernelGGL(k_dense_rows_t, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, nd, n, Ad, rows, cols, v, y,
+  const int np = (int)dense_rows_t_parts(nd);
+  hipLaunchKernelGGL(k_dense_rows_t, dim3((unsigned)ceil_div(n, 256), (unsigned)np), dim3(256), 0, st, nd, n, Ad, rows,
+                     v, part);
+  HC_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_dense_rows_t_sum, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, np, part, cols, y,
                      alpha);
   HC_LAUNCH_CHECK();
 }
