@@ -23,7 +23,9 @@ struct SegDev {
 void cone_scale(const SegDev& g, const double* s, const double* z, double mu, int force_dual, double* hdiag,
                 int* branch_pd_count, hipStream_t st);
 // Explicit lower-triangle entries of (H + delta I)^-1 per cone into g.mblk.
-void cone_mblock(const SegDev& g, double delta, hipStream_t st);
+// work: cone_mblock_work(g) doubles of device scratch (PSD: the G_i factors)
+void cone_mblock(const SegDev& g, double delta, double* work, hipStream_t st);
+int64_t cone_mblock_work(const SegDev& g);
 // y[rows] = H x[rows]  (mode 0) or (H + delta I)^-1 x[rows] (mode 1), spectral form.
 void cone_apply(const SegDev& g, int mode, double delta, const double* x, double* y, hipStream_t st);
 // y[rows] = -ds[rows] - H x[rows]  (direction recovery of Delta s)

@@ -763,53 +763,57 @@ void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, dou
 
 // explicit lower-triangle entries of M = (H + delta I)^-1, packed index
 // p = a (a + 1) / 2 + b for a >= b, stored mblk[p * count + cone]
-// PSD: one workgroup per cone, one lane per svec row a; Q and m of the cone
-// staged in LDS
-template <int KM>
-__global__ __launch_bounds__(KM <= 12 ? 128 : 576) void k_psd_mblock(SegDev g, double delta) {
-  __shared__ double Q[Psd<KM>::MAT], m[KM];
-  const int64_t N = g.count, c = blockIdx.x;
-  const int sd = g.dim, k = g.k;
-  const int64_t kk = (int64_t)k * k;
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) Q[(e / k) * KM + e % k] = g.state[(2 * kk + e) * N + c];
+//
+// PSD: with f(i,j) = 1/(m_i m_j + delta) and svec index a = (ia, ja),
+//   M_ab = (c_a c_b / 2) sum_i Q[ia][i] (Q[ib][i] G_i[ja][jb] + Q[jb][i] G_i[ja][ib]),
+//   G_i[q][s] = sum_j f(i,j) Q[q][j] Q[s][j],
+// (c = 1 on the diagonal, sqrt2 off it), which is sum_e svec(E_e)_a svec(E_e)_b f_e
+// over the eigenvectors E_e = (q_i q_j' + q_j q_i')/sqrt2 of H, expanded by the
+// Kronecker structure: k^4 flops for the G_i and 2k per entry instead of k(k+1)/2
+// per entry.  G (k^3 per cone) lives in the caller's work buffer.
+__global__ __launch_bounds__(256) void k_psd_mblock_g(SegDev g, double delta, double* __restrict__ G) {
+  __shared__ double Q[PSD_KLARGE * (PSD_KLARGE + 1)], m[PSD_KLARGE];
+  const int k = g.k, LQ = PSD_KLARGE + 1;
+  const int64_t N = g.count, kk = (int64_t)k * k, c = blockIdx.x;
+  const int i = blockIdx.y;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) Q[(e / k) * LQ + e % k] = g.state[(2 * kk + e) * N + c];
   for (int e = threadIdx.x; e < k; e += blockDim.x) m[e] = g.state[(3 * kk + k + e) * N + c];
   __syncthreads();
-  const int arow = threadIdx.x;
-  if (arow >= sd) return;
-  {
-    // (ia, ja) of svec row a
-    int ia = 0, ja = 0;
-    {
-      int p = 0;
-      for (int j = 0; j < k; ++j)
-        for (int r = 0; r <= j; ++r, ++p)
-          if (p == arow) { ia = r; ja = j; }
-    }
-    const double ca = (ia == ja) ? 1.0 : 1.41421356237309504880;
-    const double is2 = 0.70710678118654752440;
-    int p = 0;
-    for (int jb = 0; jb < k; ++jb)
-      for (int ib = 0; ib <= jb; ++ib, ++p) {
-        if (p > arow) continue;
-        const double cb = (ib == jb) ? 1.0 : 1.41421356237309504880;
-        double acc = 0;
-        for (int jj = 0; jj < k; ++jj)
-          for (int ii = 0; ii <= jj; ++ii) {
-            // svec(E_ii,jj) at (ia, ja) and (ib, jb)
-            double ea, eb;
-            if (ii == jj) {
-              ea = ca * Q[ia * KM + ii] * Q[ja * KM + ii];
-              eb = cb * Q[ib * KM + ii] * Q[jb * KM + ii];
-            } else {
-              ea = ca * is2 * (Q[ia * KM + ii] * Q[ja * KM + jj] + Q[ia * KM + jj] * Q[ja * KM + ii]);
-              eb = cb * is2 * (Q[ib * KM + ii] * Q[jb * KM + jj] + Q[ib * KM + jj] * Q[jb * KM + ii]);
-            }
-            acc += ea * eb / (m[ii] * m[jj] + delta);
-          }
-        const int64_t pk = (int64_t)arow * (arow + 1) / 2 + p;
-        g.mblk[pk * N + c] = acc;
-      }
+  double* Gi = G + (c * k + i) * kk;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int q = e / k, sx = e % k;
+    double acc = 0;
+    for (int j = 0; j < k; ++j) acc += Q[q * LQ + j] * Q[sx * LQ + j] / (m[i] * m[j] + delta);
+    Gi[e] = acc;
   }
+}
+
+__global__ __launch_bounds__(576) void k_psd_mblock(SegDev g, const double* __restrict__ G) {
+  __shared__ double Q[PSD_KLARGE * (PSD_KLARGE + 1)];
+  const int k = g.k, LQ = PSD_KLARGE + 1, sd = g.dim;
+  const int64_t N = g.count, kk = (int64_t)k * k, c = blockIdx.x;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) Q[(e / k) * LQ + e % k] = g.state[(2 * kk + e) * N + c];
+  __syncthreads();
+  const int a = threadIdx.x;
+  if (a >= sd) return;
+  int ja = (int)((sqrt(8.0 * a + 1.0) - 1.0) / 2.0);
+  while (ja * (ja + 1) / 2 > a) --ja;
+  while ((ja + 1) * (ja + 2) / 2 <= a) ++ja;
+  const int ia = a - ja * (ja + 1) / 2;
+  const double ca = (ia == ja) ? 1.0 : 1.41421356237309504880;
+  const double* Gc = G + c * k * kk;
+  for (int jb = 0; jb <= ja; ++jb)
+    for (int ib = 0; ib <= jb; ++ib) {
+      const int b = jb * (jb + 1) / 2 + ib;
+      if (b > a) break;
+      const double cb = (ib == jb) ? 1.0 : 1.41421356237309504880;
+      double acc = 0;
+      for (int i = 0; i < k; ++i) {
+        const double* Gi = Gc + (int64_t)i * kk + (int64_t)ja * k;
+        acc += Q[ia * LQ + i] * (Q[ib * LQ + i] * Gi[jb] + Q[jb * LQ + i] * Gi[ib]);
+      }
+      g.mblk[((int64_t)a * (a + 1) / 2 + b) * N + c] = 0.5 * ca * cb * acc;
+    }
 }
 
 __global__ void k_cone_mblock(SegDev g, double delta) {
@@ -866,14 +870,18 @@ __global__ void k_cone_mblock(SegDev g, double delta) {
   }
 }
 
-void cone_mblock(const SegDev& g, double delta, hipStream_t st) {
+int64_t cone_mblock_work(const SegDev& g) {
+  return g.kind == HC_CONE_PSD ? g.count * (int64_t)g.k * g.k * g.k : 0;
+}
+
+void cone_mblock(const SegDev& g, double delta, double* work, hipStream_t st) {
   if (g.count == 0) return;
-  const dim3 psd_threads((unsigned)(ceil_div(g.dim, 64) * 64));
-  if (g.kind == HC_CONE_PSD && g.k <= PSD_KSMALL)
-    hipLaunchKernelGGL(k_psd_mblock<PSD_KSMALL>, dim3((unsigned)g.count), psd_threads, 0, st, g, delta);
-  else if (g.kind == HC_CONE_PSD)
-    hipLaunchKernelGGL(k_psd_mblock<PSD_KLARGE>, dim3((unsigned)g.count), psd_threads, 0, st, g, delta);
-  else
+  if (g.kind == HC_CONE_PSD) {
+    hipLaunchKernelGGL(k_psd_mblock_g, dim3((unsigned)g.count, (unsigned)g.k), dim3(256), 0, st, g, delta, work);
+    HC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_psd_mblock, dim3((unsigned)g.count), dim3((unsigned)(ceil_div(g.dim, 64) * 64)), 0, st, g,
+                       (const double*)work);
+  } else
     hipLaunchKernelGGL(k_cone_mblock, dim3((unsigned)std::max<int64_t>(1, ceil_div(g.count, CONE_BLOCK))),
                        dim3(CONE_BLOCK), 0, st, g, delta);
   HC_LAUNCH_CHECK();

@@ -117,6 +117,7 @@ struct hc_solver {
   int32_t* ddrows = nullptr;
   int64_t* ddmidx = nullptr;
   double* dDrT = nullptr;           // per-chunk partial sums of A'z over the dense rows
+  double* dmwork = nullptr;         // scratch of the PSD M blocks (largest segment's need)
   int32_t *dls_cone = nullptr, *dls_col = nullptr;
   int64_t* dls_dst = nullptr;
   double *dq = nullptr, *db = nullptr, *dD = nullptr, *dE = nullptr, *dalpha = nullptr;
@@ -1149,7 +1150,7 @@ void factor(hc_solver* S, bool fp64 = false) {
     const double dd = S->mixed ? std::ldexp(1.0, -104) : S->st.dyn_reg;
     S->delta = ds + dd * std::max(S->maxPdiag, hmax);
   }
-  for (auto& g : S->sdev) cone_mblock(g, S->delta, st);
+  for (auto& g : S->sdev) cone_mblock(g, S->delta, S->dmwork, st);   // segments run in order: one work buffer
   // The tail is factored padded to ld (a multiple of 64) with an identity
   // block on the padding: [[S, 0], [0, I]] = [[L, 0], [0, I]] [[L, 0], [0, I]]',
   // so every panel, TRSM and trailing update is a whole number of 64-blocks
@@ -1789,6 +1790,18 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
     d.k = sg.k;
     d.count = sg.count;
     S->npart += cone_blocks(d) + 2048;   // a step or max kernel writes at most this many
+  }
+  {
+    int64_t mw = 1;
+    for (const Segment& sg : S->segs) {
+      SegDev d{};
+      d.kind = sg.kind;
+      d.dim = sg.dim;
+      d.k = sg.k;
+      d.count = sg.count;
+      mw = std::max(mw, cone_mblock_work(d));
+    }
+    S->dmwork = buf.take<double>(mw);
   }
   S->dpart = buf.take<double>(S->npart);
   S->dmask = buf.take<unsigned long long>(S->npart);

@@ -167,7 +167,7 @@ int32_t hc_test_cone_mblock(int32_t type, int64_t count, int32_t dim, const doub
     int* pd = (int*)T.alloc(1);
     HC_HIP(hipMemsetAsync(pd, 0, sizeof(double), st));
     cone_scale(T.g, si, zi, mu, 0, hd, pd, st);
-    cone_mblock(T.g, delta, st);
+    cone_mblock(T.g, delta, T.alloc(std::max<int64_t>(1, cone_mblock_work(T.g))), st);
     const int64_t per = mblock_doubles(type, T.g.dim);
     std::vector<double> hm(per * T.g.count), dense((size_t)count * T.rows * T.rows, 0.0);
     HC_HIP(hipMemcpyAsync(hm.data(), T.g.mblk, hm.size() * 8, hipMemcpyDeviceToHost, st));
