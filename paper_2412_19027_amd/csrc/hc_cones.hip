@@ -456,12 +456,6 @@ __device__ inline void psd_smat(const double* v, int k, double* X) {
       X[j * KM + i] = v[p] * f;
     }
 }
-template <int KM>
-__device__ inline void psd_svec(const double* X, int k, double* v) {
-  int p = 0;
-  for (int j = 0; j < k; ++j)
-    for (int i = 0; i <= j; ++i, ++p) v[p] = X[i * KM + j] * ((i == j) ? 1.0 : 1.41421356237309504880);
-}
 // cyclic Jacobi eigenvalues of a symmetric matrix (destroys A); returns lambda_min
 template <int KM>
 __device__ double psd_min_eig(double* A, int k) {
@@ -508,27 +502,29 @@ __device__ double psd_min_eig(double* A, int k) {
 // are odd so the lanes of a block fall on distinct banks.
 // ---------------------------------------------------------------------------
 constexpr int odd_stride(int n) { return n | 1; }
-// The per-lane PSD kernels (d_s correction, initial-point shift) come in two
-// instantiations: KM = 12 (sides up to 12, eight cones per workgroup) and
-// KM = 32 (sides 13..32, the paper's limit; a 32 x 32 FP64 matrix is 8 KB, so
-// two to four cones per workgroup keep the slices within ~150 KB of LDS).
-// Scaling, step and spectral apply run one wave per cone for every side
-// (the wave kernels below); the M block one lane per (cone, svec row).
+// The one per-lane PSD kernel left (the initial-point shift, run once per
+// solve) comes in two instantiations: KM = 12 (sides up to 12, eight cones per
+// workgroup) and KM = 32 (sides 13..32, the paper's limit; a 32 x 32 FP64
+// matrix is 8 KB, so four cones per workgroup keep the slices within LDS).
+// Scaling, d_s correction, step and spectral apply run one wave per cone for
+// every side (the wave kernels below).
 template <int KM> struct Psd {
   static constexpr int MAT = KM * KM;
   static constexpr int SVEC = KM * (KM + 1) / 2;
-  static constexpr int WS_DS = odd_stride(8 * MAT + KM);
   static constexpr int WS_STEP = odd_stride(3 * MAT);
-  static constexpr int TB_DS = KM <= 12 ? 8 : 2;     // lanes (cones) per workgroup
-  static constexpr int TB_STEP = KM <= 12 ? 8 : 4;
+  static constexpr int TB_STEP = KM <= 12 ? 8 : 4;     // lanes (cones) per workgroup
   static int blocks(int64_t count, int tb) { return (int)std::max<int64_t>(1, ceil_div(count, tb)); }
 };
 constexpr int PSD_KSMALL = 12, PSD_KLARGE = 32;
 
 
-// PSD scaling, one wave per cone (defined with the other wave kernels below)
+// PSD scaling and d_s correction, one wave per cone (defined with the other
+// wave kernels below)
 __global__ __launch_bounds__(64) void k_psd_scale_wave(SegDev g, const double* __restrict__ s,
                                                        const double* __restrict__ z, double* __restrict__ hdiag);
+__global__ __launch_bounds__(64) void k_psd_ds_wave(SegDev g, const double* __restrict__ dsa,
+                                                    const double* __restrict__ dza, double sm,
+                                                    double* __restrict__ ds);
 
 void cone_scale(const SegDev& g, const double* s, const double* z, double mu, int force_dual, double* hdiag,
                 int* pd_count, hipStream_t st) {
@@ -979,82 +975,8 @@ __global__ void k_cone_ds(SegDev g, const double* __restrict__ s, const double* 
       break;
     }
     case HC_CONE_PSD:
-      break;   // k_psd_ds
+      break;   // k_psd_ds_wave
   }
-}
-
-template <int KM>
-__global__ __launch_bounds__(Psd<KM>::TB_DS) void k_psd_ds(SegDev g, const double* __restrict__ dsa,
-                                                   const double* __restrict__ dza, double sm, double* __restrict__ ds) {
-  __shared__ double wsall[Psd<KM>::TB_DS * Psd<KM>::WS_DS];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.count) return;
-  const int64_t N = g.count;
-  const int k = g.k, sd = g.dim;
-  const int64_t kk = (int64_t)k * k;
-  double* ws = wsall + threadIdx.x * Psd<KM>::WS_DS;
-  double *R = ws, *Ri = ws + Psd<KM>::MAT, *dS = ws + 2 * Psd<KM>::MAT, *dZ = ws + 3 * Psd<KM>::MAT, *T1 = ws + 4 * Psd<KM>::MAT,
-         *Aa = ws + 5 * Psd<KM>::MAT, *Bb = ws + 6 * Psd<KM>::MAT, *X = ws + 7 * Psd<KM>::MAT, *lam = ws + 8 * Psd<KM>::MAT;
-  for (int r = 0; r < k; ++r)
-    for (int j = 0; j < k; ++j) {
-      R[r * KM + j] = g.state[(r * k + j) * N + i];
-      Ri[r * KM + j] = g.state[(kk + r * k + j) * N + i];
-    }
-  for (int j = 0; j < k; ++j) lam[j] = g.state[(3 * kk + j) * N + i];
-  psd_smat<KM>(dsa + g.base + i * sd, k, dS);
-  psd_smat<KM>(dza + g.base + i * sd, k, dZ);
-  // Aa = Ri dS Ri'
-  for (int r = 0; r < k; ++r)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Ri[r * KM + p] * dS[p * KM + j];
-      T1[r * KM + j] = acc;
-    }
-  for (int r = 0; r < k; ++r)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += T1[r * KM + p] * Ri[j * KM + p];
-      Aa[r * KM + j] = acc;
-    }
-  // Bb = R' dZ R
-  for (int r = 0; r < k; ++r)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += R[p * KM + r] * dZ[p * KM + j];
-      T1[r * KM + j] = acc;
-    }
-  for (int r = 0; r < k; ++r)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += T1[r * KM + p] * R[p * KM + j];
-      Bb[r * KM + j] = acc;
-    }
-  // V = (Aa Bb + Bb Aa)/2 + diag(lam^2) - sm I ;  X_ij = 2 V_ij / (lam_i + lam_j)
-  // (V is formed on the upper triangle and mirrored, so X is exactly
-  // symmetric before the large 1/(lam_i + lam_j) factors)
-  for (int r = 0; r < k; ++r)
-    for (int j = r; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += Aa[r * KM + p] * Bb[p * KM + j] + Bb[r * KM + p] * Aa[p * KM + j];
-      double v = 0.5 * acc;
-      if (r == j) v += lam[r] * lam[r] - sm;
-      X[r * KM + j] = 2.0 * v / (lam[r] + lam[j]);
-      X[j * KM + r] = X[r * KM + j];
-    }
-  // ds = svec(R X R')
-  for (int r = 0; r < k; ++r)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += R[r * KM + p] * X[p * KM + j];
-      T1[r * KM + j] = acc;
-    }
-  for (int r = 0; r < k; ++r)
-    for (int j = 0; j < k; ++j) {
-      double acc = 0;
-      for (int p = 0; p < k; ++p) acc += T1[r * KM + p] * R[j * KM + p];
-      X[r * KM + j] = acc;
-    }
-  psd_svec<KM>(X, k, ds + g.base + i * sd);
 }
 
 void cone_ds_combined(const SegDev& g, const double* s, const double* z, const double* dsa, const double* dza,
@@ -1063,12 +985,8 @@ void cone_ds_combined(const SegDev& g, const double* s, const double* z, const d
   if (soc_large(g.kind, g.dim))
     lsoc_ds(g, dsa, dza, sm, ds, st);
   else if (g.kind == HC_CONE_PSD)
-    if (g.k <= PSD_KSMALL)
-      hipLaunchKernelGGL(k_psd_ds<PSD_KSMALL>, dim3(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_DS)),
-                         dim3(Psd<PSD_KSMALL>::TB_DS), 0, st, g, dsa, dza, sm, ds);
-    else
-      hipLaunchKernelGGL(k_psd_ds<PSD_KLARGE>, dim3(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_DS)),
-                         dim3(Psd<PSD_KLARGE>::TB_DS), 0, st, g, dsa, dza, sm, ds);
+    hipLaunchKernelGGL(k_psd_ds_wave, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0, st, g, dsa, dza,
+                       sm, ds);
   else
     hipLaunchKernelGGL(k_cone_ds, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, s, z, dsa, dza, sm, ds);
   HC_LAUNCH_CHECK();
@@ -1386,6 +1304,55 @@ __global__ __launch_bounds__(64) void k_psd_scale_wave(SegDev g, const double* _
       const double v = (a == b) ? sq(B[a * PW_LD + a])
                                 : (B[a * PW_LD + a] * B[b * PW_LD + b] + sq(B[a * PW_LD + b]));
       hdiag[g.base + c * sd + p] = v;
+    }
+  }
+}
+
+// combined-step d_s of a PSD cone (as k_psd_ds), one wave per cone:
+//   A = R^-1 dS R^-T, B = R' dZ R, V = (A B + B A)/2 + diag(lam^2) - sm I,
+//   X_ij = 2 V_ij / (lam_i + lam_j), ds = svec(R X R')
+__global__ __launch_bounds__(64) void k_psd_ds_wave(SegDev g, const double* __restrict__ dsa,
+                                                    const double* __restrict__ dza, double sm,
+                                                    double* __restrict__ ds) {
+  __shared__ double R[PW_MAT], Ri[PW_MAT], dS[PW_MAT], dZ[PW_MAT], T1[PW_MAT], Aa[PW_MAT], Bb[PW_MAT],
+      lam[PSD_KLARGE];
+  const int lane = threadIdx.x, k = g.k, sd = g.dim;
+  const int64_t N = g.count, kk = (int64_t)k * k;
+  for (int64_t c = blockIdx.x; c < N; c += gridDim.x) {
+    __syncthreads();
+    for (int e = lane; e < k * k; e += 64) {
+      R[(e / k) * PW_LD + e % k] = g.state[(int64_t)e * N + c];
+      Ri[(e / k) * PW_LD + e % k] = g.state[(kk + e) * N + c];
+    }
+    if (lane < k) lam[lane] = g.state[(3 * kk + lane) * N + c];
+    wave_smat(dsa + g.base + c * sd, k, dS, lane);
+    wave_smat(dza + g.base + c * sd, k, dZ, lane);
+    __syncthreads();
+    wave_mm(Ri, false, dS, false, k, T1, lane);   // Ri dS
+    wave_mm(T1, false, Ri, true, k, Aa, lane);    // (Ri dS) Ri'
+    wave_mm(R, true, dZ, false, k, T1, lane);     // R' dZ
+    wave_mm(T1, false, R, false, k, Bb, lane);    // (R' dZ) R
+    // V on the upper triangle, mirrored, so X is exactly symmetric before the
+    // large 1/(lam_i + lam_j) factors
+    for (int e = lane; e < k * k; e += 64) {
+      const int r = e / k, j = e % k;
+      if (j < r) continue;
+      double acc = 0;
+      for (int p = 0; p < k; ++p)
+        acc += Aa[r * PW_LD + p] * Bb[p * PW_LD + j] + Bb[r * PW_LD + p] * Aa[p * PW_LD + j];
+      double v = 0.5 * acc;
+      if (r == j) v += lam[r] * lam[r] - sm;
+      const double x = 2.0 * v / (lam[r] + lam[j]);
+      dS[r * PW_LD + j] = x;   // dS and dZ are free now
+      dS[j * PW_LD + r] = x;
+    }
+    __syncthreads();
+    wave_mm(R, false, dS, false, k, T1, lane);    // R X
+    wave_mm(T1, false, R, true, k, dZ, lane);     // (R X) R'
+    for (int p = lane; p < sd; p += 64) {
+      int j, i;
+      tri_index(p, j, i);
+      ds[g.base + c * sd + p] = dZ[i * PW_LD + j] * (i == j ? 1.0 : 1.41421356237309504880);
     }
   }
 }
