@@ -443,78 +443,10 @@ __global__ void k_nonsym_scale(SegDev g, const double* __restrict__ s, const dou
   }
 }
 
-// ---------------------------------------------------------------------------
-// PSD (k <= KM), one lane per cone; matrices row-major in local arrays
-// ---------------------------------------------------------------------------
-template <int KM>
-__device__ inline void psd_smat(const double* v, int k, double* X) {
-  int p = 0;
-  for (int j = 0; j < k; ++j)
-    for (int i = 0; i <= j; ++i, ++p) {
-      const double f = (i == j) ? 1.0 : 0.70710678118654752440;
-      X[i * KM + j] = v[p] * f;
-      X[j * KM + i] = v[p] * f;
-    }
-}
-// cyclic Jacobi eigenvalues of a symmetric matrix (destroys A); returns lambda_min
-template <int KM>
-__device__ double psd_min_eig(double* A, int k) {
-  // an off-diagonal entry below 1e-18 |A|_F moves no eigenvalue by more than
-  // rounding does, so it is not rotated away; the sweeps end when a sweep
-  // rotates nothing (quadratic convergence: a handful of sweeps), or at 60
-  double tot = 0;
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) tot += sq(A[i * KM + j]);
-  const double small = 1e-18 * sqrt(tot);
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    bool rot = false;
-    for (int p = 0; p < k - 1; ++p)
-      for (int q = p + 1; q < k; ++q) {
-        const double apq = A[p * KM + q];
-        if (!(fabs(apq) > small)) continue;
-        rot = true;
-        const double theta = (A[q * KM + q] - A[p * KM + p]) / (2.0 * apq);
-        const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(1.0 + theta * theta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int r = 0; r < k; ++r) {   // A <- A J (columns p, q)
-          const double arp = A[r * KM + p], arq = A[r * KM + q];
-          A[r * KM + p] = c * arp - s * arq;
-          A[r * KM + q] = s * arp + c * arq;
-        }
-        for (int r = 0; r < k; ++r) {   // A <- J' A (rows p, q)
-          const double apr = A[p * KM + r], aqr = A[q * KM + r];
-          A[p * KM + r] = c * apr - s * aqr;
-          A[q * KM + r] = s * apr + c * aqr;
-        }
-      }
-    if (!rot) break;
-  }
-  double m = A[0];
-  for (int i = 1; i < k; ++i) m = fmin(m, A[i * KM + i]);
-  return m;
-}
-
-// ---------------------------------------------------------------------------
-// PSD kernels: one lane per cone, with the lane's k x k matrices in an LDS
-// slice of its own (private arrays of this size would sit in scratch memory,
-// and the per-entry loops below would pay a memory round trip on every
-// access).  Blocks of a few lanes keep the slices within LDS; slice strides
-// are odd so the lanes of a block fall on distinct banks.
-// ---------------------------------------------------------------------------
-constexpr int odd_stride(int n) { return n | 1; }
-// The one per-lane PSD kernel left (the initial-point shift, run once per
-// solve) comes in two instantiations: KM = 12 (sides up to 12, eight cones per
-// workgroup) and KM = 32 (sides 13..32, the paper's limit; a 32 x 32 FP64
-// matrix is 8 KB, so four cones per workgroup keep the slices within LDS).
-// Scaling, d_s correction, step and spectral apply run one wave per cone for
-// every side (the wave kernels below).
-template <int KM> struct Psd {
-  static constexpr int MAT = KM * KM;
-  static constexpr int SVEC = KM * (KM + 1) / 2;
-  static constexpr int WS_STEP = odd_stride(3 * MAT);
-  static constexpr int TB_STEP = KM <= 12 ? 8 : 4;     // lanes (cones) per workgroup
-  static int blocks(int64_t count, int tb) { return (int)std::max<int64_t>(1, ceil_div(count, tb)); }
-};
+// PSD kernels run one wave per cone for every side up to 32 (the paper's
+// limit), with the cone's k x k matrices in LDS (the wave kernels below).  The
+// spectral apply comes in two instantiations, KM = 12 and KM = 32, for the
+// size of its per-lane arrays.
 constexpr int PSD_KSMALL = 12, PSD_KLARGE = 32;
 
 
@@ -1123,9 +1055,10 @@ __device__ bool wave_chol(double* A, int k, int lane) {
   return true;
 }
 
-// smallest eigenvalue of the symmetric A (destroyed): parallel cyclic Jacobi
-// with psd_min_eig's stopping rule (no rotation of entries at most
-// 1e-18 |A|_F; end on a sweep without rotations, or after 60)
+// smallest eigenvalue of the symmetric A (destroyed): parallel cyclic Jacobi.
+// An off-diagonal entry at most 1e-18 |A|_F moves no eigenvalue by more than
+// rounding does, so it is not rotated; the sweeps end on a sweep without
+// rotations (quadratic convergence: a handful), or after 60.
 __device__ double wave_min_eig(double* A, int k, int lane, double* rc, double* rs, int* rp, int* rq, int* flag) {
   double tot = 0;
   for (int e = lane; e < k * k; e += 64) tot += sq(A[(e / k) * PW_LD + e % k]);
@@ -1417,8 +1350,7 @@ int cone_step_sym(const SegDev& g, const double* s, const double* z, const doubl
   if (g.count == 0 || g.kind == HC_CONE_ZERO || g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) return 0;
   if (soc_large(g.kind, g.dim)) return lsoc_step(g, s, z, ds, dz, INFINITY, false, partial, st);
   if (g.kind == HC_CONE_PSD) {
-    int nbp;
-    nbp = (int)std::min<int64_t>(g.count, PSD_STEP_GRID);
+    const int nbp = (int)std::min<int64_t>(g.count, PSD_STEP_GRID);
     hipLaunchKernelGGL(k_step_psd_wave, dim3(nbp), dim3(64), 0, st, g, s, z, ds, dz, INFINITY, 0, partial);
     HC_LAUNCH_CHECK();
     return nbp;
@@ -1591,37 +1523,29 @@ __global__ void k_max_neg_eig(SegDev g, const double* __restrict__ v, double* __
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// PSD: one lane per cone (k x k matrix in an LDS slice), grid-stride over
-// the cones, one partial maximum per workgroup
-template <int KM>
-__global__ __launch_bounds__(Psd<KM>::TB_STEP) void k_psd_max_neg_eig(SegDev g, const double* __restrict__ v,
-                                                                      double* __restrict__ partial) {
-  __shared__ double wsall[Psd<KM>::TB_STEP * Psd<KM>::WS_STEP];
-  double* X = wsall + threadIdx.x * Psd<KM>::WS_STEP;
+// PSD: one wave per cone (Jacobi eigenvalues as in the step kernel),
+// grid-stride over the cones, one partial maximum per workgroup
+__global__ __launch_bounds__(64) void k_psd_max_neg_eig_wave(SegDev g, const double* __restrict__ v,
+                                                             double* __restrict__ partial) {
+  __shared__ double X[PW_MAT], rc[PSD_KLARGE / 2], rs[PSD_KLARGE / 2];
+  __shared__ int rp[PSD_KLARGE / 2], rq[PSD_KLARGE / 2], flag;
+  const int lane = threadIdx.x;
   double a = -INFINITY;
-  for (int64_t i = (int64_t)blockIdx.x * Psd<KM>::TB_STEP + threadIdx.x; i < g.count;
-       i += (int64_t)gridDim.x * Psd<KM>::TB_STEP) {
-    psd_smat<KM>(v + g.base + i * g.dim, g.k, X);
-    a = fmax(a, -psd_min_eig<KM>(X, g.k));
+  for (int64_t c = blockIdx.x; c < g.count; c += gridDim.x) {
+    __syncthreads();
+    wave_smat(v + g.base + c * g.dim, g.k, X, lane);
+    __syncthreads();
+    a = fmax(a, -wave_min_eig(X, g.k, lane, rc, rs, rp, rq, &flag));
   }
-  for (int off = Psd<KM>::TB_STEP / 2; off > 0; off >>= 1) a = fmax(a, __shfl_xor(a, off, Psd<KM>::TB_STEP));
-  if (threadIdx.x == 0) partial[blockIdx.x] = a;
+  if (lane == 0) partial[blockIdx.x] = a;
 }
 
 int cone_max_neg_eig(const SegDev& g, const double* v, double* partial, hipStream_t st) {
   if (g.count == 0 || !(g.kind == HC_CONE_NONNEG || g.kind == HC_CONE_SOC || g.kind == HC_CONE_PSD)) return 0;
   if (soc_large(g.kind, g.dim)) return lsoc_max_neg_eig(g, v, partial, st);
   if (g.kind == HC_CONE_PSD) {
-    int nbp;
-    if (g.k <= PSD_KSMALL) {
-      nbp = std::min(Psd<PSD_KSMALL>::blocks(g.count, Psd<PSD_KSMALL>::TB_STEP), PSD_STEP_GRID);
-      hipLaunchKernelGGL(k_psd_max_neg_eig<PSD_KSMALL>, dim3(nbp), dim3(Psd<PSD_KSMALL>::TB_STEP), 0, st, g, v,
-                         partial);
-    } else {
-      nbp = std::min(Psd<PSD_KLARGE>::blocks(g.count, Psd<PSD_KLARGE>::TB_STEP), PSD_STEP_GRID);
-      hipLaunchKernelGGL(k_psd_max_neg_eig<PSD_KLARGE>, dim3(nbp), dim3(Psd<PSD_KLARGE>::TB_STEP), 0, st, g, v,
-                         partial);
-    }
+    const int nbp = (int)std::min<int64_t>(g.count, PSD_STEP_GRID);
+    hipLaunchKernelGGL(k_psd_max_neg_eig_wave, dim3(nbp), dim3(64), 0, st, g, v, partial);
     HC_LAUNCH_CHECK();
     return nbp;
   }

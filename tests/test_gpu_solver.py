@@ -86,3 +86,28 @@ def test_against_oracle(name, make, precision):
     assert info["status_name"] == "solved", (name, info)
     gp = certify(prob, x, sv, z)
     assert abs(gp - ref.objective) <= 1e-7 * max(1.0, abs(ref.objective)), (gp, ref.objective)
+
+
+@pytest.mark.parametrize("name,make", [
+    ("psd_sides_to_32", lambda: W.psd_mixed(0, n=300, sides=(3, 14, 32), per_side=6)),
+    ("trace_min_32", lambda: PS.trace_min(1, k=32)[0]),
+    ("soc_balls", lambda: PS.soc_balls()[0]),
+    ("multistage_small", lambda: W.multistage_portfolio(0, n=40, k=4, T=3)),
+])
+def test_initial_point_against_oracle(name, make):
+    """The starting iterate before any iteration (Section 2.2: a KKT solve with
+    identity scaling, then s and z each moved along e by one plus the largest
+    negative cone eigenvalue when it is not positive) against the oracle's,
+    in the scaled internal coordinates and row order."""
+    prob = make()
+    o = ipm.Solver(prob)
+    g = HC.Solver(prob, max_iter=0)
+    try:
+        g.solve()
+        x, s, z, tau, kappa, perm = g.iterate()
+    finally:
+        g.close()
+    for a, b, what in ((x, o.x, "x"), (s, o.s[perm], "s"), (z, o.z[perm], "z")):
+        err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+        assert err <= 1e-9, (name, what, err)
+    assert tau == 1.0 and kappa == 1.0
