@@ -6,9 +6,9 @@
 // component-major (row base + j*count + i), so each component load of a wave is
 // one coalesced 512-byte access.  Second-order cones above 16 rows run one
 // workgroup per cone (hc_soc.hip).  PSD cones (sides up to 32) run one wave
-// per cone for the scaling, step and spectral apply (parallel Jacobi), one
-// lane per cone for the d_s correction, and one lane per (cone, svec row) for
-// the explicit (H + delta I)^-1 block.
+// per cone for the scaling, d_s correction, step, initial shift and spectral
+// apply (parallel Jacobi, products split by output entry), and one lane per
+// (cone, svec entry) for the explicit (H + delta I)^-1 block.
 //
 // Scalings are kept in spectral form H = V diag(lam) V': near the optimum
 // cond(H) exceeds 1/eps, and applying H or (H + delta I)^-1 through the
@@ -445,8 +445,8 @@ __global__ void k_nonsym_scale(SegDev g, const double* __restrict__ s, const dou
 
 // PSD kernels run one wave per cone for every side up to 32 (the paper's
 // limit), with the cone's k x k matrices in LDS (the wave kernels below).  The
-// spectral apply comes in two instantiations, KM = 12 and KM = 32, for the
-// size of its per-lane arrays.
+// spectral apply comes in two instantiations, KM = 12 and KM = 32, which size
+// its LDS arrays.
 constexpr int PSD_KSMALL = 12, PSD_KLARGE = 32;
 
 
@@ -539,8 +539,8 @@ __global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __r
   }
 }
 
-// Sides 13..32: one wave per cone for the spectral application (the per-lane
-// form's four k x k products cost k^3 dependent LDS round trips each).  The
+// Spectral application, one wave per cone (one lane per cone would pay k^3
+// dependent LDS round trips for each of the four k x k products).  The
 // wave's 64 lanes split every product by output entry; Q, X and the two
 // intermediate products live in LDS (row stride KM + 1).  With dsr the
 // kernel returns the direction recovery -dsr - H dz instead (mode 0).
