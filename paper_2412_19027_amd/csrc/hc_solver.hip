@@ -94,6 +94,12 @@ struct hc_solver {
   std::vector<int32_t> tra, trb;   // Schur assembly tasks: short ones first, then
   std::vector<int64_t> tm;         // those of more than PAIR_WIDE products (one wave each)
   int64_t ntask_short = 0;
+  // PSD segments assembled by the T = M_c A_c gather (build_psd_dense): their
+  // segment index and first T row; per column j of A the T rows and the
+  // positions of their values in A' (so new values need no rebuild)
+  std::vector<std::pair<int, int64_t>> pdense;
+  std::vector<int32_t> pe_rp, pe_e, pe_p;
+  int64_t pe_rows = 0;
   // two-level split of the Schur complement (leaf blocks + dense tail)
   int64_t nt = 0;                  // tail columns
   std::vector<int64_t> tail_last;  // envelope of the tail (see dense_cholesky), padded to ld
@@ -118,6 +124,8 @@ struct hc_solver {
   int64_t* ddmidx = nullptr;
   double* dDrT = nullptr;           // per-chunk partial sums of A'z over the dense rows
   double* dmwork = nullptr;         // scratch of the PSD M blocks (largest segment's need)
+  int32_t *dpe_rp = nullptr, *dpe_e = nullptr, *dpe_p = nullptr;
+  double* dT = nullptr;   // the T rows of the gathered PSD segments (pe_rows x n)
   int32_t *dls_cone = nullptr, *dls_col = nullptr;
   int64_t* dls_dst = nullptr;
   double *dq = nullptr, *db = nullptr, *dD = nullptr, *dE = nullptr, *dalpha = nullptr;
@@ -416,6 +424,7 @@ void equilibrate(hc_solver* S, const HostCsr& A, const HostCsr& Pf, const std::v
 constexpr int LEAF_DEGREE = 64;
 constexpr int64_t PAIR_WIDE = 1024;   // products per pair task above which one wave takes the task
 
+void build_psd_dense(hc_solver* S);
 void build_lowrank(hc_solver* S, int nd);
 
 void build_leaves(hc_solver* S) {
@@ -801,6 +810,7 @@ void setup_host(hc_solver* S, const hc_problem* p) {
   S->A = std::move(As);
   S->At = std::move(At);
   build_leaves(S);
+  build_psd_dense(S);
   if (S->leaves && nd) {   // dense rows live on tail columns only: re-index them
     std::vector<double> Adt((size_t)nd * S->nt);
     for (int d = 0; d < nd; ++d)
@@ -812,6 +822,72 @@ void setup_host(hc_solver* S, const hc_problem* p) {
   for (int64_t t = S->nt; t < S->ld; ++t) S->tail_last.push_back(t + 1);   // identity padding
   if (S->st.static_reg <= 0) S->st.static_reg = S->mixed ? 3.4526698300124393e-04 : 1e-8;
   if (S->st.dyn_reg < 0) S->st.dyn_reg = S->mixed ? std::ldexp(1.0, -46) : std::ldexp(1.0, -104);
+}
+
+// PSD segments whose row pairs would cost more than forming T = M_c A_c for
+// each of their rows (n entries per row) leave the pair tasks: their block
+// A_c' M_c A_c is added as A_e' T, a gather over the columns of A (one writer
+// per entry of S, no atomics).  Only without leaf blocks (every column is a
+// Schur column), for n up to PSD_DENSE_NMAX, and with T within 4 GiB.
+void build_psd_dense(hc_solver* S) {
+  S->pdense.clear();
+  S->pe_rp.assign(1, 0);
+  S->pe_e.clear();
+  S->pe_p.clear();
+  S->pe_rows = 0;
+  const int64_t n = S->n, m = S->m;
+  if (S->leaves || n > PSD_DENSE_NMAX || n == 0) return;
+  const HostCsr& A = S->A;
+  std::vector<int64_t> trow(m, -1);   // T row of an internal row, -1 if none
+  for (size_t si = 0; si < S->segs.size(); ++si) {
+    const Segment& g = S->segs[si];
+    if (g.kind != HC_CONE_PSD || g.count == 0) continue;
+    double pairs = 0;
+    for (int64_t c = 0; c < g.count; ++c) {
+      double sum = 0, sq = 0;
+      for (int a = 0; a < g.dim; ++a) {
+        const int64_t r = g.base + c * g.dim + a;
+        const double k = A.rp[r + 1] - A.rp[r];
+        sum += k;
+        sq += k * k;
+      }
+      pairs += 0.5 * (sum * sum + sq);
+    }
+    const int64_t rows = g.count * g.dim;
+    if (!(pairs > (double)rows * (double)n)) continue;
+    if ((double)(S->pe_rows + rows) * (double)n * 8.0 > 4294967296.0) continue;
+    S->pdense.push_back({(int)si, S->pe_rows});
+    for (int64_t e = 0; e < rows; ++e) trow[g.base + e] = S->pe_rows + e;
+    S->pe_rows += rows;
+  }
+  if (S->pdense.empty()) return;
+  // drop the pair tasks of those segments (both rows of a task lie in one cone)
+  const int64_t nt = (int64_t)S->tra.size();
+  int64_t keep = 0, keep_short = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    if (trow[S->tra[t]] >= 0) continue;
+    if (t < S->ntask_short) keep_short++;
+    S->tra[keep] = S->tra[t];
+    S->trb[keep] = S->trb[t];
+    S->tm[keep] = S->tm[t];
+    keep++;
+  }
+  S->tra.resize(keep);
+  S->trb.resize(keep);
+  S->tm.resize(keep);
+  S->ntask_short = keep_short;
+  // per column j: the T rows of its entries in those segments
+  const HostCsr& At = S->At;
+  S->pe_rp.assign(n + 1, 0);
+  for (int64_t j = 0; j < n; ++j) {
+    for (int32_t p = At.rp[j]; p < At.rp[j + 1]; ++p) {
+      const int64_t e = trow[At.ci[p]];
+      if (e < 0) continue;
+      S->pe_e.push_back((int32_t)e);
+      S->pe_p.push_back(p);
+    }
+    S->pe_rp[j + 1] = (int32_t)S->pe_e.size();
+  }
 }
 
 // (cone, column) entries of the rank-2 rows of the large second-order cones
@@ -1173,6 +1249,13 @@ void factor(hc_solver* S, bool fp64 = false) {
     const int64_t ns = S->ntask_short, nl = (int64_t)S->tra.size() - ns;
     assemble_pairs(ns, S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->ld, S->dS, false, st);
     assemble_pairs(nl, S->dtra + ns, S->dtrb + ns, S->dtm + ns, S->dmval, S->dA, S->ld, S->dS, true, st);
+    if (!S->pdense.empty()) {
+      for (const auto& pd : S->pdense) {
+        const Segment& g = S->segs[pd.first];
+        psd_dense_T(g.base, g.dim, g.count, g.moff, S->dmval, S->dA, S->n, S->dT + pd.second * S->n, st);
+      }
+      dense_T_gather(S->n, S->dpe_rp, S->dpe_e, S->dpe_p, S->dAt.val, S->dT, S->ld, S->dS, st);
+    }
   }
   const int nd = (int)S->drows.size();
   if (S->K1 > 0) {
@@ -1803,6 +1886,10 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
     }
     S->dmwork = buf.take<double>(mw);
   }
+  S->dpe_rp = upload(buf, S->pe_rp, st);
+  S->dpe_e = upload(buf, S->pe_e, st);
+  S->dpe_p = upload(buf, S->pe_p, st);
+  S->dT = buf.take<double>(std::max<size_t>(1, (size_t)S->pe_rows * (size_t)S->n));
   S->dpart = buf.take<double>(S->npart);
   S->dmask = buf.take<unsigned long long>(S->npart);
   const int64_t L = std::max(n, m);

@@ -34,6 +34,18 @@ void add_P_delta(const Csr& P, int64_t n, double delta, int64_t ld, double* S, h
 // wide: one wave per task (long rows) instead of one lane
 void assemble_pairs(int64_t ntask, const int32_t* tra, const int32_t* trb, const int64_t* tm, const double* mval,
                     const Csr& A, int64_t ld, double* S, bool wide, hipStream_t st);
+// Schur contribution of PSD cones whose blocks touch most columns, as a
+// gather instead of row-pair atomics: T = M_c A_c for every row of the
+// segment (psd_dense_T, row-major rows of n doubles starting at T), then the
+// lower triangle of S gains A_e' T over the rows of all such segments
+// (dense_T_gather, erp/ee/ep: per column j of A the T rows e and the
+// positions in atval of the values A[row(e), j]).  n <= PSD_DENSE_NMAX (one
+// LDS row of n doubles per workgroup).
+constexpr int64_t PSD_DENSE_NMAX = 8192;
+void psd_dense_T(int64_t base, int32_t dim, int64_t count, int64_t moff, const double* mval, const Csr& A, int64_t n,
+                 double* T, hipStream_t st);
+void dense_T_gather(int64_t n, const int32_t* erp, const int32_t* ee, const int32_t* ep, const double* atval,
+                    const double* T, int64_t ld, double* S, hipStream_t st);
 void scale_dense_rows(int nd, int64_t n, const double* Ad, const int64_t* midx, const double* mval, double* B,
                       hipStream_t st);
 void aos_to_cm(int64_t count, int dim, const double* a, double* c, bool inverse, hipStream_t st);

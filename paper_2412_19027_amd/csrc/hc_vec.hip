@@ -371,6 +371,67 @@ void assemble_pairs(int64_t ntask, const int32_t* tra, const int32_t* trb, const
   HC_LAUNCH_CHECK();
 }
 
+// T[e, :] = sum_b M_c[a, b] A[row b of cone c, :] for segment row e = c dim + a
+// (M_c symmetric, stored as its lower triangle: entry (a, b), a >= b, at
+// moff + (a (a + 1) / 2 + b) count + c).  One workgroup per row, the n-entry
+// sum in LDS (FP64 LDS atomics: rows of the cone share columns).
+__global__ __launch_bounds__(256) void k_psd_dense_T(int64_t base, int32_t dim, int64_t count, int64_t moff,
+                                                     const double* __restrict__ mval, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const double* __restrict__ av,
+                                                     int64_t n, double* __restrict__ T) {
+  extern __shared__ double acc[];
+  const int64_t rows = count * dim;
+  for (int64_t e = blockIdx.x; e < rows; e += gridDim.x) {
+    const int64_t c = e / dim;
+    const int a = (int)(e % dim);
+    __syncthreads();   // the previous row's readers are done
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) acc[j] = 0.0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < dim; b += blockDim.x) {
+      const int hi = a > b ? a : b, lo = a > b ? b : a;
+      const double m = mval[moff + ((int64_t)hi * (hi + 1) / 2 + lo) * count + c];
+      const int64_t rb = base + c * dim + b;
+      for (int32_t p = rp[rb]; p < rp[rb + 1]; ++p) atomicAdd(&acc[ci[p]], m * av[p]);
+    }
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) T[e * n + j] = acc[j];
+  }
+}
+void psd_dense_T(int64_t base, int32_t dim, int64_t count, int64_t moff, const double* mval, const Csr& A, int64_t n,
+                 double* T, hipStream_t st) {
+  const int64_t rows = count * dim;
+  if (rows == 0) return;
+  hipLaunchKernelGGL(k_psd_dense_T, dim3((unsigned)std::min<int64_t>(rows, 8192)), dim3(256), n * sizeof(double), st,
+                     base, dim, count, moff, mval, A.rowptr, A.col, A.val, n, T);
+  HC_LAUNCH_CHECK();
+}
+
+// S[j, k] += sum_e A[row(e), j] T[e, k] for k <= j: one workgroup per column
+// j of A (row j of S), lanes over k, so each entry has one writer and the T
+// rows are read contiguously
+__global__ __launch_bounds__(256) void k_dense_T_gather(int64_t n, const int32_t* __restrict__ erp,
+                                                        const int32_t* __restrict__ ee, const int32_t* __restrict__ ep,
+                                                        const double* __restrict__ atval,
+                                                        const double* __restrict__ T, int64_t ld,
+                                                        double* __restrict__ S) {
+  for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
+    const int32_t b = erp[j], e = erp[j + 1];
+    if (b == e) continue;
+    for (int64_t k = threadIdx.x; k <= j; k += blockDim.x) {
+      double s = 0.0;
+      for (int32_t p = b; p < e; ++p) s += atval[ep[p]] * T[(int64_t)ee[p] * n + k];
+      S[j + k * ld] += s;
+    }
+  }
+}
+void dense_T_gather(int64_t n, const int32_t* erp, const int32_t* ee, const int32_t* ep, const double* atval,
+                    const double* T, int64_t ld, double* S, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_dense_T_gather, dim3((unsigned)std::min<int64_t>(n, 8192)), dim3(256), 0, st, n, erp, ee, ep,
+                     atval, T, ld, S);
+  HC_LAUNCH_CHECK();
+}
+
 // B (nd x n row-major, i.e. n x nd column-major with ld n) = sqrt|m_r| Ad[r, :];
 // rows with midx < 0 are padding and stay zero
 __global__ void k_scale_dense_rows(int nd, int64_t n, const double* __restrict__ Ad, const int64_t* __restrict__ midx,

@@ -40,6 +40,9 @@ CASES = [
     ("psdpow_small", lambda: W.psd_pow(0, n=250, n_pow=120, n_psd=25, k=4)),
     ("multistage_small", lambda: W.multistage_portfolio(0, n=40, k=4, T=3)),
     ("multistage_dense_rows", lambda: W.multistage_portfolio(1, n=600, k=6, T=2)),
+    # PSD sides 14 and 32 touch most of the 300 columns: their blocks enter S
+    # through T = M_c A_c and a column gather, side 3 through row pairs
+    ("psd_gathered", lambda: W.psd_mixed(0, n=300, sides=(3, 14, 32), per_side=6)),
 ]
 
 
