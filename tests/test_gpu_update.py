@@ -1,6 +1,8 @@
 """Parametric re-solve (hc_update_data): a solver set up for one problem
 and given the values of another problem of the same structure solves that
 problem as a fresh set-up does, against the oracle's objective."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -29,6 +31,12 @@ PAIRS = [
     # transaction cost and inflow: new q and b on the same structure
     ("multistage", lambda s: W.multistage_portfolio(0, n=40, k=4, T=3, gamma=1.0 + s, cost=0.01 * (1 + s),
                                                     inflow=0.1 - 0.05 * s)),
+    # PSD sides 14 and 32 assembled through T = M_c A_c and the column gather
+    # (its value positions follow new A values): A scaled by 1.1, which keeps
+    # the problem feasible (x / 1.1 and z / 1.1 are feasible)
+    ("psd_gathered", lambda s: dataclasses.replace(
+        W.psd_mixed(0, n=300, sides=(3, 14, 32), per_side=6),
+        A=W.psd_mixed(0, n=300, sides=(3, 14, 32), per_side=6).A * (1.0 + 0.1 * s))),
 ]
 
 
