@@ -716,32 +716,31 @@ __global__ __launch_bounds__(256) void k_psd_mblock_g(SegDev g, double delta, do
   }
 }
 
-__global__ __launch_bounds__(576) void k_psd_mblock(SegDev g, const double* __restrict__ G) {
+__device__ inline void tri_index(int e, int& i, int& j);
+
+// one thread per (cone, packed entry p = a (a + 1) / 2 + b): the grid's y
+// dimension covers a cone's entries, so even a few large cones fill the chip
+__global__ __launch_bounds__(256) void k_psd_mblock(SegDev g, const double* __restrict__ G) {
   __shared__ double Q[PSD_KLARGE * (PSD_KLARGE + 1)];
   const int k = g.k, LQ = PSD_KLARGE + 1, sd = g.dim;
   const int64_t N = g.count, kk = (int64_t)k * k, c = blockIdx.x;
   for (int e = threadIdx.x; e < k * k; e += blockDim.x) Q[(e / k) * LQ + e % k] = g.state[(2 * kk + e) * N + c];
   __syncthreads();
-  const int a = threadIdx.x;
-  if (a >= sd) return;
-  int ja = (int)((sqrt(8.0 * a + 1.0) - 1.0) / 2.0);
-  while (ja * (ja + 1) / 2 > a) --ja;
-  while ((ja + 1) * (ja + 2) / 2 <= a) ++ja;
-  const int ia = a - ja * (ja + 1) / 2;
-  const double ca = (ia == ja) ? 1.0 : 1.41421356237309504880;
-  const double* Gc = G + c * k * kk;
-  for (int jb = 0; jb <= ja; ++jb)
-    for (int ib = 0; ib <= jb; ++ib) {
-      const int b = jb * (jb + 1) / 2 + ib;
-      if (b > a) break;
-      const double cb = (ib == jb) ? 1.0 : 1.41421356237309504880;
-      double acc = 0;
-      for (int i = 0; i < k; ++i) {
-        const double* Gi = Gc + (int64_t)i * kk + (int64_t)ja * k;
-        acc += Q[ia * LQ + i] * (Q[ib * LQ + i] * Gi[jb] + Q[jb * LQ + i] * Gi[ib]);
-      }
-      g.mblk[((int64_t)a * (a + 1) / 2 + b) * N + c] = 0.5 * ca * cb * acc;
-    }
+  const int np = sd * (sd + 1) / 2;
+  const int p = (int)blockIdx.y * (int)blockDim.x + (int)threadIdx.x;
+  if (p >= np) return;
+  int a, b, ja, ia, jb, ib;
+  tri_index(p, a, b);
+  tri_index(a, ja, ia);
+  tri_index(b, jb, ib);
+  const double ca = (ia == ja) ? 1.0 : 1.41421356237309504880, cb = (ib == jb) ? 1.0 : 1.41421356237309504880;
+  const double* Gc = G + c * k * kk + (int64_t)ja * k;
+  double acc = 0;
+  for (int i = 0; i < k; ++i) {
+    const double* Gi = Gc + (int64_t)i * kk;
+    acc += Q[ia * LQ + i] * (Q[ib * LQ + i] * Gi[jb] + Q[jb * LQ + i] * Gi[ib]);
+  }
+  g.mblk[(int64_t)p * N + c] = 0.5 * ca * cb * acc;
 }
 
 __global__ void k_cone_mblock(SegDev g, double delta) {
@@ -807,8 +806,8 @@ void cone_mblock(const SegDev& g, double delta, double* work, hipStream_t st) {
   if (g.kind == HC_CONE_PSD) {
     hipLaunchKernelGGL(k_psd_mblock_g, dim3((unsigned)g.count, (unsigned)g.k), dim3(256), 0, st, g, delta, work);
     HC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_psd_mblock, dim3((unsigned)g.count), dim3((unsigned)(ceil_div(g.dim, 64) * 64)), 0, st, g,
-                       (const double*)work);
+    hipLaunchKernelGGL(k_psd_mblock, dim3((unsigned)g.count, (unsigned)ceil_div((int64_t)g.dim * (g.dim + 1) / 2, 256)),
+                       dim3(256), 0, st, g, (const double*)work);
   } else
     hipLaunchKernelGGL(k_cone_mblock, dim3((unsigned)std::max<int64_t>(1, ceil_div(g.count, CONE_BLOCK))),
                        dim3(CONE_BLOCK), 0, st, g, delta);
