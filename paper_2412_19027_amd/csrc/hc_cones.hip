@@ -1330,18 +1330,23 @@ __global__ __launch_bounds__(64) void k_step_psd_wave(SegDev g, const double* __
   __shared__ int rp[PSD_KLARGE / 2], rq[PSD_KLARGE / 2], flag;
   const int lane = threadIdx.x, sd = g.dim;
   double best = INFINITY;
-  for (int64_t c = blockIdx.x; c < g.count; c += gridDim.x) {
-    const int64_t o = g.base + c * sd;
-    const double a1 = wave_step_one(s + o, ds + o, g.k, lane, L, D, T, rc, rs, rp, rq, &flag);
-    const double a2 = wave_step_one(z + o, dz + o, g.k, lane, L, D, T, rc, rs, rp, rq, &flag);
-    const double a = fmin(a1, a2);
-    if (per_cone) {
-      if (lane == 0) out[c] = fmin(amax, a);
-    } else {
-      best = fmin(best, a);
+  if (per_cone) {
+    for (int64_t c = blockIdx.x; c < g.count; c += gridDim.x) {
+      const int64_t o = g.base + c * sd;
+      const double a1 = wave_step_one(s + o, ds + o, g.k, lane, L, D, T, rc, rs, rp, rq, &flag);
+      const double a2 = wave_step_one(z + o, dz + o, g.k, lane, L, D, T, rc, rs, rp, rq, &flag);
+      if (lane == 0) out[c] = fmin(amax, fmin(a1, a2));
     }
+    return;
   }
-  if (!per_cone && lane == 0) out[blockIdx.x] = best;
+  // the minimum over all cones: the s and z halves of a cone are separate
+  // tasks, so twice as many waves share the chip
+  for (int64_t t = blockIdx.x; t < 2 * g.count; t += gridDim.x) {
+    const int64_t o = g.base + (t >> 1) * sd;
+    const bool zh = (t & 1) != 0;
+    best = fmin(best, wave_step_one((zh ? z : s) + o, (zh ? dz : ds) + o, g.k, lane, L, D, T, rc, rs, rp, rq, &flag));
+  }
+  if (lane == 0) out[blockIdx.x] = best;
 }
 
 int cone_step_sym(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz,
@@ -1349,7 +1354,7 @@ int cone_step_sym(const SegDev& g, const double* s, const double* z, const doubl
   if (g.count == 0 || g.kind == HC_CONE_ZERO || g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) return 0;
   if (soc_large(g.kind, g.dim)) return lsoc_step(g, s, z, ds, dz, INFINITY, false, partial, st);
   if (g.kind == HC_CONE_PSD) {
-    const int nbp = (int)std::min<int64_t>(g.count, PSD_STEP_GRID);
+    const int nbp = (int)std::min<int64_t>(2 * g.count, PSD_STEP_GRID);
     hipLaunchKernelGGL(k_step_psd_wave, dim3(nbp), dim3(64), 0, st, g, s, z, ds, dz, INFINITY, 0, partial);
     HC_LAUNCH_CHECK();
     return nbp;
