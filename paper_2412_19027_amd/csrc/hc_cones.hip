@@ -539,24 +539,26 @@ __global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __r
   }
 }
 
-// Spectral application, one wave per cone (one lane per cone would pay k^3
-// dependent LDS round trips for each of the four k x k products).  The
-// wave's 64 lanes split every product by output entry; Q, X and the two
-// intermediate products live in LDS (row stride KM + 1).  With dsr the
-// kernel returns the direction recovery -dsr - H dz instead (mode 0).
+// Spectral application, one workgroup per cone (one lane per cone would pay
+// k^3 dependent LDS round trips for each of the four k x k products): one
+// wave up to side 12, four above.  The threads split every product by output
+// entry; Q, X and the two intermediate products live in LDS (row stride
+// KM + 1).  With dsr the kernel returns the direction recovery -dsr - H dz
+// instead (mode 0).
 template <int KM>
-__global__ __launch_bounds__(64) void k_psd_apply_wave(SegDev g, int mode, double delta, const double* __restrict__ x,
+__global__ __launch_bounds__(KM <= 12 ? 64 : 256) void k_psd_apply_wave(SegDev g, int mode, double delta, const double* __restrict__ x,
                                                        const double* __restrict__ dsr, double* __restrict__ y) {
   constexpr int LD = KM + 1;
   __shared__ double Q[KM * LD], X[KM * LD], T[KM * LD], U[KM * LD], m[KM];
   const int k = g.k, lane = threadIdx.x, sd = g.dim;
   const int64_t N = g.count, kk = (int64_t)k * k;
+  constexpr int NT = KM <= 12 ? 64 : 256;   // four waves per cone above side 12
   for (int64_t c = blockIdx.x; c < N; c += gridDim.x) {
     const double* xc = x + g.base + c * sd;
     __syncthreads();   // the previous cone's readers are done
-    for (int e = lane; e < k * k; e += 64) Q[(e / k) * LD + e % k] = g.state[(2 * kk + e) * N + c];
-    for (int e = lane; e < k; e += 64) m[e] = g.state[(3 * kk + k + e) * N + c];
-    for (int p = lane; p < sd; p += 64) {   // smat: svec entry p is (i, j), i <= j, column by column
+    for (int e = lane; e < k * k; e += NT) Q[(e / k) * LD + e % k] = g.state[(2 * kk + e) * N + c];
+    for (int e = lane; e < k; e += NT) m[e] = g.state[(3 * kk + k + e) * N + c];
+    for (int p = lane; p < sd; p += NT) {   // smat: svec entry p is (i, j), i <= j, column by column
       int j = (int)((sqrt(8.0 * p + 1.0) - 1.0) / 2.0);
       while (j * (j + 1) / 2 > p) --j;
       while ((j + 1) * (j + 2) / 2 <= p) ++j;
@@ -566,14 +568,14 @@ __global__ __launch_bounds__(64) void k_psd_apply_wave(SegDev g, int mode, doubl
       X[j * LD + i] = v;
     }
     __syncthreads();
-    for (int e = lane; e < k * k; e += 64) {   // T = X Q
+    for (int e = lane; e < k * k; e += NT) {   // T = X Q
       const int i = e / k, j = e % k;
       double acc = 0;
       for (int p = 0; p < k; ++p) acc += X[i * LD + p] * Q[p * LD + j];
       T[i * LD + j] = acc;
     }
     __syncthreads();
-    for (int e = lane; e < k * k; e += 64) {   // U = Q' T
+    for (int e = lane; e < k * k; e += NT) {   // U = Q' T
       const int i = e / k, j = e % k;
       double acc = 0;
       for (int p = 0; p < k; ++p) acc += Q[p * LD + i] * T[p * LD + j];
@@ -581,27 +583,27 @@ __global__ __launch_bounds__(64) void k_psd_apply_wave(SegDev g, int mode, doubl
     }
     __syncthreads();
     // average the two roundings of each eigen-coefficient, then scale
-    for (int e = lane; e < k * k; e += 64) {
+    for (int e = lane; e < k * k; e += NT) {
       const int i = e / k, j = e % k;
       const double lam = m[i] * m[j];
       T[i * LD + j] = 0.5 * (U[i * LD + j] + U[j * LD + i]) * (mode == 0 ? lam : 1.0 / (lam + delta));
     }
     __syncthreads();
-    for (int e = lane; e < k * k; e += 64) {   // U = T Q'
+    for (int e = lane; e < k * k; e += NT) {   // U = T Q'
       const int i = e / k, j = e % k;
       double acc = 0;
       for (int p = 0; p < k; ++p) acc += T[i * LD + p] * Q[j * LD + p];
       U[i * LD + j] = acc;
     }
     __syncthreads();
-    for (int e = lane; e < k * k; e += 64) {   // X = Q U
+    for (int e = lane; e < k * k; e += NT) {   // X = Q U
       const int i = e / k, j = e % k;
       double acc = 0;
       for (int p = 0; p < k; ++p) acc += Q[i * LD + p] * U[p * LD + j];
       X[i * LD + j] = acc;
     }
     __syncthreads();
-    for (int p = lane; p < sd; p += 64) {   // svec of the upper triangle
+    for (int p = lane; p < sd; p += NT) {   // svec of the upper triangle
       int j = (int)((sqrt(8.0 * p + 1.0) - 1.0) / 2.0);
       while (j * (j + 1) / 2 > p) --j;
       while ((j + 1) * (j + 2) / 2 <= p) ++j;
@@ -622,7 +624,7 @@ void cone_apply(const SegDev& g, int mode, double delta, const double* x, double
       hipLaunchKernelGGL(k_psd_apply_wave<PSD_KSMALL>, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0,
                          st, g, mode, delta, x, (const double*)nullptr, y);
     else
-      hipLaunchKernelGGL(k_psd_apply_wave<PSD_KLARGE>, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0,
+      hipLaunchKernelGGL(k_psd_apply_wave<PSD_KLARGE>, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(256), 0,
                          st, g, mode, delta, x, (const double*)nullptr, y);
   else
     hipLaunchKernelGGL(k_cone_apply, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, mode, delta, x, y);
@@ -682,7 +684,7 @@ void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, dou
       hipLaunchKernelGGL(k_psd_apply_wave<PSD_KSMALL>, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0,
                          st, g, 0, 0.0, dz, dsrhs, out);
     else
-      hipLaunchKernelGGL(k_psd_apply_wave<PSD_KLARGE>, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(64), 0,
+      hipLaunchKernelGGL(k_psd_apply_wave<PSD_KLARGE>, dim3((unsigned)std::min<int64_t>(g.count, 4096)), dim3(256), 0,
                          st, g, 0, 0.0, dz, dsrhs, out);
   else
     hipLaunchKernelGGL(k_cone_recover, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, dsrhs, dz, out);
