@@ -122,6 +122,12 @@ typedef struct {
   size_t arena_bytes;
   void* stream;         /* hipStream_t to run on; NULL = the null stream          */
   int32_t device;       /* HIP device ordinal                                     */
+  void* host_stage;     /* pinned host memory (hipHostMalloc) for the per-iteration
+                           read-backs of reduction partials, owned by the caller
+                           and used only while the handle runs; NULL, or fewer
+                           than hc_host_stage_bytes bytes: the library allocates
+                           (and frees) its own                                     */
+  size_t host_stage_bytes;
 } hc_device;
 
 /* ---- results -------------------------------------------------------------- */
@@ -162,6 +168,16 @@ typedef struct {
                               1e-6 (1 + |rhs|_inf) or not finite                 */
   int64_t n_leaves;        /* leaf blocks factored ahead of the tail               */
   int64_t leaf_columns;    /* columns inside leaf blocks (n = leaf_columns + n_ordered) */
+  int64_t psd_gathered_rows; /* rows of PSD cones whose Schur blocks enter through
+                              T = M_c A_c and a column gather (0: row pairs only)  */
+  double cone_kernel_ms;   /* with settings.profile: summed device time (events on
+                              the handle's stream) of the cone-layer launches:
+                              scaling, M blocks, H applications, d_s, direction
+                              recovery and step lengths                           */
+  double cone_bytes;       /* their algorithmic HBM bytes (each launch's minimum
+                              reads and writes of iterate, direction and scaling
+                              state)                                              */
+  int64_t cone_launches;
 } hc_info;
 
 typedef struct hc_solver hc_solver;
@@ -178,6 +194,9 @@ int32_t hc_setup(hc_solver** out, const hc_problem* prob, const hc_settings* set
 
 /* Device bytes hc_bind needs for this handle (arena size). */
 int32_t hc_workspace_bytes(const hc_solver* s, size_t* bytes);
+/* Pinned host bytes of the read-back staging (hc_device.host_stage) this
+ * handle needs.  HC_ERR_INVALID_ARG on NULL. */
+int32_t hc_host_stage_bytes(const hc_solver* s, size_t* bytes);
 
 /* Place the solver on a device: sub-allocate the arena (or allocate) and upload
  * the data.  The arena and stream must outlive the
@@ -192,10 +211,13 @@ int32_t hc_solve(hc_solver* s);
 
 int32_t hc_get_info(const hc_solver* s, hc_info* out);
 
-/* Solution in the user's row order, unscaled and divided by tau: x (n), s (m),
- * z (m), caller-owned host buffers (any may be NULL).  For an infeasible
- * status the unnormalised certificate is returned instead. */
-int32_t hc_get_solution(const hc_solver* s, double* x, double* sv, double* z);
+/* Solution in the user's row order, unscaled and divided by tau (Sec. 2.2:
+ * x/tau, s/tau, z/tau): x (n), s (m), z (m), caller-owned buffers (any may be
+ * NULL).  on_device = 0: host buffers; nonzero: device buffers of the handle's
+ * device, written by a kernel on the handle's stream (complete on return).
+ * For an infeasible status the unnormalised certificate (eq.
+ * infeasibility-check) is returned instead.  HC_ERR_STATE before hc_bind. */
+int32_t hc_get_solution(const hc_solver* s, double* x, double* sv, double* z, int32_t on_device);
 
 /* Raw internal iterate (scaled, rows in the library's family order):
  * x (n), s (m), z (m), tau, kappa; and the internal->user row map (m int64). */
@@ -276,23 +298,34 @@ const char* hc_status_str(int32_t status);
  *   z + alpha dz in the closed cones (nonneg/SOC/PSD: exact boundary step;
  *   exp/pow: interior membership tested at alpha = amax * 0.8^j, j = 0..63,
  *   reported as the first passing trial, or 0).
+ * hc_test_cone_step_min: the minimum over all `count` cones of that exact
+ *   boundary step (no cap; INFINITY when no direction leaves its cone), by the
+ *   launch hc_solve uses for the step length (Sec. 2.2, "Update iterates"),
+ *   written to the host double *alpha_min.  Nonneg, SOC and PSD only
+ *   (HC_ERR_INVALID_ARG otherwise).
+ * force_dual (scale, mblock, ds): nonzero selects the dual scaling
+ *   H = mu grad^2 f(z) for exp/pow cones (Appendix A), as hc_solve does after a
+ *   short primal-dual step; ignored by the symmetric families.
  */
 int32_t hc_test_cone_scale(int32_t type, int64_t count, int32_t dim, const double* alpha,
-                           const double* s, const double* z, double mu, double* H_out,
-                           double* lam_out, int32_t* branch_out, void* stream);
+                           const double* s, const double* z, double mu, int32_t force_dual,
+                           double* H_out, double* lam_out, int32_t* branch_out, void* stream);
 /* hc_test_cone_mblock: the explicit blocks M_c = (H_c + delta I)^-1 that the
  *   Schur complement is assembled from (eq. linsys_2x2 with the cone rows
  *   eliminated first), at the scaling of (s, z); M_out (device, count x rows
  *   x rows, dense symmetric).  delta > 0. */
 int32_t hc_test_cone_mblock(int32_t type, int64_t count, int32_t dim, const double* alpha,
-                            const double* s, const double* z, double mu, double delta, double* M_out,
-                            void* stream);
+                            const double* s, const double* z, double mu, int32_t force_dual,
+                            double delta, double* M_out, void* stream);
 int32_t hc_test_cone_ds(int32_t type, int64_t count, int32_t dim, const double* alpha,
                         const double* s, const double* z, const double* dsa, const double* dza,
-                        double mu, double sm, double* ds_out, void* stream);
+                        double mu, int32_t force_dual, double sm, double* ds_out, void* stream);
 int32_t hc_test_cone_step(int32_t type, int64_t count, int32_t dim, const double* alpha,
                           const double* s, const double* z, const double* ds, const double* dz,
                           double amax, double* alpha_out, void* stream);
+int32_t hc_test_cone_step_min(int32_t type, int64_t count, int32_t dim, const double* alpha,
+                              const double* s, const double* z, const double* ds, const double* dz,
+                              double* alpha_min, void* stream);
 
 /* Dense Cholesky of an SPD matrix (device, column-major, n x n, leading dim
  * ld >= n, lower triangle referenced) followed by the solve of `nrhs`

@@ -360,47 +360,12 @@ class Solver:
     def ds_combined(self, scal, dsa, dza, sigma, mu):
         """d_s of the combined step (eq. ds-correction-step), per family."""
         ds = np.zeros(self.m)
-        sm = sigma * mu
         for g, sc in zip(self.groups, scal):
             r = g.rows
             if g.kind == ZERO:
                 continue
-            s, z = self.s[r], self.z[r]
-            a, b_ = dsa[r], dza[r]
-            if g.kind == NONNEG:
-                lam = sc["lam"]
-                w = sc["w"]
-                eta = (a / w) * (w * b_)
-                v = lam * lam + eta - sm
-                ds[r] = w * (v / lam)
-            elif g.kind == SOC:
-                W, Winv, lam = sc["W"], sc["Winv"], sc["lam"]
-                Wi_ds = np.einsum("cji,cj->ci", Winv, a)       # W^-T ds
-                W_dz = np.einsum("cij,cj->ci", W, b_)
-                eta = C.soc_circ(Wi_ds, W_dz)
-                e = np.zeros_like(lam)
-                e[:, 0] = 1.0
-                v = C.soc_circ(lam, lam) + eta - sm * e
-                ds[r] = np.einsum("cji,cj->ci", W, C.soc_inv_circ(lam, v))   # W' (lam \ v)
-            elif g.kind == PSD:
-                k = g.k
-                R, Rinv, lam = sc["R"], sc["Rinv"], sc["lam"]
-                dS = C.smat(a, k)
-                dZ = C.smat(b_, k)
-                Aa = np.einsum("cij,cjk,clk->cil", Rinv, dS, Rinv)    # R^-1 dS R^-T
-                Bb = np.einsum("cji,cjk,ckl->cil", R, dZ, R)          # R' dZ R
-                eta = C.psd_circ(Aa, Bb)
-                V = eta.copy()
-                V += np.einsum("ci,ij->cij", lam * lam, np.eye(k))
-                V -= sm * np.eye(k)[None]
-                X = 2.0 * V / (lam[:, :, None] + lam[:, None, :])
-                ds[r] = C.svec(np.einsum("cij,cjk,clk->cil", R, X, R))   # R X R'
-            else:
-                fam = _fam(g)
-                g_ = sc["grad"]
-                u = fam.hinv_apply(sc["hinv"], a)                       # Hf^-1 ds_a
-                eta = -0.5 * fam.third(z, b_, u)
-                ds[r] = s + sm * g_ + eta
+            ds[r] = ds_family(g.kind, self.s[r], self.z[r], sc, dsa[r], dza[r], sigma * mu,
+                              k=g.k, fam=_fam(g) if g.kind in (EXP, POW) else None)
         return ds
 
     def H_apply(self, scal, v):
@@ -571,3 +536,46 @@ def solve(prob, **kw):
     s = Solver(prob, Settings(**kw))
     s.solve()
     return s
+
+
+def ds_family(kind, s, z, sc, dsa, dza, sm, k=0, fam=None):
+    """d_s of the combined step (eq. ds-correction-step) for the cones of one family.
+
+    s, z, dsa, dza: (N, d) rows of the N cones; sc: that family's scaling state
+    (Solver.scale); sm = sigma * mu.
+      nonneg/SOC/PSD: d_s = W'(lambda \\ (lambda o lambda + eta - sm e)) with the
+        Mehrotra term eta = (W^-T ds_a) o (W dz_a);
+      exp/pow: d_s = s + sm grad f(z) - 1/2 grad^3 f(z)[dz_a, grad^2 f(z)^-1 ds_a].
+    """
+    a, b_ = dsa, dza
+    if kind == NONNEG:
+        lam = sc["lam"]
+        w = sc["w"]
+        eta = (a / w) * (w * b_)
+        v = lam * lam + eta - sm
+        return w * (v / lam)
+    if kind == SOC:
+        W, Winv, lam = sc["W"], sc["Winv"], sc["lam"]
+        Wi_ds = np.einsum("cji,cj->ci", Winv, a)       # W^-T ds
+        W_dz = np.einsum("cij,cj->ci", W, b_)
+        eta = C.soc_circ(Wi_ds, W_dz)
+        e = np.zeros_like(lam)
+        e[:, 0] = 1.0
+        v = C.soc_circ(lam, lam) + eta - sm * e
+        return np.einsum("cji,cj->ci", W, C.soc_inv_circ(lam, v))   # W' (lam \\ v)
+    if kind == PSD:
+        R, Rinv, lam = sc["R"], sc["Rinv"], sc["lam"]
+        dS = C.smat(a, k)
+        dZ = C.smat(b_, k)
+        Aa = np.einsum("cij,cjk,clk->cil", Rinv, dS, Rinv)    # R^-1 dS R^-T
+        Bb = np.einsum("cji,cjk,ckl->cil", R, dZ, R)          # R' dZ R
+        eta = C.psd_circ(Aa, Bb)
+        V = eta.copy()
+        V += np.einsum("ci,ij->cij", lam * lam, np.eye(k))
+        V -= sm * np.eye(k)[None]
+        X = 2.0 * V / (lam[:, :, None] + lam[:, None, :])
+        return C.svec(np.einsum("cij,cjk,clk->cil", R, X, R))   # R X R'
+    g_ = sc["grad"]
+    u = fam.hinv_apply(sc["hinv"], a)                       # Hf^-1 ds_a
+    eta = -0.5 * fam.third(z, b_, u)
+    return s + sm * g_ + eta

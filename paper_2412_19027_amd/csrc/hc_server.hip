@@ -3,8 +3,9 @@
 // Requests are validated and analysed on the submitting thread (hc_setup),
 // queued first-in first-out, and admitted into active slots while their
 // device workspace fits the HBM budget; the workspace is carved from one
-// device pool allocated at creation, so admission and retirement never call
-// hipMalloc or hipFree.  Worker threads each own a stream (default priority)
+// device pool allocated at creation, and the pinned read-back staging is one
+// block per slot allocated when a worker starts, so admission and retirement
+// never allocate or free memory.  Worker threads each own a stream (default priority)
 // and a share of the slots; every tick advances each of a worker's active
 // problems by one pass of the loop body of Algorithm 1, so short and long
 // solves interleave and a finished problem frees its slot and memory for the
@@ -29,6 +30,11 @@
 
 namespace {
 
+// pinned read-back block per slot: enough for the reduction partials and
+// step masks of problems with a few dozen cone segments; a problem that
+// needs more allocates its own at bind
+constexpr size_t kStageBytes = (size_t)1 << 20;
+
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -37,6 +43,7 @@ struct Job {
   uint64_t ticket = 0, tag = 0;
   hc_solver* h = nullptr;
   size_t bytes = 0, offset = 0;
+  int stage = -1;                  // the worker's pinned read-back block it uses
   int64_t n = 0, m = 0;
   double t_submit = 0, t_start = 0, t_end = 0;
   int32_t status = HC_STATUS_UNSOLVED;
@@ -119,7 +126,7 @@ void hc_server::finish(const std::shared_ptr<Job>& j, int32_t rc, hipStream_t st
       j->x.resize(j->n);
       j->s.resize(j->m);
       j->z.resize(j->m);
-      rc = hc_get_solution(j->h, j->x.data(), j->s.data(), j->z.data());
+      rc = hc_get_solution(j->h, j->x.data(), j->s.data(), j->z.data(), 0);
     }
     hc_destroy(j->h);
     j->h = nullptr;
@@ -145,6 +152,13 @@ void hc_server::worker(int w, int cap) {
   (void)hipSetDevice(cfg.device);
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+  // one pinned read-back block per slot, allocated once: binding a problem
+  // then allocates no pinned memory, and retiring it frees none (hipHostFree
+  // would synchronise the whole device, stalling the other workers' streams)
+  std::vector<void*> stage(cap, nullptr);
+  std::vector<int> stage_free;
+  for (int i = cap - 1; i >= 0; --i)
+    if (hipHostMalloc(&stage[i], kStageBytes, hipHostMallocDefault) == hipSuccess) stage_free.push_back(i);
   std::vector<std::shared_ptr<Job>> mine, fresh;
   for (;;) {
     fresh.clear();
@@ -173,11 +187,18 @@ void hc_server::worker(int w, int cap) {
       }
     }
     for (auto& j : fresh) {
-      hc_device dev{pool_base + j->offset, Pool::round(j->bytes), st, cfg.device};
+      hc_device dev{pool_base + j->offset, Pool::round(j->bytes), st, cfg.device, nullptr, 0};
+      if (!stage_free.empty()) {
+        j->stage = stage_free.back();
+        stage_free.pop_back();
+        dev.host_stage = stage[j->stage];
+        dev.host_stage_bytes = kStageBytes;
+      }
       j->t_start = now_ms();
       int32_t rc = hc_bind(j->h, &dev);
       if (rc == HC_OK) rc = hc::solver_begin(j->h);
       if (rc != HC_OK) {
+        if (j->stage >= 0) stage_free.push_back(j->stage);
         finish(j, rc, st);
         mine.erase(std::find(mine.begin(), mine.end(), j));
       }
@@ -188,6 +209,7 @@ void hc_server::worker(int w, int cap) {
       int done = 0;
       const int32_t rc = hc::solver_step(mine[i]->h, &done);
       if (rc != HC_OK || done) {
+        if (mine[i]->stage >= 0) stage_free.push_back(mine[i]->stage);
         finish(mine[i], rc, st);
         mine.erase(mine.begin() + (long)i);
       } else {
@@ -214,6 +236,8 @@ void hc_server::worker(int w, int cap) {
     cancelled++;
   }
   (void)hipStreamSynchronize(st);
+  for (void* b : stage)
+    if (b) (void)hipHostFree(b);
   (void)hipStreamDestroy(st);
 }
 

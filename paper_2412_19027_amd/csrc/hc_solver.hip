@@ -129,6 +129,7 @@ struct hc_solver {
   int32_t *dls_cone = nullptr, *dls_col = nullptr;
   int64_t* dls_dst = nullptr;
   double *dq = nullptr, *db = nullptr, *dD = nullptr, *dE = nullptr, *dalpha = nullptr;
+  int64_t* dperm = nullptr;         // internal row -> user row (device copy of perm)
   int32_t *dtra = nullptr, *dtrb = nullptr;
   int64_t* dtm = nullptr;
   double *dstate = nullptr, *dmval = nullptr, *dhdiag = nullptr;
@@ -145,6 +146,7 @@ struct hc_solver {
   int64_t npart = 0;                // capacity of the partial buffers (two reductions, or every segment's step partials)
   double* dpart = nullptr;          // reduction partials
   double* hpart = nullptr;          // pinned host copy
+  bool own_stage = false;           // hpart/hmask allocated here (no caller staging)
   unsigned long long *dmask = nullptr, *hmask = nullptr;
   // iterate and work vectors
   double *x, *s, *z;
@@ -161,6 +163,7 @@ struct hc_solver {
   double delta = 0;
   double xPx_cache = 0;             // x'Px of the current iterate (from residuals)
   std::unique_ptr<Prof> prof;
+  std::unique_ptr<Prof> cprof;      // events around the cone-layer launches (settings.profile)
   Aux aux;   // side stream + events of the look-ahead factorisation
   bool use64 = false;               // mixed mode: this iteration fell back to the FP64 factor
   int kiter = 0;                    // loop counter of the current solve
@@ -1185,6 +1188,48 @@ void At_mul(hc_solver* S, const double* z, double* y, double alpha, double beta)
   dense_rows_gemv_t((int)S->drows.size(), S->leaves ? S->nt : S->n, S->dAd, S->ddrows,
                     S->leaves ? S->cm.tcols : nullptr, z, y, alpha, S->dDrT, S->stream);
 }
+// Cone-layer probes (settings.profile): an event pair on the handle's stream
+// around each group of cone launches, and the algorithmic HBM bytes of every
+// launch from its segment's size: what the step must read and write at least
+// once (iterate and direction rows, the scaling state, H diagonal, M blocks).
+enum ConeOp { CO_SCALE, CO_MBLOCK, CO_APPLY, CO_RECOVER, CO_DS, CO_STEP };
+double cone_op_bytes(const SegDev& g, ConeOp op) {
+  if (g.count == 0 || g.kind == HC_CONE_ZERO) return 0.0;
+  const double R = (double)g.count * (double)g.dim;
+  const double SD = (double)state_doubles(g.kind, g.dim, g.k) * (double)g.count;
+  const double MB = (double)mblock_doubles(g.kind, g.dim) * (double)g.count;
+  switch (op) {
+    case CO_SCALE: return 8.0 * (3.0 * R + SD);     // s, z in; state, diag(H) out
+    case CO_MBLOCK: return 8.0 * (SD + MB);         // state in; M blocks out
+    case CO_APPLY: return 8.0 * (2.0 * R + SD);     // x, state in; y out
+    case CO_RECOVER: return 8.0 * (3.0 * R + SD);   // d_s, dz, state in; ds out
+    case CO_DS: return 8.0 * (5.0 * R + SD);        // s, z, ds_a, dz_a, state in; d_s out
+    case CO_STEP: return 8.0 * 4.0 * R;             // s, z, ds, dz in
+  }
+  return 0.0;
+}
+struct ConeProbe {
+  hc_solver* S;
+  // which: 0 every segment, 1 the symmetric ones, 2 exp/pow
+  // (only: that segment alone)
+  explicit ConeProbe(hc_solver* S_, ConeOp op, int which = 0, const SegDev* only = nullptr) : S(S_) {
+    if (!S->st.profile || !S->cprof) return;
+    HC_HIP(hipEventRecord(S->cprof->next(), S->stream));
+    for (const SegDev& g : S->sdev) {
+      const bool ns = g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW;
+      if ((which == 1 && ns) || (which == 2 && !ns) || (only && only != &g)) continue;
+      const double b = cone_op_bytes(g, op);
+      if (b > 0.0) {
+        S->info.cone_bytes += b;
+        S->info.cone_launches++;
+      }
+    }
+  }
+  ~ConeProbe() {
+    if (S->st.profile && S->cprof) (void)hipEventRecord(S->cprof->next(), S->stream);
+  }
+};
+
 void P_mul(hc_solver* S, const double* x, double* y, double alpha, double beta) {
   if (S->dP.nnz == 0) {
     if (beta == 0.0) vfill(S->n, 0.0, y, S->stream);
@@ -1194,6 +1239,7 @@ void P_mul(hc_solver* S, const double* x, double* y, double alpha, double beta) 
   spmv(S->dP, x, y, alpha, beta, S->stream);
 }
 void H_apply(hc_solver* S, int mode, const double* x, double* y) {
+  ConeProbe probe(S, CO_APPLY);
   for (auto& g : S->sdev) cone_apply(g, mode, S->delta, x, y, S->stream);
 }
 
@@ -1226,7 +1272,10 @@ void factor(hc_solver* S, bool fp64 = false) {
     const double dd = S->mixed ? std::ldexp(1.0, -104) : S->st.dyn_reg;
     S->delta = ds + dd * std::max(S->maxPdiag, hmax);
   }
-  for (auto& g : S->sdev) cone_mblock(g, S->delta, S->dmwork, st);   // segments run in order: one work buffer
+  {
+    ConeProbe probe(S, CO_MBLOCK);
+    for (auto& g : S->sdev) cone_mblock(g, S->delta, S->dmwork, st);   // segments run in order: one work buffer
+  }
   // The tail is factored padded to ld (a multiple of 64) with an identity
   // block on the padding: [[S, 0], [0, I]] = [[L, 0], [0, I]] [[L, 0], [0, I]]',
   // so every panel, TRSM and trailing update is a whole number of 64-blocks
@@ -1497,7 +1546,10 @@ int check(hc_solver* S, const Resid& R) {
 
 void scale_all(hc_solver* S, double mu, bool force_dual, int* pd_count) {
   HC_HIP(hipMemsetAsync(S->dpd, 0, sizeof(int), S->stream));
-  for (auto& g : S->sdev) cone_scale(g, S->s, S->z, mu, force_dual ? 1 : 0, S->dhdiag, S->dpd, S->stream);
+  {
+    ConeProbe probe(S, CO_SCALE);
+    for (auto& g : S->sdev) cone_scale(g, S->s, S->z, mu, force_dual ? 1 : 0, S->dhdiag, S->dpd, S->stream);
+  }
   int h = 0;
   HC_HIP(hipMemcpyAsync(&h, S->dpd, sizeof(int), hipMemcpyDeviceToHost, S->stream));
   HC_HIP(hipStreamSynchronize(S->stream));
@@ -1529,7 +1581,10 @@ Dir direction(hc_solver* S, const double* r1, const double* r2, double dtau_rhs,
   d.dtau = num / den;
   vlin3(n, 1.0, S->x1, d.dtau, S->x2, 0.0, nullptr, dxo, st);
   vlin3(m, 1.0, S->z1, d.dtau, S->z2, 0.0, nullptr, dzo, st);
-  for (auto& g : S->sdev) cone_recover_ds(g, ds_rhs, dzo, dso, st);
+  {
+    ConeProbe probe(S, CO_RECOVER);
+    for (auto& g : S->sdev) cone_recover_ds(g, ds_rhs, dzo, dso, st);
+  }
   d.dkappa = -(dkap_rhs + S->kappa * d.dtau) / S->tau;
   return d;
 }
@@ -1553,7 +1608,10 @@ double step_length(hc_solver* S, const Step& d, bool combined) {
   if (d.dkappa < 0) a = std::min(a, -S->kappa / d.dkappa);
   {   // every symmetric segment's partial minima, then one host round trip
     int64_t off = 0;
-    for (auto& g : S->sdev) off += cone_step_sym(g, S->s, S->z, d.ds, d.dz, S->dpart + off, st);
+    {
+      ConeProbe probe(S, CO_STEP, 1);
+      for (auto& g : S->sdev) off += cone_step_sym(g, S->s, S->z, d.ds, d.dz, S->dpart + off, st);
+    }
     if (off) {
       HC_HIP(hipMemcpyAsync(S->hpart, S->dpart, off * sizeof(double), hipMemcpyDeviceToHost, st));
       HC_HIP(hipStreamSynchronize(st));
@@ -1586,8 +1644,12 @@ double step_length(hc_solver* S, const Step& d, bool combined) {
     unsigned long long all = (nt >= 64) ? ~0ull : ((1ull << nt) - 1ull);
     for (auto& g : S->sdev) {
       if (g.kind != HC_CONE_EXP && g.kind != HC_CONE_POW) continue;
-      const int nb = cone_trial_nonsym(g, S->s, S->z, d.ds, d.dz, a, ratio, nt, combined ? 1 : 0, S->st.beta, c0, c1,
-                                       c2, (double)(S->nu + 1), S->dmask, st);
+      int nb = 0;
+      {
+        ConeProbe probe(S, CO_STEP, 2, &g);
+        nb = cone_trial_nonsym(g, S->s, S->z, d.ds, d.dz, a, ratio, nt, combined ? 1 : 0, S->st.beta, c0, c1, c2,
+                               (double)(S->nu + 1), S->dmask, st);
+      }
       HC_HIP(hipMemcpyAsync(S->hmask, S->dmask, nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
       HC_HIP(hipStreamSynchronize(st));
       for (int i = 0; i < nb; ++i) all &= S->hmask[i];
@@ -1711,7 +1773,10 @@ int iterate(hc_solver* S, const Resid& R) {
     sigma = (1.0 - alpha_a) * (1.0 - alpha_a) * (1.0 - alpha_a);
     // combined
     const double dk = S->kappa * S->tau + da.dkappa * da.dtau - sigma * mu;
-    for (auto& g : S->sdev) cone_ds_combined(g, S->s, S->z, S->dsa, S->dza, sigma * mu, S->dsrhs, st);
+    {
+      ConeProbe probe(S, CO_DS);
+      for (auto& g : S->sdev) cone_ds_combined(g, S->s, S->z, S->dsa, S->dza, sigma * mu, S->dsrhs, st);
+    }
     const double f = 1.0 - sigma;
     vlin3(n, -f, S->rdv, 0.0, nullptr, 0.0, nullptr, S->r1, st);
     // r2 = -(f gz - ds) = f rpv + ds
@@ -1726,6 +1791,7 @@ int iterate(hc_solver* S, const Resid& R) {
     }
     break;
   }
+  if (S->st.profile && S->cprof) S->info.cone_kernel_ms += S->cprof->collect_ms();
   if (S->st.verbose) {
     std::printf("    sigma %.3e alpha_a %.4f alpha_c %.4f delta %.2e ir %lld fp64-fallbacks %lld\n", sigma, alpha_a,
                 alpha_c, S->delta, (long long)S->info.ir_solves, (long long)S->info.fp64_fallbacks);
@@ -1748,6 +1814,7 @@ void begin_solve(hc_solver* S) {
   S->info.n_ordered = keep.n_ordered;
   S->info.n_leaves = keep.n_leaves;
   S->info.leaf_columns = keep.leaf_columns;
+  S->info.psd_gathered_rows = keep.psd_gathered_rows;
   S->info.factor_flops = keep.factor_flops;
   HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), S->stream));
   S->sdiag_max = 0;
@@ -1819,6 +1886,7 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->db = upload(buf, S->b, st);
   S->dD = upload(buf, S->D, st);
   S->dE = upload(buf, S->E, st);
+  S->dperm = upload(buf, S->perm, st);
   S->dalpha = upload(buf, S->alpha_pow, st);
   S->dtra = upload(buf, S->tra, st);
   S->dtrb = upload(buf, S->trb, st);
@@ -1915,6 +1983,12 @@ size_t workspace_bytes(const hc_solver* S) {
   return b.used + 4096;
 }
 
+// pinned read-back staging: the partials, then the step masks
+size_t host_stage_bytes(const hc_solver* S) {
+  if (!S->bound) workspace_bytes(S);   // the dry run sets npart
+  return (size_t)S->npart * (sizeof(double) + sizeof(unsigned long long));
+}
+
 void bind(hc_solver* S, const hc_device* dev) {
   S->device = dev ? dev->device : 0;
   HC_HIP(hipSetDevice(S->device));
@@ -1937,8 +2011,14 @@ void bind(hc_solver* S, const hc_device* dev) {
   S->mem_bytes = need;
   hipStream_t st = S->stream;
   alloc_all(S, buf, st);
-  HC_HIP(hipHostMalloc((void**)&S->hpart, S->npart * sizeof(double), hipHostMallocDefault));
-  HC_HIP(hipHostMalloc((void**)&S->hmask, S->npart * sizeof(unsigned long long), hipHostMallocDefault));
+  if (dev && dev->host_stage && dev->host_stage_bytes >= host_stage_bytes(S)) {
+    S->hpart = (double*)dev->host_stage;
+    S->hmask = (unsigned long long*)(S->hpart + S->npart);
+  } else {
+    HC_HIP(hipHostMalloc((void**)&S->hpart, S->npart * sizeof(double), hipHostMallocDefault));
+    HC_HIP(hipHostMalloc((void**)&S->hmask, S->npart * sizeof(unsigned long long), hipHostMallocDefault));
+    S->own_stage = true;
+  }
   HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), st));
   if (S->K1 + S->K2 > 0) {   // zero padding rows of the dense-row operand, zero rank-2 rows
     HC_HIP(hipMemsetAsync(S->dBd, 0, (size_t)(S->K1 + S->K2) * S->nt * sizeof(double), st));
@@ -1963,6 +2043,7 @@ void bind(hc_solver* S, const hc_device* dev) {
     S->sdev.push_back(d);
   }
   S->prof.reset(new Prof());
+  S->cprof.reset(new Prof());
   S->bound = true;
   HC_HIP(hipStreamSynchronize(st));
 }
@@ -2023,6 +2104,24 @@ int32_t solver_finish(hc_solver* S) {
 // ===========================================================================
 // C-ABI
 // ===========================================================================
+// the iterate in the user's coordinates: x = D x~ / t, s[perm] = s~ / (E t),
+// z[perm] = E z~ / (c t)
+__global__ void k_user_solution(int64_t n, int64_t m, const double* __restrict__ xi, const double* __restrict__ si,
+                                const double* __restrict__ zi, const double* __restrict__ D,
+                                const double* __restrict__ E, const int64_t* __restrict__ perm, double inv_c,
+                                double t, double* __restrict__ x, double* __restrict__ s, double* __restrict__ z) {
+  const double it = 1.0 / t;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n > m ? n : m);
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (x && i < n) x[i] = D[i] * xi[i] * it;
+    if (i < m) {
+      const int64_t u = perm[i];
+      if (s) s[u] = si[i] / E[i] * it;
+      if (z) z[u] = E[i] * zi[i] * inv_c * it;
+    }
+  }
+}
+
 extern "C" {
 
 int32_t hc_settings_default(hc_settings* o) {
@@ -2065,6 +2164,7 @@ int32_t hc_setup(hc_solver** out, const hc_problem* prob, const hc_settings* set
     S->info.n_ordered = S->nt;
     S->info.n_leaves = (int64_t)S->leaf_size.size();
     S->info.leaf_columns = S->n - S->nt;
+    S->info.psd_gathered_rows = S->pe_rows;
     S->info.factor_flops = envelope_cholesky_flops(S->nt, S->tail_last.data()) + S->leaf_flops;
   } catch (const Error& e) {
     g_last_error = e.msg;
@@ -2082,6 +2182,12 @@ int32_t hc_setup(hc_solver** out, const hc_problem* prob, const hc_settings* set
 int32_t hc_workspace_bytes(const hc_solver* S, size_t* bytes) {
   if (!S || !bytes) return HC_ERR_INVALID_ARG;
   *bytes = workspace_bytes(S);
+  return HC_OK;
+}
+
+int32_t hc_host_stage_bytes(const hc_solver* S, size_t* bytes) {
+  if (!S || !bytes) return HC_ERR_INVALID_ARG;
+  *bytes = host_stage_bytes(S);
   return HC_OK;
 }
 
@@ -2126,11 +2232,21 @@ int32_t hc_get_info(const hc_solver* S, hc_info* out) {
   return HC_OK;
 }
 
-int32_t hc_get_solution(const hc_solver* S, double* x, double* sv, double* z) {
+int32_t hc_get_solution(const hc_solver* S, double* x, double* sv, double* z, int32_t on_device) {
   if (!S) return HC_ERR_INVALID_ARG;
   if (!S->bound) return HC_ERR_STATE;
   try {
     const int64_t n = S->n, m = S->m;
+    const bool cert0 = S->status == HC_STATUS_PRIMAL_INFEASIBLE || S->status == HC_STATUS_DUAL_INFEASIBLE;
+    if (on_device) {
+      const int64_t L = std::max(n, m);
+      const int nb = (int)std::min<int64_t>(std::max<int64_t>(1, ceil_div(L, 256)), 65535);
+      hipLaunchKernelGGL(k_user_solution, dim3(nb), dim3(256), 0, S->stream, n, m, S->x, S->s, S->z, S->dD, S->dE,
+                         S->dperm, 1.0 / S->cscale, cert0 ? 1.0 : S->tau, x, sv, z);
+      HC_LAUNCH_CHECK();
+      HC_HIP(hipStreamSynchronize(S->stream));
+      return HC_OK;
+    }
     std::vector<double> hx(n), hs(m), hz(m);
     HC_HIP(hipMemcpy(hx.data(), S->x, n * 8, hipMemcpyDeviceToHost));
     HC_HIP(hipMemcpy(hs.data(), S->s, m * 8, hipMemcpyDeviceToHost));
@@ -2344,8 +2460,10 @@ int32_t hc_test_kkt_solve(hc_solver* S, double mu, int32_t force_dual, const dou
 void hc_destroy(hc_solver* S) {
   if (!S) return;
   if (S->own_mem && S->mem) (void)hipFree(S->mem);
-  if (S->hpart) (void)hipHostFree(S->hpart);
-  if (S->hmask) (void)hipHostFree(S->hmask);
+  if (S->own_stage) {
+    if (S->hpart) (void)hipHostFree(S->hpart);
+    if (S->hmask) (void)hipHostFree(S->hmask);
+  }
   delete S;
 }
 

@@ -100,8 +100,8 @@ __global__ __launch_bounds__(256) void k_copy_reference(const uint4* __restrict_
 extern "C" {
 
 int32_t hc_test_cone_scale(int32_t type, int64_t count, int32_t dim, const double* alpha, const double* s,
-                           const double* z, double mu, double* H_out, double* lam_out, int32_t* branch_out,
-                           void* stream) {
+                           const double* z, double mu, int32_t force_dual, double* H_out, double* lam_out,
+                           int32_t* branch_out, void* stream) {
   return guard([&] {
     hipStream_t st = (hipStream_t)stream;
     TestSeg T;
@@ -112,7 +112,7 @@ int32_t hc_test_cone_scale(int32_t type, int64_t count, int32_t dim, const doubl
     double* hd = T.alloc(tot);
     int* pd = (int*)T.alloc(1);
     HC_HIP(hipMemsetAsync(pd, 0, sizeof(double), st));
-    cone_scale(T.g, si, zi, mu, 0, hd, pd, st);
+    cone_scale(T.g, si, zi, mu, force_dual ? 1 : 0, hd, pd, st);
     // H column by column: H e_j
     double* e = T.alloc(tot);
     double* y = T.alloc(tot);
@@ -154,7 +154,8 @@ int32_t hc_test_cone_scale(int32_t type, int64_t count, int32_t dim, const doubl
 }
 
 int32_t hc_test_cone_mblock(int32_t type, int64_t count, int32_t dim, const double* alpha, const double* s,
-                            const double* z, double mu, double delta, double* M_out, void* stream) {
+                            const double* z, double mu, int32_t force_dual, double delta, double* M_out,
+                            void* stream) {
   return guard([&] {
     if (!M_out || !(delta > 0.0)) throw Error{HC_ERR_INVALID_ARG, "M_out is NULL or delta <= 0"};
     hipStream_t st = (hipStream_t)stream;
@@ -166,7 +167,7 @@ int32_t hc_test_cone_mblock(int32_t type, int64_t count, int32_t dim, const doub
     double* hd = T.alloc(tot);
     int* pd = (int*)T.alloc(1);
     HC_HIP(hipMemsetAsync(pd, 0, sizeof(double), st));
-    cone_scale(T.g, si, zi, mu, 0, hd, pd, st);
+    cone_scale(T.g, si, zi, mu, force_dual ? 1 : 0, hd, pd, st);
     cone_mblock(T.g, delta, T.alloc(std::max<int64_t>(1, cone_mblock_work(T.g))), st);
     const int64_t per = mblock_doubles(type, T.g.dim);
     std::vector<double> hm(per * T.g.count), dense((size_t)count * T.rows * T.rows, 0.0);
@@ -215,8 +216,8 @@ int32_t hc_test_cone_mblock(int32_t type, int64_t count, int32_t dim, const doub
 }
 
 int32_t hc_test_cone_ds(int32_t type, int64_t count, int32_t dim, const double* alpha, const double* s,
-                        const double* z, const double* dsa, const double* dza, double mu, double sm, double* ds_out,
-                        void* stream) {
+                        const double* z, const double* dsa, const double* dza, double mu, int32_t force_dual,
+                        double sm, double* ds_out, void* stream) {
   return guard([&] {
     hipStream_t st = (hipStream_t)stream;
     TestSeg T;
@@ -229,7 +230,7 @@ int32_t hc_test_cone_ds(int32_t type, int64_t count, int32_t dim, const double* 
     double* hd = T.alloc(tot);
     int* pd = (int*)T.alloc(1);
     HC_HIP(hipMemsetAsync(pd, 0, sizeof(double), st));
-    cone_scale(T.g, si, zi, mu, 0, hd, pd, st);
+    cone_scale(T.g, si, zi, mu, force_dual ? 1 : 0, hd, pd, st);
     double* o = T.alloc(tot);
     cone_ds_combined(T.g, si, zi, ai, bi, sm, o, st);
     T.out(o, ds_out, st);
@@ -265,6 +266,31 @@ int32_t hc_test_cone_step(int32_t type, int64_t count, int32_t dim, const double
       HC_HIP(hipMemcpyAsync(alpha_out, o, count * 8, hipMemcpyDeviceToDevice, st));
     }
     HC_HIP(hipStreamSynchronize(st));
+  });
+}
+
+int32_t hc_test_cone_step_min(int32_t type, int64_t count, int32_t dim, const double* alpha, const double* s,
+                              const double* z, const double* ds, const double* dz, double* alpha_min, void* stream) {
+  return guard([&] {
+    if (!alpha_min) throw Error{HC_ERR_INVALID_ARG, "alpha_min is NULL"};
+    if (type != HC_CONE_NONNEG && type != HC_CONE_SOC && type != HC_CONE_PSD)
+      throw Error{HC_ERR_INVALID_ARG, "the minimum step is for nonneg, SOC and PSD cones"};
+    hipStream_t st = (hipStream_t)stream;
+    TestSeg T;
+    make(T, type, count, dim, alpha);
+    double* si = T.in(s, st);
+    double* zi = T.in(z, st);
+    double* a = T.in(ds, st);
+    double* b = T.in(dz, st);
+    // as many partials as the solver's launch may write (one per workgroup)
+    double* part = T.alloc(std::max<int64_t>(2 * T.g.count, cone_blocks(T.g)) + 64);
+    const int nb = cone_step_sym(T.g, si, zi, a, b, part, st);
+    std::vector<double> h(std::max(nb, 1));
+    if (nb) HC_HIP(hipMemcpyAsync(h.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    HC_HIP(hipStreamSynchronize(st));
+    double v = INFINITY;
+    for (int i = 0; i < nb; ++i) v = std::min(v, h[i]);
+    *alpha_min = v;
   });
 }
 

@@ -21,9 +21,9 @@ STATUS = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasibl
           5: "insufficient_progress", 6: "numerical_error", 7: "cancelled"}
 
 EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "hc_solve", "hc_get_info",
-           "hc_get_solution", "hc_get_iterate", "hc_set_iterate", "hc_update_data", "hc_test_kkt_solve", "hc_test_kkt_ops",
+           "hc_get_solution", "hc_host_stage_bytes", "hc_get_iterate", "hc_set_iterate", "hc_update_data", "hc_test_kkt_solve", "hc_test_kkt_ops",
            "hc_test_schur", "hc_destroy", "hc_last_error", "hc_status_str",
-           "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_dense_chol_solve",
+           "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_cone_step_min", "hc_test_dense_chol_solve",
            "hc_test_dense_chol_solve_env",
            "hc_test_copy", "hc_test_cone_mblock", "hc_server_config_default", "hc_server_create", "hc_server_submit", "hc_server_poll",
            "hc_server_wait", "hc_server_stats", "hc_server_destroy"]
@@ -53,7 +53,7 @@ class hc_settings(C.Structure):
 
 class hc_device(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("stream", C.c_void_p),
-                ("device", C.c_int32)]
+                ("device", C.c_int32), ("host_stage", C.c_void_p), ("host_stage_bytes", C.c_size_t)]
 
 
 class hc_info(C.Structure):
@@ -64,7 +64,9 @@ class hc_info(C.Structure):
                 ("ir_solves", C.c_int64), ("pivot_guard_hits", C.c_int64), ("dual_switches", C.c_int64),
                 ("n_ordered", C.c_int64), ("factor_flops", C.c_double), ("factorizations", C.c_int64),
                 ("gemm_ms", C.c_double), ("gemm_flops", C.c_double), ("gemm_launches", C.c_int64),
-                ("fp64_fallbacks", C.c_int64), ("n_leaves", C.c_int64), ("leaf_columns", C.c_int64)]
+                ("fp64_fallbacks", C.c_int64), ("n_leaves", C.c_int64), ("leaf_columns", C.c_int64),
+                ("psd_gathered_rows", C.c_int64), ("cone_kernel_ms", C.c_double), ("cone_bytes", C.c_double),
+                ("cone_launches", C.c_int64)]
 
 
 class hc_server_config(C.Structure):
@@ -108,7 +110,8 @@ def lib():
         L.hc_bind.argtypes = [vp, C.POINTER(hc_device)]
         L.hc_solve.argtypes = [vp]
         L.hc_get_info.argtypes = [vp, C.POINTER(hc_info)]
-        L.hc_get_solution.argtypes = [vp, vp, vp, vp]
+        L.hc_get_solution.argtypes = [vp, vp, vp, vp, i32]
+        L.hc_host_stage_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.hc_get_iterate.argtypes = [vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp]
         L.hc_set_iterate.argtypes = [vp, vp, vp, vp, dbl, dbl]
         L.hc_update_data.argtypes = [vp, vp, vp, vp, vp]
@@ -121,13 +124,14 @@ def lib():
         L.hc_last_error.restype = C.c_char_p
         L.hc_status_str.argtypes = [i32]
         L.hc_status_str.restype = C.c_char_p
-        L.hc_test_cone_scale.argtypes = [i32, i64, i32, vp, vp, vp, dbl, vp, vp, vp, vp]
-        L.hc_test_cone_ds.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, dbl, dbl, vp, vp]
+        L.hc_test_cone_scale.argtypes = [i32, i64, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
+        L.hc_test_cone_ds.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, dbl, i32, dbl, vp, vp]
         L.hc_test_cone_step.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, dbl, vp, vp]
+        L.hc_test_cone_step_min.argtypes = [i32, i64, i32, vp, vp, vp, vp, vp, C.POINTER(dbl), vp]
         L.hc_test_dense_chol_solve.argtypes = [i32, i64, i64, vp, i32, vp, C.POINTER(i64), vp]
         L.hc_test_dense_chol_solve_env.argtypes = [i32, i64, i64, vp, vp, i32, vp, C.POINTER(i64), vp]
         L.hc_test_copy.argtypes = [vp, vp, i64, vp]
-        L.hc_test_cone_mblock.argtypes = [i32, i64, i32, vp, vp, vp, C.c_double, C.c_double, vp, vp]
+        L.hc_test_cone_mblock.argtypes = [i32, i64, i32, vp, vp, vp, C.c_double, i32, C.c_double, vp, vp]
         L.hc_server_config_default.argtypes = [C.POINTER(hc_server_config)]
         L.hc_server_create.argtypes = [C.POINTER(vp), C.POINTER(hc_server_config)]
         L.hc_server_submit.argtypes = [vp, C.POINTER(hc_problem), C.c_uint64, C.POINTER(C.c_uint64)]
@@ -230,7 +234,8 @@ class Solver:
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        dev = hc_device(self.arena.data_ptr(), int(nbytes.value), self.stream.cuda_stream, self.device.index or 0)
+        dev = hc_device(self.arena.data_ptr(), int(nbytes.value), self.stream.cuda_stream, self.device.index or 0,
+                        None, 0)
         _check(L.hc_bind(h, C.byref(dev)), h)
 
     def solve(self):
@@ -244,11 +249,21 @@ class Solver:
         out["status_name"] = STATUS.get(inf.status, "unknown")
         return out
 
-    def solution(self):
+    def solution(self, on_device=False):
+        """x, s, z in the user's coordinates (divided by tau; the certificate
+        for an infeasible status): numpy arrays, or torch cuda tensors written
+        on the device when on_device."""
+        if on_device:
+            torch = self._torch
+            x = torch.empty(self.n, dtype=torch.float64, device=self.device)
+            s = torch.empty(self.m, dtype=torch.float64, device=self.device)
+            z = torch.empty(self.m, dtype=torch.float64, device=self.device)
+            _check(lib().hc_get_solution(self._h, x.data_ptr(), s.data_ptr(), z.data_ptr(), 1), self._h)
+            return x, s, z
         x = np.zeros(self.n)
         s = np.zeros(self.m)
         z = np.zeros(self.m)
-        _check(lib().hc_get_solution(self._h, x.ctypes.data, s.ctypes.data, z.ctypes.data), self._h)
+        _check(lib().hc_get_solution(self._h, x.ctypes.data, s.ctypes.data, z.ctypes.data, 0), self._h)
         return x, s, z
 
     def iterate(self):
@@ -343,7 +358,7 @@ def _stream():
     return torch.cuda.current_stream().cuda_stream
 
 
-def test_cone_scale(kind, dim, s, z, mu, alpha=None):
+def test_cone_scale(kind, dim, s, z, mu, alpha=None, force_dual=False):
     """Scaling of `count` cones given cone by cone (torch cuda float64, shape (count, rows))."""
     import torch
     count, rows = s.shape
@@ -351,27 +366,28 @@ def test_cone_scale(kind, dim, s, z, mu, alpha=None):
     lam = torch.zeros((count, rows), dtype=torch.float64, device=s.device)
     br = torch.zeros(count, dtype=torch.int32, device=s.device)
     _check(lib().hc_test_cone_scale(kind, count, dim, _dptr(alpha), _dptr(s.contiguous()), _dptr(z.contiguous()),
-                                    float(mu), _dptr(H), _dptr(lam), _dptr(br), _stream()))
+                                    float(mu), int(bool(force_dual)), _dptr(H), _dptr(lam), _dptr(br), _stream()))
     torch.cuda.synchronize()
     return H, lam, br
 
 
-def test_cone_mblock(kind, dim, s, z, mu, delta, alpha=None):
+def test_cone_mblock(kind, dim, s, z, mu, delta, alpha=None, force_dual=False):
     """Explicit M = (H + delta I)^-1 blocks used in the Schur assembly, (count, rows, rows)."""
     import torch
     count, rows = s.shape
     M = torch.zeros((count, rows, rows), dtype=torch.float64, device=s.device)
     _check(lib().hc_test_cone_mblock(kind, count, dim, _dptr(alpha), _dptr(s.contiguous()), _dptr(z.contiguous()),
-                                     float(mu), float(delta), _dptr(M), _stream()))
+                                     float(mu), int(bool(force_dual)), float(delta), _dptr(M), _stream()))
     torch.cuda.synchronize()
     return M
 
 
-def test_cone_ds(kind, dim, s, z, dsa, dza, mu, sm, alpha=None):
+def test_cone_ds(kind, dim, s, z, dsa, dza, mu, sm, alpha=None, force_dual=False):
     import torch
     out = torch.zeros_like(s)
     _check(lib().hc_test_cone_ds(kind, s.shape[0], dim, _dptr(alpha), _dptr(s.contiguous()), _dptr(z.contiguous()),
-                                 _dptr(dsa.contiguous()), _dptr(dza.contiguous()), float(mu), float(sm), _dptr(out),
+                                 _dptr(dsa.contiguous()), _dptr(dza.contiguous()), float(mu), int(bool(force_dual)),
+                                 float(sm), _dptr(out),
                                  _stream()))
     torch.cuda.synchronize()
     return out
@@ -384,6 +400,18 @@ def test_cone_step(kind, dim, s, z, ds, dz, amax, alpha=None):
                                    _dptr(ds.contiguous()), _dptr(dz.contiguous()), float(amax), _dptr(out), _stream()))
     torch.cuda.synchronize()
     return out
+
+
+def test_cone_step_min(kind, dim, s, z, ds, dz, alpha=None):
+    """Minimum over all cones of the exact boundary step, by the solver's own
+    step-length launch (nonneg, SOC, PSD)."""
+    import torch
+    out = C.c_double(0.0)
+    _check(lib().hc_test_cone_step_min(kind, s.shape[0], dim, _dptr(alpha), _dptr(s.contiguous()),
+                                       _dptr(z.contiguous()), _dptr(ds.contiguous()), _dptr(dz.contiguous()),
+                                       C.byref(out), _stream()))
+    torch.cuda.synchronize()
+    return out.value
 
 
 def test_dense_chol_solve(A, B, precision=PRECISION_FP64, ld=None, last=None):

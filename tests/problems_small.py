@@ -154,6 +154,22 @@ def unbounded_lp():
     return Problem(1, 1, sp.csr_matrix((1, 1)), np.array([-1.0]), A, b, [(NONNEG, 1, 0.0)], "unbounded_lp")
 
 
+def infeasible_socp():
+    """|(x1, x2)|_2 <= 1 and x1 >= 2: primal infeasible."""
+    A = sp.csr_matrix(np.array([[0.0, 0.0], [-1.0, 0.0], [0.0, -1.0], [-1.0, 0.0]]))
+    b = np.array([1.0, 0.0, 0.0, -2.0])
+    return Problem(2, 4, sp.csr_matrix((2, 2)), np.array([1.0, 1.0]), A, b,
+                   [(SOC, 3, 0.0), (NONNEG, 1, 0.0)], "infeasible_socp")
+
+
+def unbounded_socp():
+    """min -x1 s.t. (x1, x2, x3) in the second-order cone, x2 <= 1: dual infeasible."""
+    A = sp.csr_matrix(np.array([[-1.0, 0.0, 0.0], [0.0, -1.0, 0.0], [0.0, 0.0, -1.0], [0.0, 1.0, 0.0]]))
+    b = np.array([0.0, 0.0, 0.0, 1.0])
+    return Problem(3, 4, sp.csr_matrix((3, 3)), np.array([-1.0, 0.0, 0.0]), A, b,
+                   [(SOC, 3, 0.0), (NONNEG, 1, 0.0)], "unbounded_socp")
+
+
 def random_small_lp(seed):
     """n <= 3, m <= 8 LP with box rows (bounded); optimum by vertex enumeration."""
     rng = np.random.default_rng(seed)

@@ -153,7 +153,7 @@ def test_nonsym_scale(kind):
     assert relerr(N(H), ref["H"]) < 1e-12
 
 
-@pytest.mark.parametrize("k", [2, 3, 4, 13, 20, 32])
+@pytest.mark.parametrize("k", [2, 3, 4, 10, 13, 20, 32])
 def test_psd_scale(k):
     """Sides up to 12 run eight cones per workgroup, sides 13..32 two
     (measured relative errors at k = 32: 3e-14 for H, 5e-15 for lambda)."""
@@ -168,33 +168,21 @@ def test_psd_scale(k):
 
 
 # ----------------------------------------------------------------- combined-step d_s
-def _oracle_ds(kind, s, z, dsa, dza, mu, sm, k=None, alpha=None):
+def _oracle_ds(kind, s, z, dsa, dza, mu, sm, k=None, alpha=None, force_dual=False):
+    """The oracle's d_s of one family (oracle.ipm.ds_family) on the oracle's scaling state."""
     from oracle import ipm
     if kind == "nonneg":
-        sc = C.nn_scale(s, z)
-        return (s * z + dsa * dza - sm) / z
+        return ipm.ds_family(ipm.NONNEG, s, z, C.nn_scale(s, z), dsa, dza, sm)
     if kind == "soc":
-        sc = C.soc_scale(s, z)
-        W, Winv, lam = sc["W"], sc["Winv"], sc["lam"]
-        eta = C.soc_circ(np.einsum("cji,cj->ci", Winv, dsa), np.einsum("cij,cj->ci", W, dza))
-        e = np.zeros_like(lam); e[:, 0] = 1
-        v = C.soc_circ(lam, lam) + eta - sm * e
-        return np.einsum("cji,cj->ci", W, C.soc_inv_circ(lam, v))
+        return ipm.ds_family(ipm.SOC, s, z, C.soc_scale(s, z), dsa, dza, sm)
     if kind == "psd":
-        sc = C.psd_scale(s, z, k)
-        R, Rinv, lam = sc["R"], sc["Rinv"], sc["lam"]
-        Aa = np.einsum("cij,cjk,clk->cil", Rinv, C.smat(dsa, k), Rinv)
-        Bb = np.einsum("cji,cjk,ckl->cil", R, C.smat(dza, k), R)
-        V = C.psd_circ(Aa, Bb) + np.einsum("ci,ij->cij", lam * lam, np.eye(k)) - sm * np.eye(k)[None]
-        X = 2.0 * V / (lam[:, :, None] + lam[:, None, :])
-        return C.svec(np.einsum("cij,cjk,clk->cil", R, X, R))
+        return ipm.ds_family(ipm.PSD, s, z, C.psd_scale(s, z, k), dsa, dza, sm, k=k)
     fam = C.NonsymFamily(kind, alpha)
-    sc = fam.scale(s, z, mu)
-    u = fam.hinv_apply(sc["hinv"], dsa)
-    return s + sm * sc["grad"] - 0.5 * fam.third(z, dza, u)
+    sc = fam.scale(s, z, mu, force_dual=force_dual)
+    return ipm.ds_family(ipm.EXP if kind == "exp" else ipm.POW, s, z, sc, dsa, dza, sm, fam=fam)
 
 
-@pytest.mark.parametrize("kind", ["nonneg", "soc", "soc_large", "exp", "pow", "psd", "psd32"])
+@pytest.mark.parametrize("kind", ["nonneg", "soc", "soc_large", "exp", "pow", "psd", "psd10", "psd32"])
 def test_combined_ds(kind):
     Nc = 200
     mu, sm = 0.8, 0.05
@@ -212,8 +200,8 @@ def test_combined_ds(kind):
         alpha = RNG.uniform(0.2, 0.8, Nc)
         s, z, dim, code = pow_primal(Nc, alpha, RNG), pow_dual(Nc, alpha, RNG), 3, HC.POW
     else:
-        k = 3 if kind == "psd" else 32
-        nc = Nc if k == 3 else 10
+        k = {"psd": 3, "psd10": 10, "psd32": 32}[kind]
+        nc = Nc if k == 3 else (60 if k == 10 else 10)
         s, z, dim, code = C.svec(spd(nc, k, RNG)), C.svec(spd(nc, k, RNG)), k, HC.PSD
         kind = "psd"
     dsa, dza = 0.3 * RNG.standard_normal(s.shape), 0.3 * RNG.standard_normal(s.shape)
@@ -225,7 +213,7 @@ def test_combined_ds(kind):
 
 
 # ----------------------------------------------------------------- step lengths
-@pytest.mark.parametrize("kind", ["nonneg", "soc", "soc_large", "psd", "psd32", "exp", "pow"])
+@pytest.mark.parametrize("kind", ["nonneg", "soc", "soc_large", "psd", "psd10", "psd32", "exp", "pow"])
 def test_step(kind):
     Nc = 150
     alpha = None
@@ -239,9 +227,10 @@ def test_step(kind):
         kind = "soc"
     elif kind == "psd":
         s, z, dim, code = C.svec(spd(Nc, 3, RNG)), C.svec(spd(Nc, 3, RNG)), 3, HC.PSD
-    elif kind == "psd32":
-        Nc = 20
-        s, z, dim, code = C.svec(spd(Nc, 32, RNG)), C.svec(spd(Nc, 32, RNG)), 32, HC.PSD
+    elif kind in ("psd10", "psd32"):
+        k = int(kind[3:])
+        Nc = 20 if k == 32 else Nc
+        s, z, dim, code = C.svec(spd(Nc, k, RNG)), C.svec(spd(Nc, k, RNG)), k, HC.PSD
         kind = "psd"
     elif kind == "exp":
         s, z, dim, code = exp_primal(Nc, RNG), exp_dual(Nc, RNG), 3, HC.EXP
@@ -308,3 +297,62 @@ def test_mblock_inverts_the_applied_scaling(kind, delta):
     cond = np.array([np.linalg.cond(h + delta * eye) for h in H])
     assert np.all(err <= 1e-13 * np.maximum(cond, 1.0) + 1e-12), (err.max(), cond[np.argmax(err)])
     assert np.allclose(M, np.transpose(M, (0, 2, 1)), rtol=0, atol=1e-12 * np.abs(M).max())
+
+
+# ----------------------------------------------------------------- the solver's step-length launch
+@pytest.mark.parametrize("kind", ["nonneg", "soc3", "soc_large", "psd3", "psd10", "psd32"])
+def test_step_min_solver_launch(kind):
+    """The launch hc_solve takes for the symmetric step (PSD: the s and z
+    halves as separate wave tasks; more tasks than the grid, so the
+    grid-stride loop wraps) against the oracle's minimum over all cones."""
+    if kind == "nonneg":
+        Nc = 300000
+        s, z, dim, code = RNG.uniform(0.1, 2, (Nc, 1)), RNG.uniform(0.1, 2, (Nc, 1)), 1, HC.NONNEG
+        ds, dz = RNG.standard_normal(s.shape), RNG.standard_normal(s.shape)
+        ref = min(C.nn_step(s, ds).min(), C.nn_step(z, dz).min())
+    elif kind.startswith("soc"):
+        Nc, d = (120000, 3) if kind == "soc3" else (2100, 257)
+        s, z, dim, code = soc_interior(Nc, d, RNG), soc_interior(Nc, d, RNG), d, HC.SOC
+        ds, dz = 0.5 * RNG.standard_normal(s.shape), 0.5 * RNG.standard_normal(s.shape)
+        ref = min(C.soc_step(s, ds).min(), C.soc_step(z, dz).min())
+    else:
+        k = int(kind[3:])
+        Nc = 1100 if k < 32 else 1030
+        s, z, dim, code = C.svec(spd(Nc, k, RNG)), C.svec(spd(Nc, k, RNG)), k, HC.PSD
+        ds, dz = 0.5 * RNG.standard_normal(s.shape), 0.5 * RNG.standard_normal(s.shape)
+        ref = min(C.psd_step(s, ds, k).min(), C.psd_step(z, dz, k).min())
+    got = HC.test_cone_step_min(code, dim, T(s), T(z), T(ds), T(dz))
+    print(kind, got, ref)
+    assert abs(got - ref) <= 1e-12 * ref
+
+
+# ----------------------------------------------------------------- exp/pow dual scaling
+@pytest.mark.parametrize("kind", ["exp", "pow"])
+def test_nonsym_dual_scaling(kind):
+    """The dual scaling H = mu grad^2 f(z) (Appendix A; taken by hc_solve
+    after a short primal-dual step): H, branch, M blocks and d_s against the
+    oracle's scale(force_dual=True)."""
+    Nc = 300
+    if kind == "exp":
+        fam, s, z, alpha = C.NonsymFamily("exp"), exp_primal(Nc, RNG), exp_dual(Nc, RNG), None
+    else:
+        a = RNG.uniform(0.2, 0.8, Nc)
+        fam, s, z, alpha = C.NonsymFamily("pow", a), pow_primal(Nc, a, RNG), pow_dual(Nc, a, RNG), a
+    code = HC.EXP if kind == "exp" else HC.POW
+    a_t = None if alpha is None else T(alpha)
+    mu, delta = 0.37, 1e-8
+    H, zt, br = HC.test_cone_scale(code, 3, T(s), T(z), mu, a_t, force_dual=True)
+    ref = fam.scale(s, z, mu, force_dual=True)
+    assert (N(br) == 1).all() and (ref["branch"] == 1).all()
+    assert relerr(N(H), ref["H"]) < 1e-12
+    assert relerr(N(zt), ref["zt"]) < 1e-12
+    M = N(HC.test_cone_mblock(code, 3, T(s), T(z), mu, delta, a_t, force_dual=True))
+    Mref = np.linalg.inv(ref["H"] + delta * np.eye(3)[None])
+    assert relerr(M, Mref) < 1e-10
+    dsa, dza = 0.3 * RNG.standard_normal(s.shape), 0.3 * RNG.standard_normal(s.shape)
+    out = HC.test_cone_ds(code, 3, T(s), T(z), T(dsa), T(dza), mu, 0.05, a_t, force_dual=True)
+    want = _oracle_ds(kind, s, z, dsa, dza, mu, 0.05, alpha=alpha, force_dual=True)
+    assert relerr(N(out), want) < 1e-12
+    # and the primal-dual scaling really differs here
+    Hpd = fam.scale(s, z, mu)["H"]
+    assert relerr(Hpd, ref["H"]) > 1e-3

@@ -19,7 +19,8 @@ by Newton's method on a system whose condition grows like 1/mu; the oracle
 and the GPU find it independently, so S and the solutions differ by up to
 ~1e-13/mu relative (measured 1.2e-4 at mu = 5e-9 on the exponential-cone case,
 2.2e-4 at mu = 6e-10 on the PSD/power case).  The bound 1e-10 + 5e-12/mu
-holds that with a margin of about 8x.  Symmetric cones stay far inside it.
+holds that with a margin of about 8x.  Problems with symmetric cones only
+are held to 1e-10 + 5e-14/mu.
 """
 import numpy as np
 import pytest
@@ -46,8 +47,10 @@ CASES = [
 ]
 
 
-def tol(mu):
-    return 1e-10 + 5e-12 / mu
+def tol(mu, nonsym=True):
+    """nonsym: the problem has exponential or power cones (conjugate points
+    found independently on the two sides); symmetric cones only: 100x tighter."""
+    return 1e-10 + (5e-12 if nonsym else 5e-14) / mu
 
 
 def rel(a, b):
@@ -57,8 +60,12 @@ def rel(a, b):
 @pytest.mark.parametrize("name,make", CASES)
 def test_kkt_layer_along_the_oracle_path(name, make):
     prob = make()
+    nonsym = any(c[0] in (W.EXP, W.POW) for c in prob.cones)
     o = ipm.Solver(prob)
     g = HC.Solver(prob, leaf_blocks=0)
+    if name == "psd_gathered":
+        assert g.info()["psd_gathered_rows"] > 0, "the T = M_c A_c gather path was not taken"
+    worst = 0.0
     perm = g.iterate()[5]                       # internal row -> user row
 
     def to_user(v):
@@ -84,7 +91,8 @@ def test_kkt_layer_along_the_oracle_path(name, make):
             Sg, Lg, st = g.test_schur(mu)
             So = (kkt.P + kkt.delta * sp.identity(prob.n) + kkt.A.T @ kkt.Mbd @ kkt.A).toarray()
             assert st["bits"] == 64 and abs(st["delta"] - kkt.delta) <= 1e-12 * kkt.delta, (case, st)
-            assert rel(Sg, So) <= tol(mu), (case, "S", rel(Sg, So))
+            assert rel(Sg, So) <= tol(mu, nonsym), (case, "S", rel(Sg, So))
+            worst = max(worst, rel(Sg, So) * mu)
             assert np.abs(Lg @ Lg.T - Sg).max() <= 1e-14 * np.abs(Sg).max(), (case, "factor")
 
             load()
@@ -97,17 +105,19 @@ def test_kkt_layer_along_the_oracle_path(name, make):
             assert res_g <= 50 * res_o + 1e-10 * nb, (case, "one solve", res_g, res_o)
             # before refinement x carries cond(S) eps (the two sides solve S
             # differently: block inverses against LAPACK substitution)
-            assert rel(xr, xo) <= max(tol(mu), 1e-4), (case, "x of one solve", rel(xr, xo))
+            assert rel(xr, xo) <= max(tol(mu, nonsym), 1e-4), (case, "x of one solve", rel(xr, xo))
 
             load()
             xs, zs, info = g.test_kkt_solve(mu, r1, r2[perm])
             zs = to_user(zs)
             xo, zo, oinfo = kkt.solve(r1, r2, 1e-12, 1e-12, 10)
-            assert rel(xs, xo) <= tol(mu) and rel(zs, zo) <= tol(mu), (case, rel(xs, xo), rel(zs, zo))
+            assert rel(xs, xo) <= tol(mu, nonsym) and rel(zs, zo) <= tol(mu, nonsym), (case, rel(xs, xo), rel(zs, zo))
+            worst = max(worst, rel(xs, xo) * mu, rel(zs, zo) * mu)
             assert info["solves"] <= oinfo["solves"] + 2, (case, info, oinfo)
 
             assert o.iterate() == 0, case
             it += 1
     finally:
         g.close()
+    print(f"{name}: largest relative difference x mu = {worst:.2e}")
     assert it >= 5, (name, it)

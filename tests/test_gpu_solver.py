@@ -111,3 +111,78 @@ def test_initial_point_against_oracle(name, make):
         err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
         assert err <= 1e-9, (name, what, err)
     assert tau == 1.0 and kappa == 1.0
+
+
+@pytest.mark.parametrize("name,make,status", [
+    ("infeasible_lp", PS.infeasible_lp, ipm.PRIMAL_INFEASIBLE),
+    ("unbounded_lp", PS.unbounded_lp, ipm.DUAL_INFEASIBLE),
+    ("infeasible_socp", PS.infeasible_socp, ipm.PRIMAL_INFEASIBLE),
+    ("unbounded_socp", PS.unbounded_socp, ipm.DUAL_INFEASIBLE),
+])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_infeasibility_certificates(name, make, status, precision):
+    """eq. infeasibility-check on the GPU: the same status as the oracle, and
+    the certificate hc_get_solution returns meets the inequalities on the
+    user's data and lies in the dual (resp. primal) cone."""
+    prob = make()
+    ref = ipm.solve(prob)
+    assert ref.status == status
+    info, x, sv, z = gpu_solve(prob, precision=precision)
+    assert info["status"] == status, (name, info)
+    if status == ipm.PRIMAL_INFEASIBLE:
+        bz = prob.b @ z
+        assert bz < 0 and np.abs(prob.A.T @ z).max() <= 1e-6 * abs(bz), (bz, prob.A.T @ z)
+        soc = z[: 3] if name == "infeasible_socp" else None
+        if soc is not None:
+            assert soc[0] >= np.linalg.norm(soc[1:]) - 1e-9 * abs(bz) and z[3] >= -1e-9 * abs(bz)
+        else:
+            assert np.all(z >= -1e-9 * abs(bz))
+    else:
+        qx = prob.q @ x
+        w = -(prob.A @ x)
+        assert qx < 0
+        if name == "unbounded_socp":
+            assert w[0] >= np.linalg.norm(w[1:3]) - 1e-9 * abs(qx) and w[3] >= -1e-9 * abs(qx)
+        else:
+            assert np.all(w >= -1e-9 * abs(qx))
+
+
+def test_solution_on_device_matches_host():
+    """hc_get_solution with on_device: the same values as the host form."""
+    for prob in (W.mpc_socp(0, 3), PS.infeasible_lp()):
+        s = HC.Solver(prob)
+        s.solve()
+        xh, sh, zh = s.solution()
+        xd, sd, zd = s.solution(on_device=True)
+        s.close()
+        assert np.array_equal(xh, xd.cpu().numpy())
+        assert np.array_equal(sh, sd.cpu().numpy())
+        assert np.array_equal(zh, zd.cpu().numpy())
+
+
+# 24 requests of the served MPC stream's generator (horizons 10..100, 4..12
+# states, 2..6 inputs), each against the oracle
+MPC_STREAM = [(7, i) for i in range(24)]
+_MPC_REF = {}
+
+
+def mpc_reference(seed, i):
+    if (seed, i) not in _MPC_REF:
+        prob = W.mpc_socp(seed, i)
+        ref = ipm.solve(prob)
+        assert ref.status == ipm.SOLVED
+        _MPC_REF[(seed, i)] = (prob, ref.objective)
+    return _MPC_REF[(seed, i)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mpc_stream_against_oracle(precision):
+    sizes = set()
+    for seed, i in MPC_STREAM:
+        prob, fo = mpc_reference(seed, i)
+        sizes.add(prob.n)
+        info, x, sv, z = gpu_solve(prob, precision=precision)
+        assert info["status_name"] == "solved", (prob.name, info)
+        gp = certify(prob, x, sv, z)
+        assert abs(gp - fo) <= 1e-7 * max(1.0, abs(fo)), (prob.name, gp, fo)
+    assert max(sizes) > 4 * min(sizes)

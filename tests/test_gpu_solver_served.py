@@ -10,7 +10,7 @@ torch = pytest.importorskip("torch")
 
 from paper_2412_19027_amd import hipcone as HC  # noqa: E402
 from paper_2412_19027_amd import workloads as W  # noqa: E402
-from tests.test_gpu_solver import certify, gpu_solve  # noqa: E402
+from tests.test_gpu_solver import MPC_STREAM, certify, gpu_solve, mpc_reference  # noqa: E402
 
 
 def test_server_matches_direct_solves():
@@ -61,3 +61,20 @@ def test_server_close_with_work_in_flight():
     for i in range(8):
         srv.submit(W.mpc_socp(2, i))
     srv.close()   # queued and active problems end as cancelled; must return promptly
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_server_mpc_stream_against_oracle(precision):
+    """The served form on 24 MPC requests of uneven size in flight together:
+    every result against the oracle's objective and the optimality
+    inequalities on the user's data."""
+    refs = [mpc_reference(seed, i) for seed, i in MPC_STREAM]
+    srv = HC.Server(hbm_budget_bytes=4 << 30, max_slots=8, workers=2,
+                    precision=HC.PRECISION_FP64 if precision == "fp64" else HC.PRECISION_MIXED)
+    tickets = [srv.submit(p, tag=i) for i, (p, _) in enumerate(refs)]
+    res = [srv.wait(t, solution=True) for t in tickets]
+    srv.close()
+    for (p, fo), r in zip(refs, res):
+        assert r["status_name"] == "solved", (p.name, r)
+        gp = certify(p, r["x"], r["s"], r["z"])
+        assert abs(gp - fo) <= 1e-7 * max(1.0, abs(fo)), (p.name, gp, fo)

@@ -75,6 +75,23 @@ def test_dual_infeasible_certificate():
     assert prob.q @ x < 0 and np.all(-(prob.A @ x) >= -1e-12)
 
 
+def test_socp_infeasibility_certificates():
+    """Second-order-cone cases of eq. infeasibility-check: the certificate
+    lies in the dual (resp. primal) cone and meets the inequalities."""
+    prob = PS.infeasible_socp()
+    s = ipm.solve(prob)
+    assert s.status == ipm.PRIMAL_INFEASIBLE
+    z = s.E * s.z / s.c
+    assert prob.b @ z < 0 and np.abs(prob.A.T @ z).max() <= 1e-6 * abs(prob.b @ z)
+    assert z[0] >= np.linalg.norm(z[1:3]) - 1e-12 and z[3] >= -1e-12
+    prob = PS.unbounded_socp()
+    s = ipm.solve(prob)
+    assert s.status == ipm.DUAL_INFEASIBLE
+    x = s.D * s.x
+    w = -(prob.A @ x)
+    assert prob.q @ x < 0 and w[0] >= np.linalg.norm(w[1:3]) - 1e-9 * abs(prob.q @ x) and w[3] >= -1e-12
+
+
 @pytest.mark.parametrize("make", [lambda: W.sparse_socp(1, nx=300, rank=4, n_zero=60, n_nonneg=200, n_soc=200),
                                   lambda: W.logreg_exp(1, samples=200, features=15),
                                   lambda: W.psd_pow(1, n=150, n_pow=60, n_psd=12, k=3)])
