@@ -107,8 +107,11 @@ typedef struct {
   int32_t equil_iters;    /* 10                                                     */
   int32_t force_dual_scaling; /* 0: exp/pow use the primal-dual (BFGS) scaling      */
   int32_t verbose;        /* 0                                                      */
-  int32_t profile;        /* 1: time the factorisation's MFMA update kernels with HIP
-                             events (hc_info.gemm_*); 0 = off                      */
+  int32_t profile;        /* 1: time the factorisation's MFMA update kernels and the
+                             cone-layer launches with HIP events (hc_info.gemm_*,
+                             cone_*); 2: the same with the look-ahead's trailing
+                             updates on the handle's stream, so that no timed
+                             kernel overlaps another; 0 = off                     */
   int32_t leaf_blocks;    /* 1: columns of the Schur complement that fall into small
                              connected components once the high-degree columns are
                              set aside are factored as leaf blocks ahead of the
@@ -210,6 +213,7 @@ int32_t hc_bind(hc_solver* s, const hc_device* dev);
 int32_t hc_solve(hc_solver* s);
 
 int32_t hc_get_info(const hc_solver* s, hc_info* out);
+
 
 /* Solution in the user's row order, unscaled and divided by tau (Sec. 2.2:
  * x/tau, s/tau, z/tau): x (n), s (m), z (m), caller-owned buffers (any may be
@@ -363,6 +367,11 @@ typedef struct {
   int32_t workers;          /* host threads / streams, 1..16 (4)                   */
   hc_settings settings;     /* applied to every problem (hc_settings_default)     */
   int32_t device;           /* HIP device ordinal (0)                              */
+  int32_t batched;          /* 1: problems the batched engine takes (hc_batch_check)
+                               run there, one wavefront each, all of them advanced
+                               by one graph-launched kernel per tick; the others on
+                               the per-slot workers.  0: every problem per slot (1) */
+  int32_t batch_slots;      /* problems in flight on the batched engine (1024)      */
 } hc_server_config;
 
 typedef struct {
@@ -382,6 +391,28 @@ typedef struct {
   double* s;
   double* z;
 } hc_result;
+
+/* Batched engine (the served form's tick, also callable directly): small
+ * problems with zero, nonnegative and second-order cones of at most 16 rows
+ * whose Schur complement S = P + delta I + A'MA has, after a reverse
+ * Cuthill-McKee ordering of its columns, a band half-width of at most 56.
+ * Each problem runs on one 64-lane wavefront and every problem in the batch
+ * advances by one iteration of Algorithm 1 per kernel launch (Sec. 3.2; the
+ * KKT system of eq. linsys_2x2 eliminated to S and factored as a band).
+ *
+ * hc_batch_check: HC_OK and the band half-width in *band when `s` (from
+ *   hc_setup) is eligible; HC_ERR_UNSUPPORTED with the reason in
+ *   hc_last_error(NULL) otherwise.
+ * hc_solve_batch: solves `count` set-up handles (they stay unbound) on
+ *   `stream` of `device`, allocating one device block for all of them and
+ *   freeing it on return; results[i] receives the outcome of handles[i] and,
+ *   where the caller set results[i].x/s/z, the solution (user coordinates,
+ *   divided by tau; the certificate for an infeasible status).  solve_ms is
+ *   the batch's device time.  Errors: HC_ERR_INVALID_ARG, HC_ERR_UNSUPPORTED
+ *   (a handle is not eligible: nothing is solved), HC_ERR_OOM, HC_ERR_DEVICE. */
+int32_t hc_batch_check(const hc_solver* s, int32_t* band);
+int32_t hc_solve_batch(hc_solver* const* handles, int32_t count, void* stream, int32_t device,
+                       hc_result* results);
 
 typedef struct {
   int64_t submitted, completed, rejected, cancelled, active, pending, iterations;

@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "hc_steps.h"
+#include "hc_wave.h"
 #include "hipcone.h"
 
 namespace {
@@ -51,6 +52,9 @@ struct Job {
   hc_info info{};
   std::vector<double> x, s, z;
   bool finished = false;
+  // batched engine
+  std::unique_ptr<hc::WavePlan> plan;
+  int slot = -1;
 };
 
 // first-fit allocator over [0, size) with coalescing, 256-byte granules
@@ -105,8 +109,14 @@ struct hc_server {
   bool stop = false;
   uint64_t next_ticket = 1;
   std::deque<std::shared_ptr<Job>> pending;
+  std::deque<std::shared_ptr<Job>> pending_wave;            // for the batched engine
+  std::deque<std::shared_ptr<Job>> to_plan;                 // set up, waiting for a planner thread
+  std::condition_variable cv_plan;
+  std::vector<std::thread> planners;
   std::unordered_map<uint64_t, std::shared_ptr<Job>> jobs;   // submitted, not yet collected
   std::vector<std::thread> workers;
+  std::thread wave_thread;
+  int64_t ticks = 0;
   // statistics
   size_t in_use = 0, peak = 0;
   int64_t submitted = 0, completed = 0, rejected = 0, cancelled = 0, iterations = 0, active = 0;
@@ -114,8 +124,25 @@ struct hc_server {
   double t_first = -1, t_last = 0, busy_ms = 0;
 
   void worker(int w, int cap);
+  void wave_worker(int cap);
+  void planner();
   void finish(const std::shared_ptr<Job>& j, int32_t rc, hipStream_t st);
+  void retire(const std::shared_ptr<Job>& j);   // bookkeeping of a finished job (lock held)
 };
+
+void hc_server::retire(const std::shared_ptr<Job>& j) {
+  j->t_end = now_ms();
+  j->finished = true;
+  pool.give(j->offset, j->bytes);
+  in_use -= Pool::round(j->bytes);
+  active--;
+  completed++;
+  iterations += j->info.iterations;
+  latencies.push_back(j->t_end - j->t_submit);
+  t_last = j->t_end;
+  cv_done.notify_all();
+  cv_work.notify_all();
+}
 
 void hc_server::finish(const std::shared_ptr<Job>& j, int32_t rc, hipStream_t st) {
   (void)st;
@@ -134,17 +161,178 @@ void hc_server::finish(const std::shared_ptr<Job>& j, int32_t rc, hipStream_t st
   std::lock_guard<std::mutex> lk(mu);
   j->error = rc;
   j->status = rc == HC_OK ? j->info.status : HC_STATUS_NUMERICAL_ERROR;
-  j->t_end = now_ms();
-  j->finished = true;
-  pool.give(j->offset, j->bytes);
-  in_use -= Pool::round(j->bytes);
-  active--;
-  completed++;
-  iterations += j->info.iterations;
-  latencies.push_back(j->t_end - j->t_submit);
-  t_last = j->t_end;
-  cv_done.notify_all();
-  cv_work.notify_all();
+  retire(j);
+}
+
+// Planner threads: the batched engine's plan of a set-up problem (ordering,
+// band layout, gather plan) is made off the submitting thread; a problem the
+// engine does not take goes to the per-slot workers.
+void hc_server::planner() {
+  for (;;) {
+    std::shared_ptr<Job> j;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_plan.wait(lk, [&] { return stop || !to_plan.empty(); });
+      if (stop) return;
+      j = to_plan.front();
+      to_plan.pop_front();
+    }
+    std::unique_ptr<hc::WavePlan> plan(new hc::WavePlan());
+    std::string why;
+    bool take = hc::wave_plan(j->h, plan.get(), &why);
+    size_t wb = take ? plan->blob_bytes() : 0;
+    if (take && Pool::round(wb) > pool.size) take = false;
+    if (take) {
+      hc_destroy(j->h);
+      j->h = nullptr;
+      j->plan = std::move(plan);
+      j->bytes = wb;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (j->plan) pending_wave.push_back(j);
+    else pending.push_back(j);
+    cv_work.notify_all();
+  }
+}
+
+// The batched engine: every tick is one graph launch (the interior-point
+// iteration of all slots in one kernel, then the slots' phase words copied to
+// pinned host memory); between ticks finished problems are read out and
+// retired and queued ones admitted into free slots and pool memory.
+void hc_server::wave_worker(int cap) {
+  using namespace hc;
+  (void)hipSetDevice(cfg.device);
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+  WaveDesc* hdesc = nullptr;
+  int32_t *hact = nullptr, *hstat = nullptr;
+  void* dtab = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ok = hipHostMalloc((void**)&hdesc, (size_t)cap * sizeof(WaveDesc), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&hact, (size_t)cap * sizeof(int32_t), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&hstat, (size_t)cap * sizeof(int32_t), hipHostMallocDefault) == hipSuccess &&
+            hipMalloc(&dtab, (size_t)cap * (sizeof(WaveDesc) + 2 * sizeof(int32_t))) == hipSuccess;
+  WaveDesc* ddesc = (WaveDesc*)dtab;
+  int32_t* dact = ok ? (int32_t*)((char*)dtab + (size_t)cap * sizeof(WaveDesc)) : nullptr;
+  int32_t* dstat = ok ? dact + cap : nullptr;
+  if (ok) {
+    std::memset(hact, 0, (size_t)cap * sizeof(int32_t));
+    ok = hipMemcpyAsync(dact, hact, (size_t)cap * sizeof(int32_t), hipMemcpyHostToDevice, st) == hipSuccess &&
+         hipStreamSynchronize(st) == hipSuccess;
+  }
+  if (ok) {   // the tick, captured once
+    ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+      wave_tick(ddesc, dact, cap, dstat, st);
+      (void)hipMemcpyAsync(hstat, dstat, (size_t)cap * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+      ok = hipStreamEndCapture(st, &graph) == hipSuccess &&
+           hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    }
+  }
+  std::vector<std::shared_ptr<Job>> slot(cap);
+  std::vector<int> free_slots;
+  for (int i = cap - 1; i >= 0; --i) free_slots.push_back(i);
+  int nact = 0;
+  for (;;) {
+    std::vector<std::shared_ptr<Job>> fresh;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      auto admissible = [&]() {
+        if (pending_wave.empty() || free_slots.empty()) return false;
+        size_t off = 0;
+        if (!pool.take(pending_wave.front()->bytes, &off)) return false;
+        pool.give(off, pending_wave.front()->bytes);
+        return true;
+      };
+      while (!stop && nact == 0 && !admissible()) cv_work.wait(lk);
+      if (stop) break;
+      while (!free_slots.empty() && !pending_wave.empty()) {
+        auto j = pending_wave.front();
+        size_t off = 0;
+        if (!pool.take(j->bytes, &off)) break;   // first in, first out: wait for memory
+        pending_wave.pop_front();
+        j->offset = off;
+        j->slot = free_slots.back();
+        free_slots.pop_back();
+        in_use += Pool::round(j->bytes);
+        peak = std::max(peak, in_use);
+        active++;
+        fresh.push_back(j);
+      }
+    }
+    if (!ok) {   // no engine on this device: fail what was admitted
+      for (auto& j : fresh) {
+        std::lock_guard<std::mutex> lk(mu);
+        j->error = HC_ERR_DEVICE;
+        j->status = HC_STATUS_NUMERICAL_ERROR;
+        free_slots.push_back(j->slot);
+        retire(j);
+      }
+      continue;
+    }
+    for (auto& j : fresh) {
+      j->t_start = now_ms();
+      wave_upload(*j->plan, pool_base + j->offset, &hdesc[j->slot], st);
+      hact[j->slot] = 1;
+      slot[j->slot] = j;
+      ++nact;
+    }
+    if (!fresh.empty()) {
+      (void)hipMemcpyAsync(ddesc, hdesc, (size_t)cap * sizeof(WaveDesc), hipMemcpyHostToDevice, st);
+      (void)hipMemcpyAsync(dact, hact, (size_t)cap * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    }
+    if (nact == 0) continue;
+    const double t0 = now_ms();
+    const bool launched = hipGraphLaunch(exec, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+    bool changed = false;
+    for (int i = 0; i < cap; ++i) {
+      if (!hact[i]) continue;
+      auto& j = slot[i];
+      if (launched && hstat[i] != PH_DONE) continue;
+      hc_info inf{};
+      j->x.resize(j->n);
+      j->s.resize(j->m);
+      j->z.resize(j->m);
+      if (launched) wave_result(hdesc[i], *j->plan, &inf, j->x.data(), j->s.data(), j->z.data(), st);
+      hact[i] = 0;
+      changed = true;
+      --nact;
+      std::lock_guard<std::mutex> lk(mu);
+      j->info = inf;
+      j->error = launched ? HC_OK : HC_ERR_DEVICE;
+      j->status = launched ? inf.status : HC_STATUS_NUMERICAL_ERROR;
+      j->plan.reset();
+      free_slots.push_back(i);
+      retire(j);
+      slot[i].reset();
+    }
+    if (changed) (void)hipMemcpyAsync(dact, hact, (size_t)cap * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    std::lock_guard<std::mutex> lk(mu);
+    busy_ms += now_ms() - t0;
+    ticks++;
+  }
+  // shutting down: cancel the active problems
+  (void)hipStreamSynchronize(st);
+  for (int i = 0; i < cap; ++i) {
+    if (!hact || !hact[i] || !slot[i]) continue;
+    std::lock_guard<std::mutex> lk(mu);
+    auto& j = slot[i];
+    j->status = HC_STATUS_CANCELLED;
+    j->finished = true;
+    j->t_end = now_ms();
+    pool.give(j->offset, j->bytes);
+    in_use -= Pool::round(j->bytes);
+    active--;
+    cancelled++;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (dtab) (void)hipFree(dtab);
+  if (hdesc) (void)hipHostFree(hdesc);
+  if (hact) (void)hipHostFree(hact);
+  if (hstat) (void)hipHostFree(hstat);
+  (void)hipStreamDestroy(st);
 }
 
 void hc_server::worker(int w, int cap) {
@@ -282,13 +470,16 @@ int32_t hc_server_config_default(hc_server_config* c) {
   c->max_slots = 64;
   c->workers = 4;
   c->device = 0;
+  c->batched = 1;
+  c->batch_slots = 1024;
   return hc_settings_default(&c->settings);
 }
 
 int32_t hc_server_create(hc_server** out, const hc_server_config* cfg) {
   if (!out || !cfg) return HC_ERR_INVALID_ARG;
   *out = nullptr;
-  if (cfg->max_slots < 1 || cfg->workers < 1 || cfg->workers > 16 || cfg->hbm_budget_bytes < 4096)
+  if (cfg->max_slots < 1 || cfg->workers < 1 || cfg->workers > 16 || cfg->hbm_budget_bytes < 4096 ||
+      (cfg->batched && (cfg->batch_slots < 1 || cfg->batch_slots > 65536)))
     return HC_ERR_INVALID_ARG;
   std::unique_ptr<hc_server> s(new hc_server());
   s->cfg = *cfg;
@@ -301,6 +492,10 @@ int32_t hc_server_create(hc_server** out, const hc_server_config* cfg) {
   for (int w = 0; w < nw; ++w) {
     const int cap = cfg->max_slots / nw + (w < cfg->max_slots % nw ? 1 : 0);
     s->workers.emplace_back(&hc_server::worker, s.get(), w, cap);
+  }
+  if (cfg->batched) {
+    s->wave_thread = std::thread(&hc_server::wave_worker, s.get(), cfg->batch_slots);
+    for (int i = 0; i < std::max(2, cfg->workers); ++i) s->planners.emplace_back(&hc_server::planner, s.get());
   }
   *out = s.release();
   return HC_OK;
@@ -329,13 +524,18 @@ int32_t hc_server_submit(hc_server* s, const hc_problem* p, uint64_t tag, uint64
   j->t_submit = t;
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) {
-    hc_destroy(h);
+    if (h) hc_destroy(h);
     return HC_ERR_STATE;
   }
   j->ticket = s->next_ticket++;
   *ticket = j->ticket;
   s->jobs[j->ticket] = j;
-  s->pending.push_back(j);
+  if (s->cfg.batched) {
+    s->to_plan.push_back(j);   // a planner thread decides where it runs
+    s->cv_plan.notify_one();
+  } else {
+    s->pending.push_back(j);
+  }
   s->submitted++;
   if (s->t_first < 0) s->t_first = t;
   s->cv_work.notify_all();
@@ -375,7 +575,7 @@ int32_t hc_server_stats(hc_server* s, hc_server_report* out) {
   out->rejected = s->rejected;
   out->cancelled = s->cancelled;
   out->active = s->active;
-  out->pending = (int64_t)s->pending.size();
+  out->pending = (int64_t)(s->pending.size() + s->pending_wave.size() + s->to_plan.size());
   out->iterations = s->iterations;
   out->hbm_in_use = s->in_use;
   out->hbm_peak = s->peak;
@@ -397,11 +597,24 @@ void hc_server_destroy(hc_server* s) {
     s->stop = true;
     s->cv_work.notify_all();
     s->cv_done.notify_all();
+    s->cv_plan.notify_all();
   }
+  for (auto& t : s->planners) t.join();
   for (auto& t : s->workers) t.join();
+  if (s->wave_thread.joinable()) s->wave_thread.join();
   for (auto& j : s->pending) {
     hc_destroy(j->h);
     j->h = nullptr;
+  }
+  for (auto& j : s->pending_wave) {
+    j->status = HC_STATUS_CANCELLED;
+    j->finished = true;
+  }
+  for (auto& j : s->to_plan) {
+    hc_destroy(j->h);
+    j->h = nullptr;
+    j->status = HC_STATUS_CANCELLED;
+    j->finished = true;
   }
   (void)hipFree(s->pool_base);
   delete s;

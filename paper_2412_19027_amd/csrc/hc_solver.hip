@@ -28,11 +28,13 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 
 #include "hc_cones.h"
 #include "hc_dense.h"
 #include "hc_leaf.h"
 #include "hc_vec.h"
+#include "hc_wave.h"
 
 using namespace hc;
 
@@ -165,6 +167,7 @@ struct hc_solver {
   std::unique_ptr<Prof> prof;
   std::unique_ptr<Prof> cprof;      // events around the cone-layer launches (settings.profile)
   Aux aux;   // side stream + events of the look-ahead factorisation
+  bool no_lookahead = false;        // factor on the handle's stream alone (no side stream)
   bool use64 = false;               // mixed mode: this iteration fell back to the FP64 factor
   int kiter = 0;                    // loop counter of the current solve
   double sdiag_max = 0;             // mixed mode: max |S_ii| of the last FP32 factorisation
@@ -1253,6 +1256,11 @@ __global__ void k_get_diag(int64_t n, int64_t ld, const double* __restrict__ A, 
   if (i < n) d[i] = A[i + i * ld];
 }
 
+// the look-ahead's side stream, unless the handle factors on its own stream
+// alone (allocation-free solves; settings.profile = 2, where the MFMA update
+// durations must not overlap other kernels)
+Aux* lookahead(hc_solver* S) { return (S->no_lookahead || S->st.profile == 2) ? nullptr : &S->aux; }
+
 // factor the regularised KKT system at the current scaling (state + hdiag
 // filled).  FP64: delta = delta_s + delta_d max|K_ii| (the oracle's reading).
 // Mixed mode factors only the Schur complement in FP32 (the cone pivots
@@ -1340,11 +1348,11 @@ void factor(hc_solver* S, bool fp64 = false) {
     // every column sits in a leaf block: nothing dense to factor
   } else if (low) {
     lower_to_f32(ntp, S->ld, S->dS, S->dS32, st);
-    dense_cholesky<float>(S->dS32, ntp, S->ld, S->dLinv32, tol, S->delta, S->dhits, st, pf, &S->aux,
+    dense_cholesky<float>(S->dS32, ntp, S->ld, S->dLinv32, tol, S->delta, S->dhits, st, pf, lookahead(S),
                           S->tail_last.data());
     dense_block_inverses<float>(S->dS32, ntp, S->ld, S->dLinv32, S->dX256f, S->dXT256f, st);
   } else {
-    dense_cholesky<double>(S->dS, ntp, S->ld, S->dLinv, tol, S->delta, S->dhits, st, pf, &S->aux,
+    dense_cholesky<double>(S->dS, ntp, S->ld, S->dLinv, tol, S->delta, S->dhits, st, pf, lookahead(S),
                            S->tail_last.data());
     dense_block_inverses<double>(S->dS, ntp, S->ld, S->dLinv, S->dX256, S->dXT256, st);
   }
@@ -2029,6 +2037,7 @@ void bind(hc_solver* S, const hc_device* dev) {
   }
   // segment views
   int pow_off = 0;
+  S->sdev.clear();
   for (const Segment& g : S->segs) {
     SegDev d;
     d.kind = g.kind;
@@ -2051,6 +2060,328 @@ void bind(hc_solver* S, const hc_device* dev) {
 void record(hc_solver* S, const Error& e) { S->last_error = e.msg; }
 
 }  // namespace
+
+// ===========================================================================
+// plan of a problem for the wave-per-problem engine (hc_wave.hip)
+// ===========================================================================
+namespace hc {
+
+namespace {
+
+// reverse Cuthill-McKee order of a symmetric graph (adjacency lists without
+// self loops): breadth-first from a pseudo-peripheral vertex of each
+// component, neighbours by increasing degree, the whole order reversed
+std::vector<int32_t> rcm_order(const std::vector<std::vector<int32_t>>& adj) {
+  const int32_t n = (int32_t)adj.size();
+  std::vector<int32_t> order;
+  order.reserve(n);
+  std::vector<char> seen(n, 0);
+  std::vector<int32_t> level(n, -1);
+  auto bfs_last = [&](int32_t s, int32_t* depth) {   // farthest vertex of s's component (least degree at that level)
+    std::vector<int32_t> q{s};
+    for (int32_t v : q) level[v] = -1;
+    level[s] = 0;
+    size_t h = 0;
+    int32_t best = s;
+    while (h < q.size()) {
+      const int32_t v = q[h++];
+      for (int32_t u : adj[v])
+        if (level[u] < 0) {
+          level[u] = level[v] + 1;
+          q.push_back(u);
+        }
+    }
+    int32_t maxl = 0;
+    for (int32_t v : q) maxl = std::max(maxl, level[v]);
+    for (int32_t v : q)
+      if (level[v] == maxl && (best == s || adj[v].size() < adj[best].size())) best = v;
+    for (int32_t v : q) level[v] = -1;
+    *depth = maxl;
+    return best;
+  };
+  for (int32_t start = 0; start < n; ++start) {
+    if (seen[start]) continue;
+    // pseudo-peripheral start: repeat the farthest-vertex search while the depth grows
+    int32_t r = start, depth = 0;
+    for (int it = 0; it < 3; ++it) {
+      int32_t d2 = 0;
+      const int32_t far = bfs_last(r, &d2);
+      if (it > 0 && d2 <= depth) break;
+      depth = d2;
+      r = far;
+    }
+    std::vector<int32_t> q{r};
+    seen[r] = 1;
+    size_t h = 0;
+    std::vector<int32_t> nb;
+    while (h < q.size()) {
+      const int32_t v = q[h++];
+      nb.clear();
+      for (int32_t u : adj[v])
+        if (!seen[u]) {
+          seen[u] = 1;
+          nb.push_back(u);
+        }
+      std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) {
+        return adj[a].size() != adj[b].size() ? adj[a].size() < adj[b].size() : a < b;
+      });
+      for (int32_t u : nb) q.push_back(u);
+    }
+    for (int32_t v : q) order.push_back(v);
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+}  // namespace
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+bool wave_plan(const hc_solver* S, WavePlan* out, std::string* why) {
+  auto no = [&](const std::string& m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (S->has_nonsym) return no("exponential or power cones");
+  if (!S->drows.empty() || S->K1 + S->K2 > 0) return no("dense rows or second-order cones above 16 rows");
+  if (S->n < 1 || S->m < 1 || S->n > (1 << 24) || S->m > (1 << 24)) return no("size outside the engine's range");
+  WavePlan& P = *out;
+  P = WavePlan{};
+  const int32_t n = (int32_t)S->n, m = (int32_t)S->m;
+  P.n = n;
+  P.m = m;
+  // engine rows: zero rows, nonneg rows, then second-order cones one after another
+  std::vector<int32_t> wrow_of(m, -1), srow_of;   // S-internal row -> engine row, and back
+  srow_of.reserve(m);
+  std::vector<int32_t> soc_dims;
+  for (const Segment& g : S->segs) {
+    if (g.kind == HC_CONE_PSD) return no("PSD cones");
+    if (g.kind == HC_CONE_SOC && g.dim > SOC_DMAX) return no("second-order cones above 16 rows");
+  }
+  for (int pass = 0; pass < 3; ++pass)
+    for (const Segment& g : S->segs) {
+      const int kind = pass == 0 ? HC_CONE_ZERO : pass == 1 ? HC_CONE_NONNEG : HC_CONE_SOC;
+      if (g.kind != kind) continue;
+      if (kind != HC_CONE_SOC) {
+        for (int64_t i = 0; i < g.count; ++i) srow_of.push_back((int32_t)(g.base + i));
+        if (kind == HC_CONE_ZERO) P.nz += (int32_t)g.count;
+        else P.nn += (int32_t)g.count;
+      } else {
+        for (int64_t i = 0; i < g.count; ++i) {
+          for (int j = 0; j < g.dim; ++j) srow_of.push_back((int32_t)(g.base + (int64_t)j * g.count + i));
+          soc_dims.push_back(g.dim);
+        }
+      }
+    }
+  if ((int32_t)srow_of.size() != m) return no("row bookkeeping");
+  for (int32_t r = 0; r < m; ++r) wrow_of[srow_of[r]] = r;
+  P.nsoc = (int32_t)soc_dims.size();
+  P.soc_off.assign(P.nsoc + 1, 0);
+  P.soc_moff.assign(P.nsoc, 0);
+  P.mtot = P.nz + P.nn;
+  for (int32_t c = 0; c < P.nsoc; ++c) {
+    P.soc_off[c + 1] = P.soc_off[c] + soc_dims[c];
+    P.soc_moff[c] = P.mtot;
+    P.mtot += soc_dims[c] * soc_dims[c];
+  }
+  // blocks of S: each zero/nonneg row, each cone; their column sets are cliques of S
+  const int32_t nblk = P.nz + P.nn + P.nsoc;
+  auto block_rows = [&](int32_t bk, int32_t* r0, int32_t* r1) {
+    if (bk < P.nz + P.nn) {
+      *r0 = bk;
+      *r1 = bk + 1;
+    } else {
+      const int32_t c = bk - P.nz - P.nn;
+      *r0 = P.nz + P.nn + P.soc_off[c];
+      *r1 = P.nz + P.nn + P.soc_off[c + 1];
+    }
+  };
+  const HostCsr& A = S->A;   // S-internal rows
+  // graph of S as adjacency lists: the cliques of the blocks and P's pattern,
+  // through the column -> block incidence (duplicates removed by a stamp)
+  std::vector<std::vector<int32_t>> adj(n);
+  {
+    std::vector<int32_t> brp(nblk + 1, 0), bci;   // block -> columns
+    bci.reserve(A.ci.size());
+    for (int32_t bk = 0; bk < nblk; ++bk) {
+      int32_t r0, r1;
+      block_rows(bk, &r0, &r1);
+      const size_t first = bci.size();
+      for (int32_t r = r0; r < r1; ++r) {
+        const int32_t sr = srow_of[r];
+        for (int32_t k = A.rp[sr]; k < A.rp[sr + 1]; ++k) bci.push_back(A.ci[k]);
+      }
+      if (r1 - r0 > 1) {
+        std::sort(bci.begin() + first, bci.end());
+        bci.erase(std::unique(bci.begin() + first, bci.end()), bci.end());
+      }
+      if (bci.size() - first > (size_t)2 * WAVE_WMAX + 2)
+        return no("a cone or row couples more columns than the band allows");
+      brp[bk + 1] = (int32_t)bci.size();
+    }
+    std::vector<int32_t> crp(n + 1, 0), cbk(bci.size());   // column -> blocks
+    for (int32_t c : bci) crp[c + 1]++;
+    for (int32_t i = 0; i < n; ++i) crp[i + 1] += crp[i];
+    {
+      std::vector<int32_t> f(crp.begin(), crp.end() - 1);
+      for (int32_t bk = 0; bk < nblk; ++bk)
+        for (int32_t k = brp[bk]; k < brp[bk + 1]; ++k) cbk[f[bci[k]]++] = bk;
+    }
+    std::vector<int32_t> stamp(n, -1);
+    for (int32_t a = 0; a < n; ++a) {
+      stamp[a] = a;
+      std::vector<int32_t>& nb = adj[a];
+      for (int32_t k = crp[a]; k < crp[a + 1]; ++k) {
+        const int32_t bk = cbk[k];
+        for (int32_t l = brp[bk]; l < brp[bk + 1]; ++l)
+          if (stamp[bci[l]] != a) {
+            stamp[bci[l]] = a;
+            nb.push_back(bci[l]);
+          }
+      }
+      for (int32_t k = S->P.rp[a]; k < S->P.rp[a + 1]; ++k)
+        if (stamp[S->P.ci[k]] != a) {
+          stamp[S->P.ci[k]] = a;
+          nb.push_back(S->P.ci[k]);
+        }
+    }
+  }
+  const std::vector<int32_t> order = rcm_order(adj);   // band position -> column
+  std::vector<int32_t> pos(n);
+  for (int32_t i = 0; i < n; ++i) pos[order[i]] = i;
+  int32_t w = 0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t u : adj[i]) w = std::max(w, std::abs(pos[i] - pos[u]));
+  if (w > WAVE_WMAX) return no("band half-width " + std::to_string(w) + " above " + std::to_string(WAVE_WMAX));
+  P.w = w;
+  const int32_t W = w + 1;
+  P.colperm = order;
+  P.rowperm.resize(m);
+  for (int32_t r = 0; r < m; ++r) P.rowperm[r] = (int32_t)S->perm[srow_of[r]];
+  // A in engine rows and band columns, and its transpose
+  P.Arp.assign(m + 1, 0);
+  for (int32_t r = 0; r < m; ++r) {
+    const int32_t sr = srow_of[r];
+    P.Arp[r + 1] = P.Arp[r] + (A.rp[sr + 1] - A.rp[sr]);
+  }
+  P.Aci.resize(P.Arp[m]);
+  P.Av.resize(P.Arp[m]);
+  {
+    std::vector<std::pair<int32_t, double>> ent;
+    for (int32_t r = 0; r < m; ++r) {
+      const int32_t sr = srow_of[r];
+      ent.clear();
+      for (int32_t k = A.rp[sr]; k < A.rp[sr + 1]; ++k) ent.emplace_back(pos[A.ci[k]], A.v[k]);
+      std::sort(ent.begin(), ent.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+      int32_t o = P.Arp[r];
+      for (const auto& e : ent) {
+        P.Aci[o] = e.first;
+        P.Av[o++] = e.second;
+      }
+    }
+  }
+  P.Atrp.assign(n + 1, 0);
+  for (int32_t k = 0; k < P.Arp[m]; ++k) P.Atrp[P.Aci[k] + 1]++;
+  for (int32_t j = 0; j < n; ++j) P.Atrp[j + 1] += P.Atrp[j];
+  P.Atci.resize(P.Arp[m]);
+  P.Atv.resize(P.Arp[m]);
+  {
+    std::vector<int32_t> fill(P.Atrp.begin(), P.Atrp.end() - 1);
+    for (int32_t r = 0; r < m; ++r)
+      for (int32_t k = P.Arp[r]; k < P.Arp[r + 1]; ++k) {
+        const int32_t o = fill[P.Aci[k]]++;
+        P.Atci[o] = r;
+        P.Atv[o] = P.Av[k];
+      }
+  }
+  // P (full, both triangles) in band columns, and its lower band
+  P.Prp.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) P.Prp[i + 1] = P.Prp[i] + (S->P.rp[order[i] + 1] - S->P.rp[order[i]]);
+  P.Pci.resize(P.Prp[n]);
+  P.Pv.resize(P.Prp[n]);
+  P.Pband.assign((size_t)n * W, 0.0);
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t o = P.Prp[i];
+    for (int32_t k = S->P.rp[order[i]]; k < S->P.rp[order[i] + 1]; ++k, ++o) {
+      const int32_t j = pos[S->P.ci[k]];
+      P.Pci[o] = j;
+      P.Pv[o] = S->P.v[k];
+      if (i >= j) P.Pband[(size_t)j * W + (i - j)] += S->P.v[k];
+    }
+  }
+  P.q.resize(n);
+  P.D.resize(n);
+  for (int32_t i = 0; i < n; ++i) {
+    P.q[i] = S->q[order[i]];
+    P.D[i] = S->D[order[i]];
+  }
+  P.b.resize(m);
+  P.E.resize(m);
+  for (int32_t r = 0; r < m; ++r) {
+    P.b[r] = S->b[srow_of[r]];
+    P.E[r] = S->E[srow_of[r]];
+  }
+  // A'MA gather plan: for every band entry (i >= j) its terms A_pi A_qj M_pq
+  // over the rows p, q of one block (p = q for zero and nonneg rows), listed
+  // in block order and then grouped by entry with a counting sort (stable, so
+  // that order is the order of the terms within an entry)
+  {
+    struct Term {
+      int32_t e, mi;
+      double c;
+    };
+    std::vector<Term> terms;
+    terms.reserve((size_t)P.Arp[m] * 8);
+    P.trp.assign((size_t)n * W + 1, 0);
+    for (int32_t bk = 0; bk < nblk; ++bk) {
+      int32_t r0, r1;
+      block_rows(bk, &r0, &r1);
+      if (bk < P.nz + P.nn) {   // one row; its columns ascend, so kb <= ka gives i >= j
+        for (int32_t ka = P.Arp[r0]; ka < P.Arp[r0 + 1]; ++ka) {
+          const int32_t i = P.Aci[ka];
+          const double va = P.Av[ka];
+          for (int32_t kb = P.Arp[r0]; kb <= ka; ++kb) {
+            const int32_t e = P.Aci[kb] * W + (i - P.Aci[kb]);
+            terms.push_back(Term{e, bk, va * P.Av[kb]});
+            P.trp[e + 1]++;
+          }
+        }
+        continue;
+      }
+      const int32_t d = r1 - r0;
+      const int32_t mo = P.soc_moff[bk - P.nz - P.nn];
+      for (int32_t p = r0; p < r1; ++p)
+        for (int32_t q2 = r0; q2 < r1; ++q2)
+          for (int32_t ka = P.Arp[p]; ka < P.Arp[p + 1]; ++ka)
+            for (int32_t kb = P.Arp[q2]; kb < P.Arp[q2 + 1]; ++kb) {
+              const int32_t i = P.Aci[ka], j = P.Aci[kb];
+              if (i < j) continue;
+              const int32_t e = j * W + (i - j);
+              terms.push_back(Term{e, mo + (p - r0) * d + (q2 - r0), P.Av[ka] * P.Av[kb]});
+              P.trp[e + 1]++;
+            }
+    }
+    for (size_t e = 0; e < (size_t)n * W; ++e) P.trp[e + 1] += P.trp[e];
+    P.tm.resize(terms.size());
+    P.tc.resize(terms.size());
+    std::vector<int32_t> fill(P.trp.begin(), P.trp.end() - 1);
+    for (const Term& tt : terms) {
+      const int32_t o = fill[tt.e]++;
+      P.tm[o] = tt.mi;
+      P.tc[o] = tt.c;
+    }
+  }
+  P.cscale = S->cscale;
+  P.bnorm = S->bnorm_user;
+  P.qnorm = S->qnorm_user;
+  P.maxPdiag = S->maxPdiag;
+  P.nu = S->nu;
+  P.st = S->st;
+  P.mixed = S->mixed;
+  return true;
+}
+
+}  // namespace hc
 
 // ===========================================================================
 // step-wise driving (continuous-batching server)

@@ -1,0 +1,1033 @@
+// Wave-per-problem engine (see hc_wave.h): device code and slot layout.
+//
+// One workgroup of 64 lanes (a single wavefront) per problem.  Vectors are
+// walked lane-strided; a __syncthreads() closes every phase that later lanes
+// read through global memory (for a one-wave workgroup it is a wait for the
+// wave's own memory operations, not a cross-wave barrier).  The band Cholesky
+// and the triangular solves keep their active rows in LDS (a circular window
+// of WAVE_WB rows) and fetch the rows of the next WAVE_PB steps while the
+// current ones are computed.
+#include "hc_cones.h"
+#include "hc_soc_math.h"
+#include "hc_wave.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace hc {
+
+namespace {
+
+constexpr int WL = 64;   // lanes per slot
+
+// work vectors of max(n, m) doubles
+enum WaveVec {
+  WV_X = 0, WV_S, WV_Z, WV_PX, WV_AX, WV_ATZ, WV_RDV, WV_RPV, WV_X2, WV_Z2, WV_X1, WV_Z1, WV_DX, WV_DZ, WV_DSV,
+  WV_DSRHS, WV_DXA, WV_DZA, WV_DSA, WV_R1, WV_R2, WV_IRX, WV_IRZ, WV_IRXN, WV_IRZN, WV_IRBX, WV_IRBZ, WV_IRRX,
+  WV_IRRZ, WV_KX, WV_KZ, WV_T1, WV_T2, WV_U1, WV_W1, WV_COUNT
+};
+
+__device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+
+// the wave's own global-memory writes are visible to all its lanes after this
+__device__ __forceinline__ void gsync() { __syncthreads(); }
+// orders the wave's LDS accesses (the LDS executes one wave's instructions in order)
+__device__ __forceinline__ void lsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wsum(double v) {
+  for (int o = WL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WL);
+  return v;
+}
+__device__ __forceinline__ double nanmax(double a, double b) { return (a != a || b != b) ? NAN : fmax(a, b); }
+__device__ __forceinline__ double wmax(double v) {
+  for (int o = WL / 2; o > 0; o >>= 1) v = nanmax(v, __shfl_xor(v, o, WL));
+  return v;
+}
+__device__ __forceinline__ double wmin(double v) {
+  for (int o = WL / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, WL));
+  return v;
+}
+
+// ---------------------------------------------------------------- vectors
+__device__ void v_fill(int n, double a, double* y) {
+  for (int i = lane_id(); i < n; i += WL) y[i] = a;
+  gsync();
+}
+__device__ void v_copy(int n, const double* x, double* y) {
+  for (int i = lane_id(); i < n; i += WL) y[i] = x[i];
+  gsync();
+}
+// o = a x + b y + c z (y, z optional)
+__device__ void v_lin(int n, double a, const double* x, double b, const double* y, double c, const double* z,
+                      double* o) {
+  for (int i = lane_id(); i < n; i += WL) {
+    double v = a * x[i];
+    if (y) v += b * y[i];
+    if (z) v += c * z[i];
+    o[i] = v;
+  }
+  gsync();
+}
+// y = a x + b y
+__device__ void v_axpby(int n, double a, const double* x, double b, double* y) {
+  for (int i = lane_id(); i < n; i += WL) y[i] = a * x[i] + b * y[i];
+  gsync();
+}
+__device__ double v_dot(int n, const double* x, const double* y) {
+  double acc = 0.0;
+  for (int i = lane_id(); i < n; i += WL) acc += x[i] * y[i];
+  return wsum(acc);
+}
+// max |(x + yc y) w| (divide: / w); w and y optional
+__device__ double v_maxabs(int n, const double* x, const double* w = nullptr, bool divide = false,
+                           const double* y = nullptr, double yc = 0.0) {
+  double acc = 0.0;
+  for (int i = lane_id(); i < n; i += WL) {
+    double v = x[i];
+    if (y) v += yc * y[i];
+    if (w) v = divide ? v / w[i] : v * w[i];
+    acc = nanmax(acc, fabs(v));
+  }
+  return wmax(acc);
+}
+// y = alpha A x + beta y (CSR, lane per row; beta = 0 does not read y)
+__device__ void spmv(int rows, const int32_t* rp, const int32_t* ci, const double* va, const double* x, double* y,
+                     double alpha, double beta) {
+  for (int r = lane_id(); r < rows; r += WL) {
+    double acc = 0.0;
+    for (int k = rp[r]; k < rp[r + 1]; ++k) acc += va[k] * x[ci[k]];
+    y[r] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * y[r];
+  }
+  gsync();
+}
+
+// ---------------------------------------------------------------- cones
+struct Cone {
+  int o, d;        // first row, rows
+  double* st;      // wbar (d), eta, lambda (d)
+};
+__device__ __forceinline__ Cone soc_cone(const WaveDesc& D, int c) {
+  Cone k;
+  k.o = D.nz + D.nn + D.soc_off[c];
+  k.d = D.soc_off[c + 1] - D.soc_off[c];
+  k.st = D.hst + D.nn + 2 * D.soc_off[c] + c;
+  return k;
+}
+
+// scaling at (s, z): nonneg h = s / z; SOC the Nesterov-Todd point; diag(H)
+__device__ void c_scale(const WaveDesc& D, const double* s, const double* z) {
+  for (int r = lane_id(); r < D.nz; r += WL) D.hdiag[r] = 0.0;
+  for (int i = lane_id(); i < D.nn; i += WL) {
+    const int r = D.nz + i;
+    const double h = s[r] / z[r];
+    D.hst[i] = h;
+    D.hdiag[r] = h;
+  }
+  for (int c = lane_id(); c < D.nsoc; c += WL) {
+    const Cone k = soc_cone(D, c);
+    double sv[SOC_DMAX], zv[SOC_DMAX], wb[SOC_DMAX], lam[SOC_DMAX];
+    for (int j = 0; j < k.d; ++j) {
+      sv[j] = s[k.o + j];
+      zv[j] = z[k.o + j];
+    }
+    const double eta = soc_nt_scale(sv, zv, k.d, wb, lam);
+    for (int j = 0; j < k.d; ++j) {
+      k.st[j] = wb[j];
+      k.st[k.d + 1 + j] = lam[j];
+    }
+    k.st[k.d] = eta;
+    const double e2 = eta * eta;
+    for (int j = 0; j < k.d; ++j) D.hdiag[k.o + j] = e2 * (2.0 * wb[j] * wb[j] - (j == 0 ? 1.0 : -1.0));
+  }
+  gsync();
+}
+
+// H = I on the cone rows (0 on zero rows): the initial point's scaling
+__device__ void c_identity(const WaveDesc& D) {
+  for (int r = lane_id(); r < D.nz; r += WL) D.hdiag[r] = 0.0;
+  for (int i = lane_id(); i < D.nn; i += WL) {
+    D.hst[i] = 1.0;
+    D.hdiag[D.nz + i] = 1.0;
+  }
+  for (int c = lane_id(); c < D.nsoc; c += WL) {
+    const Cone k = soc_cone(D, c);
+    for (int j = 0; j < k.d; ++j) {
+      k.st[j] = (j == 0) ? 1.0 : 0.0;
+      k.st[k.d + 1 + j] = (j == 0) ? 1.0 : 0.0;
+      D.hdiag[k.o + j] = 1.0;
+    }
+    k.st[k.d] = 1.0;
+  }
+  gsync();
+}
+
+// M = (H + delta I)^-1: one entry per zero/nonneg row, a full d x d block per SOC
+__device__ void c_mblock(const WaveDesc& D, double delta) {
+  for (int r = lane_id(); r < D.nz; r += WL) D.Mv[r] = 1.0 / delta;
+  for (int i = lane_id(); i < D.nn; i += WL) D.Mv[D.nz + i] = 1.0 / (D.hst[i] + delta);
+  for (int c = lane_id(); c < D.nsoc; c += WL) {
+    const Cone k = soc_cone(D, c);
+    double wb[SOC_DMAX], u[SOC_DMAX];
+    for (int j = 0; j < k.d; ++j) wb[j] = k.st[j];
+    const SocSpec sp = soc_spec(wb, k.d, k.st[k.d]);
+    for (int j = 1; j < k.d; ++j) u[j] = (sp.r > 0.0) ? wb[j] / sp.r : (j == 1 ? 1.0 : 0.0);
+    const double fp = 1.0 / (sp.lp + delta), fm = 1.0 / (sp.lm + delta), fo = 1.0 / (sp.lo + delta);
+    double* M = D.Mv + D.soc_moff[c];
+    for (int a = 0; a < k.d; ++a)
+      for (int b = 0; b <= a; ++b) {
+        double v;
+        if (a == 0) v = 0.5 * (fp + fm);
+        else if (b == 0) v = 0.5 * (fp - fm) * u[a];
+        else v = 0.5 * (fp + fm) * u[a] * u[b] + fo * ((a == b ? 1.0 : 0.0) - u[a] * u[b]);
+        M[a * k.d + b] = v;
+        M[b * k.d + a] = v;
+      }
+  }
+  gsync();
+}
+
+// y = H x (mode 0) or (H + delta I)^-1 x (mode 1); with dsr: y = -dsr - H x
+__device__ void c_apply(const WaveDesc& D, int mode, double delta, const double* x, const double* dsr, double* y) {
+  for (int r = lane_id(); r < D.nz; r += WL) y[r] = dsr ? -dsr[r] : ((mode == 0) ? 0.0 : x[r] / delta);
+  for (int i = lane_id(); i < D.nn; i += WL) {
+    const int r = D.nz + i;
+    const double h = D.hst[i];
+    if (dsr) y[r] = -dsr[r] - h * x[r];
+    else y[r] = (mode == 0) ? h * x[r] : x[r] / (h + delta);
+  }
+  for (int c = lane_id(); c < D.nsoc; c += WL) {
+    const Cone k = soc_cone(D, c);
+    double wb[SOC_DMAX], xv[SOC_DMAX], yv[SOC_DMAX];
+    for (int j = 0; j < k.d; ++j) {
+      wb[j] = k.st[j];
+      xv[j] = x[k.o + j];
+    }
+    const SocSpec sp = soc_spec(wb, k.d, k.st[k.d]);
+    if (mode == 0)
+      soc_spec_apply(wb, k.d, sp, sp.lp, sp.lm, sp.lo, xv, yv);
+    else
+      soc_spec_apply(wb, k.d, sp, 1.0 / (sp.lp + delta), 1.0 / (sp.lm + delta), 1.0 / (sp.lo + delta), xv, yv);
+    for (int j = 0; j < k.d; ++j) y[k.o + j] = dsr ? -dsr[k.o + j] - yv[j] : yv[j];
+  }
+  gsync();
+}
+
+// combined-step d_s (eq. ds-correction-step)
+__device__ void c_ds(const WaveDesc& D, const double* s, const double* z, const double* dsa, const double* dza,
+                     double sm, double* ds) {
+  for (int r = lane_id(); r < D.nz; r += WL) ds[r] = 0.0;
+  for (int i = lane_id(); i < D.nn; i += WL) {
+    const int r = D.nz + i;
+    ds[r] = (s[r] * z[r] + dsa[r] * dza[r] - sm) / z[r];
+  }
+  for (int c = lane_id(); c < D.nsoc; c += WL) {
+    const Cone k = soc_cone(D, c);
+    double wb[SOC_DMAX], lam[SOC_DMAX], a[SOC_DMAX], b[SOC_DMAX], x[SOC_DMAX];
+    for (int j = 0; j < k.d; ++j) {
+      wb[j] = k.st[j];
+      lam[j] = k.st[k.d + 1 + j];
+      a[j] = dsa[k.o + j];
+      b[j] = dza[k.o + j];
+    }
+    soc_ds_one(wb, k.st[k.d], lam, a, b, k.d, sm, x);
+    for (int j = 0; j < k.d; ++j) ds[k.o + j] = x[j];
+  }
+  gsync();
+}
+
+__device__ __forceinline__ double soc_step_x(const double* x, const double* dx, int d) {
+  double a = dx[0] * dx[0], b = x[0] * dx[0], c = x[0] * x[0];
+  for (int j = 1; j < d; ++j) {
+    a -= dx[j] * dx[j];
+    b -= x[j] * dx[j];
+    c -= x[j] * x[j];
+  }
+  return soc_boundary_step(a, b, c);
+}
+
+// largest alpha keeping s + alpha ds and z + alpha dz in the closed cones
+__device__ double c_step(const WaveDesc& D, const double* s, const double* z, const double* ds, const double* dz) {
+  double a = INFINITY;
+  for (int i = lane_id(); i < D.nn; i += WL) {
+    const int r = D.nz + i;
+    if (ds[r] < 0.0) a = fmin(a, -s[r] / ds[r]);
+    if (dz[r] < 0.0) a = fmin(a, -z[r] / dz[r]);
+  }
+  for (int c = lane_id(); c < D.nsoc; c += WL) {
+    const Cone k = soc_cone(D, c);
+    double xs[SOC_DMAX], xds[SOC_DMAX], xz[SOC_DMAX], xdz[SOC_DMAX];
+    for (int j = 0; j < k.d; ++j) {
+      xs[j] = s[k.o + j];
+      xds[j] = ds[k.o + j];
+      xz[j] = z[k.o + j];
+      xdz[j] = dz[k.o + j];
+    }
+    a = fmin(a, fmin(soc_step_x(xs, xds, k.d), soc_step_x(xz, xdz, k.d)));
+  }
+  return wmin(a);
+}
+
+// max over cones of -lambda_min(v)
+__device__ double c_max_neg_eig(const WaveDesc& D, const double* v) {
+  double a = -INFINITY;
+  for (int i = lane_id(); i < D.nn; i += WL) a = fmax(a, -v[D.nz + i]);
+  for (int c = lane_id(); c < D.nsoc; c += WL) {
+    const Cone k = soc_cone(D, c);
+    double r2 = 0.0;
+    for (int j = 1; j < k.d; ++j) r2 += v[k.o + j] * v[k.o + j];
+    a = fmax(a, sqrt(r2) - v[k.o]);
+  }
+  for (int o = WL / 2; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o, WL));
+  return a;
+}
+
+// v += a e on the cone rows
+__device__ void c_add_e(const WaveDesc& D, double a, double* v) {
+  for (int i = lane_id(); i < D.nn; i += WL) v[D.nz + i] += a;
+  for (int c = lane_id(); c < D.nsoc; c += WL) v[soc_cone(D, c).o] += a;
+  gsync();
+}
+
+// ---------------------------------------------------------------- band Cholesky and solves
+// S in band storage: column j holds S(j + t, j), t = 0..w, at Sb[j W + t].
+// In place: L (the diagonal L_jj at t = 0) and dinv[j] = 1 / L_jj.  A pivot
+// that is not positive is replaced by `fix` and counted.
+template <typename T>
+__device__ int band_cholesky(T* __restrict__ Sb, T* __restrict__ dinv, int n, int w, T fix, T* win, T* lcol) {
+  constexpr int WB = WAVE_WB, PB = WAVE_PB, LD = WAVE_WB + 1;
+  const int lane = lane_id();
+  const int W = w + 1;
+  int hits = 0;
+  // rows [0, w + PB) of the band
+  for (int i = 0; i < min(n, w + PB); ++i)
+    if (lane <= w && i - lane >= 0) win[(i & (WB - 1)) * LD + ((i - lane) & (WB - 1))] = Sb[(size_t)(i - lane) * W + lane];
+  lsync();
+  for (int j0 = 0; j0 < n; j0 += PB) {
+    // rows needed by the next block's steps, fetched now
+    T pf[PB];
+#pragma unroll
+    for (int s = 0; s < PB; ++s) {
+      const int i = j0 + w + PB + s;
+      pf[s] = (lane <= w && i < n && i - lane >= 0) ? Sb[(size_t)(i - lane) * W + lane] : T(0);
+    }
+#pragma unroll
+    for (int s = 0; s < PB; ++s) {
+      const int j = j0 + s;
+      if (j < n) {
+        const int jc = j & (WB - 1);
+        T d = win[jc * LD + jc];
+        if (!(d > T(0))) {
+          d = fix;
+          ++hits;
+        }
+        const T ljj = sqrt(d);
+        const T inv = T(1) / ljj;
+        const int rows = min(w, n - 1 - j);
+        T lk = T(0);
+        if (lane >= 1 && lane <= rows) {
+          lk = win[((j + lane) & (WB - 1)) * LD + jc] * inv;
+          lcol[lane] = lk;
+          Sb[(size_t)j * W + lane] = lk;
+        }
+        if (lane == 0) {
+          Sb[(size_t)j * W] = ljj;
+          dinv[j] = inv;
+        }
+        lsync();
+        if (lane >= 1 && lane <= rows) {
+          T* row = win + ((j + lane) & (WB - 1)) * LD;
+          for (int c = 1; c <= lane; ++c) row[(j + c) & (WB - 1)] -= lk * lcol[c];
+        }
+        lsync();
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < PB; ++s) {
+      const int i = j0 + w + PB + s;
+      if (lane <= w && i < n && i - lane >= 0) win[(i & (WB - 1)) * LD + ((i - lane) & (WB - 1))] = pf[s];
+    }
+    lsync();
+  }
+  gsync();
+  return hits;
+}
+
+// L y = b then L' x = y, in place on b (global, n entries)
+template <typename T>
+__device__ void band_solve(const T* __restrict__ L, const T* __restrict__ dinv, int n, int w, T* __restrict__ b,
+                           T* buf) {
+  constexpr int WB = WAVE_WB, PB = WAVE_PB;
+  const int lane = lane_id();
+  const int W = w + 1;
+  // forward: column j updates rows j + 1 .. j + w
+  if (lane < min(n, w + PB)) buf[lane & (WB - 1)] = b[lane];
+  lsync();
+  for (int j0 = 0; j0 < n; j0 += PB) {
+    T lc[PB], dv[PB];
+    T bn = T(0);
+#pragma unroll
+    for (int s = 0; s < PB; ++s) {
+      const int j = j0 + s;
+      lc[s] = (j < n && lane >= 1 && lane <= w && j + lane < n) ? L[(size_t)j * W + lane] : T(0);
+      dv[s] = (j < n) ? dinv[j] : T(0);
+    }
+    {
+      const int i = j0 + w + PB + lane;
+      if (lane < PB && i < n) bn = b[i];
+    }
+#pragma unroll
+    for (int s = 0; s < PB; ++s) {
+      const int j = j0 + s;
+      if (j < n) {
+        const T yj = buf[j & (WB - 1)] * dv[s];
+        if (lane == 0) b[j] = yj;
+        if (lane >= 1 && lane <= w && j + lane < n) buf[(j + lane) & (WB - 1)] -= lc[s] * yj;
+        lsync();
+      }
+    }
+    {
+      const int i = j0 + w + PB + lane;
+      if (lane < PB && i < n) buf[i & (WB - 1)] = bn;
+    }
+    lsync();
+  }
+  gsync();
+  // backward: row j of L (L(j, j - t), t = 1..w) updates rows j - 1 .. j - w
+  for (int t = lane; t < min(n, w + PB); t += WL) buf[(n - 1 - t) & (WB - 1)] = b[n - 1 - t];
+  lsync();
+  for (int j0 = n - 1; j0 >= 0; j0 -= PB) {
+    T lr[PB], dv[PB];
+    T bn = T(0);
+#pragma unroll
+    for (int s = 0; s < PB; ++s) {
+      const int j = j0 - s;
+      lr[s] = (j >= 0 && lane >= 1 && lane <= w && j - lane >= 0) ? L[(size_t)(j - lane) * W + lane] : T(0);
+      dv[s] = (j >= 0) ? dinv[j] : T(0);
+    }
+    {
+      const int i = j0 - w - PB - lane;
+      if (lane < PB && i >= 0) bn = b[i];
+    }
+#pragma unroll
+    for (int s = 0; s < PB; ++s) {
+      const int j = j0 - s;
+      if (j >= 0) {
+        const T xj = buf[j & (WB - 1)] * dv[s];
+        if (lane == 0) b[j] = xj;
+        if (lane >= 1 && lane <= w && j - lane >= 0) buf[(j - lane) & (WB - 1)] -= lr[s] * xj;
+        lsync();
+      }
+    }
+    {
+      const int i = j0 - w - PB - lane;
+      if (lane < PB && i >= 0) buf[i & (WB - 1)] = bn;
+    }
+    lsync();
+  }
+  gsync();
+}
+
+// ---------------------------------------------------------------- one problem
+struct Wave {
+  const WaveDesc& D;
+  double* lds;        // WAVE_WB * (WAVE_WB + 1) + 2 WAVE_WB doubles
+  int L;              // max(n, m)
+  double tau, kappa, delta, sdmax, xPx;
+  bool use64;
+  int64_t hits, fallbacks, irs, facts;
+
+  __device__ double* V(int k) const { return D.v + (size_t)k * L; }
+
+  // S = P + delta I + A'MA into band storage; returns max |S_jj|
+  __device__ double assemble(bool low) {
+    const int W = D.W, ne = D.n * W;
+    double dmax = 0.0;
+    for (int e = lane_id(); e < ne; e += WL) {
+      const bool diag = (e % W) == 0;
+      double v = D.Pband[e] + (diag ? delta : 0.0);
+      for (int t = D.trp[e]; t < D.trp[e + 1]; ++t) v += D.tc[t] * D.Mv[D.tm[t]];
+      if (low) D.Sb32[e] = (float)v;
+      else D.Sb[e] = v;
+      if (diag) dmax = nanmax(dmax, fabs(v));
+    }
+    gsync();
+    return wmax(dmax);
+  }
+
+  // factor the regularised system at the current scaling (hdiag and state filled)
+  __device__ void factor(bool fp64) {
+    const bool low = D.mixed && !fp64;
+    if (low) {
+      delta = D.static_reg + D.dyn_reg * fmax(D.maxPdiag, sdmax);
+    } else {
+      const double hmax = v_maxabs(D.m, D.hdiag);
+      const double ds = D.mixed ? 1e-8 : D.static_reg;
+      const double dd = D.mixed ? ldexp(1.0, -104) : D.dyn_reg;
+      delta = ds + dd * fmax(D.maxPdiag, hmax);
+    }
+    c_mblock(D, delta);
+    const double dmax = assemble(low);
+    if (low) {
+      sdmax = dmax;
+      hits += band_cholesky<float>(D.Sb32, D.dinv32, D.n, D.w, (float)delta, (float*)lds,
+                                   (float*)lds + WAVE_WB * (WAVE_WB + 1));
+    } else {
+      hits += band_cholesky<double>(D.Sb, D.dinv, D.n, D.w, delta, lds, lds + WAVE_WB * (WAVE_WB + 1));
+    }
+    facts++;
+  }
+
+  // x = S^-1 u in the factor precision (FP32 right-hand sides scaled by 1/|u|_inf)
+  __device__ void schur_solve(const double* u, double* x) {
+    if (D.mixed && !use64) {
+      double sc = v_maxabs(D.n, u);
+      sc = (sc > 0.0) ? sc : 1.0;
+      for (int i = lane_id(); i < D.n; i += WL) D.f32[i] = (float)(u[i] / sc);
+      gsync();
+      band_solve<float>(D.Sb32, D.dinv32, D.n, D.w, D.f32, (float*)lds);
+      for (int i = lane_id(); i < D.n; i += WL) x[i] = (double)D.f32[i] * sc;
+      gsync();
+    } else {
+      v_copy(D.n, u, x);
+      band_solve<double>(D.Sb, D.dinv, D.n, D.w, x, lds);
+    }
+  }
+
+  // K_reg [x; z] = [r1; r2]: z = M (A x - r2), S x = r1 + A'M r2
+  __device__ void solve_reg(const double* r1, const double* r2, double* x, double* z) {
+    double* t1 = V(WV_T1);
+    double* u1 = V(WV_U1);
+    double* w1 = V(WV_W1);
+    c_apply(D, 1, delta, r2, nullptr, t1);
+    v_copy(D.n, r1, u1);
+    spmv(D.n, D.Atrp, D.Atci, D.Atv, t1, u1, 1.0, 1.0);
+    schur_solve(u1, x);
+    spmv(D.m, D.Arp, D.Aci, D.Av, x, w1, 1.0, 0.0);
+    v_axpby(D.m, -1.0, r2, 1.0, w1);
+    c_apply(D, 1, delta, w1, nullptr, z);
+  }
+
+  // iterative refinement against the unregularised K; result in (xo, zo)
+  __device__ void kkt_solve_once(const double* r1, const double* r2, double* xo, double* zo, double* best_out,
+                                 double* nb_out) {
+    const int n = D.n, m = D.m;
+    const double nb = fmax(v_maxabs(n, r1), v_maxabs(m, r2));
+    double *x = V(WV_IRX), *z = V(WV_IRZ), *xn = V(WV_IRXN), *zn = V(WV_IRZN);
+    double *rx = V(WV_IRRX), *rz = V(WV_IRRZ), *kx = V(WV_KX), *kz = V(WV_KZ), *t2 = V(WV_T2);
+    v_fill(n, 0.0, x);
+    v_fill(m, 0.0, z);
+    v_copy(n, r1, rx);
+    v_copy(m, r2, rz);
+    double best = nb, rnorm = nb;
+    bool have_best = false;
+    for (int it = 0; it <= D.ir_max; ++it) {
+      solve_reg(rx, rz, kx, kz);
+      v_lin(n, 1.0, x, 1.0, kx, 0.0, nullptr, xn);
+      v_lin(m, 1.0, z, 1.0, kz, 0.0, nullptr, zn);
+      ++irs;
+      // r - K [xn; zn]
+      spmv(n, D.Prp, D.Pci, D.Pv, xn, kx, 1.0, 0.0);
+      spmv(n, D.Atrp, D.Atci, D.Atv, zn, kx, 1.0, 1.0);
+      spmv(m, D.Arp, D.Aci, D.Av, xn, kz, 1.0, 0.0);
+      c_apply(D, 0, 0.0, zn, nullptr, t2);
+      v_axpby(m, -1.0, t2, 1.0, kz);
+      v_lin(n, 1.0, r1, -1.0, kx, 0.0, nullptr, kx);
+      v_lin(m, 1.0, r2, -1.0, kz, 0.0, nullptr, kz);
+      const double rn = fmax(v_maxabs(n, kx), v_maxabs(m, kz));
+      if (rn < best || !have_best) {
+        if (rn < best) {
+          v_copy(n, xn, V(WV_IRBX));
+          v_copy(m, zn, V(WV_IRBZ));
+          best = rn;
+          have_best = true;
+        }
+      }
+      if (rn <= D.ir_abstol + D.ir_reltol * nb) break;
+      if (it > 0 && rn > 0.5 * rnorm) break;
+      double* tp;
+      tp = x; x = xn; xn = tp;
+      tp = z; z = zn; zn = tp;
+      tp = rx; rx = kx; kx = tp;
+      tp = rz; rz = kz; kz = tp;
+      rnorm = rn;
+    }
+    if (have_best) {
+      v_copy(n, V(WV_IRBX), xo);
+      v_copy(m, V(WV_IRBZ), zo);
+    } else {
+      v_fill(n, 0.0, xo);
+      v_fill(m, 0.0, zo);
+    }
+    *best_out = have_best ? best : NAN;
+    *nb_out = nb;
+  }
+
+  __device__ void kkt_solve(const double* r1, const double* r2, double* xo, double* zo) {
+    double best = 0.0, nb = 0.0;
+    kkt_solve_once(r1, r2, xo, zo, &best, &nb);
+    if (D.mixed && !use64 && !(best <= 1e-6 * (1.0 + nb))) {
+      use64 = true;            // FP64 factorisation for the rest of the iteration
+      factor(true);
+      fallbacks++;
+      kkt_solve_once(r1, r2, xo, zo, &best, &nb);
+    }
+  }
+
+  struct Resid {
+    double xPx, qx, bz, sz, rd_n, rp_n, x_n, s_n, z_n, atz_n, px_n, axs_n;
+  };
+
+  __device__ Resid residuals() {
+    const int n = D.n, m = D.m;
+    double *x = V(WV_X), *s = V(WV_S), *z = V(WV_Z), *Px = V(WV_PX), *Ax = V(WV_AX), *Atz = V(WV_ATZ);
+    double *rdv = V(WV_RDV), *rpv = V(WV_RPV);
+    spmv(n, D.Prp, D.Pci, D.Pv, x, Px, 1.0, 0.0);
+    spmv(m, D.Arp, D.Aci, D.Av, x, Ax, 1.0, 0.0);
+    spmv(n, D.Atrp, D.Atci, D.Atv, z, Atz, 1.0, 0.0);
+    v_lin(n, 1.0, Px, 1.0, Atz, tau, D.q, rdv);
+    v_lin(m, -1.0, Ax, -1.0, s, tau, D.b, rpv);
+    Resid R;
+    R.xPx = v_dot(n, x, Px);
+    R.qx = v_dot(n, D.q, x);
+    R.rd_n = v_maxabs(n, rdv, D.D, true);
+    R.x_n = v_maxabs(n, x, D.D, false);
+    R.atz_n = v_maxabs(n, Atz, D.D, true);
+    R.px_n = v_maxabs(n, Px, D.D, true);
+    R.bz = v_dot(m, D.b, z);
+    R.sz = v_dot(m, s, z);
+    R.rp_n = v_maxabs(m, rpv, D.E, true);
+    R.s_n = v_maxabs(m, s, D.E, true);
+    R.z_n = v_maxabs(m, z, D.E, false);
+    R.axs_n = v_maxabs(m, Ax, D.E, true, s, 1.0);
+    return R;
+  }
+
+  // termination tests (eq. termination-check, infeasibility-check); fills the report
+  __device__ int check(const Resid& R) {
+    const double t = tau, c = D.cscale, eps = D.eps_feas, ei = D.eps_inf;
+    const double rp = R.rp_n / t, rd = R.rd_n / (c * t);
+    const double gp = (0.5 * R.xPx / t + R.qx) / (c * t), gd = (-0.5 * R.xPx / t - R.bz) / (c * t);
+    const double xn = R.x_n / t, sn = R.s_n / t, zn = R.z_n / (c * t);
+    if (lane_id() == 0) {
+      D.sc[SC_RESP] = rp;
+      D.sc[SC_RESD] = rd;
+      D.sc[SC_OBJP] = gp;
+      D.sc[SC_OBJD] = gd;
+      D.sc[SC_GAP] = fabs(gp - gd);
+    }
+    if (rp < eps * fmax(1.0, D.bnorm + xn + sn) && rd < eps * fmax(1.0, D.qnorm + xn + zn) &&
+        fabs(gp - gd) < eps * fmax(1.0, fmin(fabs(gp), fabs(gd))))
+      return HC_STATUS_SOLVED;
+    const double bz = R.bz / c, xu = R.x_n, zu = R.z_n / c, su = R.s_n;
+    if (bz < -ei && R.atz_n / c < -ei * fmax(1.0, xu + zu) * bz) return HC_STATUS_PRIMAL_INFEASIBLE;
+    const double qx = R.qx / c;
+    if (qx < -ei && R.px_n / c < -ei * fmax(1.0, xu) * qx && R.axs_n < -ei * fmax(1.0, xu + su) * qx)
+      return HC_STATUS_DUAL_INFEASIBLE;
+    if (!isfinite(rp) || !isfinite(rd) || !isfinite(gp)) return HC_STATUS_NUMERICAL_ERROR;
+    return 0;
+  }
+
+  __device__ double step_length(const double* ds, const double* dz, double dtau, double dkappa) {
+    double a = 1.0;
+    if (dtau < 0) a = fmin(a, -tau / dtau);
+    if (dkappa < 0) a = fmin(a, -kappa / dkappa);
+    return fmin(a, c_step(D, V(WV_S), V(WV_Z), ds, dz));
+  }
+
+  struct Dir {
+    double dtau, dkappa;
+  };
+
+  // solve for the right-hand side (d_x = r1, -(d_z - d_s) = r2, d_tau, d_kappa)
+  // and recover Delta (eq. step-direction)
+  __device__ Dir direction(const double* r1, const double* r2, double dtau_rhs, double dkap_rhs,
+                           const double* ds_rhs, double* dxo, double* dzo, double* dso) {
+    const int n = D.n, m = D.m;
+    double *x1 = V(WV_X1), *z1 = V(WV_Z1), *x2 = V(WV_X2), *z2 = V(WV_Z2), *t2 = V(WV_T2);
+    kkt_solve(r1, r2, x1, z1);
+    v_lin(n, 2.0 / tau, V(WV_PX), 1.0, D.q, 0.0, nullptr, t2);
+    const double a1 = v_dot(n, t2, x1), a2 = v_dot(n, t2, x2);
+    const double b1 = v_dot(m, D.b, z1), b2 = v_dot(m, D.b, z2);
+    Dir d;
+    const double num = dtau_rhs - dkap_rhs / tau + a1 + b1;
+    const double den = kappa / tau + xPx / (tau * tau) - a2 - b2;
+    d.dtau = num / den;
+    v_lin(n, 1.0, x1, d.dtau, x2, 0.0, nullptr, dxo);
+    v_lin(m, 1.0, z1, d.dtau, z2, 0.0, nullptr, dzo);
+    c_apply(D, 0, 0.0, dzo, ds_rhs, dso);
+    d.dkappa = -(dkap_rhs + kappa * d.dtau) / tau;
+    return d;
+  }
+
+  // one pass of the loop body after the termination tests; status or 0
+  __device__ int iterate(const Resid& R) {
+    const int n = D.n, m = D.m;
+    const double mu = (R.sz + kappa * tau) / D.nu1;
+    const double gt = kappa + R.qx + R.bz + R.xPx / tau;
+    use64 = false;
+    c_scale(D, V(WV_S), V(WV_Z));
+    factor(false);
+    // constant system K [x2; z2] = [-q; b]
+    double* r1 = V(WV_R1);
+    double* r2 = V(WV_R2);
+    v_lin(n, -1.0, D.q, 0.0, nullptr, 0.0, nullptr, r1);
+    kkt_solve(r1, D.b, V(WV_X2), V(WV_Z2));
+    // affine: r1 = -rdv, r2 = rpv + s
+    v_lin(n, -1.0, V(WV_RDV), 0.0, nullptr, 0.0, nullptr, r1);
+    v_lin(m, 1.0, V(WV_RPV), 1.0, V(WV_S), 0.0, nullptr, r2);
+    const Dir da = direction(r1, r2, gt, kappa * tau, V(WV_S), V(WV_DXA), V(WV_DZA), V(WV_DSA));
+    const double alpha_a = step_length(V(WV_DSA), V(WV_DZA), da.dtau, da.dkappa);
+    const double sigma = (1.0 - alpha_a) * (1.0 - alpha_a) * (1.0 - alpha_a);
+    // combined
+    const double dk = kappa * tau + da.dkappa * da.dtau - sigma * mu;
+    c_ds(D, V(WV_S), V(WV_Z), V(WV_DSA), V(WV_DZA), sigma * mu, V(WV_DSRHS));
+    const double f = 1.0 - sigma;
+    v_lin(n, -f, V(WV_RDV), 0.0, nullptr, 0.0, nullptr, r1);
+    v_lin(m, f, V(WV_RPV), 1.0, V(WV_DSRHS), 0.0, nullptr, r2);
+    const Dir dc = direction(r1, r2, f * gt, dk, V(WV_DSRHS), V(WV_DX), V(WV_DZ), V(WV_DSV));
+    const double alpha_c = step_length(V(WV_DSV), V(WV_DZ), dc.dtau, dc.dkappa);
+    if (alpha_c < 1e-4) return HC_STATUS_INSUFFICIENT_PROGRESS;
+    const double a = D.step_fraction * alpha_c;
+    v_axpby(n, a, V(WV_DX), 1.0, V(WV_X));
+    v_axpby(m, a, V(WV_DSV), 1.0, V(WV_S));
+    v_axpby(m, a, V(WV_DZ), 1.0, V(WV_Z));
+    tau += a * dc.dtau;
+    kappa += a * dc.dkappa;
+    return 0;
+  }
+
+  // initial point: K with H = I for [-q; b], s = -z (0 on zero rows), then s
+  // and z moved along e by 1 + max(-lambda_min) when that is not negative
+  __device__ void init_point() {
+    const int n = D.n, m = D.m;
+    tau = kappa = 1.0;
+    use64 = false;
+    c_identity(D);
+    factor(false);
+    double* r1 = V(WV_R1);
+    v_lin(n, -1.0, D.q, 0.0, nullptr, 0.0, nullptr, r1);
+    kkt_solve(r1, D.b, V(WV_X), V(WV_Z));
+    double* s = V(WV_S);
+    double* z = V(WV_Z);
+    v_lin(m, -1.0, z, 0.0, nullptr, 0.0, nullptr, s);
+    v_fill(D.nz, 0.0, s);
+    for (int which = 0; which < 2; ++which) {
+      double* v = which == 0 ? s : z;
+      const double amax = c_max_neg_eig(D, v);
+      if (amax >= 0.0) c_add_e(D, 1.0 + amax, v);
+    }
+  }
+
+  // the result in the user's coordinates (the certificate for infeasible statuses)
+  __device__ void write_result(int status) {
+    const bool cert = status == HC_STATUS_PRIMAL_INFEASIBLE || status == HC_STATUS_DUAL_INFEASIBLE;
+    const double t = cert ? 1.0 : tau;
+    const double *x = V(WV_X), *s = V(WV_S), *z = V(WV_Z);
+    for (int i = lane_id(); i < D.n; i += WL) D.xo[D.colperm[i]] = D.D[i] * x[i] / t;
+    for (int r = lane_id(); r < D.m; r += WL) {
+      const int u = D.rowperm[r];
+      D.so[u] = s[r] / D.E[r] / t;
+      D.zo[u] = D.E[r] * z[r] / (D.cscale * t);
+    }
+    gsync();
+  }
+};
+
+__global__ __launch_bounds__(WL) void k_wave_tick(const WaveDesc* __restrict__ descs,
+                                                 const int32_t* __restrict__ active, int nslots,
+                                                 int32_t* __restrict__ status) {
+  __shared__ double lds[WAVE_WB * (WAVE_WB + 1) + 2 * WAVE_WB];
+  const int slot = blockIdx.x;
+  if (slot >= nslots || !active[slot]) return;
+  const WaveDesc D = descs[slot];
+  double* sc = D.sc;
+  int phase = (int)sc[SC_PHASE];
+  if (phase == PH_DONE) {
+    if (threadIdx.x == 0) status[slot] = PH_DONE;
+    return;
+  }
+  Wave w{D, lds, max(D.n, D.m)};
+  w.sdmax = sc[SC_SDMAX];
+  w.hits = (int64_t)sc[SC_HITS];
+  w.fallbacks = (int64_t)sc[SC_FALLBACKS];
+  w.irs = (int64_t)sc[SC_IRS];
+  w.facts = (int64_t)sc[SC_FACTS];
+  w.delta = 0.0;
+  w.use64 = false;
+  int k = (int)sc[SC_K], iters = (int)sc[SC_ITERS];
+  if (phase == PH_NEW) {
+    w.sdmax = 0.0;
+    w.init_point();
+    k = 0;
+    iters = 0;
+  } else {
+    w.tau = sc[SC_TAU];
+    w.kappa = sc[SC_KAPPA];
+  }
+  // one pass of the Algorithm 1 loop
+  const Wave::Resid R = w.residuals();
+  w.xPx = R.xPx;
+  int st = w.check(R);
+  const double mu = (R.sz + w.kappa * w.tau) / D.nu1;
+  bool done = false;
+  if (st) {
+    done = true;
+  } else if (k == D.max_iter) {
+    st = HC_STATUS_MAX_ITER;
+    done = true;
+  } else {
+    st = w.iterate(R);
+    iters++;
+    if (st) {
+      const Wave::Resid R2 = w.residuals();
+      w.check(R2);
+      done = true;
+    }
+  }
+  k++;
+  if (done) w.write_result(st);
+  if (threadIdx.x == 0) {
+    sc[SC_TAU] = w.tau;
+    sc[SC_KAPPA] = w.kappa;
+    sc[SC_K] = k;
+    sc[SC_ITERS] = iters;
+    sc[SC_STATUS] = st;
+    sc[SC_SDMAX] = w.sdmax;
+    sc[SC_HITS] = (double)w.hits;
+    sc[SC_FALLBACKS] = (double)w.fallbacks;
+    sc[SC_IRS] = (double)w.irs;
+    sc[SC_FACTS] = (double)w.facts;
+    sc[SC_MU] = mu;
+    sc[SC_PHASE] = done ? PH_DONE : PH_RUN;
+    status[slot] = done ? PH_DONE : PH_RUN;
+  }
+}
+
+// bump layout of one slot's blob
+struct Carve {
+  char* base;
+  size_t used = 0;
+  template <typename T> T* take(size_t count) {
+    used = (used + 255) / 256 * 256;
+    T* p = base ? (T*)(base + used) : nullptr;
+    used += std::max<size_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+template <typename T>
+T* put(Carve& c, const std::vector<T>& v, hipStream_t st) {
+  T* p = c.take<T>(v.size());
+  if (p && !v.empty()) HC_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return p;
+}
+
+void layout(const WavePlan& P, Carve& c, WaveDesc* d, hipStream_t st) {
+  const size_t L = (size_t)std::max(P.n, P.m);
+  const size_t ne = (size_t)P.n * (P.w + 1);
+  std::memset(d, 0, sizeof(*d));
+  d->n = P.n;
+  d->m = P.m;
+  d->w = P.w;
+  d->W = P.w + 1;
+  d->nz = P.nz;
+  d->nn = P.nn;
+  d->nsoc = P.nsoc;
+  d->mtot = P.mtot;
+  d->ir_max = P.st.ir_max;
+  d->max_iter = P.st.max_iter;
+  d->mixed = P.mixed ? 1 : 0;
+  d->cscale = P.cscale;
+  d->bnorm = P.bnorm;
+  d->qnorm = P.qnorm;
+  d->maxPdiag = P.maxPdiag;
+  d->nu1 = (double)(P.nu + 1);
+  d->eps_feas = P.st.eps_feas;
+  d->eps_inf = P.st.eps_inf;
+  d->static_reg = P.st.static_reg;
+  d->dyn_reg = P.st.dyn_reg;
+  d->ir_abstol = P.st.ir_abstol;
+  d->ir_reltol = P.st.ir_reltol;
+  d->step_fraction = P.st.step_fraction;
+  d->Arp = put(c, P.Arp, st);
+  d->Aci = put(c, P.Aci, st);
+  d->Av = put(c, P.Av, st);
+  d->Atrp = put(c, P.Atrp, st);
+  d->Atci = put(c, P.Atci, st);
+  d->Atv = put(c, P.Atv, st);
+  d->Prp = put(c, P.Prp, st);
+  d->Pci = put(c, P.Pci, st);
+  d->Pv = put(c, P.Pv, st);
+  d->q = put(c, P.q, st);
+  d->b = put(c, P.b, st);
+  d->D = put(c, P.D, st);
+  d->E = put(c, P.E, st);
+  d->Pband = put(c, P.Pband, st);
+  d->trp = put(c, P.trp, st);
+  d->tm = put(c, P.tm, st);
+  d->tc = put(c, P.tc, st);
+  d->soc_off = put(c, P.soc_off, st);
+  d->soc_moff = put(c, P.soc_moff, st);
+  d->colperm = put(c, P.colperm, st);
+  d->rowperm = put(c, P.rowperm, st);
+  d->v = c.take<double>(WV_COUNT * L);
+  d->Sb = c.take<double>(ne);
+  d->dinv = c.take<double>(P.n);
+  d->hst = c.take<double>((size_t)P.nn + 2 * (size_t)(P.m - P.nz - P.nn) + P.nsoc);
+  d->hdiag = c.take<double>(P.m);
+  d->Mv = c.take<double>(P.mtot);
+  d->sc = c.take<double>(SC_COUNT);
+  if (P.mixed) {
+    d->Sb32 = c.take<float>(ne);
+    d->dinv32 = c.take<float>(P.n);
+    d->f32 = c.take<float>(P.n);
+  }
+  d->xo = c.take<double>(P.n);
+  d->so = c.take<double>(P.m);
+  d->zo = c.take<double>(P.m);
+}
+
+}  // namespace
+
+size_t WavePlan::blob_bytes() const {
+  Carve c{nullptr};
+  WaveDesc d;
+  layout(*this, c, &d, nullptr);
+  return c.used + 256;
+}
+
+void wave_upload(const WavePlan& plan, void* blob, WaveDesc* desc, hipStream_t st) {
+  Carve c{(char*)(((uintptr_t)blob + 255) / 256 * 256)};
+  layout(plan, c, desc, st);
+  // fresh scalars: phase NEW
+  std::vector<double> sc(SC_COUNT, 0.0);
+  HC_HIP(hipMemcpyAsync(desc->sc, sc.data(), SC_COUNT * sizeof(double), hipMemcpyHostToDevice, st));
+}
+
+void wave_tick(const WaveDesc* descs, const int32_t* active, int nslots, int32_t* status, hipStream_t st) {
+  if (nslots <= 0) return;
+  hipLaunchKernelGGL(k_wave_tick, dim3((unsigned)nslots), dim3(WL), 0, st, descs, active, nslots, status);
+  HC_LAUNCH_CHECK();
+}
+
+void wave_result(const WaveDesc& d, const WavePlan& plan, hc_info* info, double* x, double* s, double* z,
+                 hipStream_t st) {
+  double sc[SC_COUNT];
+  HC_HIP(hipMemcpyAsync(sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost, st));
+  if (x) HC_HIP(hipMemcpyAsync(x, d.xo, (size_t)plan.n * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (s) HC_HIP(hipMemcpyAsync(s, d.so, (size_t)plan.m * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (z) HC_HIP(hipMemcpyAsync(z, d.zo, (size_t)plan.m * sizeof(double), hipMemcpyDeviceToHost, st));
+  HC_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->status = (int32_t)sc[SC_STATUS];
+    info->iterations = (int32_t)sc[SC_ITERS];
+    info->obj_primal = sc[SC_OBJP];
+    info->obj_dual = sc[SC_OBJD];
+    info->res_primal = sc[SC_RESP];
+    info->res_dual = sc[SC_RESD];
+    info->gap = sc[SC_GAP];
+    info->mu = sc[SC_MU];
+    info->pivot_guard_hits = (int64_t)sc[SC_HITS];
+    info->fp64_fallbacks = (int64_t)sc[SC_FALLBACKS];
+    info->ir_solves = (int64_t)sc[SC_IRS];
+    info->factorizations = (int64_t)sc[SC_FACTS];
+  }
+}
+
+}  // namespace hc
+
+// ===========================================================================
+// C-ABI: batched solve of many small problems, one wavefront each
+// ===========================================================================
+using namespace hc;
+
+extern "C" {
+
+int32_t hc_batch_check(const hc_solver* s, int32_t* band) {
+  if (!s) return HC_ERR_INVALID_ARG;
+  WavePlan plan;
+  std::string why;
+  if (!wave_plan(s, &plan, &why)) {
+    set_last_error("not eligible for the batched engine: " + why);
+    return HC_ERR_UNSUPPORTED;
+  }
+  if (band) *band = plan.w;
+  return HC_OK;
+}
+
+int32_t hc_solve_batch(hc_solver* const* handles, int32_t count, void* stream, int32_t device, hc_result* results) {
+  if (!handles || !results || count < 1) return HC_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<WavePlan> plans(count);
+  for (int32_t i = 0; i < count; ++i) {
+    std::string why;
+    if (!handles[i]) return HC_ERR_INVALID_ARG;
+    if (!wave_plan(handles[i], &plans[i], &why)) {
+      set_last_error("problem " + std::to_string(i) + " is not eligible for the batched engine: " + why);
+      return HC_ERR_UNSUPPORTED;
+    }
+  }
+  char* mem = nullptr;
+  void* aux = nullptr;
+  int32_t rc = HC_OK;
+  try {
+    HC_HIP(hipSetDevice(device));
+    std::vector<size_t> off(count + 1, 0);
+    for (int32_t i = 0; i < count; ++i) off[i + 1] = off[i] + (plans[i].blob_bytes() + 255) / 256 * 256;
+    const size_t tab = (size_t)count * (sizeof(WaveDesc) + 2 * sizeof(int32_t)) + 1024;
+    if (hipMalloc((void**)&mem, off[count] + 256) != hipSuccess) throw Error{HC_ERR_OOM, "hipMalloc of the batch"};
+    if (hipMalloc(&aux, tab) != hipSuccess) throw Error{HC_ERR_OOM, "hipMalloc of the slot table"};
+    WaveDesc* ddesc = (WaveDesc*)aux;
+    int32_t* dactive = (int32_t*)((char*)aux + (size_t)count * sizeof(WaveDesc));
+    int32_t* dstatus = dactive + count;
+    std::vector<WaveDesc> desc(count);
+    const double t0 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    for (int32_t i = 0; i < count; ++i) wave_upload(plans[i], mem + off[i], &desc[i], st);
+    std::vector<int32_t> act(count, 1), stat(count, PH_RUN);
+    HC_HIP(hipMemcpyAsync(ddesc, desc.data(), count * sizeof(WaveDesc), hipMemcpyHostToDevice, st));
+    HC_HIP(hipMemcpyAsync(dactive, act.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    int max_ticks = 0;
+    for (const WavePlan& p : plans) max_ticks = std::max(max_ticks, p.st.max_iter + 2);
+    for (int tick = 0; tick < max_ticks; ++tick) {
+      wave_tick(ddesc, dactive, count, dstatus, st);
+      HC_HIP(hipMemcpyAsync(stat.data(), dstatus, count * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HC_HIP(hipStreamSynchronize(st));
+      bool all = true;
+      for (int32_t i = 0; i < count; ++i) all = all && stat[i] == PH_DONE;
+      if (all) break;
+    }
+    const double t1 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    for (int32_t i = 0; i < count; ++i) {
+      hc_result& r = results[i];
+      hc_info inf{};
+      wave_result(desc[i], plans[i], &inf, r.x, r.s, r.z, st);
+      r.tag = (uint64_t)i;
+      r.status = stat[i] == PH_DONE ? inf.status : HC_STATUS_MAX_ITER;
+      r.error = HC_OK;
+      r.iterations = inf.iterations;
+      r.obj_primal = inf.obj_primal;
+      r.obj_dual = inf.obj_dual;
+      r.res_primal = inf.res_primal;
+      r.res_dual = inf.res_dual;
+      r.queue_ms = 0.0;
+      r.solve_ms = t1 - t0;
+      r.latency_ms = t1 - t0;
+      r.n = plans[i].n;
+      r.m = plans[i].m;
+    }
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    rc = e.code;
+  }
+  if (st) (void)hipStreamSynchronize(st);
+  if (mem) (void)hipFree(mem);
+  if (aux) (void)hipFree(aux);
+  return rc;
+}
+
+}  // extern "C"

@@ -21,7 +21,7 @@ STATUS = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasibl
           5: "insufficient_progress", 6: "numerical_error", 7: "cancelled"}
 
 EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "hc_solve", "hc_get_info",
-           "hc_get_solution", "hc_host_stage_bytes", "hc_get_iterate", "hc_set_iterate", "hc_update_data", "hc_test_kkt_solve", "hc_test_kkt_ops",
+           "hc_get_solution", "hc_host_stage_bytes", "hc_batch_check", "hc_solve_batch", "hc_get_iterate", "hc_set_iterate", "hc_update_data", "hc_test_kkt_solve", "hc_test_kkt_ops",
            "hc_test_schur", "hc_destroy", "hc_last_error", "hc_status_str",
            "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_cone_step_min", "hc_test_dense_chol_solve",
            "hc_test_dense_chol_solve_env",
@@ -71,7 +71,8 @@ class hc_info(C.Structure):
 
 class hc_server_config(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("workers", C.c_int32),
-                ("settings", hc_settings), ("device", C.c_int32)]
+                ("settings", hc_settings), ("device", C.c_int32), ("batched", C.c_int32),
+                ("batch_slots", C.c_int32)]
 
 
 class hc_result(C.Structure):
@@ -91,6 +92,7 @@ class hc_server_report(C.Structure):
 
 
 HC_PENDING = 1
+ERR_UNSUPPORTED = -9
 ERR_TOO_LARGE = -10
 
 _lib = None
@@ -112,6 +114,8 @@ def lib():
         L.hc_get_info.argtypes = [vp, C.POINTER(hc_info)]
         L.hc_get_solution.argtypes = [vp, vp, vp, vp, i32]
         L.hc_host_stage_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.hc_batch_check.argtypes = [vp, C.POINTER(i32)]
+        L.hc_solve_batch.argtypes = [vp, i32, vp, i32, vp]
         L.hc_get_iterate.argtypes = [vp, vp, vp, vp, C.POINTER(dbl), C.POINTER(dbl), vp]
         L.hc_set_iterate.argtypes = [vp, vp, vp, vp, dbl, dbl]
         L.hc_update_data.argtypes = [vp, vp, vp, vp, vp]
@@ -214,6 +218,54 @@ def analyze(prob, **settings) -> dict:
         return out
     finally:
         L.hc_destroy(h)
+
+
+def batch_band(prob, **settings):
+    """Band half-width of the problem's Schur complement under the batched
+    engine's ordering, or None when the engine does not take it."""
+    L = lib()
+    h, keep = _setup(prob, default_settings(**settings))
+    try:
+        w = C.c_int32(0)
+        rc = L.hc_batch_check(h, C.byref(w))
+        return int(w.value) if rc == 0 else None
+    finally:
+        L.hc_destroy(h)
+
+
+def solve_batch(probs, device=0, stream=None, **settings):
+    """Solves a list of problems together on the batched engine (one
+    wavefront per problem).  Returns a list of result dicts with x, s, z."""
+    import torch
+    L = lib()
+    handles, keeps = [], []
+    try:
+        for p in probs:
+            h, k = _setup(p, default_settings(**settings))
+            handles.append(h)
+            keeps.append(k)
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        res = (hc_result * len(probs))()
+        outs = []
+        for i, p in enumerate(probs):
+            x, s, z = np.zeros(p.n), np.zeros(p.m), np.zeros(p.m)
+            outs.append((x, s, z))
+            res[i].x = _ptr(x, C.c_double)
+            res[i].s = _ptr(s, C.c_double)
+            res[i].z = _ptr(z, C.c_double)
+        arr = (C.c_void_p * len(handles))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+        _check(L.hc_solve_batch(arr, len(handles), st.cuda_stream, dev.index or 0, res))
+        out = []
+        for i in range(len(probs)):
+            r = {f: getattr(res[i], f) for f, _ in hc_result._fields_ if f not in ("x", "s", "z")}
+            r["status_name"] = STATUS.get(r["status"], "unknown")
+            r["x"], r["s"], r["z"] = outs[i]
+            out.append(r)
+        return out
+    finally:
+        for h in handles:
+            L.hc_destroy(h)
 
 
 class Solver:
@@ -449,7 +501,8 @@ class Server:
     """Continuous-batching server (hc_server_*): many problems in flight on one
     GPU, admitted by device-memory footprint."""
 
-    def __init__(self, hbm_budget_bytes=64 << 30, max_slots=64, workers=4, device=0, **settings):
+    def __init__(self, hbm_budget_bytes=64 << 30, max_slots=64, workers=4, device=0, batched=True,
+                 batch_slots=1024, **settings):
         L = lib()
         cfg = hc_server_config()
         _check(L.hc_server_config_default(C.byref(cfg)))
@@ -457,6 +510,8 @@ class Server:
         cfg.max_slots = int(max_slots)
         cfg.workers = int(workers)
         cfg.device = int(device)
+        cfg.batched = 1 if batched else 0
+        cfg.batch_slots = int(batch_slots)
         cfg.settings = default_settings(**settings)
         self._h = C.c_void_p()
         _check(L.hc_server_create(C.byref(self._h), C.byref(cfg)))
