@@ -60,10 +60,29 @@ def calibrate_copy(nbytes=1 << 30, reps=3):
     print(f"reference copy: {reps} launches of {nbytes} bytes", file=sys.stderr)
 
 
+HBM_PEAK_GBS = 8000.0
+
+
+def cone_roofline(info):
+    """Cone layer (scalings, M blocks, H applications, d_s, recovery, step
+    lengths) from one profiled solve: summed device time of its launches (HIP
+    events on the solver's stream) against their algorithmic bytes."""
+    ms, b = info["cone_kernel_ms"], info["cone_bytes"]
+    achieved = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                traffic=None, device_ms_per_iteration=ms / max(1, info["iterations"]),
+                algorithmic_bytes_per_iteration=b / max(1, info["iterations"]),
+                launches_per_iteration=info["cone_launches"] / max(1, info["iterations"]))
+
+
 def run_gpu(prob, precision, steps, warmup):
+    """Timed solves (no profiling events), then one profiled solve with the
+    look-ahead's trailing updates on the main stream (settings.profile = 2) so
+    that no timed MFMA update overlaps another kernel: the roofline comes from
+    that solve, the throughput from the timed ones."""
     import torch
     from paper_2412_19027_amd import hipcone as HC
-    solver = HC.Solver(prob, precision=precision, profile=1)
+    solver = HC.Solver(prob, precision=precision, profile=0)
     for _ in range(warmup):
         solver.solve()
     torch.cuda.synchronize()
@@ -74,12 +93,15 @@ def run_gpu(prob, precision, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     iters = sum(i["iterations"] for i in infos)
-    gemm_ms = sum(i["gemm_ms"] for i in infos)
-    gemm_flops = sum(i["gemm_flops"] for i in infos)
-    launches = sum(i["gemm_launches"] for i in infos)
     last = infos[-1]
-    x, s, z = solver.solution()
     solver.close()
+    prof = HC.Solver(prob, precision=precision, profile=2)
+    t1 = time.perf_counter()
+    pi = prof.solve()
+    torch.cuda.synchronize()
+    prof_ms = 1e3 * (time.perf_counter() - t1)
+    prof.close()
+    gemm_ms, gemm_flops, launches = pi["gemm_ms"], pi["gemm_flops"], pi["gemm_launches"]
     peak = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
     achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
     kernel = "k_gemm_nt_dma" if precision == "fp64" else "k_gemm_nt_dma32"
@@ -89,14 +111,45 @@ def run_gpu(prob, precision, steps, warmup):
         iterations_per_solve=iters / steps, ms_per_solve=1e3 * wall / steps, ms_per_iteration=1e3 * wall / iters,
         factor_ms_per_iteration=sum(i["factor_ms"] for i in infos) / iters,
         kkt_ms_per_iteration=sum(i["solve_kkt_ms"] for i in infos) / iters,
-        cone_ms_per_iteration=sum(i["cone_ms"] for i in infos) / iters,
         ir_solves_per_iteration=sum(i["ir_solves"] for i in infos) / iters,
+        fp64_fallbacks_per_solve=sum(i["fp64_fallbacks"] for i in infos) / steps,
         roofline=dict(bound="mfma", kernel=kernel,
                       achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
                       traffic=measured_traffic(kernel), traffic_unit="HBM bytes per launch",
                       launches=launches, avg_launch_us=1e3 * gemm_ms / max(1, launches),
-                      algorithmic_flops_per_launch=gemm_flops / max(1, launches)),
+                      algorithmic_flops_per_launch=gemm_flops / max(1, launches),
+                      measured_in="one solve with settings.profile = 2 (trailing updates on the main stream, "
+                                  "no overlap)",
+                      gemm_ms_per_solve=gemm_ms, profiled_solve_ms=prof_ms),
+        cone_roofline=cone_roofline(pi),
     )
+
+
+def run_seeds(precision, seeds=(1, 2, 3, 4)):
+    """The same configuration at other seeds: one solve each after a warm-up
+    (problem resident); time per solve and per iteration."""
+    import torch
+    from paper_2412_19027_amd import hipcone as HC
+    from paper_2412_19027_amd import workloads as W
+    out = {}
+    for sd in seeds:
+        prob = W.sparse_socp(sd)
+        s = HC.Solver(prob, precision=precision, profile=0)
+        s.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s.solve()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s.close()
+        out[str(sd)] = dict(status=info["status_name"], iterations=info["iterations"], ms_per_solve=1e3 * wall,
+                            ms_per_iteration=1e3 * wall / max(1, info["iterations"]), objective=info["obj_primal"])
+    return out
+
+
+def spread(vals):
+    v = sorted(vals)
+    return dict(median=v[len(v) // 2], min=v[0], max=v[-1])
 
 
 OTHER_WORKLOADS = ("logreg_exp", "psd_pow", "entropy_max", "portfolio_qp", "multistage_portfolio", "psd_sides_to_32")
@@ -127,38 +180,48 @@ def run_other_workloads(steps=1, only=None):
         it = sum(i["iterations"] for i in infos)
         last = infos[-1]
         s.close()
+        sp = HC.Solver(prob, profile=2)
+        pinfo = sp.solve()
+        sp.close()
         out[name] = dict(problem=prob.name, n=prob.n, m=prob.m, status=last["status_name"],
                          iterations=last["iterations"], objective=last["obj_primal"],
                          ms_per_iteration=1e3 * wall / max(1, it), ms_per_solve=1e3 * wall / steps,
                          factor_ms_per_iteration=last["factor_ms"] / max(1, last["iterations"]),
                          setup_ms=last["setup_ms"],
-                         dense_tail=last["n_ordered"], leaf_blocks=last["n_leaves"])
+                         dense_tail=last["n_ordered"], leaf_blocks=last["n_leaves"],
+                         cone_roofline=cone_roofline(pinfo))
     return out
 
 
-def run_served(count, rate=2000.0, workers=4, slots=32, budget=16 << 30, seed=0):
+def run_served(count, precision="fp64", rate=2000.0, workers=4, slots=32, budget=64 << 30, seed=0, batched=True,
+               feeders=4):
     """The served form on a stream of MPC requests: problems are generated
-    beforehand, submitted at Poisson arrival times by one thread, and every
-    ticket is waited for; throughput and latency come from the server."""
+    beforehand, submitted at their Poisson arrival times by `feeders` threads
+    (request i by thread i mod feeders; submit is thread-safe and runs the
+    host analysis), and every ticket is waited for; throughput and latency
+    come from the server."""
     import threading
     from paper_2412_19027_amd import hipcone as HC
     from paper_2412_19027_amd import workloads as W
     probs = [W.mpc_socp(seed, i) for i in range(count)]
     arrivals = W.mpc_arrivals(seed, count, rate)
-    srv = HC.Server(hbm_budget_bytes=budget, max_slots=slots, workers=workers)
+    srv = HC.Server(hbm_budget_bytes=budget, max_slots=slots, workers=workers, batched=batched,
+                    precision=precision)
     tickets = [None] * count
     t0 = time.perf_counter()
 
-    def feed():
-        for i, (p, a) in enumerate(zip(probs, arrivals)):
-            dt = a - (time.perf_counter() - t0)
+    def feed(k):
+        for i in range(k, count, feeders):
+            dt = arrivals[i] - (time.perf_counter() - t0)
             if dt > 0:
                 time.sleep(dt)
-            tickets[i] = srv.submit(p, tag=i)
+            tickets[i] = srv.submit(probs[i], tag=i)
 
-    th = threading.Thread(target=feed)
-    th.start()
-    th.join()
+    ths = [threading.Thread(target=feed, args=(k,)) for k in range(feeders)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
     res = [srv.wait(t) for t in tickets]
     wall = time.perf_counter() - t0
     st = srv.stats()
@@ -169,10 +232,13 @@ def run_served(count, rate=2000.0, workers=4, slots=32, budget=16 << 30, seed=0)
     return dict(
         workload=f"MPC SOCP stream: {count} requests, Poisson {rate:g}/s, T in [10,100], nx in [4,12], "
                  f"nu in [2,6] (n in [64,1812]), seed {seed}",
+        precision=precision, engine="batched (one wavefront per problem, one graph launch per tick)" if batched
+        else "per-slot workers",
         requests=count, wall_s=wall, solves_per_s=st["solves_per_s"], p50_latency_ms=st["p50_latency_ms"],
         p99_latency_ms=st["p99_latency_ms"], mean_latency_ms=st["mean_latency_ms"],
         mean_iterations=st["iterations"] / max(1, st["completed"]), statuses=statuses,
-        hbm_peak_bytes=st["hbm_peak"], workers=workers, max_slots=slots, hbm_budget_bytes=budget)
+        hbm_peak_bytes=st["hbm_peak"], workers=workers, max_slots=slots, hbm_budget_bytes=budget,
+        feeder_threads=feeders)
 
 
 def run_sequential(count, seed=0):
@@ -264,8 +330,11 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--served", type=int, default=1000,
+    ap.add_argument("--served", type=int, default=10000,
                     help="requests in the served-form measurement (MPC stream at 2000/s); 0 = skip")
+    ap.add_argument("--no-seeds", action="store_true", help="skip the seeds 1-4 solves")
+    ap.add_argument("--served-only", action="store_true",
+                    help="run only the served-form measurement (FP64 and mixed) and print its JSON")
     ap.add_argument("--no-workloads", action="store_true", help="skip the other full-size configurations")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run the reference copy kernel (for byte-counter scaling)")
@@ -283,6 +352,11 @@ def main():
     if args.workload_only:
         print(json.dumps(run_other_workloads(only=args.workload_only)))
         return
+    if args.served_only:
+        sv = run_served(args.served, "fp64")
+        sv["mixed"] = run_served(args.served, "mixed")
+        print(json.dumps(sv))
+        return
     sc = args.scale
     prob = W.sparse_socp(0, nx=int(20000 * sc), n_zero=int(10000 * sc), n_nonneg=int(30000 * sc),
                          n_soc=int(40000 * sc))
@@ -293,14 +367,29 @@ def main():
         r = run_gpu(prob, alt, args.steps, args.warmup)
         other = {k: r[k] for k in ("status", "objective", "res_primal", "res_dual", "gap", "iterations_per_solve",
                                    "ms_per_solve", "ms_per_iteration", "factor_ms_per_iteration",
-                                   "kkt_ms_per_iteration", "ir_solves_per_iteration")}
+                                   "kkt_ms_per_iteration", "ir_solves_per_iteration", "fp64_fallbacks_per_solve")}
         other["precision"] = alt
         other["roofline"] = r["roofline"]
+        other["cone_roofline"] = r["cone_roofline"]
+        other["ms_per_solve_vs_main"] = r["ms_per_solve"] / main_run["ms_per_solve"]
         other["objective_rel_diff_vs_main"] = abs(r["objective"] - main_run["objective"]) / max(
             1.0, abs(main_run["objective"]))
-    served = run_served(args.served) if args.served > 0 else None
-    if served is not None and args.sequential > 0:
-        served["plain_fp64_sequential"] = run_sequential(args.sequential)
+    seeds = None
+    if not args.no_seeds and sc == 1.0:
+        per = run_seeds(args.precision)
+        per["0"] = dict(status=main_run["status"], iterations=main_run["iterations_per_solve"],
+                        ms_per_solve=main_run["ms_per_solve"], ms_per_iteration=main_run["ms_per_iteration"],
+                        objective=main_run["objective"])
+        seeds = dict(per_seed=per, ms_per_solve=spread([v["ms_per_solve"] for v in per.values()]),
+                     ms_per_iteration=spread([v["ms_per_iteration"] for v in per.values()]),
+                     iterations=spread([v["iterations"] for v in per.values()]))
+    served = None
+    if args.served > 0:
+        served = run_served(args.served, "fp64")
+        served["mixed"] = run_served(args.served, "mixed")
+        served["per_slot_fp64_1000"] = run_served(min(1000, args.served), "fp64", budget=16 << 30, batched=False)
+        if args.sequential > 0:
+            served["plain_fp64_sequential"] = run_sequential(args.sequential)
     parametric = run_parametric() if args.served > 0 else None
     others = None if args.no_workloads else run_other_workloads()
     if args.calibrate_copy:
@@ -329,9 +418,10 @@ def main():
         "ms_per_iteration": main_run["ms_per_iteration"],
         "factor_ms_per_iteration": main_run["factor_ms_per_iteration"],
         "kkt_ms_per_iteration": main_run["kkt_ms_per_iteration"],
-        "cone_ms_per_iteration": main_run["cone_ms_per_iteration"],
         "ir_solves_per_iteration": main_run["ir_solves_per_iteration"],
         "roofline": main_run["roofline"],
+        "cone_roofline": main_run["cone_roofline"],
+        "seeds": seeds,
         "alt_precision": other,
         "served": served,
         "parametric": parametric,

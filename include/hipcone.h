@@ -116,6 +116,12 @@ typedef struct {
                              connected components once the high-degree columns are
                              set aside are factored as leaf blocks ahead of the
                              dense tail (two-level LDL'); 0: one dense block      */
+  int32_t warm_start;     /* 1: a solve after hc_update_data starts from the blend
+                             (1 - warm_blend) v_prev + warm_blend v_0 of the last
+                             solved iterate v_prev = (x, s, z)/tau, carried over
+                             to the new equilibration, and the usual initial point
+                             v_0 (tau = kappa = 1); 0: always from v_0 (0)        */
+  double warm_blend;      /* 0.02                                                   */
 } hc_settings;
 
 /* ---- device hand-off ------------------------------------------------------ */

@@ -1,5 +1,7 @@
 // Cone-layer kernels (gfx950): one lane per small cone, component-major data.
 #pragma once
+#include <vector>
+
 #include "hc_common.h"
 
 namespace hc {
@@ -30,13 +32,25 @@ int64_t cone_mblock_work(const SegDev& g);
 void cone_apply(const SegDev& g, int mode, double delta, const double* x, double* y, hipStream_t st);
 // y[rows] = -ds[rows] - H x[rows]  (direction recovery of Delta s)
 void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, double* out, hipStream_t st);
+// cone_apply (dsr null) or cone_recover_ds (dsr given, mode 0) over every
+// segment: the lane-per-cone families (zero, nonneg, SOC up to SOC_DMAX,
+// exp, pow) in one launch, PSD and larger SOC segments by their own kernels
+void cone_apply_all(const std::vector<SegDev>& segs, int mode, double delta, const double* x, const double* dsr,
+                    double* y, hipStream_t st);
 // combined-step d_s (eq. ds-correction-step) from the scaling state
 void cone_ds_combined(const SegDev& g, const double* s, const double* z, const double* dsa, const double* dza,
                       double sm, double* ds, hipStream_t st);
+// the same over every segment, the lane-per-cone families in one launch
+void cone_ds_all(const std::vector<SegDev>& segs, const double* s, const double* z, const double* dsa,
+                 const double* dza, double sm, double* ds, hipStream_t st);
 // symmetric families: per-block minimum of the exact boundary steps of s and z
 // (written to partial[block]); returns number of blocks
 int cone_step_sym(const SegDev& g, const double* s, const double* z, const double* ds, const double* dz,
                   double* partial, hipStream_t st);
+// the same over every symmetric segment (nonneg rows and lane-per-cone SOCs in
+// one launch); returns the number of partials written
+int64_t cone_step_sym_all(const std::vector<SegDev>& segs, const double* s, const double* z, const double* ds,
+                          const double* dz, double* partial, hipStream_t st);
 // exp/pow: per block, bit j of the result (j < ntrial) is set when every cone
 // of the block passes the trial alpha_j = a0 * ratio^j: s + a ds in int K and
 // z + a dz in int K* and, when check_nbhd, 3 / <z~(s_a), s~(z_a)> >= beta mu(alpha_j)

@@ -435,24 +435,28 @@ void cone_scale(const SegDev& g, const double* s, const double* z, double mu, in
   HC_LAUNCH_CHECK();
 }
 
+constexpr int FUSED_SEGS = 8;
+
 // ===========================================================================
 // spectral application of H or (H + delta I)^-1, and the explicit inverse block
 // ===========================================================================
 __device__ inline double fsel(int mode, double lam, double delta) { return mode == 0 ? lam : 1.0 / (lam + delta); }
 
-__global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __restrict__ x,
-                             double* __restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.count) return;
+// one cone (or zero/nonneg row) i of segment g: y = H x (mode 0) or
+// (H + delta I)^-1 x (mode 1); with dsr (mode 0): y = -dsr - H x, the
+// direction recovery of Delta s
+__device__ inline void cone_apply_one(const SegDev& g, int64_t i, int mode, double delta, const double* __restrict__ x,
+                                      const double* __restrict__ dsr, double* __restrict__ y) {
   const int64_t N = g.count;
   switch (g.kind) {
     case HC_CONE_ZERO:
-      y[g.base + i] = (mode == 0) ? 0.0 : x[g.base + i] / delta;
+      y[g.base + i] = dsr ? -dsr[g.base + i] : ((mode == 0) ? 0.0 : x[g.base + i] / delta);
       break;
-    case HC_CONE_NONNEG:
-      y[g.base + i] = fsel(mode, g.state[i], delta) * (mode == 0 ? x[g.base + i] : 1.0) *
-                      (mode == 0 ? 1.0 : x[g.base + i]);
+    case HC_CONE_NONNEG: {
+      const double h = g.state[i], xv = x[g.base + i];
+      y[g.base + i] = dsr ? -dsr[g.base + i] - h * xv : ((mode == 0) ? h * xv : (1.0 / (h + delta)) * xv);
       break;
+    }
     case HC_CONE_SOC: {
       const int d = g.dim;
       double wb[SOC_DMAX], xv[SOC_DMAX], yv[SOC_DMAX];
@@ -464,7 +468,7 @@ __global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __r
       const SocSpec sp = soc_spec(wb, d, eta);
       soc_spec_apply(wb, d, sp, fsel(mode, sp.lp, delta), fsel(mode, sp.lm, delta), fsel(mode, sp.lo, delta), xv,
                      yv);
-      for (int j = 0; j < d; ++j) y[g.base + j * N + i] = yv[j];
+      for (int j = 0; j < d; ++j) y[g.base + j * N + i] = dsr ? -dsr[g.base + j * N + i] - yv[j] : yv[j];
       break;
     }
     case HC_CONE_EXP:
@@ -477,12 +481,37 @@ __global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __r
       }
       double p[3];
       for (int r = 0; r < 3; ++r) p[r] = lam[r] * (V[0 * 3 + r] * xv[0] + V[1 * 3 + r] * xv[1] + V[2 * 3 + r] * xv[2]);
-      for (int j = 0; j < 3; ++j) y[g.base + j * N + i] = V[j * 3 + 0] * p[0] + V[j * 3 + 1] * p[1] + V[j * 3 + 2] * p[2];
+      for (int j = 0; j < 3; ++j) {
+        const double hv = V[j * 3 + 0] * p[0] + V[j * 3 + 1] * p[1] + V[j * 3 + 2] * p[2];
+        y[g.base + j * N + i] = dsr ? -dsr[g.base + j * N + i] - hv : hv;
+      }
       break;
     }
-    case HC_CONE_PSD:
-      break;   // k_psd_apply_wave
+    default:
+      break;   // PSD and large SOC: their own kernels
   }
+}
+
+__global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __restrict__ x,
+                             double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < g.count) cone_apply_one(g, i, mode, delta, x, nullptr, y);
+}
+
+// every lane-per-cone segment in one launch: block b belongs to the segment s
+// with first[s] <= b < first[s + 1]
+struct SegTable {
+  SegDev g[FUSED_SEGS];
+  int32_t first[FUSED_SEGS + 1];
+  int32_t nseg;
+};
+
+__global__ void k_cone_apply_fused(SegTable tb, int mode, double delta, const double* __restrict__ x,
+                                   const double* __restrict__ dsr, double* __restrict__ y) {
+  int s = 0;
+  while (s + 1 < tb.nseg && (int)blockIdx.x >= tb.first[s + 1]) ++s;
+  const int64_t i = (int64_t)(blockIdx.x - tb.first[s]) * blockDim.x + threadIdx.x;
+  if (i < tb.g[s].count) cone_apply_one(tb.g[s], i, mode, delta, x, dsr, y);
 }
 
 // Spectral application, one workgroup per cone (one lane per cone would pay
@@ -580,45 +609,7 @@ void cone_apply(const SegDev& g, int mode, double delta, const double* x, double
 __global__ void k_cone_recover(SegDev g, const double* __restrict__ dsr, const double* __restrict__ dz,
                                double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.count) return;
-  const int64_t N = g.count;
-  switch (g.kind) {
-    case HC_CONE_ZERO:
-      out[g.base + i] = -dsr[g.base + i];
-      break;
-    case HC_CONE_NONNEG:
-      out[g.base + i] = -dsr[g.base + i] - g.state[i] * dz[g.base + i];
-      break;
-    case HC_CONE_SOC: {
-      const int d = g.dim;
-      double wb[SOC_DMAX], xv[SOC_DMAX], yv[SOC_DMAX];
-      for (int j = 0; j < d; ++j) {
-        wb[j] = g.state[j * N + i];
-        xv[j] = dz[g.base + j * N + i];
-      }
-      const SocSpec sp = soc_spec(wb, d, g.state[d * N + i]);
-      soc_spec_apply(wb, d, sp, sp.lp, sp.lm, sp.lo, xv, yv);
-      for (int j = 0; j < d; ++j) out[g.base + j * N + i] = -dsr[g.base + j * N + i] - yv[j];
-      break;
-    }
-    case HC_CONE_EXP:
-    case HC_CONE_POW: {
-      double V[9], lam[3], xv[3];
-      for (int j = 0; j < 9; ++j) V[j] = g.state[(NS_V + j) * N + i];
-      for (int j = 0; j < 3; ++j) {
-        lam[j] = g.state[(NS_LAM + j) * N + i];
-        xv[j] = dz[g.base + j * N + i];
-      }
-      double p[3];
-      for (int r = 0; r < 3; ++r) p[r] = lam[r] * (V[0 * 3 + r] * xv[0] + V[1 * 3 + r] * xv[1] + V[2 * 3 + r] * xv[2]);
-      for (int j = 0; j < 3; ++j)
-        out[g.base + j * N + i] =
-            -dsr[g.base + j * N + i] - (V[j * 3 + 0] * p[0] + V[j * 3 + 1] * p[1] + V[j * 3 + 2] * p[2]);
-      break;
-    }
-    case HC_CONE_PSD:
-      break;   // k_psd_apply_wave (with dsr)
-  }
+  if (i < g.count) cone_apply_one(g, i, 0, 0.0, dz, dsr, out);
 }
 
 void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, double* out, hipStream_t st) {
@@ -635,6 +626,38 @@ void cone_recover_ds(const SegDev& g, const double* dsrhs, const double* dz, dou
   else
     hipLaunchKernelGGL(k_cone_recover, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, dsrhs, dz, out);
   HC_LAUNCH_CHECK();
+}
+
+bool lane_per_cone(const SegDev& g) {
+  return g.count > 0 && g.kind != HC_CONE_PSD && !soc_large(g.kind, g.dim);
+}
+
+void cone_apply_all(const std::vector<SegDev>& segs, int mode, double delta, const double* x, const double* dsr,
+                    double* y, hipStream_t st) {
+  SegTable tb{};
+  int nb = 0;
+  auto flush = [&]() {
+    if (tb.nseg == 0) return;
+    tb.first[tb.nseg] = nb;
+    hipLaunchKernelGGL(k_cone_apply_fused, dim3((unsigned)nb), dim3(CONE_BLOCK), 0, st, tb, mode, delta, x, dsr, y);
+    HC_LAUNCH_CHECK();
+    tb.nseg = 0;
+    nb = 0;
+  };
+  for (const SegDev& g : segs) {
+    if (g.count == 0) continue;
+    if (!lane_per_cone(g)) {   // PSD and large SOC keep their own kernels
+      if (dsr) cone_recover_ds(g, dsr, x, y, st);
+      else cone_apply(g, mode, delta, x, y, st);
+      continue;
+    }
+    if (tb.nseg == FUSED_SEGS) flush();
+    tb.g[tb.nseg] = g;
+    tb.first[tb.nseg] = nb;
+    tb.nseg++;
+    nb += (int)ceil_div(g.count, CONE_BLOCK);
+  }
+  flush();
 }
 
 // explicit lower-triangle entries of M = (H + delta I)^-1, packed index
@@ -765,11 +788,9 @@ void cone_mblock(const SegDev& g, double delta, double* work, hipStream_t st) {
 // ===========================================================================
 // combined-step d_s (eq. ds-correction-step)
 // ===========================================================================
-__global__ void k_cone_ds(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
-                          const double* __restrict__ dsa, const double* __restrict__ dza, double sm,
-                          double* __restrict__ ds) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.count) return;
+__device__ inline void cone_ds_one(const SegDev& g, int64_t i, const double* __restrict__ s,
+                                   const double* __restrict__ z, const double* __restrict__ dsa,
+                                   const double* __restrict__ dza, double sm, double* __restrict__ ds) {
   const int64_t N = g.count;
   switch (g.kind) {
     case HC_CONE_ZERO:
@@ -817,9 +838,52 @@ __global__ void k_cone_ds(SegDev g, const double* __restrict__ s, const double* 
       for (int j = 0; j < 3; ++j) ds[g.base + j * N + i] = sv[j] + sm * gr[j] - 0.5 * T[j];
       break;
     }
-    case HC_CONE_PSD:
-      break;   // k_psd_ds_wave
+    default:
+      break;   // PSD: k_psd_ds_wave; large SOC: lsoc_ds
   }
+}
+
+__global__ void k_cone_ds(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+                          const double* __restrict__ dsa, const double* __restrict__ dza, double sm,
+                          double* __restrict__ ds) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < g.count) cone_ds_one(g, i, s, z, dsa, dza, sm, ds);
+}
+
+__global__ void k_cone_ds_fused(SegTable tb, const double* __restrict__ s, const double* __restrict__ z,
+                                const double* __restrict__ dsa, const double* __restrict__ dza, double sm,
+                                double* __restrict__ ds) {
+  int q = 0;
+  while (q + 1 < tb.nseg && (int)blockIdx.x >= tb.first[q + 1]) ++q;
+  const int64_t i = (int64_t)(blockIdx.x - tb.first[q]) * blockDim.x + threadIdx.x;
+  if (i < tb.g[q].count) cone_ds_one(tb.g[q], i, s, z, dsa, dza, sm, ds);
+}
+
+void cone_ds_all(const std::vector<SegDev>& segs, const double* s, const double* z, const double* dsa,
+                 const double* dza, double sm, double* ds, hipStream_t st) {
+  SegTable tb{};
+  int nb = 0;
+  auto flush = [&]() {
+    if (tb.nseg == 0) return;
+    tb.first[tb.nseg] = nb;
+    hipLaunchKernelGGL(k_cone_ds_fused, dim3((unsigned)nb), dim3(CONE_BLOCK), 0, st, tb, s, z, dsa, dza, sm, ds);
+    HC_LAUNCH_CHECK();
+    tb.nseg = 0;
+    nb = 0;
+  };
+  for (const SegDev& g : segs) {
+    if (g.count == 0) continue;
+    if (!lane_per_cone(g)) {
+      cone_ds_combined(g, s, z, dsa, dza, sm, ds, st);
+      continue;
+    }
+    if (tb.nseg == FUSED_SEGS) flush();
+    tb.g[tb.nseg] = g;
+    tb.first[tb.nseg] = nb;
+    tb.nseg++;
+    nb += (int)ceil_div(g.count, CONE_BLOCK);
+  }
+  flush();
 }
 
 void cone_ds_combined(const SegDev& g, const double* s, const double* z, const double* dsa, const double* dza,
@@ -848,13 +912,13 @@ __device__ inline double soc_step_one(const double* x, const double* dx, int d) 
   return soc_boundary_step(a, b, c);
 }
 
-__global__ void k_step_sym(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
-                           const double* __restrict__ ds, const double* __restrict__ dz, double* __restrict__ partial) {
-  __shared__ double red[CONE_BLOCK];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// exact boundary step of one nonneg row or lane-per-cone SOC
+__device__ inline double step_sym_one(const SegDev& g, int64_t i, const double* __restrict__ s,
+                                      const double* __restrict__ z, const double* __restrict__ ds,
+                                      const double* __restrict__ dz) {
   const int64_t N = g.count;
   double a = INFINITY;
-  if (i < N) {
+  {
     if (g.kind == HC_CONE_NONNEG) {
       const int64_t r = g.base + i;
       if (ds[r] < 0.0) a = fmin(a, -s[r] / ds[r]);
@@ -871,6 +935,11 @@ __global__ void k_step_sym(SegDev g, const double* __restrict__ s, const double*
       a = fmin(soc_step_one(xs, xds, d), soc_step_one(xz, xdz, d));
     }
   }
+  return a;
+}
+
+__device__ inline void block_min_to(double a, double* __restrict__ partial) {
+  __shared__ double red[CONE_BLOCK];
   red[threadIdx.x] = a;
   __syncthreads();
   for (int off = CONE_BLOCK / 2; off > 0; off >>= 1) {
@@ -878,6 +947,21 @@ __global__ void k_step_sym(SegDev g, const double* __restrict__ s, const double*
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_step_sym(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+                           const double* __restrict__ ds, const double* __restrict__ dz, double* __restrict__ partial) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  block_min_to(i < g.count ? step_sym_one(g, i, s, z, ds, dz) : INFINITY, partial);
+}
+
+__global__ void k_step_sym_fused(SegTable tb, const double* __restrict__ s, const double* __restrict__ z,
+                                 const double* __restrict__ ds, const double* __restrict__ dz,
+                                 double* __restrict__ partial) {
+  int q = 0;
+  while (q + 1 < tb.nseg && (int)blockIdx.x >= tb.first[q + 1]) ++q;
+  const int64_t i = (int64_t)(blockIdx.x - tb.first[q]) * blockDim.x + threadIdx.x;
+  block_min_to(i < tb.g[q].count ? step_sym_one(tb.g[q], i, s, z, ds, dz) : INFINITY, partial);
 }
 
 // PSD: grid-stride over the cones with at most PSD_STEP_GRID blocks, one
@@ -1275,6 +1359,37 @@ int cone_step_sym(const SegDev& g, const double* s, const double* z, const doubl
   hipLaunchKernelGGL(k_step_sym, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, ds, dz, partial);
   HC_LAUNCH_CHECK();
   return nb;
+}
+
+int64_t cone_step_sym_all(const std::vector<SegDev>& segs, const double* s, const double* z, const double* ds,
+                          const double* dz, double* partial, hipStream_t st) {
+  int64_t off = 0;
+  SegTable tb{};
+  int nb = 0;
+  auto flush = [&]() {
+    if (tb.nseg == 0) return;
+    tb.first[tb.nseg] = nb;
+    hipLaunchKernelGGL(k_step_sym_fused, dim3((unsigned)nb), dim3(CONE_BLOCK), 0, st, tb, s, z, ds, dz,
+                       partial + off);
+    HC_LAUNCH_CHECK();
+    off += nb;
+    tb.nseg = 0;
+    nb = 0;
+  };
+  for (const SegDev& g : segs) {
+    if (g.count == 0 || g.kind == HC_CONE_ZERO || g.kind == HC_CONE_EXP || g.kind == HC_CONE_POW) continue;
+    if (!lane_per_cone(g)) {
+      off += cone_step_sym(g, s, z, ds, dz, partial + off, st);
+      continue;
+    }
+    if (tb.nseg == FUSED_SEGS) flush();
+    tb.g[tb.nseg] = g;
+    tb.first[tb.nseg] = nb;
+    tb.nseg++;
+    nb += (int)ceil_div(g.count, CONE_BLOCK);
+  }
+  flush();
+  return off;
 }
 
 struct Trials {

@@ -495,7 +495,8 @@ int32_t hc_server_create(hc_server** out, const hc_server_config* cfg) {
   }
   if (cfg->batched) {
     s->wave_thread = std::thread(&hc_server::wave_worker, s.get(), cfg->batch_slots);
-    for (int i = 0; i < std::max(2, cfg->workers); ++i) s->planners.emplace_back(&hc_server::planner, s.get());
+    // planning takes 1-3 ms per MPC request on the host: two planners per worker
+    for (int i = 0; i < 2 * std::max(2, cfg->workers); ++i) s->planners.emplace_back(&hc_server::planner, s.get());
   }
   *out = s.release();
   return HC_OK;

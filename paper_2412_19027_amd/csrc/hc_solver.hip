@@ -132,6 +132,8 @@ struct hc_solver {
   int64_t* dls_dst = nullptr;
   double *dq = nullptr, *db = nullptr, *dD = nullptr, *dE = nullptr, *dalpha = nullptr;
   int64_t* dperm = nullptr;         // internal row -> user row (device copy of perm)
+  double *wx = nullptr, *ws = nullptr, *wz = nullptr;   // last solved iterate, unscaled, internal rows
+  bool have_warm = false;
   int32_t *dtra = nullptr, *dtrb = nullptr;
   int64_t* dtm = nullptr;
   double *dstate = nullptr, *dmval = nullptr, *dhdiag = nullptr;
@@ -1243,7 +1245,7 @@ void P_mul(hc_solver* S, const double* x, double* y, double alpha, double beta) 
 }
 void H_apply(hc_solver* S, int mode, const double* x, double* y) {
   ConeProbe probe(S, CO_APPLY);
-  for (auto& g : S->sdev) cone_apply(g, mode, S->delta, x, y, S->stream);
+  cone_apply_all(S->sdev, mode, S->delta, x, nullptr, y, S->stream);
 }
 
 // unit diagonal on the padding rows [nt, ntp) of the dense tail
@@ -1553,7 +1555,7 @@ int check(hc_solver* S, const Resid& R) {
 }
 
 void scale_all(hc_solver* S, double mu, bool force_dual, int* pd_count) {
-  HC_HIP(hipMemsetAsync(S->dpd, 0, sizeof(int), S->stream));
+  vfill(1, 0.0, (double*)S->dpd, S->stream);   // both counters (fill kernels, not memsets, throughout)
   {
     ConeProbe probe(S, CO_SCALE);
     for (auto& g : S->sdev) cone_scale(g, S->s, S->z, mu, force_dual ? 1 : 0, S->dhdiag, S->dpd, S->stream);
@@ -1591,7 +1593,7 @@ Dir direction(hc_solver* S, const double* r1, const double* r2, double dtau_rhs,
   vlin3(m, 1.0, S->z1, d.dtau, S->z2, 0.0, nullptr, dzo, st);
   {
     ConeProbe probe(S, CO_RECOVER);
-    for (auto& g : S->sdev) cone_recover_ds(g, ds_rhs, dzo, dso, st);
+    cone_apply_all(S->sdev, 0, 0.0, dzo, ds_rhs, dso, st);
   }
   d.dkappa = -(dkap_rhs + S->kappa * d.dtau) / S->tau;
   return d;
@@ -1618,7 +1620,7 @@ double step_length(hc_solver* S, const Step& d, bool combined) {
     int64_t off = 0;
     {
       ConeProbe probe(S, CO_STEP, 1);
-      for (auto& g : S->sdev) off += cone_step_sym(g, S->s, S->z, d.ds, d.dz, S->dpart + off, st);
+      off = cone_step_sym_all(S->sdev, S->s, S->z, d.ds, d.dz, S->dpart, st);
     }
     if (off) {
       HC_HIP(hipMemcpyAsync(S->hpart, S->dpart, off * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1706,6 +1708,36 @@ __global__ void k_identity_state(SegDev g, double* hdiag) {
   }
 }
 
+// the last solved iterate without the equilibration: x D / tau, s / (E tau),
+// E z / (c tau), internal rows
+__global__ void k_warm_store(int64_t n, int64_t m, const double* __restrict__ x, const double* __restrict__ s,
+                             const double* __restrict__ z, const double* __restrict__ D, const double* __restrict__ E,
+                             double inv_ct, double inv_t, double* __restrict__ wx, double* __restrict__ ws,
+                             double* __restrict__ wz) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n > m ? n : m);
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n) wx[i] = D[i] * x[i] * inv_t;
+    if (i < m) {
+      ws[i] = s[i] / E[i] * inv_t;
+      wz[i] = E[i] * z[i] * inv_ct;
+    }
+  }
+}
+// v = (1 - th) v_prev + th v, with v_prev carried to the current equilibration
+__global__ void k_warm_blend(int64_t n, int64_t m, double th, const double* __restrict__ wx,
+                             const double* __restrict__ ws, const double* __restrict__ wz,
+                             const double* __restrict__ D, const double* __restrict__ E, double c,
+                             double* __restrict__ x, double* __restrict__ s, double* __restrict__ z) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n > m ? n : m);
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n) x[i] = (1.0 - th) * (wx[i] / D[i]) + th * x[i];
+    if (i < m) {
+      s[i] = (1.0 - th) * (ws[i] * E[i]) + th * s[i];
+      z[i] = (1.0 - th) * (wz[i] * c / E[i]) + th * z[i];
+    }
+  }
+}
+
 void init_point(hc_solver* S) {
   hipStream_t st = S->stream;
   const int64_t n = S->n, m = S->m;
@@ -1783,7 +1815,7 @@ int iterate(hc_solver* S, const Resid& R) {
     const double dk = S->kappa * S->tau + da.dkappa * da.dtau - sigma * mu;
     {
       ConeProbe probe(S, CO_DS);
-      for (auto& g : S->sdev) cone_ds_combined(g, S->s, S->z, S->dsa, S->dza, sigma * mu, S->dsrhs, st);
+      cone_ds_all(S->sdev, S->s, S->z, S->dsa, S->dza, sigma * mu, S->dsrhs, st);
     }
     const double f = 1.0 - sigma;
     vlin3(n, -f, S->rdv, 0.0, nullptr, 0.0, nullptr, S->r1, st);
@@ -1824,11 +1856,30 @@ void begin_solve(hc_solver* S) {
   S->info.leaf_columns = keep.leaf_columns;
   S->info.psd_gathered_rows = keep.psd_gathered_rows;
   S->info.factor_flops = keep.factor_flops;
-  HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), S->stream));
+  vfill(1, 0.0, (double*)S->dhits, S->stream);
   S->sdiag_max = 0;
   init_point(S);
+  if (S->st.warm_start && S->have_warm) {   // parametric re-solve from the last solution (Sec. 4.6)
+    const int64_t L = std::max(S->n, S->m);
+    const int nb = (int)std::min<int64_t>(std::max<int64_t>(1, ceil_div(L, 256)), 65535);
+    hipLaunchKernelGGL(k_warm_blend, dim3(nb), dim3(256), 0, S->stream, S->n, S->m, S->st.warm_blend, S->wx, S->ws,
+                       S->wz, S->dD, S->dE, S->cscale, S->x, S->s, S->z);
+    HC_LAUNCH_CHECK();
+    S->tau = S->kappa = 1.0;
+  }
   S->status = 0;
   S->kiter = 0;
+}
+
+// keeps a solved iterate for the next warm start
+void end_solve(hc_solver* S) {
+  if (!S->st.warm_start || S->status != HC_STATUS_SOLVED) return;
+  const int64_t L = std::max(S->n, S->m);
+  const int nb = (int)std::min<int64_t>(std::max<int64_t>(1, ceil_div(L, 256)), 65535);
+  hipLaunchKernelGGL(k_warm_store, dim3(nb), dim3(256), 0, S->stream, S->n, S->m, S->x, S->s, S->z, S->dD, S->dE,
+                     1.0 / (S->cscale * S->tau), 1.0 / S->tau, S->wx, S->ws, S->wz);
+  HC_LAUNCH_CHECK();
+  S->have_warm = true;
 }
 
 // one pass of the loop body of Algorithm 1 (residuals, termination tests,
@@ -1868,6 +1919,7 @@ void run_solve(hc_solver* S) {
   begin_solve(S);
   while (!step_solve(S)) {
   }
+  end_solve(S);
 }
 
 // every device allocation of a solver, in order (dry run: byte count only)
@@ -1981,6 +2033,9 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->sb = buf.take<double>(nt);
   S->sy = buf.take<double>(nt);
   S->sx = buf.take<double>(nt);
+  S->wx = buf.take<double>(n);
+  S->ws = buf.take<double>(m);
+  S->wz = buf.take<double>(m);
 }
 
 size_t workspace_bytes(const hc_solver* S) {
@@ -2027,13 +2082,13 @@ void bind(hc_solver* S, const hc_device* dev) {
     HC_HIP(hipHostMalloc((void**)&S->hmask, S->npart * sizeof(unsigned long long), hipHostMallocDefault));
     S->own_stage = true;
   }
-  HC_HIP(hipMemsetAsync(S->dhits, 0, sizeof(unsigned long long), st));
+  vfill(1, 0.0, (double*)S->dhits, st);
   if (S->K1 + S->K2 > 0) {   // zero padding rows of the dense-row operand, zero rank-2 rows
-    HC_HIP(hipMemsetAsync(S->dBd, 0, (size_t)(S->K1 + S->K2) * S->nt * sizeof(double), st));
+    vfill((S->K1 + S->K2) * S->nt, 0.0, S->dBd, st);
     const size_t real = S->drows.size() * (size_t)S->nt;
     const size_t rows = std::max<size_t>(S->drows.size(), (size_t)(S->K1 + S->K2));
     if (rows * S->nt > real)
-      HC_HIP(hipMemsetAsync(S->dAd + real, 0, (rows * S->nt - real) * sizeof(double), st));
+      vfill((int64_t)(rows * S->nt - real), 0.0, S->dAd + real, st);
   }
   // segment views
   int pow_off = 0;
@@ -2322,28 +2377,37 @@ bool wave_plan(const hc_solver* S, WavePlan* out, std::string* why) {
     P.E[r] = S->E[srow_of[r]];
   }
   // A'MA gather plan: for every band entry (i >= j) its terms A_pi A_qj M_pq
-  // over the rows p, q of one block (p = q for zero and nonneg rows), listed
-  // in block order and then grouped by entry with a counting sort (stable, so
-  // that order is the order of the terms within an entry)
+  // over the rows p, q of one block (p = q for zero and nonneg rows).  Every
+  // zero row has the same M = 1/delta, so their products are summed per entry
+  // here (in row order) into one term on M[0]; the other blocks' terms follow
+  // in block order, grouped by entry with a stable counting sort.
   {
     struct Term {
       int32_t e, mi;
       double c;
     };
+    const size_t ne = (size_t)n * W;
+    std::vector<double> zsum(P.nz > 0 ? ne : 0, 0.0);
+    std::vector<char> ztouch(P.nz > 0 ? ne : 0, 0);
     std::vector<Term> terms;
-    terms.reserve((size_t)P.Arp[m] * 8);
-    P.trp.assign((size_t)n * W + 1, 0);
+    P.trp.assign(ne + 1, 0);
     for (int32_t bk = 0; bk < nblk; ++bk) {
       int32_t r0, r1;
       block_rows(bk, &r0, &r1);
       if (bk < P.nz + P.nn) {   // one row; its columns ascend, so kb <= ka gives i >= j
+        const bool zero = bk < P.nz;
         for (int32_t ka = P.Arp[r0]; ka < P.Arp[r0 + 1]; ++ka) {
           const int32_t i = P.Aci[ka];
           const double va = P.Av[ka];
           for (int32_t kb = P.Arp[r0]; kb <= ka; ++kb) {
             const int32_t e = P.Aci[kb] * W + (i - P.Aci[kb]);
-            terms.push_back(Term{e, bk, va * P.Av[kb]});
-            P.trp[e + 1]++;
+            if (zero) {
+              zsum[e] += va * P.Av[kb];
+              ztouch[e] = 1;
+            } else {
+              terms.push_back(Term{e, bk, va * P.Av[kb]});
+              P.trp[e + 1]++;
+            }
           }
         }
         continue;
@@ -2361,10 +2425,20 @@ bool wave_plan(const hc_solver* S, WavePlan* out, std::string* why) {
               P.trp[e + 1]++;
             }
     }
-    for (size_t e = 0; e < (size_t)n * W; ++e) P.trp[e + 1] += P.trp[e];
-    P.tm.resize(terms.size());
-    P.tc.resize(terms.size());
+    for (size_t e = 0; e < ne; ++e) {
+      if (P.nz > 0 && ztouch[e]) P.trp[e + 1]++;
+      P.trp[e + 1] += P.trp[e];
+    }
+    P.tm.resize(P.trp[ne]);
+    P.tc.resize(P.trp[ne]);
     std::vector<int32_t> fill(P.trp.begin(), P.trp.end() - 1);
+    if (P.nz > 0)
+      for (size_t e = 0; e < ne; ++e)
+        if (ztouch[e]) {
+          const int32_t o = fill[e]++;
+          P.tm[o] = 0;
+          P.tc[o] = zsum[e];
+        }
     for (const Term& tt : terms) {
       const int32_t o = fill[tt.e]++;
       P.tm[o] = tt.mi;
@@ -2435,20 +2509,19 @@ int32_t solver_finish(hc_solver* S) {
 // ===========================================================================
 // C-ABI
 // ===========================================================================
-// the iterate in the user's coordinates: x = D x~ / t, s[perm] = s~ / (E t),
-// z[perm] = E z~ / (c t)
+// the iterate in the user's coordinates: x = D x~ / t, s[perm] = s~ / E / t,
+// z[perm] = E z~ / (c t) (the host form's operations, so both agree bit for bit)
 __global__ void k_user_solution(int64_t n, int64_t m, const double* __restrict__ xi, const double* __restrict__ si,
                                 const double* __restrict__ zi, const double* __restrict__ D,
-                                const double* __restrict__ E, const int64_t* __restrict__ perm, double inv_c,
+                                const double* __restrict__ E, const int64_t* __restrict__ perm, double c,
                                 double t, double* __restrict__ x, double* __restrict__ s, double* __restrict__ z) {
-  const double it = 1.0 / t;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n > m ? n : m);
        i += (int64_t)gridDim.x * blockDim.x) {
-    if (x && i < n) x[i] = D[i] * xi[i] * it;
+    if (x && i < n) x[i] = D[i] * xi[i] / t;
     if (i < m) {
       const int64_t u = perm[i];
-      if (s) s[u] = si[i] / E[i] * it;
-      if (z) z[u] = E[i] * zi[i] * inv_c * it;
+      if (s) s[u] = si[i] / E[i] / t;
+      if (z) z[u] = E[i] * zi[i] / (c * t);
     }
   }
 }
@@ -2476,6 +2549,8 @@ int32_t hc_settings_default(hc_settings* o) {
   o->verbose = 0;
   o->profile = 0;
   o->leaf_blocks = 1;
+  o->warm_start = 0;
+  o->warm_blend = 0.02;
   return HC_OK;
 }
 
@@ -2573,7 +2648,7 @@ int32_t hc_get_solution(const hc_solver* S, double* x, double* sv, double* z, in
       const int64_t L = std::max(n, m);
       const int nb = (int)std::min<int64_t>(std::max<int64_t>(1, ceil_div(L, 256)), 65535);
       hipLaunchKernelGGL(k_user_solution, dim3(nb), dim3(256), 0, S->stream, n, m, S->x, S->s, S->z, S->dD, S->dE,
-                         S->dperm, 1.0 / S->cscale, cert0 ? 1.0 : S->tau, x, sv, z);
+                         S->dperm, S->cscale, cert0 ? 1.0 : S->tau, x, sv, z);
       HC_LAUNCH_CHECK();
       HC_HIP(hipStreamSynchronize(S->stream));
       return HC_OK;

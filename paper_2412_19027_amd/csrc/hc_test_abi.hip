@@ -123,7 +123,7 @@ int32_t hc_test_cone_scale(int32_t type, int64_t count, int32_t dim, const doubl
       double* ea = T.alloc(tot);
       HC_HIP(hipMemcpyAsync(ea, he.data(), tot * 8, hipMemcpyHostToDevice, st));
       double* ei = T.in(ea, st);
-      cone_apply(T.g, 0, 0.0, ei, y, st);
+      cone_apply_all(std::vector<SegDev>{T.g}, 0, 0.0, ei, nullptr, y, st);
       double* ya = T.alloc(tot);
       T.out(y, ya, st);
       HC_HIP(hipMemcpyAsync(hy.data(), ya, tot * 8, hipMemcpyDeviceToHost, st));
@@ -232,7 +232,7 @@ int32_t hc_test_cone_ds(int32_t type, int64_t count, int32_t dim, const double* 
     HC_HIP(hipMemsetAsync(pd, 0, sizeof(double), st));
     cone_scale(T.g, si, zi, mu, force_dual ? 1 : 0, hd, pd, st);
     double* o = T.alloc(tot);
-    cone_ds_combined(T.g, si, zi, ai, bi, sm, o, st);
+    cone_ds_all(std::vector<SegDev>{T.g}, si, zi, ai, bi, sm, o, st);
     T.out(o, ds_out, st);
     HC_HIP(hipStreamSynchronize(st));
   });
@@ -284,7 +284,7 @@ int32_t hc_test_cone_step_min(int32_t type, int64_t count, int32_t dim, const do
     double* b = T.in(dz, st);
     // as many partials as the solver's launch may write (one per workgroup)
     double* part = T.alloc(std::max<int64_t>(2 * T.g.count, cone_blocks(T.g)) + 64);
-    const int nb = cone_step_sym(T.g, si, zi, a, b, part, st);
+    const int nb = (int)cone_step_sym_all(std::vector<SegDev>{T.g}, si, zi, a, b, part, st);
     std::vector<double> h(std::max(nb, 1));
     if (nb) HC_HIP(hipMemcpyAsync(h.data(), part, nb * sizeof(double), hipMemcpyDeviceToHost, st));
     HC_HIP(hipStreamSynchronize(st));

@@ -26,7 +26,11 @@ CASES = {
     "psd_pow_full_s0": lambda: W.psd_pow(0),
     "logreg_exp_2k_s0": lambda: W.logreg_exp(0, samples=2000, features=50),
     "logreg_exp_20k_s0": lambda: W.logreg_exp(0, samples=20000, features=100),
+    "logreg_exp_full_s0": lambda: W.logreg_exp(0),
 }
+for _s in (1, 2, 3, 4):
+    CASES[f"sparse_socp_full_s{_s}"] = (lambda s: lambda: W.sparse_socp(s))(_s)
+    CASES[f"psd_pow_full_s{_s}"] = (lambda s: lambda: W.psd_pow(s))(_s)
 
 
 def main(names):

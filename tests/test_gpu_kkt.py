@@ -20,7 +20,7 @@ and the GPU find it independently, so S and the solutions differ by up to
 ~1e-13/mu relative (measured 1.2e-4 at mu = 5e-9 on the exponential-cone case,
 2.2e-4 at mu = 6e-10 on the PSD/power case).  The bound 1e-10 + 5e-12/mu
 holds that with a margin of about 8x.  Problems with symmetric cones only
-are held to 1e-10 + 5e-14/mu.
+are held to 1e-10 + 5e-13/mu (largest measured 5.4e-14/mu).
 """
 import numpy as np
 import pytest
@@ -49,8 +49,9 @@ CASES = [
 
 def tol(mu, nonsym=True):
     """nonsym: the problem has exponential or power cones (conjugate points
-    found independently on the two sides); symmetric cones only: 100x tighter."""
-    return 1e-10 + (5e-12 if nonsym else 5e-14) / mu
+    found independently on the two sides); symmetric cones only: 10x tighter
+    (largest measured 5.4e-14/mu, the multistage case with rank-2 SOC rows)."""
+    return 1e-10 + (5e-12 if nonsym else 5e-13) / mu
 
 
 def rel(a, b):
