@@ -24,9 +24,15 @@ struct SegDev {
 // whether any cone took the primal-dual scaling.
 void cone_scale(const SegDev& g, const double* s, const double* z, double mu, int force_dual, double* hdiag,
                 int* branch_pd_count, hipStream_t st);
+// the same over every segment: zero, nonneg and lane-per-cone SOC segments in
+// one launch, the others by their own kernels
+void cone_scale_all(const std::vector<SegDev>& segs, const double* s, const double* z, double mu, int force_dual,
+                    double* hdiag, int* branch_pd_count, hipStream_t st);
 // Explicit lower-triangle entries of (H + delta I)^-1 per cone into g.mblk.
 // work: cone_mblock_work(g) doubles of device scratch (PSD: the G_i factors)
 void cone_mblock(const SegDev& g, double delta, double* work, hipStream_t st);
+// over every segment, all but the PSD ones in one launch
+void cone_mblock_all(const std::vector<SegDev>& segs, double delta, double* work, hipStream_t st);
 int64_t cone_mblock_work(const SegDev& g);
 // y[rows] = H x[rows]  (mode 0) or (H + delta I)^-1 x[rows] (mode 1), spectral form.
 void cone_apply(const SegDev& g, int mode, double delta, const double* x, double* y, hipStream_t st);

@@ -263,24 +263,19 @@ __device__ bool pow_conj(const double* s, double a, double* z) {
 // ===========================================================================
 // kernels: scaling
 // ===========================================================================
-__global__ void k_zero_scale(int64_t base, int64_t count, double* hdiag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) hdiag[base + i] = 0.0;
-}
-
-__global__ void k_nonneg_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
-                               double* __restrict__ hdiag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.count) return;
-  const double h = s[g.base + i] / z[g.base + i];
-  g.state[i] = h;
-  hdiag[g.base + i] = h;
-}
-
-__global__ void k_soc_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
-                            double* __restrict__ hdiag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.count) return;
+// scaling of one zero/nonneg row or lane-per-cone SOC i of segment g
+__device__ inline void sym_scale_one(const SegDev& g, int64_t i, const double* __restrict__ s,
+                                     const double* __restrict__ z, double* __restrict__ hdiag) {
+  if (g.kind == HC_CONE_ZERO) {
+    hdiag[g.base + i] = 0.0;
+    return;
+  }
+  if (g.kind == HC_CONE_NONNEG) {
+    const double h = s[g.base + i] / z[g.base + i];
+    g.state[i] = h;
+    hdiag[g.base + i] = h;
+    return;
+  }
   const int d = g.dim;
   const int64_t N = g.count;
   double sv[SOC_DMAX], zv[SOC_DMAX];
@@ -297,6 +292,12 @@ __global__ void k_soc_scale(SegDev g, const double* __restrict__ s, const double
   g.state[d * N + i] = eta;
   const double e2 = eta * eta;
   for (int j = 0; j < d; ++j) hdiag[g.base + j * N + i] = e2 * (2.0 * wb[j] * wb[j] - (j == 0 ? 1.0 : -1.0));
+}
+
+__global__ void k_sym_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+                            double* __restrict__ hdiag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < g.count) sym_scale_one(g, i, s, z, hdiag);
 }
 
 // exp/pow state fields (field-major): lam 0..2, V 3..11 (row-major), Uh 12..20,
@@ -410,17 +411,15 @@ void cone_scale(const SegDev& g, const double* s, const double* z, double mu, in
   const int nb = cone_blocks(g);
   switch (g.kind) {
     case HC_CONE_ZERO:
-      hipLaunchKernelGGL(k_zero_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g.base, g.count, hdiag);
-      break;
     case HC_CONE_NONNEG:
-      hipLaunchKernelGGL(k_nonneg_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, hdiag);
+      hipLaunchKernelGGL(k_sym_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, hdiag);
       break;
     case HC_CONE_SOC:
       if (soc_large(g.kind, g.dim)) {
         lsoc_scale(g, s, z, hdiag, st);
         return;
       }
-      hipLaunchKernelGGL(k_soc_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, hdiag);
+      hipLaunchKernelGGL(k_sym_scale, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, hdiag);
       break;
     case HC_CONE_EXP:
     case HC_CONE_POW:
@@ -660,6 +659,42 @@ void cone_apply_all(const std::vector<SegDev>& segs, int mode, double delta, con
   flush();
 }
 
+__global__ void k_sym_scale_fused(SegTable tb, const double* __restrict__ s, const double* __restrict__ z,
+                                  double* __restrict__ hdiag) {
+  int q = 0;
+  while (q + 1 < tb.nseg && (int)blockIdx.x >= tb.first[q + 1]) ++q;
+  const int64_t i = (int64_t)(blockIdx.x - tb.first[q]) * blockDim.x + threadIdx.x;
+  if (i < tb.g[q].count) sym_scale_one(tb.g[q], i, s, z, hdiag);
+}
+
+void cone_scale_all(const std::vector<SegDev>& segs, const double* s, const double* z, double mu, int force_dual,
+                    double* hdiag, int* pd_count, hipStream_t st) {
+  SegTable tb{};
+  int nb = 0;
+  auto flush = [&]() {
+    if (tb.nseg == 0) return;
+    tb.first[tb.nseg] = nb;
+    hipLaunchKernelGGL(k_sym_scale_fused, dim3((unsigned)nb), dim3(CONE_BLOCK), 0, st, tb, s, z, hdiag);
+    HC_LAUNCH_CHECK();
+    tb.nseg = 0;
+    nb = 0;
+  };
+  for (const SegDev& g : segs) {
+    if (g.count == 0) continue;
+    const bool sym = g.kind == HC_CONE_ZERO || g.kind == HC_CONE_NONNEG || (g.kind == HC_CONE_SOC && !soc_large(g.kind, g.dim));
+    if (!sym) {   // exp/pow (primal-dual or dual scaling), PSD, large SOC: their own kernels
+      cone_scale(g, s, z, mu, force_dual, hdiag, pd_count, st);
+      continue;
+    }
+    if (tb.nseg == FUSED_SEGS) flush();
+    tb.g[tb.nseg] = g;
+    tb.first[tb.nseg] = nb;
+    tb.nseg++;
+    nb += (int)ceil_div(g.count, CONE_BLOCK);
+  }
+  flush();
+}
+
 // explicit lower-triangle entries of M = (H + delta I)^-1, packed index
 // p = a (a + 1) / 2 + b for a >= b, stored mblk[p * count + cone]
 //
@@ -714,10 +749,8 @@ __global__ __launch_bounds__(256) void k_psd_mblock(SegDev g, const double* __re
   g.mblk[(int64_t)p * N + c] = 0.5 * ca * cb * acc;
 }
 
-__global__ void k_cone_mblock(SegDev g, double delta) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void cone_mblock_one(const SegDev& g, int64_t i, double delta) {
   const int64_t N = g.count;
-  if (i >= N) return;
   switch (g.kind) {
     case HC_CONE_ZERO:
       g.mblk[i] = 1.0 / delta;
@@ -768,6 +801,18 @@ __global__ void k_cone_mblock(SegDev g, double delta) {
   }
 }
 
+__global__ void k_cone_mblock(SegDev g, double delta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < g.count) cone_mblock_one(g, i, delta);
+}
+
+__global__ void k_cone_mblock_fused(SegTable tb, double delta) {
+  int q = 0;
+  while (q + 1 < tb.nseg && (int)blockIdx.x >= tb.first[q + 1]) ++q;
+  const int64_t i = (int64_t)(blockIdx.x - tb.first[q]) * blockDim.x + threadIdx.x;
+  if (i < tb.g[q].count) cone_mblock_one(tb.g[q], i, delta);
+}
+
 int64_t cone_mblock_work(const SegDev& g) {
   return g.kind == HC_CONE_PSD ? g.count * (int64_t)g.k * g.k * g.k : 0;
 }
@@ -783,6 +828,32 @@ void cone_mblock(const SegDev& g, double delta, double* work, hipStream_t st) {
     hipLaunchKernelGGL(k_cone_mblock, dim3((unsigned)std::max<int64_t>(1, ceil_div(g.count, CONE_BLOCK))),
                        dim3(CONE_BLOCK), 0, st, g, delta);
   HC_LAUNCH_CHECK();
+}
+
+void cone_mblock_all(const std::vector<SegDev>& segs, double delta, double* work, hipStream_t st) {
+  SegTable tb{};
+  int nb = 0;
+  auto flush = [&]() {
+    if (tb.nseg == 0) return;
+    tb.first[tb.nseg] = nb;
+    hipLaunchKernelGGL(k_cone_mblock_fused, dim3((unsigned)nb), dim3(CONE_BLOCK), 0, st, tb, delta);
+    HC_LAUNCH_CHECK();
+    tb.nseg = 0;
+    nb = 0;
+  };
+  for (const SegDev& g : segs) {
+    if (g.count == 0) continue;
+    if (g.kind == HC_CONE_PSD) {   // PSD: its own kernels (and the work buffer)
+      cone_mblock(g, delta, work, st);
+      continue;
+    }
+    if (tb.nseg == FUSED_SEGS) flush();
+    tb.g[tb.nseg] = g;
+    tb.first[tb.nseg] = nb;
+    tb.nseg++;
+    nb += (int)ceil_div(g.count, CONE_BLOCK);
+  }
+  flush();
 }
 
 // ===========================================================================

@@ -1284,7 +1284,7 @@ void factor(hc_solver* S, bool fp64 = false) {
   }
   {
     ConeProbe probe(S, CO_MBLOCK);
-    for (auto& g : S->sdev) cone_mblock(g, S->delta, S->dmwork, st);   // segments run in order: one work buffer
+    cone_mblock_all(S->sdev, S->delta, S->dmwork, st);   // segments run in order: one work buffer
   }
   // The tail is factored padded to ld (a multiple of 64) with an identity
   // block on the padding: [[S, 0], [0, I]] = [[L, 0], [0, I]] [[L, 0], [0, I]]',
@@ -1558,7 +1558,7 @@ void scale_all(hc_solver* S, double mu, bool force_dual, int* pd_count) {
   vfill(1, 0.0, (double*)S->dpd, S->stream);   // both counters (fill kernels, not memsets, throughout)
   {
     ConeProbe probe(S, CO_SCALE);
-    for (auto& g : S->sdev) cone_scale(g, S->s, S->z, mu, force_dual ? 1 : 0, S->dhdiag, S->dpd, S->stream);
+    cone_scale_all(S->sdev, S->s, S->z, mu, force_dual ? 1 : 0, S->dhdiag, S->dpd, S->stream);
   }
   int h = 0;
   HC_HIP(hipMemcpyAsync(&h, S->dpd, sizeof(int), hipMemcpyDeviceToHost, S->stream));

@@ -112,7 +112,7 @@ int32_t hc_test_cone_scale(int32_t type, int64_t count, int32_t dim, const doubl
     double* hd = T.alloc(tot);
     int* pd = (int*)T.alloc(1);
     HC_HIP(hipMemsetAsync(pd, 0, sizeof(double), st));
-    cone_scale(T.g, si, zi, mu, force_dual ? 1 : 0, hd, pd, st);
+    cone_scale_all(std::vector<SegDev>{T.g}, si, zi, mu, force_dual ? 1 : 0, hd, pd, st);
     // H column by column: H e_j
     double* e = T.alloc(tot);
     double* y = T.alloc(tot);
@@ -167,8 +167,8 @@ int32_t hc_test_cone_mblock(int32_t type, int64_t count, int32_t dim, const doub
     double* hd = T.alloc(tot);
     int* pd = (int*)T.alloc(1);
     HC_HIP(hipMemsetAsync(pd, 0, sizeof(double), st));
-    cone_scale(T.g, si, zi, mu, force_dual ? 1 : 0, hd, pd, st);
-    cone_mblock(T.g, delta, T.alloc(std::max<int64_t>(1, cone_mblock_work(T.g))), st);
+    cone_scale_all(std::vector<SegDev>{T.g}, si, zi, mu, force_dual ? 1 : 0, hd, pd, st);
+    cone_mblock_all(std::vector<SegDev>{T.g}, delta, T.alloc(std::max<int64_t>(1, cone_mblock_work(T.g))), st);
     const int64_t per = mblock_doubles(type, T.g.dim);
     std::vector<double> hm(per * T.g.count), dense((size_t)count * T.rows * T.rows, 0.0);
     HC_HIP(hipMemcpyAsync(hm.data(), T.g.mblk, hm.size() * 8, hipMemcpyDeviceToHost, st));
@@ -230,7 +230,7 @@ int32_t hc_test_cone_ds(int32_t type, int64_t count, int32_t dim, const double* 
     double* hd = T.alloc(tot);
     int* pd = (int*)T.alloc(1);
     HC_HIP(hipMemsetAsync(pd, 0, sizeof(double), st));
-    cone_scale(T.g, si, zi, mu, force_dual ? 1 : 0, hd, pd, st);
+    cone_scale_all(std::vector<SegDev>{T.g}, si, zi, mu, force_dual ? 1 : 0, hd, pd, st);
     double* o = T.alloc(tot);
     cone_ds_all(std::vector<SegDev>{T.g}, si, zi, ai, bi, sm, o, st);
     T.out(o, ds_out, st);
