@@ -195,10 +195,13 @@ void hc_server::planner() {
   }
 }
 
-// The batched engine: every tick is one graph launch (the interior-point
-// iteration of all slots in one kernel, then the slots' phase words copied to
+// The batched engine: every tick is one graph launch (interior-point
+// iterations of all slots in one kernel, then the slots' phase words copied to
 // pinned host memory); between ticks finished problems are read out and
-// retired and queued ones admitted into free slots and pool memory.
+// retired and queued ones admitted into free slots and pool memory.  A tick
+// lasts about one iteration of its largest problem; the smaller ones run as
+// many iterations as fit in that time (the budget is 0.9 of the last tick's
+// length), so a small problem does not wait a whole tick per iteration.
 void hc_server::wave_worker(int cap) {
   using namespace hc;
   (void)hipSetDevice(cfg.device);
@@ -206,25 +209,30 @@ void hc_server::wave_worker(int cap) {
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
   WaveDesc* hdesc = nullptr;
   int32_t *hact = nullptr, *hstat = nullptr;
+  int64_t* hbudget = nullptr;
   void* dtab = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool ok = hipHostMalloc((void**)&hdesc, (size_t)cap * sizeof(WaveDesc), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void**)&hact, (size_t)cap * sizeof(int32_t), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void**)&hstat, (size_t)cap * sizeof(int32_t), hipHostMallocDefault) == hipSuccess &&
-            hipMalloc(&dtab, (size_t)cap * (sizeof(WaveDesc) + 2 * sizeof(int32_t))) == hipSuccess;
+            hipHostMalloc((void**)&hbudget, sizeof(int64_t), hipHostMallocDefault) == hipSuccess &&
+            hipMalloc(&dtab, (size_t)cap * (sizeof(WaveDesc) + 2 * sizeof(int32_t)) + 64) == hipSuccess;
   WaveDesc* ddesc = (WaveDesc*)dtab;
   int32_t* dact = ok ? (int32_t*)((char*)dtab + (size_t)cap * sizeof(WaveDesc)) : nullptr;
   int32_t* dstat = ok ? dact + cap : nullptr;
+  int64_t* dbudget = ok ? (int64_t*)(((uintptr_t)(dstat + cap) + 15) / 16 * 16) : nullptr;
   if (ok) {
     std::memset(hact, 0, (size_t)cap * sizeof(int32_t));
+    *hbudget = 0;
     ok = hipMemcpyAsync(dact, hact, (size_t)cap * sizeof(int32_t), hipMemcpyHostToDevice, st) == hipSuccess &&
+         hipMemcpyAsync(dbudget, hbudget, sizeof(int64_t), hipMemcpyHostToDevice, st) == hipSuccess &&
          hipStreamSynchronize(st) == hipSuccess;
   }
   if (ok) {   // the tick, captured once
     ok = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) == hipSuccess;
     if (ok) {
-      wave_tick(ddesc, dact, cap, dstat, st);
+      wave_tick(ddesc, dact, cap, dstat, dbudget, st);
       (void)hipMemcpyAsync(hstat, dstat, (size_t)cap * sizeof(int32_t), hipMemcpyDeviceToHost, st);
       ok = hipStreamEndCapture(st, &graph) == hipSuccess &&
            hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
@@ -285,6 +293,7 @@ void hc_server::wave_worker(int cap) {
     if (nact == 0) continue;
     const double t0 = now_ms();
     const bool launched = hipGraphLaunch(exec, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+    const double tick_ms = now_ms() - t0;
     bool changed = false;
     for (int i = 0; i < cap; ++i) {
       if (!hact[i]) continue;
@@ -308,6 +317,9 @@ void hc_server::wave_worker(int cap) {
       slot[i].reset();
     }
     if (changed) (void)hipMemcpyAsync(dact, hact, (size_t)cap * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    // next tick's budget: 0.9 of this tick's length (10 ns clock ticks)
+    *hbudget = (int64_t)(0.9 * tick_ms * 1e5);
+    (void)hipMemcpyAsync(dbudget, hbudget, sizeof(int64_t), hipMemcpyHostToDevice, st);
     std::lock_guard<std::mutex> lk(mu);
     busy_ms += now_ms() - t0;
     ticks++;
@@ -332,6 +344,7 @@ void hc_server::wave_worker(int cap) {
   if (hdesc) (void)hipHostFree(hdesc);
   if (hact) (void)hipHostFree(hact);
   if (hstat) (void)hipHostFree(hstat);
+  if (hbudget) (void)hipHostFree(hbudget);
   (void)hipStreamDestroy(st);
 }
 

@@ -2376,21 +2376,20 @@ bool wave_plan(const hc_solver* S, WavePlan* out, std::string* why) {
     P.b[r] = S->b[srow_of[r]];
     P.E[r] = S->E[srow_of[r]];
   }
-  // A'MA gather plan: for every band entry (i >= j) its terms A_pi A_qj M_pq
-  // over the rows p, q of one block (p = q for zero and nonneg rows).  Every
-  // zero row has the same M = 1/delta, so their products are summed per entry
-  // here (in row order) into one term on M[0]; the other blocks' terms follow
-  // in block order, grouped by entry with a stable counting sort.
+  // A'MA: every zero row has the same M = 1/delta, so their products are
+  // summed per band entry here (in row order) into Zband; the nonneg rows' and
+  // cones' products A_pi A_qj M_pq (p = q for a nonneg row) are listed per
+  // band entry, only for the entries that have any (te), in block order
+  // within an entry (a stable counting sort)
   {
     struct Term {
       int32_t e, mi;
       double c;
     };
     const size_t ne = (size_t)n * W;
-    std::vector<double> zsum(P.nz > 0 ? ne : 0, 0.0);
-    std::vector<char> ztouch(P.nz > 0 ? ne : 0, 0);
+    P.Zband.assign(ne, 0.0);
     std::vector<Term> terms;
-    P.trp.assign(ne + 1, 0);
+    std::vector<int32_t> cnt(ne, 0);
     for (int32_t bk = 0; bk < nblk; ++bk) {
       int32_t r0, r1;
       block_rows(bk, &r0, &r1);
@@ -2402,11 +2401,10 @@ bool wave_plan(const hc_solver* S, WavePlan* out, std::string* why) {
           for (int32_t kb = P.Arp[r0]; kb <= ka; ++kb) {
             const int32_t e = P.Aci[kb] * W + (i - P.Aci[kb]);
             if (zero) {
-              zsum[e] += va * P.Av[kb];
-              ztouch[e] = 1;
+              P.Zband[e] += va * P.Av[kb];
             } else {
               terms.push_back(Term{e, bk, va * P.Av[kb]});
-              P.trp[e + 1]++;
+              cnt[e]++;
             }
           }
         }
@@ -2422,25 +2420,23 @@ bool wave_plan(const hc_solver* S, WavePlan* out, std::string* why) {
               if (i < j) continue;
               const int32_t e = j * W + (i - j);
               terms.push_back(Term{e, mo + (p - r0) * d + (q2 - r0), P.Av[ka] * P.Av[kb]});
-              P.trp[e + 1]++;
+              cnt[e]++;
             }
     }
-    for (size_t e = 0; e < ne; ++e) {
-      if (P.nz > 0 && ztouch[e]) P.trp[e + 1]++;
-      P.trp[e + 1] += P.trp[e];
-    }
-    P.tm.resize(P.trp[ne]);
-    P.tc.resize(P.trp[ne]);
+    std::vector<int32_t> slot(ne, -1);
+    P.te.clear();
+    P.trp.assign(1, 0);
+    for (size_t e = 0; e < ne; ++e)
+      if (cnt[e]) {
+        slot[e] = (int32_t)P.te.size();
+        P.te.push_back((int32_t)e);
+        P.trp.push_back(P.trp.back() + cnt[e]);
+      }
+    P.tm.resize(terms.size());
+    P.tc.resize(terms.size());
     std::vector<int32_t> fill(P.trp.begin(), P.trp.end() - 1);
-    if (P.nz > 0)
-      for (size_t e = 0; e < ne; ++e)
-        if (ztouch[e]) {
-          const int32_t o = fill[e]++;
-          P.tm[o] = 0;
-          P.tc[o] = zsum[e];
-        }
     for (const Term& tt : terms) {
-      const int32_t o = fill[tt.e]++;
+      const int32_t o = fill[slot[tt.e]]++;
       P.tm[o] = tt.mi;
       P.tc[o] = tt.c;
     }

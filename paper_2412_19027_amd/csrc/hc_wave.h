@@ -38,8 +38,10 @@ struct WavePlan {
   std::vector<int32_t> Arp, Aci, Atrp, Atci, Prp, Pci;
   std::vector<double> Av, Atv, Pv, q, b, D, E;
   std::vector<double> Pband;             // P in band storage (n x (w + 1), column-major)
-  std::vector<int32_t> trp, tm;          // A'MA gather plan: per band entry its terms,
-  std::vector<double> tc;                // each coefficient A_a A_b times M[tm]
+  std::vector<double> Zband;             // sum over zero rows of A_r'A_r (their M is 1/delta), same storage
+  std::vector<int32_t> te, trp, tm;      // A'MA terms of the nonneg rows and cones: the band entries
+  std::vector<double> tc;                // that have any (te), per such entry its terms (trp),
+                                         // each a coefficient A_a A_b times M[tm]
   std::vector<int32_t> colperm;          // band column -> user column
   std::vector<int32_t> rowperm;          // engine row -> user row
   double cscale = 1, bnorm = 0, qnorm = 0, maxPdiag = 0;
@@ -57,11 +59,11 @@ void set_last_error(const std::string& msg);
 // device view of one slot (pointers into its blob)
 struct WaveDesc {
   int32_t n, m, w, W, nz, nn, nsoc, mtot;
-  int32_t ir_max, max_iter, mixed, pad_;
+  int32_t ir_max, max_iter, mixed, nte;   // nte: band entries with nonneg/cone terms
   double cscale, bnorm, qnorm, maxPdiag, nu1;
   double eps_feas, eps_inf, static_reg, dyn_reg, ir_abstol, ir_reltol, step_fraction;
-  const int32_t *Arp, *Aci, *Atrp, *Atci, *Prp, *Pci, *trp, *tm, *soc_off, *soc_moff, *colperm, *rowperm;
-  const double *Av, *Atv, *Pv, *q, *b, *D, *E, *Pband, *tc;
+  const int32_t *Arp, *Aci, *Atrp, *Atci, *Prp, *Pci, *te, *trp, *tm, *soc_off, *soc_moff, *colperm, *rowperm;
+  const double *Av, *Atv, *Pv, *q, *b, *D, *E, *Pband, *Zband, *tc;
   double* v;                      // WV_COUNT work vectors of max(n, m) doubles
   double *Sb, *dinv, *hst, *hdiag, *Mv, *sc;
   float *Sb32, *dinv32, *f32;     // mixed precision only
@@ -78,10 +80,14 @@ enum WavePhase { PH_NEW = 0, PH_RUN = 1, PH_DONE = 2 };
 // lays the slot out in `blob` (device memory of plan.blob_bytes()), uploads
 // the plan's data on `st` and fills `desc` (host copy of the descriptor)
 void wave_upload(const WavePlan& plan, void* blob, WaveDesc* desc, hipStream_t st);
-// one interior-point iteration (or the initial point) of every active slot:
-// descs[i] for i < nslots with active[i] != 0; status[i] receives the
-// slot's phase after the tick (PH_DONE when its solve has ended)
-void wave_tick(const WaveDesc* descs, const int32_t* active, int nslots, int32_t* status, hipStream_t st);
+// interior-point iterations (the first starting from the initial point) of
+// every active slot: descs[i] for i < nslots with active[i] != 0.  Each slot
+// runs at least one iteration and then more while the next one is expected to
+// end within *budget (device scalar, 10 ns clock ticks from the launch);
+// status[i] receives the slot's phase after the tick (PH_DONE when its solve
+// has ended)
+void wave_tick(const WaveDesc* descs, const int32_t* active, int nslots, int32_t* status, const int64_t* budget,
+               hipStream_t st);
 // result of a finished slot (reads its scalars; host copies)
 void wave_result(const WaveDesc& desc, const WavePlan& plan, hc_info* info, double* x, double* s, double* z,
                  hipStream_t st);

@@ -13,6 +13,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 
 namespace hc {
@@ -29,6 +30,23 @@ enum WaveVec {
 };
 
 __device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+
+// Values the whole wave shares, made visibly uniform (scalar registers, scalar
+// branches), and pointers into the slot's blob as global-memory pointers
+// (global loads count only against the vector-memory counter, so LDS waits do
+// not wait for them and loads issued ahead stay in flight).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+using lptr = __attribute__((address_space(3))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gp(T* p) {
+  const unsigned long long u = (unsigned long long)p;
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return (gptr<T>)(((unsigned long long)hi << 32) | lo);
+}
 
 // the wave's own global-memory writes are visible to all its lanes after this
 __device__ __forceinline__ void gsync() { __syncthreads(); }
@@ -54,53 +72,134 @@ __device__ __forceinline__ double wmin(double v) {
 }
 
 // ---------------------------------------------------------------- vectors
-__device__ void v_fill(int n, double a, double* y) {
+// Each lane walks its elements four at a time, the loads of a group issued
+// together, so a wave keeps several memory accesses in flight per lane (one
+// wave per problem has no other source of memory parallelism).
+constexpr int UN = 4;
+
+__device__ void v_fill(int n_, double a, double* y_) {
+  const int n = uni(n_);
+  const auto y = gp(y_);
   for (int i = lane_id(); i < n; i += WL) y[i] = a;
   gsync();
 }
-__device__ void v_copy(int n, const double* x, double* y) {
-  for (int i = lane_id(); i < n; i += WL) y[i] = x[i];
-  gsync();
-}
 // o = a x + b y + c z (y, z optional)
-__device__ void v_lin(int n, double a, const double* x, double b, const double* y, double c, const double* z,
-                      double* o) {
-  for (int i = lane_id(); i < n; i += WL) {
-    double v = a * x[i];
-    if (y) v += b * y[i];
-    if (z) v += c * z[i];
-    o[i] = v;
+__device__ void v_lin(int n_, double a, const double* x_, double b, const double* y_, double c, const double* z_,
+                      double* o_) {
+  const int n = uni(n_);
+  const auto x = gp(x_), y = gp(y_), z = gp(z_);
+  const auto o = gp(o_);
+  for (int i0 = lane_id(); i0 < n; i0 += UN * WL) {
+    double xv[UN], yv[UN], zv[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int i = i0 + u * WL;
+      xv[u] = i < n ? x[i] : 0.0;
+      yv[u] = (y && i < n) ? y[i] : 0.0;
+      zv[u] = (z && i < n) ? z[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int i = i0 + u * WL;
+      double v = a * xv[u];
+      if (y) v += b * yv[u];
+      if (z) v += c * zv[u];
+      if (i < n) o[i] = v;
+    }
   }
   gsync();
 }
+__device__ void v_copy(int n, const double* x, double* y) { v_lin(n, 1.0, x, 0.0, nullptr, 0.0, nullptr, y); }
 // y = a x + b y
-__device__ void v_axpby(int n, double a, const double* x, double b, double* y) {
-  for (int i = lane_id(); i < n; i += WL) y[i] = a * x[i] + b * y[i];
+__device__ void v_axpby(int n_, double a, const double* x_, double b, double* y_) {
+  const int n = uni(n_);
+  const auto x = gp(x_);
+  const auto y = gp(y_);
+  for (int i0 = lane_id(); i0 < n; i0 += UN * WL) {
+    double xv[UN], yv[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int i = i0 + u * WL;
+      xv[u] = i < n ? x[i] : 0.0;
+      yv[u] = i < n ? y[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int i = i0 + u * WL;
+      if (i < n) y[i] = a * xv[u] + b * yv[u];
+    }
+  }
   gsync();
 }
-__device__ double v_dot(int n, const double* x, const double* y) {
+__device__ double v_dot(int n_, const double* x_, const double* y_) {
+  const int n = uni(n_);
+  const auto x = gp(x_), y = gp(y_);
   double acc = 0.0;
-  for (int i = lane_id(); i < n; i += WL) acc += x[i] * y[i];
+  for (int i0 = lane_id(); i0 < n; i0 += UN * WL) {
+    double xv[UN], yv[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int i = i0 + u * WL;
+      xv[u] = i < n ? x[i] : 0.0;
+      yv[u] = i < n ? y[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) acc += xv[u] * yv[u];
+  }
   return wsum(acc);
 }
 // max |(x + yc y) w| (divide: / w); w and y optional
-__device__ double v_maxabs(int n, const double* x, const double* w = nullptr, bool divide = false,
-                           const double* y = nullptr, double yc = 0.0) {
+__device__ double v_maxabs(int n_, const double* x_, const double* w_ = nullptr, bool divide = false,
+                           const double* y_ = nullptr, double yc = 0.0) {
+  const int n = uni(n_);
+  const auto x = gp(x_), w = gp(w_), y = gp(y_);
   double acc = 0.0;
-  for (int i = lane_id(); i < n; i += WL) {
-    double v = x[i];
-    if (y) v += yc * y[i];
-    if (w) v = divide ? v / w[i] : v * w[i];
-    acc = nanmax(acc, fabs(v));
+  for (int i0 = lane_id(); i0 < n; i0 += UN * WL) {
+    double xv[UN], yv[UN], wv[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int i = i0 + u * WL;
+      xv[u] = i < n ? x[i] : 0.0;
+      yv[u] = (y && i < n) ? y[i] : 0.0;
+      wv[u] = (w && i < n) ? w[i] : 1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      double v = xv[u];
+      if (y) v += yc * yv[u];
+      if (w) v = divide ? v / wv[u] : v * wv[u];
+      acc = nanmax(acc, fabs(v));
+    }
   }
   return wmax(acc);
 }
-// y = alpha A x + beta y (CSR, lane per row; beta = 0 does not read y)
-__device__ void spmv(int rows, const int32_t* rp, const int32_t* ci, const double* va, const double* x, double* y,
-                     double alpha, double beta) {
+// y = alpha A x + beta y (CSR, lane per row; beta = 0 does not read y); a
+// row's entries are taken four at a time (their column indices and values
+// loaded together, then the four gathers of x), summed in order
+__device__ void spmv(int rows_, const int32_t* rp_, const int32_t* ci_, const double* va_, const double* x_,
+                     double* y_, double alpha, double beta) {
+  const int rows = uni(rows_);
+  const auto rp = gp(rp_), ci = gp(ci_);
+  const auto va = gp(va_), x = gp(x_);
+  const auto y = gp(y_);
   for (int r = lane_id(); r < rows; r += WL) {
+    const int k0 = rp[r], k1 = rp[r + 1];
     double acc = 0.0;
-    for (int k = rp[r]; k < rp[r + 1]; ++k) acc += va[k] * x[ci[k]];
+    int k = k0;
+    for (; k + UN <= k1; k += UN) {
+      int cc[UN];
+      double aa[UN], xx[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        cc[u] = ci[k + u];
+        aa[u] = va[k + u];
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u) xx[u] = x[cc[u]];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) acc += aa[u] * xx[u];
+    }
+    for (; k < k1; ++k) acc += va[k] * x[ci[k]];
     y[r] = (beta == 0.0) ? alpha * acc : alpha * acc + beta * y[r];
   }
   gsync();
@@ -294,12 +393,45 @@ __device__ void c_add_e(const WaveDesc& D, double a, double* v) {
 }
 
 // ---------------------------------------------------------------- band Cholesky and solves
+// lane k's value in every lane (k uniform)
+__device__ __forceinline__ float wget(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double wget(double v, int k) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, k);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), k);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// lane t receives lane t + 1's value, lane 63 receives 0 (DPP wavefront shift)
+__device__ __forceinline__ int wshl1_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ float wshl1(float v) { return __int_as_float(wshl1_i(__float_as_int(v))); }
+__device__ __forceinline__ double wshl1(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)wshl1_i((int)(unsigned)u);
+  const unsigned hi = (unsigned)wshl1_i((int)(unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // S in band storage: column j holds S(j + t, j), t = 0..w, at Sb[j W + t].
 // In place: L (the diagonal L_jj at t = 0) and dinv[j] = 1 / L_jj.  A pivot
-// that is not positive is replaced by `fix` and counted.
+// that is not positive is replaced by `fix` and counted.  Blocked by PB
+// columns: the rows a block's columns reach (j0 .. j0 + PB - 1 + w) sit in a
+// circular LDS window (row i at i mod WB, entry (i, c) at column slot
+// c mod WB).  Lane r takes row j0 + r of the block's columns into registers,
+// the PB columns are factored there (pivots and multipliers exchanged by
+// readlane), the block's L goes out to Sb and to an LDS panel, and each lane
+// then applies the block's rank-PB update to the rest of its row in the
+// window.  Every entry receives its updates in column order, as in the
+// column-by-column algorithm.
 template <typename T>
-__device__ int band_cholesky(T* __restrict__ Sb, T* __restrict__ dinv, int n, int w, T fix, T* win, T* lcol) {
-  constexpr int WB = WAVE_WB, PB = WAVE_PB, LD = WAVE_WB + 1;
+__device__ int band_cholesky(T* Sb_, T* dinv_, int n_, int w_, T fix, T* win_) {
+  constexpr int WB = WAVE_WB, PB = WAVE_PB, LD = WAVE_WB + 1, PLD = sizeof(T) == 8 ? 10 : 12;
+  const lptr<T> win = (lptr<T>)win_;   // the kernel's LDS array: window, then panel
+  const lptr<T> pl = win + WB * LD;    // row r of the block's columns of L (PB entries, stride PLD)
+  const auto Sb = gp(Sb_);
+  const auto dinv = gp(dinv_);
+  const int n = uni(n_), w = uni(w_);
   const int lane = lane_id();
   const int W = w + 1;
   int hits = 0;
@@ -308,48 +440,76 @@ __device__ int band_cholesky(T* __restrict__ Sb, T* __restrict__ dinv, int n, in
     if (lane <= w && i - lane >= 0) win[(i & (WB - 1)) * LD + ((i - lane) & (WB - 1))] = Sb[(size_t)(i - lane) * W + lane];
   lsync();
   for (int j0 = 0; j0 < n; j0 += PB) {
-    // rows needed by the next block's steps, fetched now
+    // rows entering the window after this block, fetched now
     T pf[PB];
 #pragma unroll
     for (int s = 0; s < PB; ++s) {
       const int i = j0 + w + PB + s;
       pf[s] = (lane <= w && i < n && i - lane >= 0) ? Sb[(size_t)(i - lane) * W + lane] : T(0);
     }
+    const int nb = min(PB, n - j0);
+    const int r = lane, i = j0 + lane;
+    const bool live = r < nb + w && i < n;   // a row the block's columns reach
+    const lptr<T> row = win + (i & (WB - 1)) * LD;
+    T P[PB];
 #pragma unroll
-    for (int s = 0; s < PB; ++s) {
-      const int j = j0 + s;
-      if (j < n) {
-        const int jc = j & (WB - 1);
-        T d = win[jc * LD + jc];
+    for (int k = 0; k < PB; ++k) {
+      const T v = row[(j0 + k) & (WB - 1)];
+      P[k] = (live && k < nb && k <= r && r - k <= w) ? v : T(0);
+    }
+    // the block's columns, one after another
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+      if (k < nb) {
+        T d = wget(P[k], k);
         if (!(d > T(0))) {
           d = fix;
           ++hits;
         }
         const T ljj = sqrt(d);
         const T inv = T(1) / ljj;
-        const int rows = min(w, n - 1 - j);
-        T lk = T(0);
-        if (lane >= 1 && lane <= rows) {
-          lk = win[((j + lane) & (WB - 1)) * LD + jc] * inv;
-          lcol[lane] = lk;
-          Sb[(size_t)j * W + lane] = lk;
+        if (lane == 0) dinv[j0 + k] = inv;
+        P[k] = (r == k) ? ljj : (r > k ? P[k] * inv : T(0));
+#pragma unroll
+        for (int c = k + 1; c < PB; ++c) {
+          const T lc = wget(P[k], c);
+          if (c < nb && r >= c) P[c] -= P[k] * lc;
         }
-        if (lane == 0) {
-          Sb[(size_t)j * W] = ljj;
-          dinv[j] = inv;
-        }
-        lsync();
-        if (lane >= 1 && lane <= rows) {
-          T* row = win + ((j + lane) & (WB - 1)) * LD;
-          for (int c = 1; c <= lane; ++c) row[(j + c) & (WB - 1)] -= lk * lcol[c];
-        }
-        lsync();
       }
     }
 #pragma unroll
+    for (int k = 0; k < PB; ++k) {
+      if (live && k < nb && r >= k && r - k <= w) Sb[(size_t)(j0 + k) * W + (r - k)] = P[k];
+      pl[r * PLD + k] = P[k];
+    }
+    lsync();
+    // rank-PB update of rows j0 + nb .. j0 + nb + w - 1 at columns from j0 + nb
+    // on: entry (i, j0 + c) for c = r - dd, two at a time (reads first)
+    const bool upd = live && r >= nb;
+    for (int dd = 0; dd <= w; dd += 2) {
+      const int c0 = r - dd, c1 = r - dd - 1;
+      const bool u0 = upd && c0 >= nb, u1 = upd && c1 >= nb && dd + 1 <= w;
+      const lptr<T> p0 = pl + (u0 ? c0 : 0) * PLD;
+      const lptr<T> p1 = pl + (u1 ? c1 : 0) * PLD;
+      T a0 = row[(j0 + c0) & (WB - 1)], a1 = row[(j0 + c1) & (WB - 1)];
+      T q0[PB], q1[PB];
+#pragma unroll
+      for (int k = 0; k < PB; ++k) {
+        q0[k] = p0[k];
+        q1[k] = p1[k];
+      }
+#pragma unroll
+      for (int k = 0; k < PB; ++k) {
+        a0 -= P[k] * q0[k];
+        a1 -= P[k] * q1[k];
+      }
+      if (u0) row[(j0 + c0) & (WB - 1)] = a0;
+      if (u1) row[(j0 + c1) & (WB - 1)] = a1;
+    }
+#pragma unroll
     for (int s = 0; s < PB; ++s) {
-      const int i = j0 + w + PB + s;
-      if (lane <= w && i < n && i - lane >= 0) win[(i & (WB - 1)) * LD + ((i - lane) & (WB - 1))] = pf[s];
+      const int i2 = j0 + w + PB + s;
+      if (lane <= w && i2 < n && i2 - lane >= 0) win[(i2 & (WB - 1)) * LD + ((i2 - lane) & (WB - 1))] = pf[s];
     }
     lsync();
   }
@@ -357,85 +517,99 @@ __device__ int band_cholesky(T* __restrict__ Sb, T* __restrict__ dinv, int n, in
   return hits;
 }
 
-// L y = b then L' x = y, in place on b (global, n entries)
+// L y = b then L' x = y, in place on b (global, n entries).  Both sweeps keep
+// the w + 1 pending entries in registers (lane t: the entry t places ahead of
+// the current column), take the current one from lane 0, subtract its
+// multiples and shift the window down one lane; the next SB columns of L, the
+// reciprocal pivots and the entries entering the window are loaded one block
+// ahead, and each block's results are stored together at its end.
+constexpr int SB = 32;
 template <typename T>
-__device__ void band_solve(const T* __restrict__ L, const T* __restrict__ dinv, int n, int w, T* __restrict__ b,
-                           T* buf) {
-  constexpr int WB = WAVE_WB, PB = WAVE_PB;
+struct SweepBlock {
+  T l[SB];   // lane t: the multiplier of column (row) s for the entry t places away
+  T dv;      // lane s: 1 / L_jj of the block's step s
+  T nb;      // lane s: the entry entering the window after step s
+};
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void sweep_load(SweepBlock<T>& B, gptr<const T> L, gptr<const T> dinv, gptr<T> b, int n,
+                                           int w, int j0) {
   const int lane = lane_id();
   const int W = w + 1;
-  // forward: column j updates rows j + 1 .. j + w
-  if (lane < min(n, w + PB)) buf[lane & (WB - 1)] = b[lane];
-  lsync();
-  for (int j0 = 0; j0 < n; j0 += PB) {
-    T lc[PB], dv[PB];
-    T bn = T(0);
+  // every load is issued (masked lanes read entry 0), so the wait for one
+  // block never waits for the block loaded after it
 #pragma unroll
-    for (int s = 0; s < PB; ++s) {
-      const int j = j0 + s;
-      lc[s] = (j < n && lane >= 1 && lane <= w && j + lane < n) ? L[(size_t)j * W + lane] : T(0);
-      dv[s] = (j < n) ? dinv[j] : T(0);
-    }
-    {
-      const int i = j0 + w + PB + lane;
-      if (lane < PB && i < n) bn = b[i];
-    }
+  for (int s = 0; s < SB; ++s) {
+    const int j = FWD ? j0 + s : j0 - s;
+    const bool ok = lane >= 1 && lane <= w && (FWD ? j + lane < n : j - lane >= 0);
+    const T v = L[ok ? (FWD ? (size_t)j * W + lane : (size_t)(j - lane) * W + lane) : 0];
+    B.l[s] = ok ? v : T(0);
+  }
+  const int j = FWD ? j0 + lane : j0 - lane;
+  const bool okj = lane < SB && j >= 0 && j < n;
+  const T dv = dinv[okj ? j : 0];
+  B.dv = okj ? dv : T(0);
+  const int i = FWD ? j0 + lane + 1 + w : j0 - lane - 1 - w;
+  const bool oki = lane < SB && i >= 0 && i < n;
+  const T nb = b[oki ? i : 0];
+  B.nb = oki ? nb : T(0);
+}
+
+template <typename T, bool FWD>
+__device__ __forceinline__ void sweep_run(const SweepBlock<T>& B, T& r, gptr<T> b, int n, int w, int j0) {
+  const int lane = lane_id();
+  T out = T(0);
+  const int steps = FWD ? min(SB, n - j0) : min(SB, j0 + 1);
 #pragma unroll
-    for (int s = 0; s < PB; ++s) {
-      const int j = j0 + s;
-      if (j < n) {
-        const T yj = buf[j & (WB - 1)] * dv[s];
-        if (lane == 0) b[j] = yj;
-        if (lane >= 1 && lane <= w && j + lane < n) buf[(j + lane) & (WB - 1)] -= lc[s] * yj;
-        lsync();
-      }
+  for (int s = 0; s < SB; ++s) {
+    if (s < steps) {
+      const T y = wget(r, 0) * wget(B.dv, s);
+      if (lane == s) out = y;
+      r = wshl1(r - B.l[s] * y);
+      if (lane == w) r = wget(B.nb, s);
     }
-    {
-      const int i = j0 + w + PB + lane;
-      if (lane < PB && i < n) buf[i & (WB - 1)] = bn;
-    }
-    lsync();
+  }
+  const int j = FWD ? j0 + lane : j0 - lane;
+  if (lane < steps) b[j] = out;
+}
+
+template <typename T, bool FWD>
+__device__ void band_sweep(const T* L_, const T* dinv_, int n_, int w_, T* b_) {
+  const auto L = gp(L_), dinv = gp(dinv_);
+  const auto b = gp(b_);
+  const int n = uni(n_), w = uni(w_);
+  if (n <= 0) return;
+  const int lane = lane_id();
+  const int nblk = (n + SB - 1) / SB;
+  T r = T(0);
+  {
+    const int i = FWD ? lane : n - 1 - lane;
+    if (lane <= w && i >= 0 && i < n) r = b[i];
+  }
+  // block k starts at column k SB (forward) or n - 1 - k SB (backward)
+  auto start = [&](int k) { return FWD ? k * SB : n - 1 - k * SB; };
+  SweepBlock<T> A, C;
+  sweep_load<T, FWD>(A, L, dinv, b, n, w, start(0));
+  for (int k = 0; k < nblk; k += 2) {
+    sweep_load<T, FWD>(C, L, dinv, b, n, w, start(k + 1));
+    sweep_run<T, FWD>(A, r, b, n, w, start(k));
+    if (k + 1 >= nblk) break;
+    sweep_load<T, FWD>(A, L, dinv, b, n, w, start(k + 2));
+    sweep_run<T, FWD>(C, r, b, n, w, start(k + 1));
   }
   gsync();
-  // backward: row j of L (L(j, j - t), t = 1..w) updates rows j - 1 .. j - w
-  for (int t = lane; t < min(n, w + PB); t += WL) buf[(n - 1 - t) & (WB - 1)] = b[n - 1 - t];
-  lsync();
-  for (int j0 = n - 1; j0 >= 0; j0 -= PB) {
-    T lr[PB], dv[PB];
-    T bn = T(0);
-#pragma unroll
-    for (int s = 0; s < PB; ++s) {
-      const int j = j0 - s;
-      lr[s] = (j >= 0 && lane >= 1 && lane <= w && j - lane >= 0) ? L[(size_t)(j - lane) * W + lane] : T(0);
-      dv[s] = (j >= 0) ? dinv[j] : T(0);
-    }
-    {
-      const int i = j0 - w - PB - lane;
-      if (lane < PB && i >= 0) bn = b[i];
-    }
-#pragma unroll
-    for (int s = 0; s < PB; ++s) {
-      const int j = j0 - s;
-      if (j >= 0) {
-        const T xj = buf[j & (WB - 1)] * dv[s];
-        if (lane == 0) b[j] = xj;
-        if (lane >= 1 && lane <= w && j - lane >= 0) buf[(j - lane) & (WB - 1)] -= lr[s] * xj;
-        lsync();
-      }
-    }
-    {
-      const int i = j0 - w - PB - lane;
-      if (lane < PB && i >= 0) buf[i & (WB - 1)] = bn;
-    }
-    lsync();
-  }
-  gsync();
+}
+
+template <typename T>
+__device__ void band_solve(const T* L, const T* dinv, int n, int w, T* b) {
+  band_sweep<T, true>(L, dinv, n, w, b);
+  band_sweep<T, false>(L, dinv, n, w, b);
 }
 
 // ---------------------------------------------------------------- one problem
 struct Wave {
   const WaveDesc& D;
-  double* lds;        // WAVE_WB * (WAVE_WB + 1) + 2 WAVE_WB doubles
+  double* lds;        // WAVE_WB * (WAVE_WB + 1) + 640 doubles: the factorisation's window and panel
   int L;              // max(n, m)
   double tau, kappa, delta, sdmax, xPx;
   bool use64;
@@ -443,19 +617,40 @@ struct Wave {
 
   __device__ double* V(int k) const { return D.v + (size_t)k * L; }
 
-  // S = P + delta I + A'MA into band storage; returns max |S_jj|
+  // S = P + delta I + A'MA into band storage (FP64; FP32 copy when low);
+  // returns max |S_jj|.  The zero rows' part is Zband / delta (their M), the
+  // rest a short list of entries with their nonneg-row and cone terms.
   __device__ double assemble(bool low) {
     const int W = D.W, ne = D.n * W;
-    double dmax = 0.0;
-    for (int e = lane_id(); e < ne; e += WL) {
-      const bool diag = (e % W) == 0;
-      double v = D.Pband[e] + (diag ? delta : 0.0);
-      for (int t = D.trp[e]; t < D.trp[e + 1]; ++t) v += D.tc[t] * D.Mv[D.tm[t]];
-      if (low) D.Sb32[e] = (float)v;
-      else D.Sb[e] = v;
-      if (diag) dmax = nanmax(dmax, fabs(v));
+    const double inv_delta = 1.0 / delta;
+    for (int e0 = lane_id(); e0 < ne; e0 += UN * WL) {
+      double pv[UN], zv[UN];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int e = e0 + u * WL;
+        pv[u] = e < ne ? D.Pband[e] : 0.0;
+        zv[u] = e < ne ? D.Zband[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        const int e = e0 + u * WL;
+        if (e < ne) D.Sb[e] = pv[u] + ((e % W) == 0 ? delta : 0.0) + zv[u] * inv_delta;
+      }
     }
     gsync();
+    for (int k = lane_id(); k < D.nte; k += WL) {
+      const int e = D.te[k];
+      double v = D.Sb[e];
+      for (int t2 = D.trp[k]; t2 < D.trp[k + 1]; ++t2) v += D.tc[t2] * D.Mv[D.tm[t2]];
+      D.Sb[e] = v;
+    }
+    gsync();
+    double dmax = 0.0;
+    for (int j = lane_id(); j < D.n; j += WL) dmax = nanmax(dmax, fabs(D.Sb[(size_t)j * W]));
+    if (low) {
+      for (int e = lane_id(); e < ne; e += WL) D.Sb32[e] = (float)D.Sb[e];
+      gsync();
+    }
     return wmax(dmax);
   }
 
@@ -474,10 +669,9 @@ struct Wave {
     const double dmax = assemble(low);
     if (low) {
       sdmax = dmax;
-      hits += band_cholesky<float>(D.Sb32, D.dinv32, D.n, D.w, (float)delta, (float*)lds,
-                                   (float*)lds + WAVE_WB * (WAVE_WB + 1));
+      hits += band_cholesky<float>(D.Sb32, D.dinv32, D.n, D.w, (float)delta, (float*)lds);
     } else {
-      hits += band_cholesky<double>(D.Sb, D.dinv, D.n, D.w, delta, lds, lds + WAVE_WB * (WAVE_WB + 1));
+      hits += band_cholesky<double>(D.Sb, D.dinv, D.n, D.w, delta, lds);
     }
     facts++;
   }
@@ -489,12 +683,12 @@ struct Wave {
       sc = (sc > 0.0) ? sc : 1.0;
       for (int i = lane_id(); i < D.n; i += WL) D.f32[i] = (float)(u[i] / sc);
       gsync();
-      band_solve<float>(D.Sb32, D.dinv32, D.n, D.w, D.f32, (float*)lds);
+      band_solve<float>(D.Sb32, D.dinv32, D.n, D.w, D.f32);
       for (int i = lane_id(); i < D.n; i += WL) x[i] = (double)D.f32[i] * sc;
       gsync();
     } else {
       v_copy(D.n, u, x);
-      band_solve<double>(D.Sb, D.dinv, D.n, D.w, x, lds);
+      band_solve<double>(D.Sb, D.dinv, D.n, D.w, x);
     }
   }
 
@@ -738,12 +932,19 @@ struct Wave {
   }
 };
 
+// Passes of the Algorithm 1 loop for one slot until its solve ends or the
+// next pass would overrun `budget` (wall-clock ticks of 10 ns from the start
+// of the launch, judged by the length of the pass just done); at least one
+// pass.  The state between passes is the same as between launches, so the
+// result does not depend on how the passes fall into launches.
 __global__ __launch_bounds__(WL) void k_wave_tick(const WaveDesc* __restrict__ descs,
                                                  const int32_t* __restrict__ active, int nslots,
-                                                 int32_t* __restrict__ status) {
-  __shared__ double lds[WAVE_WB * (WAVE_WB + 1) + 2 * WAVE_WB];
+                                                 int32_t* __restrict__ status, const int64_t* __restrict__ budget) {
+  __shared__ __align__(16) double lds[WAVE_WB * (WAVE_WB + 1) + 64 * 10];
   const int slot = blockIdx.x;
   if (slot >= nslots || !active[slot]) return;
+  const uint64_t t_start = wall_clock64();
+  const int64_t limit = *budget;
   const WaveDesc D = descs[slot];
   double* sc = D.sc;
   int phase = (int)sc[SC_PHASE];
@@ -757,10 +958,10 @@ __global__ __launch_bounds__(WL) void k_wave_tick(const WaveDesc* __restrict__ d
   w.fallbacks = (int64_t)sc[SC_FALLBACKS];
   w.irs = (int64_t)sc[SC_IRS];
   w.facts = (int64_t)sc[SC_FACTS];
-  w.delta = 0.0;
-  w.use64 = false;
   int k = (int)sc[SC_K], iters = (int)sc[SC_ITERS];
   if (phase == PH_NEW) {
+    w.delta = 0.0;
+    w.use64 = false;
     w.sdmax = 0.0;
     w.init_point();
     k = 0;
@@ -769,27 +970,38 @@ __global__ __launch_bounds__(WL) void k_wave_tick(const WaveDesc* __restrict__ d
     w.tau = sc[SC_TAU];
     w.kappa = sc[SC_KAPPA];
   }
-  // one pass of the Algorithm 1 loop
-  const Wave::Resid R = w.residuals();
-  w.xPx = R.xPx;
-  int st = w.check(R);
-  const double mu = (R.sz + w.kappa * w.tau) / D.nu1;
+  int st = 0;
+  double mu = 0.0;
   bool done = false;
-  if (st) {
-    done = true;
-  } else if (k == D.max_iter) {
-    st = HC_STATUS_MAX_ITER;
-    done = true;
-  } else {
-    st = w.iterate(R);
-    iters++;
+  for (;;) {
+    const uint64_t t_pass = wall_clock64();
+    w.delta = 0.0;
+    w.use64 = false;
+    // one pass of the Algorithm 1 loop
+    const Wave::Resid R = w.residuals();
+    w.xPx = R.xPx;
+    st = w.check(R);
+    mu = (R.sz + w.kappa * w.tau) / D.nu1;
     if (st) {
-      const Wave::Resid R2 = w.residuals();
-      w.check(R2);
       done = true;
+    } else if (k == D.max_iter) {
+      st = HC_STATUS_MAX_ITER;
+      done = true;
+    } else {
+      st = w.iterate(R);
+      iters++;
+      if (st) {
+        const Wave::Resid R2 = w.residuals();
+        w.check(R2);
+        done = true;
+      }
     }
+    k++;
+    if (done) break;
+    const uint64_t t_now = wall_clock64();
+    const int64_t elapsed = (int64_t)(t_now - t_start), pass = (int64_t)(t_now - t_pass);
+    if (__builtin_amdgcn_readfirstlane((int)(elapsed + pass >= limit))) break;
   }
-  k++;
   if (done) w.write_result(st);
   if (threadIdx.x == 0) {
     sc[SC_TAU] = w.tau;
@@ -842,6 +1054,7 @@ void layout(const WavePlan& P, Carve& c, WaveDesc* d, hipStream_t st) {
   d->ir_max = P.st.ir_max;
   d->max_iter = P.st.max_iter;
   d->mixed = P.mixed ? 1 : 0;
+  d->nte = (int32_t)P.te.size();
   d->cscale = P.cscale;
   d->bnorm = P.bnorm;
   d->qnorm = P.qnorm;
@@ -868,6 +1081,8 @@ void layout(const WavePlan& P, Carve& c, WaveDesc* d, hipStream_t st) {
   d->D = put(c, P.D, st);
   d->E = put(c, P.E, st);
   d->Pband = put(c, P.Pband, st);
+  d->Zband = put(c, P.Zband, st);
+  d->te = put(c, P.te, st);
   d->trp = put(c, P.trp, st);
   d->tm = put(c, P.tm, st);
   d->tc = put(c, P.tc, st);
@@ -909,9 +1124,10 @@ void wave_upload(const WavePlan& plan, void* blob, WaveDesc* desc, hipStream_t s
   HC_HIP(hipMemcpyAsync(desc->sc, sc.data(), SC_COUNT * sizeof(double), hipMemcpyHostToDevice, st));
 }
 
-void wave_tick(const WaveDesc* descs, const int32_t* active, int nslots, int32_t* status, hipStream_t st) {
+void wave_tick(const WaveDesc* descs, const int32_t* active, int nslots, int32_t* status, const int64_t* budget,
+               hipStream_t st) {
   if (nslots <= 0) return;
-  hipLaunchKernelGGL(k_wave_tick, dim3((unsigned)nslots), dim3(WL), 0, st, descs, active, nslots, status);
+  hipLaunchKernelGGL(k_wave_tick, dim3((unsigned)nslots), dim3(WL), 0, st, descs, active, nslots, status, budget);
   HC_LAUNCH_CHECK();
 }
 
@@ -985,6 +1201,10 @@ int32_t hc_solve_batch(hc_solver* const* handles, int32_t count, void* stream, i
     WaveDesc* ddesc = (WaveDesc*)aux;
     int32_t* dactive = (int32_t*)((char*)aux + (size_t)count * sizeof(WaveDesc));
     int32_t* dstatus = dactive + count;
+    // no time limit: every slot runs to the end of its solve in one launch
+    int64_t* dbudget = (int64_t*)(((uintptr_t)(dstatus + count) + 15) / 16 * 16);
+    const int64_t unlimited = INT64_MAX / 4;
+    HC_HIP(hipMemcpyAsync(dbudget, &unlimited, sizeof(int64_t), hipMemcpyHostToDevice, st));
     std::vector<WaveDesc> desc(count);
     const double t0 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
     for (int32_t i = 0; i < count; ++i) wave_upload(plans[i], mem + off[i], &desc[i], st);
@@ -994,7 +1214,7 @@ int32_t hc_solve_batch(hc_solver* const* handles, int32_t count, void* stream, i
     int max_ticks = 0;
     for (const WavePlan& p : plans) max_ticks = std::max(max_ticks, p.st.max_iter + 2);
     for (int tick = 0; tick < max_ticks; ++tick) {
-      wave_tick(ddesc, dactive, count, dstatus, st);
+      wave_tick(ddesc, dactive, count, dstatus, dbudget, st);
       HC_HIP(hipMemcpyAsync(stat.data(), dstatus, count * sizeof(int32_t), hipMemcpyDeviceToHost, st));
       HC_HIP(hipStreamSynchronize(st));
       bool all = true;
