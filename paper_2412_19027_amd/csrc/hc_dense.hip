@@ -204,40 +204,46 @@ __global__ __launch_bounds__(256) void k_chol_diag(T* __restrict__ A, int64_t ld
 // ---------------------------------------------------------------------------
 // TRSM: rows [r0, r1) of the 64 columns starting at c: A21 <- A21 * Linv'
 // ---------------------------------------------------------------------------
-// On MFMA with operands straight from global memory (Linv is 32 KB and stays
-// in cache): each wave takes 16 rows and all 64 columns (four 16 x 16 output
-// tiles, 16 k-steps of four).  No LDS and few registers, so a workgroup fits
-// beside a running trailing-update workgroup on the same CU instead of
-// waiting for one to finish: this kernel sits on the factorisation's critical
-// path while the trailing update runs.
+// On MFMA: each wave takes 16 rows and all 64 columns (four 16 x 16 output
+// tiles, 16 k-steps of four).  A wave's 16 x 64 block of A21 is loaded into
+// registers at once; Linv goes through an 8 KB LDS slice, the 16 rows of Linv
+// that one output tile needs, one tile after another.  With few registers and
+// 8 KB of LDS a workgroup fits beside a running trailing-update workgroup on
+// the same compute unit instead of waiting for one to finish: this kernel sits
+// on the factorisation's critical path while the trailing update runs.
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_trsm(
     T* __restrict__ A, int64_t ld, int64_t c, int64_t r0, int64_t r1, const T* __restrict__ Linv) {
   typedef typename Mfma<T>::acc_t acc_t;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ T Ls[BS][16];   // Ls[k][jj] = Linv[16 t + jj][k] for the current tile t
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t rb = r0 + (int64_t)blockIdx.x * BS + wave * 16;   // first row of this wave
   // operand lanes: A[i = lane % 16][k = lane / 16], B[k = lane / 16][j = lane % 16]
   const int64_t ra = std::min<int64_t>(rb + (lane & 15), r1 - 1);   // rows past r1 repeat the last one
   const T* pa = A + ra + (c + (lane >> 4)) * ld;
-  const T* pb = Linv + (lane & 15) + (lane >> 4) * BS;
-  acc_t acc[4];
+  T a[BS / 4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = acc_t{0, 0, 0, 0};
-#pragma unroll 2
-  for (int kk = 0; kk < BS; kk += 4) {
-    const T a = pa[(int64_t)kk * ld];
+  for (int q = 0; q < BS / 4; ++q) a[q] = pa[(int64_t)(4 * q) * ld];
+#pragma unroll 1
+  for (int t = 0; t < 4; ++t) {
+    __syncthreads();   // the previous slice has been read
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::op(a, pb[16 * t + kk * BS], acc[t]);
-  }
-  // X[i][j] = sum_k A[i][k] Linv[j][k]; stores after this wave's loads of the
-  // same rows (program order), other waves own other rows
+    for (int q = 0; q < BS * 16 / 256; ++q) {
+      const int e = tid + 256 * q;
+      Ls[e >> 4][e & 15] = Linv[(16 * t + (e & 15)) + (e >> 4) * BS];
+    }
+    __syncthreads();
+    acc_t acc = acc_t{0, 0, 0, 0};
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+    for (int q = 0; q < BS / 4; ++q) acc = Mfma<T>::op(a[q], Ls[4 * q + (lane >> 4)][lane & 15], acc);
+    // X[i][j] = sum_k A[i][k] Linv[j][k]; this wave loaded its rows above,
+    // other waves own other rows
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = rb + Mfma<T>::row(lane, r);
-      if (row < r1) A[row + (c + 16 * t + (lane & 15)) * ld] = acc[t][r];
+      if (row < r1) A[row + (c + 16 * t + (lane & 15)) * ld] = acc[r];
     }
+  }
 }
 
 // ---------------------------------------------------------------------------
