@@ -241,6 +241,29 @@ def run_served(count, precision="fp64", rate=2000.0, workers=4, slots=32, budget
         feeder_threads=feeders)
 
 
+def run_batch(count, precision="fp64", seed=0):
+    """The first `count` requests of the served stream solved together by one
+    hc_solve_batch call (one wave per problem, plain kernel launches, no
+    server): problems set up beforehand; solves/s of the call."""
+    import torch
+    from paper_2412_19027_amd import hipcone as HC
+    from paper_2412_19027_amd import workloads as W
+    probs = [W.mpc_socp(seed, i) for i in range(count)]
+    HC.solve_batch(probs[:8], precision=precision)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = HC.solve_batch(probs, precision=precision)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    statuses = {}
+    for r in res:
+        statuses[r["status_name"]] = statuses.get(r["status_name"], 0) + 1
+    return dict(workload=f"first {count} requests of the MPC stream (seed {seed}) in one hc_solve_batch call",
+                precision=precision, requests=count, wall_s=wall, solves_per_s=count / wall,
+                mean_iterations=sum(r["iterations"] for r in res) / count, statuses=statuses,
+                note="includes the call's host set-up of the batch (plans, uploads)")
+
+
 def run_sequential(count, seed=0):
     """The same MPC requests solved one after another by a plain FP64 solver
     (set-up, solve, results, release per request): the baseline the served
@@ -306,6 +329,56 @@ def run_parametric(count=50, T=100, nx=12, nu=6):
                 solved_fresh=solved_f)
 
 
+def _oracle_mpc(args):
+    """One MPC request solved by the oracle (worker process of the served
+    CPU baseline)."""
+    seed, i = args
+    from oracle import ipm
+    from paper_2412_19027_amd import workloads as W
+    r = ipm.solve(W.mpc_socp(seed, i))
+    return r.status == ipm.SOLVED
+
+
+def cpu_served_baseline(count=400, workers=16, rate=2000.0, seed=0):
+    """The oracle on the served stream: a pool of single-threaded worker
+    processes takes the first `count` MPC requests first come first served at
+    their Poisson arrival times; solves/s and latency from arrival to result."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    from paper_2412_19027_amd import workloads as W
+    arrivals = W.mpc_arrivals(seed, count, rate)
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as pool:
+            list(pool.map(_oracle_mpc, [(seed, i) for i in range(workers)]))   # start-up and imports
+            done_at = [0.0] * count
+            futs = []
+            t0 = time.perf_counter()
+            for i in range(count):
+                dt = arrivals[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                f = pool.submit(_oracle_mpc, (seed, i))
+                f.add_done_callback(lambda f, i=i: done_at.__setitem__(i, time.perf_counter() - t0))
+                futs.append(f)
+            solved = sum(f.result() for f in futs)
+            wall = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    lat = sorted(1e3 * (done_at[i] - arrivals[i]) for i in range(count))
+    return dict(value=count / wall, unit="solves/s", cores=workers, kind="oracle",
+                sample=f"the first {count} requests of the served MPC stream (seed {seed}, Poisson {rate:.0f}/s), "
+                       f"{workers} single-threaded oracle processes, first come first served",
+                p50_latency_ms=float(lat[count // 2]), p99_latency_ms=float(lat[min(count - 1, int(0.99 * count))]),
+                solved=solved)
+
+
 def cpu_baseline(prob):
     """The oracle as it stands, on one IPM iteration of the same problem
     (its setup and initial point are not timed)."""
@@ -341,6 +414,8 @@ def main():
     ap.add_argument("--sequential", type=int, default=200,
                     help="requests of the same stream solved one by one (plain FP64 baseline of the served form); "
                          "0 = skip")
+    ap.add_argument("--batch-only", type=int, default=0,
+                    help="solve the first N requests of the MPC stream in one batched call (FP64) and print its JSON")
     ap.add_argument("--workload-only", choices=OTHER_WORKLOADS,
                     help="run only this other configuration (one warm-up and one timed solve) and print its line")
     args = ap.parse_args()
@@ -351,6 +426,11 @@ def main():
     from paper_2412_19027_amd import workloads as W
     if args.workload_only:
         print(json.dumps(run_other_workloads(only=args.workload_only)))
+        if args.calibrate_copy:
+            calibrate_copy()
+        return
+    if args.batch_only > 0:
+        print(json.dumps(run_batch(args.batch_only)))
         return
     if args.served_only:
         sv = run_served(args.served, "fp64")
@@ -395,6 +475,8 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
     cpu = None if args.no_cpu_baseline else cpu_baseline(prob)
+    if cpu is not None and args.served > 0:
+        cpu["served"] = cpu_served_baseline()
     out = {
         "metric": METRIC,
         "value": main_run["iters"] / main_run["wall"],

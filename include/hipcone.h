@@ -174,7 +174,10 @@ typedef struct {
   int64_t gemm_launches;   /* lower-triangle entry updated)                          */
   int64_t fp64_fallbacks;  /* mixed mode: iterations refactored in FP64 because the
                               FP32-factor refinement left a residual above
-                              1e-6 (1 + |rhs|_inf) or not finite                 */
+                              1e-6 (1 + |rhs|_inf) or not finite; in a served
+                              result of the batched engine, plus one when the
+                              whole solve broke down in mixed precision and ran
+                              again in FP64 (iterations then count both runs) */
   int64_t n_leaves;        /* leaf blocks factored ahead of the tail               */
   int64_t leaf_columns;    /* columns inside leaf blocks (n = leaf_columns + n_ordered) */
   int64_t psd_gathered_rows; /* rows of PSD cones whose Schur blocks enter through

@@ -247,6 +247,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 }
 
 // ---------------------------------------------------------------------------
+// In-panel update after a TRSM: C -= A B' with K <= 64 (one 64-column block
+// of L), the shape of the TRSM so that it also fits beside a running
+// trailing-update workgroup: a workgroup takes 64 rows x 64 columns of C,
+// each wave 16 rows (its 16 x K block of A in registers) and four 16 x 16
+// tiles, B through an 8 KB LDS slice per tile.  Tiles strictly above the
+// global diagonal (C[0, 0] at global (gr, gc)) are skipped.  The products are
+// the same MFMA chain as the large update kernels' (k in steps of four).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_gemm_panel(
+    T* __restrict__ C, int64_t ldc, const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+    int64_t M, int64_t N, int K, int64_t gr, int64_t gc) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T Bs[BS][16];   // Bs[k][jj] = B[j0 + jj][k] for the current tile
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i_blk = (int64_t)blockIdx.x * BS, j_blk = (int64_t)blockIdx.y * BS;
+  if (gr + i_blk + BS - 1 < gc + j_blk) return;   // block strictly above the diagonal
+  const int64_t rb = i_blk + wave * 16;             // first row of this wave
+  const int64_t ra = std::min<int64_t>(rb + (lane & 15), M - 1);
+  const T* pa = A + ra;
+  T a[BS / 4];
+#pragma unroll
+  for (int q = 0; q < BS / 4; ++q) {
+    const int k = 4 * q + (lane >> 4);
+    const T v = pa[(int64_t)std::min(k, K - 1) * lda];
+    a[q] = k < K ? v : T(0);
+  }
+#pragma unroll 1
+  for (int t = 0; t < 4; ++t) {
+    const int64_t j0 = j_blk + 16 * t;
+    if (j0 >= N) break;
+    __syncthreads();   // the previous slice has been read
+#pragma unroll
+    for (int q = 0; q < BS * 16 / 256; ++q) {
+      const int e = tid + 256 * q, k = e >> 4, jj = e & 15;
+      const T v = B[std::min<int64_t>(j0 + jj, N - 1) + (int64_t)std::min(k, K - 1) * ldb];
+      Bs[k][jj] = k < K ? v : T(0);
+    }
+    __syncthreads();
+    if (gr + rb + 15 < gc + j0) continue;   // this wave's rows lie above the tile's columns
+    acc_t acc = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < BS / 4; ++q) acc = Mfma<T>::op(a[q], Bs[4 * q + (lane >> 4)][lane & 15], acc);
+    const int64_t j = j0 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = rb + Mfma<T>::row(lane, r);
+      if (i < M && j < N) C[i + j * ldc] -= acc[r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // C[i, j] += alpha * sum_k A[i, k] * B[j, k]  (i < M, j < N, k < K), all
 // column-major; 128 x 128 tiles of 4 waves, each wave 64 x 64 on 16 MFMA
 // accumulators.  `lower` skips tiles strictly above the global diagonal, whose
@@ -767,8 +820,15 @@ static void factor_panel(T* S, int64_t n, int64_t ld, T* Linv, double tol, doubl
                          (const T*)(Linv + (c / BS) * BS * BS));
       HC_LAUNCH_CHECK();
     }
-    if (r0 < Kend && r0 < R)
-      gemm_nt_sub<T>(S, ld, r0, r0, r0, r0, c, R - r0, std::min(Kend, R) - r0, cb, true, st, prof);
+    if (r0 < Kend && r0 < R) {
+      // rows [r0, R) of the panel's remaining columns [r0, min(Kend, R)) (not in
+      // the profile's MFMA-update figures, which cover the large update kernels)
+      const int64_t M = R - r0, N = std::min(Kend, R) - r0;
+      hipLaunchKernelGGL(k_gemm_panel<T>, dim3((unsigned)ceil_div(M, BS), (unsigned)ceil_div(N, BS)), dim3(256), 0,
+                         st, S + r0 + r0 * ld, ld, (const T*)(S + r0 + c * ld), ld, (const T*)(S + r0 + c * ld), ld,
+                         M, N, (int)cb, r0, r0);
+      HC_LAUNCH_CHECK();
+    }
   }
 }
 

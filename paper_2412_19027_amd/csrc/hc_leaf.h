@@ -19,6 +19,7 @@ namespace hc {
 
 constexpr int LEAF_MAX = 32;       // columns per leaf block
 constexpr int LEAF_CPL_MAX = 64;   // tail columns coupled to one leaf
+constexpr int LEAF_SMALL = 4;      // leaves up to this size are solved one lane per leaf
 
 // Where column j of S lives: leaf[j] < 0 -> tail index loc[j]; otherwise
 // leaf block leaf[j], local index loc[j].  All arrays are device arrays.
@@ -39,6 +40,15 @@ struct ColMap {
   double* cval = nullptr;              // coupling blocks (S_Tb, then W_b)
   double* ST = nullptr;                // tail matrix, column-major, leading dim ldt
   double* sink = nullptr;              // one double: target of impossible pairs
+  // the leaf solves: leaves of at most LEAF_SMALL columns (one lane each) and
+  // the rest (one wave each), and per tail index its couplings (the leaf and
+  // the row of that leaf's coupling block), for a gather instead of atomics
+  int64_t nsmall = 0, nlarge = 0;
+  const int32_t* small = nullptr;
+  const int32_t* large = nullptr;
+  const int64_t* tc_ptr = nullptr;     // nt + 1
+  const int32_t* tc_leaf = nullptr;
+  const int32_t* tc_row = nullptr;
 };
 
 // Schur assembly over row pairs of one cone (as assemble_pairs), routed
@@ -51,7 +61,9 @@ void add_P_delta_map(const Csr& P, int64_t n, double delta, const ColMap& cm, hi
 // W_b = S_Tb L_b^-T, and S_TT -= W_b W_b' (lower part, FP64 atomics).
 void leaf_factor(const ColMap& cm, double tol, double fix, unsigned long long* hits, hipStream_t st);
 // Forward half of the leaf solve: y_b = L_b^-1 u_b written to y at the leaf
-// columns, and uT -= W_b y_b (uT: compact tail vector, already gathered).
+// columns, then uT[t] -= sum over the leaves coupled to t of (W_b y_b)[t]
+// (uT: compact tail vector, already gathered), one writer per t in a fixed
+// order.
 void leaf_forward(const ColMap& cm, const double* u, double* y, double* uT, hipStream_t st);
 // Backward half: x_b = L_b^-T (y_b - W_b' xT), reading y_b from x at the
 // leaf columns and overwriting it.

@@ -177,12 +177,36 @@ __device__ inline void load_leaf_L(const ColMap& cm, int b, int l, int lane, dou
   for (int e = lane; e < l * l; e += 64) Lb[e % l][e / l] = lv[e];
 }
 
-__global__ __launch_bounds__(64) void k_leaf_fwd(ColMap cm, const double* __restrict__ u, double* __restrict__ y,
-                                                 double* __restrict__ uT) {
+// Leaf solves.  Leaves of at most LEAF_SMALL columns run one lane each
+// (their L and coupling rows read straight from memory), larger ones one wave
+// each through LDS; the tail's share of the forward solve is a gather per tail
+// index over the leaves coupled to it (no atomics, a fixed order).
+__global__ __launch_bounds__(256) void k_leaf_fwd_small(ColMap cm, const double* __restrict__ u,
+                                                        double* __restrict__ y) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= cm.nsmall) return;
+  const int b = cm.small[k];
+  const int l = cm.lsize[b];
+  const double* lv = cm.lval + cm.lval_off[b];   // L_b column-major: L[i][j] = lv[i + j l]
+  const int32_t* cols = cm.lcols + cm.lcol_off[b];
+  double yb[LEAF_SMALL];
+#pragma unroll
+  for (int j = 0; j < LEAF_SMALL; ++j) {
+    if (j < l) {
+      double v = u[cols[j]];
+#pragma unroll
+      for (int q = 0; q < j; ++q) v -= lv[j + q * l] * yb[q];
+      yb[j] = v / lv[j + j * l];
+      y[cols[j]] = yb[j];
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_leaf_fwd(ColMap cm, const double* __restrict__ u, double* __restrict__ y) {
   __shared__ double Lb[LEAF_MAX][LEAF_MAX + 1];
   __shared__ double yb[LEAF_MAX];
-  const int b = blockIdx.x, lane = threadIdx.x;
-  const int l = cm.lsize[b], cnt = cm.ccnt[b];
+  const int b = cm.large[blockIdx.x], lane = threadIdx.x;
+  const int l = cm.lsize[b];
   const int32_t* cols = cm.lcols + cm.lcol_off[b];
   load_leaf_L(cm, b, l, lane, Lb);
   if (lane < l) yb[lane] = u[cols[lane]];
@@ -195,18 +219,64 @@ __global__ __launch_bounds__(64) void k_leaf_fwd(ColMap cm, const double* __rest
     }
   __syncthreads();
   if (lane < l) y[cols[lane]] = yb[lane];
-  if (lane < cnt) {
-    const double* cv = cm.cval + cm.cval_off[b];
+}
+
+// uT[t] -= sum over the couplings (b, a) of t of sum_j W_b[a][j] y_b[j]; one
+// wave per tail index, lanes over its couplings, then a shuffle tree
+__global__ __launch_bounds__(64) void k_leaf_tail(ColMap cm, const double* __restrict__ y, double* __restrict__ uT) {
+  const int64_t t = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t e0 = cm.tc_ptr[t], e1 = cm.tc_ptr[t + 1];
+  double acc = 0.0;
+  for (int64_t e = e0 + lane; e < e1; e += 64) {
+    const int b = cm.tc_leaf[e], a = cm.tc_row[e];
+    const int l = cm.lsize[b], cnt = cm.ccnt[b];
+    const double* cv = cm.cval + cm.cval_off[b];   // W_b column-major (cnt x l)
+    const int32_t* cols = cm.lcols + cm.lcol_off[b];
     double v = 0.0;
-    for (int j = 0; j < l; ++j) v += cv[lane + (int64_t)j * cnt] * yb[j];
-    atomicAdd(&uT[cm.clist[cm.clist_off[b] + lane]], -v);
+    for (int j = 0; j < l; ++j) v += cv[a + (int64_t)j * cnt] * y[cols[j]];
+    acc += v;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0 && e1 > e0) uT[t] -= acc;
+}
+
+__global__ __launch_bounds__(256) void k_leaf_bwd_small(ColMap cm, const double* __restrict__ xT,
+                                                        double* __restrict__ x) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= cm.nsmall) return;
+  const int b = cm.small[k];
+  const int l = cm.lsize[b], cnt = cm.ccnt[b];
+  const double* lv = cm.lval + cm.lval_off[b];
+  const int32_t* cols = cm.lcols + cm.lcol_off[b];
+  const int32_t* cl = cm.clist + cm.clist_off[b];
+  const double* cv = cm.cval + cm.cval_off[b];
+  double vb[LEAF_SMALL];
+#pragma unroll
+  for (int j = 0; j < LEAF_SMALL; ++j) {
+    if (j < l) {
+      double v = x[cols[j]];
+      for (int a = 0; a < cnt; ++a) v -= cv[a + (int64_t)j * cnt] * xT[cl[a]];
+      vb[j] = v;
+    }
+  }
+#pragma unroll
+  for (int j = LEAF_SMALL - 1; j >= 0; --j) {
+    if (j < l) {
+      double v = vb[j];
+#pragma unroll
+      for (int q = j + 1; q < LEAF_SMALL; ++q)
+        if (q < l) v -= lv[q + j * l] * vb[q];
+      vb[j] = v / lv[j + j * l];
+      x[cols[j]] = vb[j];
+    }
   }
 }
 
 __global__ __launch_bounds__(64) void k_leaf_bwd(ColMap cm, const double* __restrict__ xT, double* __restrict__ x) {
   __shared__ double Lb[LEAF_MAX][LEAF_MAX + 1];
   __shared__ double vb[LEAF_MAX];
-  const int b = blockIdx.x, lane = threadIdx.x;
+  const int b = cm.large[blockIdx.x], lane = threadIdx.x;
   const int l = cm.lsize[b], cnt = cm.ccnt[b];
   const int32_t* cols = cm.lcols + cm.lcol_off[b];
   const int32_t* cl = cm.clist + cm.clist_off[b];
@@ -230,14 +300,30 @@ __global__ __launch_bounds__(64) void k_leaf_bwd(ColMap cm, const double* __rest
 
 void leaf_forward(const ColMap& cm, const double* u, double* y, double* uT, hipStream_t st) {
   if (cm.nleaf == 0) return;
-  hipLaunchKernelGGL(k_leaf_fwd, dim3((unsigned)cm.nleaf), dim3(64), 0, st, cm, u, y, uT);
-  HC_LAUNCH_CHECK();
+  if (cm.nsmall) {
+    hipLaunchKernelGGL(k_leaf_fwd_small, dim3((unsigned)ceil_div(cm.nsmall, 256)), dim3(256), 0, st, cm, u, y);
+    HC_LAUNCH_CHECK();
+  }
+  if (cm.nlarge) {
+    hipLaunchKernelGGL(k_leaf_fwd, dim3((unsigned)cm.nlarge), dim3(64), 0, st, cm, u, y);
+    HC_LAUNCH_CHECK();
+  }
+  if (cm.nt) {
+    hipLaunchKernelGGL(k_leaf_tail, dim3((unsigned)cm.nt), dim3(64), 0, st, cm, (const double*)y, uT);
+    HC_LAUNCH_CHECK();
+  }
 }
 
 void leaf_backward(const ColMap& cm, const double* xT, double* x, hipStream_t st) {
   if (cm.nleaf == 0) return;
-  hipLaunchKernelGGL(k_leaf_bwd, dim3((unsigned)cm.nleaf), dim3(64), 0, st, cm, xT, x);
-  HC_LAUNCH_CHECK();
+  if (cm.nsmall) {
+    hipLaunchKernelGGL(k_leaf_bwd_small, dim3((unsigned)ceil_div(cm.nsmall, 256)), dim3(256), 0, st, cm, xT, x);
+    HC_LAUNCH_CHECK();
+  }
+  if (cm.nlarge) {
+    hipLaunchKernelGGL(k_leaf_bwd, dim3((unsigned)cm.nlarge), dim3(64), 0, st, cm, xT, x);
+    HC_LAUNCH_CHECK();
+  }
 }
 
 __global__ void k_gather_tail(int64_t nt, const int32_t* __restrict__ tcols, const double* __restrict__ u,

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -55,6 +56,7 @@ struct Job {
   // batched engine
   std::unique_ptr<hc::WavePlan> plan;
   int slot = -1;
+  int32_t first_iterations = 0;    // iterations of a mixed-precision attempt run again in FP64
 };
 
 // first-fit allocator over [0, size) with coalescing, 256-byte granules
@@ -294,7 +296,7 @@ void hc_server::wave_worker(int cap) {
     const double t0 = now_ms();
     const bool launched = hipGraphLaunch(exec, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
     const double tick_ms = now_ms() - t0;
-    bool changed = false;
+    bool changed = false, restarted = false;
     for (int i = 0; i < cap; ++i) {
       if (!hact[i]) continue;
       auto& j = slot[i];
@@ -304,6 +306,22 @@ void hc_server::wave_worker(int cap) {
       j->s.resize(j->m);
       j->z.resize(j->m);
       if (launched) wave_result(hdesc[i], *j->plan, &inf, j->x.data(), j->s.data(), j->z.data(), st);
+      // a mixed-precision solve that broke down runs again in FP64, in the same
+      // slot and pool block (the FP64 layout is the mixed one without its FP32
+      // buffers), with the regularisation of the mixed mode's FP64 fallback
+      // factorisation; its iterations and one fallback are added to the report
+      if (launched && j->plan->mixed &&
+          (inf.status == HC_STATUS_NUMERICAL_ERROR || inf.status == HC_STATUS_INSUFFICIENT_PROGRESS)) {
+        j->plan->mixed = false;
+        j->plan->st.static_reg = 1e-8;
+        j->plan->st.dyn_reg = std::ldexp(1.0, -104);
+        j->first_iterations = inf.iterations;
+        wave_upload(*j->plan, pool_base + j->offset, &hdesc[i], st);
+        restarted = true;
+        continue;
+      }
+      inf.iterations += j->first_iterations;
+      if (j->first_iterations) inf.fp64_fallbacks += 1;
       hact[i] = 0;
       changed = true;
       --nact;
@@ -317,6 +335,7 @@ void hc_server::wave_worker(int cap) {
       slot[i].reset();
     }
     if (changed) (void)hipMemcpyAsync(dact, hact, (size_t)cap * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (restarted) (void)hipMemcpyAsync(ddesc, hdesc, (size_t)cap * sizeof(WaveDesc), hipMemcpyHostToDevice, st);
     // next tick's budget: 0.9 of this tick's length (10 ns clock ticks)
     *hbudget = (int64_t)(0.9 * tick_ms * 1e5);
     (void)hipMemcpyAsync(dbudget, hbudget, sizeof(int64_t), hipMemcpyHostToDevice, st);

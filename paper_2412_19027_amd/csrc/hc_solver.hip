@@ -108,6 +108,8 @@ struct hc_solver {
   bool leaves = false;             // any leaf block
   std::vector<int32_t> col_leaf, col_loc, tail_cols, leaf_size, leaf_cols, leaf_ccnt, leaf_clist;
   std::vector<int64_t> leaf_lval_off, leaf_lcol_off, leaf_clist_off, leaf_cval_off;
+  std::vector<int32_t> leaf_small, leaf_large, tc_leaf, tc_row;   // solve lists; couplings per tail index
+  std::vector<int64_t> tc_ptr;
   int64_t lval_total = 0, cval_total = 0;
   double leaf_flops = 0;
   int64_t mtotal = 0, stotal = 0;  // M entries, state entries
@@ -599,6 +601,27 @@ void build_leaves(hc_solver* S) {
     S->leaf_flops += (double)l * l * l / 3.0 + (double)cnt * l * l + (double)cnt * cnt * l;
   }
   S->leaves = !S->leaf_size.empty();
+  // leaf solve lists (one lane per small leaf, one wave per larger one) and,
+  // per tail index, the (leaf, coupling row) pairs in leaf order
+  S->leaf_small.clear();
+  S->leaf_large.clear();
+  for (int32_t b = 0; b < (int32_t)S->leaf_size.size(); ++b)
+    (S->leaf_size[b] <= LEAF_SMALL ? S->leaf_small : S->leaf_large).push_back(b);
+  S->tc_ptr.assign(S->nt + 1, 0);
+  for (size_t b = 0; b < S->leaf_size.size(); ++b)
+    for (int a = 0; a < S->leaf_ccnt[b]; ++a) S->tc_ptr[S->leaf_clist[S->leaf_clist_off[b] + a] + 1]++;
+  for (int64_t t2 = 0; t2 < S->nt; ++t2) S->tc_ptr[t2 + 1] += S->tc_ptr[t2];
+  S->tc_leaf.assign(S->tc_ptr[S->nt], 0);
+  S->tc_row.assign(S->tc_ptr[S->nt], 0);
+  {
+    std::vector<int64_t> fill(S->tc_ptr.begin(), S->tc_ptr.end() - 1);
+    for (size_t b = 0; b < S->leaf_size.size(); ++b)
+      for (int a = 0; a < S->leaf_ccnt[b]; ++a) {
+        const int64_t o = fill[S->leaf_clist[S->leaf_clist_off[b] + a]]++;
+        S->tc_leaf[o] = (int32_t)b;
+        S->tc_row[o] = a;
+      }
+  }
   // Envelope of the tail in its order: the first tail column each tail row is
   // coupled to, through a cone's clique (dense rows and large SOC rank-2 rows
   // included), an entry of P, or a leaf block's update W_b W_b' (a clique on
@@ -1985,6 +2008,13 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   cm.clist_off = upload(buf, S->leaf_clist_off, st);
   cm.clist = upload(buf, S->leaf_clist, st);
   cm.cval_off = upload(buf, S->leaf_cval_off, st);
+  cm.nsmall = (int64_t)S->leaf_small.size();
+  cm.nlarge = (int64_t)S->leaf_large.size();
+  cm.small = upload(buf, S->leaf_small, st);
+  cm.large = upload(buf, S->leaf_large, st);
+  cm.tc_ptr = upload(buf, S->tc_ptr, st);
+  cm.tc_leaf = upload(buf, S->tc_leaf, st);
+  cm.tc_row = upload(buf, S->tc_row, st);
   cm.lval = buf.take<double>(S->lval_total + 1);
   cm.cval = buf.take<double>(S->cval_total + 1);
   cm.sink = buf.take<double>(1);
