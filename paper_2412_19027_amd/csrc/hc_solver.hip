@@ -93,6 +93,12 @@ struct hc_solver {
   double bnorm_user = 0, qnorm_user = 0, maxPdiag = 0;
   int64_t nu = 0;                  // cone degree
   bool has_nonsym = false;
+  // Schur assembly by groups (the cones' row sets) and a column gather; the
+  // pair tasks below keep only what the groups do not take
+  std::vector<int64_t> ga_rows_off, ga_u_off, ga_m_off, ga_t_off, ga_gm, ga_c_ptr;
+  std::vector<int32_t> ga_rows, ga_u, ga_c_b, ga_c_k, ga_rgrp, ga_rloc;
+  int64_t ga_ng = 0, ga_t_total = 0;
+  GroupPlan gplan;
   std::vector<int32_t> tra, trb;   // Schur assembly tasks: short ones first, then
   std::vector<int64_t> tm;         // those of more than PAIR_WIDE products (one wave each)
   int64_t ntask_short = 0;
@@ -435,6 +441,7 @@ constexpr int LEAF_DEGREE = 64;
 constexpr int64_t PAIR_WIDE = 1024;   // products per pair task above which one wave takes the task
 
 void build_psd_dense(hc_solver* S);
+void build_groups(hc_solver* S);
 void build_lowrank(hc_solver* S, int nd);
 
 void build_leaves(hc_solver* S) {
@@ -842,6 +849,7 @@ void setup_host(hc_solver* S, const hc_problem* p) {
   S->At = std::move(At);
   build_leaves(S);
   build_psd_dense(S);
+  build_groups(S);
   if (S->leaves && nd) {   // dense rows live on tail columns only: re-index them
     std::vector<double> Adt((size_t)nd * S->nt);
     for (int d = 0; d < nd; ++d)
@@ -853,6 +861,137 @@ void setup_host(hc_solver* S, const hc_problem* p) {
   for (int64_t t = S->nt; t < S->ld; ++t) S->tail_last.push_back(t + 1);   // identity padding
   if (S->st.static_reg <= 0) S->st.static_reg = S->mixed ? 3.4526698300124393e-04 : 1e-8;
   if (S->st.dyn_reg < 0) S->st.dyn_reg = S->mixed ? std::ldexp(1.0, -46) : std::ldexp(1.0, -104);
+}
+
+// Groups of the Schur assembly (only without leaf blocks): the rows the pair
+// tasks link (a cone's rows; a single row of a zero or nonneg segment or of a
+// large SOC) form a group g, with U_g the sorted union of their columns.  Per
+// iteration T_g = M_g A_g and each column of S gathers A[r][j] T_r over the
+// rows of that column of A (group_T, group_gather: one writer per entry, a
+// fixed order).  When a column of S fits two LDS chunks (n <= 2 GATHER_CHUNK)
+// every group is taken, so the whole assembly has one writer per entry and a
+// fixed order; on larger problems only groups of at least GROUP_MIN_ROWS rows
+// (PSD cones: many row pairs, each S entry hit by many of them) are taken, and
+// the rest keep their pair tasks, which are cheaper there (a gather over a
+// 20,000-row column in five chunks costs more than the few atomics a 3-row
+// cone adds).  A group whose T_g would exceed GROUP_T_MAX entries keeps its
+// pair tasks.
+constexpr int64_t GROUP_MIN_ROWS = 6;
+constexpr int64_t GROUP_T_MAX = int64_t(1) << 22;
+void build_groups(hc_solver* S) {
+  S->ga_ng = S->ga_t_total = 0;
+  S->ga_rows_off.assign(1, 0);
+  S->ga_u_off.assign(1, 0);
+  S->ga_c_ptr.assign(1, 0);
+  S->ga_m_off.clear();
+  S->ga_t_off.clear();
+  S->ga_gm.clear();
+  S->ga_rows.clear();
+  S->ga_u.clear();
+  S->ga_c_b.clear();
+  S->ga_c_k.clear();
+  S->ga_rgrp.clear();
+  S->ga_rloc.clear();
+  if (S->leaves || S->tra.empty()) return;
+  const HostCsr& A = S->A;
+  const int64_t m = A.nrows, nt = (int64_t)S->tra.size();
+  std::vector<int32_t> par(m);
+  for (int64_t r = 0; r < m; ++r) par[r] = (int32_t)r;
+  auto find = [&](int32_t x) {
+    while (par[x] != x) x = par[x] = par[par[x]];
+    return x;
+  };
+  std::vector<char> used(m, 0);
+  for (int64_t k = 0; k < nt; ++k) {
+    used[S->tra[k]] = used[S->trb[k]] = 1;
+    const int32_t a = find(S->tra[k]), b = find(S->trb[k]);
+    if (a != b) par[std::max(a, b)] = std::min(a, b);
+  }
+  // groups in order of their first row, rows ascending within a group
+  std::vector<int32_t> gid(m, -1), loc(m, 0);
+  std::vector<std::vector<int32_t>> rows;
+  for (int64_t r = 0; r < m; ++r) {
+    if (!used[r]) continue;
+    const int32_t root = find((int32_t)r);
+    if (gid[root] < 0) {
+      gid[root] = (int32_t)rows.size();
+      rows.emplace_back();
+    }
+    const int32_t g = gid[root];
+    gid[r] = g;
+    loc[r] = (int32_t)rows[g].size();
+    rows[g].push_back((int32_t)r);
+  }
+  S->ga_rgrp.assign(m, -1);
+  S->ga_rloc.assign(m, 0);
+  std::vector<int32_t> u, cnt;
+  struct Ent {
+    int32_t col, k, b;   // column, index in A, group-local row
+  };
+  std::vector<Ent> ent;   // the group's entries in row order
+  for (size_t g = 0; g < rows.size(); ++g) {
+    ent.clear();
+    for (int32_t r : rows[g])
+      for (int32_t k = A.rp[r]; k < A.rp[r + 1]; ++k) ent.push_back({A.ci[k], k, loc[r]});
+    u.clear();
+    for (const Ent& en : ent) u.push_back(en.col);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    const int64_t nr = (int64_t)rows[g].size(), s = (int64_t)u.size();
+    if ((A.ncols > 2 * GATHER_CHUNK && nr < GROUP_MIN_ROWS) || nr * s > GROUP_T_MAX) continue;
+    const int32_t id = (int32_t)S->ga_ng++;
+    S->ga_m_off.push_back((int64_t)S->ga_gm.size());
+    S->ga_t_off.push_back(S->ga_t_total);
+    S->ga_gm.resize(S->ga_gm.size() + nr * nr, -1);
+    S->ga_t_total += nr * s;
+    for (int32_t r : rows[g]) {
+      S->ga_rows.push_back(r);
+      S->ga_rgrp[r] = id;
+      S->ga_rloc[r] = loc[r];
+    }
+    // per column of U_g its entries, in row order (a stable counting sort)
+    cnt.assign(s + 1, 0);
+    std::vector<int32_t> pos(ent.size());
+    for (size_t e = 0; e < ent.size(); ++e) {
+      pos[e] = (int32_t)(std::lower_bound(u.begin(), u.end(), ent[e].col) - u.begin());
+      cnt[pos[e] + 1]++;
+    }
+    for (int64_t q = 0; q < s; ++q) cnt[q + 1] += cnt[q];
+    const int64_t base = (int64_t)S->ga_c_b.size();
+    S->ga_c_b.resize(base + ent.size());
+    S->ga_c_k.resize(base + ent.size());
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (size_t e = 0; e < ent.size(); ++e) {
+      const int64_t o = base + fill[pos[e]]++;
+      S->ga_c_b[o] = ent[e].b;
+      S->ga_c_k[o] = ent[e].k;
+    }
+    for (int64_t q = 0; q < s; ++q) S->ga_c_ptr.push_back(base + cnt[q + 1]);
+    S->ga_u.insert(S->ga_u.end(), u.begin(), u.end());
+    S->ga_rows_off.push_back((int64_t)S->ga_rows.size());
+    S->ga_u_off.push_back((int64_t)S->ga_u.size());
+  }
+  // M entries of the taken groups; their tasks leave the pair list
+  int64_t keep = 0, keep_short = 0;
+  for (int64_t k = 0; k < nt; ++k) {
+    const int32_t ra = S->tra[k], rb = S->trb[k], g = S->ga_rgrp[ra];
+    if (g >= 0) {
+      const int64_t nr = S->ga_rows_off[g + 1] - S->ga_rows_off[g];
+      int64_t* gm = S->ga_gm.data() + S->ga_m_off[g];
+      gm[(int64_t)S->ga_rloc[ra] * nr + S->ga_rloc[rb]] = S->tm[k];
+      gm[(int64_t)S->ga_rloc[rb] * nr + S->ga_rloc[ra]] = S->tm[k];
+      continue;
+    }
+    if (k < S->ntask_short) keep_short++;
+    S->tra[keep] = ra;
+    S->trb[keep] = rb;
+    S->tm[keep] = S->tm[k];
+    keep++;
+  }
+  S->tra.resize(keep);
+  S->trb.resize(keep);
+  S->tm.resize(keep);
+  S->ntask_short = keep_short;
 }
 
 // PSD segments whose row pairs would cost more than forming T = M_c A_c for
@@ -1328,6 +1467,8 @@ void factor(hc_solver* S, bool fp64 = false) {
     assemble_pairs_map(nl, S->dtra + ns, S->dtrb + ns, S->dtm + ns, S->dmval, S->dA, S->cm, true, st);
   } else {
     add_P_delta(S->dP, S->n, S->delta, S->ld, S->dS, st);
+    group_T(S->gplan, S->dmval, S->dA, st);
+    group_gather(S->gplan, S->n, S->dAt, S->ld, S->dS, st);
     const int64_t ns = S->ntask_short, nl = (int64_t)S->tra.size() - ns;
     assemble_pairs(ns, S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->ld, S->dS, false, st);
     assemble_pairs(nl, S->dtra + ns, S->dtrb + ns, S->dtm + ns, S->dmval, S->dA, S->ld, S->dS, true, st);
@@ -1971,6 +2112,23 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->dE = upload(buf, S->E, st);
   S->dperm = upload(buf, S->perm, st);
   S->dalpha = upload(buf, S->alpha_pow, st);
+  {
+    GroupPlan& gp = S->gplan;
+    gp.ng = S->ga_ng;
+    gp.rows_off = upload(buf, S->ga_rows_off, st);
+    gp.u_off = upload(buf, S->ga_u_off, st);
+    gp.m_off = upload(buf, S->ga_m_off, st);
+    gp.t_off = upload(buf, S->ga_t_off, st);
+    gp.gm = upload(buf, S->ga_gm, st);
+    gp.rows = upload(buf, S->ga_rows, st);
+    gp.u = upload(buf, S->ga_u, st);
+    gp.c_ptr = upload(buf, S->ga_c_ptr, st);
+    gp.c_b = upload(buf, S->ga_c_b, st);
+    gp.c_k = upload(buf, S->ga_c_k, st);
+    gp.rgrp = upload(buf, S->ga_rgrp, st);
+    gp.rloc = upload(buf, S->ga_rloc, st);
+    gp.T = buf.take<double>(S->ga_t_total + 1);
+  }
   S->dtra = upload(buf, S->tra, st);
   S->dtrb = upload(buf, S->trb, st);
   S->dtm = upload(buf, S->tm, st);

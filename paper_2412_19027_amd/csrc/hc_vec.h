@@ -46,6 +46,27 @@ void psd_dense_T(int64_t base, int32_t dim, int64_t count, int64_t moff, const d
                  double* T, hipStream_t st);
 void dense_T_gather(int64_t n, const int32_t* erp, const int32_t* ee, const int32_t* ep, const double* atval,
                     const double* T, int64_t ld, double* S, hipStream_t st);
+// Schur contribution A' M A of the cone rows as a gather (no atomics, a fixed
+// order).  The rows the cones couple form groups g (one per cone; one per row
+// of a zero or nonneg segment) with the sorted union U_g of their columns.
+// group_T: T_g = M_g A_g (|R_g| x |U_g|, row-major at T + t_off[g]), one wave
+// per group, a lane per column of U_g summing over that column's entries of
+// the group's rows (c_ptr / c_b / c_k: per entry of the concatenated U lists,
+// the group-local row b and the index k of the entry in A), in row order; gm
+// (|R_g|^2 per group at m_off[g]) holds the index of M_g[a][b] in mval or -1.
+// group_gather: column j of S (rows i >= j) gains sum over the rows r of
+// column j of A, in order, of A[r][j] T_r[i]; one wave per column, the column
+// in LDS chunks of GATHER_CHUNK rows.
+constexpr int GATHER_CHUNK = 4096;
+struct GroupPlan {
+  int64_t ng = 0;
+  const int64_t *rows_off = nullptr, *u_off = nullptr, *m_off = nullptr, *t_off = nullptr, *gm = nullptr,
+                *c_ptr = nullptr;
+  const int32_t *rows = nullptr, *u = nullptr, *c_b = nullptr, *c_k = nullptr, *rgrp = nullptr, *rloc = nullptr;
+  double* T = nullptr;
+};
+void group_T(const GroupPlan& gp, const double* mval, const Csr& A, hipStream_t st);
+void group_gather(const GroupPlan& gp, int64_t n, const Csr& At, int64_t ld, double* S, hipStream_t st);
 void scale_dense_rows(int nd, int64_t n, const double* Ad, const int64_t* midx, const double* mval, double* B,
                       hipStream_t st);
 void aos_to_cm(int64_t count, int dim, const double* a, double* c, bool inverse, hipStream_t st);

@@ -432,6 +432,67 @@ void dense_T_gather(int64_t n, const int32_t* erp, const int32_t* ee, const int3
   HC_LAUNCH_CHECK();
 }
 
+__global__ __launch_bounds__(64) void k_group_T(GroupPlan gp, const double* __restrict__ mval,
+                                                const double* __restrict__ av) {
+  const int lane = threadIdx.x;
+  for (int64_t g = blockIdx.x; g < gp.ng; g += gridDim.x) {
+    const int64_t nr = gp.rows_off[g + 1] - gp.rows_off[g];
+    const int64_t uo = gp.u_off[g], s = gp.u_off[g + 1] - uo;
+    const int64_t* gm = gp.gm + gp.m_off[g];
+    double* T = gp.T + gp.t_off[g];
+    for (int64_t a = 0; a < nr; ++a)
+      for (int64_t t = lane; t < s; t += 64) {
+        double v = 0.0;
+        for (int64_t e = gp.c_ptr[uo + t]; e < gp.c_ptr[uo + t + 1]; ++e) {
+          const int64_t mi = gm[a * nr + gp.c_b[e]];
+          if (mi >= 0) v += mval[mi] * av[gp.c_k[e]];
+        }
+        T[a * s + t] = v;
+      }
+  }
+}
+void group_T(const GroupPlan& gp, const double* mval, const Csr& A, hipStream_t st) {
+  if (gp.ng == 0) return;
+  hipLaunchKernelGGL(k_group_T, dim3((unsigned)std::min<int64_t>(gp.ng, 65536)), dim3(64), 0, st, gp, mval, A.val);
+  HC_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(64) void k_group_gather(GroupPlan gp, int64_t n, const int32_t* __restrict__ atrp,
+                                                     const int32_t* __restrict__ atci,
+                                                     const double* __restrict__ atv, int64_t ld,
+                                                     double* __restrict__ S) {
+  __shared__ double acc[GATHER_CHUNK];
+  const int lane = threadIdx.x;
+  for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
+    const int32_t p0 = atrp[j], p1 = atrp[j + 1];
+    for (int64_t c0 = j; c0 < n; c0 += GATHER_CHUNK) {
+      const int64_t c1 = std::min<int64_t>(n, c0 + GATHER_CHUNK);
+      for (int64_t i = c0 + lane; i < c1; i += 64) acc[i - c0] = 0.0;
+      for (int32_t p = p0; p < p1; ++p) {
+        const int32_t r = atci[p], g = gp.rgrp[r];
+        if (g < 0) continue;
+        const double coef = atv[p];
+        const int64_t uo = gp.u_off[g], s = gp.u_off[g + 1] - uo;
+        const double* vals = gp.T + gp.t_off[g] + (int64_t)gp.rloc[r] * s;
+        for (int64_t t = lane; t < s; t += 64) {
+          const int64_t i = gp.u[uo + t];
+          if (i >= c0 && i < c1) acc[i - c0] += coef * vals[t];
+        }
+      }
+      for (int64_t i = c0 + lane; i < c1; i += 64) {
+        const double v = acc[i - c0];
+        if (v != 0.0) S[i + j * ld] += v;
+      }
+    }
+  }
+}
+void group_gather(const GroupPlan& gp, int64_t n, const Csr& At, int64_t ld, double* S, hipStream_t st) {
+  if (gp.ng == 0 || n == 0) return;
+  hipLaunchKernelGGL(k_group_gather, dim3((unsigned)std::min<int64_t>(n, 16384)), dim3(64), 0, st, gp, n, At.rowptr,
+                     At.col, At.val, ld, S);
+  HC_LAUNCH_CHECK();
+}
+
 // B (nd x n row-major, i.e. n x nd column-major with ld n) = sqrt|m_r| Ad[r, :];
 // rows with midx < 0 are padding and stay zero
 __global__ void k_scale_dense_rows(int nd, int64_t n, const double* __restrict__ Ad, const int64_t* __restrict__ midx,

@@ -186,3 +186,23 @@ def test_mpc_stream_against_oracle(precision):
         gp = certify(prob, x, sv, z)
         assert abs(gp - fo) <= 1e-7 * max(1.0, abs(fo)), (prob.name, gp, fo)
     assert max(sizes) > 4 * min(sizes)
+
+
+@pytest.mark.parametrize("make", [lambda: W.psd_pow(0, n=250, n_pow=120, n_psd=25, k=4),
+                                  lambda: W.psd_mixed(0, n=300, sides=(3, 5, 8), per_side=20)],
+                         ids=["psd_pow_small", "psd_mixed_small"])
+def test_schur_assembly_deterministic(make):
+    """Problems whose Schur columns fit two gather chunks assemble S with one
+    writer per entry in a fixed order (no atomics): two solves agree bit for
+    bit, iterations and solution."""
+    prob = make()
+    runs = []
+    for _ in range(2):
+        s = HC.Solver(prob)
+        info = s.solve()
+        x, sv, z = s.solution()
+        s.close()
+        assert info["status_name"] == "solved", info
+        runs.append((info["iterations"], x, z))
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
