@@ -27,6 +27,14 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """One line per step on stderr (the JSON result goes to stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def workload_desc(p):
     return (f"sparse_socp: n={p.n} (x 20,000 + 20 factor vars), m={p.m} (zero 10,020 incl. 20 dense lift rows, "
             f"nonneg 30,000, 40,000 SOC-3), A 6 nnz/row N(0,1), P = diag(U(0.01,1)) + rank-20 factor, seed 0")
@@ -82,6 +90,7 @@ def run_gpu(prob, precision, steps, warmup):
     that solve, the throughput from the timed ones."""
     import torch
     from paper_2412_19027_amd import hipcone as HC
+    progress(f"{prob.name} {precision}: set-up, {warmup} warm-up and {steps} timed solves")
     solver = HC.Solver(prob, precision=precision, profile=0)
     for _ in range(warmup):
         solver.solve()
@@ -95,6 +104,7 @@ def run_gpu(prob, precision, steps, warmup):
     iters = sum(i["iterations"] for i in infos)
     last = infos[-1]
     solver.close()
+    progress(f"{prob.name} {precision}: profiled solve (settings.profile = 2)")
     prof = HC.Solver(prob, precision=precision, profile=2)
     t1 = time.perf_counter()
     pi = prof.solve()
@@ -134,6 +144,7 @@ def run_seeds(precision, seeds=(1, 2, 3, 4)):
     out = {}
     for sd in seeds:
         prob = W.sparse_socp(sd)
+        progress(f"seed {sd} {precision}")
         s = HC.Solver(prob, precision=precision, profile=0)
         s.solve()
         torch.cuda.synchronize()
@@ -170,6 +181,7 @@ def run_other_workloads(steps=1, only=None):
         if only and name != only:
             continue
         prob = makers[name]()
+        progress(f"{name}: set-up, warm-up, {steps} timed and one profiled solve")
         s = HC.Solver(prob)
         s.solve()
         torch.cuda.synchronize()
@@ -203,6 +215,7 @@ def run_served(count, precision="fp64", rate=2000.0, workers=4, slots=32, budget
     import threading
     from paper_2412_19027_amd import hipcone as HC
     from paper_2412_19027_amd import workloads as W
+    progress(f"served stream: {count} requests, {precision}, {'batched' if batched else 'per-slot'}")
     probs = [W.mpc_socp(seed, i) for i in range(count)]
     arrivals = W.mpc_arrivals(seed, count, rate)
     srv = HC.Server(hbm_budget_bytes=budget, max_slots=slots, workers=workers, batched=batched,
@@ -440,6 +453,7 @@ def main():
     sc = args.scale
     prob = W.sparse_socp(0, nx=int(20000 * sc), n_zero=int(10000 * sc), n_nonneg=int(30000 * sc),
                          n_soc=int(40000 * sc))
+    progress("start")
     main_run = run_gpu(prob, args.precision, args.steps, args.warmup)
     other = None
     if not args.no_mixed:
@@ -469,13 +483,19 @@ def main():
         served["mixed"] = run_served(args.served, "mixed")
         served["per_slot_fp64_1000"] = run_served(min(1000, args.served), "fp64", budget=16 << 30, batched=False)
         if args.sequential > 0:
+            progress(f"sequential FP64 solves of {args.sequential} requests")
             served["plain_fp64_sequential"] = run_sequential(args.sequential)
+    if args.served > 0:
+        progress("parametric re-solves")
     parametric = run_parametric() if args.served > 0 else None
     others = None if args.no_workloads else run_other_workloads()
     if args.calibrate_copy:
         calibrate_copy()
+    if not args.no_cpu_baseline:
+        progress("oracle: one IPM iteration on the host")
     cpu = None if args.no_cpu_baseline else cpu_baseline(prob)
     if cpu is not None and args.served > 0:
+        progress("oracle pool on the served stream")
         cpu["served"] = cpu_served_baseline()
     out = {
         "metric": METRIC,
@@ -510,6 +530,7 @@ def main():
         "workloads": others,
         "cpu_baseline": cpu,
     }
+    progress("done")
     print(json.dumps(out))
 
 

@@ -18,6 +18,7 @@ struct Prof {
 // while the next panel is factored on the caller's stream.
 struct Aux {
   int64_t nb = 768;     // panel width (multiple of 64) of the delayed updates
+  bool serial = false;  // every launch on the caller's stream, one at a time (timing)
   hipStream_t side = nullptr;
   std::vector<hipEvent_t> ev;
   size_t used = 0;
@@ -28,8 +29,9 @@ struct Aux {
 // In-place lower Cholesky of the n x n column-major S (leading dim ld).
 // Linv receives the inverses of the 64 x 64 diagonal factor blocks
 // (linv_elems(n) entries).  Pivots <= tol are replaced by fix and counted.
-// With `aux` the trailing updates overlap the next panel's factorisation;
-// all work is complete with respect to `st` on return.
+// The trailing updates overlap the next panel's factorisation on aux's side
+// stream unless aux->serial; all work is complete with respect to `st` on
+// return.
 // `last` (host, n entries, or null for a dense matrix) is the envelope of
 // the lower triangle: last[j] - 1 is the largest row i with a nonzero S[i, k]
 // for some k <= j (non-decreasing in j).  Cholesky fill stays inside it, so
@@ -37,7 +39,7 @@ struct Aux {
 // reach; entries below the envelope are never touched and stay zero.
 template <typename T>
 void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
-                    hipStream_t st, Prof* prof = nullptr, Aux* aux = nullptr, const int64_t* last = nullptr);
+                    hipStream_t st, Prof* prof, Aux* aux, const int64_t* last = nullptr);
 // flops of the envelope-limited factorisation (n^3 / 3 when last is null)
 double envelope_cholesky_flops(int64_t n, const int64_t* last);
 // Inverses X (and X') of the 256 x 256 diagonal blocks of the factor, from

@@ -14,10 +14,10 @@
 //           also writes the inverse of the factor block (Linv, 64x64 per block)
 //   trsm:   L21 = A21 * Linv' in place, one workgroup per 64 rows
 //   update: trailing C -= L21 L21' on MFMA (v_mfma_f64_16x16x4f64 or
-//           v_mfma_f32_16x16x4f32), 128x128 tiles, lower tiles only.  The
-//           update of the trailing matrix is delayed to every NB = 256
-//           columns (the panel's own columns are updated eagerly), so the
-//           trailing matrix is read and written once per 256 columns.
+//           v_mfma_f32_16x16x4f32), 256x128 tiles, lower tiles only.  The
+//           update of the trailing matrix is delayed to every panel of
+//           Aux::nb columns (the panel's own columns are updated eagerly),
+//           so the trailing matrix is read and written once per panel.
 // Triangular solves use the stored Linv blocks: one launch per 256 rows.
 #include "hc_dense.h"
 
@@ -51,7 +51,6 @@ template <> struct Mfma<float> {
 };
 
 constexpr int BS = 64;    // diagonal block
-constexpr int NB = 256;   // delayed-update panel width (multiple of BS)
 
 // ---------------------------------------------------------------------------
 // diagonal block: Cholesky + inverse of the factor, one wave
@@ -836,28 +835,26 @@ template <typename T>
 void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix, unsigned long long* hits,
                     hipStream_t st, Prof* prof, Aux* aux, const int64_t* last) {
   if (n <= 0) return;
-  if (!aux) {
-    for (int64_t K0 = 0; K0 < n; K0 += NB) {
-      const int64_t Kend = std::min<int64_t>(n, K0 + NB);
-      factor_panel<T>(S, n, ld, Linv, tol, fix, hits, K0, Kend, last, st, prof);
-      // delayed update of the trailing matrix with the whole panel
-      const int64_t R = rows_below(last, n, Kend - 1);
-      if (Kend < R) gemm_nt_sub<T>(S, ld, Kend, Kend, Kend, Kend, K0, R - Kend, R - Kend, Kend - K0, true, st, prof);
-    }
-    return;
-  }
   // Look-ahead.  After panel k is factored: U1 updates panel k+1 on `st`, U2
   // updates every later column on `side`.  Panel k+1 is then factored on `st`
   // while U2 runs.  U1 writes the columns that the previous U2 wrote, so it
   // waits for that U2; U2 waits for panel k to be factored.  Both stop at the
   // rows the panel's columns reach (the envelope); a panel whose columns reach
-  // no row past the next panel launches no U2.
-  aux->init();
-  aux->used = 0;
+  // no row past the next panel launches no U2.  In serial mode U2 runs on
+  // `st` before U1: the same launches, one at a time.
+  const bool serial = aux->serial;
+  hipStream_t side = st;
+  if (!serial) {
+    aux->init();
+    aux->used = 0;
+    side = aux->side;
+  }
   const int64_t W = std::max<int64_t>(BS, aux->nb / BS * BS);   // panel width
-  hipEvent_t start = aux->next();
-  HC_HIP(hipEventRecord(start, st));
-  HC_HIP(hipStreamWaitEvent(aux->side, start, 0));
+  if (!serial) {
+    hipEvent_t start = aux->next();
+    HC_HIP(hipEventRecord(start, st));
+    HC_HIP(hipStreamWaitEvent(side, start, 0));
+  }
   hipEvent_t u2_done = nullptr;
   for (int64_t K0 = 0; K0 < n; K0 += W) {
     const int64_t Kend = std::min<int64_t>(n, K0 + W);
@@ -867,20 +864,22 @@ void dense_cholesky(T* S, int64_t n, int64_t ld, T* Linv, double tol, double fix
     const int64_t R = rows_below(last, n, Kend - 1);
     const bool u2 = K1 < R;
     if (u2) {
-      hipEvent_t factored = aux->next();
-      HC_HIP(hipEventRecord(factored, st));
-      HC_HIP(hipStreamWaitEvent(aux->side, factored, 0));
-      // U2 on the side stream: rows and columns [K1, R)
-      gemm_nt_sub<T>(S, ld, K1, K1, K1, K1, K0, R - K1, R - K1, Kend - K0, true, aux->side, prof);
+      if (!serial) {
+        hipEvent_t factored = aux->next();
+        HC_HIP(hipEventRecord(factored, st));
+        HC_HIP(hipStreamWaitEvent(side, factored, 0));
+      }
+      // U2: rows and columns [K1, R)
+      gemm_nt_sub<T>(S, ld, K1, K1, K1, K1, K0, R - K1, R - K1, Kend - K0, true, side, prof);
     }
     if (u2_done) HC_HIP(hipStreamWaitEvent(st, u2_done, 0));
     // U1 on the caller's stream: rows [Kend, R), columns [Kend, min(K1, R))
     if (Kend < R)
       gemm_nt_sub<T>(S, ld, Kend, Kend, Kend, Kend, K0, R - Kend, std::min(K1, R) - Kend, Kend - K0, true, st, prof);
     u2_done = nullptr;
-    if (u2) {
+    if (u2 && !serial) {
       u2_done = aux->next();
-      HC_HIP(hipEventRecord(u2_done, aux->side));
+      HC_HIP(hipEventRecord(u2_done, side));
     }
   }
   if (u2_done) HC_HIP(hipStreamWaitEvent(st, u2_done, 0));

@@ -177,7 +177,6 @@ struct hc_solver {
   std::unique_ptr<Prof> prof;
   std::unique_ptr<Prof> cprof;      // events around the cone-layer launches (settings.profile)
   Aux aux;   // side stream + events of the look-ahead factorisation
-  bool no_lookahead = false;        // factor on the handle's stream alone (no side stream)
   bool use64 = false;               // mixed mode: this iteration fell back to the FP64 factor
   int kiter = 0;                    // loop counter of the current solve
   double sdiag_max = 0;             // mixed mode: max |S_ii| of the last FP32 factorisation
@@ -1420,10 +1419,13 @@ __global__ void k_get_diag(int64_t n, int64_t ld, const double* __restrict__ A, 
   if (i < n) d[i] = A[i + i * ld];
 }
 
-// the look-ahead's side stream, unless the handle factors on its own stream
-// alone (allocation-free solves; settings.profile = 2, where the MFMA update
-// durations must not overlap other kernels)
-Aux* lookahead(hc_solver* S) { return (S->no_lookahead || S->st.profile == 2) ? nullptr : &S->aux; }
+// the look-ahead's schedule; with settings.profile = 2 its launches run one at
+// a time on the handle's stream, so that the MFMA update durations do not
+// overlap other kernels
+Aux* lookahead(hc_solver* S) {
+  S->aux.serial = S->st.profile == 2;
+  return &S->aux;
+}
 
 // factor the regularised KKT system at the current scaling (state + hdiag
 // filled).  FP64: delta = delta_s + delta_d max|K_ii| (the oracle's reading).

@@ -206,3 +206,29 @@ def test_schur_assembly_deterministic(make):
         runs.append((info["iterations"], x, z))
     assert runs[0][0] == runs[1][0]
     assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_profile_mode_serial_schedule(precision):
+    """settings.profile = 2 issues the look-ahead factorisation's launches one
+    at a time on the handle's stream (for per-launch timing).  A dense tail of
+    four 768-column panels, so both trailing updates of the look-ahead run:
+    the timed schedule reaches the same solution as the overlapped one (each
+    entry of S receives its updates in the same order; the pair assembly's
+    atomics may reorder sums, hence a tolerance rather than bitwise)."""
+    prob = W.sparse_socp(0, nx=2500, rank=5, n_zero=1250, n_nonneg=3750, n_soc=5000)
+    runs = []
+    for profile in (0, 2):
+        s = HC.Solver(prob, precision=precision, profile=profile)
+        info = s.solve()
+        x, sv, z = s.solution()
+        s.close()
+        assert info["status_name"] == "solved", info
+        runs.append((info, x, sv, z))
+    (ia, xa, _, _), (ib, xb, sb, zb) = runs
+    assert ib["n_ordered"] > 2 * 768, ib["n_ordered"]
+    assert ib["gemm_launches"] > 0 and ib["gemm_ms"] > 0
+    assert ia["iterations"] == ib["iterations"]
+    assert abs(ia["obj_primal"] - ib["obj_primal"]) <= 1e-9 * max(1.0, abs(ia["obj_primal"]))
+    assert np.abs(xa - xb).max() <= 1e-6 * max(1.0, np.abs(xa).max())
+    certify(prob, xb, sb, zb)
