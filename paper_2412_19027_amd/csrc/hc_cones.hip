@@ -1596,9 +1596,12 @@ static void exp_unit_point(double* u) {
 
 void cone_unit(const SegDev& g, double* v, hipStream_t st) {
   if (g.count == 0) return;
-  static double eu[3] = {0, 0, 0};
-  if (eu[0] == 0.0) exp_unit_point(eu);
-  hipLaunchKernelGGL(k_cone_unit, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, v, eu[0], eu[1], eu[2]);
+  struct UnitPoint {
+    double u[3];
+    UnitPoint() { exp_unit_point(u); }
+  };
+  static const UnitPoint eu;   // computed once, thread-safe (solvers on several threads)
+  hipLaunchKernelGGL(k_cone_unit, dim3(cone_blocks(g)), dim3(CONE_BLOCK), 0, st, g, v, eu.u[0], eu.u[1], eu.u[2]);
   HC_LAUNCH_CHECK();
 }
 

@@ -2236,10 +2236,17 @@ size_t workspace_bytes(const hc_solver* S) {
   return b.used + 4096;
 }
 
-// pinned read-back staging: the partials, then the step masks
-size_t host_stage_bytes(const hc_solver* S) {
-  if (!S->bound) workspace_bytes(S);   // the dry run sets npart
+// pinned read-back staging: the partials, then the step masks (npart is set
+// by alloc_all, real or dry)
+size_t stage_bytes_of(const hc_solver* S) {
   return (size_t)S->npart * (sizeof(double) + sizeof(unsigned long long));
+}
+
+// before bind only: the dry run that sets npart also sets every device
+// pointer of the handle (to null)
+size_t host_stage_bytes(const hc_solver* S) {
+  if (!S->bound) workspace_bytes(S);
+  return stage_bytes_of(S);
 }
 
 void bind(hc_solver* S, const hc_device* dev) {
@@ -2264,7 +2271,7 @@ void bind(hc_solver* S, const hc_device* dev) {
   S->mem_bytes = need;
   hipStream_t st = S->stream;
   alloc_all(S, buf, st);
-  if (dev && dev->host_stage && dev->host_stage_bytes >= host_stage_bytes(S)) {
+  if (dev && dev->host_stage && dev->host_stage_bytes >= stage_bytes_of(S)) {   // npart from the allocation above
     S->hpart = (double*)dev->host_stage;
     S->hmask = (unsigned long long*)(S->hpart + S->npart);
   } else {

@@ -273,7 +273,10 @@ class Solver:
     """One problem on one GPU.  `prob` is a workloads.Problem (or any object
     with n, m, P (upper CSR), q, A (CSR), b, cones)."""
 
-    def __init__(self, prob, device=0, stream=None, **settings):
+    def __init__(self, prob, device=0, stream=None, pinned_stage=False, **settings):
+        """With pinned_stage the read-back staging is a pinned host buffer of
+        hc_host_stage_bytes owned by this object (as the served form's workers
+        pass theirs) instead of one the library allocates."""
         import torch
         self._torch = torch
         L = lib()
@@ -287,8 +290,14 @@ class Solver:
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.arena = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        stage, stage_bytes = None, 0
+        if pinned_stage:
+            sb = C.c_size_t()
+            _check(L.hc_host_stage_bytes(h, C.byref(sb)), h)
+            self.stage = torch.empty(int(sb.value), dtype=torch.uint8, pin_memory=True)
+            stage, stage_bytes = self.stage.data_ptr(), int(sb.value)
         dev = hc_device(self.arena.data_ptr(), int(nbytes.value), self.stream.cuda_stream, self.device.index or 0,
-                        None, 0)
+                        stage, stage_bytes)
         _check(L.hc_bind(h, C.byref(dev)), h)
 
     def solve(self):

@@ -232,3 +232,21 @@ def test_profile_mode_serial_schedule(precision):
     assert abs(ia["obj_primal"] - ib["obj_primal"]) <= 1e-9 * max(1.0, abs(ia["obj_primal"]))
     assert np.abs(xa - xb).max() <= 1e-6 * max(1.0, np.abs(xa).max())
     certify(prob, xb, sb, zb)
+
+
+@pytest.mark.parametrize("make", [lambda: W.mpc_socp(0, 3),
+                                  lambda: W.sparse_socp(0, nx=600, rank=5, n_zero=150, n_nonneg=400, n_soc=500)],
+                         ids=["mpc", "socp_small"])
+def test_bind_with_caller_pinned_stage(make):
+    """hc_bind with a caller-owned arena and caller-owned pinned read-back
+    staging (the form the served form's per-slot workers use) solves as with
+    the library's own staging.  Binding once checked the staging size by a
+    dry run of the allocation that reset the handle's device pointers."""
+    prob = make()
+    a, xa, _, _ = gpu_solve(prob)
+    b, xb, sb, zb = gpu_solve(prob, pinned_stage=True)
+    assert a["status_name"] == b["status_name"] == "solved", (a, b)
+    assert a["iterations"] == b["iterations"]
+    assert abs(a["obj_primal"] - b["obj_primal"]) <= 1e-9 * max(1.0, abs(a["obj_primal"]))
+    assert np.abs(xa - xb).max() <= 1e-6 * max(1.0, np.abs(xa).max())
+    certify(prob, xb, sb, zb)

@@ -13,10 +13,14 @@ from paper_2412_19027_amd import workloads as W  # noqa: E402
 from tests.test_gpu_solver import MPC_STREAM, certify, gpu_solve, mpc_reference  # noqa: E402
 
 
-def test_server_matches_direct_solves():
+@pytest.mark.parametrize("batched", [True, False], ids=["batched", "per_slot"])
+def test_server_matches_direct_solves(batched):
+    """Every request as by a direct solve, on the batched engine or on the
+    per-slot workers (which bind each problem into the pool with a pinned
+    read-back block of their own)."""
     probs = [W.mpc_socp(0, i) for i in range(10)] + [W.tiny_lp(s) for s in range(4)]
     budget = 2 << 30
-    srv = HC.Server(hbm_budget_bytes=budget, max_slots=6, workers=3)
+    srv = HC.Server(hbm_budget_bytes=budget, max_slots=6, workers=3, batched=batched)
     tickets = [srv.submit(p, tag=100 + i) for i, p in enumerate(probs)]
     res = [srv.wait(t, solution=True) for t in tickets]
     st = srv.stats()
