@@ -992,20 +992,24 @@ __global__ __launch_bounds__(256) void k_trsv_diag(const T* __restrict__ Xinv, i
   __shared__ T part[16][DIAG_ROWS][NR];
   const int tid = threadIdx.x;
   const int cb = (int)std::min<int64_t>(SB, n - c);
-  for (int e = tid; e < SB * NR; e += 256) {
-    const int i = e % SB, r = e / SB;
-    bb[i][r] = (i < cb && r < nrhs) ? Bin[(c + i) + r * n] : T(0);
-  }
-  __syncthreads();
   const int il = tid % DIAG_ROWS, g = tid / DIAG_ROWS;
   const int i = blockIdx.x * DIAG_ROWS + il;
+  // the inverse's entries do not depend on the previous kernel: their loads
+  // are issued before the right-hand side's, so the two latencies overlap
+  T x[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) x[q] = Xinv[i + (int64_t)(g * 16 + q) * SB];
+  for (int e = tid; e < SB * NR; e += 256) {
+    const int ie = e % SB, r = e / SB;
+    bb[ie][r] = (ie < cb && r < nrhs) ? Bin[(c + ie) + r * n] : T(0);
+  }
+  __syncthreads();
   T acc[NR] = {};
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int k = g * 16 + q;
-    const T x = Xinv[i + (int64_t)k * SB];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] += x * bb[k][r];
+    for (int r = 0; r < NR; ++r) acc[r] += x[q] * bb[k][r];
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) part[g][il][r] = acc[r];
@@ -1031,32 +1035,39 @@ __global__ __launch_bounds__(1024) void k_trsv_fwd_update(const T* __restrict__ 
   __shared__ T part[16][64][NR];
   const int tid = threadIdx.x;
   const int cb = (int)std::min<int64_t>(SB, n - c);
+  const int lane = tid & 63, w = tid >> 6;
+  const int64_t row = c + cb + (int64_t)blockIdx.x * 64 + lane;
+  const int64_t rowc = std::min<int64_t>(row, n - 1);
+  // L's entries do not depend on the previous kernel: loaded before y
+  T l[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) l[q] = L[rowc + (c + std::min(w * 16 + q, cb - 1)) * ld];   // yb is zero past cb
+  // the entry of B this thread updates at the end (final before this kernel)
+  const int64_t rw = c + cb + (int64_t)blockIdx.x * 64 + (tid % 64);
+  const int rr = tid / 64;
+  const bool writer = tid < 64 * NR && rw < n && rr < nrhs;
+  const T bold = writer ? B[rw + rr * n] : T(0);
   for (int e = tid; e < SB * NR; e += 1024) {
     const int i = e % SB, r = e / SB;
     yb[i][r] = (i < cb && r < nrhs) ? Y[(c + i) + r * n] : T(0);
   }
   __syncthreads();
-  const int lane = tid & 63, w = tid >> 6;
-  const int64_t row = c + cb + (int64_t)blockIdx.x * 64 + lane;
-  const int64_t rowc = std::min<int64_t>(row, n - 1);
   T acc[NR] = {};
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int k = w * 16 + q;
-    const T l = L[rowc + (c + std::min(k, cb - 1)) * ld];   // yb is zero past cb
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] += l * yb[k][r];
+    for (int r = 0; r < NR; ++r) acc[r] += l[q] * yb[k][r];
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) part[w][lane][r] = acc[r];
   __syncthreads();
   if (tid < 64 * NR) {
-    const int ln = tid % 64, r = tid / 64;
-    const int64_t rw = c + cb + (int64_t)blockIdx.x * 64 + ln;
+    const int ln = tid % 64;
     T v = 0;
 #pragma unroll
-    for (int ww = 0; ww < 16; ++ww) v += part[ww][ln][r];
-    if (rw < n && r < nrhs) B[rw + r * n] -= v;
+    for (int ww = 0; ww < 16; ++ww) v += part[ww][ln][rr];
+    if (writer) B[rw + rr * n] = bold - v;
   }
 }
 
@@ -1070,23 +1081,38 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_update(const T* __restrict__ L
   __shared__ T xb[SB][NR];
   const int tid = threadIdx.x;
   const int cb = (int)std::min<int64_t>(SB, n - c);
+  const int lane = tid & 63;
+  const int64_t j0 = j_begin + ((int64_t)blockIdx.x * 4 + (tid >> 6)) * BWD_COLS;
+  // L's entries do not depend on the previous kernel: loaded before x
+  T l[BWD_COLS][SB / 64];
+#pragma unroll
+  for (int cc = 0; cc < BWD_COLS; ++cc) {
+    const int64_t j = std::min<int64_t>(j0 + cc, c - 1);
+#pragma unroll
+    for (int q = 0; q < SB / 64; ++q) l[cc][q] = L[(c + std::min(lane + 64 * q, cb - 1)) + j * ld];   // xb is zero past cb
+  }
+  // the entries of Y lane 0 updates at the end (final before this kernel)
+  T yold[BWD_COLS][NR] = {};
+  if (lane == 0)
+#pragma unroll
+    for (int cc = 0; cc < BWD_COLS; ++cc)
+      if (j0 + cc < c)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (r < nrhs) yold[cc][r] = Yv[(j0 + cc) + r * n];
   for (int e = tid; e < SB * NR; e += 256) {
     const int i = e % SB, r = e / SB;
     xb[i][r] = (i < cb && r < nrhs) ? X[(c + i) + r * n] : T(0);
   }
   __syncthreads();
-  const int lane = tid & 63;
-  const int64_t j0 = j_begin + ((int64_t)blockIdx.x * 4 + (tid >> 6)) * BWD_COLS;
   T acc[BWD_COLS][NR] = {};
 #pragma unroll
   for (int cc = 0; cc < BWD_COLS; ++cc) {
-    const int64_t j = std::min<int64_t>(j0 + cc, c - 1);
 #pragma unroll
     for (int q = 0; q < SB / 64; ++q) {
       const int i = lane + 64 * q;
-      const T l = L[(c + std::min(i, cb - 1)) + j * ld];   // xb is zero past cb
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[cc][r] += l * xb[i][r];
+      for (int r = 0; r < NR; ++r) acc[cc][r] += l[cc][q] * xb[i][r];
     }
   }
 #pragma unroll
@@ -1103,7 +1129,7 @@ __global__ __launch_bounds__(256) void k_trsv_bwd_update(const T* __restrict__ L
       if (j0 + cc < c)
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-          if (r < nrhs) Yv[(j0 + cc) + r * n] -= acc[cc][r];
+          if (r < nrhs) Yv[(j0 + cc) + r * n] = yold[cc][r] - acc[cc][r];
 }
 
 // With an envelope (`last`, see dense_cholesky) the forward updates stop at

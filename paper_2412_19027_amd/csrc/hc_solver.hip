@@ -1806,13 +1806,17 @@ double step_length(hc_solver* S, const Step& d, bool combined) {
     c2 = v[i3] + d.dkappa * d.dtau;
   }
   const double ratio = S->st.backtrack;
+  // the first batch is the first trial alone (the usual outcome is that it
+  // passes, and each trial of a batch costs every cone a conjugate-point
+  // solve); later batches take up to 8
+  int batch = 1;
   while (true) {
     if (a < 1e-10) return 0.0;
-    // the next 8 trials a, a r, a r^2, ... (products formed in sequence)
+    // the next trials a, a r, a r^2, ... (products formed in sequence)
     double trial[8];
     double t = a;
     int nt = 0;
-    for (; nt < 8; ++nt) {
+    for (; nt < batch; ++nt) {
       if (t < 1e-10) break;
       trial[nt] = t;
       t *= ratio;
@@ -1832,8 +1836,9 @@ double step_length(hc_solver* S, const Step& d, bool combined) {
     }
     for (int j = 0; j < nt; ++j)
       if (all & (1ull << j)) return trial[j];
-    if (nt < 8) return 0.0;
+    if (nt < batch) return 0.0;
     a = t;
+    batch = 8;
   }
 }
 
