@@ -223,6 +223,29 @@ int32_t hc_solve(hc_solver* s);
 
 int32_t hc_get_info(const hc_solver* s, hc_info* out);
 
+/* For callers that cannot allocate (tight serving loops, harnesses that
+ * forbid device allocation): hc_bind + hc_solve
+ * + hc_get_solution of a set-up, unbound handle without allocating.  The
+ * workspace is the library's static device array of HC_NOALLOC_BYTES bytes
+ * (each device the library runs on holds its own copy until the process
+ * ends; its address is taken once per device, on the first call there), the
+ * read-back staging a static 4 MiB host block, and the dense factorisation
+ * issues its look-ahead schedule's launches on `stream` alone (no stream or
+ * event is created).  No hipMalloc, hipHostMalloc or hipFree is called.
+ * Calls are serialised by a process-wide lock, so calls on one GPU never
+ * overlap (the array is shared by all of them and keeps the last call's
+ * contents; each call initialises what it reads) and each returns after its
+ * work on the GPU has finished.  stream: a HIP stream of `device` (NULL: the
+ * null stream).  x (n), sv (m), z (m): host buffers for the solution as
+ * hc_get_solution returns it, any may be NULL; info: as hc_get_info, may be
+ * NULL.  The handle is left unbound (timing settings are ignored).  Errors:
+ * HC_ERR_INVALID_ARG (NULL handle, device outside 0-63), HC_ERR_STATE (the
+ * handle is bound), HC_ERR_TOO_LARGE (workspace above HC_NOALLOC_BYTES or
+ * staging above 4 MiB; both sizes are in hc_last_error), HC_ERR_DEVICE. */
+#define HC_NOALLOC_BYTES ((size_t)64 << 20)
+int32_t hc_solve_noalloc(hc_solver* s, void* stream, int32_t device, double* x, double* sv, double* z,
+                         hc_info* info);
+
 
 /* Solution in the user's row order, unscaled and divided by tau (Sec. 2.2:
  * x/tau, s/tau, z/tau): x (n), s (m), z (m), caller-owned buffers (any may be

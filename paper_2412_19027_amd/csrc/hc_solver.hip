@@ -123,6 +123,7 @@ struct hc_solver {
   bool mixed = false;
   // ---- device
   bool bound = false;
+  bool noalloc = false;             // bound to the static workspace for one hc_solve_noalloc call
   bool own_mem = false;
   void* mem = nullptr;
   size_t mem_bytes = 0;
@@ -1423,7 +1424,7 @@ __global__ void k_get_diag(int64_t n, int64_t ld, const double* __restrict__ A, 
 // a time on the handle's stream, so that the MFMA update durations do not
 // overlap other kernels
 Aux* lookahead(hc_solver* S) {
-  S->aux.serial = S->st.profile == 2;
+  S->aux.serial = S->st.profile == 2 || S->noalloc;   // the allocation-free call creates no stream or events
   return &S->aux;
 }
 
@@ -2705,6 +2706,35 @@ int32_t solver_finish(hc_solver* S) {
 }  // namespace hc
 
 // ===========================================================================
+// allocation-free solve (hc_solve_noalloc): the workspace is a static device
+// array (one copy per device, its address taken once per device), the
+// read-back staging a static host block, and the dense factorisation issues
+// the look-ahead schedule's launches on the caller's stream alone
+// ===========================================================================
+static __device__ __align__(256) unsigned char scratch[HC_NOALLOC_BYTES];
+
+namespace {
+
+constexpr size_t NOALLOC_STAGE_BYTES = (size_t)4 << 20;
+alignas(256) unsigned char g_noalloc_stage[NOALLOC_STAGE_BYTES];
+std::mutex g_noalloc_mu;                 // one call at a time in the process
+constexpr int NOALLOC_MAX_DEVICES = 64;
+void* g_scratch[NOALLOC_MAX_DEVICES];    // device -> address of its copy of `scratch`
+
+// the handle leaves the static workspace: unbound, nothing of it kept
+void noalloc_release(hc_solver* S) {
+  S->bound = false;
+  S->noalloc = false;
+  S->hpart = nullptr;
+  S->hmask = nullptr;
+  S->own_stage = false;
+  S->have_warm = false;
+  S->mem_bytes = 0;
+}
+
+}  // namespace
+
+// ===========================================================================
 // C-ABI
 // ===========================================================================
 // the iterate in the user's coordinates: x = D x~ / t, s[perm] = s~ / E / t,
@@ -2827,6 +2857,54 @@ int32_t hc_solve(hc_solver* S) {
     g_last_error = e.msg;
     return e.code;
   }
+  return HC_OK;
+}
+
+int32_t hc_solve_noalloc(hc_solver* S, void* stream, int32_t device, double* x, double* sv, double* z,
+                         hc_info* info) {
+  if (!S || device < 0 || device >= NOALLOC_MAX_DEVICES) return HC_ERR_INVALID_ARG;
+  if (S->bound) return HC_ERR_STATE;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  const int32_t profile = S->st.profile;
+  try {
+    const size_t need = workspace_bytes(S), stage = host_stage_bytes(S);
+    if (need > HC_NOALLOC_BYTES || stage > NOALLOC_STAGE_BYTES)
+      fail(HC_ERR_TOO_LARGE, "hc_solve_noalloc: the problem needs " + std::to_string(need) +
+                                 " bytes of device workspace (at most " + std::to_string((size_t)HC_NOALLOC_BYTES) +
+                                 ") and " + std::to_string(stage) + " bytes of read-back staging (at most " +
+                                 std::to_string(NOALLOC_STAGE_BYTES) + ")");
+    HC_HIP(hipSetDevice(device));
+    if (!g_scratch[device]) {
+      void* p = nullptr;
+      const hipError_t rc = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (rc != hipSuccess || !p)
+        fail(HC_ERR_DEVICE, std::string("hipGetSymbolAddress of the static workspace: ") + hipGetErrorString(rc));
+      g_scratch[device] = p;
+    }
+    hc_device dev{g_scratch[device], (size_t)HC_NOALLOC_BYTES, stream, device, g_noalloc_stage, NOALLOC_STAGE_BYTES};
+    S->st.profile = 0;   // no timing events
+    S->noalloc = true;
+    const double t0 = now_ms();
+    bind(S, &dev);
+    run_solve(S);
+    HC_HIP(hipStreamSynchronize(S->stream));
+    S->info.solve_ms = now_ms() - t0;
+    unsigned long long h = 0;
+    HC_HIP(hipMemcpy(&h, S->dhits, sizeof(h), hipMemcpyDeviceToHost));
+    S->info.pivot_guard_hits = (int64_t)h;
+    const int32_t rc = hc_get_solution(S, x, sv, z, 0);
+    if (rc != HC_OK) fail(rc, g_last_error);
+    if (info) *info = S->info;
+  } catch (const Error& e) {
+    if (S->bound) (void)hipStreamSynchronize(S->stream);
+    noalloc_release(S);
+    S->st.profile = profile;
+    record(S, e);
+    g_last_error = e.msg;
+    return e.code;
+  }
+  noalloc_release(S);
+  S->st.profile = profile;
   return HC_OK;
 }
 

@@ -21,7 +21,7 @@ STATUS = {0: "unsolved", 1: "solved", 2: "primal_infeasible", 3: "dual_infeasibl
           5: "insufficient_progress", 6: "numerical_error", 7: "cancelled"}
 
 EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "hc_solve", "hc_get_info",
-           "hc_get_solution", "hc_host_stage_bytes", "hc_batch_check", "hc_solve_batch", "hc_get_iterate", "hc_set_iterate", "hc_update_data", "hc_test_kkt_solve", "hc_test_kkt_ops",
+           "hc_get_solution", "hc_solve_noalloc", "hc_host_stage_bytes", "hc_batch_check", "hc_solve_batch", "hc_get_iterate", "hc_set_iterate", "hc_update_data", "hc_test_kkt_solve", "hc_test_kkt_ops",
            "hc_test_schur", "hc_destroy", "hc_last_error", "hc_status_str",
            "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_cone_step_min", "hc_test_dense_chol_solve",
            "hc_test_dense_chol_solve_env",
@@ -95,6 +95,7 @@ class hc_server_report(C.Structure):
 HC_PENDING = 1
 ERR_UNSUPPORTED = -9
 ERR_TOO_LARGE = -10
+NOALLOC_BYTES = 64 << 20     # the static device workspace of hc_solve_noalloc (HC_NOALLOC_BYTES)
 
 _lib = None
 
@@ -114,6 +115,7 @@ def lib():
         L.hc_solve.argtypes = [vp]
         L.hc_get_info.argtypes = [vp, C.POINTER(hc_info)]
         L.hc_get_solution.argtypes = [vp, vp, vp, vp, i32]
+        L.hc_solve_noalloc.argtypes = [vp, vp, i32, vp, vp, vp, C.POINTER(hc_info)]
         L.hc_host_stage_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.hc_batch_check.argtypes = [vp, C.POINTER(i32)]
         L.hc_solve_batch.argtypes = [vp, i32, vp, i32, vp]
@@ -217,6 +219,27 @@ def analyze(prob, **settings) -> dict:
         out = {f: getattr(inf, f) for f, _ in hc_info._fields_}
         out["workspace_bytes"] = int(nbytes.value)
         return out
+    finally:
+        L.hc_destroy(h)
+
+
+def solve_noalloc(prob, device=0, stream=None, **settings):
+    """hc_solve_noalloc: set-up on the host, then the solve in the library's
+    static device workspace (no device or pinned allocation); returns (info,
+    x, s, z) with the solution in host arrays.  stream: a torch stream of the
+    device (default: its current stream)."""
+    import torch
+    L = lib()
+    h, keep = _setup(prob, default_settings(**settings))
+    try:
+        st = stream if stream is not None else torch.cuda.current_stream(device)
+        x, s, z = np.zeros(prob.n), np.zeros(prob.m), np.zeros(prob.m)
+        inf = hc_info()
+        _check(L.hc_solve_noalloc(h, st.cuda_stream, int(device), x.ctypes.data, s.ctypes.data, z.ctypes.data,
+                                  C.byref(inf)), h)
+        out = {f: getattr(inf, f) for f, _ in hc_info._fields_}
+        out["status_name"] = STATUS.get(inf.status, "unknown")
+        return out, x, s, z
     finally:
         L.hc_destroy(h)
 
