@@ -164,6 +164,7 @@ def spread(vals):
 
 
 OTHER_WORKLOADS = ("logreg_exp", "psd_pow", "entropy_max", "portfolio_qp", "multistage_portfolio", "psd_sides_to_32")
+MIXED_TOO = ("logreg_exp",)   # also solved in mixed precision (the logistic regression's stated precision)
 
 
 def run_other_workloads(steps=1, only=None):
@@ -202,6 +203,26 @@ def run_other_workloads(steps=1, only=None):
                          setup_ms=last["setup_ms"],
                          dense_tail=last["n_ordered"], leaf_blocks=last["n_leaves"],
                          cone_roofline=cone_roofline(pinfo))
+        if name in MIXED_TOO:   # the configuration's stated precision: FP32 factor, FP64 refinement
+            progress(f"{name}: mixed precision, warm-up and {steps} timed solves")
+            sm = HC.Solver(prob, precision="mixed")
+            sm.solve()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            minfos = [sm.solve() for _ in range(steps)]
+            torch.cuda.synchronize()
+            mwall = time.perf_counter() - t0
+            sm.close()
+            mit = sum(i["iterations"] for i in minfos)
+            ml = minfos[-1]
+            out[name]["mixed"] = dict(
+                status=ml["status_name"], iterations=ml["iterations"], objective=ml["obj_primal"],
+                objective_rel_diff_vs_fp64=abs(ml["obj_primal"] - last["obj_primal"]) / max(1.0, abs(last["obj_primal"])),
+                ms_per_iteration=1e3 * mwall / max(1, mit), ms_per_solve=1e3 * mwall / steps,
+                ms_per_solve_vs_fp64=(mwall / steps) / (wall / steps),
+                factor_ms_per_iteration=ml["factor_ms"] / max(1, ml["iterations"]),
+                ir_solves_per_iteration=sum(i["ir_solves"] for i in minfos) / max(1, mit),
+                fp64_fallbacks_per_solve=sum(i["fp64_fallbacks"] for i in minfos) / steps)
     return out
 
 

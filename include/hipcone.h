@@ -190,6 +190,15 @@ typedef struct {
                               reads and writes of iterate, direction and scaling
                               state)                                              */
   int64_t cone_launches;
+  int64_t sym_split_columns; /* columns outside the tail's dense rows and hubs
+                              whose graph the setup ordered (approximate
+                              minimum degree) and split along its elimination
+                              tree: subtrees of at most 32 columns coupled to
+                              at most 64 others became leaf blocks, the rest
+                              joined the tail (0: no such columns)              */
+  int64_t sym_supernodes;  /* fundamental supernodes of that graph's factor      */
+  int64_t sym_levels;      /* levels of its supernodal tree                     */
+  int64_t sym_nnz_l;       /* nonzeros of its Cholesky factor (column counts)    */
 } hc_info;
 
 typedef struct hc_solver hc_solver;
@@ -480,6 +489,19 @@ void hc_server_destroy(hc_server* s);
  * (bytes read, bytes written) against which hardware byte counters of the
  * other kernels are scaled. */
 int32_t hc_test_copy(const void* src, void* dst, int64_t bytes, void* stream);
+
+/* hc_test_symbolic: the setup's symbolic analysis (host only, no device) of a
+ * caller's symmetric graph: n vertices, CSR adjacency ptr (n + 1) / adj
+ * (both directions of every edge, self loops ignored).  Writes the
+ * approximate minimum degree order with its elimination tree postordered
+ * (order[k] = vertex eliminated k-th), the tree (parent[k]: position of the
+ * parent, -1 for a root), the Cholesky column counts (diagonal included),
+ * the fundamental supernodes (sn_first: nsuper + 1 column starts, sn_parent,
+ * sn_level; every array sized n, or n + 1 for sn_first) and the number of
+ * levels.  HC_ERR_INVALID_ARG on NULL, HC_ERR_CSR on a malformed graph. */
+int32_t hc_test_symbolic(int32_t n, const int64_t* ptr, const int32_t* adj, int32_t* order, int32_t* parent,
+                         int64_t* count, int32_t* sn_first, int32_t* sn_parent, int32_t* sn_level,
+                         int32_t* nsuper, int32_t* nlevels);
 
 #ifdef __cplusplus
 }

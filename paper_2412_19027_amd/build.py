@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhipcone.so")
-SOURCES = ["hc_dense.hip", "hc_cones.hip", "hc_soc.hip", "hc_vec.hip", "hc_leaf.hip", "hc_solver.hip", "hc_server.hip", "hc_test_abi.hip", "hc_wave.hip"]
+SOURCES = ["hc_dense.hip", "hc_cones.hip", "hc_soc.hip", "hc_vec.hip", "hc_leaf.hip", "hc_solver.hip", "hc_server.hip", "hc_test_abi.hip", "hc_wave.hip", "hc_symbolic.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

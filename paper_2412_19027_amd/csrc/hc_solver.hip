@@ -33,6 +33,7 @@
 #include "hc_cones.h"
 #include "hc_dense.h"
 #include "hc_leaf.h"
+#include "hc_symbolic.h"
 #include "hc_vec.h"
 #include "hc_wave.h"
 
@@ -124,6 +125,8 @@ struct hc_solver {
   // ---- device
   bool bound = false;
   bool noalloc = false;             // bound to the static workspace for one hc_solve_noalloc call
+  // symbolic analysis of the components split along their elimination tree
+  int64_t sym_split_columns = 0, sym_supernodes = 0, sym_levels = 0, sym_nnz_l = 0;
   bool own_mem = false;
   void* mem = nullptr;
   size_t mem_bytes = 0;
@@ -444,7 +447,200 @@ void build_psd_dense(hc_solver* S);
 void build_groups(hc_solver* S);
 void build_lowrank(hc_solver* S, int nd);
 
+// Leaf blocks from the symbolic analysis of the columns outside the tail:
+// their graph (cliques and P restricted to them) is ordered by approximate
+// minimum degree and its elimination tree postordered, so that every subtree
+// is a run of consecutive columns.  A subtree couples, outside itself, only
+// to its ancestors (the factor column of its root, without the root) and to
+// tail columns; the maximal subtrees of at most LEAF_MAX columns with at most
+// LEAF_CPL_MAX such couplings become leaf blocks (a connected component that
+// fits is one subtree), and the other columns join the tail.  The symbolic
+// figures (supernodes, level sets, factor nonzeros of this graph) are
+// recorded in the handle.  Should a subtree touch a column of another leaf
+// (which the tree rules out), or the ordering exceed its work limit, every
+// component of more than LEAF_MAX columns goes to the tail whole and the
+// others stay leaf candidates as they are.
+void etree_leaves(hc_solver* S, std::vector<std::vector<int32_t>>& comp, std::vector<char>& tail,
+                  const std::vector<int64_t>& cp, const std::vector<int32_t>& cc, const std::vector<int64_t>& ip,
+                  const std::vector<int32_t>& inc) {
+  const HostCsr& P = S->P;
+  const int64_t n = S->n;
+  std::vector<int32_t> big;
+  for (auto& c : comp) big.insert(big.end(), c.begin(), c.end());
+  if (big.empty()) return;
+  std::vector<std::vector<int32_t>> saved;
+  saved.swap(comp);
+  auto to_tail = [&]() {   // the rule without the tree: components that fit stay candidates
+    comp.clear();
+    for (auto& c : saved) {
+      if ((int)c.size() > LEAF_MAX) {
+        for (int32_t j : c) tail[j] = 1;
+      } else {
+        comp.push_back(c);
+      }
+    }
+  };
+  std::sort(big.begin(), big.end());
+  const int32_t nb = (int32_t)big.size();
+  std::vector<int32_t> loc(n, -1);
+  for (int32_t a = 0; a < nb; ++a) loc[big[a]] = a;
+  // graph of the components' columns and, per column, its tail neighbours
+  SymGraph g;
+  g.n = nb;
+  g.ptr.assign(nb + 1, 0);
+  std::vector<std::vector<int32_t>> nbr(nb), tnb(nb);
+  for (int32_t a = 0; a < nb; ++a) {
+    const int32_t j = big[a];
+    for (int64_t e = ip[j]; e < ip[j + 1]; ++e) {
+      const int32_t c = inc[e];
+      for (int64_t f = cp[c]; f < cp[c + 1]; ++f) {
+        const int32_t u = cc[f];
+        if (u == j) continue;
+        if (loc[u] >= 0) nbr[a].push_back(loc[u]);
+        else if (tail[u]) tnb[a].push_back(u);
+      }
+    }
+    for (int32_t k = P.rp[j]; k < P.rp[j + 1]; ++k) {
+      const int32_t u = P.ci[k];
+      if (u == j) continue;
+      if (loc[u] >= 0) {
+        nbr[a].push_back(loc[u]);
+        nbr[loc[u]].push_back(a);
+      } else if (tail[u]) {
+        tnb[a].push_back(u);
+      }
+    }
+  }
+  for (int32_t a = 0; a < nb; ++a) {
+    for (int32_t k = P.rp[big[a]]; k < P.rp[big[a] + 1]; ++k) {   // P's other triangle
+      const int32_t u = P.ci[k];
+      if (u != big[a] && loc[u] < 0 && tail[u]) tnb[a].push_back(u);
+    }
+    std::sort(nbr[a].begin(), nbr[a].end());
+    nbr[a].erase(std::unique(nbr[a].begin(), nbr[a].end()), nbr[a].end());
+    std::sort(tnb[a].begin(), tnb[a].end());
+    tnb[a].erase(std::unique(tnb[a].begin(), tnb[a].end()), tnb[a].end());
+    g.ptr[a + 1] = g.ptr[a] + (int64_t)nbr[a].size();
+  }
+  g.adj.reserve(g.ptr[nb]);
+  for (int32_t a = 0; a < nb; ++a) g.adj.insert(g.adj.end(), nbr[a].begin(), nbr[a].end());
+  // symmetric closure (P may be stored as one triangle)
+  {
+    std::vector<std::vector<int32_t>> sym(nb);
+    for (int32_t a = 0; a < nb; ++a)
+      for (int32_t b : nbr[a]) {
+        sym[a].push_back(b);
+        sym[b].push_back(a);
+      }
+    g.adj.clear();
+    for (int32_t a = 0; a < nb; ++a) {
+      std::sort(sym[a].begin(), sym[a].end());
+      sym[a].erase(std::unique(sym[a].begin(), sym[a].end()), sym[a].end());
+      g.ptr[a + 1] = g.ptr[a] + (int64_t)sym[a].size();
+      g.adj.insert(g.adj.end(), sym[a].begin(), sym[a].end());
+    }
+  }
+  const std::vector<int32_t> o = amd_order(g, 64 * (g.ptr[nb] + nb) + (1 << 20));
+  if ((int32_t)o.size() != nb) {
+    to_tail();
+    return;
+  }
+  const std::vector<int32_t> par0 = elimination_tree(g, o);
+  const std::vector<int32_t> post = tree_postorder(par0);
+  std::vector<int32_t> order(nb);
+  for (int32_t k = 0; k < nb; ++k) order[k] = o[post[k]];
+  const std::vector<int32_t> parent = elimination_tree(g, order);
+  std::vector<int32_t> pos(nb);
+  for (int32_t k = 0; k < nb; ++k) pos[order[k]] = k;
+  // per position: subtree size, its couplings to ancestors (the factor column's
+  // rows below the root, exact: the column counts) and to tail columns (kept
+  // only up to CAP entries: a set above that stays above it in every ancestor)
+  constexpr size_t CAP = LEAF_CPL_MAX + 2;
+  std::vector<int32_t> size(nb, 1);
+  std::vector<std::vector<int32_t>> up(nb), tl(nb);
+  std::vector<char> over(nb, 0);
+  std::vector<std::vector<int32_t>> kids(nb);
+  for (int32_t k = 0; k < nb; ++k)
+    if (parent[k] >= 0) kids[parent[k]].push_back(k);
+  std::vector<int32_t> mark(nb, -1);
+  std::vector<int64_t> count(nb, 1);
+  std::vector<char> eligible(nb, 0);
+  for (int32_t k = 0; k < nb; ++k) {
+    const int32_t a = order[k];
+    auto& u = up[k];
+    auto& tt = tl[k];
+    mark[k] = k;
+    bool ov = false;
+    for (int64_t e = g.ptr[a]; e < g.ptr[a + 1]; ++e) {
+      const int32_t i = pos[g.adj[e]];
+      if (i > k && mark[i] != k) {
+        mark[i] = k;
+        u.push_back(i);
+      }
+    }
+    tt = tnb[a];
+    for (int32_t c : kids[k]) {
+      size[k] += size[c];
+      ov = ov || over[c];
+      for (int32_t i : up[c])
+        if (i > k && mark[i] != k) {
+          mark[i] = k;
+          u.push_back(i);
+        }
+      tt.insert(tt.end(), tl[c].begin(), tl[c].end());
+      std::vector<int32_t>().swap(up[c]);
+      std::vector<int32_t>().swap(tl[c]);
+    }
+    std::sort(tt.begin(), tt.end());
+    tt.erase(std::unique(tt.begin(), tt.end()), tt.end());
+    count[k] = 1 + (int64_t)u.size();
+    if (u.size() + tt.size() > CAP) {   // the ancestor rows stay exact (column counts)
+      ov = true;
+      tt.resize(std::min(tt.size(), CAP));
+    }
+    over[k] = ov;
+    eligible[k] = !ov && size[k] <= LEAF_MAX && u.size() + tt.size() <= (size_t)LEAF_CPL_MAX;
+  }
+  // leaves: eligible subtrees whose parent's subtree is not
+  std::vector<int32_t> leaf_of(nb, -1);
+  std::vector<std::vector<int32_t>> leaves;
+  for (int32_t k = 0; k < nb; ++k) {
+    if (!eligible[k] || (parent[k] >= 0 && eligible[parent[k]])) continue;
+    std::vector<int32_t> cols;
+    for (int32_t q = k - size[k] + 1; q <= k; ++q) {
+      leaf_of[q] = (int32_t)leaves.size();
+      cols.push_back(big[order[q]]);
+    }
+    leaves.push_back(std::move(cols));
+  }
+  // every neighbour of a leaf's column lies in the leaf or outside all leaves
+  for (int32_t k = 0; k < nb; ++k) {
+    if (leaf_of[k] < 0) continue;
+    const int32_t a = order[k];
+    for (int64_t e = g.ptr[a]; e < g.ptr[a + 1]; ++e) {
+      const int32_t other = leaf_of[pos[g.adj[e]]];
+      if (other >= 0 && other != leaf_of[k]) {
+        to_tail();
+        return;
+      }
+    }
+  }
+  for (int32_t k = 0; k < nb; ++k)
+    if (leaf_of[k] < 0) tail[big[order[k]]] = 1;
+  for (auto& c : leaves) comp.push_back(std::move(c));
+  std::sort(comp.begin(), comp.end(), [](const std::vector<int32_t>& x, const std::vector<int32_t>& y) {
+    return *std::min_element(x.begin(), x.end()) < *std::min_element(y.begin(), y.end());
+  });
+  // symbolic figures of the split components (their graph, before the split)
+  const Supernodes sn = find_supernodes(parent, count);
+  S->sym_supernodes += (int64_t)sn.parent.size();
+  S->sym_levels = std::max<int64_t>(S->sym_levels, sn.nlevels);
+  for (int64_t c : count) S->sym_nnz_l += c;
+  S->sym_split_columns += nb;
+}
+
 void build_leaves(hc_solver* S) {
+  S->sym_split_columns = S->sym_supernodes = S->sym_levels = S->sym_nnz_l = 0;
   const int64_t n = S->n;
   const HostCsr& A = S->A;
   const HostCsr& P = S->P;
@@ -535,10 +731,7 @@ void build_leaves(hc_solver* S) {
     }
     comp[comp_of[r]].push_back((int32_t)j);
   }
-  for (auto& c : comp)
-    if ((int)c.size() > LEAF_MAX)
-      for (int32_t j : c) tail[j] = 1;
-  // incidence column -> cliques, then each leaf's coupled tail columns
+  // incidence column -> cliques
   std::vector<int64_t> ip(n + 1, 0);
   for (int64_t e = 0; e < (int64_t)cc.size(); ++e) ip[cc[e] + 1]++;
   for (int64_t j = 0; j < n; ++j) ip[j + 1] += ip[j];
@@ -548,6 +741,8 @@ void build_leaves(hc_solver* S) {
     for (int64_t c = 0; c < ncl; ++c)
       for (int64_t e = cp[c]; e < cp[c + 1]; ++e) inc[fillp[cc[e]]++] = (int32_t)c;
   }
+  // leaf blocks: subtrees of the elimination tree of the non-tail columns
+  etree_leaves(S, comp, tail, cp, cc, ip, inc);
   std::vector<std::vector<int32_t>> cpl(comp.size());
   for (size_t b = 0; b < comp.size(); ++b) {
     if (tail[comp[b][0]]) continue;
@@ -2026,6 +2221,10 @@ void begin_solve(hc_solver* S) {
   S->info.n_ordered = keep.n_ordered;
   S->info.n_leaves = keep.n_leaves;
   S->info.leaf_columns = keep.leaf_columns;
+  S->info.sym_split_columns = keep.sym_split_columns;
+  S->info.sym_supernodes = keep.sym_supernodes;
+  S->info.sym_levels = keep.sym_levels;
+  S->info.sym_nnz_l = keep.sym_nnz_l;
   S->info.psd_gathered_rows = keep.psd_gathered_rows;
   S->info.factor_flops = keep.factor_flops;
   vfill(1, 0.0, (double*)S->dhits, S->stream);
@@ -2798,6 +2997,10 @@ int32_t hc_setup(hc_solver** out, const hc_problem* prob, const hc_settings* set
     S->info.n_ordered = S->nt;
     S->info.n_leaves = (int64_t)S->leaf_size.size();
     S->info.leaf_columns = S->n - S->nt;
+    S->info.sym_split_columns = S->sym_split_columns;
+    S->info.sym_supernodes = S->sym_supernodes;
+    S->info.sym_levels = S->sym_levels;
+    S->info.sym_nnz_l = S->sym_nnz_l;
     S->info.psd_gathered_rows = S->pe_rows;
     S->info.factor_flops = envelope_cholesky_flops(S->nt, S->tail_last.data()) + S->leaf_flops;
   } catch (const Error& e) {

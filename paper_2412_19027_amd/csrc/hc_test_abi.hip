@@ -6,6 +6,7 @@
 
 #include "hc_cones.h"
 #include "hc_dense.h"
+#include "hc_symbolic.h"
 #include "hc_vec.h"
 
 using namespace hc;
@@ -374,3 +375,32 @@ int32_t hc_test_copy(const void* src, void* dst, int64_t bytes, void* stream) {
 }
 
 }  // extern "C"
+
+// symbolic analysis of a caller's graph (host only)
+int32_t hc_test_symbolic(int32_t n, const int64_t* ptr, const int32_t* adj, int32_t* order, int32_t* parent,
+                         int64_t* count, int32_t* sn_first, int32_t* sn_parent, int32_t* sn_level, int32_t* nsuper,
+                         int32_t* nlevels) {
+  if (n < 0 || !ptr || (n > 0 && (!adj || !order || !parent || !count || !sn_first || !sn_parent || !sn_level)) ||
+      !nsuper || !nlevels)
+    return HC_ERR_INVALID_ARG;
+  SymGraph g;
+  g.n = n;
+  g.ptr.assign(ptr, ptr + n + 1);
+  if (g.ptr[0] != 0) return HC_ERR_CSR;
+  for (int32_t i = 0; i < n; ++i)
+    if (g.ptr[i + 1] < g.ptr[i]) return HC_ERR_CSR;
+  g.adj.assign(adj, adj + g.ptr[n]);
+  for (int32_t v : g.adj)
+    if (v < 0 || v >= n) return HC_ERR_CSR;
+  const SymbolicPlan P = symbolic_analysis(g);
+  std::copy(P.order.begin(), P.order.end(), order);
+  std::copy(P.parent.begin(), P.parent.end(), parent);
+  std::copy(P.count.begin(), P.count.end(), count);
+  const int32_t ns = (int32_t)P.sn.parent.size();
+  std::copy(P.sn.first.begin(), P.sn.first.end(), sn_first);
+  std::copy(P.sn.parent.begin(), P.sn.parent.end(), sn_parent);
+  std::copy(P.sn.level.begin(), P.sn.level.end(), sn_level);
+  *nsuper = ns;
+  *nlevels = P.sn.nlevels;
+  return HC_OK;
+}

@@ -25,7 +25,7 @@ EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "
            "hc_test_schur", "hc_destroy", "hc_last_error", "hc_status_str",
            "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_cone_step_min", "hc_test_dense_chol_solve",
            "hc_test_dense_chol_solve_env",
-           "hc_test_copy", "hc_test_cone_mblock", "hc_server_config_default", "hc_server_create", "hc_server_submit", "hc_server_poll",
+           "hc_test_copy", "hc_test_symbolic", "hc_test_cone_mblock", "hc_server_config_default", "hc_server_create", "hc_server_submit", "hc_server_poll",
            "hc_server_wait", "hc_server_stats", "hc_server_destroy"]
 
 
@@ -67,7 +67,8 @@ class hc_info(C.Structure):
                 ("gemm_ms", C.c_double), ("gemm_flops", C.c_double), ("gemm_launches", C.c_int64),
                 ("fp64_fallbacks", C.c_int64), ("n_leaves", C.c_int64), ("leaf_columns", C.c_int64),
                 ("psd_gathered_rows", C.c_int64), ("cone_kernel_ms", C.c_double), ("cone_bytes", C.c_double),
-                ("cone_launches", C.c_int64)]
+                ("cone_launches", C.c_int64), ("sym_split_columns", C.c_int64), ("sym_supernodes", C.c_int64),
+                ("sym_levels", C.c_int64), ("sym_nnz_l", C.c_int64)]
 
 
 class hc_server_config(C.Structure):
@@ -116,6 +117,7 @@ def lib():
         L.hc_get_info.argtypes = [vp, C.POINTER(hc_info)]
         L.hc_get_solution.argtypes = [vp, vp, vp, vp, i32]
         L.hc_solve_noalloc.argtypes = [vp, vp, i32, vp, vp, vp, C.POINTER(hc_info)]
+        L.hc_test_symbolic.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), C.POINTER(i32)]
         L.hc_host_stage_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.hc_batch_check.argtypes = [vp, C.POINTER(i32)]
         L.hc_solve_batch.argtypes = [vp, i32, vp, i32, vp]
@@ -242,6 +244,27 @@ def solve_noalloc(prob, device=0, stream=None, **settings):
         return out, x, s, z
     finally:
         L.hc_destroy(h)
+
+
+def symbolic(n, ptr, adj):
+    """The setup's symbolic analysis of a symmetric graph (host only):
+    dict with order, parent, count (numpy arrays), supernodes (first, parent,
+    level) and nlevels."""
+    ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+    adj = np.ascontiguousarray(adj, dtype=np.int32)
+    order = np.zeros(n, np.int32)
+    parent = np.zeros(n, np.int32)
+    count = np.zeros(n, np.int64)
+    first = np.zeros(n + 1, np.int32)
+    sp = np.zeros(max(n, 1), np.int32)
+    sl = np.zeros(max(n, 1), np.int32)
+    ns, nl = C.c_int32(), C.c_int32()
+    _check(lib().hc_test_symbolic(int(n), ptr.ctypes.data, adj.ctypes.data, order.ctypes.data, parent.ctypes.data,
+                                  count.ctypes.data, first.ctypes.data, sp.ctypes.data, sl.ctypes.data,
+                                  C.byref(ns), C.byref(nl)))
+    k = ns.value
+    return dict(order=order, parent=parent, count=count, sn_first=first[:k + 1], sn_parent=sp[:k],
+                sn_level=sl[:k], nlevels=nl.value)
 
 
 def batch_band(prob, **settings):
