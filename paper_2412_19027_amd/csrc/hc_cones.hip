@@ -36,15 +36,21 @@ __device__ inline double sq(double x) { return x * x; }
 // small dense helpers (per lane)
 // ===========================================================================
 
-// one-sided Jacobi on the 3 rows of G (3 x nc, row-major, nc <= 6):
-// on return rows are orthogonal, U (3x3, row-major) accumulates G = U G'.
-__device__ void jacobi_rows3(double* G, int nc, double* U) {
+// one-sided Jacobi on the 3 rows of G (3 x NC, row-major): on return rows
+// are orthogonal, U (3x3, row-major) accumulates G = U G'.  NC is a
+// compile-time size so that every index is static (registers, no scratch).
+template <int NC>
+__device__ void jacobi_rows3(double* G, double* U) {
+  constexpr int nc = NC;
+#pragma unroll
   for (int i = 0; i < 9; ++i) U[i] = (i % 4 == 0) ? 1.0 : 0.0;
   for (int sweep = 0; sweep < 40; ++sweep) {
     bool rot = false;
+#pragma unroll
     for (int pq = 0; pq < 3; ++pq) {
       const int p = (pq == 2) ? 1 : 0, q = (pq == 0) ? 1 : 2;
       double a = 0, b = 0, g = 0;
+#pragma unroll
       for (int c = 0; c < nc; ++c) {
         a += G[p * nc + c] * G[p * nc + c];
         b += G[q * nc + c] * G[q * nc + c];
@@ -55,11 +61,13 @@ __device__ void jacobi_rows3(double* G, int nc, double* U) {
       const double zeta = (b - a) / (2.0 * g);
       const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
       const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+#pragma unroll
       for (int c = 0; c < nc; ++c) {
         const double gp = G[p * nc + c], gq = G[q * nc + c];
         G[p * nc + c] = cs * gp - sn * gq;
         G[q * nc + c] = sn * gp + cs * gq;
       }
+#pragma unroll
       for (int r = 0; r < 3; ++r) {
         const double up = U[r * 3 + p], uq = U[r * 3 + q];
         U[r * 3 + p] = cs * up - sn * uq;
@@ -294,7 +302,7 @@ __device__ inline void sym_scale_one(const SegDev& g, int64_t i, const double* _
   for (int j = 0; j < d; ++j) hdiag[g.base + j * N + i] = e2 * (2.0 * wb[j] * wb[j] - (j == 0 ? 1.0 : -1.0));
 }
 
-__global__ void k_sym_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+__global__ __launch_bounds__(CONE_BLOCK) void k_sym_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
                             double* __restrict__ hdiag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < g.count) sym_scale_one(g, i, s, z, hdiag);
@@ -304,7 +312,7 @@ __global__ void k_sym_scale(SegDev g, const double* __restrict__ s, const double
 // sig_h 21..23, grad 24..26, branch 27
 constexpr int NS_LAM = 0, NS_V = 3, NS_UH = 12, NS_SH = 21, NS_GRAD = 24, NS_BR = 27;
 
-__global__ void k_nonsym_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z, double mu,
+__global__ __launch_bounds__(CONE_BLOCK) void k_nonsym_scale(SegDev g, const double* __restrict__ s, const double* __restrict__ z, double mu,
                                int force_dual, double* __restrict__ hdiag, int* __restrict__ pd_count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.count) return;
@@ -325,14 +333,29 @@ __global__ void k_nonsym_scale(SegDev g, const double* __restrict__ s, const dou
   const double mut_i = (st[0] * zt[0] + st[1] * zt[1] + st[2] * zt[2]) / 3.0;
   bool dual = force_dual || !ok || !(mu_i * mut_i - 1.0 >= 1.4901161193847656e-08);
   // factor of Hess f and its SVD (Hess f^-1 = Uh diag(1/sig^2) Uh')
-  double G[18], Uh[9];
-  const int nc = is_exp ? exp_hess_factor(zv, G) : pow_hess_factor(zv, a, G);
-  jacobi_rows3(G, nc, Uh);
-  double sig[3];
-  for (int r = 0; r < 3; ++r) {
-    double acc = 0;
-    for (int c = 0; c < nc; ++c) acc += G[r * nc + c] * G[r * nc + c];
-    sig[r] = sqrt(acc);
+  double Uh[9], sig[3];
+  if (is_exp) {
+    double G[12];
+    exp_hess_factor(zv, G);
+    jacobi_rows3<4>(G, Uh);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      double acc = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc += G[r * 4 + c] * G[r * 4 + c];
+      sig[r] = sqrt(acc);
+    }
+  } else {
+    double G[18];
+    pow_hess_factor(zv, a, G);
+    jacobi_rows3<6>(G, Uh);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      double acc = 0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc += G[r * 6 + c] * G[r * 6 + c];
+      sig[r] = sqrt(acc);
+    }
   }
   double lam[3], V[9];
   if (!dual) {
@@ -360,7 +383,7 @@ __global__ void k_nonsym_scale(SegDev g, const double* __restrict__ s, const dou
     }
     bool fin = isfinite(c1) && isfinite(c2) && isfinite(c3) && dd > 0.0 && uHu > 0.0;
     if (fin) {
-      jacobi_rows3(Gp, 3, V);
+      jacobi_rows3<3>(Gp, V);
       for (int r = 0; r < 3; ++r) lam[r] = Gp[r * 3 + 0] * Gp[r * 3 + 0] + Gp[r * 3 + 1] * Gp[r * 3 + 1] +
                                            Gp[r * 3 + 2] * Gp[r * 3 + 2];
     } else {
@@ -491,7 +514,7 @@ __device__ inline void cone_apply_one(const SegDev& g, int64_t i, int mode, doub
   }
 }
 
-__global__ void k_cone_apply(SegDev g, int mode, double delta, const double* __restrict__ x,
+__global__ __launch_bounds__(CONE_BLOCK) void k_cone_apply(SegDev g, int mode, double delta, const double* __restrict__ x,
                              double* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < g.count) cone_apply_one(g, i, mode, delta, x, nullptr, y);
@@ -505,7 +528,7 @@ struct SegTable {
   int32_t nseg;
 };
 
-__global__ void k_cone_apply_fused(SegTable tb, int mode, double delta, const double* __restrict__ x,
+__global__ __launch_bounds__(CONE_BLOCK) void k_cone_apply_fused(SegTable tb, int mode, double delta, const double* __restrict__ x,
                                    const double* __restrict__ dsr, double* __restrict__ y) {
   int s = 0;
   while (s + 1 < tb.nseg && (int)blockIdx.x >= tb.first[s + 1]) ++s;
@@ -605,7 +628,7 @@ void cone_apply(const SegDev& g, int mode, double delta, const double* x, double
   HC_LAUNCH_CHECK();
 }
 
-__global__ void k_cone_recover(SegDev g, const double* __restrict__ dsr, const double* __restrict__ dz,
+__global__ __launch_bounds__(CONE_BLOCK) void k_cone_recover(SegDev g, const double* __restrict__ dsr, const double* __restrict__ dz,
                                double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < g.count) cone_apply_one(g, i, 0, 0.0, dz, dsr, out);
@@ -659,7 +682,7 @@ void cone_apply_all(const std::vector<SegDev>& segs, int mode, double delta, con
   flush();
 }
 
-__global__ void k_sym_scale_fused(SegTable tb, const double* __restrict__ s, const double* __restrict__ z,
+__global__ __launch_bounds__(CONE_BLOCK) void k_sym_scale_fused(SegTable tb, const double* __restrict__ s, const double* __restrict__ z,
                                   double* __restrict__ hdiag) {
   int q = 0;
   while (q + 1 < tb.nseg && (int)blockIdx.x >= tb.first[q + 1]) ++q;
@@ -806,7 +829,7 @@ __global__ void k_cone_mblock(SegDev g, double delta) {
   if (i < g.count) cone_mblock_one(g, i, delta);
 }
 
-__global__ void k_cone_mblock_fused(SegTable tb, double delta) {
+__global__ __launch_bounds__(CONE_BLOCK) void k_cone_mblock_fused(SegTable tb, double delta) {
   int q = 0;
   while (q + 1 < tb.nseg && (int)blockIdx.x >= tb.first[q + 1]) ++q;
   const int64_t i = (int64_t)(blockIdx.x - tb.first[q]) * blockDim.x + threadIdx.x;
@@ -914,14 +937,14 @@ __device__ inline void cone_ds_one(const SegDev& g, int64_t i, const double* __r
   }
 }
 
-__global__ void k_cone_ds(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+__global__ __launch_bounds__(CONE_BLOCK) void k_cone_ds(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
                           const double* __restrict__ dsa, const double* __restrict__ dza, double sm,
                           double* __restrict__ ds) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < g.count) cone_ds_one(g, i, s, z, dsa, dza, sm, ds);
 }
 
-__global__ void k_cone_ds_fused(SegTable tb, const double* __restrict__ s, const double* __restrict__ z,
+__global__ __launch_bounds__(CONE_BLOCK) void k_cone_ds_fused(SegTable tb, const double* __restrict__ s, const double* __restrict__ z,
                                 const double* __restrict__ dsa, const double* __restrict__ dza, double sm,
                                 double* __restrict__ ds) {
   int q = 0;
@@ -1020,13 +1043,13 @@ __device__ inline void block_min_to(double a, double* __restrict__ partial) {
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void k_step_sym(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+__global__ __launch_bounds__(CONE_BLOCK) void k_step_sym(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
                            const double* __restrict__ ds, const double* __restrict__ dz, double* __restrict__ partial) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   block_min_to(i < g.count ? step_sym_one(g, i, s, z, ds, dz) : INFINITY, partial);
 }
 
-__global__ void k_step_sym_fused(SegTable tb, const double* __restrict__ s, const double* __restrict__ z,
+__global__ __launch_bounds__(CONE_BLOCK) void k_step_sym_fused(SegTable tb, const double* __restrict__ s, const double* __restrict__ z,
                                  const double* __restrict__ ds, const double* __restrict__ dz,
                                  double* __restrict__ partial) {
   int q = 0;
@@ -1463,12 +1486,10 @@ int64_t cone_step_sym_all(const std::vector<SegDev>& segs, const double* s, cons
   return off;
 }
 
-struct Trials {
-  double a[8];
-};
-
-__global__ void k_trial_nonsym(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
-                               const double* __restrict__ ds, const double* __restrict__ dz, Trials tr, int ntrial,
+// trial t is a0 r^t, the products formed in sequence (as the host forms them)
+__global__ __launch_bounds__(CONE_BLOCK) void k_trial_nonsym(SegDev g, const double* __restrict__ s, const double* __restrict__ z,
+                               const double* __restrict__ ds, const double* __restrict__ dz, double a0,
+                               double ratio, int ntrial,
                                int check_nbhd, double beta, double c0, double c1, double c2, double nu1,
                                unsigned long long* __restrict__ partial) {
   __shared__ unsigned long long red[CONE_BLOCK];
@@ -1486,8 +1507,8 @@ __global__ void k_trial_nonsym(SegDev g, const double* __restrict__ s, const dou
       dzv[j] = dz[g.base + j * N + i];
     }
     mask = 0;
-    for (int t = 0; t < ntrial; ++t) {
-      const double a = tr.a[t];
+    double a = a0;
+    for (int t = 0; t < ntrial; ++t, a *= ratio) {
       double sa[3], za[3];
       for (int j = 0; j < 3; ++j) {
         sa[j] = sv[j] + a * dsv[j];
@@ -1518,14 +1539,8 @@ int cone_trial_nonsym(const SegDev& g, const double* s, const double* z, const d
                       double a0, double ratio, int ntrial, int check_nbhd, double beta, double c0, double c1,
                       double c2, double nu1, unsigned long long* partial, hipStream_t st) {
   if (g.count == 0) return 0;
-  Trials tr;
-  double a = a0;
-  for (int t = 0; t < 8; ++t) {
-    tr.a[t] = a;
-    a *= ratio;
-  }
   const int nb = cone_blocks(g);
-  hipLaunchKernelGGL(k_trial_nonsym, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, ds, dz, tr, std::min(ntrial, 8),
+  hipLaunchKernelGGL(k_trial_nonsym, dim3(nb), dim3(CONE_BLOCK), 0, st, g, s, z, ds, dz, a0, ratio, std::min(ntrial, 8),
                      check_nbhd, beta, c0, c1, c2, nu1, partial);
   HC_LAUNCH_CHECK();
   return nb;

@@ -47,6 +47,7 @@ struct ColMap {
   const int32_t* small = nullptr;
   const int32_t* large = nullptr;
   const int64_t* tc_ptr = nullptr;     // nt + 1
+  int32_t tail_threads = 64;           // threads per tail index in the tail gather (64, 256 or 1024)
   const int32_t* tc_leaf = nullptr;
   const int32_t* tc_row = nullptr;
 };

@@ -223,12 +223,19 @@ __global__ __launch_bounds__(64) void k_leaf_fwd(ColMap cm, const double* __rest
 
 // uT[t] -= sum over the couplings (b, a) of t of sum_j W_b[a][j] y_b[j]; one
 // wave per tail index, lanes over its couplings, then a shuffle tree
-__global__ __launch_bounds__(64) void k_leaf_tail(ColMap cm, const double* __restrict__ y, double* __restrict__ uT) {
+// one workgroup per tail index, of cm.tail_threads threads (its (leaf, row)
+// pairs split over the waves: each pair is a chain of dependent loads, so the
+// chains of many pairs must be in flight at once); per-wave shuffle sums meet
+// in LDS in a fixed order
+constexpr int TAIL_THREADS_MAX = 1024;
+__global__ __launch_bounds__(TAIL_THREADS_MAX) void k_leaf_tail(ColMap cm, const double* __restrict__ y,
+                                                                double* __restrict__ uT) {
+  __shared__ double part[TAIL_THREADS_MAX / 64];
   const int64_t t = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
   const int64_t e0 = cm.tc_ptr[t], e1 = cm.tc_ptr[t + 1];
   double acc = 0.0;
-  for (int64_t e = e0 + lane; e < e1; e += 64) {
+  for (int64_t e = e0 + tid; e < e1; e += nthr) {
     const int b = cm.tc_leaf[e], a = cm.tc_row[e];
     const int l = cm.lsize[b], cnt = cm.ccnt[b];
     const double* cv = cm.cval + cm.cval_off[b];   // W_b column-major (cnt x l)
@@ -238,7 +245,13 @@ __global__ __launch_bounds__(64) void k_leaf_tail(ColMap cm, const double* __res
     acc += v;
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (lane == 0 && e1 > e0) uT[t] -= acc;
+  if (lane == 0) part[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0 && e1 > e0) {
+    double s = 0.0;
+    for (int w = 0; w < nthr / 64; ++w) s += part[w];
+    uT[t] -= s;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_leaf_bwd_small(ColMap cm, const double* __restrict__ xT,
@@ -309,7 +322,8 @@ void leaf_forward(const ColMap& cm, const double* u, double* y, double* uT, hipS
     HC_LAUNCH_CHECK();
   }
   if (cm.nt) {
-    hipLaunchKernelGGL(k_leaf_tail, dim3((unsigned)cm.nt), dim3(64), 0, st, cm, (const double*)y, uT);
+    const int thr = cm.tail_threads == 1024 || cm.tail_threads == 256 ? cm.tail_threads : 64;
+    hipLaunchKernelGGL(k_leaf_tail, dim3((unsigned)cm.nt), dim3(thr), 0, st, cm, (const double*)y, uT);
     HC_LAUNCH_CHECK();
   }
 }

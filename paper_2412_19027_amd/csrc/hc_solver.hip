@@ -2378,6 +2378,10 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   cm.small = upload(buf, S->leaf_small, st);
   cm.large = upload(buf, S->leaf_large, st);
   cm.tc_ptr = upload(buf, S->tc_ptr, st);
+  {   // threads per tail index: enough for the mean number of (leaf, row) pairs
+    const double mean = nt > 0 && !S->tc_ptr.empty() ? (double)S->tc_ptr[nt] / (double)nt : 0.0;
+    cm.tail_threads = mean >= 256 ? 1024 : mean >= 32 ? 256 : 64;
+  }
   cm.tc_leaf = upload(buf, S->tc_leaf, st);
   cm.tc_row = upload(buf, S->tc_row, st);
   cm.lval = buf.take<double>(S->lval_total + 1);

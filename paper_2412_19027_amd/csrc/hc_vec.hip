@@ -35,18 +35,30 @@ __global__ __launch_bounds__(256) void k_spmv(int32_t nrows, const int32_t* __re
 }
 
 // the long rows, one wave each
-__global__ __launch_bounds__(256) void k_spmv_long(int32_t nlong, const int32_t* __restrict__ rows,
-                                                   const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                                   const double* __restrict__ v, const double* __restrict__ x,
-                                                   double* __restrict__ y, double alpha, double beta) {
-  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-  const int lane = threadIdx.x & 63;
-  if (w >= nlong) return;
-  const int32_t row = rows[w], b = rp[row], e = rp[row + 1];
+// one workgroup of 1024 threads per long row (many independent loads in
+// flight for a row of tens of thousands of entries); per-wave shuffle sums
+// meet in LDS in a fixed order
+constexpr int LONG_THREADS = 1024;
+__global__ __launch_bounds__(LONG_THREADS) void k_spmv_long(int32_t nlong, const int32_t* __restrict__ rows,
+                                                            const int32_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ ci,
+                                                            const double* __restrict__ v,
+                                                            const double* __restrict__ x, double* __restrict__ y,
+                                                            double alpha, double beta) {
+  __shared__ double part[LONG_THREADS / 64];
+  if ((int32_t)blockIdx.x >= nlong) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int32_t row = rows[blockIdx.x], b = rp[row], e = rp[row + 1];
   double acc = 0.0;
-  for (int32_t p = b + lane; p < e; p += 64) acc += v[p] * x[ci[p]];
+  for (int32_t p = b + tid; p < e; p += LONG_THREADS) acc += v[p] * x[ci[p]];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) y[row] = alpha * acc + (beta == 0.0 ? 0.0 : beta * y[row]);
+  if (lane == 0) part[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int w = 0; w < LONG_THREADS / 64; ++w) s += part[w];
+    y[row] = alpha * s + (beta == 0.0 ? 0.0 : beta * y[row]);
+  }
 }
 
 void spmv(const Csr& A, const double* x, double* y, double alpha, double beta, hipStream_t st) {
@@ -62,8 +74,8 @@ void spmv(const Csr& A, const double* x, double* y, double alpha, double beta, h
   }
   HC_LAUNCH_CHECK();
   if (A.nlong > 0) {
-    hipLaunchKernelGGL(k_spmv_long, dim3((unsigned)ceil_div((int64_t)A.nlong * 64, 256)), dim3(256), 0, st, A.nlong,
-                       A.longrows, A.rowptr, A.col, A.val, x, y, alpha, beta);
+    hipLaunchKernelGGL(k_spmv_long, dim3((unsigned)A.nlong), dim3(LONG_THREADS), 0, st, A.nlong, A.longrows,
+                       A.rowptr, A.col, A.val, x, y, alpha, beta);
     HC_LAUNCH_CHECK();
   }
 }

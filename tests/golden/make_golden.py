@@ -31,6 +31,7 @@ CASES = {
 for _s in (1, 2, 3, 4):
     CASES[f"sparse_socp_full_s{_s}"] = (lambda s: lambda: W.sparse_socp(s))(_s)
     CASES[f"psd_pow_full_s{_s}"] = (lambda s: lambda: W.psd_pow(s))(_s)
+    CASES[f"logreg_exp_full_s{_s}"] = (lambda s: lambda: W.logreg_exp(s))(_s)
 
 
 def main(names):
