@@ -37,13 +37,14 @@ def test_full_size_against_oracle_objective(key, make):
 
 
 SEED_CASES = [(f"{name}_full_s{s}", s, make) for s in (1, 2, 3, 4)
-              for name, make in (("sparse_socp", W.sparse_socp), ("psd_pow", W.psd_pow))]
+              for name, make in (("sparse_socp", W.sparse_socp), ("psd_pow", W.psd_pow),
+                                 ("logreg_exp", W.logreg_exp))]
 
 
 @pytest.mark.parametrize("key,seed,make", SEED_CASES, ids=[c[0] for c in SEED_CASES])
 def test_full_size_other_seeds_against_oracle(key, seed, make):
-    """The sparse-SOCP and PSD/power configurations at seeds 1-4, FP64,
-    against the oracle's objective (skipped for a seed whose golden value has
+    """The sparse-SOCP, PSD/power and logistic-regression configurations at
+    seeds 1-4, FP64, against the oracle's objective (skipped for a seed whose golden value has
     not been computed)."""
     if key not in GOLD:
         pytest.skip(f"no oracle value for {key}")
