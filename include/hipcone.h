@@ -122,6 +122,11 @@ typedef struct {
                              to the new equilibration, and the usual initial point
                              v_0 (tau = kappa = 1); 0: always from v_0 (0)        */
   double warm_blend;      /* 0.02                                                   */
+  double ir_mu_frac;      /* the refinement also stops once its residual is at most
+                             ir_mu_frac min(mu, 1) (1 + |rhs|_inf), mu the
+                             iteration's complementarity; < 0 picks 1e-3 for the
+                             mixed mode and 0 (off: the fixed tolerances alone) for
+                             FP64                                                 */
 } hc_settings;
 
 /* ---- device hand-off ------------------------------------------------------ */

@@ -315,6 +315,7 @@ void hc_server::wave_worker(int cap) {
         j->plan->mixed = false;
         j->plan->st.static_reg = 1e-8;
         j->plan->st.dyn_reg = std::ldexp(1.0, -104);
+        j->plan->st.ir_mu_frac = 0.0;
         j->first_iterations = inf.iterations;
         wave_upload(*j->plan, pool_base + j->offset, &hdesc[i], st);
         restarted = true;

@@ -1056,6 +1056,7 @@ void setup_host(hc_solver* S, const hc_problem* p) {
   for (int64_t t = S->nt; t < S->ld; ++t) S->tail_last.push_back(t + 1);   // identity padding
   if (S->st.static_reg <= 0) S->st.static_reg = S->mixed ? 3.4526698300124393e-04 : 1e-8;
   if (S->st.dyn_reg < 0) S->st.dyn_reg = S->mixed ? std::ldexp(1.0, -46) : std::ldexp(1.0, -104);
+  if (S->st.ir_mu_frac < 0) S->st.ir_mu_frac = S->mixed ? 1e-3 : 0.0;
 }
 
 // Groups of the Schur assembly (only without leaf blocks): the rows the pair
@@ -1787,10 +1788,17 @@ void solve_reg(hc_solver* S, const double* r1, const double* r2, double* x, doub
 // iterative refinement against the unregularised K; result in (xo, zo)
 int64_t kkt_solve_once(hc_solver* S, const double* r1, const double* r2, double* xo, double* zo, double* best_out,
                        double* nb_out);
+// the residual at which the refinement stops: the fixed tolerances, or (with
+// ir_mu_frac) a fraction of the iteration's mu relative to the right-hand side
+double ir_target(const hc_solver* S, double nb) {
+  return std::max(S->st.ir_abstol + S->st.ir_reltol * nb,
+                  S->st.ir_mu_frac * std::min(S->info.mu, 1.0) * (1.0 + nb));
+}
+
 int64_t kkt_solve(hc_solver* S, const double* r1, const double* r2, double* xo, double* zo) {
   double best = 0, nb = 0;
   int64_t k = kkt_solve_once(S, r1, r2, xo, zo, &best, &nb);
-  if (S->mixed && !S->use64 && !(best <= 1e-6 * (1.0 + nb))) {
+  if (S->mixed && !S->use64 && !(best <= std::max(1e-6 * (1.0 + nb), ir_target(S, nb)))) {
     fallback_fp64(S);
     k += kkt_solve_once(S, r1, r2, xo, zo, &best, &nb);
   }
@@ -1812,6 +1820,7 @@ int64_t kkt_solve_once(hc_solver* S, const double* r1, const double* r2, double*
   vcopy(n, r1, S->irrx, st);
   vcopy(m, r2, S->irrz, st);
   double best = nb, rnorm = nb;
+  const double target = ir_target(S, nb);
   bool have_best = false;
   int64_t solves = 0;
   for (int it = 0; it <= S->st.ir_max; ++it) {
@@ -1836,7 +1845,7 @@ int64_t kkt_solve_once(hc_solver* S, const double* r1, const double* r2, double*
         have_best = true;
       }
     }
-    if (rn <= S->st.ir_abstol + S->st.ir_reltol * nb) break;
+    if (rn <= target) break;
     if (it > 0 && rn > 0.5 * rnorm) break;
     std::swap(x, xn);
     std::swap(z, zn);
@@ -2982,6 +2991,7 @@ int32_t hc_settings_default(hc_settings* o) {
   o->leaf_blocks = 1;
   o->warm_start = 0;
   o->warm_blend = 0.02;
+  o->ir_mu_frac = -1.0;
   return HC_OK;
 }
 

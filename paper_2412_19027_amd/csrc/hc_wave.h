@@ -61,7 +61,7 @@ struct WaveDesc {
   int32_t n, m, w, W, nz, nn, nsoc, mtot;
   int32_t ir_max, max_iter, mixed, nte;   // nte: band entries with nonneg/cone terms
   double cscale, bnorm, qnorm, maxPdiag, nu1;
-  double eps_feas, eps_inf, static_reg, dyn_reg, ir_abstol, ir_reltol, step_fraction;
+  double eps_feas, eps_inf, static_reg, dyn_reg, ir_abstol, ir_reltol, step_fraction, ir_mu_frac;
   const int32_t *Arp, *Aci, *Atrp, *Atci, *Prp, *Pci, *te, *trp, *tm, *soc_off, *soc_moff, *colperm, *rowperm;
   const double *Av, *Atv, *Pv, *q, *b, *D, *E, *Pband, *Zband, *tc;
   double* v;                      // WV_COUNT work vectors of max(n, m) doubles

@@ -612,6 +612,7 @@ struct Wave {
   double* lds;        // WAVE_WB * (WAVE_WB + 1) + 640 doubles: the factorisation's window and panel
   int L;              // max(n, m)
   double tau, kappa, delta, sdmax, xPx;
+  double mu_it = 0.0; // the iteration's mu (the refinement's relative stop; 0 at the initial point)
   bool use64;
   int64_t hits, fallbacks, irs, facts;
 
@@ -706,6 +707,11 @@ struct Wave {
     c_apply(D, 1, delta, w1, nullptr, z);
   }
 
+  // the residual at which the refinement stops (as the per-slot solver)
+  __device__ double ir_target(double nb) const {
+    return fmax(D.ir_abstol + D.ir_reltol * nb, D.ir_mu_frac * fmin(mu_it, 1.0) * (1.0 + nb));
+  }
+
   // iterative refinement against the unregularised K; result in (xo, zo)
   __device__ void kkt_solve_once(const double* r1, const double* r2, double* xo, double* zo, double* best_out,
                                  double* nb_out) {
@@ -718,6 +724,7 @@ struct Wave {
     v_copy(n, r1, rx);
     v_copy(m, r2, rz);
     double best = nb, rnorm = nb;
+    const double target = ir_target(nb);
     bool have_best = false;
     for (int it = 0; it <= D.ir_max; ++it) {
       solve_reg(rx, rz, kx, kz);
@@ -741,7 +748,7 @@ struct Wave {
           have_best = true;
         }
       }
-      if (rn <= D.ir_abstol + D.ir_reltol * nb) break;
+      if (rn <= target) break;
       if (it > 0 && rn > 0.5 * rnorm) break;
       double* tp;
       tp = x; x = xn; xn = tp;
@@ -764,7 +771,7 @@ struct Wave {
   __device__ void kkt_solve(const double* r1, const double* r2, double* xo, double* zo) {
     double best = 0.0, nb = 0.0;
     kkt_solve_once(r1, r2, xo, zo, &best, &nb);
-    if (D.mixed && !use64 && !(best <= 1e-6 * (1.0 + nb))) {
+    if (D.mixed && !use64 && !(best <= fmax(1e-6 * (1.0 + nb), ir_target(nb)))) {
       use64 = true;            // FP64 factorisation for the rest of the iteration
       factor(true);
       fallbacks++;
@@ -863,6 +870,7 @@ struct Wave {
     const int n = D.n, m = D.m;
     const double mu = (R.sz + kappa * tau) / D.nu1;
     const double gt = kappa + R.qx + R.bz + R.xPx / tau;
+    mu_it = mu;
     use64 = false;
     c_scale(D, V(WV_S), V(WV_Z));
     factor(false);
@@ -1066,6 +1074,7 @@ void layout(const WavePlan& P, Carve& c, WaveDesc* d, hipStream_t st) {
   d->dyn_reg = P.st.dyn_reg;
   d->ir_abstol = P.st.ir_abstol;
   d->ir_reltol = P.st.ir_reltol;
+  d->ir_mu_frac = P.st.ir_mu_frac;
   d->step_fraction = P.st.step_fraction;
   d->Arp = put(c, P.Arp, st);
   d->Aci = put(c, P.Aci, st);

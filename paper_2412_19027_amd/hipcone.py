@@ -49,7 +49,7 @@ class hc_settings(C.Structure):
                 ("beta", C.c_double), ("backtrack", C.c_double), ("step_fraction", C.c_double),
                 ("equilibrate", C.c_int32), ("equil_iters", C.c_int32), ("force_dual_scaling", C.c_int32),
                 ("verbose", C.c_int32), ("profile", C.c_int32), ("leaf_blocks", C.c_int32),
-                ("warm_start", C.c_int32), ("warm_blend", C.c_double)]
+                ("warm_start", C.c_int32), ("warm_blend", C.c_double), ("ir_mu_frac", C.c_double)]
 
 
 class hc_device(C.Structure):
