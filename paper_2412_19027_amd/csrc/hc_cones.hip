@@ -56,7 +56,7 @@ __device__ void jacobi_rows3(double* G, double* U) {
         b += G[q * nc + c] * G[q * nc + c];
         g += G[p * nc + c] * G[q * nc + c];
       }
-      if (g == 0.0 || fabs(g) <= 1e-16 * sqrt(a * b)) continue;
+      if (g == 0.0 || fabs(g) <= 1e-15 * sqrt(a * b)) continue;   // orthogonal to a few ulps
       rot = true;
       const double zeta = (b - a) / (2.0 * g);
       const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -220,7 +220,10 @@ __device__ bool exp_conj(const double* s, double* z) {
     const double h = log1p(y) + y - r;
     const double dy = -h / (1.0 / (1.0 + y) + 1.0);
     y += dy;
-    if (fabs(dy) <= 1e-16 * y) break;
+    // the exact steps increase y; once a step is down to a couple of ulps
+    // (or rounding turns it negative) y is the root to working accuracy (a
+    // bound of 1e-16 y, below half an ulp, let most cones run all 200 steps)
+    if (!(dy > 4e-16 * y)) break;
   }
   const double t = 1.0 / y;
   const double u = -t / s[1];
@@ -1230,7 +1233,7 @@ __device__ void wave_jacobi_cols(double* B, int k, double* W, int lane, int* fla
         b += __shfl_xor(b, off, 64);
         gg += __shfl_xor(gg, off, 64);
       }
-      if (gg == 0.0 || fabs(gg) <= 1e-16 * sqrt(a * b)) continue;
+      if (gg == 0.0 || fabs(gg) <= 1e-15 * sqrt(a * b)) continue;   // orthogonal to a few ulps
       const double zeta = (b - a) / (2.0 * gg);
       const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
       const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
