@@ -46,10 +46,10 @@ struct ColMap {
   int64_t nsmall = 0, nlarge = 0;
   const int32_t* small = nullptr;
   const int32_t* large = nullptr;
-  const int64_t* tc_ptr = nullptr;     // nt + 1
+  const int64_t* tc_ptr = nullptr;     // nt + 1: per tail index its range of W entries
   int32_t tail_threads = 64;           // threads per tail index in the tail gather (64, 256 or 1024)
-  const int32_t* tc_leaf = nullptr;
-  const int32_t* tc_row = nullptr;
+  const int64_t* te_cv = nullptr;      // per entry: index into cval
+  const int32_t* te_y = nullptr;       // per entry: the leaf column it multiplies
 };
 
 // Schur assembly over row pairs of one cone (as assemble_pairs), routed

@@ -223,9 +223,9 @@ __global__ __launch_bounds__(64) void k_leaf_fwd(ColMap cm, const double* __rest
 
 // uT[t] -= sum over the couplings (b, a) of t of sum_j W_b[a][j] y_b[j]; one
 // wave per tail index, lanes over its couplings, then a shuffle tree
-// one workgroup per tail index, of cm.tail_threads threads (its (leaf, row)
-// pairs split over the waves: each pair is a chain of dependent loads, so the
-// chains of many pairs must be in flight at once); per-wave shuffle sums meet
+// one workgroup per tail index, of cm.tail_threads threads: its W entries
+// (flattened at set-up into (cval index, leaf column) pairs, so each costs
+// two independent gathers) split over the threads; per-wave shuffle sums meet
 // in LDS in a fixed order
 constexpr int TAIL_THREADS_MAX = 1024;
 __global__ __launch_bounds__(TAIL_THREADS_MAX) void k_leaf_tail(ColMap cm, const double* __restrict__ y,
@@ -235,15 +235,7 @@ __global__ __launch_bounds__(TAIL_THREADS_MAX) void k_leaf_tail(ColMap cm, const
   const int tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
   const int64_t e0 = cm.tc_ptr[t], e1 = cm.tc_ptr[t + 1];
   double acc = 0.0;
-  for (int64_t e = e0 + tid; e < e1; e += nthr) {
-    const int b = cm.tc_leaf[e], a = cm.tc_row[e];
-    const int l = cm.lsize[b], cnt = cm.ccnt[b];
-    const double* cv = cm.cval + cm.cval_off[b];   // W_b column-major (cnt x l)
-    const int32_t* cols = cm.lcols + cm.lcol_off[b];
-    double v = 0.0;
-    for (int j = 0; j < l; ++j) v += cv[a + (int64_t)j * cnt] * y[cols[j]];
-    acc += v;
-  }
+  for (int64_t e = e0 + tid; e < e1; e += nthr) acc += cm.cval[cm.te_cv[e]] * y[cm.te_y[e]];
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if (lane == 0) part[tid >> 6] = acc;
   __syncthreads();

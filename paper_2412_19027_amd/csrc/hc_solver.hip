@@ -115,8 +115,9 @@ struct hc_solver {
   bool leaves = false;             // any leaf block
   std::vector<int32_t> col_leaf, col_loc, tail_cols, leaf_size, leaf_cols, leaf_ccnt, leaf_clist;
   std::vector<int64_t> leaf_lval_off, leaf_lcol_off, leaf_clist_off, leaf_cval_off;
-  std::vector<int32_t> leaf_small, leaf_large, tc_leaf, tc_row;   // solve lists; couplings per tail index
-  std::vector<int64_t> tc_ptr;
+  std::vector<int32_t> leaf_small, leaf_large;   // solve lists
+  std::vector<int64_t> tc_ptr, te_cv;             // per tail index its W entries: index into cval,
+  std::vector<int32_t> te_y;                      // and the leaf column they multiply
   int64_t lval_total = 0, cval_total = 0;
   double leaf_flops = 0;
   int64_t mtotal = 0, stotal = 0;  // M entries, state entries
@@ -809,20 +810,29 @@ void build_leaves(hc_solver* S) {
   S->leaf_large.clear();
   for (int32_t b = 0; b < (int32_t)S->leaf_size.size(); ++b)
     (S->leaf_size[b] <= LEAF_SMALL ? S->leaf_small : S->leaf_large).push_back(b);
+  // per tail index t the entries of its rows of the W_b, flattened: W_b[a][j]
+  // (at cval index cval_off[b] + a + j cnt_b) times y at leaf column j, for
+  // every leaf b coupled to t (a: t's coupling row in b), in leaf order
   S->tc_ptr.assign(S->nt + 1, 0);
   for (size_t b = 0; b < S->leaf_size.size(); ++b)
-    for (int a = 0; a < S->leaf_ccnt[b]; ++a) S->tc_ptr[S->leaf_clist[S->leaf_clist_off[b] + a] + 1]++;
+    for (int a = 0; a < S->leaf_ccnt[b]; ++a)
+      S->tc_ptr[S->leaf_clist[S->leaf_clist_off[b] + a] + 1] += S->leaf_size[b];
   for (int64_t t2 = 0; t2 < S->nt; ++t2) S->tc_ptr[t2 + 1] += S->tc_ptr[t2];
-  S->tc_leaf.assign(S->tc_ptr[S->nt], 0);
-  S->tc_row.assign(S->tc_ptr[S->nt], 0);
+  S->te_cv.assign(S->tc_ptr[S->nt], 0);
+  S->te_y.assign(S->tc_ptr[S->nt], 0);
   {
     std::vector<int64_t> fill(S->tc_ptr.begin(), S->tc_ptr.end() - 1);
-    for (size_t b = 0; b < S->leaf_size.size(); ++b)
-      for (int a = 0; a < S->leaf_ccnt[b]; ++a) {
-        const int64_t o = fill[S->leaf_clist[S->leaf_clist_off[b] + a]]++;
-        S->tc_leaf[o] = (int32_t)b;
-        S->tc_row[o] = a;
+    for (size_t b = 0; b < S->leaf_size.size(); ++b) {
+      const int l = S->leaf_size[b], cnt = S->leaf_ccnt[b];
+      for (int a = 0; a < cnt; ++a) {
+        const int32_t tt = S->leaf_clist[S->leaf_clist_off[b] + a];
+        for (int j = 0; j < l; ++j) {
+          const int64_t o = fill[tt]++;
+          S->te_cv[o] = S->leaf_cval_off[b] + a + (int64_t)j * cnt;
+          S->te_y[o] = S->leaf_cols[S->leaf_lcol_off[b] + j];
+        }
       }
+    }
   }
   // Envelope of the tail in its order: the first tail column each tail row is
   // coupled to, through a cone's clique (dense rows and large SOC rank-2 rows
@@ -2387,12 +2397,12 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   cm.small = upload(buf, S->leaf_small, st);
   cm.large = upload(buf, S->leaf_large, st);
   cm.tc_ptr = upload(buf, S->tc_ptr, st);
-  {   // threads per tail index: enough for the mean number of (leaf, row) pairs
+  {   // threads per tail index: enough for the mean number of W entries
     const double mean = nt > 0 && !S->tc_ptr.empty() ? (double)S->tc_ptr[nt] / (double)nt : 0.0;
-    cm.tail_threads = mean >= 256 ? 1024 : mean >= 32 ? 256 : 64;
+    cm.tail_threads = mean >= 1024 ? 1024 : mean >= 128 ? 256 : 64;
   }
-  cm.tc_leaf = upload(buf, S->tc_leaf, st);
-  cm.tc_row = upload(buf, S->tc_row, st);
+  cm.te_cv = upload(buf, S->te_cv, st);
+  cm.te_y = upload(buf, S->te_y, st);
   cm.lval = buf.take<double>(S->lval_total + 1);
   cm.cval = buf.take<double>(S->cval_total + 1);
   cm.sink = buf.take<double>(1);
