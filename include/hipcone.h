@@ -303,6 +303,18 @@ int32_t hc_test_kkt_solve(hc_solver* s, double mu, int32_t force_dual, const dou
 int32_t hc_test_kkt_ops(hc_solver* s, double mu, int32_t force_dual, const double* r1,
                         const double* r2, double* xr, double* zr, double* kx, double* kz);
 
+/* hc_test_ordered_sums: host-only check of a set-up handle's ordered Schur
+ * sums (the A' M A products of Sec. 3.7's Schur complement grouped by the
+ * entry of S they land on, and the leaf blocks' updates of the tail grouped
+ * by tail entry; no device).  With synthetic weights in place of M it adds
+ * every product where it lands, one by one, and again from the ordered
+ * lists: out[0] = max |difference| / max |entry|, out[1] = leaf update slots
+ * not listed exactly once or listed under the wrong tail entry, out[2] = the
+ * number of destinations.  *ordered = 0 when the lists were not built
+ * (beyond their size limit: the FP64-atomic kernels run), and then out is
+ * zero.  HC_ERR_INVALID_ARG on NULL. */
+int32_t hc_test_ordered_sums(hc_solver* s, int32_t* ordered, double* out);
+
 /* Test entry: the Schur complement S = P + delta I + A' M A (Sec. 3.7, cone
  * rows eliminated) assembled at the scaling of the current iterate, and its
  * Cholesky factor.  Only for solvers whose columns all sit in the dense block

@@ -50,6 +50,11 @@ struct ColMap {
   int32_t tail_threads = 64;           // threads per tail index in the tail gather (64, 256 or 1024)
   const int64_t* te_cv = nullptr;      // per entry: index into cval
   const int32_t* te_y = nullptr;       // per entry: the leaf column it multiplies
+  // per leaf the first of its cnt (cnt + 1) / 2 slots: with lslot set the leaf
+  // factor stores -(W_b W_b')[a][c] there (pair p = a (a + 1) / 2 + c) and an
+  // ordered sum adds the slots to S_TT, instead of FP64 atomics
+  double* lslot = nullptr;
+  const int64_t* lp_off = nullptr;
 };
 
 // Schur assembly over row pairs of one cone (as assemble_pairs), routed
@@ -59,7 +64,8 @@ void assemble_pairs_map(int64_t ntask, const int32_t* tra, const int32_t* trb, c
 // P (full CSR, lower part used) and delta on the diagonal, through the map.
 void add_P_delta_map(const Csr& P, int64_t n, double delta, const ColMap& cm, hipStream_t st);
 // Per leaf: Cholesky of S_bb (pivots <= tol replaced by fix and counted),
-// W_b = S_Tb L_b^-T, and S_TT -= W_b W_b' (lower part, FP64 atomics).
+// W_b = S_Tb L_b^-T, and S_TT -= W_b W_b' (lower part: into cm.lslot for an
+// ordered sum when set, else with FP64 atomics).
 void leaf_factor(const ColMap& cm, double tol, double fix, unsigned long long* hits, hipStream_t st);
 // Forward half of the leaf solve: y_b = L_b^-1 u_b written to y at the leaf
 // columns, then uT[t] -= sum over the leaves coupled to t of (W_b y_b)[t]

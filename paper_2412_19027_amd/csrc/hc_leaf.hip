@@ -162,7 +162,8 @@ __global__ __launch_bounds__(64) void k_leaf_factor(ColMap cm, double tol, doubl
     const int c = p - a * (a + 1) / 2;
     double v = 0.0;
     for (int j = 0; j < l; ++j) v += W[a][j] * W[c][j];
-    atomicAdd(&cm.ST[cl[a] + (int64_t)cl[c] * cm.ldt], -v);
+    if (cm.lslot) cm.lslot[cm.lp_off[b] + p] = -v;
+    else atomicAdd(&cm.ST[cl[a] + (int64_t)cl[c] * cm.ldt], -v);
   }
 }
 

@@ -23,6 +23,7 @@
 //     [1e-4, 1e4], row factors averaged over each SOC/exp/pow/PSD cone), cost
 //     scale 1/max(1, mean column max of P, |Dq|_inf);
 //   * dual-infeasibility test multiplies by q'x.
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -109,6 +110,20 @@ struct hc_solver {
   std::vector<std::pair<int, int64_t>> pdense;
   std::vector<int32_t> pe_rp, pe_e, pe_p;
   int64_t pe_rows = 0;
+  // and per cone of those segments (pdense_coff: each segment's first cone)
+  // its columns with their entries, for the column-ordered T rows
+  std::vector<int64_t> pdense_coff, pc_cu_off, pc_cu_ptr;
+  std::vector<int32_t> pc_cu_col, pc_cu_b, pc_cu_p;
+  PsdCols pcols;
+  // ordered Schur sums (build_ordered): the products of the pair tasks grouped
+  // by the entry of S they land on, and the leaves' updates of S_TT grouped by
+  // tail entry (leaf_lp_off: each leaf's first slot); `ordered` is false when
+  // the lists would exceed ORDERED_MAX_TERMS (the FP64-atomic kernels run)
+  bool ordered = false;
+  std::vector<int64_t> op_ptr, op_dst, ol_ptr, ol_dst, leaf_lp_off;
+  std::vector<int32_t> op_pm, op_pp, op_pq, ol_pp;
+  int64_t op_nshort = 0, ol_nshort = 0, lpair_total = 0;
+  OrderedSum opair, oleaf;
   // two-level split of the Schur complement (leaf blocks + dense tail)
   int64_t nt = 0;                  // tail columns
   std::vector<int64_t> tail_last;  // envelope of the tail (see dense_cholesky), padded to ld
@@ -446,6 +461,7 @@ constexpr int64_t PAIR_WIDE = 1024;   // products per pair task above which one 
 
 void build_psd_dense(hc_solver* S);
 void build_groups(hc_solver* S);
+void build_ordered(hc_solver* S);
 void build_lowrank(hc_solver* S, int nd);
 
 // Leaf blocks from the symbolic analysis of the columns outside the tail:
@@ -1067,6 +1083,7 @@ void setup_host(hc_solver* S, const hc_problem* p) {
   if (S->st.static_reg <= 0) S->st.static_reg = S->mixed ? 3.4526698300124393e-04 : 1e-8;
   if (S->st.dyn_reg < 0) S->st.dyn_reg = S->mixed ? std::ldexp(1.0, -46) : std::ldexp(1.0, -104);
   if (S->st.ir_mu_frac < 0) S->st.ir_mu_frac = S->mixed ? 1e-3 : 0.0;
+  build_ordered(S);
 }
 
 // Groups of the Schur assembly (only without leaf blocks): the rows the pair
@@ -1207,6 +1224,8 @@ void build_groups(hc_solver* S) {
 // Schur column), for n up to PSD_DENSE_NMAX, and with T within 4 GiB.
 void build_psd_dense(hc_solver* S) {
   S->pdense.clear();
+  S->pdense_coff.clear(), S->pc_cu_off.clear(), S->pc_cu_ptr.clear();
+  S->pc_cu_col.clear(), S->pc_cu_b.clear(), S->pc_cu_p.clear();
   S->pe_rp.assign(1, 0);
   S->pe_e.clear();
   S->pe_p.clear();
@@ -1264,6 +1283,171 @@ void build_psd_dense(hc_solver* S) {
     }
     S->pe_rp[j + 1] = (int32_t)S->pe_e.size();
   }
+  // per cone its columns, each with its entries (row of the cone, index in A)
+  // in row order
+  std::vector<std::array<int64_t, 3>> ent;
+  for (const auto& pd : S->pdense) {
+    const Segment& g = S->segs[pd.first];
+    S->pdense_coff.push_back((int64_t)S->pc_cu_off.size());
+    for (int64_t c = 0; c < g.count; ++c) {
+      S->pc_cu_off.push_back((int64_t)S->pc_cu_col.size());
+      ent.clear();
+      for (int b = 0; b < g.dim; ++b) {
+        const int64_t r = g.base + c * g.dim + b;
+        for (int32_t p = A.rp[r]; p < A.rp[r + 1]; ++p) ent.push_back({(int64_t)A.ci[p], (int64_t)b, (int64_t)p});
+      }
+      std::stable_sort(ent.begin(), ent.end(),
+                       [](const std::array<int64_t, 3>& x, const std::array<int64_t, 3>& y) { return x[0] < y[0]; });
+      for (size_t k = 0; k < ent.size(); ++k) {
+        if (k == 0 || ent[k][0] != ent[k - 1][0]) {
+          S->pc_cu_col.push_back((int32_t)ent[k][0]);
+          S->pc_cu_ptr.push_back((int64_t)S->pc_cu_b.size());
+        }
+        S->pc_cu_b.push_back((int32_t)ent[k][1]);
+        S->pc_cu_p.push_back((int32_t)ent[k][2]);
+      }
+    }
+  }
+  S->pc_cu_off.push_back((int64_t)S->pc_cu_col.size());
+  S->pc_cu_ptr.push_back((int64_t)S->pc_cu_b.size());
+}
+
+// Stable sort of 0 .. key.size() - 1 by key (LSD radix, 16-bit digits; digits
+// that every key shares are skipped).
+std::vector<int64_t> radix_order(const std::vector<uint64_t>& key) {
+  const int64_t np = (int64_t)key.size();
+  std::vector<int64_t> idx(np), tmp(np);
+  for (int64_t i = 0; i < np; ++i) idx[i] = i;
+  std::vector<int64_t> cnt(65537);
+  for (int sh = 0; sh < 64; sh += 16) {
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t i = 0; i < np; ++i) cnt[((key[i] >> sh) & 0xffff) + 1]++;
+    if (np == 0 || *std::max_element(cnt.begin(), cnt.end()) == np) continue;
+    for (int d = 0; d < 65536; ++d) cnt[d + 1] += cnt[d];
+    for (int64_t i = 0; i < np; ++i) tmp[cnt[(key[idx[i]] >> sh) & 0xffff]++] = idx[i];
+    idx.swap(tmp);
+  }
+  return idx;
+}
+
+// Group terms (sorted by destination, enumeration order kept within one) into
+// destinations: ptr / dst, short destinations first (order kept), then those
+// of more than ORDERED_WIDE terms; `perm` receives the term order to use.
+void group_terms(const std::vector<uint64_t>& key, std::vector<int64_t>& ptr, std::vector<int64_t>& dst,
+                 int64_t& nshort, std::vector<int64_t>& perm) {
+  const std::vector<int64_t> ord = radix_order(key);
+  const int64_t np = (int64_t)key.size();
+  std::vector<int64_t> b;   // start of each destination's run in ord
+  for (int64_t i = 0; i < np; ++i)
+    if (i == 0 || key[ord[i]] != key[ord[i - 1]]) b.push_back(i);
+  const int64_t nd = (int64_t)b.size();
+  b.push_back(np);
+  std::vector<int64_t> dorder;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int64_t d = 0; d < nd; ++d)
+      if ((b[d + 1] - b[d] > ORDERED_WIDE) == (pass == 1)) dorder.push_back(d);
+  nshort = 0;
+  for (int64_t d = 0; d < nd; ++d) nshort += (b[d + 1] - b[d] <= ORDERED_WIDE);
+  ptr.assign(1, 0);
+  dst.clear();
+  perm.clear();
+  perm.reserve(np);
+  for (int64_t d : dorder) {
+    for (int64_t i = b[d]; i < b[d + 1]; ++i) perm.push_back(ord[i]);
+    ptr.push_back((int64_t)perm.size());
+    dst.push_back((int64_t)key[ord[b[d]]]);
+  }
+}
+
+// The ordered Schur sums.  Every product a pair task adds, m_t A[ra][j]
+// A[rb][k] (doubled where two products of a row pair meet on the diagonal),
+// becomes a term of the entry of S it lands on, and each leaf's update of
+// S_TT[t_a][t_c] a slot; terms keep the order of the tasks, so each entry of
+// S is one sum in a fixed order (bitwise the same from run to run).  Entries
+// are encoded as in OrderedSum: the dense S (or S_TT) at hi + lo ld, a leaf
+// block at lval_off + hi + lo l, a coupling block at cval_off + row + col cnt.
+constexpr int64_t ORDERED_MAX_TERMS = int64_t(1) << 30;
+void build_ordered(hc_solver* S) {
+  S->ordered = false;
+  S->op_ptr.clear(), S->op_dst.clear(), S->op_pm.clear(), S->op_pp.clear(), S->op_pq.clear();
+  S->ol_ptr.clear(), S->ol_dst.clear(), S->ol_pp.clear(), S->leaf_lp_off.clear();
+  S->op_nshort = S->ol_nshort = S->lpair_total = 0;
+  const HostCsr& A = S->A;
+  const int64_t nt = (int64_t)S->tra.size();
+  int64_t np = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t ka = A.rp[S->tra[t] + 1] - A.rp[S->tra[t]], kb = A.rp[S->trb[t] + 1] - A.rp[S->trb[t]];
+    np += S->tra[t] == S->trb[t] ? ka * (ka + 1) / 2 : ka * kb;
+  }
+  int64_t nl = 0;
+  for (size_t b = 0; b < S->leaf_size.size(); ++b) nl += (int64_t)S->leaf_ccnt[b] * (S->leaf_ccnt[b] + 1) / 2;
+  if (np > ORDERED_MAX_TERMS || nl > ORDERED_MAX_TERMS || S->mtotal >= (int64_t(1) << 31)) return;
+  const int64_t ld = S->ld;
+  const uint64_t SEL1 = uint64_t(1) << 62, SEL2 = uint64_t(2) << 62;
+  const uint64_t NONE = ~uint64_t(0);   // two distinct leaves (never coupled); selector 3 is unused
+  auto enc = [&](int32_t j, int32_t k) -> uint64_t {
+    if (!S->leaves) return (uint64_t)std::max(j, k) + (uint64_t)std::min(j, k) * ld;
+    const int32_t bj = S->col_leaf[j], bk = S->col_leaf[k], lj = S->col_loc[j], lk = S->col_loc[k];
+    if (bj < 0 && bk < 0) return (uint64_t)std::max(lj, lk) + (uint64_t)std::min(lj, lk) * ld;
+    if (bj >= 0 && bk >= 0) {
+      if (bj != bk) return NONE;
+      return SEL1 | (uint64_t)(S->leaf_lval_off[bj] + std::max(lj, lk) + (int64_t)std::min(lj, lk) * S->leaf_size[bj]);
+    }
+    const int32_t b = bj >= 0 ? bj : bk, l = bj >= 0 ? lj : lk, t = bj >= 0 ? lk : lj;
+    const int32_t* cl = S->leaf_clist.data() + S->leaf_clist_off[b];
+    const int32_t* f = std::lower_bound(cl, cl + S->leaf_ccnt[b], t);
+    if (f == cl + S->leaf_ccnt[b] || *f != t) return NONE;
+    return SEL2 | (uint64_t)(S->leaf_cval_off[b] + (f - cl) + (int64_t)l * S->leaf_ccnt[b]);
+  };
+  {
+    std::vector<uint64_t> key;
+    std::vector<int32_t> pm, pp, pq;
+    key.reserve(np), pm.reserve(np), pp.reserve(np), pq.reserve(np);
+    auto term = [&](int64_t t, int32_t p, int32_t q, bool two) {
+      const uint64_t e = enc(A.ci[p], A.ci[q]);
+      if (e == NONE) return;
+      key.push_back(e);
+      pm.push_back((int32_t)S->tm[t]);
+      pp.push_back(p);
+      pq.push_back(two ? ~q : q);
+    };
+    for (int64_t t = 0; t < nt; ++t) {
+      const int32_t ra = S->tra[t], rb = S->trb[t];
+      if (ra == rb) {
+        for (int32_t p = A.rp[ra]; p < A.rp[ra + 1]; ++p)
+          for (int32_t q = A.rp[ra]; q <= p; ++q) term(t, p, q, false);
+      } else {
+        for (int32_t p = A.rp[ra]; p < A.rp[ra + 1]; ++p)
+          for (int32_t q = A.rp[rb]; q < A.rp[rb + 1]; ++q) term(t, p, q, A.ci[p] == A.ci[q]);
+      }
+    }
+    std::vector<int64_t> perm;
+    group_terms(key, S->op_ptr, S->op_dst, S->op_nshort, perm);
+    const int64_t nk = (int64_t)perm.size();
+    S->op_pm.resize(nk), S->op_pp.resize(nk), S->op_pq.resize(nk);
+    for (int64_t i = 0; i < nk; ++i) {
+      S->op_pm[i] = pm[perm[i]];
+      S->op_pp[i] = pp[perm[i]];
+      S->op_pq[i] = pq[perm[i]];
+    }
+  }
+  {   // leaf b's pair p = a (a + 1) / 2 + c (a >= c) lands on S_TT[cl[a]][cl[c]]
+    std::vector<uint64_t> key;
+    key.reserve(nl);
+    for (size_t b = 0; b < S->leaf_size.size(); ++b) {
+      S->leaf_lp_off.push_back(S->lpair_total);
+      const int cnt = S->leaf_ccnt[b];
+      const int32_t* cl = S->leaf_clist.data() + S->leaf_clist_off[b];
+      for (int a = 0; a < cnt; ++a)
+        for (int c = 0; c <= a; ++c) key.push_back((uint64_t)(cl[a] + (int64_t)cl[c] * ld));
+      S->lpair_total += (int64_t)cnt * (cnt + 1) / 2;
+    }
+    std::vector<int64_t> perm;
+    group_terms(key, S->ol_ptr, S->ol_dst, S->ol_nshort, perm);
+    S->ol_pp.resize(perm.size());
+    for (size_t i = 0; i < perm.size(); ++i) S->ol_pp[i] = (int32_t)perm[i];
+  }
+  S->ordered = true;
 }
 
 // (cone, column) entries of the rank-2 rows of the large second-order cones
@@ -1671,20 +1855,30 @@ void factor(hc_solver* S, bool fp64 = false) {
     vfill(S->lval_total, 0.0, S->cm.lval, st);
     vfill(S->cval_total, 0.0, S->cm.cval, st);
     add_P_delta_map(S->dP, S->n, S->delta, S->cm, st);
-    const int64_t ns = S->ntask_short, nl = (int64_t)S->tra.size() - ns;
-    assemble_pairs_map(ns, S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->cm, false, st);
-    assemble_pairs_map(nl, S->dtra + ns, S->dtrb + ns, S->dtm + ns, S->dmval, S->dA, S->cm, true, st);
+    if (S->ordered) {
+      ordered_sum(S->opair, S->dmval, S->dA.val, nullptr, S->cm.ST, S->cm.lval, S->cm.cval, st);
+    } else {
+      const int64_t ns = S->ntask_short, nl = (int64_t)S->tra.size() - ns;
+      assemble_pairs_map(ns, S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->cm, false, st);
+      assemble_pairs_map(nl, S->dtra + ns, S->dtrb + ns, S->dtm + ns, S->dmval, S->dA, S->cm, true, st);
+    }
   } else {
     add_P_delta(S->dP, S->n, S->delta, S->ld, S->dS, st);
     group_T(S->gplan, S->dmval, S->dA, st);
     group_gather(S->gplan, S->n, S->dAt, S->ld, S->dS, st);
-    const int64_t ns = S->ntask_short, nl = (int64_t)S->tra.size() - ns;
-    assemble_pairs(ns, S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->ld, S->dS, false, st);
-    assemble_pairs(nl, S->dtra + ns, S->dtrb + ns, S->dtm + ns, S->dmval, S->dA, S->ld, S->dS, true, st);
+    if (S->ordered) {
+      ordered_sum(S->opair, S->dmval, S->dA.val, nullptr, S->dS, nullptr, nullptr, st);
+    } else {
+      const int64_t ns = S->ntask_short, nl = (int64_t)S->tra.size() - ns;
+      assemble_pairs(ns, S->dtra, S->dtrb, S->dtm, S->dmval, S->dA, S->ld, S->dS, false, st);
+      assemble_pairs(nl, S->dtra + ns, S->dtrb + ns, S->dtm + ns, S->dmval, S->dA, S->ld, S->dS, true, st);
+    }
     if (!S->pdense.empty()) {
-      for (const auto& pd : S->pdense) {
+      for (size_t i = 0; i < S->pdense.size(); ++i) {
+        const auto& pd = S->pdense[i];
         const Segment& g = S->segs[pd.first];
-        psd_dense_T(g.base, g.dim, g.count, g.moff, S->dmval, S->dA, S->n, S->dT + pd.second * S->n, st);
+        psd_dense_T(g.dim, g.count, S->pdense_coff[i], g.moff, S->dmval, S->pcols, S->dA.val, S->n,
+                    S->dT + pd.second * S->n, st);
       }
       dense_T_gather(S->n, S->dpe_rp, S->dpe_e, S->dpe_p, S->dAt.val, S->dT, S->ld, S->dS, st);
     }
@@ -1706,6 +1900,7 @@ void factor(hc_solver* S, bool fp64 = false) {
   const double tol = 0.0;
   // leaves are factored in FP64 in both modes; their updates land in the tail
   leaf_factor(S->cm, tol, S->delta, S->dhits, st);
+  if (S->cm.lslot) ordered_sum(S->oleaf, nullptr, nullptr, S->cm.lslot, S->cm.ST, nullptr, nullptr, st);
   S->use64 = !low;
   Prof* pf = S->st.profile ? S->prof.get() : nullptr;
   if (low && nt > 0) {   // max |S_ii| for the next FP32 factorisation's delta
@@ -2403,6 +2598,27 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   }
   cm.te_cv = upload(buf, S->te_cv, st);
   cm.te_y = upload(buf, S->te_y, st);
+  if (S->ordered) {
+    auto dev = [&](OrderedSum& o, const std::vector<int64_t>& ptr, const std::vector<int64_t>& dst, int64_t nshort,
+                   const std::vector<int32_t>* pm, const std::vector<int32_t>& pp, const std::vector<int32_t>* pq) {
+      o.nd = (int64_t)dst.size();
+      o.nshort = nshort;
+      o.ptr = upload(buf, ptr, st);
+      o.dst = upload(buf, dst, st);
+      o.pm = pm ? upload(buf, *pm, st) : nullptr;
+      o.pp = upload(buf, pp, st);
+      o.pq = pq ? upload(buf, *pq, st) : nullptr;
+    };
+    dev(S->opair, S->op_ptr, S->op_dst, S->op_nshort, &S->op_pm, S->op_pp, &S->op_pq);
+    dev(S->oleaf, S->ol_ptr, S->ol_dst, S->ol_nshort, nullptr, S->ol_pp, nullptr);
+    cm.lp_off = upload(buf, S->leaf_lp_off, st);
+    cm.lslot = S->lpair_total > 0 ? buf.take<double>(S->lpair_total) : nullptr;
+  } else {
+    S->opair = OrderedSum{};
+    S->oleaf = OrderedSum{};
+    cm.lp_off = nullptr;
+    cm.lslot = nullptr;
+  }
   cm.lval = buf.take<double>(S->lval_total + 1);
   cm.cval = buf.take<double>(S->cval_total + 1);
   cm.sink = buf.take<double>(1);
@@ -2436,6 +2652,13 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->dpe_e = upload(buf, S->pe_e, st);
   S->dpe_p = upload(buf, S->pe_p, st);
   S->dT = buf.take<double>(std::max<size_t>(1, (size_t)S->pe_rows * (size_t)S->n));
+  S->pcols.cu_off = upload(buf, S->pc_cu_off, st);
+  S->pcols.cu_ptr = upload(buf, S->pc_cu_ptr, st);
+  S->pcols.cu_col = upload(buf, S->pc_cu_col, st);
+  S->pcols.cu_b = upload(buf, S->pc_cu_b, st);
+  S->pcols.cu_p = upload(buf, S->pc_cu_p, st);
+  // T's columns outside a cone's own stay zero from here on
+  if (!buf.dry && S->pe_rows > 0) vfill(S->pe_rows * S->n, 0.0, S->dT, st);
   S->dpart = buf.take<double>(S->npart);
   S->dmask = buf.take<unsigned long long>(S->npart);
   const int64_t L = std::max(n, m);
@@ -3251,6 +3474,100 @@ int32_t hc_update_data(hc_solver* S, const double* P_val, const double* q, const
   } catch (const std::exception& e) {
     g_last_error = e.what();
     return HC_ERR_INVALID_ARG;
+  }
+  return HC_OK;
+}
+
+int32_t hc_test_ordered_sums(hc_solver* S, int32_t* ordered, double* out) {
+  if (!S || !ordered || !out) return HC_ERR_INVALID_ARG;
+  try {
+    *ordered = S->ordered ? 1 : 0;
+    out[0] = out[1] = out[2] = 0.0;
+    if (!S->ordered) return HC_OK;
+    const HostCsr& A = S->A;
+    const int64_t ld = S->ld;
+    auto weight = [](int64_t i) { return 1.0 + 0.001 * (double)(i % 97); };
+    std::vector<double> ST0((size_t)ld * ld), L0(S->lval_total + 1), C0(S->cval_total + 1);
+    std::vector<double> ST1(ST0.size()), L1(L0.size()), C1(C0.size());
+    double lost = 0.0;
+    // (1) each product added where it lands: the tail (or the whole dense S)
+    // at (hi, lo); one leaf's block at (hi, lo) of its l x l block; a leaf
+    // column l against tail index t at row i of the coupling block, where
+    // the leaf's coupling list holds t at position i (linear search)
+    auto at = [&](int32_t j, int32_t k) -> double* {
+      if (!S->leaves) return &ST0[std::max(j, k) + (int64_t)std::min(j, k) * ld];
+      const int32_t bj = S->col_leaf[j], bk = S->col_leaf[k], lj = S->col_loc[j], lk = S->col_loc[k];
+      if (bj < 0 && bk < 0) return &ST0[std::max(lj, lk) + (int64_t)std::min(lj, lk) * ld];
+      if (bj >= 0 && bk >= 0)
+        return bj == bk ? &L0[S->leaf_lval_off[bj] + std::max(lj, lk) + (int64_t)std::min(lj, lk) * S->leaf_size[bj]]
+                        : &lost;
+      const int32_t b = bj >= 0 ? bj : bk, l = bj >= 0 ? lj : lk, t = bj >= 0 ? lk : lj;
+      for (int i = 0; i < S->leaf_ccnt[b]; ++i)
+        if (S->leaf_clist[S->leaf_clist_off[b] + i] == t)
+          return &C0[S->leaf_cval_off[b] + i + (int64_t)l * S->leaf_ccnt[b]];
+      return &lost;
+    };
+    for (size_t t = 0; t < S->tra.size(); ++t) {
+      const int32_t ra = S->tra[t], rb = S->trb[t];
+      const double m = weight(S->tm[t]);
+      for (int32_t p = A.rp[ra]; p < A.rp[ra + 1]; ++p)
+        for (int32_t q = A.rp[rb]; q < (ra == rb ? p + 1 : A.rp[rb + 1]); ++q) {
+          double v = m * A.v[p] * A.v[q];
+          if (ra != rb && A.ci[p] == A.ci[q]) v *= 2.0;
+          *at(A.ci[p], A.ci[q]) += v;
+        }
+    }
+    // (2) the ordered lists
+    for (size_t d = 0; d + 1 < S->op_ptr.size(); ++d) {
+      double acc = 0.0;
+      for (int64_t k = S->op_ptr[d]; k < S->op_ptr[d + 1]; ++k) {
+        int32_t q = S->op_pq[k];
+        const bool two = q < 0;
+        if (two) q = ~q;
+        double v = weight(S->op_pm[k]) * A.v[S->op_pp[k]] * A.v[q];
+        if (two) v *= 2.0;
+        acc += v;
+      }
+      const uint64_t e = (uint64_t)S->op_dst[d];
+      const uint64_t off = e & ((uint64_t(1) << 62) - 1);
+      std::vector<double>& tgt = (e >> 62) == 0 ? ST1 : (e >> 62) == 1 ? L1 : C1;
+      if ((e >> 62) == 3 || off >= tgt.size()) fail(HC_ERR_STATE, "ordered sum: destination out of range");
+      tgt[off] += acc;
+    }
+    double big = 0.0, diff = std::fabs(lost);
+    const std::vector<double>* pairs[3][2] = {{&ST0, &ST1}, {&L0, &L1}, {&C0, &C1}};
+    for (auto& pr : pairs)
+      for (size_t i = 0; i < pr[0]->size(); ++i) {
+        big = std::max(big, std::fabs((*pr[0])[i]));
+        diff = std::max(diff, std::fabs((*pr[0])[i] - (*pr[1])[i]));
+      }
+    out[0] = big > 0.0 ? diff / big : diff;
+    // leaf slots: every slot in exactly one list, the list's entry being the
+    // (coupling row a, coupling row c) entry of S_TT the slot's pair names
+    std::vector<int> seen(S->lpair_total, 0);
+    double bad = 0.0;
+    std::vector<std::pair<int64_t, int64_t>> who(S->lpair_total);   // slot -> (leaf, pair)
+    for (size_t b = 0; b < S->leaf_size.size(); ++b)
+      for (int64_t p = 0; p < (int64_t)S->leaf_ccnt[b] * (S->leaf_ccnt[b] + 1) / 2; ++p)
+        who[S->leaf_lp_off[b] + p] = {(int64_t)b, p};
+    for (size_t d = 0; d + 1 < S->ol_ptr.size(); ++d)
+      for (int64_t k = S->ol_ptr[d]; k < S->ol_ptr[d + 1]; ++k) {
+        const int32_t sl = S->ol_pp[k];
+        if (sl < 0 || sl >= S->lpair_total) { bad += 1; continue; }
+        seen[sl]++;
+        const int64_t b = who[sl].first, p = who[sl].second;
+        int64_t a = 0;
+        while ((a + 1) * (a + 2) / 2 <= p) ++a;
+        const int64_t c = p - a * (a + 1) / 2;
+        const int32_t* cl = S->leaf_clist.data() + S->leaf_clist_off[b];
+        if (S->ol_dst[d] != cl[a] + (int64_t)cl[c] * ld) bad += 1;
+      }
+    for (int64_t i = 0; i < S->lpair_total; ++i) bad += (seen[i] != 1);
+    out[1] = bad;
+    out[2] = (double)S->op_ptr.size() - 1.0 + (double)S->ol_ptr.size() - 1.0;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
   }
   return HC_OK;
 }

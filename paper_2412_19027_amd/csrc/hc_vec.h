@@ -41,9 +41,18 @@ void assemble_pairs(int64_t ntask, const int32_t* tra, const int32_t* trb, const
 // (dense_T_gather, erp/ee/ep: per column j of A the T rows e and the
 // positions in atval of the values A[row(e), j]).  n <= PSD_DENSE_NMAX (one
 // LDS row of n doubles per workgroup).
+// psd_dense_T writes T[e, j] for the columns j the cone touches (per cone
+// coff + c its columns cu_col[cu_off[.] ..] and per column u its entries
+// cu_ptr[u] .. cu_ptr[u + 1] as (row b of the cone, index of A[row b, j] in A),
+// rows ascending): a thread per column, no atomics, a fixed order.  T's other
+// columns stay zero (cleared once when T is allocated).
 constexpr int64_t PSD_DENSE_NMAX = 8192;
-void psd_dense_T(int64_t base, int32_t dim, int64_t count, int64_t moff, const double* mval, const Csr& A, int64_t n,
-                 double* T, hipStream_t st);
+struct PsdCols {
+  const int64_t *cu_off = nullptr, *cu_ptr = nullptr;
+  const int32_t *cu_col = nullptr, *cu_b = nullptr, *cu_p = nullptr;
+};
+void psd_dense_T(int32_t dim, int64_t count, int64_t coff, int64_t moff, const double* mval, const PsdCols& pc,
+                 const double* av, int64_t n, double* T, hipStream_t st);
 void dense_T_gather(int64_t n, const int32_t* erp, const int32_t* ee, const int32_t* ep, const double* atval,
                     const double* T, int64_t ld, double* S, hipStream_t st);
 // Schur contribution A' M A of the cone rows as a gather (no atomics, a fixed
@@ -67,6 +76,23 @@ struct GroupPlan {
 };
 void group_T(const GroupPlan& gp, const double* mval, const Csr& A, hipStream_t st);
 void group_gather(const GroupPlan& gp, int64_t n, const Csr& At, int64_t ld, double* S, hipStream_t st);
+// Ordered Schur sums (no atomics, a fixed order): destination d gains the sum,
+// in list order, of its terms k in [ptr[d], ptr[d + 1]).  Pair terms are
+// mval[pm[k]] A[pp[k]] A[q] with q = pq[k], or q = ~pq[k] and the term doubled
+// when pq[k] < 0 (the two products of a row pair that meet on the diagonal);
+// slot terms (pm == nullptr) are slot[pp[k]].  dst[d] names the entry: bits
+// 62-63 select base[0], base[1] or base[2], the rest is the offset in it; no
+// two destinations name one entry.  Destinations [0, nshort) run one lane
+// each, the rest (more than ORDERED_WIDE terms) one wave each with a fixed
+// shuffle-tree sum.
+constexpr int ORDERED_WIDE = 32;
+struct OrderedSum {
+  int64_t nd = 0, nshort = 0;
+  const int64_t *ptr = nullptr, *dst = nullptr;
+  const int32_t *pm = nullptr, *pp = nullptr, *pq = nullptr;
+};
+void ordered_sum(const OrderedSum& os, const double* mval, const double* av, const double* slot, double* b0,
+                 double* b1, double* b2, hipStream_t st);
 void scale_dense_rows(int nd, int64_t n, const double* Ad, const int64_t* midx, const double* mval, double* B,
                       hipStream_t st);
 void aos_to_cm(int64_t count, int dim, const double* a, double* c, bool inverse, hipStream_t st);

@@ -383,39 +383,84 @@ void assemble_pairs(int64_t ntask, const int32_t* tra, const int32_t* trb, const
   HC_LAUNCH_CHECK();
 }
 
-// T[e, :] = sum_b M_c[a, b] A[row b of cone c, :] for segment row e = c dim + a
+// T[e, j] = sum_b M_c[a, b] A[row b of cone c, j] for segment row e = c dim + a
 // (M_c symmetric, stored as its lower triangle: entry (a, b), a >= b, at
-// moff + (a (a + 1) / 2 + b) count + c).  One workgroup per row, the n-entry
-// sum in LDS (FP64 LDS atomics: rows of the cone share columns).
-__global__ __launch_bounds__(256) void k_psd_dense_T(int64_t base, int32_t dim, int64_t count, int64_t moff,
-                                                     const double* __restrict__ mval, const int32_t* __restrict__ rp,
-                                                     const int32_t* __restrict__ ci, const double* __restrict__ av,
-                                                     int64_t n, double* __restrict__ T) {
-  extern __shared__ double acc[];
+// moff + (a (a + 1) / 2 + b) count + c).  One workgroup per row, a thread per
+// column the cone touches summing that column's entries in row order.
+__global__ __launch_bounds__(256) void k_psd_dense_T(int32_t dim, int64_t count, int64_t coff, int64_t moff,
+                                                     const double* __restrict__ mval, PsdCols pc,
+                                                     const double* __restrict__ av, int64_t n,
+                                                     double* __restrict__ T) {
   const int64_t rows = count * dim;
   for (int64_t e = blockIdx.x; e < rows; e += gridDim.x) {
     const int64_t c = e / dim;
     const int a = (int)(e % dim);
-    __syncthreads();   // the previous row's readers are done
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) acc[j] = 0.0;
-    __syncthreads();
-    for (int b = threadIdx.x; b < dim; b += blockDim.x) {
-      const int hi = a > b ? a : b, lo = a > b ? b : a;
-      const double m = mval[moff + ((int64_t)hi * (hi + 1) / 2 + lo) * count + c];
-      const int64_t rb = base + c * dim + b;
-      for (int32_t p = rp[rb]; p < rp[rb + 1]; ++p) atomicAdd(&acc[ci[p]], m * av[p]);
+    for (int64_t u = pc.cu_off[coff + c] + threadIdx.x; u < pc.cu_off[coff + c + 1]; u += blockDim.x) {
+      double acc = 0.0;
+      for (int64_t k = pc.cu_ptr[u]; k < pc.cu_ptr[u + 1]; ++k) {
+        const int b = pc.cu_b[k];
+        const int hi = a > b ? a : b, lo = a > b ? b : a;
+        acc += mval[moff + ((int64_t)hi * (hi + 1) / 2 + lo) * count + c] * av[pc.cu_p[k]];
+      }
+      T[e * n + pc.cu_col[u]] = acc;
     }
-    __syncthreads();
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) T[e * n + j] = acc[j];
   }
 }
-void psd_dense_T(int64_t base, int32_t dim, int64_t count, int64_t moff, const double* mval, const Csr& A, int64_t n,
-                 double* T, hipStream_t st) {
+void psd_dense_T(int32_t dim, int64_t count, int64_t coff, int64_t moff, const double* mval, const PsdCols& pc,
+                 const double* av, int64_t n, double* T, hipStream_t st) {
   const int64_t rows = count * dim;
   if (rows == 0) return;
-  hipLaunchKernelGGL(k_psd_dense_T, dim3((unsigned)std::min<int64_t>(rows, 8192)), dim3(256), n * sizeof(double), st,
-                     base, dim, count, moff, mval, A.rowptr, A.col, A.val, n, T);
+  hipLaunchKernelGGL(k_psd_dense_T, dim3((unsigned)std::min<int64_t>(rows, 16384)), dim3(256), 0, st, dim, count,
+                     coff, moff, mval, pc, av, n, T);
   HC_LAUNCH_CHECK();
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_ordered_sum(OrderedSum os, int64_t first, int64_t cnt,
+                                                     const double* __restrict__ mval, const double* __restrict__ av,
+                                                     const double* __restrict__ slot, double* b0, double* b1,
+                                                     double* b2) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = WIDE ? gid / 64 : gid;
+  const int lane = WIDE ? (int)(threadIdx.x & 63) : 0, nl = WIDE ? 64 : 1;
+  if (i >= cnt) return;   // wide: one destination per wave, so whole waves leave together
+  const int64_t d = first + i;
+  const int64_t k0 = os.ptr[d], k1 = os.ptr[d + 1];
+  double acc = 0.0;
+  if (os.pm) {
+    for (int64_t k = k0 + lane; k < k1; k += nl) {
+      int32_t q = os.pq[k];
+      const bool two = q < 0;
+      if (two) q = ~q;
+      double v = mval[os.pm[k]] * av[os.pp[k]] * av[q];
+      if (two) v *= 2.0;
+      acc += v;
+    }
+  } else {
+    for (int64_t k = k0 + lane; k < k1; k += nl) acc += slot[os.pp[k]];
+  }
+  if (WIDE)
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    const int64_t e = os.dst[d];
+    const int sel = (int)((uint64_t)e >> 62);
+    double* base = sel == 0 ? b0 : sel == 1 ? b1 : b2;
+    base[e & ((int64_t(1) << 62) - 1)] += acc;
+  }
+}
+void ordered_sum(const OrderedSum& os, const double* mval, const double* av, const double* slot, double* b0,
+                 double* b1, double* b2, hipStream_t st) {
+  const int64_t ns = os.nshort, nl = os.nd - os.nshort;
+  if (ns > 0) {
+    hipLaunchKernelGGL(k_ordered_sum<false>, dim3((unsigned)ceil_div(ns, 256)), dim3(256), 0, st, os, (int64_t)0,
+                       ns, mval, av, slot, b0, b1, b2);
+    HC_LAUNCH_CHECK();
+  }
+  if (nl > 0) {
+    hipLaunchKernelGGL(k_ordered_sum<true>, dim3((unsigned)ceil_div(nl * 64, 256)), dim3(256), 0, st, os, ns, nl,
+                       mval, av, slot, b0, b1, b2);
+    HC_LAUNCH_CHECK();
+  }
 }
 
 // S[j, k] += sum_e A[row(e), j] T[e, k] for k <= j: one workgroup per column

@@ -25,7 +25,7 @@ EXPORTS = ["hc_settings_default", "hc_setup", "hc_workspace_bytes", "hc_bind", "
            "hc_test_schur", "hc_destroy", "hc_last_error", "hc_status_str",
            "hc_test_cone_scale", "hc_test_cone_ds", "hc_test_cone_step", "hc_test_cone_step_min", "hc_test_dense_chol_solve",
            "hc_test_dense_chol_solve_env",
-           "hc_test_copy", "hc_test_symbolic", "hc_test_cone_mblock", "hc_server_config_default", "hc_server_create", "hc_server_submit", "hc_server_poll",
+           "hc_test_copy", "hc_test_symbolic", "hc_test_ordered_sums", "hc_test_cone_mblock", "hc_server_config_default", "hc_server_create", "hc_server_submit", "hc_server_poll",
            "hc_server_wait", "hc_server_stats", "hc_server_destroy"]
 
 
@@ -118,6 +118,7 @@ def lib():
         L.hc_get_solution.argtypes = [vp, vp, vp, vp, i32]
         L.hc_solve_noalloc.argtypes = [vp, vp, i32, vp, vp, vp, C.POINTER(hc_info)]
         L.hc_test_symbolic.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), C.POINTER(i32)]
+        L.hc_test_ordered_sums.argtypes = [vp, C.POINTER(i32), vp]
         L.hc_host_stage_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.hc_batch_check.argtypes = [vp, C.POINTER(i32)]
         L.hc_solve_batch.argtypes = [vp, i32, vp, i32, vp]
@@ -244,6 +245,20 @@ def solve_noalloc(prob, device=0, stream=None, **settings):
         return out, x, s, z
     finally:
         L.hc_destroy(h)
+
+
+def ordered_sums_check(prob, **settings) -> dict:
+    """hc_test_ordered_sums on a set-up handle (host only): the ordered Schur
+    sums against every product added where it lands."""
+    h, _ = _setup(prob, default_settings(**settings))
+    try:
+        flag = C.c_int32()
+        out = np.zeros(3)
+        _check(lib().hc_test_ordered_sums(h, C.byref(flag), out.ctypes.data), h)
+        return {"ordered": bool(flag.value), "rel_diff": float(out[0]), "bad_slots": int(out[1]),
+                "destinations": int(out[2])}
+    finally:
+        lib().hc_destroy(h)
 
 
 def symbolic(n, ptr, adj):

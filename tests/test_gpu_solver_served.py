@@ -2,6 +2,7 @@
 uneven MPC and LP problems is solved as by a direct hc_solve, memory stays
 within the HBM budget, oversize requests are rejected, and closing a server
 with work in flight cancels it."""
+import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -30,8 +31,10 @@ def test_server_matches_direct_solves(batched):
     assert st["p50_latency_ms"] <= st["p99_latency_ms"] and 0 < st["hbm_peak"] <= budget
     for i, (p, r) in enumerate(zip(probs, res)):
         assert r["tag"] == 100 + i and r["status_name"] == "solved", r
-        info, _, _, _ = gpu_solve(p)
+        info, x, _, _ = gpu_solve(p)
         assert abs(r["obj_primal"] - info["obj_primal"]) <= 1e-9 * max(1.0, abs(info["obj_primal"]))
+        if not batched:   # the same kernels in the same order: bitwise, alone or in the mix
+            assert r["iterations"] == info["iterations"] and np.array_equal(r["x"], x)
         certify(p, r["x"], r["s"], r["z"])
         assert r["latency_ms"] >= r["solve_ms"] >= 0
 
