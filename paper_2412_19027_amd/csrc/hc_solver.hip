@@ -169,6 +169,7 @@ struct hc_solver {
   double* dLinv = nullptr;
   ColMap cm;                        // column map of the two-level split
   double *uT = nullptr, *xT = nullptr;   // compact tail vectors
+  double *uTb = nullptr, *xTb = nullptr; // and those of a second right-hand side
   float *dS32 = nullptr, *dLinv32 = nullptr;
   double *dX256 = nullptr, *dXT256 = nullptr;
   float *dX256f = nullptr, *dXT256f = nullptr;
@@ -186,7 +187,10 @@ struct hc_solver {
   double *Px, *Ax, *Atz, *rdv, *rpv;   // rdv = Px + A'z + q tau ; rpv = -Ax - s + b tau
   double *x2, *z2, *x1, *z1, *dx, *dz, *dsv, *dsrhs, *dxa, *dza, *dsa;
   double *r1, *r2, *irx, *irz, *irxn, *irzn, *irbx, *irbz, *irrx, *irrz, *kx, *kz, *t1, *t2, *u1, *w1;
-  double *sb, *sy, *sx;             // dense solve buffers (n)
+  double *sb, *sy, *sx;             // dense solve buffers (two right-hand sides of n_T)
+  // the second system's refinement vectors (kkt_solve_pair) and the constant
+  // system's first block
+  double *jrx, *jrz, *jrxn, *jrzn, *jrbx, *jrbz, *jrrx, *jrrz, *jkx, *jkz, *u1b, *r1c;
   float *sb32, *sy32, *sx32;
   std::vector<SegDev> sdev;
   // ---- results
@@ -1943,40 +1947,52 @@ void fallback_fp64(hc_solver* S) {
   S->info.fp64_fallbacks++;
 }
 
-// x = S^-1 u (one right-hand side): leaves in FP64, the tail in the factor
-// precision
-void schur_solve(hc_solver* S, const double* u, double* x) {
+// x_r = S^-1 u_r for k = 1 or 2 right-hand sides: leaves in FP64 (one pass
+// per right-hand side), the tail in the factor precision with both
+// right-hand sides in one pass of the dense triangular solves
+void schur_solve_n(hc_solver* S, int k, const double* const* u, double* const* x) {
   hipStream_t st = S->stream;
   const int64_t nt = S->nt;
-  const double* ut = u;
-  double* xt = x;
-  if (S->leaves) {
-    gather_tail(S->cm, u, S->uT, st);
-    leaf_forward(S->cm, u, x, S->uT, st);   // y_b into x at the leaf columns
-    ut = S->uT;
-    xt = S->xT;
-  }
+  const double* ut[2] = {u[0], k > 1 ? u[1] : nullptr};
+  double* xt[2] = {x[0], k > 1 ? x[1] : nullptr};
+  double* uTs[2] = {S->uT, S->uTb};
+  double* xTs[2] = {S->xT, S->xTb};
+  if (S->leaves)
+    for (int r = 0; r < k; ++r) {
+      gather_tail(S->cm, u[r], uTs[r], st);
+      leaf_forward(S->cm, u[r], x[r], uTs[r], st);   // y_b into x at the leaf columns
+      ut[r] = uTs[r];
+      xt[r] = xTs[r];
+    }
   if (nt == 0) {
     // all columns in leaf blocks
   } else if (S->mixed && !S->use64) {
-    RedOps ops{};
-    ops.nops = 1;
-    ops.op[0] = RedOp{RED_MAX_MUL, ut, nullptr, 0.0, nullptr};
-    const int nb = reduce_launch(nt, ops, S->dpart, st);
-    combine_max(nb, S->dpart, S->dscal, st);
-    to_f32(nt, ut, S->dscal, S->sb32, st);
-    dense_solve<float>(S->dS32, nt, S->ld, S->dX256f, S->dXT256f, S->sb32, S->sy32, S->sx32, 1, st,
+    for (int r = 0; r < k; ++r) {   // per right-hand side: scale by its max |entry| for FP32
+      RedOps ops{};
+      ops.nops = 1;
+      ops.op[0] = RedOp{RED_MAX_MUL, ut[r], nullptr, 0.0, nullptr};
+      const int nb = reduce_launch(nt, ops, S->dpart, st);
+      combine_max(nb, S->dpart, S->dscal + r, st);
+      to_f32(nt, ut[r], S->dscal + r, S->sb32 + r * nt, st);
+    }
+    dense_solve<float>(S->dS32, nt, S->ld, S->dX256f, S->dXT256f, S->sb32, S->sy32, S->sx32, k, st,
                        S->tail_last.data());
-    from_f32(nt, S->sx32, S->dscal, xt, st);
+    for (int r = 0; r < k; ++r) from_f32(nt, S->sx32 + r * nt, S->dscal + r, xt[r], st);
+  } else if (k == 1) {
+    vcopy(nt, ut[0], S->sb, st);
+    dense_solve<double>(S->dS, nt, S->ld, S->dX256, S->dXT256, S->sb, S->sy, xt[0], 1, st, S->tail_last.data());
   } else {
-    vcopy(nt, ut, S->sb, st);
-    dense_solve<double>(S->dS, nt, S->ld, S->dX256, S->dXT256, S->sb, S->sy, xt, 1, st, S->tail_last.data());
+    for (int r = 0; r < k; ++r) vcopy(nt, ut[r], S->sb + r * nt, st);
+    dense_solve<double>(S->dS, nt, S->ld, S->dX256, S->dXT256, S->sb, S->sy, S->sx, k, st, S->tail_last.data());
+    for (int r = 0; r < k; ++r) vcopy(nt, S->sx + r * nt, xt[r], st);
   }
-  if (S->leaves) {
-    leaf_backward(S->cm, S->xT, x, st);
-    scatter_tail(S->cm, S->xT, x, st);
-  }
+  if (S->leaves)
+    for (int r = 0; r < k; ++r) {
+      leaf_backward(S->cm, xTs[r], x[r], st);
+      scatter_tail(S->cm, xTs[r], x[r], st);
+    }
 }
+void schur_solve(hc_solver* S, const double* u, double* x) { schur_solve_n(S, 1, &u, &x); }
 
 // K_reg [x; z] = [r1; r2]:  z = M (A x - r2),  S x = r1 + A' M r2
 void solve_reg(hc_solver* S, const double* r1, const double* r2, double* x, double* z) {
@@ -2080,6 +2096,116 @@ int64_t kkt_solve_once(hc_solver* S, const double* r1, const double* r2, double*
   return solves;
 }
 
+// Two systems K [x; z] = [r1; r2] refined in lockstep (kkt_solve_once's
+// rule for each): every step's two Schur solves share one pass of the dense
+// triangular solves; a system leaves the loop under its own stopping test.
+// Results in (xa, za) and (xb, zb); the mixed mode's FP64 fallback as in
+// kkt_solve, per system.
+struct IRSys {
+  const double *r1, *r2;
+  double *xo, *zo, *x, *z, *xn, *zn, *bx, *bz, *rx, *rz, *kx, *kz, *u;
+  double nb = 0, best = 0, rnorm = 0, target = 0;
+  bool have_best = false, done = false;
+};
+int64_t kkt_solve_pair(hc_solver* S, const double* r1a, const double* r2a, double* xa, double* za, const double* r1b,
+                       const double* r2b, double* xb, double* zb) {
+  hipStream_t st = S->stream;
+  const int64_t n = S->n, m = S->m;
+  const bool low = S->mixed && !S->use64;
+  IRSys sy[2];
+  sy[0] = IRSys{r1a, r2a, xa, za, S->irx, S->irz, S->irxn, S->irzn, S->irbx, S->irbz, S->irrx, S->irrz, S->kx,
+                S->kz, S->u1};
+  sy[1] = IRSys{r1b, r2b, xb, zb, S->jrx, S->jrz, S->jrxn, S->jrzn, S->jrbx, S->jrbz, S->jrrx, S->jrrz, S->jkx,
+                S->jkz, S->u1b};
+  for (IRSys& y : sy) {
+    y.nb = maxabs2(S, y.r1, n, y.r2, m);
+    vfill(n, 0.0, y.x, st);
+    vfill(m, 0.0, y.z, st);
+    vcopy(n, y.r1, y.rx, st);
+    vcopy(m, y.r2, y.rz, st);
+    y.best = y.rnorm = y.nb;
+    y.target = ir_target(S, y.nb);
+  }
+  int64_t solves = 0;
+  for (int it = 0; it <= S->st.ir_max; ++it) {
+    IRSys* act[2];
+    int k = 0;
+    for (IRSys& y : sy)
+      if (!y.done) act[k++] = &y;
+    if (k == 0) break;
+    const double* us[2];
+    double* xs[2];
+    for (int r = 0; r < k; ++r) {   // Schur right-hand side r1 + A' M r2 of the residual
+      IRSys& y = *act[r];
+      H_apply(S, 1, y.rz, S->t1);
+      vcopy(n, y.rx, y.u, st);
+      At_mul(S, S->t1, y.u, 1.0, 1.0);
+      us[r] = y.u;
+      xs[r] = y.kx;
+    }
+    schur_solve_n(S, k, us, xs);
+    for (int r = 0; r < k; ++r) {
+      IRSys& y = *act[r];
+      A_mul(S, y.kx, S->w1, 1.0, 0.0);           // correction z = M (A x - r2)
+      vaxpby(m, -1.0, y.rz, 1.0, S->w1, st);
+      H_apply(S, 1, S->w1, y.kz);
+      vlin3(n, 1.0, y.x, 1.0, y.kx, 0.0, nullptr, y.xn, st);
+      vlin3(m, 1.0, y.z, 1.0, y.kz, 0.0, nullptr, y.zn, st);
+      ++solves;
+      P_mul(S, y.xn, y.kx, 1.0, 0.0);            // residual with the unregularised K
+      At_mul(S, y.zn, y.kx, 1.0, 1.0);
+      A_mul(S, y.xn, y.kz, 1.0, 0.0);
+      H_apply(S, 0, y.zn, S->t2);
+      vaxpby(m, -1.0, S->t2, 1.0, y.kz, st);
+      vlin3(n, 1.0, y.r1, -1.0, y.kx, 0.0, nullptr, y.kx, st);
+      vlin3(m, 1.0, y.r2, -1.0, y.kz, 0.0, nullptr, y.kz, st);
+      const double rn = maxabs2(S, y.kx, n, y.kz, m);
+      if (rn < y.best) {
+        vcopy(n, y.xn, y.bx, st);
+        vcopy(m, y.zn, y.bz, st);
+        y.best = rn;
+        y.have_best = true;
+      }
+      if (rn <= y.target || (it > 0 && rn > 0.5 * y.rnorm)) {
+        y.done = true;
+        continue;
+      }
+      std::swap(y.x, y.xn);
+      std::swap(y.z, y.zn);
+      std::swap(y.rx, y.kx);
+      std::swap(y.rz, y.kz);
+      y.rnorm = rn;
+    }
+  }
+  for (IRSys& y : sy) {
+    if (y.have_best) {
+      vcopy(n, y.bx, y.xo, st);
+      vcopy(m, y.bz, y.zo, st);
+    } else {
+      vfill(n, 0.0, y.xo, st);
+      vfill(m, 0.0, y.zo, st);
+    }
+  }
+  S->irx = sy[0].x, S->irz = sy[0].z, S->irxn = sy[0].xn, S->irzn = sy[0].zn;
+  S->irrx = sy[0].rx, S->irrz = sy[0].rz, S->kx = sy[0].kx, S->kz = sy[0].kz;
+  S->jrx = sy[1].x, S->jrz = sy[1].z, S->jrxn = sy[1].xn, S->jrzn = sy[1].zn;
+  S->jrrx = sy[1].rx, S->jrrz = sy[1].rz, S->jkx = sy[1].kx, S->jkz = sy[1].kz;
+  S->info.ir_solves += solves;
+  if (S->st.verbose >= 2) {
+    std::printf("      kkt solve pair: |rhs| %.3e / %.3e best residual %.3e / %.3e solves %lld\n", sy[0].nb, sy[1].nb,
+                sy[0].have_best ? sy[0].best : NAN, sy[1].have_best ? sy[1].best : NAN, (long long)solves);
+    std::fflush(stdout);
+  }
+  if (low)
+    for (IRSys& y : sy) {   // the mixed mode's fallback, per system
+      if (y.have_best && y.best <= std::max(1e-6 * (1.0 + y.nb), ir_target(S, y.nb))) continue;
+      if (!S->use64) fallback_fp64(S);
+      double best = 0, nb = 0;
+      solves += kkt_solve_once(S, y.r1, y.r2, y.xo, y.zo, &best, &nb);
+    }
+  return solves;
+}
+
 struct Resid {
   double xPx, qx, bz, sz, rd_n, rp_n, x_n, s_n, z_n, atz_n, px_n, axs_n;
 };
@@ -2146,12 +2272,13 @@ struct Dir {
   double dtau, dkappa;
 };
 
-// solve for the RHS (d_x = r1, -(d_z - d_s) = r2, d_tau, d_kappa) and recover Delta
+// solve for the RHS (d_x = r1, -(d_z - d_s) = r2, d_tau, d_kappa) and recover
+// Delta (r1 == nullptr: (x1, z1) already solved for it)
 Dir direction(hc_solver* S, const double* r1, const double* r2, double dtau_rhs, double dkap_rhs,
               const double* ds_rhs, double* dxo, double* dzo, double* dso) {
   hipStream_t st = S->stream;
   const int64_t n = S->n, m = S->m;
-  kkt_solve(S, r1, r2, S->x1, S->z1);
+  if (r1) kkt_solve(S, r1, r2, S->x1, S->z1);
   // w = 2 P xi + q with xi = x / tau:  w'x1, w'x2 ; b'z1, b'z2
   Red rn(S, n), rm(S, m);
   const double ti = 1.0 / S->tau;
@@ -2383,13 +2510,13 @@ int iterate(hc_solver* S, const Resid& R) {
     double t2 = now_ms();
     S->info.cone_ms += t1 - t0;
     S->info.factor_ms += t2 - t1;
-    // constant system K [x2; z2] = [-q; b]
-    vlin3(n, -1.0, S->dq, 0.0, nullptr, 0.0, nullptr, S->r1, st);
-    kkt_solve(S, S->r1, S->db, S->x2, S->z2);
-    // affine: r1 = gx, r2 = -(gz - s) = rpv + s
+    // constant system K [x2; z2] = [-q; b] and the affine one, r1 = gx,
+    // r2 = -(gz - s) = rpv + s, refined together
+    vlin3(n, -1.0, S->dq, 0.0, nullptr, 0.0, nullptr, S->r1c, st);
     vlin3(n, -1.0, S->rdv, 0.0, nullptr, 0.0, nullptr, S->r1, st);
     vlin3(m, 1.0, S->rpv, 1.0, S->s, 0.0, nullptr, S->r2, st);
-    const Dir da = direction(S, S->r1, S->r2, gt, S->kappa * S->tau, S->s, S->dxa, S->dza, S->dsa);
+    kkt_solve_pair(S, S->r1c, S->db, S->x2, S->z2, S->r1, S->r2, S->x1, S->z1);
+    const Dir da = direction(S, nullptr, nullptr, gt, S->kappa * S->tau, S->s, S->dxa, S->dza, S->dsa);
     alpha_a = step_length(S, Step{S->dsa, S->dza, da.dtau, da.dkappa}, false);
     sigma = (1.0 - alpha_a) * (1.0 - alpha_a) * (1.0 - alpha_a);
     // combined
@@ -2566,9 +2693,9 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
     S->dLinv32 = buf.take<float>(linv_elems(ntp));
     S->dX256f = buf.take<float>(inv256_elems(ntp));
     S->dXT256f = buf.take<float>(inv256_elems(ntp));
-    S->sb32 = buf.take<float>(nt);
-    S->sy32 = buf.take<float>(nt);
-    S->sx32 = buf.take<float>(nt);
+    S->sb32 = buf.take<float>(2 * nt);   // two right-hand sides (kkt_solve_pair)
+    S->sy32 = buf.take<float>(2 * nt);
+    S->sx32 = buf.take<float>(2 * nt);
   }
   // column map of the two-level split
   ColMap& cm = S->cm;
@@ -2624,6 +2751,8 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   cm.sink = buf.take<double>(1);
   S->uT = buf.take<double>(nt);
   S->xT = buf.take<double>(nt);
+  S->uTb = buf.take<double>(nt);
+  S->xTb = buf.take<double>(nt);
   S->dhits = buf.take<unsigned long long>(1);
   S->dpd = buf.take<int>(2);
   S->dscal = buf.take<double>(8);
@@ -2671,9 +2800,13 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
   S->t2 = buf.take<double>(L);
   S->u1 = buf.take<double>(L);
   S->w1 = buf.take<double>(L);
-  S->sb = buf.take<double>(nt);
-  S->sy = buf.take<double>(nt);
-  S->sx = buf.take<double>(nt);
+  S->sb = buf.take<double>(2 * nt);
+  S->sy = buf.take<double>(2 * nt);
+  S->sx = buf.take<double>(2 * nt);
+  // the second system of kkt_solve_pair
+  double** vecs2[] = {&S->jrx, &S->jrz, &S->jrxn, &S->jrzn, &S->jrbx, &S->jrbz, &S->jrrx, &S->jrrz,
+                      &S->jkx, &S->jkz, &S->u1b, &S->r1c};
+  for (double** v : vecs2) *v = buf.take<double>(L);
   S->wx = buf.take<double>(n);
   S->ws = buf.take<double>(m);
   S->wz = buf.take<double>(m);
