@@ -1173,6 +1173,7 @@ void dense_solve(const T* L, int64_t n, int64_t ld, const T* X256, const T* XT25
                  hipStream_t st, const int64_t* last) {
   if (n <= 0) return;
   if (nrhs == 1) dense_solve_nr<T, 1>(L, n, ld, X256, XT256, B, Y, X, nrhs, last, st);
+  else if (nrhs == 2) dense_solve_nr<T, 2>(L, n, ld, X256, XT256, B, Y, X, nrhs, last, st);
   else dense_solve_nr<T, MAXRHS>(L, n, ld, X256, XT256, B, Y, X, nrhs, last, st);
 }
 

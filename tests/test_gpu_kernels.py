@@ -30,7 +30,7 @@ def relerr(a, b):
 
 # ----------------------------------------------------------------- dense factor
 @pytest.mark.parametrize("n", [1, 37, 64, 200, 333, 700, 1100, 2049])
-@pytest.mark.parametrize("nrhs", [1, 3])
+@pytest.mark.parametrize("nrhs", [1, 2, 3])
 def test_dense_cholesky_fp64(n, nrhs):
     G = RNG.standard_normal((n, n))
     A = G @ G.T + n * np.eye(n)
