@@ -99,6 +99,8 @@ struct hc_solver {
   // pair tasks below keep only what the groups do not take
   std::vector<int64_t> ga_rows_off, ga_u_off, ga_m_off, ga_t_off, ga_gm, ga_c_ptr;
   std::vector<int32_t> ga_rows, ga_u, ga_c_b, ga_c_k, ga_rgrp, ga_rloc;
+  std::vector<int64_t> ga_e_t, ga_e_u;   // per entry of A': its T row and column list
+  std::vector<int32_t> ga_e_s;           // and the list's length (0: row in no group)
   int64_t ga_ng = 0, ga_t_total = 0;
   GroupPlan gplan;
   std::vector<int32_t> tra, trb;   // Schur assembly tasks: short ones first, then
@@ -1219,6 +1221,20 @@ void build_groups(hc_solver* S) {
   S->trb.resize(keep);
   S->tm.resize(keep);
   S->ntask_short = keep_short;
+  // per entry p of A' (row r of column j): the T row of r's group (offset in
+  // T), that group's column list and length, 0 length when r is in no group
+  const HostCsr& At = S->At;
+  S->ga_e_t.assign(At.ci.size(), 0);
+  S->ga_e_u.assign(At.ci.size(), 0);
+  S->ga_e_s.assign(At.ci.size(), 0);
+  for (size_t p = 0; p < At.ci.size(); ++p) {
+    const int32_t r = At.ci[p], g = S->ga_rgrp[r];
+    if (g < 0) continue;
+    const int64_t uo = S->ga_u_off[g], sz = S->ga_u_off[g + 1] - uo;
+    S->ga_e_t[p] = S->ga_t_off[g] + (int64_t)S->ga_rloc[r] * sz;
+    S->ga_e_u[p] = uo;
+    S->ga_e_s[p] = (int32_t)sz;
+  }
 }
 
 // PSD segments whose row pairs would cost more than forming T = M_c A_c for
@@ -2675,6 +2691,9 @@ void alloc_all(hc_solver* S, Buf& buf, hipStream_t st) {
     gp.c_k = upload(buf, S->ga_c_k, st);
     gp.rgrp = upload(buf, S->ga_rgrp, st);
     gp.rloc = upload(buf, S->ga_rloc, st);
+    gp.e_t = upload(buf, S->ga_e_t, st);
+    gp.e_u = upload(buf, S->ga_e_u, st);
+    gp.e_s = upload(buf, S->ga_e_s, st);
     gp.T = buf.take<double>(S->ga_t_total + 1);
   }
   S->dtra = upload(buf, S->tra, st);

@@ -72,6 +72,10 @@ struct GroupPlan {
   const int64_t *rows_off = nullptr, *u_off = nullptr, *m_off = nullptr, *t_off = nullptr, *gm = nullptr,
                 *c_ptr = nullptr;
   const int32_t *rows = nullptr, *u = nullptr, *c_b = nullptr, *c_k = nullptr, *rgrp = nullptr, *rloc = nullptr;
+  // per entry of A' (the column gather's rows): offset of the row's T row,
+  // its group's column list, that list's length (0: the row is in no group)
+  const int64_t *e_t = nullptr, *e_u = nullptr;
+  const int32_t* e_s = nullptr;
   double* T = nullptr;
 };
 void group_T(const GroupPlan& gp, const double* mval, const Csr& A, hipStream_t st);

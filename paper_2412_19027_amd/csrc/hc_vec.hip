@@ -525,12 +525,22 @@ __global__ __launch_bounds__(64) void k_group_gather(GroupPlan gp, int64_t n, co
     for (int64_t c0 = j; c0 < n; c0 += GATHER_CHUNK) {
       const int64_t c1 = std::min<int64_t>(n, c0 + GATHER_CHUNK);
       for (int64_t i = c0 + lane; i < c1; i += 64) acc[i - c0] = 0.0;
+      // each row's T row and column list come from per-entry tables (one
+      // load level), and the next row's are loaded before this row's sum
+      int32_t s_nx = p0 < p1 ? gp.e_s[p0] : 0;
+      int64_t u_nx = p0 < p1 ? gp.e_u[p0] : 0, t_nx = p0 < p1 ? gp.e_t[p0] : 0;
+      double c_nx = p0 < p1 ? atv[p0] : 0.0;
       for (int32_t p = p0; p < p1; ++p) {
-        const int32_t r = atci[p], g = gp.rgrp[r];
-        if (g < 0) continue;
-        const double coef = atv[p];
-        const int64_t uo = gp.u_off[g], s = gp.u_off[g + 1] - uo;
-        const double* vals = gp.T + gp.t_off[g] + (int64_t)gp.rloc[r] * s;
+        const int64_t s = s_nx, uo = u_nx, to = t_nx;
+        const double coef = c_nx;
+        if (p + 1 < p1) {
+          s_nx = gp.e_s[p + 1];
+          u_nx = gp.e_u[p + 1];
+          t_nx = gp.e_t[p + 1];
+          c_nx = atv[p + 1];
+        }
+        if (s == 0) continue;
+        const double* vals = gp.T + to;
         for (int64_t t = lane; t < s; t += 64) {
           const int64_t i = gp.u[uo + t];
           if (i >= c0 && i < c1) acc[i - c0] += coef * vals[t];
