@@ -412,8 +412,10 @@ int32_t hc_test_dense_chol_solve_env(int32_t precision, int64_t n, int64_t ld, d
  * Requests are analysed on the submitting thread (as hc_setup: the problem is
  * copied, the caller may free it on return), queued first in first out, and
  * admitted into active slots while their device workspace fits the HBM
- * budget; the server allocates one device pool of hbm_budget_bytes at
- * creation and carves every workspace from it.  `workers` host threads each
+ * budget; the server carves every workspace from one device pool of
+ * hbm_budget_bytes: the caller's (hc_server_config.pool, as hc_device.arena
+ * for one handle) or one it allocates at creation (the batched engine's
+ * descriptor table, a few bytes per slot, is allocated apart).  `workers` host threads each
  * own a stream and a share of the slots; a tick advances each of a worker's
  * problems by one interior-point iteration, so problems of uneven size
  * interleave and a finished problem's slot and memory go to the next request.
@@ -430,6 +432,11 @@ typedef struct {
                                by one graph-launched kernel per tick; the others on
                                the per-slot workers.  0: every problem per slot (1) */
   int32_t batch_slots;      /* problems in flight on the batched engine (1024)      */
+  void* pool;               /* caller's device memory of hbm_budget_bytes on
+                               `device` (256-byte aligned) to carve the workspaces
+                               from, owned by the caller and kept until
+                               hc_server_destroy returns; NULL: the server
+                               allocates the pool itself (NULL)                     */
 } hc_server_config;
 
 typedef struct {
@@ -484,7 +491,8 @@ typedef struct hc_server hc_server;
 
 /* Defaults listed above.  HC_ERR_INVALID_ARG on NULL. */
 int32_t hc_server_config_default(hc_server_config* out);
-/* Creates the pool and the workers.  HC_ERR_INVALID_ARG (bad config),
+/* Creates the pool (unless the caller gives one) and the workers.
+ * HC_ERR_INVALID_ARG (bad config, or a pool not 256-byte aligned),
  * HC_ERR_DEVICE, HC_ERR_OOM (pool allocation failed). */
 int32_t hc_server_create(hc_server** out, const hc_server_config* cfg);
 /* Validates and analyses `p` (errors as hc_setup; HC_ERR_TOO_LARGE when its

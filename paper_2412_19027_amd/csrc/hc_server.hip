@@ -105,6 +105,7 @@ struct Pool {
 struct hc_server {
   hc_server_config cfg{};
   char* pool_base = nullptr;
+  bool own_pool = false;            // allocated here (else the caller's hc_server_config.pool)
   Pool pool;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -517,8 +518,13 @@ int32_t hc_server_create(hc_server** out, const hc_server_config* cfg) {
   std::unique_ptr<hc_server> s(new hc_server());
   s->cfg = *cfg;
   if (hipSetDevice(cfg->device) != hipSuccess) return HC_ERR_DEVICE;
-  void* p = nullptr;
-  if (hipMalloc(&p, cfg->hbm_budget_bytes) != hipSuccess) return HC_ERR_OOM;
+  void* p = cfg->pool;
+  if (p) {
+    if ((uintptr_t)p % 256 != 0) return HC_ERR_INVALID_ARG;
+  } else {
+    if (hipMalloc(&p, cfg->hbm_budget_bytes) != hipSuccess) return HC_ERR_OOM;
+    s->own_pool = true;
+  }
   s->pool_base = (char*)p;
   s->pool.init(cfg->hbm_budget_bytes / 256 * 256);
   const int nw = std::min(cfg->workers, cfg->max_slots);
@@ -650,7 +656,7 @@ void hc_server_destroy(hc_server* s) {
     j->status = HC_STATUS_CANCELLED;
     j->finished = true;
   }
-  (void)hipFree(s->pool_base);
+  if (s->own_pool) (void)hipFree(s->pool_base);
   delete s;
 }
 

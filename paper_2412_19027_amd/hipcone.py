@@ -74,7 +74,7 @@ class hc_info(C.Structure):
 class hc_server_config(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("workers", C.c_int32),
                 ("settings", hc_settings), ("device", C.c_int32), ("batched", C.c_int32),
-                ("batch_slots", C.c_int32)]
+                ("batch_slots", C.c_int32), ("pool", C.c_void_p)]
 
 
 class hc_result(C.Structure):
@@ -573,7 +573,10 @@ class Server:
     GPU, admitted by device-memory footprint."""
 
     def __init__(self, hbm_budget_bytes=64 << 30, max_slots=64, workers=4, device=0, batched=True,
-                 batch_slots=1024, **settings):
+                 batch_slots=1024, pool=None, **settings):
+        """pool: a caller-owned device buffer (e.g. a torch uint8 tensor) of at
+        least hbm_budget_bytes to carve the workspaces from; it must outlive
+        close()."""
         L = lib()
         cfg = hc_server_config()
         _check(L.hc_server_config_default(C.byref(cfg)))
@@ -584,6 +587,11 @@ class Server:
         cfg.batched = 1 if batched else 0
         cfg.batch_slots = int(batch_slots)
         cfg.settings = default_settings(**settings)
+        if pool is not None:
+            if pool.numel() * pool.element_size() < cfg.hbm_budget_bytes:
+                raise ValueError("pool smaller than hbm_budget_bytes")
+            cfg.pool = pool.data_ptr()
+            self._pool = pool
         self._h = C.c_void_p()
         _check(L.hc_server_create(C.byref(self._h), C.byref(cfg)))
         self._shapes = {}

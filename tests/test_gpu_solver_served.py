@@ -39,6 +39,29 @@ def test_server_matches_direct_solves(batched):
         assert r["latency_ms"] >= r["solve_ms"] >= 0
 
 
+@pytest.mark.parametrize("batched", [True, False], ids=["batched", "per_slot"])
+def test_server_in_caller_pool(batched):
+    """hc_server_config.pool: the workspaces are carved from the caller's
+    device buffer (no pool allocation by the server); results as by direct
+    solves, the buffer untouched past the budget."""
+    probs = [W.mpc_socp(2, i) for i in range(6)] + [W.tiny_lp(s) for s in range(2)]
+    budget = 512 << 20
+    pool = torch.empty(budget + 4096, dtype=torch.uint8, device="cuda")
+    pool[budget:].fill_(0x5A)
+    torch.cuda.synchronize()
+    srv = HC.Server(hbm_budget_bytes=budget, max_slots=4, workers=2, batched=batched, pool=pool)
+    res = [srv.wait(t, solution=True) for t in [srv.submit(p) for p in probs]]
+    st = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    assert st["completed"] == len(probs) and 0 < st["hbm_peak"] <= budget
+    assert bool((pool[budget:] == 0x5A).all())
+    for p, r in zip(probs, res):
+        info, x, _, _ = gpu_solve(p)
+        assert r["status_name"] == "solved", r
+        assert abs(r["obj_primal"] - info["obj_primal"]) <= 1e-9 * max(1.0, abs(info["obj_primal"]))
+
+
 def test_server_budget_bounds_memory():
     probs = [W.mpc_socp(1, i) for i in range(6)]
     need = max(HC.analyze(p)["workspace_bytes"] for p in probs)
